@@ -1,0 +1,35 @@
+"""Discretisation errors, as in the grid-convergence appendix: the error
+(u - u_h, p - p_h) with its components along the trivial kernel (constant
+fields) removed by Gram-Schmidt, measured in L2 and at a fine Gauss grid per
+element (max norm)."""
+from __future__ import annotations
+
+import numpy as np
+
+from .basis import ref_basis, tensor_gauss
+from .assemble import Grid
+
+
+def solution_errors(prob, x, k0):
+    d, p, n = prob.dim, prob.p, prob.n
+    g = Grid(d, n, p, prob.bc, prob.phases)
+    nq = g.nq
+    pts, w = tensor_gauss(prob.q_err, d)
+    B = ref_basis(p, pts) * g.h ** (-d / 2)
+    X = (g.ijk[:, None, :] + pts[None]) * g.h
+    NE, Q = X.shape[:2]
+    chi = np.broadcast_to(g.chi[:, None], (NE, Q)).reshape(-1)
+    xr = x.reshape(NE, d + 1, nq)
+    uh = np.einsum("qa,efa->eqf", B, xr)                     # (NE, Q, d+1)
+    ue = prob.exact.velocity(X.reshape(-1, d), chi).reshape(NE, Q, d)
+    pe = prob.exact.pressure(X.reshape(-1, d), chi).reshape(NE, Q)
+    err = np.concatenate([ue, pe[..., None]], axis=2) - uh
+    wq = w[None, :] * g.h ** d
+    vol = wq.sum()
+    fields = [d] if k0 == 1 else list(range(d + 1))
+    for f in fields:                                         # remove constants
+        err[..., f] -= (err[..., f] * wq).sum() / vol
+    l2 = np.sqrt((err ** 2 * wq[..., None]).sum(axis=(0, 1)))
+    linf = np.abs(err).max(axis=(0, 1))
+    return dict(u_l2=float(np.sqrt((l2[:d] ** 2).sum())), p_l2=float(l2[d]),
+                u_max=float(linf[:d].max()), p_max=float(linf[d]))

@@ -1,0 +1,301 @@
+"""Closed-form coefficient fields, manufactured solutions and forcings.
+
+Every object evaluates pointwise on an array of points ``x`` of shape
+``(N, d)`` with coordinates in the unit cube.  Nothing here discretises
+anything: these are the PDE data of the Stokes problems of the paper,
+eq. (govern1)-(govern3) and its unsteady variant eq. (timedep1).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+
+
+# ---------------------------------------------------------------------------
+# Coefficient fields (viscosity mu, density rho)
+# ---------------------------------------------------------------------------
+@dataclass
+class ConstField:
+    """mu(x) = c."""
+    c: float = 1.0
+    kind: str = "const"
+
+    def value(self, x, chi=None):
+        return np.full(x.shape[0], float(self.c))
+
+    def grad(self, x, chi=None):
+        return np.zeros_like(x, dtype=float)
+
+    def params(self):
+        return np.array([self.c], dtype=float)
+
+
+@dataclass
+class SinProductField:
+    """mu(x) = a + b * prod_j sin(2 pi k x_j)  (the C2 viscosity has a=1, b=0.9, k=1)."""
+    a: float = 1.0
+    b: float = 0.9
+    k: float = 1.0
+    kind: str = "sinsin"
+
+    def value(self, x, chi=None):
+        return self.a + self.b * np.prod(np.sin(TWO_PI * self.k * x), axis=1)
+
+    def grad(self, x, chi=None):
+        s = np.sin(TWO_PI * self.k * x)
+        c = np.cos(TWO_PI * self.k * x)
+        d = x.shape[1]
+        g = np.empty_like(x, dtype=float)
+        for j in range(d):
+            others = np.prod(np.delete(s, j, axis=1), axis=1)
+            g[:, j] = self.b * TWO_PI * self.k * c[:, j] * others
+        return g
+
+    def params(self):
+        return np.array([self.a, self.b, self.k], dtype=float)
+
+
+@dataclass
+class PhaseField:
+    """Piecewise-constant field on two phases of the square/cube inclusion.
+
+    Phase 1 is the open box (lo, hi)^d, phase 2 its complement (the paper's
+    square inclusion test).  ``values[chi-1]`` is the value in phase chi.
+    """
+    values: tuple = (1.0e4, 1.0)
+    lo: float = 0.25
+    hi: float = 0.75
+    kind: str = "phase"
+
+    def phase(self, x):
+        inside = np.all((x > self.lo) & (x < self.hi), axis=1)
+        return np.where(inside, 1, 2)
+
+    def value(self, x, chi=None):
+        if chi is None:
+            chi = self.phase(x)
+        vals = np.asarray(self.values, dtype=float)
+        return vals[np.asarray(chi) - 1]
+
+    def grad(self, x, chi=None):
+        return np.zeros_like(x, dtype=float)
+
+    def params(self):
+        return np.array([self.values[0], self.values[1], self.lo, self.hi], dtype=float)
+
+
+@dataclass
+class LogNormalRFF:
+    """mu(x) = 10**g(x), g = sqrt(2/K) sum_m cos(k_m . x + phi_m).
+
+    Random Fourier features of a unit-variance Gaussian field with squared
+    exponential covariance of correlation length ``ell``: k_m ~ N(0, ell^-2 I),
+    phi_m ~ U[0, 2 pi), drawn from numpy's PCG64 with the given seed.
+    """
+    kvecs: np.ndarray = field(default_factory=lambda: np.zeros((1, 3)))
+    phases: np.ndarray = field(default_factory=lambda: np.zeros(1))
+    kind: str = "lognormal_rff"
+
+    @staticmethod
+    def from_seed(seed: int, dim: int, K: int = 256, ell: float = 0.1):
+        rng = np.random.Generator(np.random.PCG64(seed))
+        kvecs = rng.normal(0.0, 1.0 / ell, size=(K, dim))
+        phases = rng.uniform(0.0, TWO_PI, size=K)
+        return LogNormalRFF(kvecs=kvecs, phases=phases)
+
+    def _g(self, x):
+        K = self.kvecs.shape[0]
+        arg = x @ self.kvecs.T + self.phases[None, :]
+        return math.sqrt(2.0 / K) * np.cos(arg).sum(axis=1), arg
+
+    def value(self, x, chi=None):
+        g, _ = self._g(x)
+        return 10.0 ** g
+
+    def grad(self, x, chi=None):
+        K = self.kvecs.shape[0]
+        g, arg = self._g(x)
+        dg = -math.sqrt(2.0 / K) * (np.sin(arg) @ self.kvecs)
+        return (10.0 ** g)[:, None] * math.log(10.0) * dg
+
+    def params(self):
+        return np.concatenate([self.kvecs.ravel(), self.phases])
+
+
+# ---------------------------------------------------------------------------
+# Manufactured solutions built from products of shifted sines
+# ---------------------------------------------------------------------------
+@dataclass
+class SinProd:
+    """c * prod_j sin(2 pi (x_j + s_j)), with value, gradient and Hessian."""
+    c: float
+    shifts: tuple
+
+    def _sc(self, x):
+        arg = TWO_PI * (x + np.asarray(self.shifts)[None, :])
+        return np.sin(arg), np.cos(arg)
+
+    def value(self, x):
+        s, _ = self._sc(x)
+        return self.c * np.prod(s, axis=1)
+
+    def grad(self, x):
+        s, co = self._sc(x)
+        d = x.shape[1]
+        g = np.empty_like(x, dtype=float)
+        for j in range(d):
+            f = TWO_PI * co[:, j]
+            for l in range(d):
+                if l != j:
+                    f = f * s[:, l]
+            g[:, j] = self.c * f
+        return g
+
+    def hess(self, x):
+        s, co = self._sc(x)
+        d = x.shape[1]
+        H = np.empty((x.shape[0], d, d))
+        for j in range(d):
+            for l in range(d):
+                f = np.full(x.shape[0], self.c)
+                for r in range(d):
+                    if r == j and r == l:
+                        f = f * (-(TWO_PI ** 2) * s[:, r])
+                    elif r == j or r == l:
+                        f = f * (TWO_PI * co[:, r])
+                    else:
+                        f = f * s[:, r]
+                H[:, j, l] = f
+        return H
+
+
+@dataclass
+class ExactSolution:
+    """Exact (u, p) per phase, with the forcing it induces for a given mu.
+
+    ``u[chi]`` is a list of d SinProd components and ``p[chi]`` a SinProd, for
+    each phase chi present.  ``forcing`` evaluates eq. (govern1):
+    f = -div(mu (grad u + gamma grad u^T)) + grad p and f_div = -div u.
+    """
+    dim: int
+    gamma: int
+    mu: object
+    u: dict
+    p: dict
+
+    def _phases(self, chi, n):
+        if chi is None:
+            return np.ones(n, dtype=int) * min(self.u.keys())
+        return np.asarray(chi)
+
+    def _per_phase(self, x, chi, fn):
+        chi = self._phases(chi, x.shape[0])
+        out = None
+        for c in np.unique(chi):
+            sel = chi == c
+            val = fn(x[sel], int(c))
+            if out is None:
+                out = np.zeros((x.shape[0],) + val.shape[1:])
+            out[sel] = val
+        return out
+
+    def velocity(self, x, chi=None):
+        return self._per_phase(x, chi, lambda y, c: np.stack([f.value(y) for f in self.u[c]], axis=1))
+
+    def grad_velocity(self, x, chi=None):
+        """(N, d, d) with [i, j] = d u_i / d x_j."""
+        return self._per_phase(x, chi, lambda y, c: np.stack([f.grad(y) for f in self.u[c]], axis=1))
+
+    def pressure(self, x, chi=None):
+        return self._per_phase(x, chi, lambda y, c: self.p[c].value(y))
+
+    def stress(self, x, chi=None):
+        """sigma = mu (grad u + gamma grad u^T) - p I."""
+        gu = self.grad_velocity(x, chi)
+        mu = self.mu.value(x, chi)
+        s = mu[:, None, None] * (gu + self.gamma * np.transpose(gu, (0, 2, 1)))
+        s -= self.pressure(x, chi)[:, None, None] * np.eye(self.dim)[None]
+        return s
+
+    def forcing(self, x, chi=None):
+        def f(y, c):
+            d = self.dim
+            mu = self.mu.value(y, np.full(y.shape[0], c))
+            dmu = self.mu.grad(y, np.full(y.shape[0], c))
+            gu = np.stack([q.grad(y) for q in self.u[c]], axis=1)       # [n, i, j]
+            Hu = np.stack([q.hess(y) for q in self.u[c]], axis=1)       # [n, i, j, l]
+            gp = self.p[c].grad(y)
+            out = np.empty((y.shape[0], d))
+            for i in range(d):
+                acc = np.zeros(y.shape[0])
+                for j in range(d):
+                    acc += dmu[:, j] * (gu[:, i, j] + self.gamma * gu[:, j, i])
+                    acc += mu * (Hu[:, i, j, j] + self.gamma * Hu[:, j, i, j])
+                out[:, i] = -acc + gp[:, i]
+            return out
+        return self._per_phase(x, chi, f)
+
+    def forcing_div(self, x, chi=None):
+        def f(y, c):
+            gu = np.stack([q.grad(y) for q in self.u[c]], axis=1)
+            return -np.einsum("nii->n", gu)
+        return self._per_phase(x, chi, f)
+
+
+def make_exact_c1(mu=None):
+    """u = (sin2pi x cos2pi y, -cos2pi x sin2pi y), p = cos2pi x cos2pi y (2D)."""
+    mu = mu or ConstField(1.0)
+    u = {1: [SinProd(1.0, (0.0, 0.25)), SinProd(-1.0, (0.25, 0.0))]}
+    p = {1: SinProd(1.0, (0.25, 0.25))}
+    return ExactSolution(dim=2, gamma=0, mu=mu, u=u, p=p)
+
+
+def make_exact_paper(dim, gamma, mu, phases=(1,), mu_chi=None):
+    """The paper's manufactured solution (grid-convergence appendix):
+
+    u_i = prod_j sin 2pi(x_j - 0.2 i - 0.25 (chi-1)),
+    p   = mu_chi prod_j sin 2pi(x_j + 0.2 - 0.25 (chi-1)),  i = 1..d.
+    """
+    mu_chi = mu_chi or {c: 1.0 for c in phases}
+    u, p = {}, {}
+    for chi in phases:
+        off = -0.25 * (chi - 1)
+        u[chi] = [SinProd(1.0, tuple([-0.2 * i + off] * dim)) for i in range(1, dim + 1)]
+        p[chi] = SinProd(float(mu_chi[chi]), tuple([0.2 + off] * dim))
+    return ExactSolution(dim=dim, gamma=gamma, mu=mu, u=u, p=p)
+
+
+@dataclass
+class FourierForcing:
+    """Seeded smooth Gaussian-random forcing.
+
+    f_c(x) = s_c sum_{k in {0..kmax-1}^d, k != 0} a_{c,k} cos 2pi k.x + b_{c,k} sin 2pi k.x
+    with a, b ~ N(0, 1) from PCG64(seed) and s_c chosen so that each component
+    has unit root-mean-square over the unit cube.  f_div = 0.
+    """
+    dim: int
+    kmodes: np.ndarray      # (M, d) integer wave vectors
+    a: np.ndarray           # (d, M)
+    b: np.ndarray           # (d, M)
+
+    @staticmethod
+    def from_seed(seed: int, dim: int, kmax: int = 8):
+        grids = np.meshgrid(*[np.arange(kmax)] * dim, indexing="ij")
+        kmodes = np.stack([g.ravel() for g in grids], axis=1)
+        kmodes = kmodes[np.any(kmodes != 0, axis=1)]
+        rng = np.random.Generator(np.random.PCG64(seed))
+        a = rng.normal(size=(dim, kmodes.shape[0]))
+        b = rng.normal(size=(dim, kmodes.shape[0]))
+        rms = np.sqrt(0.5 * (a ** 2 + b ** 2).sum(axis=1))
+        return FourierForcing(dim=dim, kmodes=kmodes, a=a / rms[:, None], b=b / rms[:, None])
+
+    def forcing(self, x, chi=None):
+        arg = TWO_PI * (x @ self.kmodes.T)
+        return np.cos(arg) @ self.a.T + np.sin(arg) @ self.b.T
+
+    def forcing_div(self, x, chi=None):
+        return np.zeros(x.shape[0])

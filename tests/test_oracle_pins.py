@@ -1,0 +1,344 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed
+forms of the 1D Legendre operators, structural facts the paper states
+(symmetry, the trivial kernel, block-diagonal velocity operator for the
+standard form), equivalence of operator coarsening and rediscretisation,
+the harmonic identity behind eq. (Etimedep), a dense direct solve, and the
+orders of accuracy the paper reports for its manufactured solutions.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from synth import (Problem, ConstField, SinProductField, c1_periodic_standard,
+                   c2_dirichlet_varmu, kernel_dimension, TAU_OPTIMAL)
+from synth.fields import make_exact_paper
+from oracle import build_hierarchy
+from oracle.assemble import FineAssembly, fine_operators, stokes_system, Grid
+from oracle.basis import leg_values, leg_derivs, gauss01
+from oracle.coarsen import coarsen, prolongation, frobenius_blend
+from oracle.rhs import assemble_rhs
+from oracle.solvers import Solver
+from oracle.errors import solution_errors
+from oracle.multigrid import Precision, colour_pass
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+# ---------------------------------------------------------------- P1 -------
+def closed_form_1d(p):
+    """e0 = l_m(0) = (-1)^m sqrt(2m+1), e1 = l_m(1) = sqrt(2m+1),
+    K_ba = int l_a' l_b = 2 sqrt((2a+1)(2b+1)) if a > b and a+b odd."""
+    m = p + 1
+    e0 = np.array([(-1) ** a * math.sqrt(2 * a + 1) for a in range(m)])
+    e1 = np.array([math.sqrt(2 * a + 1) for a in range(m)])
+    K = np.zeros((m, m))
+    for b in range(m):
+        for a in range(m):
+            if a > b and (a + b) % 2 == 1:
+                K[b, a] = 2.0 * math.sqrt((2 * a + 1) * (2 * b + 1))
+    return e0, e1, K
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_p1_legendre_closed_forms(p):
+    e0, e1, K = closed_form_1d(p)
+    assert np.allclose(leg_values(p, [0.0])[0], e0, atol=1e-13)
+    assert np.allclose(leg_values(p, [1.0])[0], e1, atol=1e-13)
+    x, w = gauss01(p + 2)
+    Kq = np.einsum("q,qa,qb->ba", w, leg_derivs(p, x), leg_values(p, x))
+    assert np.allclose(Kq, K, atol=1e-12)
+    # integration by parts: K + K^T = e1 e1^T - e0 e0^T
+    assert np.allclose(K + K.T, np.outer(e1, e1) - np.outer(e0, e0), atol=1e-12)
+    # orthonormality
+    assert np.allclose(np.einsum("q,qa,qb->ab", w, leg_values(p, x), leg_values(p, x)), np.eye(p + 1), atol=1e-13)
+
+
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+@pytest.mark.parametrize("axis", [0, 1])
+def test_p1_quadrature_gradient_equals_1d_factor_form(bc, axis):
+    """The quadrature-assembled G_k equals the tensor form with 1D factors:
+    interior G(E,E) = h^-1 (K + e0 e0^T)_k, G(E, E-e_k) = -h^-1 (e0 e1^T)_k;
+    Dirichlet high-side element G(E,E) = -h^-1 (K^T)_k."""
+    n, p = 4, 2
+    prob = Problem(name="t", dim=2, n=n, p=p, gamma=0, bc=(bc, bc))
+    G = fine_operators(prob)["G"][axis].toarray()
+    e0, e1, K = closed_form_1d(p)
+    h = 1.0 / n
+    m = p + 1
+    I = np.eye(m)
+
+    def on_axis(mat):
+        return np.kron(I, mat) if axis == 0 else np.kron(mat, I)
+
+    g = Grid(2, n, p, prob.bc)
+    ref = np.zeros_like(G)
+    nq = m * m
+    for E in range(g.NE):
+        i = g.ijk[E]
+        diag = K + np.outer(e0, e0)
+        if bc == "dirichlet" and i[axis] == n - 1:
+            diag = diag - np.outer(e1, e1)
+        ref[E * nq:(E + 1) * nq, E * nq:(E + 1) * nq] += on_axis(diag) / h
+        if i[axis] > 0 or bc == "periodic":
+            j = i.copy()
+            j[axis] = (i[axis] - 1) % n
+            F = g.index(j)[0]
+            ref[E * nq:(E + 1) * nq, F * nq:(F + 1) * nq] += -on_axis(np.outer(e0, e1)) / h
+    assert np.abs(G - ref).max() <= 1e-12 * np.abs(ref).max()
+    if bc == "dirichlet":
+        assert np.allclose(K + np.outer(e0, e0) - np.outer(e1, e1), -K.T)
+
+
+# ---------------------------------------------------------------- P2 -------
+def test_p2_mass_identity_and_injection():
+    prob = c2_dirichlet_varmu(n=8, p=2)
+    ops = fine_operators(prob)
+    assert np.allclose(ops["M"].toarray(), np.eye(ops["M"].shape[0]), atol=1e-13)
+    c1 = coarsen(ops, prob, False)
+    I = c1["I"]
+    assert np.allclose((I.T @ I).toarray(), np.eye(I.shape[1]), atol=1e-13)
+    assert np.allclose(c1["M"].toarray(), np.eye(c1["M"].shape[0]), atol=1e-13)
+    # injection is exact on Q_p: evaluate a random coarse polynomial on each child
+    from oracle.basis import ref_basis
+    rng = np.random.default_rng(0)
+    fine, coarse = ops["grid"], c1["grid"]
+    coef_c = rng.standard_normal(coarse.NE * coarse.nq)
+    coef_f = I @ coef_c
+    pts = rng.random((5, 2))
+    for E in [0, 5, 37, fine.NE - 1]:
+        X = (fine.ijk[E] + pts) * fine.h
+        Ec = coarse.index(fine.ijk[E] // 2)[0]
+        vf = ref_basis(2, pts) @ coef_f[E * 9:(E + 1) * 9] * fine.h ** -1
+        xi_c = X / coarse.h - coarse.ijk[Ec]
+        vc = ref_basis(2, xi_c) @ coef_c[Ec * 9:(Ec + 1) * 9] * coarse.h ** -1
+        assert np.allclose(vf, vc, atol=1e-12)
+
+
+# ------------------------------------------------------------- P3 P4 P5 ----
+PROBS = [
+    lambda: c1_periodic_standard(n=8, p=2),
+    lambda: c2_dirichlet_varmu(n=8, p=2),
+    lambda: Problem(name="3d_per_vs", dim=3, n=4, p=1, gamma=1, bc=("periodic",) * 3, coarsest_n=2),
+]
+
+
+@pytest.mark.parametrize("mk", PROBS)
+def test_p3_symmetry_all_levels(mk):
+    H = build_hierarchy(mk())
+    for lv in H.levels:
+        A = lv.A
+        assert abs(A - A.T).max() <= 1e-13 * abs(A).max()
+
+
+@pytest.mark.parametrize("mk", PROBS)
+def test_p4_trivial_kernel(mk):
+    prob = mk()
+    H = build_hierarchy(prob)
+    K = H.kernel_basis()
+    A = H.fine.A
+    nrm = abs(A).max()
+    assert K.shape[1] == kernel_dimension(prob)
+    assert np.linalg.norm(A @ K) <= 1e-13 * nrm
+    # the kernel is no larger than stated: the bottom solver found exactly k0 near-zero modes
+    lam = np.sort(np.abs(H.levels[-1].eig))
+    assert lam[H.k0] > 1e-8 * lam[-1]
+
+
+def test_kernel_dimensions_match_paper():
+    for form, d, dim in [(r[0], int(r[1]), int(r[2])) for r in _read_golden("kernel_dimensions.txt")]:
+        bc = ("periodic",) * d if form.startswith("periodic") else ("dirichlet",) * d
+        delta = 1e-3 if form == "periodic_unsteady" else None
+        prob = Problem(name="k", dim=d, n=4, p=1, gamma=1, bc=bc, delta=delta,
+                       rho=ConstField(1.0) if delta else None, coarsest_n=2)
+        assert kernel_dimension(prob) == dim
+
+
+def test_p5_standard_form_velocity_blocks_identical():
+    prob = c1_periodic_standard(n=4, p=2)
+    ops = fine_operators(prob)
+    A = stokes_system(ops, 2, 0, 9).toarray()
+    nb, nq = 27, 9
+    NE = A.shape[0] // nb
+    u1 = np.concatenate([np.arange(E * nb, E * nb + nq) for E in range(NE)])
+    u2 = u1 + nq
+    assert np.abs(A[np.ix_(u1, u2)]).max() == 0.0
+    assert np.allclose(A[np.ix_(u1, u1)], A[np.ix_(u2, u2)], atol=1e-12)
+
+
+def test_table1_tau_fixture_matches_problem_defaults():
+    for row in _read_golden("table1_optimal_tau.txt"):
+        vals = tuple(float(v) for v in row[2:] if v != "-")
+        assert TAU_OPTIMAL[(row[0], int(row[1]))] == vals
+
+
+# ---------------------------------------------------------------- P6 -------
+@pytest.mark.parametrize("gamma,bc", [(0, "periodic"), (1, "dirichlet"), (1, "periodic")])
+def test_p6_coarsening_equals_rediscretisation(gamma, bc):
+    fine = Problem(name="f", dim=2, n=8, p=2, gamma=gamma, bc=(bc, bc))
+    coarse = Problem(name="c", dim=2, n=4, p=2, gamma=gamma, bc=(bc, bc), tau=fine.tau)
+    ops_f = fine_operators(fine)
+    ops_c = fine_operators(coarse)
+    ops_2h = coarsen(ops_f, fine, False)
+    A2 = stokes_system(ops_2h, 2, gamma, 9)
+    Ac = stokes_system(ops_c, 2, gamma, 9)
+    assert abs(A2 - Ac).max() <= 1e-11 * abs(Ac).max()
+    # RAT on the whole operator is a different (and, for LDG, wrong) operator
+    Af = stokes_system(ops_f, 2, gamma, 9)
+    I = sp.block_diag([ops_2h["I"]] * 3).tocsr()
+    from oracle.assemble import field_to_element_major
+    pf = field_to_element_major(64, 3, 9)
+    pc = field_to_element_major(16, 3, 9)
+    Ie = I[pf][:, pc]
+    rat = Ie.T @ Af @ Ie
+    assert abs(rat - Ac).max() > 1e-2 * abs(Ac).max()
+
+
+# ---------------------------------------------------------------- P7 -------
+def test_p7_frobenius_blend_is_harmonic_for_proportional_blocks():
+    rng = np.random.default_rng(1)
+    nq = 4
+    B = sp.random(3 * nq, 3 * nq, density=0.6, random_state=2).tocsr()
+    a, b = 2.5, 0.3
+    out = frobenius_blend(a * B, b * B, nq)
+    assert abs(out - (a * b / (a + b)) * B).max() <= 1e-14 * abs(B).max()
+    assert rng is not None
+
+
+def test_p7_unsteady_coarsening_equals_taugeneral_at_2h():
+    kw = dict(dim=2, p=2, gamma=1, bc=("periodic", "periodic"), rho=ConstField(1.0), mu=ConstField(0.7))
+    fine = Problem(name="f", n=8, delta=2e-3, **kw)
+    coarse = Problem(name="c", n=4, delta=2e-3, tau=fine.tau, **kw)
+    ops_2h = coarsen(fine_operators(fine), fine, True)
+    Ec = fine_operators(coarse)["E"]
+    assert abs(ops_2h["E"] - Ec).max() <= 1e-12 * abs(Ec).max()
+
+
+# ---------------------------------------------------------------- P8 -------
+@pytest.mark.parametrize("mk", PROBS[:2])
+def test_p8_colour_pass_zeroes_colour_residual(mk):
+    prob = mk()
+    H = build_hierarchy(prob)
+    P = Precision(H)
+    lv = H.fine
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(lv.A.shape[0])
+    b = rng.standard_normal(lv.A.shape[0])
+    for c in range(lv.ncol):
+        elems = np.nonzero(lv.colours == c)[0]
+        colour_pass(lv.A, lv.Ainv, x, b, elems, lv.nb)
+        r = (b - lv.A @ x).reshape(-1, lv.nb)
+        bE = b.reshape(-1, lv.nb)
+        assert np.linalg.norm(r[elems]) <= 1e-11 * np.linalg.norm(bE[elems])
+    assert P is not None
+
+
+def test_colourings_are_proper_for_the_stencil():
+    """No two elements of one colour are coupled by the assembled operator."""
+    for mk in PROBS:
+        prob = mk()
+        H = build_hierarchy(prob)
+        for lv in H.levels[:-1]:
+            Ab = sp.csr_matrix(lv.A).tobsr(blocksize=(lv.nb, lv.nb))
+            for r in range(lv.NE):
+                for k in range(Ab.indptr[r], Ab.indptr[r + 1]):
+                    c = Ab.indices[k]
+                    if c != r and np.abs(Ab.data[k]).max() > 0:
+                        assert lv.colours[c] != lv.colours[r]
+
+
+# ---------------------------------------------------------------- P9 -------
+@pytest.mark.parametrize("mk", [lambda: c1_periodic_standard(n=8, p=2),
+                                lambda: c2_dirichlet_varmu(n=8, p=2)])
+def test_p9_dense_direct_solve_matches_multigrid(mk):
+    prob = mk()
+    H = build_hierarchy(prob)
+    b = assemble_rhs(prob, H.fine.ops)
+    S = Solver(H)
+    x_mg, hist = S.stationary(b, 60, tol=1e-13)
+    assert hist[-1] < 1e-12
+    A = S.A.toarray()
+    x_d = np.linalg.lstsq(A, H.project_kernel(b), rcond=None)[0]
+    x_mg, x_d = H.project_kernel(x_mg), H.project_kernel(x_d)
+    assert np.linalg.norm(x_mg - x_d) <= 1e-10 * np.linalg.norm(x_d)
+
+
+# --------------------------------------------------------------- P10 -------
+def _orders(mk, ns):
+    errs = []
+    for n in ns:
+        prob = mk(n)
+        H = build_hierarchy(prob)
+        b = assemble_rhs(prob, H.fine.ops)
+        x, hist = Solver(H).stationary(b, 60, tol=1e-13)
+        errs.append(solution_errors(prob, H.project_kernel(x), H.k0))
+    return {k: math.log2(errs[0][k] / errs[1][k]) for k in errs[0]}
+
+
+def test_p10_periodic_orders():
+    o = _orders(lambda n: c1_periodic_standard(n=n, p=2), [8, 16])
+    gold = {r[1]: float(r[2]) for r in _read_golden("convergence_orders.txt") if r[0] == "periodic"}
+    for q, off in gold.items():
+        assert o[q] >= 2 + off - 0.3, (q, o[q])
+
+
+def test_p10_dirichlet_variable_mu_orders():
+    o = _orders(lambda n: c2_dirichlet_varmu(n=n, p=2), [8, 16])
+    gold = {r[1]: float(r[2]) for r in _read_golden("convergence_orders.txt") if r[0] == "dirichlet_varmu"}
+    for q, off in gold.items():
+        assert o[q] >= 2 + off - 0.3, (q, o[q])
+
+
+# --------------------------------------------------------------- P11 -------
+def test_p11_rho_context_periodic_p2():
+    """Context: rho ~ 0.05 for periodic standard form, p >= 2, V(3,3) (paper,
+    section 5.1).  A loose bound; the paper's figure values are not available."""
+    prob = c1_periodic_standard(n=16, p=2, nu=(3, 3))
+    rho, its = Solver(build_hierarchy(prob)).rho_metric()
+    assert rho < 0.12, rho
+
+
+def test_p14_p1_converges_worse():
+    def rate(p):
+        prob = c1_periodic_standard(n=16, p=p, nu=(3, 3))
+        return Solver(build_hierarchy(prob)).rho_metric()[0]
+    assert rate(1) > rate(2)
+
+
+# ------------------------------------------------- planted-mistake checks --
+def test_s5_reading_printed_form_degrades_velocity_order(monkeypatch):
+    """Dropping M_mu from G_j^T M_mu J_g (the form printed in eq. wform /
+    appstokes1) must spoil the p+1 velocity order under variable mu with
+    Dirichlet data; the pin above passes only with the derived M_mu."""
+    import oracle.rhs as R
+    orig = R.assemble_rhs
+
+    def printed(prob, ops):
+        ops2 = dict(ops)
+        ops2["Mmu"] = sp.identity(ops["Mmu"].shape[0], format="csr")
+        return orig(prob, ops2)
+
+    monkeypatch.setattr(R, "assemble_rhs", printed)
+    errs = []
+    for n in (8, 16):
+        prob = c2_dirichlet_varmu(n=n, p=2)
+        H = build_hierarchy(prob)
+        b = R.assemble_rhs(prob, H.fine.ops)
+        x, _ = Solver(H).stationary(b, 60, tol=1e-13)
+        errs.append(solution_errors(prob, H.project_kernel(x), H.k0))
+    order = math.log2(errs[0]["u_l2"] / errs[1]["u_l2"])
+    assert order < 2.5, order
