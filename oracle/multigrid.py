@@ -1,5 +1,11 @@
 """Element-block Gauss-Seidel smoothing and the V-cycle (Algorithm 1).
 
+Bottom solve (footnote to the bottom solver in section 3): the least-squares
+solution with the eigendecomposition pseudo-inverse, near-zero eigenvalues
+snapped to zero.  Reading: the solve is the least-squares solution computed
+to working accuracy, i.e. A_c^+ applied with one refinement step; the
+pseudo-inverse alone has a backward error of order eps * cond(A_c).
+
 Block Gauss-Seidel (section 3): for element i of the current colour,
 x_i <- A_ii^{-1} (b_i - sum_{j != i} A_ij x_j).  Elements of one colour are
 updated together from the iterate as it stood at the start of the colour
@@ -53,8 +59,14 @@ def vcycle(P, li, x, b):
     prob = hier.prob
     if li == len(hier.levels) - 1:
         lv = hier.levels[li]
-        # bottom solve in FP64 (cast in and out for reduced-precision cycles)
-        return (lv.pinv @ b.astype(np.float64)).astype(P.dtype)
+        # bottom solve in FP64 (cast in and out for reduced-precision cycles):
+        # the least-squares solution A_c^+ b of the bottom-solver footnote,
+        # applied with one step of iterative refinement so that it is
+        # computed to working accuracy
+        b64 = b.astype(np.float64)
+        x = lv.pinv @ b64
+        x = x + lv.pinv @ (b64 - lv.A @ x)
+        return x.astype(P.dtype)
     smooth(P, li, x, b, prob.nu1)
     r2 = P.I[li].T @ (b - P.A[li] @ x)
     x2 = vcycle(P, li + 1, np.zeros_like(r2), r2)
