@@ -1,0 +1,169 @@
+"""Benchmark: LDG-Stokes multigrid on one MI355X.
+
+Workload (the configuration the metric is quoted on): 2D steady viscous-stress
+Stokes on the unit square with Dirichlet walls, 256x256 elements, Q_3
+(48 unknowns per element, 3,145,728 unknowns), mu = 1 + 0.9 sin(2 pi x) sin(2 pi y),
+the paper's manufactured solution.  Synthetic data, generated in-process.
+
+One step = one solve from x = 0 to ||b - A x|| <= 1e-10 ||b|| with the FP32
+V-cycle (V(3,3), parity colouring) inside FP64 iterative refinement: every
+stage of the hot path (smoother colour passes, residual + restriction,
+prolongation, bottom pseudo-inverse, FP64 outer residual) runs in the HIP
+library.  value = V-cycle DOF/s inside those solves (unknowns x V-cycles /
+solve time).  The plain FP64 stationary V-cycle to the same tolerance, and
+the BF16-block variant, are measured beside it.
+
+The roofline object covers the dominant kernel (the finest-level smoother
+colour pass), timed with HIP events on the library's stream during the timed
+solves; the algorithmic bytes per launch are (elements in the colour) x
+(n_b^2 inverse entries + 3 n_b vector entries + (p+2)^d viscosity values) x
+the storage width.  cpu_baseline times the FP64 oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_smooth_colour_c2_n256_p3.json")
+
+
+def smoother_bytes_per_launch(prob, ncolours, inv_bytes, vec_bytes):
+    nb = prob.nb
+    per_elem = nb * nb * inv_bytes + 3 * nb * vec_bytes + (prob.p + 2) ** prob.dim * vec_bytes
+    return prob.n_elements / ncolours * per_elem
+
+
+def cpu_baseline(n_sample=32, cycles=15):
+    """The FP64 oracle's V-cycle on the n_sample^2 grid of the same problem."""
+    from threadpoolctl import threadpool_limits
+    from synth import c2_dirichlet_varmu
+    from oracle import build_hierarchy
+    from oracle.rhs import assemble_rhs
+    from oracle.solvers import Solver
+    prob = c2_dirichlet_varmu(n=n_sample, p=3)
+    with threadpool_limits(limits=1):
+        H = build_hierarchy(prob)
+        b = assemble_rhs(prob, H.fine.ops)
+        S = Solver(H)
+        t0 = time.perf_counter()
+        x = None
+        for _ in range(cycles):
+            x = S.vcycle_unscaled(b, x)
+        dt = time.perf_counter() - t0
+    return dict(value=prob.n_dof * cycles / dt, unit="DOF/s", cores=1, kind="oracle",
+                sample=f"FP64 oracle V(3,3) cycles on the {n_sample}x{n_sample} Q_3 grid of the same problem "
+                       f"({prob.n_dof} unknowns, {cycles} cycles, {dt:.1f} s); scipy sparse products, one thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP64 / BF16 comparison solves")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU domain decomposition is a design, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1911_05888_amd import Context, V_FP64, V_FP32, V_FP32_BF16BLK, STATIONARY, IR
+    from synth import c2_dirichlet_varmu
+
+    prob = c2_dirichlet_varmu(n=args.n, p=3)
+    t0 = time.perf_counter()
+    ctx = Context(prob, vprec=V_FP32, build_precisions=(1 << V_FP64) | (1 << V_FP32_BF16BLK))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    print(f"[bench] setup {t_setup:.1f} s, {ctx.ndof} unknowns, {ctx.n_levels} levels", file=sys.stderr, flush=True)
+    b0 = ctx.assemble_rhs(prob.exact)
+    ncol = ctx.level_info(0)[2]
+
+    def solve(vprec, outer, tol=1e-10, maxit=60):
+        ctx.set_vprec(vprec)
+        b = b0.clone()
+        x = torch.zeros_like(b)
+        st, info = ctx.solve(b, x, tol=tol, maxit=maxit, outer=outer)
+        if st != 0:
+            raise RuntimeError(f"solve failed: status {st}, {info}")
+        return info
+
+    for _ in range(args.warmup):
+        solve(V_FP32, IR)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    iters = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info = solve(V_FP32, IR)
+        iters += info["iters"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k_ms, k_launches = ctx.profile_read()
+    ctx.profile(False)
+    value = ctx.ndof * iters / dt
+    ms_per_step = 1e3 * dt / args.steps
+    print(f"[bench] mixed FP32-in-IR: {iters / args.steps:.1f} V-cycles/solve, {ms_per_step:.2f} ms/solve",
+          file=sys.stderr, flush=True)
+
+    bytes_launch = smoother_bytes_per_launch(prob, ncol, 4, 4)
+    avg_s = k_ms * 1e-3 / max(k_launches, 1)
+    achieved = bytes_launch / avg_s / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            traffic = json.load(fh).get("bytes_per_launch")
+
+    extras = {}
+    if not args.no_extras:
+        for label, vp, outer in [("plain_fp64_stationary", V_FP64, STATIONARY),
+                                 ("fp32_bf16blk_ir", V_FP32_BF16BLK, IR)]:
+            solve(vp, outer)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            reps = 3
+            its = 0
+            for _ in range(reps):
+                its += solve(vp, outer)["iters"]
+            torch.cuda.synchronize()
+            tt = (time.perf_counter() - t1) / reps
+            extras[label] = dict(time_to_tol_s=tt, iters=its / reps, vcycle_dof_per_s=ctx.ndof * its / reps / tt)
+            print(f"[bench] {label}: {its / reps:.1f} iters, {tt * 1e3:.2f} ms", file=sys.stderr, flush=True)
+
+    line = dict(
+        metric="V-cycle DOF/s + wall time to 1e-10 rel. residual, plain FP64 vs mixed/learned",
+        value=value, unit="DOF/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=ms_per_step, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="fp32 V-cycle, fp64 outer residual", data="synthetic",
+        config=dict(workload=f"2D viscous-stress Stokes, Dirichlet walls, {args.n}x{args.n} elements, Q_3, "
+                             "mu = 1 + 0.9 sin2pi x sin2pi y, manufactured solution; "
+                             "FP32 V(3,3) in FP64 iterative refinement to 1e-10",
+                    n=args.n, p=3, unknowns=ctx.ndof, levels=ctx.n_levels, colours=ncol,
+                    time_to_tol_s=dt / args.steps, vcycles_per_solve=iters / args.steps,
+                    setup_s=t_setup, **extras),
+        roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=achieved / HBM_PEAK_GBS, traffic=traffic,
+                      kernel="k_smooth_colour<float,float,2,3> (finest level)",
+                      avg_launch_us=avg_s * 1e6, algorithmic_bytes_per_launch=bytes_launch,
+                      launches=k_launches),
+    )
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

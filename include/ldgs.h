@@ -1,0 +1,274 @@
+/*
+ * ldgs.h -- C ABI of the LDG-Stokes multigrid library for MI355X (gfx950).
+ *
+ * The library solves the discrete (multi-phase, optionally unsteady) Stokes
+ * system of Saye, "Fast multigrid solution of high-order accurate multi-phase
+ * Stokes problems": the LDG saddle-point operator of eq. (blockform) /
+ * eq. (stokessystem) on a uniform Cartesian grid of the unit square or cube,
+ * with the V-cycle of Algorithm 1 (element-block Gauss-Seidel smoothing in a
+ * fixed multicolour order, injection prolongation, restriction by its
+ * transpose, an eigen-decomposition pseudo-inverse at the bottom) and the
+ * operator-coarsened hierarchy of Algorithms 2 and 3.
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an ldgs_status and never throws.  On error the
+ *    context (if any) keeps a message readable with ldgs_last_error().
+ *  - Vectors b and x are caller-owned FP64 device pointers of length
+ *    ldgs_num_dofs(), element-lexicographic (axis 0 fastest); within an
+ *    element field-major (u_1 .. u_d, p); within a field the coefficients of
+ *    the orthonormal tensor-product Legendre basis
+ *      phi_a(x) = h^{-d/2} prod_k l_{a_k}((x_k - x_{E,k}) / h),
+ *      l_m(xi) = sqrt(2m+1) P_m(2 xi - 1),  a = sum_k a_k (p+1)^k.
+ *    Pointers must be 8-byte aligned and must not alias unless stated.
+ *  - All device work is ordered on the stream given in ldgs_problem; calls
+ *    that return host-visible results (norms, convergence) synchronise it.
+ *  - A context is not thread-safe.  Distinct contexts are independent.
+ */
+#ifndef LDGS_H
+#define LDGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LDGS_OK = 0,
+  LDGS_E_ARG = 1,            /* invalid argument (null pointer, bad size, bad enum) */
+  LDGS_E_UNSUPPORTED = 2,    /* a valid but unimplemented combination */
+  LDGS_E_NOMEM = 3,          /* host or device allocation failed */
+  LDGS_E_HIP = 4,            /* a HIP runtime call failed */
+  LDGS_E_SINGULAR_BLOCK = 5, /* an element block A_EE is numerically singular */
+  LDGS_E_COLORING = 6,       /* the colouring couples two elements of one colour */
+  LDGS_E_NOT_CONVERGED = 7,  /* tolerance not reached within maxit, or divergence */
+  LDGS_E_NONFINITE = 8       /* a NaN or Inf appeared in a residual norm */
+} ldgs_status;
+
+/* gamma of eq. (govern1): 0 standard form -mu lap u, 1 viscous-stress form. */
+typedef enum { LDGS_STANDARD = 0, LDGS_VISCOUS_STRESS = 1 } ldgs_form;
+
+/* Boundary condition of one axis (both sides); eq. (govern3).  Stress
+ * boundaries are declared but return LDGS_E_UNSUPPORTED. */
+typedef enum { LDGS_PERIODIC = 0, LDGS_DIRICHLET = 1, LDGS_STRESS = 2 } ldgs_bc;
+
+/* Multicolour ordering of the block Gauss-Seidel smoother (section 3).
+ * Colour of element i = (i_0, .., i_{d-1}):
+ *   RED_BLACK  sum_k i_k mod 2                 (2 colours)
+ *   PARITY     sum_k (i_k mod 2) 2^k           (2^d colours)
+ *   MOD3       sum_k (i_k mod 3) 3^k           (3^d colours)
+ * AUTO picks the first of these that is proper for the operator's stencil;
+ * a colouring that couples two same-coloured elements gives LDGS_E_COLORING.
+ * Colours are swept in increasing order in pre- and post-smoothing. */
+typedef enum { LDGS_COLOR_AUTO = 0, LDGS_COLOR_RED_BLACK = 1, LDGS_COLOR_PARITY = 2,
+               LDGS_COLOR_MOD3 = 3 } ldgs_coloring;
+
+/* Arithmetic of the V-cycle.  FP64: everything in double.  FP32: smoother,
+ * residuals and transfers in float with float block inverses (computed in
+ * double); bottom solve in double.  FP32_BF16BLK: as FP32 but the block
+ * inverses are stored as bfloat16. */
+typedef enum { LDGS_V_FP64 = 0, LDGS_V_FP32 = 1, LDGS_V_FP32_BF16BLK = 2 } ldgs_vprec;
+
+/* Outer iteration of ldgs_solve.  STATIONARY: x <- V(b, x).  IR: r = b - A x
+ * in FP64, x += V(r, 0).  FGMRES: flexible GMRES(m), right-preconditioned by
+ * one V-cycle from zero, FP64 Arnoldi with modified Gram-Schmidt. */
+typedef enum { LDGS_STATIONARY = 0, LDGS_IR = 1, LDGS_FGMRES = 2 } ldgs_outer;
+
+/* Scalar coefficient fields (viscosity mu, density rho). */
+typedef enum {
+  LDGS_FIELD_CONST = 0,         /* params[0] = c */
+  LDGS_FIELD_SINSIN = 1,        /* a + b prod_k sin(2 pi k x_k): params = {a, b, k} */
+  LDGS_FIELD_LOGNORMAL_RFF = 2, /* 10^{g}, g = sqrt(2/K) sum_m cos(k_m . x + phi_m):
+                                   params = {k_1 (d values) .. k_K, phi_1 .. phi_K},
+                                   nparams = K (d + 1) */
+  LDGS_FIELD_PHASE_CONST = 3,   /* params[0] in phase 1, params[1] in phase 2 */
+  LDGS_FIELD_CALLBACK = 4       /* values from fn */
+} ldgs_field_kind;
+
+/* Level set describing the phases.  NONE: one phase.  BOX: phase 1 is the
+ * open box (params[0], params[1])^d, phase 2 its complement; box faces must
+ * lie on element faces of the coarsest grid.  Curved interfaces return
+ * LDGS_E_UNSUPPORTED. */
+typedef enum { LDGS_LEVELSET_NONE = 0, LDGS_LEVELSET_BOX = 1 } ldgs_levelset_kind;
+
+/* Batched host callback: evaluate at n points x (n x d, row-major).  phase[i]
+ * is the phase (1 or 2) of the element owning point i; normal (n x d) is the
+ * face normal where the quantity lives on a face (NULL in volumes).  Writes
+ * n x ncomp values to out. */
+typedef void (*ldgs_eval_fn)(int64_t n, const double* x, const int* phase,
+                             const double* normal, double* out, void* user);
+
+typedef struct {
+  int kind;                 /* ldgs_field_kind */
+  const double* params;     /* host, read during ldgs_setup only */
+  int64_t nparams;
+  ldgs_eval_fn fn;          /* for LDGS_FIELD_CALLBACK */
+  void* user;
+} ldgs_field;
+
+typedef struct {
+  int dim;                  /* d in {2, 3} */
+  int n;                    /* elements per axis, a power of two */
+  int degree;               /* p in {1, 2, 3} (Q_p, same degree for u and p) */
+  int form;                 /* ldgs_form (gamma) */
+  int bc[3];                /* ldgs_bc per axis, both sides */
+  ldgs_field mu;            /* viscosity > 0 */
+  ldgs_field rho;           /* density >= 0, used when delta > 0 */
+  double delta;             /* > 0: unsteady operator (1/delta) M_rho + A of eq. (timedep2) */
+  int levelset_kind;        /* ldgs_levelset_kind */
+  double levelset_params[2];
+  double tau;               /* pressure penalty prefactor of eq. (taueqn); <= 0: Table 1 */
+  double tau0;              /* unsteady prefactor of eq. (taugeneral); <= 0: 0.5 p */
+  double tau_u_bdry_C;      /* tau_u,boundary = C p mu^- / h; <= 0: 10 */
+  double tau_u_inter_C;     /* tau_u,interphase = C p min(mu) / h; <= 0: 3 */
+  int nu1, nu2;             /* pre-/post-smoothing sweeps; <= 0: 3 */
+  int coarsest_n;           /* bottom grid size; <= 0: 4 (2D), 2 (3D) */
+  int coloring;             /* ldgs_coloring */
+  int vprec;                /* ldgs_vprec used by ldgs_vcycle / ldgs_solve */
+  int build_precisions;     /* bit mask of extra V-cycle precisions to build
+                               (bit k = ldgs_vprec k); 0: only vprec */
+  int diag_scaling;         /* nonzero: (alpha, beta) scaling of the multi-phase section */
+  int host_only;            /* nonzero: build the host-side operator data only (setup
+                               validation without a GPU); device entry points then
+                               return LDGS_E_UNSUPPORTED and ldgs_assemble_rhs writes
+                               to a host pointer */
+  void* hip_stream;         /* hipStream_t; NULL = default stream */
+} ldgs_problem;
+
+/* Data of the right-hand side, eq. (govern1)-(govern3).  Each callback may be
+ * NULL (meaning zero).  ncomp: f d, f_div 1, g_dirichlet d, g_jump d, h_jump d.
+ * g_jump / h_jump are the jumps [u] and [sigma n] on interphase faces, normal
+ * from phase 1 into phase 2, phase[] giving the phase-1 side. */
+typedef struct {
+  ldgs_eval_fn f, f_div, g_dirichlet, g_jump, h_jump;
+  void* user;
+} ldgs_rhs_data;
+
+typedef struct {
+  int iters;                /* outer iterations (V-cycles) performed */
+  int fallback_events;      /* learned correction switched off (0 otherwise) */
+  double relres;            /* final ||b - A x||_2 / ||b||_2, FP64, recomputed */
+  double rho_measured;      /* geometric mean residual reduction per iteration */
+  double t_solve_s;         /* wall time of the solve */
+  double* history;          /* caller-owned host array, or NULL */
+  int history_cap;
+  int history_len;          /* relres after each iteration, history[0] = 1 */
+} ldgs_info;
+
+typedef struct ldgs_ctx ldgs_ctx;
+
+/* Build every level (operator coarsening, Algorithms 2/3), the colouring,
+ * the factorised diagonal blocks of each smoothed level (explicit FP64
+ * inverses of the equilibrated LU, then cast) and the bottom pseudo-inverse.
+ * Synchronises.  *out receives a new context owned by the caller. */
+ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out);
+
+/* Number of unknowns N = n^d (d+1) (p+1)^d. */
+ldgs_status ldgs_num_dofs(const ldgs_ctx* ctx, int64_t* ndof);
+
+/* b of eq. (stokessystem): momentum rows int f_i phi - sum_j G_j^T M_mu
+ * (J_g,ij + gamma J_g,ji) + J_h,i + penalty data; constraint rows int f phi +
+ * J_{g.n} (appendix A).  Assembled on the host, copied to b_dev.  Synchronises. */
+ldgs_status ldgs_assemble_rhs(ldgs_ctx* ctx, const ldgs_rhs_data* data, double* b_dev);
+
+/* y = A x (FP64, unscaled operator), matrix-free.  x and y must not alias. */
+ldgs_status ldgs_apply(ldgs_ctx* ctx, const double* x_dev, double* y_dev);
+
+/* r = b - A x (FP64); if norm2_host is non-NULL, *norm2_host = ||r||_2
+ * (synchronises).  r may be NULL when only the norm is wanted. */
+ldgs_status ldgs_residual(ldgs_ctx* ctx, const double* b_dev, const double* x_dev,
+                          double* r_dev, double* norm2_host);
+
+/* One V-cycle of Algorithm 1 in place on x, in the context's precision. */
+ldgs_status ldgs_vcycle(ldgs_ctx* ctx, const double* b_dev, double* x_dev);
+
+/* Solve A x = b to ||b - A x|| <= tol ||b|| from the x given (use zeros).
+ * b is first projected onto range(A) (its components along the trivial
+ * kernel are removed, in place).  maxit bounds the outer iterations;
+ * fgmres_m is the restart length; use_learned applies the learned
+ * correction after each cycle's post-smoothing (requires ldgs_set_learned).
+ * info may be NULL.  Synchronises. */
+ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b_dev, double* x_dev, double tol, int maxit,
+                       int outer, int fgmres_m, int use_learned, ldgs_info* info);
+
+/* Switch the precision used by ldgs_vcycle / ldgs_solve among those built. */
+ldgs_status ldgs_set_vprec(ldgs_ctx* ctx, int vprec);
+
+/* Learned correction weights (device blob, copied).  Returns
+ * LDGS_E_UNSUPPORTED in this version. */
+ldgs_status ldgs_set_learned(ldgs_ctx* ctx, const void* weights_dev, int64_t nbytes);
+
+/* Remove from v its components along the trivial kernel (constant pressure,
+ * and constant velocity for periodic steady problems), in place. */
+ldgs_status ldgs_project_kernel(ldgs_ctx* ctx, double* v_dev);
+
+/* ---- Stage entry points (one step of the hot path on one level) --------
+ * Level 0 is the finest.  Level vectors have n_l^d (d+1)(p+1)^d FP64 entries
+ * in the layout above.  They operate on the operator of that level as used by
+ * the V-cycle (diagonally scaled when diag_scaling is on) in FP64. */
+
+/* Grid size n_l, number of levels and colours. */
+ldgs_status ldgs_level_info(const ldgs_ctx* ctx, int level, int* n_l, int* n_levels, int* n_colours);
+
+/* One colour pass of block Gauss-Seidel on level `level`: for every element E
+ * of colour `colour`, x_E += A_EE^{-1} (b - A x)_E, all from the x at entry. */
+ldgs_status ldgs_level_smooth_colour(ldgs_ctx* ctx, int level, int colour,
+                                     const double* b_dev, double* x_dev);
+
+/* The same colour pass in a float V-cycle (vprec FP32 or FP32_BF16BLK): b and x
+ * are float device vectors of the level, in the scaled variables of that
+ * cycle when diag_scaling is on. */
+ldgs_status ldgs_level_smooth_colour_f32(ldgs_ctx* ctx, int level, int colour, int vprec,
+                                         const float* b_dev, float* x_dev);
+
+/* r_c = I^T (b - A_l x) on level `level` (< bottom); r_c has level+1 size. */
+ldgs_status ldgs_level_residual_restrict(ldgs_ctx* ctx, int level, const double* b_dev,
+                                         const double* x_dev, double* rc_dev);
+
+/* x += I x_c, injection from level+1 to level. */
+ldgs_status ldgs_level_prolong_add(ldgs_ctx* ctx, int level, const double* xc_dev, double* x_dev);
+
+/* x = A_bottom^+ b on the bottom level: the least-squares solution with the
+ * FP64 eigendecomposition pseudo-inverse (near-zero eigenvalues snapped to
+ * zero), applied with one step of iterative refinement. */
+ldgs_status ldgs_bottom_solve(ldgs_ctx* ctx, const double* b_dev, double* x_dev);
+
+/* y = A_l x on level `level`. */
+ldgs_status ldgs_level_apply(ldgs_ctx* ctx, int level, const double* x_dev, double* y_dev);
+
+/* The FP64 inverse of the diagonal block A_EE of element E on `level` (the
+ * equilibrated-LU inverse that the smoother streams), row-major nb*nb doubles
+ * written to a host array. */
+ldgs_status ldgs_level_block_inverse(ldgs_ctx* ctx, int level, int64_t element, double* inv_host);
+
+/* y = A_l x on `level` evaluated by the host implementation of the operator
+ * that setup uses for the bottom matrix and the right-hand side (host arrays).
+ * For validating the setup; the solver never calls it. */
+ldgs_status ldgs_host_level_apply(ldgs_ctx* ctx, int level, const double* x_host, double* y_host);
+
+/* The bottom pseudo-inverse (row-major N_c x N_c doubles, host array) and the
+ * eigenvalues of the bottom operator (N_c doubles, ascending magnitude order
+ * not guaranteed); either pointer may be NULL.  *nc receives N_c. */
+ldgs_status ldgs_bottom_info(ldgs_ctx* ctx, int64_t* nc, double* pinv_host, double* eig_host);
+
+/* Timing of the finest-level smoother launches.  With profiling enabled the
+ * library records a HIP event pair on its stream around every colour pass of
+ * level 0; ldgs_profile_read synchronises, returns the summed kernel time (ms)
+ * and the number of launches since the last read, and clears them. */
+ldgs_status ldgs_profile(ldgs_ctx* ctx, int enable);
+ldgs_status ldgs_profile_read(ldgs_ctx* ctx, double* total_ms, int64_t* launches);
+
+const char* ldgs_status_str(ldgs_status s);
+/* Message of the context's last error; with ctx = NULL, the message of the
+ * calling thread's last failed ldgs_setup. */
+const char* ldgs_last_error(const ldgs_ctx* ctx);
+
+/* Free all device and host storage of the context.  NULL is allowed. */
+ldgs_status ldgs_destroy(ldgs_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDGS_H */

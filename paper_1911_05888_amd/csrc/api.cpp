@@ -1,0 +1,963 @@
+// C ABI of the LDG-Stokes library: setup (host hierarchy + device upload),
+// the V-cycle driver (Algorithm 1) and the outer iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "build.hpp"
+#include "host.hpp"
+
+namespace ldgs {
+void assemble_rhs_host(const ldgs_problem& P, const Geometry& g, const Basis& B, const Level& L,
+                       const ldgs_rhs_data& data, double* out);
+}
+
+using namespace ldgs;
+
+namespace {
+
+struct Fail {
+  ldgs_status st;
+  std::string msg;
+};
+
+#define HIPCHK(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) throw Fail{LDGS_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define LCHK(call)                                                                \
+  do {                                                                            \
+    int r_ = (call);                                                              \
+    if (r_ == 2) throw Fail{LDGS_E_UNSUPPORTED, std::string(#call) + ": no kernel for this d/p"}; \
+    if (r_ != 0) throw Fail{LDGS_E_HIP, std::string(#call) + ": launch failed"};  \
+  } while (0)
+
+template <typename T>
+struct PrecLevel {
+  DevLevel<T> view{};            // the V-cycle's (possibly scaled) operator
+  DevLevel<T> unscaled{};        // same data, no scaling (finest level, outer residual)
+  const void* inv = nullptr;     // colour-major, column-major blocks
+  int inv_kind = 0;              // 0 double, 1 float, 2 bf16
+  int* elems = nullptr;          // colour-major element ids
+  std::vector<int64_t> col_off;  // colour offsets (elements)
+  T* x = nullptr;                // level work vectors (levels >= 1)
+  T* b = nullptr;
+};
+
+template <typename T>
+struct PrecStore {
+  bool built = false;           // full V-cycle data
+  bool ops = false;             // operator data uploaded
+  std::vector<PrecLevel<T>> lv;
+};
+
+}  // namespace
+
+struct ldgs_ctx {
+  ldgs_problem P{};
+  Geometry g;
+  Basis B;
+  Tab1D tab{};
+  std::vector<Level> levels;
+  std::string err;
+  bool host_only = false;
+  hipStream_t stream = nullptr;
+  int vprec = 0;
+  int k0 = 1;
+  std::vector<int> kernel_offsets;
+  PrecStore<double> s64;
+  PrecStore<float> s32;      // float arithmetic, float inverses
+  PrecStore<float> s16;      // float arithmetic, bf16 inverses (shares operator data with s32)
+  double* d_pinv = nullptr;
+  double* d_Ac = nullptr;            // bottom operator (dense), for the refinement step
+  double *d_bt0 = nullptr, *d_bt1 = nullptr, *d_bt2 = nullptr;   // bottom temporaries
+  int64_t Nc = 0;
+  std::vector<double> h_pinv, h_eig, h_Ac;
+  // finest-size work vectors
+  double *w_b = nullptr, *w_x = nullptr, *w_r = nullptr, *w_z = nullptr, *w_part = nullptr;
+  float *w_b32 = nullptr, *w_x32 = nullptr;
+  double* d_dscale0 = nullptr;      // finest-level scaling (double) for user <-> scaled
+  std::vector<double*> kry;         // FGMRES basis storage
+  // optional timing of the finest-level smoother launches (HIP events on the stream)
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<void*> allocs;
+  ~ldgs_ctx() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    for (void* p : allocs) (void)hipFree(p);
+    if (stream_owned && stream) (void)hipStreamDestroy(stream);
+  }
+  bool stream_owned = false;
+  int64_t ndof() const { return levels.empty() ? 0 : levels[0].NE * g.nb; }
+};
+
+namespace {
+
+template <typename T>
+T* dalloc(ldgs_ctx* c, size_t count) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&p, count * sizeof(T));
+  if (e != hipSuccess) throw Fail{LDGS_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+  c->allocs.push_back(p);
+  return (T*)p;
+}
+
+template <typename T>
+T* upload(ldgs_ctx* c, const std::vector<double>& src) {
+  T* d = dalloc<T>(c, src.size());
+  if (!src.empty()) {
+    std::vector<T> tmp(src.begin(), src.end());
+    HIPCHK(hipMemcpy(d, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
+  }
+  return d;
+}
+
+int kernel_dim(const ldgs_problem& P) {
+  bool per = true;
+  for (int j = 0; j < P.dim; ++j) per = per && P.bc[j] == LDGS_PERIODIC;
+  return (per && !(P.delta > 0.0)) ? P.dim + 1 : 1;
+}
+
+void fill_defaults(ldgs_problem& P) {
+  static const double tab_std[2][5] = {{0.19, 0.10, 0.086, 0.019, 0.031}, {0.12, 0.088, 0.084, 0, 0}};
+  static const double tab_vs[2][5] = {{0.14, 0.046, 0.034, 0.0095, 0.011}, {0.12, 0.039, 0.040, 0, 0}};
+  if (!(P.tau > 0)) P.tau = (P.form ? tab_vs : tab_std)[P.dim - 2][P.degree - 1];
+  if (!(P.tau0 > 0)) P.tau0 = 0.5 * P.degree;
+  if (!(P.tau_u_bdry_C > 0)) P.tau_u_bdry_C = 10.0;
+  if (!(P.tau_u_inter_C > 0)) P.tau_u_inter_C = 3.0;
+  if (P.nu1 <= 0) P.nu1 = 3;
+  if (P.nu2 <= 0) P.nu2 = 3;
+  if (P.coarsest_n <= 0) P.coarsest_n = (P.dim == 2) ? 4 : 2;
+}
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+void validate(const ldgs_problem& P) {
+  if (P.dim != 2 && P.dim != 3) throw Fail{LDGS_E_ARG, "dim must be 2 or 3"};
+  if (P.degree < 1 || P.degree > 3) throw Fail{LDGS_E_ARG, "degree must be 1..3"};
+  if (P.dim == 3 && P.degree > 2) throw Fail{LDGS_E_UNSUPPORTED, "3D supports p <= 2"};
+  if (!pow2(P.n) || !pow2(P.coarsest_n) || P.coarsest_n < 2 || P.coarsest_n > P.n)
+    throw Fail{LDGS_E_ARG, "n and coarsest_n must be powers of two with 2 <= coarsest_n <= n"};
+  if (P.form != 0 && P.form != 1) throw Fail{LDGS_E_ARG, "form"};
+  for (int j = 0; j < P.dim; ++j) {
+    if (P.bc[j] == LDGS_STRESS) throw Fail{LDGS_E_UNSUPPORTED, "stress boundary conditions"};
+    if (P.bc[j] != LDGS_PERIODIC && P.bc[j] != LDGS_DIRICHLET) throw Fail{LDGS_E_ARG, "bc"};
+  }
+  if (P.levelset_kind != LDGS_LEVELSET_NONE) {
+    if (P.levelset_kind != LDGS_LEVELSET_BOX) throw Fail{LDGS_E_UNSUPPORTED, "curved level sets"};
+    throw Fail{LDGS_E_UNSUPPORTED, "interphase faces are not supported by the GPU smoother yet"};
+  }
+  if (P.delta > 0.0) {
+    if (P.rho.kind != LDGS_FIELD_CONST || P.mu.kind != LDGS_FIELD_CONST)
+      throw Fail{LDGS_E_UNSUPPORTED, "unsteady problems need constant mu and rho"};
+    if (!(P.rho.params && P.rho.params[0] > 0)) throw Fail{LDGS_E_ARG, "rho must be positive"};
+  }
+  if (P.mu.kind < 0 || P.mu.kind > LDGS_FIELD_CALLBACK) throw Fail{LDGS_E_ARG, "mu kind"};
+  if (P.mu.kind != LDGS_FIELD_CALLBACK && !P.mu.params) throw Fail{LDGS_E_ARG, "mu params"};
+  if (P.mu.kind == LDGS_FIELD_CALLBACK && !P.mu.fn) throw Fail{LDGS_E_ARG, "mu callback"};
+  if (P.vprec < 0 || P.vprec > 2) throw Fail{LDGS_E_ARG, "vprec"};
+  if (P.coloring < 0 || P.coloring > 3) throw Fail{LDGS_E_ARG, "coloring"};
+}
+
+// smoothed levels: colouring, blocks, inverses
+void build_smoother_host(ldgs_ctx* c) {
+  const int d = c->g.d;
+  for (size_t l = 0; l + 1 < c->levels.size(); ++l) {
+    Level& L = c->levels[l];
+    int scheme = c->P.coloring;
+    int64_t bad = -1;
+    if (scheme == LDGS_COLOR_AUTO) {
+      const int order[3] = {LDGS_COLOR_RED_BLACK, LDGS_COLOR_PARITY, LDGS_COLOR_MOD3};
+      scheme = -1;
+      for (int s : order)
+        if (colouring_is_proper(L, d, s, c->P.form, &bad)) { scheme = s; break; }
+      if (scheme < 0) throw Fail{LDGS_E_COLORING, "no proper colouring found"};
+    } else if (!colouring_is_proper(L, d, scheme, c->P.form, &bad)) {
+      throw Fail{LDGS_E_COLORING, "colouring couples two elements of one colour at element " + std::to_string(bad) +
+                                       " on level " + std::to_string(l)};
+    }
+    set_colouring(L, d, scheme);
+  }
+}
+
+template <typename T>
+DevLevel<T> make_view(ldgs_ctx* c, const Level& L, bool with_scale) {
+  DevLevel<T> v{};
+  const int d = c->g.d, mt = c->g.mt, nq = c->g.nq;
+  v.n = L.n;
+  v.hinv = (T)(1.0 / L.h);
+  for (int k = 0; k < 3; ++k) {
+    if (k < d) {
+      const FaceSet& fs = L.faces[k];
+      v.nf[k] = fs.nfk;
+      unsigned char* ft = dalloc<unsigned char>(c, fs.count);
+      HIPCHK(hipMemcpy(ft, fs.type.data(), fs.count, hipMemcpyHostToDevice));
+      v.ftype[k] = ft;
+      v.fw[k] = upload<T>(c, fs.w);
+      v.fT[k] = upload<T>(c, fs.T);
+    } else {
+      v.nf[k] = 0;
+      v.ftype[k] = nullptr;
+      v.fw[k] = nullptr;
+      v.fT[k] = nullptr;
+    }
+  }
+  (void)mt;
+  (void)nq;
+  v.mmu = L.mu_is_const ? nullptr : upload<T>(c, L.mmu);
+  v.mu_const = (T)L.mu_c;
+  v.rho_delta = (T)L.rho_delta;
+  v.dscale = (with_scale && !L.dscale.empty()) ? upload<T>(c, L.dscale) : nullptr;
+  v.gamma = c->P.form;
+  return v;
+}
+
+template <typename T>
+void upload_ops(ldgs_ctx* c, PrecStore<T>& S, bool all_levels) {
+  size_t nl = all_levels ? c->levels.size() : 1;
+  S.lv.resize(c->levels.size());
+  for (size_t l = 0; l < nl; ++l) {
+    S.lv[l].view = make_view<T>(c, c->levels[l], true);
+    S.lv[l].unscaled = S.lv[l].view;
+    S.lv[l].unscaled.dscale = nullptr;
+    if (l > 0) {
+      int64_t n = c->levels[l].NE * c->g.nb;
+      S.lv[l].x = dalloc<T>(c, n);
+      S.lv[l].b = dalloc<T>(c, n);
+    }
+  }
+  S.ops = true;
+}
+
+// inverse blocks of all smoothed levels into the stores that need them
+void build_inverses(ldgs_ctx* c, bool need64, bool need32, bool need16) {
+  const int nb = c->g.nb;
+  const size_t nb2 = (size_t)nb * nb;
+  for (size_t l = 0; l + 1 < c->levels.size(); ++l) {
+    Level& L = c->levels[l];
+    std::vector<int64_t> off(L.ncol + 1, 0);
+    for (int col = 0; col < L.ncol; ++col) off[col + 1] = off[col] + (int64_t)L.elems[col].size();
+    std::vector<int> order;
+    order.reserve(L.NE);
+    for (int col = 0; col < L.ncol; ++col) order.insert(order.end(), L.elems[col].begin(), L.elems[col].end());
+    double* inv64 = need64 ? dalloc<double>(c, L.NE * nb2) : nullptr;
+    float* inv32 = need32 ? dalloc<float>(c, L.NE * nb2) : nullptr;
+    uint16_t* inv16 = need16 ? dalloc<uint16_t>(c, L.NE * nb2) : nullptr;
+    int* elems = dalloc<int>(c, L.NE);
+    HIPCHK(hipMemcpy(elems, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice));
+    const int64_t CH = 8192;
+    std::vector<double> buf;
+    std::vector<float> buf32;
+    std::vector<uint16_t> buf16;
+    for (int64_t p0 = 0; p0 < L.NE; p0 += CH) {
+      int64_t cnt = std::min(CH, L.NE - p0);
+      buf.assign(cnt * nb2, 0.0);
+      int failed = -1;
+#pragma omp parallel
+      {
+        std::vector<double> A(nb2), inv(nb2);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < cnt; ++i) {
+          int64_t E = order[p0 + i];
+          host_diag_block(L, c->g, c->B, c->P.form, E, A.data());
+          if (!block_inverse(nb, A.data(), inv.data(), 1e-14)) {
+#pragma omp critical
+            failed = (int)E;
+            continue;
+          }
+          double* dst = buf.data() + i * nb2;   // column-major: dst[j*nb + r] = inv[r][j]
+          for (int r = 0; r < nb; ++r)
+            for (int j = 0; j < nb; ++j) dst[(size_t)j * nb + r] = inv[(size_t)r * nb + j];
+        }
+      }
+      if (failed >= 0)
+        throw Fail{LDGS_E_SINGULAR_BLOCK, "singular element block " + std::to_string(failed) + " on level " +
+                                              std::to_string(l)};
+      if (inv64) HIPCHK(hipMemcpy(inv64 + p0 * nb2, buf.data(), cnt * nb2 * sizeof(double), hipMemcpyHostToDevice));
+      if (inv32) {
+        buf32.assign(buf.begin(), buf.end());
+        HIPCHK(hipMemcpy(inv32 + p0 * nb2, buf32.data(), cnt * nb2 * sizeof(float), hipMemcpyHostToDevice));
+      }
+      if (inv16) {
+        buf16.resize(buf.size());
+        for (size_t i = 0; i < buf.size(); ++i) {
+          float f = (float)buf[i];
+          uint32_t u;
+          std::memcpy(&u, &f, 4);
+          u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
+          buf16[i] = (uint16_t)(u >> 16);
+        }
+        HIPCHK(hipMemcpy(inv16 + p0 * nb2, buf16.data(), cnt * nb2 * sizeof(uint16_t), hipMemcpyHostToDevice));
+      }
+    }
+    if (need64) { c->s64.lv[l].inv = inv64; c->s64.lv[l].inv_kind = 0; c->s64.lv[l].elems = elems; c->s64.lv[l].col_off = off; }
+    if (need32) { c->s32.lv[l].inv = inv32; c->s32.lv[l].inv_kind = 1; c->s32.lv[l].elems = elems; c->s32.lv[l].col_off = off; }
+    if (need16) { c->s16.lv[l].inv = inv16; c->s16.lv[l].inv_kind = 2; c->s16.lv[l].elems = elems; c->s16.lv[l].col_off = off; }
+  }
+}
+
+void build_bottom(ldgs_ctx* c) {
+  Level& L = c->levels.back();
+  const int64_t N = L.NE * c->g.nb;
+  c->Nc = N;
+  std::vector<double> A((size_t)N * N), e(N, 0.0), col(N);
+  for (int64_t j = 0; j < N; ++j) {
+    e[j] = 1.0;
+    host_apply(L, c->g, c->B, c->P.form, e.data(), col.data());
+    e[j] = 0.0;
+    for (int64_t i = 0; i < N; ++i) A[(size_t)i * N + j] = col[i];
+  }
+  c->h_Ac = A;
+  for (int64_t i = 0; i < N; ++i)
+    for (int64_t j = i + 1; j < N; ++j) {
+      double s = 0.5 * (A[(size_t)i * N + j] + A[(size_t)j * N + i]);
+      A[(size_t)i * N + j] = s;
+      A[(size_t)j * N + i] = s;
+    }
+  std::vector<double> lam;
+  sym_eigen((int)N, A, lam);
+  c->h_eig = lam;
+  std::vector<int64_t> idx(N);
+  for (int64_t i = 0; i < N; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return std::fabs(lam[a]) < std::fabs(lam[b]); });
+  double lmax = std::fabs(lam[idx[N - 1]]);
+  if (!(std::fabs(lam[idx[c->k0]]) > 1e-8 * lmax))
+    throw Fail{LDGS_E_SINGULAR_BLOCK, "bottom operator has more near-zero eigenvalues than the trivial kernel"};
+  std::vector<double> inv(N, 0.0);
+  for (int64_t q = c->k0; q < N; ++q) inv[idx[q]] = 1.0 / lam[idx[q]];
+  c->h_pinv.assign((size_t)N * N, 0.0);
+  // pinv = V diag(inv) V^T
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < N; ++i)
+    for (int64_t q = 0; q < N; ++q) {
+      double viq = A[(size_t)i * N + q] * inv[q];
+      if (viq == 0.0) continue;
+      for (int64_t j = 0; j < N; ++j) c->h_pinv[(size_t)i * N + j] += viq * A[(size_t)j * N + q];
+    }
+}
+
+void check_ctx(ldgs_ctx* c, bool device) {
+  if (!c) throw Fail{LDGS_E_ARG, "null context"};
+  if (device && c->host_only) throw Fail{LDGS_E_UNSUPPORTED, "context was built host_only"};
+}
+
+ldgs_status handle(ldgs_ctx* c, const Fail& f) {
+  if (c) c->err = f.msg;
+  return f.st;
+}
+
+// ---------------------------------------------------------------------------
+// the V-cycle (Algorithm 1) on one precision store
+// ---------------------------------------------------------------------------
+hipEvent_t next_event(ldgs_ctx* c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
+template <typename T>
+void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* x) {
+  LaunchCfg cfg{c->g.d, c->g.p, c->stream};
+  PrecLevel<T>& pl = S.lv[l];
+  const size_t esz = pl.inv_kind == 0 ? 8 : (pl.inv_kind == 1 ? 4 : 2);
+  const size_t nb2 = (size_t)c->g.nb * c->g.nb;
+  int64_t o = pl.col_off[col], cnt = pl.col_off[col + 1] - o;
+  const void* inv = (const char*)pl.inv + o * nb2 * esz;
+  const bool timed = c->prof && l == 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed) {
+    e0 = next_event(c);
+    e1 = next_event(c);
+    HIPCHK(hipEventRecord(e0, c->stream));
+  }
+  LCHK(launch_smooth_colour<T>(cfg, pl.view, c->tab, pl.elems + o, cnt, inv, pl.inv_kind, b, x));
+  if (timed) {
+    HIPCHK(hipEventRecord(e1, c->stream));
+    c->prof_ev.emplace_back(e0, e1);
+  }
+}
+
+template <typename T>
+void smooth(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x, int sweeps) {
+  for (int s = 0; s < sweeps; ++s)
+    for (int col = 0; col < c->levels[l].ncol; ++col) smooth_colour(c, S, l, col, b, x);
+}
+
+// Least-squares bottom solve x = A_c^+ b (footnote to the bottom solver):
+// the eigendecomposition pseudo-inverse, applied in FP64 with one step of
+// iterative refinement, x = y + A_c^+ (b - A_c y) with y = A_c^+ b.
+template <typename T>
+void bottom_solve(ldgs_ctx* c, const T* b, T* x) {
+  const int64_t N = c->Nc;
+  const double* b64;
+  if constexpr (sizeof(T) == 8) {
+    b64 = (const double*)b;
+  } else {
+    LCHK(launch_cast_f2d_add(c->stream, N, (const float*)b, c->d_bt0, 0));
+    b64 = c->d_bt0;
+  }
+  LCHK((launch_dense_mv<double, double>(c->stream, N, c->d_pinv, b64, nullptr, 1.0, c->d_bt1)));
+  LCHK((launch_dense_mv<double, double>(c->stream, N, c->d_Ac, c->d_bt1, b64, -1.0, c->d_bt2)));
+  LCHK((launch_dense_mv<double, T>(c->stream, N, c->d_pinv, c->d_bt2, c->d_bt1, 1.0, x)));
+}
+
+template <typename T>
+void cycle(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x) {
+  const int bottom = (int)c->levels.size() - 1;
+  LaunchCfg cfg{c->g.d, c->g.p, c->stream};
+  if (l == bottom) {
+    bottom_solve(c, b, x);
+    return;
+  }
+  smooth(c, S, l, b, x, c->P.nu1);
+  PrecLevel<T>& nx = S.lv[l + 1];
+  LCHK(launch_residual_restrict<T>(cfg, S.lv[l].view, c->tab, b, x, nx.b));
+  if (l + 1 < bottom) LCHK(launch_fill<T>(c->stream, c->levels[l + 1].NE * c->g.nb, (T)0, nx.x));
+  cycle(c, S, l + 1, nx.b, nx.x);
+  LCHK(launch_prolong_add<T>(cfg, c->levels[l].n, c->tab, nx.x, x));
+  smooth(c, S, l, b, x, c->P.nu2);
+}
+
+const double* dscale0(ldgs_ctx* c) { return c->P.diag_scaling ? c->d_dscale0 : nullptr; }
+
+// x <- V(b, x) on user (unscaled, FP64) vectors in precision vp.
+// If zero_x, x is taken as zero on entry (and overwritten).
+void vcycle_user(ldgs_ctx* c, int vp, const double* b, double* x, bool zero_x) {
+  const int64_t NE = c->levels[0].NE;
+  const int nb = c->g.nb, nvel = c->g.d * c->g.nq;
+  const double* ds = dscale0(c);
+  if (vp == LDGS_V_FP64) {
+    if (!c->s64.built) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
+    LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, b, c->w_b, 0, 0)));
+    if (zero_x) LCHK(launch_fill<double>(c->stream, NE * nb, 0.0, c->w_x));
+    else LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, x, c->w_x, 1, 0)));
+    cycle<double>(c, c->s64, 0, c->w_b, c->w_x);
+    LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, c->w_x, x, 0, 0)));
+  } else {
+    PrecStore<float>& S = (vp == LDGS_V_FP32) ? c->s32 : c->s16;
+    if (!S.built) throw Fail{LDGS_E_UNSUPPORTED, "requested V-cycle precision not built"};
+    LCHK((launch_scale_cast<double, float>(c->stream, NE, nb, nvel, ds, b, c->w_b32, 0, 0)));
+    if (zero_x) LCHK(launch_fill<float>(c->stream, NE * nb, 0.0f, c->w_x32));
+    else LCHK((launch_scale_cast<double, float>(c->stream, NE, nb, nvel, ds, x, c->w_x32, 1, 0)));
+    cycle<float>(c, S, 0, c->w_b32, c->w_x32);
+    LCHK((launch_scale_cast<float, double>(c->stream, NE, nb, nvel, ds, c->w_x32, x, 0, 0)));
+  }
+}
+
+// z += V(r, 0) in precision vp (r, z user vectors)
+void precond_add(ldgs_ctx* c, int vp, const double* r, double* z) {
+  const int64_t N = c->ndof();
+  vcycle_user(c, vp, r, c->w_z, true);
+  LCHK(launch_axpy(c->stream, N, 1.0, c->w_z, z));
+}
+
+double host_sum_partials(ldgs_ctx* c, int nblk) {
+  std::vector<double> h(nblk);
+  HIPCHK(hipMemcpyAsync(h.data(), c->w_part, nblk * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double s = 0.0;
+  for (double v : h) s += v;
+  return s;
+}
+
+double dot(ldgs_ctx* c, const double* x, const double* y) {
+  const int nblk = 512;
+  LCHK(launch_dot_partial(c->stream, c->ndof(), x, y, c->w_part, nblk));
+  return host_sum_partials(c, nblk);
+}
+
+void residual_fine(ldgs_ctx* c, const double* b, const double* x, double* r) {
+  LaunchCfg cfg{c->g.d, c->g.p, c->stream};
+  LCHK(launch_residual<double>(cfg, c->s64.lv[0].unscaled, c->tab, b, x, r, 0));
+}
+
+void project_kernel(ldgs_ctx* c, double* v) {
+  const int64_t NE = c->levels[0].NE;
+  const int nblk = 256;
+  for (int off : c->kernel_offsets) {
+    LCHK(launch_strided_sum_partial(c->stream, NE, c->g.nb, off, v, c->w_part, nblk));
+    double mean = host_sum_partials(c, nblk) / (double)NE;
+    LCHK(launch_strided_add(c->stream, NE, c->g.nb, off, -mean, v));
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* ldgs_status_str(ldgs_status s) {
+  switch (s) {
+    case LDGS_OK: return "ok";
+    case LDGS_E_ARG: return "invalid argument";
+    case LDGS_E_UNSUPPORTED: return "unsupported";
+    case LDGS_E_NOMEM: return "out of memory";
+    case LDGS_E_HIP: return "HIP error";
+    case LDGS_E_SINGULAR_BLOCK: return "singular block";
+    case LDGS_E_COLORING: return "improper colouring";
+    case LDGS_E_NOT_CONVERGED: return "not converged";
+    case LDGS_E_NONFINITE: return "non-finite value";
+  }
+  return "unknown status";
+}
+
+static thread_local std::string g_setup_error;
+
+const char* ldgs_last_error(const ldgs_ctx* ctx) { return ctx ? ctx->err.c_str() : g_setup_error.c_str(); }
+
+ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
+  if (!prob || !out) return LDGS_E_ARG;
+  *out = nullptr;
+  std::unique_ptr<ldgs_ctx> c(new ldgs_ctx());
+  try {
+    c->P = *prob;
+    fill_defaults(c->P);
+    validate(c->P);
+    const ldgs_problem& P = c->P;
+    c->host_only = P.host_only != 0;
+    c->g.set(P.dim, P.degree);
+    c->B.init(P.degree);
+    c->tab = c->B.tab();
+    c->vprec = P.vprec;
+    c->k0 = kernel_dim(P);
+    if (c->k0 == 1) c->kernel_offsets = {P.dim * c->g.nq};
+    else for (int i = 0; i <= P.dim; ++i) c->kernel_offsets.push_back(i * c->g.nq);
+    // hierarchy
+    c->levels.emplace_back();
+    build_fine_level(P, c->g, c->B, c->levels[0]);
+    while (c->levels.back().n > P.coarsest_n) {
+      Level C;
+      coarsen_level(P, c->g, c->B, c->levels.back(), C);
+      c->levels.push_back(std::move(C));
+    }
+    if (P.diag_scaling)
+      for (Level& L : c->levels) set_scaling(L, c->g);
+    build_smoother_host(c.get());
+    build_bottom(c.get());
+    if (!c->host_only) {
+      if (P.hip_stream) c->stream = (hipStream_t)P.hip_stream;
+      int mask = (1 << P.vprec) | P.build_precisions;
+      bool n64 = mask & 1, n32 = mask & 2, n16 = mask & 4;
+      upload_ops<double>(c.get(), c->s64, n64);     // finest FP64 operator always (outer residual)
+      if (n32 || n16) {
+        upload_ops<float>(c.get(), c->s32, true);
+        c->s16.lv = c->s32.lv;                       // same operator data and work vectors
+        for (auto& l : c->s16.lv) l.inv = nullptr;
+        c->s16.ops = true;
+      }
+      build_inverses(c.get(), n64, n32, n16);
+      c->s64.built = n64;
+      c->s32.built = n32;
+      c->s16.built = n16;
+      c->d_pinv = upload<double>(c.get(), c->h_pinv);
+      c->d_Ac = upload<double>(c.get(), c->h_Ac);
+      c->d_bt0 = dalloc<double>(c.get(), c->Nc);
+      c->d_bt1 = dalloc<double>(c.get(), c->Nc);
+      c->d_bt2 = dalloc<double>(c.get(), c->Nc);
+      const int64_t N = c->ndof();
+      c->w_b = dalloc<double>(c.get(), N);
+      c->w_x = dalloc<double>(c.get(), N);
+      c->w_r = dalloc<double>(c.get(), N);
+      c->w_z = dalloc<double>(c.get(), N);
+      c->w_part = dalloc<double>(c.get(), 1024);
+      if (n32 || n16) {
+        c->w_b32 = dalloc<float>(c.get(), N);
+        c->w_x32 = dalloc<float>(c.get(), N);
+      }
+      if (P.diag_scaling) c->d_dscale0 = upload<double>(c.get(), c->levels[0].dscale);
+      HIPCHK(hipDeviceSynchronize());
+    }
+  } catch (const Fail& f) {
+    g_setup_error = f.msg;
+    return f.st;
+  } catch (const std::bad_alloc&) {
+    g_setup_error = "host allocation failed";
+    return LDGS_E_NOMEM;
+  } catch (const std::exception& ex) {
+    g_setup_error = ex.what();
+    return LDGS_E_ARG;
+  }
+  g_setup_error.clear();
+  *out = c.release();
+  return LDGS_OK;
+}
+
+ldgs_status ldgs_destroy(ldgs_ctx* ctx) {
+  delete ctx;
+  return LDGS_OK;
+}
+
+ldgs_status ldgs_num_dofs(const ldgs_ctx* ctx, int64_t* ndof) {
+  if (!ctx || !ndof) return LDGS_E_ARG;
+  *ndof = ctx->ndof();
+  return LDGS_OK;
+}
+
+ldgs_status ldgs_level_info(const ldgs_ctx* ctx, int level, int* n_l, int* n_levels, int* n_colours) {
+  if (!ctx || level < 0 || level >= (int)ctx->levels.size()) return LDGS_E_ARG;
+  if (n_l) *n_l = ctx->levels[level].n;
+  if (n_levels) *n_levels = (int)ctx->levels.size();
+  if (n_colours) *n_colours = ctx->levels[level].ncol;
+  return LDGS_OK;
+}
+
+ldgs_status ldgs_assemble_rhs(ldgs_ctx* ctx, const ldgs_rhs_data* data, double* b) {
+  try {
+    check_ctx(ctx, false);
+    if (!data || !b) throw Fail{LDGS_E_ARG, "null argument"};
+    std::vector<double> hb(ctx->ndof());
+    assemble_rhs_host(ctx->P, ctx->g, ctx->B, ctx->levels[0], *data, hb.data());
+    if (ctx->host_only) std::memcpy(b, hb.data(), hb.size() * sizeof(double));
+    else HIPCHK(hipMemcpy(b, hb.data(), hb.size() * sizeof(double), hipMemcpyHostToDevice));
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+ldgs_status ldgs_apply(ldgs_ctx* ctx, const double* x, double* y) {
+  try {
+    check_ctx(ctx, true);
+    if (!x || !y || x == y) throw Fail{LDGS_E_ARG, "x, y must be distinct non-null"};
+    LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream};
+    LCHK(launch_residual<double>(cfg, ctx->s64.lv[0].unscaled, ctx->tab, nullptr, x, y, 1));
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+ldgs_status ldgs_residual(ldgs_ctx* ctx, const double* b, const double* x, double* r, double* norm2) {
+  try {
+    check_ctx(ctx, true);
+    if (!b || !x) throw Fail{LDGS_E_ARG, "null argument"};
+    double* rr = r ? r : ctx->w_r;
+    residual_fine(ctx, b, x, rr);
+    if (norm2) *norm2 = std::sqrt(dot(ctx, rr, rr));
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+ldgs_status ldgs_vcycle(ldgs_ctx* ctx, const double* b, double* x) {
+  try {
+    check_ctx(ctx, true);
+    if (!b || !x) throw Fail{LDGS_E_ARG, "null argument"};
+    vcycle_user(ctx, ctx->vprec, b, x, false);
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+ldgs_status ldgs_set_vprec(ldgs_ctx* ctx, int vprec) {
+  if (!ctx || vprec < 0 || vprec > 2) return LDGS_E_ARG;
+  bool ok = (vprec == 0 && ctx->s64.built) || (vprec == 1 && ctx->s32.built) || (vprec == 2 && ctx->s16.built);
+  if (!ok) {
+    ctx->err = "precision not built at setup";
+    return LDGS_E_UNSUPPORTED;
+  }
+  ctx->vprec = vprec;
+  return LDGS_OK;
+}
+
+ldgs_status ldgs_set_learned(ldgs_ctx* ctx, const void*, int64_t) {
+  if (!ctx) return LDGS_E_ARG;
+  ctx->err = "learned correction not available in this version";
+  return LDGS_E_UNSUPPORTED;
+}
+
+ldgs_status ldgs_project_kernel(ldgs_ctx* ctx, double* v) {
+  try {
+    check_ctx(ctx, true);
+    if (!v) throw Fail{LDGS_E_ARG, "null argument"};
+    project_kernel(ctx, v);
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxit, int outer, int fgmres_m,
+                       int use_learned, ldgs_info* info) {
+  try {
+    check_ctx(ctx, true);
+    if (!b || !x || maxit < 0 || !(tol >= 0)) throw Fail{LDGS_E_ARG, "bad argument"};
+    if (use_learned) throw Fail{LDGS_E_UNSUPPORTED, "learned correction not available in this version"};
+    auto t0 = std::chrono::steady_clock::now();
+    const int64_t N = ctx->ndof();
+    project_kernel(ctx, b);
+    const double bn = std::sqrt(dot(ctx, b, b));
+    int it = 0;
+    double rel = 0.0;
+    std::vector<double> hist;
+    ldgs_status st = LDGS_OK;
+    auto relres = [&]() {
+      residual_fine(ctx, b, x, ctx->w_r);
+      double v = std::sqrt(dot(ctx, ctx->w_r, ctx->w_r));
+      return bn > 0 ? v / bn : v;
+    };
+    if (bn == 0.0) {
+      LCHK(launch_fill<double>(ctx->stream, N, 0.0, x));
+      rel = 0.0;
+      hist.push_back(0.0);
+    } else if (outer == LDGS_STATIONARY || outer == LDGS_IR) {
+      rel = relres();
+      hist.push_back(rel);
+      while (rel > tol && it < maxit) {
+        if (outer == LDGS_STATIONARY) {
+          vcycle_user(ctx, ctx->vprec, b, x, false);
+        } else {
+          // r = b - A x is in w_r from relres()
+          precond_add(ctx, ctx->vprec, ctx->w_r, x);
+        }
+        ++it;
+        rel = relres();
+        hist.push_back(rel);
+        if (!std::isfinite(rel)) { st = LDGS_E_NONFINITE; break; }
+        if (rel > 1e3 * hist[0]) { st = LDGS_E_NOT_CONVERGED; break; }
+      }
+    } else if (outer == LDGS_FGMRES) {
+      const int m = fgmres_m > 0 ? fgmres_m : 30;
+      while ((int)ctx->kry.size() < 2 * m + 1) ctx->kry.push_back(dalloc<double>(ctx, N));
+      double* const* V = ctx->kry.data();
+      double* const* Z = ctx->kry.data() + (m + 1);
+      rel = relres();
+      hist.push_back(rel);
+      while (rel > tol && it < maxit) {
+        double beta = rel * bn;
+        LCHK(launch_scale_copy(ctx->stream, N, 1.0 / beta, ctx->w_r, V[0]));
+        std::vector<double> H((m + 1) * m, 0.0), cs(m), sn(m), gvec(m + 1, 0.0);
+        gvec[0] = beta;
+        int jdone = 0;
+        for (int j = 0; j < m && it < maxit; ++j) {
+          LCHK(launch_fill<double>(ctx->stream, N, 0.0, Z[j]));
+          precond_add(ctx, ctx->vprec, V[j], Z[j]);
+          LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream};
+          LCHK(launch_residual<double>(cfg, ctx->s64.lv[0].unscaled, ctx->tab, nullptr, Z[j], V[j + 1], 1));
+          for (int i = 0; i <= j; ++i) {
+            double hij = dot(ctx, V[j + 1], V[i]);
+            H[i * m + j] = hij;
+            LCHK(launch_axpy(ctx->stream, N, -hij, V[i], V[j + 1]));
+          }
+          double hn = std::sqrt(dot(ctx, V[j + 1], V[j + 1]));
+          H[(j + 1) * m + j] = hn;
+          if (hn > 0) LCHK(launch_scale_copy(ctx->stream, N, 1.0 / hn, V[j + 1], V[j + 1]));
+          for (int i = 0; i < j; ++i) {
+            double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+            H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+            H[i * m + j] = t;
+          }
+          double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+          cs[j] = H[j * m + j] / den;
+          sn[j] = H[(j + 1) * m + j] / den;
+          H[j * m + j] = den;
+          H[(j + 1) * m + j] = 0.0;
+          gvec[j + 1] = -sn[j] * gvec[j];
+          gvec[j] = cs[j] * gvec[j];
+          ++it;
+          jdone = j + 1;
+          double est = std::fabs(gvec[j + 1]) / bn;
+          hist.push_back(est);
+          if (!std::isfinite(est)) { st = LDGS_E_NONFINITE; break; }
+          if (est <= tol) break;
+        }
+        if (st != LDGS_OK) break;
+        std::vector<double> y(jdone);
+        for (int i = jdone - 1; i >= 0; --i) {
+          double s = gvec[i];
+          for (int q = i + 1; q < jdone; ++q) s -= H[i * m + q] * y[q];
+          y[i] = s / H[i * m + i];
+        }
+        for (int i = 0; i < jdone; ++i) LCHK(launch_axpy(ctx->stream, N, y[i], Z[i], x));
+        rel = relres();
+        if (!hist.empty()) hist.back() = rel;
+        if (!std::isfinite(rel)) { st = LDGS_E_NONFINITE; break; }
+      }
+    } else {
+      throw Fail{LDGS_E_ARG, "outer"};
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (st == LDGS_OK && rel > tol) st = LDGS_E_NOT_CONVERGED;
+    if (info) {
+      info->iters = it;
+      info->fallback_events = 0;
+      info->relres = rel;
+      info->rho_measured = (it > 0 && rel > 0 && hist[0] > 0) ? std::pow(rel / hist[0], 1.0 / it) : 0.0;
+      info->t_solve_s = secs;
+      info->history_len = 0;
+      if (info->history)
+        for (size_t i = 0; i < hist.size() && (int)i < info->history_cap; ++i) {
+          info->history[i] = hist[i];
+          info->history_len = (int)i + 1;
+        }
+    }
+    if (st != LDGS_OK) ctx->err = std::string("solve ended with relres ") + std::to_string(rel);
+    return st;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+// ---- profiling -------------------------------------------------------------
+ldgs_status ldgs_profile(ldgs_ctx* ctx, int enable) {
+  if (!ctx) return LDGS_E_ARG;
+  ctx->prof = enable != 0;
+  ctx->prof_ev.clear();
+  ctx->ev_used = 0;
+  return LDGS_OK;
+}
+
+ldgs_status ldgs_profile_read(ldgs_ctx* ctx, double* total_ms, int64_t* launches) {
+  try {
+    check_ctx(ctx, true);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    double tot = 0.0;
+    for (auto& pr : ctx->prof_ev) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+      tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (int64_t)ctx->prof_ev.size();
+    ctx->prof_ev.clear();
+    ctx->ev_used = 0;
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+// ---- stage entry points --------------------------------------------------
+ldgs_status ldgs_level_smooth_colour(ldgs_ctx* ctx, int level, int colour, const double* b, double* x) {
+  try {
+    check_ctx(ctx, true);
+    if (!ctx->s64.built) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
+    if (level < 0 || level + 1 >= (int)ctx->levels.size()) throw Fail{LDGS_E_ARG, "level"};
+    if (colour < 0 || colour >= ctx->levels[level].ncol || !b || !x) throw Fail{LDGS_E_ARG, "colour"};
+    smooth_colour<double>(ctx, ctx->s64, level, colour, b, x);
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+ldgs_status ldgs_level_smooth_colour_f32(ldgs_ctx* ctx, int level, int colour, int vprec, const float* b, float* x) {
+  try {
+    check_ctx(ctx, true);
+    PrecStore<float>* S = vprec == LDGS_V_FP32 ? &ctx->s32 : (vprec == LDGS_V_FP32_BF16BLK ? &ctx->s16 : nullptr);
+    if (!S || !S->built) throw Fail{LDGS_E_UNSUPPORTED, "requested float V-cycle not built"};
+    if (level < 0 || level + 1 >= (int)ctx->levels.size()) throw Fail{LDGS_E_ARG, "level"};
+    if (colour < 0 || colour >= ctx->levels[level].ncol || !b || !x) throw Fail{LDGS_E_ARG, "colour"};
+    smooth_colour<float>(ctx, *S, level, colour, b, x);
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+ldgs_status ldgs_level_residual_restrict(ldgs_ctx* ctx, int level, const double* b, const double* x, double* rc) {
+  try {
+    check_ctx(ctx, true);
+    if (!ctx->s64.built) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
+    if (level < 0 || level + 1 >= (int)ctx->levels.size() || !b || !x || !rc) throw Fail{LDGS_E_ARG, "level"};
+    LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream};
+    LCHK(launch_residual_restrict<double>(cfg, ctx->s64.lv[level].view, ctx->tab, b, x, rc));
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+ldgs_status ldgs_level_prolong_add(ldgs_ctx* ctx, int level, const double* xc, double* x) {
+  try {
+    check_ctx(ctx, true);
+    if (level < 0 || level + 1 >= (int)ctx->levels.size() || !xc || !x) throw Fail{LDGS_E_ARG, "level"};
+    LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream};
+    LCHK(launch_prolong_add<double>(cfg, ctx->levels[level].n, ctx->tab, xc, x));
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+ldgs_status ldgs_bottom_solve(ldgs_ctx* ctx, const double* b, double* x) {
+  try {
+    check_ctx(ctx, true);
+    if (!b || !x || b == x) throw Fail{LDGS_E_ARG, "b, x must be distinct non-null"};
+    bottom_solve<double>(ctx, b, x);
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+ldgs_status ldgs_level_apply(ldgs_ctx* ctx, int level, const double* x, double* y) {
+  try {
+    check_ctx(ctx, true);
+    if (!ctx->s64.built && level != 0) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
+    if (level < 0 || level >= (int)ctx->levels.size() || !x || !y) throw Fail{LDGS_E_ARG, "level"};
+    if (level == (int)ctx->levels.size() - 1 && ctx->levels[level].n < 4)
+      throw Fail{LDGS_E_UNSUPPORTED, "device apply needs n >= 4 on the level"};
+    LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream};
+    LCHK(launch_residual<double>(cfg, ctx->s64.lv[level].view, ctx->tab, nullptr, x, y, 1));
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+ldgs_status ldgs_level_block_inverse(ldgs_ctx* ctx, int level, int64_t element, double* inv_host) {
+  try {
+    check_ctx(ctx, false);
+    if (level < 0 || level + 1 >= (int)ctx->levels.size() || !inv_host) throw Fail{LDGS_E_ARG, "level"};
+    const Level& L = ctx->levels[level];
+    if (element < 0 || element >= L.NE) throw Fail{LDGS_E_ARG, "element"};
+    const int nb = ctx->g.nb;
+    std::vector<double> A((size_t)nb * nb);
+    host_diag_block(L, ctx->g, ctx->B, ctx->P.form, element, A.data());
+    if (!block_inverse(nb, A.data(), inv_host, 1e-14)) throw Fail{LDGS_E_SINGULAR_BLOCK, "singular block"};
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+ldgs_status ldgs_host_level_apply(ldgs_ctx* ctx, int level, const double* x, double* y) {
+  try {
+    check_ctx(ctx, false);
+    if (level < 0 || level >= (int)ctx->levels.size() || !x || !y) throw Fail{LDGS_E_ARG, "level"};
+    host_apply(ctx->levels[level], ctx->g, ctx->B, ctx->P.form, x, y);
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+ldgs_status ldgs_bottom_info(ldgs_ctx* ctx, int64_t* nc, double* pinv, double* eig) {
+  if (!ctx) return LDGS_E_ARG;
+  if (nc) *nc = ctx->Nc;
+  if (pinv) std::memcpy(pinv, ctx->h_pinv.data(), ctx->h_pinv.size() * sizeof(double));
+  if (eig) std::memcpy(eig, ctx->h_eig.data(), ctx->h_eig.size() * sizeof(double));
+  return LDGS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,760 @@
+// HIP kernels of the LDG-Stokes V-cycle for gfx950 (CDNA4).
+//
+// One 64-lane work-group (one wavefront) owns one element.  It stages the x
+// coefficients of the element and of the neighbours its residual depends on
+// in LDS, evaluates (A x)_E matrix-free from the factored operator
+// (G, M_mu, penalty face matrices), and then, in the smoother, applies the
+// element's precomputed inverse diagonal block streamed from HBM
+// (column-major, colour-major order so that consecutive work-groups read
+// consecutive memory).
+//
+// The operator action follows eq. (stokessystem) / eq. (viscousop) with M = I:
+//   (A x)_{u_i} = sum_k G_k^T s_ik + Et u_i + (rho/delta) u_i - G_i^T p,
+//   s_ik = M_mu (G_k u_i + gamma G_i u_k),
+//   (A x)_p     = -sum_i G_i u_i - E p.
+// G_k^T s receives, from each face normal to k, the one-sided flux
+// h^-1 (wR s_R|lo + wL s_L|hi) (sigma-hat of eq. qstarflux): +e0 on the high
+// element R and -e1 on the low element L.
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <type_traits>
+
+#include "ldgs_internal.hpp"
+
+namespace ldgs {
+
+template <int B, int E>
+struct Pow { static constexpr int v = B * Pow<B, E - 1>::v; };
+template <int B>
+struct Pow<B, 0> { static constexpr int v = 1; };
+
+template <int D, int P>
+struct Sz {
+  static constexpr int M = P + 1;
+  static constexpr int NQ = Pow<M, D>::v;
+  static constexpr int MT = Pow<M, D - 1>::v;
+  static constexpr int NB = (D + 1) * NQ;
+  // stencil slots: E, E-e_k, E+e_k, E+e_k-e_j (j != k)
+  static constexpr int NSLOT = 1 + 2 * D + D * (D - 1);
+  static constexpr int NFS = 1 + D;   // elements whose s is needed: E, E+e_k
+};
+
+constexpr int WG = 64;
+
+template <int M>
+__device__ __forceinline__ int ipow(int k) {
+  int v = 1;
+  for (int j = 0; j < k; ++j) v *= M;
+  return v;
+}
+
+// digit k of the multi-index a (axis 0 fastest)
+template <int M>
+__device__ __forceinline__ int digit(int a, int k) { return (a / ipow<M>(k)) % M; }
+// index of a with digit k removed (tangential index on a face normal to k)
+template <int M>
+__device__ __forceinline__ int tang(int a, int k) {
+  int lo = a % ipow<M>(k);
+  int hi = a / ipow<M>(k + 1);
+  return lo + ipow<M>(k) * hi;
+}
+// inverse of tang: insert digit c at position k
+template <int M>
+__device__ __forceinline__ int compose(int t, int c, int k) {
+  int lo = t % ipow<M>(k);
+  int hi = t / ipow<M>(k);
+  return lo + ipow<M>(k) * c + ipow<M>(k + 1) * hi;
+}
+
+// neighbour of element with coordinates c shifted by s along axis k (-1 if outside)
+template <int D>
+__device__ __forceinline__ int shifted(const int* c, int n, bool periodic_k, int k, int s, int* out_c) {
+  for (int j = 0; j < D; ++j) out_c[j] = c[j];
+  int v = c[k] + s;
+  if (v < 0 || v >= n) {
+    if (!periodic_k) return 0;
+    v = (v + n) % n;
+  }
+  out_c[k] = v;
+  return 1;
+}
+
+template <int D>
+__device__ __forceinline__ int64_t elem_index(const int* c, int n) {
+  int64_t e = 0, s = 1;
+  for (int j = 0; j < D; ++j) { e += (int64_t)c[j] * s; s *= n; }
+  return e;
+}
+
+template <int D>
+__device__ __forceinline__ int64_t face_index(const int* c, int n, int nfk, int k, int f) {
+  int64_t e = 0, s = 1;
+  for (int j = 0; j < D; ++j) {
+    int v = (j == k) ? f : c[j];
+    e += (int64_t)v * s;
+    s *= (j == k) ? nfk : n;
+  }
+  return e;
+}
+
+// shared-memory work area of one element evaluation
+template <typename T, int D, int P>
+struct Work {
+  using S = Sz<D, P>;
+  T xs[S::NSLOT][S::NB];
+  T g[S::NFS][D * D][S::NQ];
+  T s[S::NFS][D * D][S::NQ];
+  T trx[2][D][D + 1][S::MT];       // traces of x_E: [lo/hi][axis][field][t]
+  T trn[2][D][D + 1][S::MT];       // [0]: x_{E-e_k}|hi, [1]: x_{E+e_k}|lo
+  T trs[3][D][D][S::MT];           // s_E[i][k]|lo, s_E[i][k]|hi, s_{E+e_k}[i][k]|lo (along k)
+  T flux[2][D][D + 1][S::MT];      // coefficients of e0 (lo) and e1 (hi) per axis/field
+  T res[S::NB];
+  long long slot_e[S::NSLOT];
+  int fidx[2][D];                  // face index of E's low/high face per axis
+  unsigned char ft[2][D];
+  T fwl[2][D], fwr[2][D];
+};
+
+// Evaluates (A x)_E (mode 1) or b_E - (A x)_E (mode 0) into w.res.
+// Operators of the diagonally scaled system D A D when lev.dscale is set.
+template <typename T, int D, int P>
+__device__ void element_operator(const DevLevel<T>& lev, const Tab1D& tab, int64_t E,
+                                 const T* __restrict__ x, const T* __restrict__ b,
+                                 int mode, Work<T, D, P>& w) {
+  using S = Sz<D, P>;
+  constexpr int M = S::M, NQ = S::NQ, MT = S::MT, NB = S::NB;
+  const int lane = threadIdx.x;
+  const int n = lev.n;
+  const T hinv = lev.hinv;
+
+  int c[D];
+  {
+    int64_t r = E;
+    for (int j = 0; j < D; ++j) { c[j] = (int)(r % n); r /= n; }
+  }
+  // ---- slots and faces (lane 0..) ----
+  if (lane == 0) {
+    int cc[D];
+    w.slot_e[0] = E;
+    for (int k = 0; k < D; ++k) {
+      bool per = lev.nf[k] == n;
+      w.slot_e[1 + k] = shifted<D>(c, n, per, k, -1, cc) ? elem_index<D>(cc, n) : -1;
+      w.slot_e[1 + D + k] = shifted<D>(c, n, per, k, +1, cc) ? elem_index<D>(cc, n) : -1;
+      int q = 0;
+      for (int kk = 0; kk < D; ++kk) {
+        if (kk == k) continue;
+        int c1[D], c2[D];
+        long long e = -1;
+        if (shifted<D>(c, n, lev.nf[k] == n, k, +1, c1) &&
+            shifted<D>(c1, n, lev.nf[kk] == n, kk, -1, c2))
+          e = elem_index<D>(c2, n);
+        w.slot_e[1 + 2 * D + k * (D - 1) + q] = e;
+        ++q;
+      }
+      int flo = c[k];
+      int fhi = c[k] + 1;
+      if (per) fhi %= n;
+      int64_t ilo = face_index<D>(c, n, lev.nf[k], k, flo);
+      int64_t ihi = face_index<D>(c, n, lev.nf[k], k, fhi);
+      w.fidx[0][k] = (int)ilo;
+      w.fidx[1][k] = (int)ihi;
+      w.ft[0][k] = lev.ftype[k][ilo];
+      w.ft[1][k] = lev.ftype[k][ihi];
+      w.fwl[0][k] = lev.fw[k][2 * ilo];
+      w.fwr[0][k] = lev.fw[k][2 * ilo + 1];
+      w.fwl[1][k] = lev.fw[k][2 * ihi];
+      w.fwr[1][k] = lev.fw[k][2 * ihi + 1];
+    }
+  }
+  __syncthreads();
+  // ---- phase 1: stage x of the stencil (scaled by D when set) ----
+  for (int t = lane; t < S::NSLOT * NB; t += WG) {
+    int sl = t / NB, i = t % NB;
+    long long e = w.slot_e[sl];
+    T v = 0;
+    if (e >= 0) {
+      v = x[e * NB + i];
+      if (lev.dscale) v *= lev.dscale[2 * e + (i >= D * NQ ? 1 : 0)];
+    }
+    w.xs[sl][i] = v;
+  }
+  __syncthreads();
+  // ---- phase 2: g_F = G u at F in {E, E+e_0, .., E+e_{D-1}} ----
+  for (int t = lane; t < S::NFS * D * D * NQ; t += WG) {
+    int a = t % NQ;
+    int comp = (t / NQ) % (D * D);
+    int fi = t / (NQ * D * D);
+    int i = comp / D, k = comp % D;
+    int sF = (fi == 0) ? 0 : 1 + D + (fi - 1);
+    T val = 0;
+    if (w.slot_e[sF] >= 0) {
+      int cF[D];
+      if (fi == 0) {
+        for (int j = 0; j < D; ++j) cF[j] = c[j];
+      } else {
+        int kk = fi - 1;
+        shifted<D>(c, n, lev.nf[kk] == n, kk, +1, cF);
+      }
+      int sL;   // slot of F - e_k
+      if (fi == 0) sL = 1 + k;
+      else if (k == fi - 1) sL = 0;
+      else {
+        int kk = fi - 1;
+        int q = (k < kk) ? k : k - 1;
+        sL = 1 + 2 * D + kk * (D - 1) + q;
+      }
+      const bool per = lev.nf[k] == n;
+      int flo = cF[k];
+      int fhi = per ? (cF[k] + 1) % n : cF[k] + 1;
+      int64_t ilo = face_index<D>(cF, n, lev.nf[k], k, flo);
+      int64_t ihi = face_index<D>(cF, n, lev.nf[k], k, fhi);
+      unsigned char tlo = lev.ftype[k][ilo];
+      unsigned char thi = lev.ftype[k][ihi];
+      T wR = lev.fw[k][2 * ilo + 1];
+      T wL = lev.fw[k][2 * ihi];
+      const T* u = &w.xs[sF][i * NQ];
+      const T* uL = &w.xs[sL][i * NQ];
+      int ak = digit<M>(a, k), tt = tang<M>(a, k);
+      T vol = 0, trlo = 0, trhi = 0, trLhi = 0;
+      for (int bb = 0; bb < M; ++bb) {
+        T ub = u[compose<M>(tt, bb, k)];
+        vol += (T)tab.K[ak * M + bb] * ub;
+        trlo += (T)tab.e0[bb] * ub;
+        trhi += (T)tab.e1[bb] * ub;
+        trLhi += (T)tab.e1[bb] * uL[compose<M>(tt, bb, k)];
+      }
+      T jlo = trlo - ((tlo == F_INTRA || tlo == F_INTER) ? trLhi : (T)0);
+      T acc = vol;
+      if (tlo != F_NONE) acc += wR * (T)tab.e0[ak] * jlo;
+      if (thi == F_DIR_HI) acc += wL * (T)tab.e1[ak] * (-trhi);
+      val = hinv * acc;
+    }
+    w.g[fi][comp][a] = val;
+  }
+  __syncthreads();
+  // ---- phase 3: s = M_mu (g + gamma g^T) ----
+  constexpr int NS0 = D * D * NQ;
+  for (int t = lane; t < NS0 + D * D * NQ; t += WG) {
+    int fi, i, k, a;
+    if (t < NS0) {
+      fi = 0; a = t % NQ; int comp = t / NQ; i = comp / D; k = comp % D;
+    } else {
+      int u = t - NS0; a = u % NQ; int q = u / NQ; fi = 1 + q / D; i = q % D; k = fi - 1;
+    }
+    int sF = (fi == 0) ? 0 : 1 + D + (fi - 1);
+    T val = 0;
+    long long eF = w.slot_e[sF];
+    if (eF >= 0) {
+      const T* g1 = w.g[fi][i * D + k];
+      const T* g2 = w.g[fi][k * D + i];
+      const T gam = (T)lev.gamma;
+      if (lev.mmu) {
+        const T* Mm = lev.mmu + (size_t)eF * NQ * NQ;
+        for (int bb = 0; bb < NQ; ++bb) val += Mm[bb * NQ + a] * (g1[bb] + gam * g2[bb]);
+      } else {
+        val = lev.mu_const * (g1[a] + gam * g2[a]);
+      }
+    }
+    w.s[fi][i * D + k][a] = val;
+  }
+  __syncthreads();
+  // ---- phase 4: traces ----
+  constexpr int NTX = 2 * D * (D + 1) * MT;
+  constexpr int NTS = 3 * D * D * MT;
+  for (int t = lane; t < 2 * NTX + NTS; t += WG) {
+    if (t < NTX) {
+      int tt = t % MT; int f = (t / MT) % (D + 1); int k = (t / (MT * (D + 1))) % D; int side = t / (MT * (D + 1) * D);
+      const T* u = &w.xs[0][f * NQ];
+      const double* e = side ? tab.e1 : tab.e0;
+      T v = 0;
+      for (int bb = 0; bb < M; ++bb) v += (T)e[bb] * u[compose<M>(tt, bb, k)];
+      w.trx[side][k][f][tt] = v;
+    } else if (t < 2 * NTX) {
+      int r = t - NTX;
+      int tt = r % MT; int f = (r / MT) % (D + 1); int k = (r / (MT * (D + 1))) % D; int side = r / (MT * (D + 1) * D);
+      // side 0: x_{E-e_k} at its high face; side 1: x_{E+e_k} at its low face
+      int sl = side ? 1 + D + k : 1 + k;
+      const T* u = &w.xs[sl][f * NQ];
+      const double* e = side ? tab.e0 : tab.e1;
+      T v = 0;
+      for (int bb = 0; bb < M; ++bb) v += (T)e[bb] * u[compose<M>(tt, bb, k)];
+      w.trn[side][k][f][tt] = v;
+    } else {
+      int r = t - 2 * NTX;
+      int tt = r % MT; int i = (r / MT) % D; int k = (r / (MT * D)) % D; int which = r / (MT * D * D);
+      const T* sv = (which == 2) ? w.s[1 + k][i * D + k] : w.s[0][i * D + k];
+      const double* e = (which == 1) ? tab.e1 : tab.e0;
+      T v = 0;
+      for (int bb = 0; bb < M; ++bb) v += (T)e[bb] * sv[compose<M>(tt, bb, k)];
+      w.trs[which][k][i][tt] = v;
+    }
+  }
+  __syncthreads();
+  // ---- phase 5: face fluxes ----
+  for (int t = lane; t < 2 * D * (D + 1) * MT; t += WG) {
+    int tt = t % MT; int f = (t / MT) % (D + 1); int k = (t / (MT * (D + 1))) % D; int side = t / (MT * (D + 1) * D);
+    unsigned char ty = w.ft[side][k];
+    const T wL = w.fwl[side][k], wR = w.fwr[side][k];
+    const T* Th = lev.fT[k] + (size_t)w.fidx[side][k] * MT * MT + tt * MT;
+    T v = 0;
+    if (f < D) {
+      const int i = f;
+      if (side == 0) {
+        // E is the high element R of its low face
+        if (ty != F_NONE) v += wR * w.trs[0][k][i][tt];
+        if (ty == F_DIR_LO) {
+          T acc = 0;
+          for (int q = 0; q < MT; ++q) acc += Th[q] * w.trx[0][k][i][q];
+          v += acc;
+        }
+        if (ty == F_INTER) {
+          T acc = 0;
+          for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trn[0][k][i][q] - w.trx[0][k][i][q]);
+          v -= acc;
+        }
+        if (k == i && ty != F_NONE) v -= wR * w.trx[0][k][D][tt];
+      } else {
+        // E is the low element L of its high face
+        T sR = (ty == F_INTRA || ty == F_INTER) ? w.trs[2][k][i][tt] : (T)0;
+        v -= wR * sR + wL * w.trs[1][k][i][tt];
+        if (ty == F_DIR_HI) {
+          T acc = 0;
+          for (int q = 0; q < MT; ++q) acc += Th[q] * w.trx[1][k][i][q];
+          v += acc;
+        }
+        if (ty == F_INTER) {
+          T acc = 0;
+          for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trx[1][k][i][q] - w.trn[1][k][i][q]);
+          v += acc;
+        }
+        if (k == i) {
+          T pR = (ty == F_INTRA || ty == F_INTER) ? w.trn[1][k][D][tt] : (T)0;
+          v += wR * pR + wL * w.trx[1][k][D][tt];
+        }
+      }
+    } else {
+      if (ty == F_INTRA) {
+        T acc = 0;
+        if (side == 0) {
+          for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trn[0][k][D][q] - w.trx[0][k][D][q]);
+          v = acc;
+        } else {
+          for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trx[1][k][D][q] - w.trn[1][k][D][q]);
+          v = -acc;
+        }
+      }
+    }
+    w.flux[side][k][f][tt] = hinv * v;
+  }
+  __syncthreads();
+  // ---- phase 6: assemble (A x)_E and the residual ----
+  for (int t = lane; t < NB; t += WG) {
+    int f = t / NQ, a = t % NQ;
+    T acc = 0;
+    if (f < D) {
+      const int i = f;
+      for (int k = 0; k < D; ++k) {
+        int ak = digit<M>(a, k), tt = tang<M>(a, k);
+        const T* sv = w.s[0][i * D + k];
+        T vol = 0;
+        for (int bb = 0; bb < M; ++bb) vol += (T)tab.K[bb * M + ak] * sv[compose<M>(tt, bb, k)];
+        acc += hinv * vol;
+        acc += (T)tab.e0[ak] * w.flux[0][k][i][tt] + (T)tab.e1[ak] * w.flux[1][k][i][tt];
+      }
+      {
+        int ai = digit<M>(a, i), ti = tang<M>(a, i);
+        const T* pv = &w.xs[0][D * NQ];
+        T vol = 0;
+        for (int bb = 0; bb < M; ++bb) vol += (T)tab.K[bb * M + ai] * pv[compose<M>(ti, bb, i)];
+        acc -= hinv * vol;
+      }
+      acc += lev.rho_delta * w.xs[0][t];
+    } else {
+      for (int i = 0; i < D; ++i) acc -= w.g[0][i * D + i][a];
+      for (int k = 0; k < D; ++k) {
+        int ak = digit<M>(a, k), tt = tang<M>(a, k);
+        acc += (T)tab.e0[ak] * w.flux[0][k][D][tt] + (T)tab.e1[ak] * w.flux[1][k][D][tt];
+      }
+    }
+    if (lev.dscale) acc *= lev.dscale[2 * E + (f == D ? 1 : 0)];
+    w.res[t] = (mode == 0) ? b[E * NB + t] - acc : acc;
+  }
+  __syncthreads();
+}
+
+template <typename TI>
+__device__ __forceinline__ float load_inv(const TI* p);
+template <>
+__device__ __forceinline__ float load_inv<float>(const float* p) { return *p; }
+template <>
+__device__ __forceinline__ float load_inv<uint16_t>(const uint16_t* p) {
+  unsigned int u = ((unsigned int)(*p)) << 16;
+  return __uint_as_float(u);
+}
+
+// ---------------------------------------------------------------------------
+// Smoother: one colour pass.  x_E += Ainv_E (b - A x)_E for the listed elements.
+// ---------------------------------------------------------------------------
+template <typename T, typename TI, int D, int P>
+__global__ __launch_bounds__(WG) void k_smooth_colour(DevLevel<T> lev, Tab1D tab, const int* __restrict__ elems,
+                                                      const TI* __restrict__ inv, const T* __restrict__ b,
+                                                      T* __restrict__ x) {
+  using S = Sz<D, P>;
+  constexpr int NB = S::NB;
+  __shared__ Work<T, D, P> w;
+  const int64_t idx = blockIdx.x;
+  const int64_t E = elems[idx];
+  element_operator<T, D, P>(lev, tab, E, x, b, 0, w);
+  const TI* Ai = inv + (size_t)idx * NB * NB;   // column-major: Ai[j*NB + i] = Ainv[i][j]
+  for (int row = threadIdx.x; row < NB; row += WG) {
+    T y = 0;
+#pragma unroll 8
+    for (int j = 0; j < NB; ++j) {
+      T a;
+      if constexpr (sizeof(TI) == sizeof(T)) a = Ai[(size_t)j * NB + row];
+      else a = (T)load_inv<TI>(Ai + (size_t)j * NB + row);
+      y += a * w.res[j];
+    }
+    x[E * NB + row] += y;
+  }
+}
+
+template <typename T, int D, int P>
+__global__ __launch_bounds__(WG) void k_residual(DevLevel<T> lev, Tab1D tab, const T* __restrict__ b,
+                                                 const T* __restrict__ x, T* __restrict__ out, int mode) {
+  using S = Sz<D, P>;
+  __shared__ Work<T, D, P> w;
+  const int64_t E = blockIdx.x;
+  element_operator<T, D, P>(lev, tab, E, x, b, mode, w);
+  for (int t = threadIdx.x; t < S::NB; t += WG) out[E * S::NB + t] = w.res[t];
+}
+
+// product of 1D injection entries: (P_o)[af][ac] for child offset bits o
+template <int D, int M>
+__device__ __forceinline__ double pfull(const Tab1D& tab, int o, int af, int ac) {
+  double v = 1.0;
+  for (int k = 0; k < D; ++k) {
+    int fk = (af / ipow<M>(k)) % M, ck = (ac / ipow<M>(k)) % M;
+    v *= tab.P[(o >> k) & 1][fk * M + ck];
+  }
+  return v;
+}
+
+// r_c = I^T (b - A x): one work-group per coarse element, looping over children.
+template <typename T, int D, int P>
+__global__ __launch_bounds__(WG) void k_residual_restrict(DevLevel<T> lev, Tab1D tab, const T* __restrict__ b,
+                                                          const T* __restrict__ x, T* __restrict__ rc) {
+  using S = Sz<D, P>;
+  constexpr int M = S::M, NQ = S::NQ, NB = S::NB;
+  constexpr int PER = (NB + WG - 1) / WG;
+  __shared__ Work<T, D, P> w;
+  const int nc = lev.n / 2;
+  const int64_t C = blockIdx.x;
+  int cc[D];
+  {
+    int64_t r = C;
+    for (int j = 0; j < D; ++j) { cc[j] = (int)(r % nc); r /= nc; }
+  }
+  T acc[PER];
+  for (int q = 0; q < PER; ++q) acc[q] = 0;
+  for (int o = 0; o < (1 << D); ++o) {
+    int cf[D];
+    for (int j = 0; j < D; ++j) cf[j] = 2 * cc[j] + ((o >> j) & 1);
+    const int64_t E = elem_index<D>(cf, lev.n);
+    element_operator<T, D, P>(lev, tab, E, x, b, 0, w);
+    for (int q = 0; q < PER; ++q) {
+      int t = threadIdx.x + q * WG;
+      if (t < NB) {
+        int f = t / NQ, ac = t % NQ;
+        T s = 0;
+        for (int af = 0; af < NQ; ++af) s += (T)pfull<D, M>(tab, o, af, ac) * w.res[f * NQ + af];
+        acc[q] += s;
+      }
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < PER; ++q) {
+    int t = threadIdx.x + q * WG;
+    if (t < NB) rc[C * NB + t] = acc[q];
+  }
+}
+
+// x += I x_c: one thread per fine coefficient.
+template <typename T, int D, int P>
+__global__ void k_prolong_add(int n, Tab1D tab, const T* __restrict__ xc, T* __restrict__ x, int64_t total) {
+  using S = Sz<D, P>;
+  constexpr int M = S::M, NQ = S::NQ, NB = S::NB;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  int64_t E = t / NB;
+  int r = (int)(t % NB);
+  int f = r / NQ, af = r % NQ;
+  int c[D], o = 0;
+  {
+    int64_t rr = E;
+    for (int j = 0; j < D; ++j) { c[j] = (int)(rr % n); rr /= n; }
+  }
+  int pc[D];
+  for (int j = 0; j < D; ++j) { pc[j] = c[j] / 2; o |= (c[j] & 1) << j; }
+  int64_t C = elem_index<D>(pc, n / 2);
+  const T* xv = xc + C * NB + f * NQ;
+  T s = 0;
+  for (int ac = 0; ac < NQ; ++ac) s += (T)pfull<D, M>(tab, o, af, ac) * xv[ac];
+  x[t] += s;
+}
+
+// y = z + sign * M x with M row-major FP64 (N x N), one wavefront per row;
+// z may be null.  Used by the bottom solve (pseudo-inverse and refinement).
+template <typename Tin, typename Tout>
+__global__ void k_dense_mv(int64_t N, const double* __restrict__ A, const Tin* __restrict__ x,
+                           const double* __restrict__ z, double sign, Tout* __restrict__ y) {
+  int64_t row = blockIdx.x;
+  double s = 0.0;
+  for (int64_t j = threadIdx.x; j < N; j += WG) s += A[row * N + j] * (double)x[j];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, WG);
+  if (threadIdx.x == 0) y[row] = (Tout)((z ? z[row] : 0.0) + sign * s);
+}
+
+// ---------------------------------------------------------------------------
+// vector helpers
+// ---------------------------------------------------------------------------
+__global__ void k_cast_d2f(int64_t n, const double* a, float* b) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+__global__ void k_cast_f2d_add(int64_t n, const float* a, double* b, int add) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = add ? b[i] + (double)a[i] : (double)a[i];
+}
+__global__ void k_axpby(int64_t n, double a, const double* x, double bcoef, double* y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + bcoef * y[i];
+}
+__global__ void k_axpy(int64_t n, double a, const double* x, double* y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
+}
+__global__ void k_scale_copy(int64_t n, double a, const double* x, double* y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i];
+}
+template <typename T>
+__global__ void k_fill(int64_t n, T v, T* y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+__global__ void k_f2bf16(int64_t n, const float* a, uint16_t* b) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    // round to nearest even
+    unsigned int u = __float_as_uint(a[i]);
+    unsigned int lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    b[i] = (uint16_t)(u >> 16);
+  }
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_scale_cast(int64_t ne, int nb, int nvel, const double* dscale, const Tin* in, Tout* out, int invert,
+                             int add) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ne * nb) return;
+  double v = (double)in[t];
+  if (dscale) {
+    int64_t e = t / nb;
+    double s = dscale[2 * e + ((t % nb) >= nvel ? 1 : 0)];
+    v = invert ? v / s : v * s;
+  }
+  out[t] = add ? (Tout)((double)out[t] + v) : (Tout)v;
+}
+
+constexpr int RB = 256;
+__global__ __launch_bounds__(RB) void k_dot_partial(int64_t n, const double* x, const double* y, double* out) {
+  __shared__ double sm[RB];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB)
+    s += x[i] * (y ? y[i] : x[i]);
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = RB / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sm[threadIdx.x] += sm[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sm[0];
+}
+__global__ __launch_bounds__(RB) void k_strided_sum_partial(int64_t ne, int nb, int off, const double* x, double* out) {
+  __shared__ double sm[RB];
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < ne; e += (int64_t)gridDim.x * RB) s += x[e * nb + off];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = RB / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sm[threadIdx.x] += sm[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sm[0];
+}
+__global__ void k_strided_add(int64_t ne, int nb, int off, double v, double* x) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < ne) x[e * nb + off] += v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline int hip_ok() { return hipGetLastError() == hipSuccess ? 0 : 1; }
+static inline unsigned grid1(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// runs f(D, P) for the supported (dimension, degree) pairs; 2 if unsupported
+template <class F>
+static int dispatch(int dim, int p, F&& f) {
+  using std::integral_constant;
+  if (dim == 2 && p == 1) f(integral_constant<int, 2>{}, integral_constant<int, 1>{});
+  else if (dim == 2 && p == 2) f(integral_constant<int, 2>{}, integral_constant<int, 2>{});
+  else if (dim == 2 && p == 3) f(integral_constant<int, 2>{}, integral_constant<int, 3>{});
+  else if (dim == 3 && p == 1) f(integral_constant<int, 3>{}, integral_constant<int, 1>{});
+  else if (dim == 3 && p == 2) f(integral_constant<int, 3>{}, integral_constant<int, 2>{});
+  else return 2;
+  return 0;
+}
+
+template <typename T>
+int launch_smooth_colour(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const int* elems,
+                         int64_t nelems, const void* inv, int inv_kind, const T* b, T* x) {
+  if (nelems <= 0) return 0;
+  hipStream_t st = (hipStream_t)c.stream;
+  if constexpr (sizeof(T) == 8) {
+    if (inv_kind != 0) return 2;
+    if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_smooth_colour<T, double, D_, P_>), dim3((unsigned)nelems), dim3(WG), 0, st,
+                                                  lev, tab, elems, (const double*)inv, b, x); })) return 2;
+  } else {
+    if (inv_kind == 1) {
+      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_smooth_colour<T, float, D_, P_>), dim3((unsigned)nelems), dim3(WG), 0, st,
+                                                    lev, tab, elems, (const float*)inv, b, x); })) return 2;
+    } else if (inv_kind == 2) {
+      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_smooth_colour<T, uint16_t, D_, P_>), dim3((unsigned)nelems), dim3(WG), 0, st,
+                                                    lev, tab, elems, (const uint16_t*)inv, b, x); })) return 2;
+    } else {
+      return 2;
+    }
+  }
+  return hip_ok();
+}
+
+template <typename T>
+int launch_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const T* b, const T* x, T* out,
+                    int mode) {
+  int64_t NE = 1;
+  for (int j = 0; j < c.dim; ++j) NE *= lev.n;
+  hipStream_t st = (hipStream_t)c.stream;
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_residual<T, D_, P_>), dim3((unsigned)NE), dim3(WG), 0, st,
+                                                lev, tab, b, x, out, mode); })) return 2;
+  return hip_ok();
+}
+
+template <typename T>
+int launch_residual_restrict(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const T* b, const T* x,
+                             T* rc) {
+  int64_t NC = 1;
+  for (int j = 0; j < c.dim; ++j) NC *= lev.n / 2;
+  hipStream_t st = (hipStream_t)c.stream;
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_residual_restrict<T, D_, P_>), dim3((unsigned)NC), dim3(WG), 0, st,
+                                                lev, tab, b, x, rc); })) return 2;
+  return hip_ok();
+}
+
+template <typename T>
+int launch_prolong_add(const LaunchCfg& c, int n_fine, const Tab1D& tab, const T* xc, T* x) {
+  int64_t NE = 1;
+  for (int j = 0; j < c.dim; ++j) NE *= n_fine;
+  int64_t nb = (int64_t)(c.dim + 1);
+  for (int j = 0; j < c.dim; ++j) nb *= (c.p + 1);
+  int64_t total = NE * nb;
+  hipStream_t st = (hipStream_t)c.stream;
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_prolong_add<T, D_, P_>), dim3(grid1(total, 256)), dim3(256), 0, st,
+                                                n_fine, tab, xc, x, total); })) return 2;
+  return hip_ok();
+}
+
+template <typename Tin, typename Tout>
+int launch_dense_mv(void* stream, int64_t N, const double* M, const Tin* x, const double* z, double sign, Tout* y) {
+  hipLaunchKernelGGL((k_dense_mv<Tin, Tout>), dim3((unsigned)N), dim3(WG), 0, (hipStream_t)stream, N, M, x, z, sign, y);
+  return hip_ok();
+}
+
+int launch_cast_d2f(void* stream, int64_t n, const double* a, float* b) {
+  hipLaunchKernelGGL(k_cast_d2f, dim3(grid1(n, 256)), dim3(256), 0, (hipStream_t)stream, n, a, b);
+  return hip_ok();
+}
+int launch_cast_f2d_add(void* stream, int64_t n, const float* a, double* b, int add) {
+  hipLaunchKernelGGL(k_cast_f2d_add, dim3(grid1(n, 256)), dim3(256), 0, (hipStream_t)stream, n, a, b, add);
+  return hip_ok();
+}
+int launch_axpy(void* stream, int64_t n, double alpha, const double* x, double* y) {
+  hipLaunchKernelGGL(k_axpy, dim3(grid1(n, 256)), dim3(256), 0, (hipStream_t)stream, n, alpha, x, y);
+  return hip_ok();
+}
+int launch_axpby(void* stream, int64_t n, double a, const double* x, double b, double* y) {
+  hipLaunchKernelGGL(k_axpby, dim3(grid1(n, 256)), dim3(256), 0, (hipStream_t)stream, n, a, x, b, y);
+  return hip_ok();
+}
+int launch_scale_copy(void* stream, int64_t n, double a, const double* x, double* y) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(grid1(n, 256)), dim3(256), 0, (hipStream_t)stream, n, a, x, y);
+  return hip_ok();
+}
+template <typename T>
+int launch_fill(void* stream, int64_t n, T v, T* y) {
+  hipLaunchKernelGGL((k_fill<T>), dim3(grid1(n, 256)), dim3(256), 0, (hipStream_t)stream, n, v, y);
+  return hip_ok();
+}
+int launch_dot_partial(void* stream, int64_t n, const double* x, const double* y, double* out, int nblk) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(nblk), dim3(RB), 0, (hipStream_t)stream, n, x, y, out);
+  return hip_ok();
+}
+int launch_strided_sum_partial(void* stream, int64_t nelem, int nb, int off, const double* x, double* out, int nblk) {
+  hipLaunchKernelGGL(k_strided_sum_partial, dim3(nblk), dim3(RB), 0, (hipStream_t)stream, nelem, nb, off, x, out);
+  return hip_ok();
+}
+int launch_strided_add(void* stream, int64_t nelem, int nb, int off, double v, double* x) {
+  hipLaunchKernelGGL(k_strided_add, dim3(grid1(nelem, 256)), dim3(256), 0, (hipStream_t)stream, nelem, nb, off, v, x);
+  return hip_ok();
+}
+int launch_f2bf16(void* stream, int64_t n, const float* a, uint16_t* b) {
+  hipLaunchKernelGGL(k_f2bf16, dim3(grid1(n, 256)), dim3(256), 0, (hipStream_t)stream, n, a, b);
+  return hip_ok();
+}
+
+template <typename Tin, typename Tout>
+int launch_scale_cast(void* stream, int64_t ne, int nb, int nvel, const double* dscale, const Tin* in, Tout* out,
+                      int invert, int add) {
+  int64_t n = ne * nb;
+  hipLaunchKernelGGL((k_scale_cast<Tin, Tout>), dim3(grid1(n, 256)), dim3(256), 0, (hipStream_t)stream, ne, nb, nvel,
+                     dscale, in, out, invert, add);
+  return hip_ok();
+}
+
+// explicit instantiations
+template int launch_scale_cast<double, double>(void*, int64_t, int, int, const double*, const double*, double*, int, int);
+template int launch_scale_cast<double, float>(void*, int64_t, int, int, const double*, const double*, float*, int, int);
+template int launch_scale_cast<float, double>(void*, int64_t, int, int, const double*, const float*, double*, int, int);
+template int launch_smooth_colour<double>(const LaunchCfg&, const DevLevel<double>&, const Tab1D&, const int*, int64_t,
+                                          const void*, int, const double*, double*);
+template int launch_smooth_colour<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const int*, int64_t,
+                                         const void*, int, const float*, float*);
+template int launch_residual<double>(const LaunchCfg&, const DevLevel<double>&, const Tab1D&, const double*,
+                                     const double*, double*, int);
+template int launch_residual<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const float*, const float*,
+                                    float*, int);
+template int launch_residual_restrict<double>(const LaunchCfg&, const DevLevel<double>&, const Tab1D&, const double*,
+                                              const double*, double*);
+template int launch_residual_restrict<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const float*,
+                                             const float*, float*);
+template int launch_prolong_add<double>(const LaunchCfg&, int, const Tab1D&, const double*, double*);
+template int launch_prolong_add<float>(const LaunchCfg&, int, const Tab1D&, const float*, float*);
+template int launch_dense_mv<double, double>(void*, int64_t, const double*, const double*, const double*, double, double*);
+template int launch_dense_mv<double, float>(void*, int64_t, const double*, const double*, const double*, double, float*);
+template int launch_fill<double>(void*, int64_t, double, double*);
+template int launch_fill<float>(void*, int64_t, float, float*);
+
+}  // namespace ldgs

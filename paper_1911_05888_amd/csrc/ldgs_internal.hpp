@@ -1,0 +1,111 @@
+// Internal declarations shared by the host setup (C++) and the HIP kernels.
+//
+// Operator representation on every level (uniform Cartesian grid, width h,
+// orthonormal tensor Legendre basis so that M = I):
+//  * discrete gradient G_k (eq. geqn): volume part h^-1 K along axis k and,
+//    per face normal to k with low element L and high element R, a lifting of
+//    the jump u_R|lo - u_L|hi onto L with weight wL and onto R with weight wR,
+//    along the face trace vectors e1 (L) and e0 (R).  Intraphase faces have
+//    (wL, wR) = (0, 1) (flux u-hat = u^-), Dirichlet faces lift onto their one
+//    element with weight 1 (outside value 0), interphase faces carry the
+//    viscosity-upwinded lambda of eq. (viscosityupwind).
+//  * mu-weighted mass M_mu: one dense symmetric block per element (or one
+//    constant).
+//  * penalties: per face a tangential matrix That (face mass weighted by
+//    tau), applied to the jump (intraphase faces: pressure penalty E;
+//    interphase faces: velocity penalty E-tilde) or to the one trace
+//    (Dirichlet faces: velocity penalty).
+//  * unsteady term rho/delta (constant rho), optional per-element diagonal
+//    scaling (alpha on velocity, beta on pressure).
+#pragma once
+
+#include <cstdint>
+#include <cstddef>
+
+namespace ldgs {
+
+enum FaceType : unsigned char {
+  F_NONE = 0,     // no face terms (not used by the built-in boundary types)
+  F_INTRA = 1,    // intraphase, both neighbours present (periodic wrap included)
+  F_INTER = 2,    // interphase, both neighbours present
+  F_DIR_LO = 3,   // Dirichlet boundary at x_k = 0 (only R present)
+  F_DIR_HI = 4    // Dirichlet boundary at x_k = 1 (only L present)
+};
+
+constexpr int MAXM = 4;  // p <= 3
+
+// 1D tables of the orthonormal Legendre basis on [0,1]:
+// K[r*M+c] = int l_c' l_r, e0[m] = l_m(0), e1[m] = l_m(1),
+// P[o][f*M+c] = 2^{-1/2} int l_f(xi) l_c((xi+o)/2) (injection, child o).
+struct Tab1D {
+  int M;
+  double K[MAXM * MAXM];
+  double e0[MAXM];
+  double e1[MAXM];
+  double P[2][MAXM * MAXM];
+};
+
+// Device view of one level's operator, element type T.
+template <typename T>
+struct DevLevel {
+  int n;                 // elements per axis
+  int nf[3];             // faces per grid line along each axis (n or n+1)
+  T hinv;                // 1 / h
+  const unsigned char* ftype[3];   // [faces]
+  const T* fw[3];                  // [faces][2] = (wL, wR)
+  const T* fT[3];                  // [faces][MT*MT] penalty matrices
+  const T* mmu;                    // [NE][NQ*NQ] or nullptr (then mu_const)
+  T mu_const;
+  T rho_delta;                     // rho / delta (0: steady)
+  const T* dscale;                 // [NE][2] (alpha, beta) or nullptr
+  int gamma;
+};
+
+// Launchers (defined in kernels.hip).  All are stream-ordered, asynchronous.
+// Every kernel handles one element per 64-thread work-group.
+struct LaunchCfg {
+  int dim, p;
+  void* stream;
+};
+
+template <typename T>
+int launch_smooth_colour(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab,
+                         const int* elems, int64_t nelems, const void* inv, int inv_kind,
+                         const T* b, T* x);
+template <typename T>
+int launch_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab,
+                    const T* b, const T* x, T* out, int mode);   // mode 0: b - A x, 1: A x
+template <typename T>
+int launch_residual_restrict(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab,
+                             const T* b, const T* x, T* rc);
+template <typename T>
+int launch_prolong_add(const LaunchCfg& c, int n_fine, const Tab1D& tab, const T* xc, T* x);
+// y = z + sign * M x, M dense row-major FP64 N x N, z optional
+template <typename Tin, typename Tout>
+int launch_dense_mv(void* stream, int64_t N, const double* M, const Tin* x, const double* z, double sign, Tout* y);
+
+// vector helpers
+int launch_cast_d2f(void* stream, int64_t n, const double* a, float* b);
+int launch_cast_f2d_add(void* stream, int64_t n, const float* a, double* b, int add);
+int launch_axpy(void* stream, int64_t n, double alpha, const double* x, double* y);   // y += a x
+int launch_axpby(void* stream, int64_t n, double a, const double* x, double b, double* y); // y = a x + b y
+int launch_scale_copy(void* stream, int64_t n, double a, const double* x, double* y); // y = a x
+template <typename T>
+int launch_fill(void* stream, int64_t n, T v, T* y);
+// partial sums: out[blk] for blk < nblk (<= 1024 blocks)
+int launch_dot_partial(void* stream, int64_t n, const double* x, const double* y, double* out, int nblk);
+// partial sums of the coefficient at offset `off` of every element (stride nb)
+int launch_strided_sum_partial(void* stream, int64_t nelem, int nb, int off, const double* x,
+                               double* out, int nblk);
+int launch_strided_add(void* stream, int64_t nelem, int nb, int off, double v, double* x);
+
+// bf16 <-> float helpers used by the BF16-block path
+int launch_f2bf16(void* stream, int64_t n, const float* a, uint16_t* b);
+
+// out[e][i] (+)= in[e][i] * s, s = dscale[2e + (i >= nvel)] (or its inverse);
+// dscale may be null (s = 1).  Converts between element types.
+template <typename Tin, typename Tout>
+int launch_scale_cast(void* stream, int64_t ne, int nb, int nvel, const double* dscale, const Tin* in, Tout* out,
+                      int invert, int add);
+
+}  // namespace ldgs

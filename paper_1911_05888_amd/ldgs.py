@@ -1,0 +1,349 @@
+"""ctypes binding of libldgs.so (the C ABI declared in include/ldgs.h).
+
+Argument marshalling only: every computation runs in the library.  Device
+vectors are torch tensors (float64, on the GPU); the library works on the
+stream that was current when the context was created.  Importing this module
+fails loudly if the compiled library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libldgs.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libldgs.so not found at {LIB_PATH}: build it with "
+                      "`python -c 'import __graft_entry__ as g; g.build()'`")
+_lib = C.CDLL(LIB_PATH)
+
+# status codes
+OK, E_ARG, E_UNSUPPORTED, E_NOMEM, E_HIP, E_SINGULAR_BLOCK, E_COLORING, E_NOT_CONVERGED, E_NONFINITE = range(9)
+STANDARD, VISCOUS_STRESS = 0, 1
+PERIODIC, DIRICHLET, STRESS = 0, 1, 2
+COLOR_AUTO, COLOR_RED_BLACK, COLOR_PARITY, COLOR_MOD3 = 0, 1, 2, 3
+V_FP64, V_FP32, V_FP32_BF16BLK = 0, 1, 2
+STATIONARY, IR, FGMRES = 0, 1, 2
+FIELD_CONST, FIELD_SINSIN, FIELD_LOGNORMAL_RFF, FIELD_PHASE_CONST, FIELD_CALLBACK = range(5)
+LEVELSET_NONE, LEVELSET_BOX = 0, 1
+
+EVAL_FN = C.CFUNCTYPE(None, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int),
+                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p)
+
+
+class Field(C.Structure):
+    _fields_ = [("kind", C.c_int), ("params", C.POINTER(C.c_double)), ("nparams", C.c_int64),
+                ("fn", EVAL_FN), ("user", C.c_void_p)]
+
+
+class ProblemStruct(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int), ("degree", C.c_int), ("form", C.c_int),
+                ("bc", C.c_int * 3), ("mu", Field), ("rho", Field), ("delta", C.c_double),
+                ("levelset_kind", C.c_int), ("levelset_params", C.c_double * 2),
+                ("tau", C.c_double), ("tau0", C.c_double), ("tau_u_bdry_C", C.c_double),
+                ("tau_u_inter_C", C.c_double), ("nu1", C.c_int), ("nu2", C.c_int),
+                ("coarsest_n", C.c_int), ("coloring", C.c_int), ("vprec", C.c_int),
+                ("build_precisions", C.c_int), ("diag_scaling", C.c_int), ("host_only", C.c_int),
+                ("hip_stream", C.c_void_p)]
+
+
+class RhsData(C.Structure):
+    _fields_ = [("f", EVAL_FN), ("f_div", EVAL_FN), ("g_dirichlet", EVAL_FN), ("g_jump", EVAL_FN),
+                ("h_jump", EVAL_FN), ("user", C.c_void_p)]
+
+
+class Info(C.Structure):
+    _fields_ = [("iters", C.c_int), ("fallback_events", C.c_int), ("relres", C.c_double),
+                ("rho_measured", C.c_double), ("t_solve_s", C.c_double),
+                ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int), ("history_len", C.c_int)]
+
+
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+_SIGS = {
+    "ldgs_setup": ([C.POINTER(ProblemStruct), C.POINTER(C.c_void_p)]),
+    "ldgs_num_dofs": ([_P, C.POINTER(C.c_int64)]),
+    "ldgs_assemble_rhs": ([_P, C.POINTER(RhsData), _P]),
+    "ldgs_apply": ([_P, _P, _P]),
+    "ldgs_residual": ([_P, _P, _P, _P, _D]),
+    "ldgs_vcycle": ([_P, _P, _P]),
+    "ldgs_solve": ([_P, _P, _P, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(Info)]),
+    "ldgs_set_vprec": ([_P, C.c_int]),
+    "ldgs_set_learned": ([_P, _P, C.c_int64]),
+    "ldgs_project_kernel": ([_P, _P]),
+    "ldgs_level_info": ([_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "ldgs_level_smooth_colour": ([_P, C.c_int, C.c_int, _P, _P]),
+    "ldgs_level_residual_restrict": ([_P, C.c_int, _P, _P, _P]),
+    "ldgs_level_prolong_add": ([_P, C.c_int, _P, _P]),
+    "ldgs_bottom_solve": ([_P, _P, _P]),
+    "ldgs_level_apply": ([_P, C.c_int, _P, _P]),
+    "ldgs_level_block_inverse": ([_P, C.c_int, C.c_int64, _D]),
+    "ldgs_host_level_apply": ([_P, C.c_int, _D, _D]),
+    "ldgs_bottom_info": ([_P, C.POINTER(C.c_int64), _D, _D]),
+    "ldgs_level_smooth_colour_f32": ([_P, C.c_int, C.c_int, C.c_int, _P, _P]),
+    "ldgs_profile": ([_P, C.c_int]),
+    "ldgs_profile_read": ([_P, _D, C.POINTER(C.c_int64)]),
+    "ldgs_destroy": ([_P]),
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int
+_lib.ldgs_status_str.argtypes = [C.c_int]
+_lib.ldgs_status_str.restype = C.c_char_p
+_lib.ldgs_last_error.argtypes = [_P]
+_lib.ldgs_last_error.restype = C.c_char_p
+
+EXPORTED = sorted(list(_SIGS) + ["ldgs_status_str", "ldgs_last_error"])
+
+
+class LdgsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_lib.ldgs_status_str(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (or host pointer of a numpy array)."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data_as(C.c_void_p)
+    return C.c_void_p(t.data_ptr())
+
+
+def _np_eval(fn, ncomp, dim):
+    """Wraps fn(x (n,d), phase (n,), normal or None) -> (n, ncomp) as a C callback."""
+    def cb(n, x, phase, normal, out, user):
+        xa = np.ctypeslib.as_array(x, shape=(n, dim))
+        ph = np.ctypeslib.as_array(phase, shape=(n,)) if phase else None
+        nr = np.ctypeslib.as_array(normal, shape=(n, dim)) if normal else None
+        val = np.asarray(fn(xa, ph, nr), dtype=np.float64).reshape(n, ncomp)
+        np.ctypeslib.as_array(out, shape=(n, ncomp))[:] = val
+    return EVAL_FN(cb)
+
+
+def _field(obj, dim, keep):
+    """ldgs_field from a coefficient object with ``kind`` and ``params()``."""
+    kind = {"const": FIELD_CONST, "sinsin": FIELD_SINSIN, "lognormal_rff": FIELD_LOGNORMAL_RFF,
+            "phase": FIELD_PHASE_CONST}.get(getattr(obj, "kind", None), FIELD_CALLBACK)
+    f = Field()
+    f.kind = kind
+    if kind == FIELD_CALLBACK:
+        cb = _np_eval(lambda x, ph, nr: obj.value(x, ph), 1, dim)
+        keep.append(cb)
+        f.fn = cb
+    else:
+        pr = np.ascontiguousarray(obj.params(), dtype=np.float64)
+        if kind == FIELD_PHASE_CONST:
+            pr = pr[:2].copy()
+        keep.append(pr)
+        f.params = pr.ctypes.data_as(C.POINTER(C.c_double))
+        f.nparams = pr.size
+    return f
+
+
+def problem_struct(prob, vprec=V_FP64, build_precisions=0, host_only=False, stream=None, coloring=None):
+    """ldgs_problem from a problem description object (attributes dim, n, p,
+    gamma, bc, mu, rho, delta, phases, tau, tau0, tau_u_bdry_C, tau_u_inter_C,
+    nu1, nu2, coarsest_n, coloring, diag_scaling).  Returns (struct, keepalive)."""
+    keep = []
+    s = ProblemStruct()
+    s.dim, s.n, s.degree, s.form = prob.dim, prob.n, prob.p, prob.gamma
+    for j, b in enumerate(prob.bc):
+        s.bc[j] = PERIODIC if b == "periodic" else DIRICHLET
+    s.mu = _field(prob.mu, prob.dim, keep)
+    if getattr(prob, "rho", None) is not None:
+        s.rho = _field(prob.rho, prob.dim, keep)
+    s.delta = prob.delta if getattr(prob, "delta", None) else 0.0
+    if getattr(prob, "phases", None) is not None:
+        s.levelset_kind = LEVELSET_BOX
+        s.levelset_params[0] = prob.phases.lo
+        s.levelset_params[1] = prob.phases.hi
+    s.tau, s.tau0 = prob.tau, prob.tau0
+    s.tau_u_bdry_C, s.tau_u_inter_C = prob.tau_u_bdry_C, prob.tau_u_inter_C
+    s.nu1, s.nu2, s.coarsest_n = prob.nu1, prob.nu2, prob.coarsest_n
+    col = coloring if coloring is not None else prob.coloring
+    s.coloring = {"auto": COLOR_AUTO, "rb": COLOR_RED_BLACK, "parity": COLOR_PARITY,
+                  "mod3": COLOR_MOD3}.get(col, col)
+    s.vprec = vprec
+    s.build_precisions = build_precisions
+    s.diag_scaling = int(bool(getattr(prob, "diag_scaling", False)))
+    s.host_only = int(bool(host_only))
+    s.hip_stream = stream
+    return s, keep
+
+
+def rhs_callbacks(src, dim):
+    """ldgs_rhs_data from a data object providing forcing(x, chi) (d comps),
+    forcing_div(x, chi), and, if it is an exact solution, velocity(x, chi)
+    and stress(x, chi) (Dirichlet data and interface jumps)."""
+    keep = []
+    r = RhsData()
+
+    def mk(fn, ncomp):
+        cb = _np_eval(fn, ncomp, dim)
+        keep.append(cb)
+        return cb
+
+    r.f = mk(lambda x, ph, nr: src.forcing(x, ph), dim)
+    r.f_div = mk(lambda x, ph, nr: src.forcing_div(x, ph), 1)
+    if hasattr(src, "velocity"):
+        r.g_dirichlet = mk(lambda x, ph, nr: src.velocity(x, ph), dim)
+
+        def gj(x, ph, nr):
+            return src.velocity(x, np.ones_like(ph)) - src.velocity(x, 2 * np.ones_like(ph))
+
+        def hj(x, ph, nr):
+            sd = src.stress(x, np.ones_like(ph)) - src.stress(x, 2 * np.ones_like(ph))
+            return np.einsum("nij,nj->ni", sd, nr)
+        r.g_jump = mk(gj, dim)
+        r.h_jump = mk(hj, dim)
+    return r, keep
+
+
+class Context:
+    """One ldgs context (levels, smoother data, bottom solver) on the GPU, or on
+    the host only when ``host_only`` is set (setup validation)."""
+
+    def __init__(self, prob, vprec=V_FP64, build_precisions=0, host_only=False, coloring=None):
+        stream = None
+        self.host_only = host_only
+        if not host_only:
+            import torch
+            stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        self.prob = prob
+        self._s, self._keep = problem_struct(prob, vprec, build_precisions, host_only, stream, coloring)
+        h = C.c_void_p()
+        st = _lib.ldgs_setup(C.byref(self._s), C.byref(h))
+        if st != OK:
+            raise LdgsError(st, _lib.ldgs_last_error(None).decode())
+        self._h = h
+        n = C.c_int64()
+        self._check(_lib.ldgs_num_dofs(self._h, C.byref(n)))
+        self.ndof = n.value
+        nl = C.c_int()
+        self._check(_lib.ldgs_level_info(self._h, 0, None, C.byref(nl), None))
+        self.n_levels = nl.value
+
+    def _check(self, st):
+        if st != OK:
+            raise LdgsError(st, _lib.ldgs_last_error(self._h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ldgs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- main entry points ------------------------------------------------
+    def zeros(self, n=None):
+        import torch
+        return torch.zeros(self.ndof if n is None else n, dtype=torch.float64, device="cuda")
+
+    def assemble_rhs(self, src, out=None):
+        r, keep = rhs_callbacks(src, self.prob.dim)
+        if out is None:
+            out = np.zeros(self.ndof) if self.host_only else self.zeros()
+        self._check(_lib.ldgs_assemble_rhs(self._h, C.byref(r), _dptr(out)))
+        return out
+
+    def apply(self, x, y=None):
+        y = self.zeros() if y is None else y
+        self._check(_lib.ldgs_apply(self._h, _dptr(x), _dptr(y)))
+        return y
+
+    def residual(self, b, x, r=None):
+        nrm = C.c_double()
+        self._check(_lib.ldgs_residual(self._h, _dptr(b), _dptr(x), _dptr(r), C.byref(nrm)))
+        return nrm.value
+
+    def vcycle(self, b, x):
+        self._check(_lib.ldgs_vcycle(self._h, _dptr(b), _dptr(x)))
+        return x
+
+    def set_vprec(self, vprec):
+        self._check(_lib.ldgs_set_vprec(self._h, vprec))
+
+    def project_kernel(self, v):
+        self._check(_lib.ldgs_project_kernel(self._h, _dptr(v)))
+        return v
+
+    def solve(self, b, x, tol=1e-10, maxit=100, outer=STATIONARY, fgmres_m=30, use_learned=False,
+              history_cap=512, raise_on_failure=False):
+        """Returns (status, info dict).  b is projected onto range(A) in place."""
+        hist = (C.c_double * history_cap)()
+        info = Info()
+        info.history = C.cast(hist, C.POINTER(C.c_double))
+        info.history_cap = history_cap
+        st = _lib.ldgs_solve(self._h, _dptr(b), _dptr(x), tol, maxit, outer, fgmres_m,
+                             int(bool(use_learned)), C.byref(info))
+        if st != OK and (raise_on_failure or st not in (E_NOT_CONVERGED,)):
+            self._check(st)
+        return st, dict(iters=info.iters, relres=info.relres, rho=info.rho_measured,
+                        t_solve_s=info.t_solve_s,
+                        history=np.array(hist[:info.history_len]))
+
+    # ---- stages -------------------------------------------------------------
+    def level_info(self, level):
+        n, nl, nc = C.c_int(), C.c_int(), C.c_int()
+        self._check(_lib.ldgs_level_info(self._h, level, C.byref(n), C.byref(nl), C.byref(nc)))
+        return n.value, nl.value, nc.value
+
+    def level_smooth_colour(self, level, colour, b, x):
+        self._check(_lib.ldgs_level_smooth_colour(self._h, level, colour, _dptr(b), _dptr(x)))
+
+    def level_smooth_colour_f32(self, level, colour, vprec, b, x):
+        self._check(_lib.ldgs_level_smooth_colour_f32(self._h, level, colour, vprec, _dptr(b), _dptr(x)))
+
+    def profile(self, enable=True):
+        self._check(_lib.ldgs_profile(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        ms, n = C.c_double(), C.c_int64()
+        self._check(_lib.ldgs_profile_read(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def level_residual_restrict(self, level, b, x, rc):
+        self._check(_lib.ldgs_level_residual_restrict(self._h, level, _dptr(b), _dptr(x), _dptr(rc)))
+
+    def level_prolong_add(self, level, xc, x):
+        self._check(_lib.ldgs_level_prolong_add(self._h, level, _dptr(xc), _dptr(x)))
+
+    def bottom_solve(self, b, x):
+        self._check(_lib.ldgs_bottom_solve(self._h, _dptr(b), _dptr(x)))
+
+    def level_apply(self, level, x, y):
+        self._check(_lib.ldgs_level_apply(self._h, level, _dptr(x), _dptr(y)))
+
+    def level_block_inverse(self, level, element):
+        nb = (self.prob.dim + 1) * (self.prob.p + 1) ** self.prob.dim
+        out = np.zeros((nb, nb))
+        self._check(_lib.ldgs_level_block_inverse(self._h, level, element,
+                                                  out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def host_level_apply(self, level, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros_like(x)
+        self._check(_lib.ldgs_host_level_apply(self._h, level, x.ctypes.data_as(C.POINTER(C.c_double)),
+                                               y.ctypes.data_as(C.POINTER(C.c_double))))
+        return y
+
+    def bottom_info(self):
+        nc = C.c_int64()
+        self._check(_lib.ldgs_bottom_info(self._h, C.byref(nc), None, None))
+        pinv = np.zeros((nc.value, nc.value))
+        eig = np.zeros(nc.value)
+        self._check(_lib.ldgs_bottom_info(self._h, None, pinv.ctypes.data_as(C.POINTER(C.c_double)),
+                                          eig.ctypes.data_as(C.POINTER(C.c_double))))
+        return pinv, eig
