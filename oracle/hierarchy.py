@@ -13,7 +13,13 @@ the bottom solver.
   mod-3 sum (i_k mod 3) 3^k; colours are swept in increasing order.
 * Bottom: symmetric eigendecomposition of the coarsest operator with the
   k0 eigenvalues of smallest magnitude snapped to zero (the bottom-solver
-  footnote), k0 = dimension of the trivial kernel.
+  footnote), k0 = dimension of the trivial kernel.  Reading: the
+  decomposition is taken of the Jacobi-equilibrated operator D A D,
+  D = |diag A|^{-1/2}, whose near-zero eigenvalues are separated from the
+  rest by many orders of magnitude even where A itself is badly scaled
+  (unsteady problems with large rho/delta); the bottom solve is then
+  x = D (D A D)^+ D r, a generalized inverse of A that solves A x = r for
+  every r in range(A) and differs from A^+ r only along the kernel.
 * Optional diagonal (alpha, beta) scaling of the multi-phase section: every
   level's operator is replaced by D A D with D = mu_E^{-1/2} on velocity and
   mu_E^{1/2} on pressure, mu_E the element mean of mu.
@@ -153,13 +159,15 @@ def build_hierarchy(prob):
     k0 = kernel_dimension(prob)
     bot = levels[-1]
     Ad = bot.A.toarray()
-    lam, V = np.linalg.eigh(0.5 * (Ad + Ad.T))
+    dg = 1.0 / np.sqrt(np.abs(np.diag(Ad)))
+    Bd = dg[:, None] * Ad * dg[None, :]
+    lam, V = np.linalg.eigh(0.5 * (Bd + Bd.T))
     order = np.argsort(np.abs(lam))
     inv = np.zeros_like(lam)
     keep = order[k0:]
     if np.abs(lam[keep]).min() <= 1e-8 * np.abs(lam).max():
         raise np.linalg.LinAlgError("coarsest operator has more near-zero eigenvalues than the kernel")
     inv[keep] = 1.0 / lam[keep]
-    bot.pinv = (V * inv[None, :]) @ V.T
+    bot.pinv = dg[:, None] * ((V * inv[None, :]) @ V.T) * dg[None, :]
     bot.eig = lam
     return Hierarchy(prob, levels, k0)

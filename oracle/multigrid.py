@@ -2,9 +2,10 @@
 
 Bottom solve (footnote to the bottom solver in section 3): the least-squares
 solution with the eigendecomposition pseudo-inverse, near-zero eigenvalues
-snapped to zero.  Reading: the solve is the least-squares solution computed
-to working accuracy, i.e. A_c^+ applied with one refinement step; the
-pseudo-inverse alone has a backward error of order eps * cond(A_c).
+snapped to zero (built in hierarchy.py on the equilibrated operator).
+Reading: the solve is that solution computed to working accuracy, i.e. the
+pseudo-inverse applied with one refinement step; the pseudo-inverse alone
+has a backward error of order eps * cond(A_c).
 
 Block Gauss-Seidel (section 3): for element i of the current colour,
 x_i <- A_ii^{-1} (b_i - sum_{j != i} A_ij x_j).  Elements of one colour are
