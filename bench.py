@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 / BF16 comparison solves")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run 3 plain device copies of 256 MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -82,6 +84,14 @@ def main():
     import torch
     from paper_1911_05888_amd import Context, V_FP64, V_FP32, V_FP32_BF16BLK, STATIONARY, IR
     from synth import c2_dirichlet_varmu
+
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     prob = c2_dirichlet_varmu(n=args.n, p=3)
     t0 = time.perf_counter()

@@ -229,9 +229,11 @@ ldgs_status ldgs_level_residual_restrict(ldgs_ctx* ctx, int level, const double*
 /* x += I x_c, injection from level+1 to level. */
 ldgs_status ldgs_level_prolong_add(ldgs_ctx* ctx, int level, const double* xc_dev, double* x_dev);
 
-/* x = A_bottom^+ b on the bottom level: the least-squares solution with the
- * FP64 eigendecomposition pseudo-inverse (near-zero eigenvalues snapped to
- * zero), applied with one step of iterative refinement. */
+/* Bottom solve x = P b, P = D (D A_c D)^+ D with D = |diag A_c|^{-1/2}: the
+ * eigendecomposition of the equilibrated bottom operator with its k0
+ * smallest-magnitude eigenvalues snapped to zero (k0 = dimension of the
+ * trivial kernel), applied in FP64 with one step of iterative refinement.
+ * Solves A_c x = b for b in range(A_c). */
 ldgs_status ldgs_bottom_solve(ldgs_ctx* ctx, const double* b_dev, double* x_dev);
 
 /* y = A_l x on level `level`. */
@@ -247,9 +249,9 @@ ldgs_status ldgs_level_block_inverse(ldgs_ctx* ctx, int level, int64_t element, 
  * For validating the setup; the solver never calls it. */
 ldgs_status ldgs_host_level_apply(ldgs_ctx* ctx, int level, const double* x_host, double* y_host);
 
-/* The bottom pseudo-inverse (row-major N_c x N_c doubles, host array) and the
- * eigenvalues of the bottom operator (N_c doubles, ascending magnitude order
- * not guaranteed); either pointer may be NULL.  *nc receives N_c. */
+/* The bottom solve matrix P above (row-major N_c x N_c doubles, host array)
+ * and the eigenvalues of the equilibrated bottom operator (N_c doubles, in no
+ * particular order); either pointer may be NULL.  *nc receives N_c. */
 ldgs_status ldgs_bottom_info(ldgs_ctx* ctx, int64_t* nc, double* pinv_host, double* eig_host);
 
 /* Timing of the finest-level smoother launches.  With profiling enabled the

@@ -50,6 +50,7 @@ struct PrecLevel {
   int inv_kind = 0;              // 0 double, 1 float, 2 bf16
   int* elems = nullptr;          // colour-major element ids
   std::vector<int64_t> col_off;  // colour offsets (elements)
+  size_t inv_stride = 0;         // entries per element in the inverse layout
   T* x = nullptr;                // level work vectors (levels >= 1)
   T* b = nullptr;
 };
@@ -242,10 +243,36 @@ void upload_ops(ldgs_ctx* c, PrecStore<T>& S, bool all_levels) {
   S.ops = true;
 }
 
+// entries of one element's inverse in the smoother's lane-blocked layout
+// (see inv_layout): inv is row-major nb x nb, out receives nb * NBP values
+static void arrange_inverse(const double* inv, int nb, int bytes, double* out) {
+  const InvLayout L = inv_layout(nb, bytes);
+  const int RGS = L.RG * L.S;
+  for (int kk = 0; kk < L.CS; ++kk)
+    for (int l = 0; l < RGS; ++l) {
+      const int g = l % L.RG, s = l / L.RG, col = s * L.CS + kk;
+      for (int v = 0; v < L.V; ++v) {
+        const int row = L.V * g + v;
+        out[((size_t)kk * RGS + l) * L.V + v] = row < nb ? inv[(size_t)row * nb + col] : 0.0;
+      }
+    }
+}
+
+static uint16_t to_bf16(double d) {
+  float f = (float)d;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+
 // inverse blocks of all smoothed levels into the stores that need them
 void build_inverses(ldgs_ctx* c, bool need64, bool need32, bool need16) {
   const int nb = c->g.nb;
   const size_t nb2 = (size_t)nb * nb;
+  const size_t st64 = (size_t)nb * inv_layout(nb, 8).NBP;
+  const size_t st32 = (size_t)nb * inv_layout(nb, 4).NBP;
+  const size_t st16 = (size_t)nb * inv_layout(nb, 2).NBP;
   for (size_t l = 0; l + 1 < c->levels.size(); ++l) {
     Level& L = c->levels[l];
     std::vector<int64_t> off(L.ncol + 1, 0);
@@ -253,62 +280,62 @@ void build_inverses(ldgs_ctx* c, bool need64, bool need32, bool need16) {
     std::vector<int> order;
     order.reserve(L.NE);
     for (int col = 0; col < L.ncol; ++col) order.insert(order.end(), L.elems[col].begin(), L.elems[col].end());
-    double* inv64 = need64 ? dalloc<double>(c, L.NE * nb2) : nullptr;
-    float* inv32 = need32 ? dalloc<float>(c, L.NE * nb2) : nullptr;
-    uint16_t* inv16 = need16 ? dalloc<uint16_t>(c, L.NE * nb2) : nullptr;
+    double* inv64 = need64 ? dalloc<double>(c, L.NE * st64) : nullptr;
+    float* inv32 = need32 ? dalloc<float>(c, L.NE * st32) : nullptr;
+    uint16_t* inv16 = need16 ? dalloc<uint16_t>(c, L.NE * st16) : nullptr;
     int* elems = dalloc<int>(c, L.NE);
     HIPCHK(hipMemcpy(elems, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice));
     const int64_t CH = 8192;
-    std::vector<double> buf;
-    std::vector<float> buf32;
-    std::vector<uint16_t> buf16;
+    std::vector<double> b64, b32, b16;
+    std::vector<float> h32;
+    std::vector<uint16_t> h16;
     for (int64_t p0 = 0; p0 < L.NE; p0 += CH) {
-      int64_t cnt = std::min(CH, L.NE - p0);
-      buf.assign(cnt * nb2, 0.0);
+      const int64_t cnt = std::min(CH, L.NE - p0);
+      if (need64) b64.assign(cnt * st64, 0.0);
+      if (need32) b32.assign(cnt * st32, 0.0);
+      if (need16) b16.assign(cnt * st16, 0.0);
       int failed = -1;
 #pragma omp parallel
       {
         std::vector<double> A(nb2), inv(nb2);
 #pragma omp for schedule(dynamic, 16)
         for (int64_t i = 0; i < cnt; ++i) {
-          int64_t E = order[p0 + i];
+          const int64_t E = order[p0 + i];
           host_diag_block(L, c->g, c->B, c->P.form, E, A.data());
           if (!block_inverse(nb, A.data(), inv.data(), 1e-14)) {
 #pragma omp critical
             failed = (int)E;
             continue;
           }
-          double* dst = buf.data() + i * nb2;   // column-major: dst[j*nb + r] = inv[r][j]
-          for (int r = 0; r < nb; ++r)
-            for (int j = 0; j < nb; ++j) dst[(size_t)j * nb + r] = inv[(size_t)r * nb + j];
+          if (need64) arrange_inverse(inv.data(), nb, 8, b64.data() + i * st64);
+          if (need32) arrange_inverse(inv.data(), nb, 4, b32.data() + i * st32);
+          if (need16) arrange_inverse(inv.data(), nb, 2, b16.data() + i * st16);
         }
       }
       if (failed >= 0)
         throw Fail{LDGS_E_SINGULAR_BLOCK, "singular element block " + std::to_string(failed) + " on level " +
                                               std::to_string(l)};
-      if (inv64) HIPCHK(hipMemcpy(inv64 + p0 * nb2, buf.data(), cnt * nb2 * sizeof(double), hipMemcpyHostToDevice));
+      if (inv64) HIPCHK(hipMemcpy(inv64 + p0 * st64, b64.data(), cnt * st64 * sizeof(double), hipMemcpyHostToDevice));
       if (inv32) {
-        buf32.assign(buf.begin(), buf.end());
-        HIPCHK(hipMemcpy(inv32 + p0 * nb2, buf32.data(), cnt * nb2 * sizeof(float), hipMemcpyHostToDevice));
+        h32.assign(b32.begin(), b32.end());
+        HIPCHK(hipMemcpy(inv32 + p0 * st32, h32.data(), cnt * st32 * sizeof(float), hipMemcpyHostToDevice));
       }
       if (inv16) {
-        buf16.resize(buf.size());
-        for (size_t i = 0; i < buf.size(); ++i) {
-          float f = (float)buf[i];
-          uint32_t u;
-          std::memcpy(&u, &f, 4);
-          u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
-          buf16[i] = (uint16_t)(u >> 16);
-        }
-        HIPCHK(hipMemcpy(inv16 + p0 * nb2, buf16.data(), cnt * nb2 * sizeof(uint16_t), hipMemcpyHostToDevice));
+        h16.resize(b16.size());
+        for (size_t i = 0; i < b16.size(); ++i) h16[i] = to_bf16(b16[i]);
+        HIPCHK(hipMemcpy(inv16 + p0 * st16, h16.data(), cnt * st16 * sizeof(uint16_t), hipMemcpyHostToDevice));
       }
     }
-    if (need64) { c->s64.lv[l].inv = inv64; c->s64.lv[l].inv_kind = 0; c->s64.lv[l].elems = elems; c->s64.lv[l].col_off = off; }
-    if (need32) { c->s32.lv[l].inv = inv32; c->s32.lv[l].inv_kind = 1; c->s32.lv[l].elems = elems; c->s32.lv[l].col_off = off; }
-    if (need16) { c->s16.lv[l].inv = inv16; c->s16.lv[l].inv_kind = 2; c->s16.lv[l].elems = elems; c->s16.lv[l].col_off = off; }
+    if (need64) { c->s64.lv[l].inv = inv64; c->s64.lv[l].inv_kind = 0; c->s64.lv[l].elems = elems; c->s64.lv[l].col_off = off; c->s64.lv[l].inv_stride = st64; }
+    if (need32) { c->s32.lv[l].inv = inv32; c->s32.lv[l].inv_kind = 1; c->s32.lv[l].elems = elems; c->s32.lv[l].col_off = off; c->s32.lv[l].inv_stride = st32; }
+    if (need16) { c->s16.lv[l].inv = inv16; c->s16.lv[l].inv_kind = 2; c->s16.lv[l].elems = elems; c->s16.lv[l].col_off = off; c->s16.lv[l].inv_stride = st16; }
   }
 }
 
+// Bottom solver (footnote to the bottom solver, section 3): eigendecomposition
+// with the k0 smallest-magnitude eigenvalues snapped to zero, taken of the
+// Jacobi-equilibrated operator D A D (D = |diag A|^{-1/2}); the solve matrix
+// is D (D A D)^+ D, a generalized inverse of A on range(A).
 void build_bottom(ldgs_ctx* c) {
   Level& L = c->levels.back();
   const int64_t N = L.NE * c->g.nb;
@@ -321,9 +348,15 @@ void build_bottom(ldgs_ctx* c) {
     for (int64_t i = 0; i < N; ++i) A[(size_t)i * N + j] = col[i];
   }
   c->h_Ac = A;
+  std::vector<double> dg(N);
+  for (int64_t i = 0; i < N; ++i) {
+    double a = std::fabs(A[(size_t)i * N + i]);
+    if (!(a > 0.0)) throw Fail{LDGS_E_SINGULAR_BLOCK, "zero diagonal entry in the bottom operator"};
+    dg[i] = 1.0 / std::sqrt(a);
+  }
   for (int64_t i = 0; i < N; ++i)
-    for (int64_t j = i + 1; j < N; ++j) {
-      double s = 0.5 * (A[(size_t)i * N + j] + A[(size_t)j * N + i]);
+    for (int64_t j = i; j < N; ++j) {
+      double s = 0.5 * (A[(size_t)i * N + j] + A[(size_t)j * N + i]) * dg[i] * dg[j];
       A[(size_t)i * N + j] = s;
       A[(size_t)j * N + i] = s;
     }
@@ -339,14 +372,17 @@ void build_bottom(ldgs_ctx* c) {
   std::vector<double> inv(N, 0.0);
   for (int64_t q = c->k0; q < N; ++q) inv[idx[q]] = 1.0 / lam[idx[q]];
   c->h_pinv.assign((size_t)N * N, 0.0);
-  // pinv = V diag(inv) V^T
+  // D V diag(inv) V^T D
 #pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < N; ++i)
+  for (int64_t i = 0; i < N; ++i) {
+    double* row = &c->h_pinv[(size_t)i * N];
     for (int64_t q = 0; q < N; ++q) {
       double viq = A[(size_t)i * N + q] * inv[q];
       if (viq == 0.0) continue;
-      for (int64_t j = 0; j < N; ++j) c->h_pinv[(size_t)i * N + j] += viq * A[(size_t)j * N + q];
+      for (int64_t j = 0; j < N; ++j) row[j] += viq * A[(size_t)j * N + q];
     }
+    for (int64_t j = 0; j < N; ++j) row[j] *= dg[i] * dg[j];
+  }
 }
 
 void check_ctx(ldgs_ctx* c, bool device) {
@@ -376,9 +412,8 @@ void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* 
   LaunchCfg cfg{c->g.d, c->g.p, c->stream};
   PrecLevel<T>& pl = S.lv[l];
   const size_t esz = pl.inv_kind == 0 ? 8 : (pl.inv_kind == 1 ? 4 : 2);
-  const size_t nb2 = (size_t)c->g.nb * c->g.nb;
   int64_t o = pl.col_off[col], cnt = pl.col_off[col + 1] - o;
-  const void* inv = (const char*)pl.inv + o * nb2 * esz;
+  const void* inv = (const char*)pl.inv + o * pl.inv_stride * esz;
   const bool timed = c->prof && l == 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {

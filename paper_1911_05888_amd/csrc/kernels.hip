@@ -102,7 +102,10 @@ __device__ __forceinline__ int64_t face_index(const int* c, int n, int nfk, int 
 template <typename T, int D, int P>
 struct Work {
   using S = Sz<D, P>;
+  static constexpr bool STAGE_M = (size_t)S::NFS * S::NQ * S::NQ * sizeof(T) <= 16384;
   T xs[S::NSLOT][S::NB];
+  T mm[STAGE_M ? S::NFS : 1][STAGE_M ? S::NQ * S::NQ : 1];   // M_mu of E, E+e_k
+  T th[2][D][S::MT * S::MT];       // penalty matrices of E's low/high faces
   T g[S::NFS][D * D][S::NQ];
   T s[S::NFS][D * D][S::NQ];
   T trx[2][D][D + 1][S::MT];       // traces of x_E: [lo/hi][axis][field][t]
@@ -111,19 +114,24 @@ struct Work {
   T flux[2][D][D + 1][S::MT];      // coefficients of e0 (lo) and e1 (hi) per axis/field
   T res[S::NB];
   long long slot_e[S::NSLOT];
-  int fidx[2][D];                  // face index of E's low/high face per axis
-  unsigned char ft[2][D];
-  T fwl[2][D], fwr[2][D];
+  long long fid[S::NFS][D][2];     // face ids of F = E, E+e_k (low/high face along each axis)
+  int lslot[S::NFS][D];            // slot of F - e_k
+  unsigned char ft[S::NFS][D][2];
+  T fwl[S::NFS][D][2], fwr[S::NFS][D][2];
 };
 
 // Evaluates (A x)_E (mode 1) or b_E - (A x)_E (mode 0) into w.res.
 // Operators of the diagonally scaled system D A D when lev.dscale is set.
+// Every global load of the element (stencil x, face data, M_mu, penalty
+// matrices) is issued in two batches; all arithmetic then runs from LDS with
+// the axis index k a compile-time constant in each unrolled loop.
 template <typename T, int D, int P>
-__device__ void element_operator(const DevLevel<T>& lev, const Tab1D& tab, int64_t E,
-                                 const T* __restrict__ x, const T* __restrict__ b,
-                                 int mode, Work<T, D, P>& w) {
+__device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const Tab1D& tab, int64_t E,
+                                                 const T* __restrict__ x, const T* __restrict__ b,
+                                                 int mode, Work<T, D, P>& w) {
   using S = Sz<D, P>;
-  constexpr int M = S::M, NQ = S::NQ, MT = S::MT, NB = S::NB;
+  constexpr int M = S::M, NQ = S::NQ, MT = S::MT, NB = S::NB, NFS = S::NFS, NSLOT = S::NSLOT;
+  using W = Work<T, D, P>;
   const int lane = threadIdx.x;
   const int n = lev.n;
   const T hinv = lev.hinv;
@@ -131,47 +139,69 @@ __device__ void element_operator(const DevLevel<T>& lev, const Tab1D& tab, int64
   int c[D];
   {
     int64_t r = E;
+#pragma unroll
     for (int j = 0; j < D; ++j) { c[j] = (int)(r % n); r /= n; }
   }
-  // ---- slots and faces (lane 0..) ----
-  if (lane == 0) {
-    int cc[D];
-    w.slot_e[0] = E;
-    for (int k = 0; k < D; ++k) {
-      bool per = lev.nf[k] == n;
-      w.slot_e[1 + k] = shifted<D>(c, n, per, k, -1, cc) ? elem_index<D>(cc, n) : -1;
-      w.slot_e[1 + D + k] = shifted<D>(c, n, per, k, +1, cc) ? elem_index<D>(cc, n) : -1;
-      int q = 0;
-      for (int kk = 0; kk < D; ++kk) {
-        if (kk == k) continue;
-        int c1[D], c2[D];
-        long long e = -1;
-        if (shifted<D>(c, n, lev.nf[k] == n, k, +1, c1) &&
-            shifted<D>(c1, n, lev.nf[kk] == n, kk, -1, c2))
-          e = elem_index<D>(c2, n);
-        w.slot_e[1 + 2 * D + k * (D - 1) + q] = e;
-        ++q;
-      }
-      int flo = c[k];
-      int fhi = c[k] + 1;
-      if (per) fhi %= n;
-      int64_t ilo = face_index<D>(c, n, lev.nf[k], k, flo);
-      int64_t ihi = face_index<D>(c, n, lev.nf[k], k, fhi);
-      w.fidx[0][k] = (int)ilo;
-      w.fidx[1][k] = (int)ihi;
-      w.ft[0][k] = lev.ftype[k][ilo];
-      w.ft[1][k] = lev.ftype[k][ihi];
-      w.fwl[0][k] = lev.fw[k][2 * ilo];
-      w.fwr[0][k] = lev.fw[k][2 * ilo + 1];
-      w.fwl[1][k] = lev.fw[k][2 * ihi];
-      w.fwr[1][k] = lev.fw[k][2 * ihi + 1];
+  // ---- setup: stencil slots (lanes 0..NSLOT-1), face tables (lanes 16..) ----
+  if (lane < NSLOT) {
+    long long e = -1;
+    int cc[D], c2[D];
+    if (lane == 0) {
+      e = E;
+    } else if (lane < 1 + D) {
+      const int k = lane - 1;
+      if (shifted<D>(c, n, lev.nf[k] == n, k, -1, cc)) e = elem_index<D>(cc, n);
+    } else if (lane < 1 + 2 * D) {
+      const int k = lane - 1 - D;
+      if (shifted<D>(c, n, lev.nf[k] == n, k, +1, cc)) e = elem_index<D>(cc, n);
+    } else {
+      const int u = lane - 1 - 2 * D;
+      const int k = u / (D - 1), q = u % (D - 1);
+      const int kk = q < k ? q : q + 1;
+      if (shifted<D>(c, n, lev.nf[k] == n, k, +1, cc) && shifted<D>(cc, n, lev.nf[kk] == n, kk, -1, c2))
+        e = elem_index<D>(c2, n);
+    }
+    w.slot_e[lane] = e;
+  } else if (lane >= 16 && lane < 16 + NFS * D * 2) {
+    const int u = lane - 16;
+    const int fi = u / (2 * D), k = (u / 2) % D, side = u % 2;
+    int cF[D];
+    bool valid = true;
+    if (fi == 0) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) cF[j] = c[j];
+    } else {
+      valid = shifted<D>(c, n, lev.nf[fi - 1] == n, fi - 1, +1, cF);
+    }
+    unsigned char ty = F_NONE;
+    T wl = 0, wr = 0;
+    long long id = 0;
+    if (valid) {
+      const bool per = lev.nf[k] == n;
+      int f = cF[k] + side;
+      if (per) f %= n;
+      id = face_index<D>(cF, n, lev.nf[k], k, f);
+      ty = lev.ftype[k][id];
+      wl = lev.fw[k][2 * id];
+      wr = lev.fw[k][2 * id + 1];
+    }
+    w.fid[fi][k][side] = id;
+    w.ft[fi][k][side] = ty;
+    w.fwl[fi][k][side] = wl;
+    w.fwr[fi][k][side] = wr;
+    if (side == 0) {
+      int sl;
+      if (fi == 0) sl = 1 + k;
+      else if (k == fi - 1) sl = 0;
+      else sl = 1 + 2 * D + (fi - 1) * (D - 1) + (k < fi - 1 ? k : k - 1);
+      w.lslot[fi][k] = sl;
     }
   }
   __syncthreads();
-  // ---- phase 1: stage x of the stencil (scaled by D when set) ----
-  for (int t = lane; t < S::NSLOT * NB; t += WG) {
-    int sl = t / NB, i = t % NB;
-    long long e = w.slot_e[sl];
+  // ---- phase 1: stage x of the stencil (scaled when set), M_mu, penalty matrices ----
+  for (int t = lane; t < NSLOT * NB; t += WG) {
+    const int sl = t / NB, i = t % NB;
+    const long long e = w.slot_e[sl];
     T v = 0;
     if (e >= 0) {
       v = x[e * NB + i];
@@ -179,201 +209,220 @@ __device__ void element_operator(const DevLevel<T>& lev, const Tab1D& tab, int64
     }
     w.xs[sl][i] = v;
   }
-  __syncthreads();
-  // ---- phase 2: g_F = G u at F in {E, E+e_0, .., E+e_{D-1}} ----
-  for (int t = lane; t < S::NFS * D * D * NQ; t += WG) {
-    int a = t % NQ;
-    int comp = (t / NQ) % (D * D);
-    int fi = t / (NQ * D * D);
-    int i = comp / D, k = comp % D;
-    int sF = (fi == 0) ? 0 : 1 + D + (fi - 1);
-    T val = 0;
-    if (w.slot_e[sF] >= 0) {
-      int cF[D];
-      if (fi == 0) {
-        for (int j = 0; j < D; ++j) cF[j] = c[j];
-      } else {
-        int kk = fi - 1;
-        shifted<D>(c, n, lev.nf[kk] == n, kk, +1, cF);
+  if constexpr (W::STAGE_M) {
+    if (lev.mmu) {
+      for (int t = lane; t < NFS * NQ * NQ; t += WG) {
+        const int fi = t / (NQ * NQ);
+        const long long e = w.slot_e[fi == 0 ? 0 : 1 + D + (fi - 1)];
+        w.mm[fi][t % (NQ * NQ)] = e >= 0 ? lev.mmu[(size_t)e * NQ * NQ + t % (NQ * NQ)] : (T)0;
       }
-      int sL;   // slot of F - e_k
-      if (fi == 0) sL = 1 + k;
-      else if (k == fi - 1) sL = 0;
-      else {
-        int kk = fi - 1;
-        int q = (k < kk) ? k : k - 1;
-        sL = 1 + 2 * D + kk * (D - 1) + q;
-      }
-      const bool per = lev.nf[k] == n;
-      int flo = cF[k];
-      int fhi = per ? (cF[k] + 1) % n : cF[k] + 1;
-      int64_t ilo = face_index<D>(cF, n, lev.nf[k], k, flo);
-      int64_t ihi = face_index<D>(cF, n, lev.nf[k], k, fhi);
-      unsigned char tlo = lev.ftype[k][ilo];
-      unsigned char thi = lev.ftype[k][ihi];
-      T wR = lev.fw[k][2 * ilo + 1];
-      T wL = lev.fw[k][2 * ihi];
-      const T* u = &w.xs[sF][i * NQ];
-      const T* uL = &w.xs[sL][i * NQ];
-      int ak = digit<M>(a, k), tt = tang<M>(a, k);
-      T vol = 0, trlo = 0, trhi = 0, trLhi = 0;
-      for (int bb = 0; bb < M; ++bb) {
-        T ub = u[compose<M>(tt, bb, k)];
-        vol += (T)tab.K[ak * M + bb] * ub;
-        trlo += (T)tab.e0[bb] * ub;
-        trhi += (T)tab.e1[bb] * ub;
-        trLhi += (T)tab.e1[bb] * uL[compose<M>(tt, bb, k)];
-      }
-      T jlo = trlo - ((tlo == F_INTRA || tlo == F_INTER) ? trLhi : (T)0);
-      T acc = vol;
-      if (tlo != F_NONE) acc += wR * (T)tab.e0[ak] * jlo;
-      if (thi == F_DIR_HI) acc += wL * (T)tab.e1[ak] * (-trhi);
-      val = hinv * acc;
     }
-    w.g[fi][comp][a] = val;
+  }
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+    for (int t = lane; t < 2 * MT * MT; t += WG) {
+      const int side = t / (MT * MT), q = t % (MT * MT);
+      w.th[side][k][q] = lev.fT[k][(size_t)w.fid[0][k][side] * MT * MT + q];
+    }
+  __syncthreads();
+  // ---- phase 2: g_F = G_k u_i at F in {E, E+e_0, .., E+e_{D-1}} ----
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    for (int t = lane; t < NFS * D * NQ; t += WG) {
+      const int a = t % NQ, i = (t / NQ) % D, fi = t / (NQ * D);
+      const int sF = (fi == 0) ? 0 : 1 + D + (fi - 1);
+      T val = 0;
+      if (w.slot_e[sF] >= 0) {
+        const unsigned char tlo = w.ft[fi][k][0], thi = w.ft[fi][k][1];
+        const T wR = w.fwr[fi][k][0], wL = w.fwl[fi][k][1];
+        const T* u = &w.xs[sF][i * NQ];
+        const T* uL = &w.xs[w.lslot[fi][k]][i * NQ];
+        const int ak = digit<M>(a, k), tt = tang<M>(a, k);
+        T vol = 0, trlo = 0, trhi = 0, trLhi = 0;
+#pragma unroll
+        for (int bb = 0; bb < M; ++bb) {
+          const T ub = u[compose<M>(tt, bb, k)];
+          vol += (T)tab.K[ak * M + bb] * ub;
+          trlo += (T)tab.e0[bb] * ub;
+          trhi += (T)tab.e1[bb] * ub;
+          trLhi += (T)tab.e1[bb] * uL[compose<M>(tt, bb, k)];
+        }
+        const T jlo = trlo - ((tlo == F_INTRA || tlo == F_INTER) ? trLhi : (T)0);
+        T acc = vol;
+        if (tlo != F_NONE) acc += wR * (T)tab.e0[ak] * jlo;
+        if (thi == F_DIR_HI) acc -= wL * (T)tab.e1[ak] * trhi;
+        val = hinv * acc;
+      }
+      w.g[fi][i * D + k][a] = val;
+    }
   }
   __syncthreads();
-  // ---- phase 3: s = M_mu (g + gamma g^T) ----
-  constexpr int NS0 = D * D * NQ;
-  for (int t = lane; t < NS0 + D * D * NQ; t += WG) {
-    int fi, i, k, a;
-    if (t < NS0) {
-      fi = 0; a = t % NQ; int comp = t / NQ; i = comp / D; k = comp % D;
-    } else {
-      int u = t - NS0; a = u % NQ; int q = u / NQ; fi = 1 + q / D; i = q % D; k = fi - 1;
-    }
-    int sF = (fi == 0) ? 0 : 1 + D + (fi - 1);
-    T val = 0;
-    long long eF = w.slot_e[sF];
-    if (eF >= 0) {
-      const T* g1 = w.g[fi][i * D + k];
-      const T* g2 = w.g[fi][k * D + i];
-      const T gam = (T)lev.gamma;
-      if (lev.mmu) {
-        const T* Mm = lev.mmu + (size_t)eF * NQ * NQ;
-        for (int bb = 0; bb < NQ; ++bb) val += Mm[bb * NQ + a] * (g1[bb] + gam * g2[bb]);
+  // ---- phase 3: s = M_mu (g + gamma g^T); for E all (i,k), for E+e_k the (i,k) column ----
+  {
+    constexpr int NS0 = D * D * NQ;
+    const T gam = (T)lev.gamma;
+    for (int t = lane; t < NS0 + D * D * NQ; t += WG) {
+      int fi, i, k, a;
+      if (t < NS0) {
+        fi = 0;
+        a = t % NQ;
+        const int comp = t / NQ;
+        i = comp / D;
+        k = comp % D;
       } else {
-        val = lev.mu_const * (g1[a] + gam * g2[a]);
+        const int u = t - NS0;
+        a = u % NQ;
+        const int q = u / NQ;
+        fi = 1 + q / D;
+        i = q % D;
+        k = fi - 1;
       }
+      const int sF = (fi == 0) ? 0 : 1 + D + (fi - 1);
+      T val = 0;
+      const long long eF = w.slot_e[sF];
+      if (eF >= 0) {
+        const T* g1 = w.g[fi][i * D + k];
+        const T* g2 = w.g[fi][k * D + i];
+        if (lev.mmu) {
+          const T* Mm;
+          if constexpr (W::STAGE_M) Mm = w.mm[fi];
+          else Mm = lev.mmu + (size_t)eF * NQ * NQ;
+#pragma unroll 4
+          for (int bb = 0; bb < NQ; ++bb) val += Mm[bb * NQ + a] * (g1[bb] + gam * g2[bb]);
+        } else {
+          val = lev.mu_const * (g1[a] + gam * g2[a]);
+        }
+      }
+      w.s[fi][i * D + k][a] = val;
     }
-    w.s[fi][i * D + k][a] = val;
   }
   __syncthreads();
   // ---- phase 4: traces ----
-  constexpr int NTX = 2 * D * (D + 1) * MT;
-  constexpr int NTS = 3 * D * D * MT;
-  for (int t = lane; t < 2 * NTX + NTS; t += WG) {
-    if (t < NTX) {
-      int tt = t % MT; int f = (t / MT) % (D + 1); int k = (t / (MT * (D + 1))) % D; int side = t / (MT * (D + 1) * D);
-      const T* u = &w.xs[0][f * NQ];
-      const double* e = side ? tab.e1 : tab.e0;
-      T v = 0;
-      for (int bb = 0; bb < M; ++bb) v += (T)e[bb] * u[compose<M>(tt, bb, k)];
-      w.trx[side][k][f][tt] = v;
-    } else if (t < 2 * NTX) {
-      int r = t - NTX;
-      int tt = r % MT; int f = (r / MT) % (D + 1); int k = (r / (MT * (D + 1))) % D; int side = r / (MT * (D + 1) * D);
-      // side 0: x_{E-e_k} at its high face; side 1: x_{E+e_k} at its low face
-      int sl = side ? 1 + D + k : 1 + k;
-      const T* u = &w.xs[sl][f * NQ];
-      const double* e = side ? tab.e0 : tab.e1;
-      T v = 0;
-      for (int bb = 0; bb < M; ++bb) v += (T)e[bb] * u[compose<M>(tt, bb, k)];
-      w.trn[side][k][f][tt] = v;
-    } else {
-      int r = t - 2 * NTX;
-      int tt = r % MT; int i = (r / MT) % D; int k = (r / (MT * D)) % D; int which = r / (MT * D * D);
-      const T* sv = (which == 2) ? w.s[1 + k][i * D + k] : w.s[0][i * D + k];
-      const double* e = (which == 1) ? tab.e1 : tab.e0;
-      T v = 0;
-      for (int bb = 0; bb < M; ++bb) v += (T)e[bb] * sv[compose<M>(tt, bb, k)];
-      w.trs[which][k][i][tt] = v;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    constexpr int NX = 2 * (D + 1) * MT;   // x_E lo/hi
+    constexpr int NN = 2 * (D + 1) * MT;   // neighbour traces
+    constexpr int NT = 3 * D * MT;         // s traces
+    for (int t = lane; t < NX + NN + NT; t += WG) {
+      if (t < NX) {
+        const int tt = t % MT, f = (t / MT) % (D + 1), side = t / (MT * (D + 1));
+        const T* u = &w.xs[0][f * NQ];
+        T v = 0;
+#pragma unroll
+        for (int bb = 0; bb < M; ++bb) v += (T)(side ? tab.e1[bb] : tab.e0[bb]) * u[compose<M>(tt, bb, k)];
+        w.trx[side][k][f][tt] = v;
+      } else if (t < NX + NN) {
+        const int r = t - NX;
+        const int tt = r % MT, f = (r / MT) % (D + 1), side = r / (MT * (D + 1));
+        const T* u = &w.xs[side ? 1 + D + k : 1 + k][f * NQ];
+        T v = 0;
+#pragma unroll
+        for (int bb = 0; bb < M; ++bb) v += (T)(side ? tab.e0[bb] : tab.e1[bb]) * u[compose<M>(tt, bb, k)];
+        w.trn[side][k][f][tt] = v;
+      } else {
+        const int r = t - NX - NN;
+        const int tt = r % MT, i = (r / MT) % D, which = r / (MT * D);
+        const T* sv = (which == 2) ? w.s[1 + k][i * D + k] : w.s[0][i * D + k];
+        T v = 0;
+#pragma unroll
+        for (int bb = 0; bb < M; ++bb) v += (T)(which == 1 ? tab.e1[bb] : tab.e0[bb]) * sv[compose<M>(tt, bb, k)];
+        w.trs[which][k][i][tt] = v;
+      }
     }
   }
   __syncthreads();
   // ---- phase 5: face fluxes ----
-  for (int t = lane; t < 2 * D * (D + 1) * MT; t += WG) {
-    int tt = t % MT; int f = (t / MT) % (D + 1); int k = (t / (MT * (D + 1))) % D; int side = t / (MT * (D + 1) * D);
-    unsigned char ty = w.ft[side][k];
-    const T wL = w.fwl[side][k], wR = w.fwr[side][k];
-    const T* Th = lev.fT[k] + (size_t)w.fidx[side][k] * MT * MT + tt * MT;
-    T v = 0;
-    if (f < D) {
-      const int i = f;
-      if (side == 0) {
-        // E is the high element R of its low face
-        if (ty != F_NONE) v += wR * w.trs[0][k][i][tt];
-        if (ty == F_DIR_LO) {
-          T acc = 0;
-          for (int q = 0; q < MT; ++q) acc += Th[q] * w.trx[0][k][i][q];
-          v += acc;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    for (int t = lane; t < 2 * (D + 1) * MT; t += WG) {
+      const int tt = t % MT, f = (t / MT) % (D + 1), side = t / (MT * (D + 1));
+      const unsigned char ty = w.ft[0][k][side];
+      const T wL = w.fwl[0][k][side], wR = w.fwr[0][k][side];
+      const T* Th = &w.th[side][k][tt * MT];
+      T v = 0;
+      if (f < D) {
+        const int i = f;
+        if (side == 0) {
+          // E is the high element R of its low face
+          if (ty != F_NONE) v += wR * w.trs[0][k][i][tt];
+          if (ty == F_DIR_LO) {
+            T acc = 0;
+#pragma unroll
+            for (int q = 0; q < MT; ++q) acc += Th[q] * w.trx[0][k][i][q];
+            v += acc;
+          } else if (ty == F_INTER) {
+            T acc = 0;
+#pragma unroll
+            for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trn[0][k][i][q] - w.trx[0][k][i][q]);
+            v -= acc;
+          }
+          if (k == i && ty != F_NONE) v -= wR * w.trx[0][k][D][tt];
+        } else {
+          // E is the low element L of its high face
+          const T sR = (ty == F_INTRA || ty == F_INTER) ? w.trs[2][k][i][tt] : (T)0;
+          v -= wR * sR + wL * w.trs[1][k][i][tt];
+          if (ty == F_DIR_HI) {
+            T acc = 0;
+#pragma unroll
+            for (int q = 0; q < MT; ++q) acc += Th[q] * w.trx[1][k][i][q];
+            v += acc;
+          } else if (ty == F_INTER) {
+            T acc = 0;
+#pragma unroll
+            for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trx[1][k][i][q] - w.trn[1][k][i][q]);
+            v += acc;
+          }
+          if (k == i) {
+            const T pR = (ty == F_INTRA || ty == F_INTER) ? w.trn[1][k][D][tt] : (T)0;
+            v += wR * pR + wL * w.trx[1][k][D][tt];
+          }
         }
-        if (ty == F_INTER) {
-          T acc = 0;
-          for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trn[0][k][i][q] - w.trx[0][k][i][q]);
-          v -= acc;
-        }
-        if (k == i && ty != F_NONE) v -= wR * w.trx[0][k][D][tt];
-      } else {
-        // E is the low element L of its high face
-        T sR = (ty == F_INTRA || ty == F_INTER) ? w.trs[2][k][i][tt] : (T)0;
-        v -= wR * sR + wL * w.trs[1][k][i][tt];
-        if (ty == F_DIR_HI) {
-          T acc = 0;
-          for (int q = 0; q < MT; ++q) acc += Th[q] * w.trx[1][k][i][q];
-          v += acc;
-        }
-        if (ty == F_INTER) {
-          T acc = 0;
-          for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trx[1][k][i][q] - w.trn[1][k][i][q]);
-          v += acc;
-        }
-        if (k == i) {
-          T pR = (ty == F_INTRA || ty == F_INTER) ? w.trn[1][k][D][tt] : (T)0;
-          v += wR * pR + wL * w.trx[1][k][D][tt];
-        }
-      }
-    } else {
-      if (ty == F_INTRA) {
+      } else if (ty == F_INTRA) {
         T acc = 0;
         if (side == 0) {
+#pragma unroll
           for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trn[0][k][D][q] - w.trx[0][k][D][q]);
           v = acc;
         } else {
+#pragma unroll
           for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trx[1][k][D][q] - w.trn[1][k][D][q]);
           v = -acc;
         }
       }
+      w.flux[side][k][f][tt] = hinv * v;
     }
-    w.flux[side][k][f][tt] = hinv * v;
   }
   __syncthreads();
   // ---- phase 6: assemble (A x)_E and the residual ----
   for (int t = lane; t < NB; t += WG) {
-    int f = t / NQ, a = t % NQ;
+    const int f = t / NQ, a = t % NQ;
     T acc = 0;
     if (f < D) {
       const int i = f;
+#pragma unroll
       for (int k = 0; k < D; ++k) {
-        int ak = digit<M>(a, k), tt = tang<M>(a, k);
+        const int ak = digit<M>(a, k), tt = tang<M>(a, k);
         const T* sv = w.s[0][i * D + k];
         T vol = 0;
+#pragma unroll
         for (int bb = 0; bb < M; ++bb) vol += (T)tab.K[bb * M + ak] * sv[compose<M>(tt, bb, k)];
         acc += hinv * vol;
         acc += (T)tab.e0[ak] * w.flux[0][k][i][tt] + (T)tab.e1[ak] * w.flux[1][k][i][tt];
-      }
-      {
-        int ai = digit<M>(a, i), ti = tang<M>(a, i);
-        const T* pv = &w.xs[0][D * NQ];
-        T vol = 0;
-        for (int bb = 0; bb < M; ++bb) vol += (T)tab.K[bb * M + ai] * pv[compose<M>(ti, bb, i)];
-        acc -= hinv * vol;
+        if (k == i) {
+          const T* pv = &w.xs[0][D * NQ];
+          T pvol = 0;
+#pragma unroll
+          for (int bb = 0; bb < M; ++bb) pvol += (T)tab.K[bb * M + ak] * pv[compose<M>(tt, bb, k)];
+          acc -= hinv * pvol;
+        }
       }
       acc += lev.rho_delta * w.xs[0][t];
     } else {
+#pragma unroll
       for (int i = 0; i < D; ++i) acc -= w.g[0][i * D + i][a];
+#pragma unroll
       for (int k = 0; k < D; ++k) {
-        int ak = digit<M>(a, k), tt = tang<M>(a, k);
+        const int ak = digit<M>(a, k), tt = tang<M>(a, k);
         acc += (T)tab.e0[ak] * w.flux[0][k][D][tt] + (T)tab.e1[ak] * w.flux[1][k][D][tt];
       }
     }
@@ -383,18 +432,27 @@ __device__ void element_operator(const DevLevel<T>& lev, const Tab1D& tab, int64
   __syncthreads();
 }
 
-template <typename TI>
-__device__ __forceinline__ float load_inv(const TI* p);
-template <>
-__device__ __forceinline__ float load_inv<float>(const float* p) { return *p; }
-template <>
-__device__ __forceinline__ float load_inv<uint16_t>(const uint16_t* p) {
-  unsigned int u = ((unsigned int)(*p)) << 16;
-  return __uint_as_float(u);
+// 16-byte word of the inverse and entry v of it in the arithmetic type
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T, typename TI>
+__device__ __forceinline__ T inv_entry(const u32x4& raw, int v) {
+  if constexpr (sizeof(TI) == 8) {
+    const unsigned long long bits = (unsigned long long)raw[2 * v] | ((unsigned long long)raw[2 * v + 1] << 32);
+    return (T)__longlong_as_double((long long)bits);
+  } else if constexpr (sizeof(TI) == 4) {
+    return (T)__uint_as_float(raw[v]);
+  } else {
+    const unsigned int word = raw[v >> 1];
+    const unsigned int bits = (v & 1) ? (word & 0xffff0000u) : (word << 16);
+    return (T)__uint_as_float(bits);
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Smoother: one colour pass.  x_E += Ainv_E (b - A x)_E for the listed elements.
+// The element's inverse (lane-blocked layout, see inv_layout) is prefetched
+// into registers before the residual is evaluated.
 // ---------------------------------------------------------------------------
 template <typename T, typename TI, int D, int P>
 __global__ __launch_bounds__(WG) void k_smooth_colour(DevLevel<T> lev, Tab1D tab, const int* __restrict__ elems,
@@ -402,21 +460,42 @@ __global__ __launch_bounds__(WG) void k_smooth_colour(DevLevel<T> lev, Tab1D tab
                                                       T* __restrict__ x) {
   using S = Sz<D, P>;
   constexpr int NB = S::NB;
+  constexpr InvLayout LY = inv_layout(NB, (int)sizeof(TI));
+  constexpr int V = LY.V, RGS = LY.RG * LY.S, CS = LY.CS;
+  constexpr int PF = CS < 16 ? CS : 16;     // chunks prefetched before the residual
   __shared__ Work<T, D, P> w;
+  __shared__ T part[LY.S][LY.NBP];
+  const int lane = threadIdx.x;
   const int64_t idx = blockIdx.x;
   const int64_t E = elems[idx];
+  const u32x4* Ai = reinterpret_cast<const u32x4*>(inv + (size_t)idx * NB * LY.NBP);
+  u32x4 pre[PF];
+  if (lane < RGS) {
+#pragma unroll
+    for (int kk = 0; kk < PF; ++kk) pre[kk] = __builtin_nontemporal_load(&Ai[kk * RGS + lane]);
+  }
   element_operator<T, D, P>(lev, tab, E, x, b, 0, w);
-  const TI* Ai = inv + (size_t)idx * NB * NB;   // column-major: Ai[j*NB + i] = Ainv[i][j]
-  for (int row = threadIdx.x; row < NB; row += WG) {
-    T y = 0;
-#pragma unroll 8
-    for (int j = 0; j < NB; ++j) {
-      T a;
-      if constexpr (sizeof(TI) == sizeof(T)) a = Ai[(size_t)j * NB + row];
-      else a = (T)load_inv<TI>(Ai + (size_t)j * NB + row);
-      y += a * w.res[j];
+  if (lane < RGS) {
+    const int g = lane % LY.RG, s = lane / LY.RG;
+    T y[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) y[v] = 0;
+#pragma unroll
+    for (int kk = 0; kk < CS; ++kk) {
+      const u32x4 raw = (kk < PF) ? pre[kk < PF ? kk : 0] : __builtin_nontemporal_load(&Ai[kk * RGS + lane]);
+      const T r = w.res[s * CS + kk];
+#pragma unroll
+      for (int v = 0; v < V; ++v) y[v] += inv_entry<T, TI>(raw, v) * r;
     }
-    x[E * NB + row] += y;
+#pragma unroll
+    for (int v = 0; v < V; ++v) part[s][g * V + v] = y[v];
+  }
+  __syncthreads();
+  for (int row = lane; row < NB; row += WG) {
+    T acc = 0;
+#pragma unroll
+    for (int s = 0; s < LY.S; ++s) acc += part[s][row];
+    x[E * NB + row] += acc;
   }
 }
 
@@ -434,8 +513,9 @@ __global__ __launch_bounds__(WG) void k_residual(DevLevel<T> lev, Tab1D tab, con
 template <int D, int M>
 __device__ __forceinline__ double pfull(const Tab1D& tab, int o, int af, int ac) {
   double v = 1.0;
+#pragma unroll
   for (int k = 0; k < D; ++k) {
-    int fk = (af / ipow<M>(k)) % M, ck = (ac / ipow<M>(k)) % M;
+    const int fk = (af / ipow<M>(k)) % M, ck = (ac / ipow<M>(k)) % M;
     v *= tab.P[(o >> k) & 1][fk * M + ck];
   }
   return v;
@@ -454,19 +534,23 @@ __global__ __launch_bounds__(WG) void k_residual_restrict(DevLevel<T> lev, Tab1D
   int cc[D];
   {
     int64_t r = C;
+#pragma unroll
     for (int j = 0; j < D; ++j) { cc[j] = (int)(r % nc); r /= nc; }
   }
   T acc[PER];
+#pragma unroll
   for (int q = 0; q < PER; ++q) acc[q] = 0;
   for (int o = 0; o < (1 << D); ++o) {
     int cf[D];
+#pragma unroll
     for (int j = 0; j < D; ++j) cf[j] = 2 * cc[j] + ((o >> j) & 1);
     const int64_t E = elem_index<D>(cf, lev.n);
     element_operator<T, D, P>(lev, tab, E, x, b, 0, w);
+#pragma unroll
     for (int q = 0; q < PER; ++q) {
-      int t = threadIdx.x + q * WG;
+      const int t = threadIdx.x + q * WG;
       if (t < NB) {
-        int f = t / NQ, ac = t % NQ;
+        const int f = t / NQ, ac = t % NQ;
         T s = 0;
         for (int af = 0; af < NQ; ++af) s += (T)pfull<D, M>(tab, o, af, ac) * w.res[f * NQ + af];
         acc[q] += s;
@@ -474,8 +558,9 @@ __global__ __launch_bounds__(WG) void k_residual_restrict(DevLevel<T> lev, Tab1D
     }
     __syncthreads();
   }
+#pragma unroll
   for (int q = 0; q < PER; ++q) {
-    int t = threadIdx.x + q * WG;
+    const int t = threadIdx.x + q * WG;
     if (t < NB) rc[C * NB + t] = acc[q];
   }
 }

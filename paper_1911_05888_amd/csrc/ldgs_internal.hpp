@@ -45,6 +45,27 @@ struct Tab1D {
   double P[2][MAXM * MAXM];
 };
 
+// Lane-blocked layout of one element's inverse block for the smoother's
+// matrix-vector product.  V = 16 / (bytes per entry) values per 16-byte load,
+// NBP = nb rounded up to a multiple of V (padding rows are zero), RG = NBP / V
+// row groups, S = number of column subsets (the largest divisor of nb with
+// RG * S <= 64 lanes), CS = nb / S columns per subset.  Lane l = g + RG * s
+// owns rows V g .. V g + V - 1 of columns s * CS + kk, kk < CS; its chunk kk
+// is stored at entry offset (kk * RG * S + l) * V, so the RG * S lanes read
+// consecutive 16-byte words at every step.  Element stride: nb * NBP entries.
+struct InvLayout {
+  int V, NBP, RG, S, CS;
+};
+constexpr InvLayout inv_layout(int nb, int bytes) {
+  InvLayout L{16 / bytes, 0, 0, 1, nb};
+  L.NBP = (nb + L.V - 1) / L.V * L.V;
+  L.RG = L.NBP / L.V;
+  for (int s = 1; s <= 64; ++s)
+    if (nb % s == 0 && L.RG * s <= 64) L.S = s;
+  L.CS = nb / L.S;
+  return L;
+}
+
 // Device view of one level's operator, element type T.
 template <typename T>
 struct DevLevel {

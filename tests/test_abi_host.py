@@ -1,0 +1,168 @@
+"""The C-ABI library on the CPU: symbol exports, argument validation and the
+host-side setup (operator on every level, block inverses, bottom solver,
+right-hand side) against the oracle.  No GPU compute: contexts are built with
+``host_only`` set, which the library supports for setup validation."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from synth import (Problem, ConstField, c1_periodic_standard, c2_dirichlet_varmu, c3_unsteady_periodic,
+                   c4a_square_inclusion)
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ldgs.h")
+
+
+def _declared_functions():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:ldgs_status|const char\*)\s+(ldgs_\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1911_05888_amd.ldgs import LIB_PATH, EXPORTED
+    lib = C.CDLL(LIB_PATH)
+    declared = _declared_functions()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(declared) == sorted(EXPORTED)
+
+
+def test_status_strings():
+    from paper_1911_05888_amd.ldgs import _lib
+    for s in range(9):
+        assert _lib.ldgs_status_str(s)
+
+
+def _ctx(prob, **kw):
+    from paper_1911_05888_amd.ldgs import Context
+    return Context(prob, host_only=True, **kw)
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("dim", 4, 1), ("n", 12, 1), ("degree", 4, 1), ("coarsest_n", 1, 1), ("form", 2, 1),
+    ("vprec", 7, 1), ("coloring", 9, 1),
+])
+def test_argument_validation(field, value, status):
+    from paper_1911_05888_amd.ldgs import _lib, problem_struct
+    s, keep = problem_struct(c1_periodic_standard(n=8), host_only=True)
+    setattr(s, field, value)
+    h = C.c_void_p()
+    st = _lib.ldgs_setup(C.byref(s), C.byref(h))
+    assert st == status
+    assert h.value is None
+    assert _lib.ldgs_last_error(None)
+
+
+def test_stress_boundaries_are_unsupported():
+    from paper_1911_05888_amd.ldgs import _lib, problem_struct, E_UNSUPPORTED, STRESS
+    s, keep = problem_struct(c2_dirichlet_varmu(n=8, p=2), host_only=True)
+    s.bc[0] = STRESS
+    h = C.c_void_p()
+    assert _lib.ldgs_setup(C.byref(s), C.byref(h)) == E_UNSUPPORTED
+
+
+def test_red_black_is_rejected_for_viscous_stress():
+    """gamma = 1 couples E to E + e_j - e_i, which red-black colours alike."""
+    from paper_1911_05888_amd.ldgs import LdgsError, E_COLORING
+    prob = c2_dirichlet_varmu(n=8, p=2)
+    with pytest.raises(LdgsError) as ei:
+        _ctx(prob, coloring="rb")
+    assert ei.value.status == E_COLORING
+
+
+def test_unsupported_combinations_are_reported():
+    from paper_1911_05888_amd.ldgs import LdgsError, E_UNSUPPORTED
+    with pytest.raises(LdgsError) as ei:
+        _ctx(c4a_square_inclusion(n=8, p=2))
+    assert ei.value.status == E_UNSUPPORTED
+    prob = Problem(name="u", dim=2, n=8, p=1, gamma=1, bc=("periodic", "periodic"),
+                   mu=c2_dirichlet_varmu(n=8).mu, rho=ConstField(1.0), delta=1e-3)
+    with pytest.raises(LdgsError) as ei:
+        _ctx(prob)
+    assert ei.value.status == E_UNSUPPORTED
+
+
+HOST_CASES = {
+    "c1_n8_p2": lambda: c1_periodic_standard(n=8, p=2),
+    "c2_n8_p3": lambda: c2_dirichlet_varmu(n=8, p=3),
+    "c2_n16_p1": lambda: c2_dirichlet_varmu(n=16, p=1),
+    "per3d_n4_p2": lambda: Problem(name="p3", dim=3, n=4, p=2, gamma=1, bc=("periodic",) * 3),
+    "c3_n8_p1": lambda: c3_unsteady_periodic(n=8, p=1, re_eff=1000.0, h_ref=1.0 / 64),
+    "dir3d_n4_p1": lambda: Problem(name="d3", dim=3, n=4, p=1, gamma=0, bc=("dirichlet",) * 3),
+}
+
+
+@pytest.mark.parametrize("name", list(HOST_CASES))
+def test_host_setup_matches_oracle(name):
+    """Level operators (matrix-free host evaluation), diagonal-block inverses
+    and the bottom pseudo-inverse of the library agree with the oracle's."""
+    from oracle import build_hierarchy
+    prob = HOST_CASES[name]()
+    H = build_hierarchy(prob)
+    ctx = _ctx(prob)
+    assert ctx.n_levels == len(H.levels)
+    rng = np.random.Generator(np.random.PCG64(5))
+    for l, lv in enumerate(H.levels):
+        x = rng.standard_normal(lv.A.shape[0])
+        y_o = lv.A @ x
+        assert np.linalg.norm(ctx.host_level_apply(l, x) - y_o) <= 1e-13 * np.linalg.norm(y_o), l
+        if l < len(H.levels) - 1:
+            for E in (0, lv.NE // 3, lv.NE - 1):
+                inv = ctx.level_block_inverse(l, E)
+                assert np.abs(inv - lv.Ainv[E]).max() <= 1e-12 * np.abs(lv.Ainv[E]).max()
+    pinv, eig = ctx.bottom_info()
+    lam_o = np.sort(H.levels[-1].eig)
+    assert np.allclose(np.sort(eig), lam_o, atol=1e-10 * np.abs(lam_o).max())
+    bot = H.levels[-1]
+    b = rng.standard_normal(bot.A.shape[0])
+    fields = [prob.dim] if H.k0 == 1 else list(range(prob.dim + 1))
+    for f in fields:                       # b in range(A_c): orthogonal to the constant fields
+        sel = np.arange(bot.NE) * bot.nb + f * bot.nq
+        b[sel] -= b[sel].mean()
+    x = pinv @ b
+    x = x + pinv @ (b - bot.A @ x)
+    scale = np.linalg.norm(np.abs(b) + abs(bot.A) @ np.abs(x))
+    assert np.linalg.norm(b - bot.A @ x) <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("name", ["c1_n8_p2", "c2_n8_p3", "c3_n8_p1"])
+def test_host_rhs_matches_oracle(name):
+    from oracle import build_hierarchy
+    from oracle.rhs import assemble_rhs
+    prob = HOST_CASES[name]()
+    H = build_hierarchy(prob)
+    b_o = assemble_rhs(prob, H.fine.ops)
+    b_l = _ctx(prob).assemble_rhs(prob.rhs_source())
+    assert np.linalg.norm(b_l - b_o) <= 1e-13 * np.linalg.norm(b_o)
+
+
+def test_host_only_context_refuses_device_calls():
+    from paper_1911_05888_amd.ldgs import LdgsError, E_UNSUPPORTED
+    ctx = _ctx(c1_periodic_standard(n=8))
+    x = np.zeros(ctx.ndof)
+    with pytest.raises(LdgsError) as ei:
+        ctx.vcycle(x, x.copy())
+    assert ei.value.status == E_UNSUPPORTED
+
+
+def test_inverse_layout_covers_every_entry():
+    """The smoother's lane-blocked layout (include-level contract shared by the
+    host packing and the kernel) places every entry of the block exactly once."""
+    for nb in (12, 27, 32, 48, 108):
+        for bytes_ in (8, 4, 2):
+            V = 16 // bytes_
+            NBP = (nb + V - 1) // V * V
+            RG = NBP // V
+            S = max(s for s in range(1, 65) if nb % s == 0 and RG * s <= 64)
+            CS = nb // S
+            seen = np.zeros((NBP, nb), dtype=int)
+            for kk in range(CS):
+                for l in range(RG * S):
+                    g, s = l % RG, l // RG
+                    for v in range(V):
+                        seen[V * g + v, s * CS + kk] += 1
+            assert (seen == 1).all()
