@@ -216,9 +216,31 @@ DevLevel<T> make_view(ldgs_ctx* c, const Level& L, bool with_scale) {
       v.fT[k] = nullptr;
     }
   }
-  (void)mt;
-  (void)nq;
+  int lg = 0;
+  while ((1 << lg) < L.n) ++lg;
+  v.lgn = lg;
   v.mmu = L.mu_is_const ? nullptr : upload<T>(c, L.mmu);
+  v.rmu = nullptr;
+  if (!L.mu_is_const) {
+    // R_k = (e0^T)_k M_mu: low-face trace rows of the mass block along axis k
+    const int M = c->g.p + 1;
+    std::vector<double> R((size_t)L.NE * d * mt * nq, 0.0);
+    for (int64_t e = 0; e < L.NE; ++e) {
+      const double* Me = L.mmu.data() + (size_t)e * nq * nq;
+      for (int k = 0; k < d; ++k) {
+        int lo = 1;
+        for (int j = 0; j < k; ++j) lo *= M;
+        double* Rk = R.data() + ((size_t)e * d + k) * mt * nq;
+        for (int t = 0; t < mt; ++t)
+          for (int cc = 0; cc < M; ++cc) {
+            const int a = t % lo + lo * cc + lo * M * (t / lo);
+            const double w = c->tab.e0[cc];
+            for (int b = 0; b < nq; ++b) Rk[t * nq + b] += w * Me[a * nq + b];
+          }
+      }
+    }
+    v.rmu = upload<T>(c, R);
+  }
   v.mu_const = (T)L.mu_c;
   v.rho_delta = (T)L.rho_delta;
   v.dscale = (with_scale && !L.dscale.empty()) ? upload<T>(c, L.dscale) : nullptr;

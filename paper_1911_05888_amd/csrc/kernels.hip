@@ -2,11 +2,12 @@
 //
 // One 64-lane work-group (one wavefront) owns one element.  It stages the x
 // coefficients of the element and of the neighbours its residual depends on
-// in LDS, evaluates (A x)_E matrix-free from the factored operator
-// (G, M_mu, penalty face matrices), and then, in the smoother, applies the
-// element's precomputed inverse diagonal block streamed from HBM
-// (column-major, colour-major order so that consecutive work-groups read
-// consecutive memory).
+// in LDS, evaluates (A x)_E matrix-free from the factored operator (G in
+// closed-form 1D tensors, M_mu blocks, penalty face matrices), and in the
+// smoother applies the element's precomputed inverse diagonal block, which is
+// streamed from HBM in a lane-blocked layout (colour-major order, so that
+// consecutive work-groups read consecutive memory) and prefetched into
+// registers before the residual is evaluated.
 //
 // The operator action follows eq. (stokessystem) / eq. (viscousop) with M = I:
 //   (A x)_{u_i} = sum_k G_k^T s_ik + Et u_i + (rho/delta) u_i - G_i^T p,
@@ -14,9 +15,10 @@
 //   (A x)_p     = -sum_i G_i u_i - E p.
 // G_k^T s receives, from each face normal to k, the one-sided flux
 // h^-1 (wR s_R|lo + wL s_L|hi) (sigma-hat of eq. qstarflux): +e0 on the high
-// element R and -e1 on the low element L.
+// element R and -e1 on the low element L.  For the neighbour E+e_k only the
+// low-face trace of s is needed; it is formed with the trace-projected mass
+// rows R_k = (e0^T)_k M_mu of that neighbour.
 #include <hip/hip_runtime.h>
-#include <hip/hip_bf16.h>
 
 #include <type_traits>
 
@@ -37,62 +39,87 @@ struct Sz {
   static constexpr int NB = (D + 1) * NQ;
   // stencil slots: E, E-e_k, E+e_k, E+e_k-e_j (j != k)
   static constexpr int NSLOT = 1 + 2 * D + D * (D - 1);
-  static constexpr int NFS = 1 + D;   // elements whose s is needed: E, E+e_k
+  static constexpr int NFS = 1 + D;   // elements whose gradient is needed: E, E+e_k
 };
 
 constexpr int WG = 64;
 
-template <int M>
-__device__ __forceinline__ int ipow(int k) {
-  int v = 1;
-  for (int j = 0; j < k; ++j) v *= M;
-  return v;
+// 1D tables in the arithmetic type of the kernel
+template <typename T>
+struct TabT {
+  T K[MAXM * MAXM];
+  T e0[MAXM];
+  T e1[MAXM];
+  T P[2][MAXM * MAXM];
+};
+template <typename T>
+static TabT<T> tab_of(const Tab1D& t) {
+  TabT<T> r{};
+  for (int i = 0; i < MAXM * MAXM; ++i) {
+    r.K[i] = (T)t.K[i];
+    r.P[0][i] = (T)t.P[0][i];
+    r.P[1][i] = (T)t.P[1][i];
+  }
+  for (int i = 0; i < MAXM; ++i) {
+    r.e0[i] = (T)t.e0[i];
+    r.e1[i] = (T)t.e1[i];
+  }
+  return r;
 }
 
-// digit k of the multi-index a (axis 0 fastest)
-template <int M>
-__device__ __forceinline__ int digit(int a, int k) { return (a / ipow<M>(k)) % M; }
-// index of a with digit k removed (tangential index on a face normal to k)
-template <int M>
-__device__ __forceinline__ int tang(int a, int k) {
-  int lo = a % ipow<M>(k);
-  int hi = a / ipow<M>(k + 1);
-  return lo + ipow<M>(k) * hi;
+// tensor index helpers (axis 0 fastest); the axis is a run-time value, each
+// case compiles to constant divisors
+template <int M, int K>
+__device__ __forceinline__ int compose_c(int t, int c) {
+  constexpr int lo = Pow<M, K>::v;
+  return t % lo + lo * c + lo * M * (t / lo);
 }
-// inverse of tang: insert digit c at position k
 template <int M>
 __device__ __forceinline__ int compose(int t, int c, int k) {
-  int lo = t % ipow<M>(k);
-  int hi = t / ipow<M>(k);
-  return lo + ipow<M>(k) * c + ipow<M>(k + 1) * hi;
+  return k == 0 ? compose_c<M, 0>(t, c) : (k == 1 ? compose_c<M, 1>(t, c) : compose_c<M, 2>(t, c));
+}
+template <int M>
+__device__ __forceinline__ int stride_of(int k) {
+  return k == 0 ? 1 : (k == 1 ? M : M * M);
+}
+template <int M, int K>
+__device__ __forceinline__ int digit_c(int a) { return (a / Pow<M, K>::v) % M; }
+template <int M, int K>
+__device__ __forceinline__ int tang_c(int a) {
+  constexpr int lo = Pow<M, K>::v;
+  return a % lo + lo * (a / (lo * M));
 }
 
-// neighbour of element with coordinates c shifted by s along axis k (-1 if outside)
+// coordinates of element e on an n^D grid, n = 2^lgn
 template <int D>
-__device__ __forceinline__ int shifted(const int* c, int n, bool periodic_k, int k, int s, int* out_c) {
-  for (int j = 0; j < D; ++j) out_c[j] = c[j];
-  int v = c[k] + s;
-  if (v < 0 || v >= n) {
-    if (!periodic_k) return 0;
-    v = (v + n) % n;
-  }
-  out_c[k] = v;
-  return 1;
+__device__ __forceinline__ void coords_of(int e, int lgn, int* c) {
+  const int mask = (1 << lgn) - 1;
+#pragma unroll
+  for (int j = 0; j < D; ++j) c[j] = (e >> (j * lgn)) & mask;
 }
-
 template <int D>
-__device__ __forceinline__ int64_t elem_index(const int* c, int n) {
-  int64_t e = 0, s = 1;
-  for (int j = 0; j < D; ++j) { e += (int64_t)c[j] * s; s *= n; }
+__device__ __forceinline__ int index_of(const int* c, int lgn) {
+  int e = 0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) e |= c[j] << (j * lgn);
   return e;
 }
-
+// shift coordinate k by s; false if it leaves a non-periodic grid
+__device__ __forceinline__ bool shift1(int* c, int k, int s, int n, bool per) {
+  int v = c[k] + s;
+  if (v < 0 || v >= n) {
+    if (!per) return false;
+    v = (v + n) & (n - 1);
+  }
+  c[k] = v;
+  return true;
+}
 template <int D>
-__device__ __forceinline__ int64_t face_index(const int* c, int n, int nfk, int k, int f) {
-  int64_t e = 0, s = 1;
+__device__ __forceinline__ int face_index(const int* c, int n, int nfk, int k, int f) {
+  int e = 0, s = 1;
+#pragma unroll
   for (int j = 0; j < D; ++j) {
-    int v = (j == k) ? f : c[j];
-    e += (int64_t)v * s;
+    e += ((j == k) ? f : c[j]) * s;
     s *= (j == k) ? nfk : n;
   }
   return e;
@@ -102,84 +129,76 @@ __device__ __forceinline__ int64_t face_index(const int* c, int n, int nfk, int 
 template <typename T, int D, int P>
 struct Work {
   using S = Sz<D, P>;
-  static constexpr bool STAGE_M = (size_t)S::NFS * S::NQ * S::NQ * sizeof(T) <= 16384;
+  static constexpr bool STAGE_M = (size_t)S::NQ * S::NQ * sizeof(T) <= 8192;
   T xs[S::NSLOT][S::NB];
-  T mm[STAGE_M ? S::NFS : 1][STAGE_M ? S::NQ * S::NQ : 1];   // M_mu of E, E+e_k
-  T th[2][D][S::MT * S::MT];       // penalty matrices of E's low/high faces
-  T g[S::NFS][D * D][S::NQ];
-  T s[S::NFS][D * D][S::NQ];
-  T trx[2][D][D + 1][S::MT];       // traces of x_E: [lo/hi][axis][field][t]
-  T trn[2][D][D + 1][S::MT];       // [0]: x_{E-e_k}|hi, [1]: x_{E+e_k}|lo
-  T trs[3][D][D][S::MT];           // s_E[i][k]|lo, s_E[i][k]|hi, s_{E+e_k}[i][k]|lo (along k)
-  T flux[2][D][D + 1][S::MT];      // coefficients of e0 (lo) and e1 (hi) per axis/field
+  T mm[STAGE_M ? S::NQ * S::NQ : 1];   // M_mu of E
+  T rr[D][S::MT * S::NQ];             // R_k = (e0^T)_k M_mu of E+e_k
+  T th[2][D][S::MT * S::MT];          // penalty matrices of E's low/high faces
+  T g[S::NFS][D * D][S::NQ];          // G_k u_i at E and E+e_k (needed components)
+  T s0[D * D][S::NQ];                 // s_ik at E
+  T trx[2][D][D + 1][S::MT];          // traces of x_E: [lo/hi][axis][field][t]
+  T trn[2][D][D + 1][S::MT];          // [0]: x_{E-e_k}|hi, [1]: x_{E+e_k}|lo
+  T trs[2][D][D][S::MT];              // s_E[i][k] lo/hi along k
+  T trr[D][D][S::MT];                 // s_{E+e_k}[i][k] at its low face along k
+  T flux[2][D][D + 1][S::MT];         // coefficients of e0 (lo) and e1 (hi) per axis/field
   T res[S::NB];
-  long long slot_e[S::NSLOT];
-  long long fid[S::NFS][D][2];     // face ids of F = E, E+e_k (low/high face along each axis)
-  int lslot[S::NFS][D];            // slot of F - e_k
+  int slot_e[S::NSLOT];
+  int fid[S::NFS][D][2];              // face ids of F = E, E+e_k (low/high face along each axis)
+  int lslot[S::NFS][D];               // slot of F - e_k
   unsigned char ft[S::NFS][D][2];
   T fwl[S::NFS][D][2], fwr[S::NFS][D][2];
 };
 
 // Evaluates (A x)_E (mode 1) or b_E - (A x)_E (mode 0) into w.res.
 // Operators of the diagonally scaled system D A D when lev.dscale is set.
-// Every global load of the element (stencil x, face data, M_mu, penalty
-// matrices) is issued in two batches; all arithmetic then runs from LDS with
-// the axis index k a compile-time constant in each unrolled loop.
 template <typename T, int D, int P>
-__device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const Tab1D& tab, int64_t E,
+__device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const TabT<T>& tab, int E,
                                                  const T* __restrict__ x, const T* __restrict__ b,
                                                  int mode, Work<T, D, P>& w) {
   using S = Sz<D, P>;
   constexpr int M = S::M, NQ = S::NQ, MT = S::MT, NB = S::NB, NFS = S::NFS, NSLOT = S::NSLOT;
   using W = Work<T, D, P>;
   const int lane = threadIdx.x;
-  const int n = lev.n;
+  const int n = lev.n, lgn = lev.lgn;
   const T hinv = lev.hinv;
+  const T gam = (T)lev.gamma;
 
   int c[D];
-  {
-    int64_t r = E;
-#pragma unroll
-    for (int j = 0; j < D; ++j) { c[j] = (int)(r % n); r /= n; }
-  }
+  coords_of<D>(E, lgn, c);
   // ---- setup: stencil slots (lanes 0..NSLOT-1), face tables (lanes 16..) ----
   if (lane < NSLOT) {
-    long long e = -1;
-    int cc[D], c2[D];
+    int e = -1;
+    int cc[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) cc[j] = c[j];
     if (lane == 0) {
       e = E;
     } else if (lane < 1 + D) {
       const int k = lane - 1;
-      if (shifted<D>(c, n, lev.nf[k] == n, k, -1, cc)) e = elem_index<D>(cc, n);
+      if (shift1(cc, k, -1, n, lev.nf[k] == n)) e = index_of<D>(cc, lgn);
     } else if (lane < 1 + 2 * D) {
       const int k = lane - 1 - D;
-      if (shifted<D>(c, n, lev.nf[k] == n, k, +1, cc)) e = elem_index<D>(cc, n);
+      if (shift1(cc, k, +1, n, lev.nf[k] == n)) e = index_of<D>(cc, lgn);
     } else {
       const int u = lane - 1 - 2 * D;
       const int k = u / (D - 1), q = u % (D - 1);
       const int kk = q < k ? q : q + 1;
-      if (shifted<D>(c, n, lev.nf[k] == n, k, +1, cc) && shifted<D>(cc, n, lev.nf[kk] == n, kk, -1, c2))
-        e = elem_index<D>(c2, n);
+      if (shift1(cc, k, +1, n, lev.nf[k] == n) && shift1(cc, kk, -1, n, lev.nf[kk] == n)) e = index_of<D>(cc, lgn);
     }
     w.slot_e[lane] = e;
   } else if (lane >= 16 && lane < 16 + NFS * D * 2) {
     const int u = lane - 16;
     const int fi = u / (2 * D), k = (u / 2) % D, side = u % 2;
     int cF[D];
-    bool valid = true;
-    if (fi == 0) {
 #pragma unroll
-      for (int j = 0; j < D; ++j) cF[j] = c[j];
-    } else {
-      valid = shifted<D>(c, n, lev.nf[fi - 1] == n, fi - 1, +1, cF);
-    }
+    for (int j = 0; j < D; ++j) cF[j] = c[j];
+    const bool valid = (fi == 0) || shift1(cF, fi - 1, +1, n, lev.nf[fi - 1] == n);
     unsigned char ty = F_NONE;
     T wl = 0, wr = 0;
-    long long id = 0;
+    int id = 0;
     if (valid) {
-      const bool per = lev.nf[k] == n;
       int f = cF[k] + side;
-      if (per) f %= n;
+      if (lev.nf[k] == n) f &= n - 1;
       id = face_index<D>(cF, n, lev.nf[k], k, f);
       ty = lev.ftype[k][id];
       wl = lev.fw[k][2 * id];
@@ -198,199 +217,212 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
     }
   }
   __syncthreads();
-  // ---- phase 1: stage x of the stencil (scaled when set), M_mu, penalty matrices ----
+  // ---- phase 1: stage x of the stencil (scaled when set), M_mu, R_k, penalty matrices ----
   for (int t = lane; t < NSLOT * NB; t += WG) {
     const int sl = t / NB, i = t % NB;
-    const long long e = w.slot_e[sl];
+    const int e = w.slot_e[sl];
     T v = 0;
     if (e >= 0) {
-      v = x[e * NB + i];
+      v = x[(size_t)e * NB + i];
       if (lev.dscale) v *= lev.dscale[2 * e + (i >= D * NQ ? 1 : 0)];
     }
     w.xs[sl][i] = v;
   }
-  if constexpr (W::STAGE_M) {
-    if (lev.mmu) {
-      for (int t = lane; t < NFS * NQ * NQ; t += WG) {
-        const int fi = t / (NQ * NQ);
-        const long long e = w.slot_e[fi == 0 ? 0 : 1 + D + (fi - 1)];
-        w.mm[fi][t % (NQ * NQ)] = e >= 0 ? lev.mmu[(size_t)e * NQ * NQ + t % (NQ * NQ)] : (T)0;
-      }
+  if (lev.mmu) {
+    if constexpr (W::STAGE_M)
+      for (int t = lane; t < NQ * NQ; t += WG) w.mm[t] = lev.mmu[(size_t)E * NQ * NQ + t];
+    for (int t = lane; t < D * MT * NQ; t += WG) {
+      const int k = t / (MT * NQ);
+      const int e = w.slot_e[1 + D + k];
+      w.rr[k][t % (MT * NQ)] = e >= 0 ? lev.rmu[((size_t)e * D + k) * MT * NQ + t % (MT * NQ)] : (T)0;
     }
   }
-#pragma unroll
-  for (int k = 0; k < D; ++k)
-    for (int t = lane; t < 2 * MT * MT; t += WG) {
-      const int side = t / (MT * MT), q = t % (MT * MT);
-      w.th[side][k][q] = lev.fT[k][(size_t)w.fid[0][k][side] * MT * MT + q];
-    }
-  __syncthreads();
-  // ---- phase 2: g_F = G_k u_i at F in {E, E+e_0, .., E+e_{D-1}} ----
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    for (int t = lane; t < NFS * D * NQ; t += WG) {
-      const int a = t % NQ, i = (t / NQ) % D, fi = t / (NQ * D);
-      const int sF = (fi == 0) ? 0 : 1 + D + (fi - 1);
-      T val = 0;
-      if (w.slot_e[sF] >= 0) {
-        const unsigned char tlo = w.ft[fi][k][0], thi = w.ft[fi][k][1];
-        const T wR = w.fwr[fi][k][0], wL = w.fwl[fi][k][1];
-        const T* u = &w.xs[sF][i * NQ];
-        const T* uL = &w.xs[w.lslot[fi][k]][i * NQ];
-        const int ak = digit<M>(a, k), tt = tang<M>(a, k);
-        T vol = 0, trlo = 0, trhi = 0, trLhi = 0;
-#pragma unroll
-        for (int bb = 0; bb < M; ++bb) {
-          const T ub = u[compose<M>(tt, bb, k)];
-          vol += (T)tab.K[ak * M + bb] * ub;
-          trlo += (T)tab.e0[bb] * ub;
-          trhi += (T)tab.e1[bb] * ub;
-          trLhi += (T)tab.e1[bb] * uL[compose<M>(tt, bb, k)];
-        }
-        const T jlo = trlo - ((tlo == F_INTRA || tlo == F_INTER) ? trLhi : (T)0);
-        T acc = vol;
-        if (tlo != F_NONE) acc += wR * (T)tab.e0[ak] * jlo;
-        if (thi == F_DIR_HI) acc -= wL * (T)tab.e1[ak] * trhi;
-        val = hinv * acc;
-      }
-      w.g[fi][i * D + k][a] = val;
-    }
+  for (int t = lane; t < 2 * D * MT * MT; t += WG) {
+    const int side = t / (D * MT * MT), k = (t / (MT * MT)) % D, q = t % (MT * MT);
+    w.th[side][k][q] = lev.fT[k][(size_t)w.fid[0][k][side] * MT * MT + q];
   }
   __syncthreads();
-  // ---- phase 3: s = M_mu (g + gamma g^T); for E all (i,k), for E+e_k the (i,k) column ----
+  // ---- phase 2: gradient lines g_F = G_k u_i along axis k ----
+  // per axis k: F = E (all i), F = E+e_k (all i), F = E+e_j (j != k, component i = j)
   {
-    constexpr int NS0 = D * D * NQ;
-    const T gam = (T)lev.gamma;
-    for (int t = lane; t < NS0 + D * D * NQ; t += WG) {
-      int fi, i, k, a;
-      if (t < NS0) {
-        fi = 0;
-        a = t % NQ;
-        const int comp = t / NQ;
-        i = comp / D;
-        k = comp % D;
-      } else {
-        const int u = t - NS0;
-        a = u % NQ;
-        const int q = u / NQ;
-        fi = 1 + q / D;
-        i = q % D;
-        k = fi - 1;
-      }
+    constexpr int PER_K = (3 * D - 1) * MT;
+    for (int u = lane; u < D * PER_K; u += WG) {
+      const int k = u / PER_K;
+      const int r = u % PER_K;
+      const int t = r % MT;
+      const int q = r / MT;
+      int fi, i;
+      if (q < D) { fi = 0; i = q; }
+      else if (q < 2 * D) { fi = 1 + k; i = q - D; }
+      else { const int j0 = q - 2 * D; const int j = j0 < k ? j0 : j0 + 1; fi = 1 + j; i = j; }
       const int sF = (fi == 0) ? 0 : 1 + D + (fi - 1);
-      T val = 0;
-      const long long eF = w.slot_e[sF];
-      if (eF >= 0) {
-        const T* g1 = w.g[fi][i * D + k];
-        const T* g2 = w.g[fi][k * D + i];
+      if (w.slot_e[sF] < 0) continue;
+      const unsigned char tlo = w.ft[fi][k][0], thi = w.ft[fi][k][1];
+      const T wR = w.fwr[fi][k][0], wL = w.fwl[fi][k][1];
+      const int base = compose<M>(t, 0, k), st = stride_of<M>(k);
+      const T* uu = &w.xs[sF][i * NQ + base];
+      const T* ul = &w.xs[w.lslot[fi][k]][i * NQ + base];
+      T uv[M];
+      T trlo = 0, trhi = 0, trLhi = 0;
+#pragma unroll
+      for (int bb = 0; bb < M; ++bb) {
+        uv[bb] = uu[bb * st];
+        trlo += tab.e0[bb] * uv[bb];
+        trhi += tab.e1[bb] * uv[bb];
+        trLhi += tab.e1[bb] * ul[bb * st];
+      }
+      const T jlo = (tlo == F_NONE) ? (T)0 : wR * (trlo - ((tlo == F_INTRA || tlo == F_INTER) ? trLhi : (T)0));
+      const T jhi = (thi == F_DIR_HI) ? wL * trhi : (T)0;
+      T* go = &w.g[fi][i * D + k][base];
+#pragma unroll
+      for (int ak = 0; ak < M; ++ak) {
+        T v = tab.e0[ak] * jlo - tab.e1[ak] * jhi;
+#pragma unroll
+        for (int bb = 0; bb < M; ++bb) v += tab.K[ak * M + bb] * uv[bb];
+        go[ak * st] = hinv * v;
+      }
+    }
+  }
+  __syncthreads();
+  // ---- phase 3: s_E = M_mu (g + gamma g^T) and the low-face traces of s at E+e_k ----
+  {
+    constexpr int NPAIR = D * D;
+    constexpr int NS0 = NPAIR * NQ;
+    for (int u = lane; u < NS0 + D * D * MT; u += WG) {
+      if (u < NS0) {
+        const int a = u % NQ, pr = u / NQ, i = pr / D, k = pr % D;
+        if (lev.gamma && i > k) continue;       // symmetric: filled from (k, i)
+        const T* g1 = w.g[0][i * D + k];
+        const T* g2 = w.g[0][k * D + i];
+        T v = 0;
         if (lev.mmu) {
           const T* Mm;
-          if constexpr (W::STAGE_M) Mm = w.mm[fi];
-          else Mm = lev.mmu + (size_t)eF * NQ * NQ;
-#pragma unroll 4
-          for (int bb = 0; bb < NQ; ++bb) val += Mm[bb * NQ + a] * (g1[bb] + gam * g2[bb]);
+          if constexpr (W::STAGE_M) Mm = w.mm;
+          else Mm = lev.mmu + (size_t)E * NQ * NQ;
+#pragma unroll 8
+          for (int bb = 0; bb < NQ; ++bb) v += Mm[bb * NQ + a] * (g1[bb] + gam * g2[bb]);
         } else {
-          val = lev.mu_const * (g1[a] + gam * g2[a]);
+          v = lev.mu_const * (g1[a] + gam * g2[a]);
         }
+        w.s0[i * D + k][a] = v;
+        if (lev.gamma && i != k) w.s0[k * D + i][a] = v;
+      } else {
+        const int r = u - NS0;
+        const int t = r % MT, i = (r / MT) % D, k = r / (MT * D);
+        T v = 0;
+        if (w.slot_e[1 + D + k] >= 0) {
+          const T* g1 = w.g[1 + k][i * D + k];
+          const T* g2 = w.g[1 + k][k * D + i];
+          if (lev.mmu) {
+            const T* R = &w.rr[k][t * NQ];
+#pragma unroll 8
+            for (int bb = 0; bb < NQ; ++bb) v += R[bb] * (g1[bb] + gam * g2[bb]);
+          } else {
+            const int base = compose<M>(t, 0, k), st = stride_of<M>(k);
+#pragma unroll
+            for (int cc = 0; cc < M; ++cc) v += tab.e0[cc] * (g1[base + cc * st] + gam * g2[base + cc * st]);
+            v *= lev.mu_const;
+          }
+        }
+        w.trr[k][i][t] = v;
       }
-      w.s[fi][i * D + k][a] = val;
     }
   }
   __syncthreads();
-  // ---- phase 4: traces ----
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
+  // ---- phase 4: traces along each axis ----
+  {
     constexpr int NX = 2 * (D + 1) * MT;   // x_E lo/hi
-    constexpr int NN = 2 * (D + 1) * MT;   // neighbour traces
-    constexpr int NT = 3 * D * MT;         // s traces
-    for (int t = lane; t < NX + NN + NT; t += WG) {
-      if (t < NX) {
-        const int tt = t % MT, f = (t / MT) % (D + 1), side = t / (MT * (D + 1));
-        const T* u = &w.xs[0][f * NQ];
+    constexpr int NN = 2 * (D + 1) * MT;   // x_{E-e_k}|hi, x_{E+e_k}|lo
+    constexpr int NT = 2 * D * MT;         // s_E[i][k] lo/hi
+    constexpr int PER_K = NX + NN + NT;
+    for (int u = lane; u < D * PER_K; u += WG) {
+      const int k = u / PER_K, r = u % PER_K;
+      const int base_mt = r % MT;
+      const int base = compose<M>(base_mt, 0, k), st = stride_of<M>(k);
+      if (r < NX) {
+        const int f = (r / MT) % (D + 1), side = r / (MT * (D + 1));
+        const T* uu = &w.xs[0][f * NQ + base];
         T v = 0;
 #pragma unroll
-        for (int bb = 0; bb < M; ++bb) v += (T)(side ? tab.e1[bb] : tab.e0[bb]) * u[compose<M>(tt, bb, k)];
-        w.trx[side][k][f][tt] = v;
-      } else if (t < NX + NN) {
-        const int r = t - NX;
-        const int tt = r % MT, f = (r / MT) % (D + 1), side = r / (MT * (D + 1));
-        const T* u = &w.xs[side ? 1 + D + k : 1 + k][f * NQ];
+        for (int bb = 0; bb < M; ++bb) v += (side ? tab.e1[bb] : tab.e0[bb]) * uu[bb * st];
+        w.trx[side][k][f][base_mt] = v;
+      } else if (r < NX + NN) {
+        const int r2 = r - NX;
+        const int f = (r2 / MT) % (D + 1), side = r2 / (MT * (D + 1));
+        const T* uu = &w.xs[side ? 1 + D + k : 1 + k][f * NQ + base];
         T v = 0;
 #pragma unroll
-        for (int bb = 0; bb < M; ++bb) v += (T)(side ? tab.e0[bb] : tab.e1[bb]) * u[compose<M>(tt, bb, k)];
-        w.trn[side][k][f][tt] = v;
+        for (int bb = 0; bb < M; ++bb) v += (side ? tab.e0[bb] : tab.e1[bb]) * uu[bb * st];
+        w.trn[side][k][f][base_mt] = v;
       } else {
-        const int r = t - NX - NN;
-        const int tt = r % MT, i = (r / MT) % D, which = r / (MT * D);
-        const T* sv = (which == 2) ? w.s[1 + k][i * D + k] : w.s[0][i * D + k];
+        const int r2 = r - NX - NN;
+        const int i = (r2 / MT) % D, side = r2 / (MT * D);
+        const T* sv = &w.s0[i * D + k][base];
         T v = 0;
 #pragma unroll
-        for (int bb = 0; bb < M; ++bb) v += (T)(which == 1 ? tab.e1[bb] : tab.e0[bb]) * sv[compose<M>(tt, bb, k)];
-        w.trs[which][k][i][tt] = v;
+        for (int bb = 0; bb < M; ++bb) v += (side ? tab.e1[bb] : tab.e0[bb]) * sv[bb * st];
+        w.trs[side][k][i][base_mt] = v;
       }
     }
   }
   __syncthreads();
   // ---- phase 5: face fluxes ----
+  for (int u = lane; u < D * 2 * (D + 1) * MT; u += WG) {
+    const int tt = u % MT, f = (u / MT) % (D + 1), side = (u / (MT * (D + 1))) % 2, k = u / (2 * MT * (D + 1));
+    const unsigned char ty = w.ft[0][k][side];
+    const T wL = w.fwl[0][k][side], wR = w.fwr[0][k][side];
+    const T* Th = &w.th[side][k][tt * MT];
+    T v = 0;
+    if (f < D) {
+      const int i = f;
+      if (side == 0) {
+        // E is the high element R of its low face
+        if (ty != F_NONE) v += wR * w.trs[0][k][i][tt];
+        if (ty == F_DIR_LO) {
+          T acc = 0;
 #pragma unroll
-  for (int k = 0; k < D; ++k) {
-    for (int t = lane; t < 2 * (D + 1) * MT; t += WG) {
-      const int tt = t % MT, f = (t / MT) % (D + 1), side = t / (MT * (D + 1));
-      const unsigned char ty = w.ft[0][k][side];
-      const T wL = w.fwl[0][k][side], wR = w.fwr[0][k][side];
-      const T* Th = &w.th[side][k][tt * MT];
-      T v = 0;
-      if (f < D) {
-        const int i = f;
-        if (side == 0) {
-          // E is the high element R of its low face
-          if (ty != F_NONE) v += wR * w.trs[0][k][i][tt];
-          if (ty == F_DIR_LO) {
-            T acc = 0;
+          for (int q = 0; q < MT; ++q) acc += Th[q] * w.trx[0][k][i][q];
+          v += acc;
+        } else if (ty == F_INTER) {
+          T acc = 0;
 #pragma unroll
-            for (int q = 0; q < MT; ++q) acc += Th[q] * w.trx[0][k][i][q];
-            v += acc;
-          } else if (ty == F_INTER) {
-            T acc = 0;
-#pragma unroll
-            for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trn[0][k][i][q] - w.trx[0][k][i][q]);
-            v -= acc;
-          }
-          if (k == i && ty != F_NONE) v -= wR * w.trx[0][k][D][tt];
-        } else {
-          // E is the low element L of its high face
-          const T sR = (ty == F_INTRA || ty == F_INTER) ? w.trs[2][k][i][tt] : (T)0;
-          v -= wR * sR + wL * w.trs[1][k][i][tt];
-          if (ty == F_DIR_HI) {
-            T acc = 0;
-#pragma unroll
-            for (int q = 0; q < MT; ++q) acc += Th[q] * w.trx[1][k][i][q];
-            v += acc;
-          } else if (ty == F_INTER) {
-            T acc = 0;
-#pragma unroll
-            for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trx[1][k][i][q] - w.trn[1][k][i][q]);
-            v += acc;
-          }
-          if (k == i) {
-            const T pR = (ty == F_INTRA || ty == F_INTER) ? w.trn[1][k][D][tt] : (T)0;
-            v += wR * pR + wL * w.trx[1][k][D][tt];
-          }
+          for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trn[0][k][i][q] - w.trx[0][k][i][q]);
+          v -= acc;
         }
-      } else if (ty == F_INTRA) {
-        T acc = 0;
-        if (side == 0) {
+        if (k == i && ty != F_NONE) v -= wR * w.trx[0][k][D][tt];
+      } else {
+        // E is the low element L of its high face
+        const T sR = (ty == F_INTRA || ty == F_INTER) ? w.trr[k][i][tt] : (T)0;
+        v -= wR * sR + wL * w.trs[1][k][i][tt];
+        if (ty == F_DIR_HI) {
+          T acc = 0;
 #pragma unroll
-          for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trn[0][k][D][q] - w.trx[0][k][D][q]);
-          v = acc;
-        } else {
+          for (int q = 0; q < MT; ++q) acc += Th[q] * w.trx[1][k][i][q];
+          v += acc;
+        } else if (ty == F_INTER) {
+          T acc = 0;
 #pragma unroll
-          for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trx[1][k][D][q] - w.trn[1][k][D][q]);
-          v = -acc;
+          for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trx[1][k][i][q] - w.trn[1][k][i][q]);
+          v += acc;
+        }
+        if (k == i) {
+          const T pR = (ty == F_INTRA || ty == F_INTER) ? w.trn[1][k][D][tt] : (T)0;
+          v += wR * pR + wL * w.trx[1][k][D][tt];
         }
       }
-      w.flux[side][k][f][tt] = hinv * v;
+    } else if (ty == F_INTRA) {
+      T acc = 0;
+      if (side == 0) {
+#pragma unroll
+        for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trn[0][k][D][q] - w.trx[0][k][D][q]);
+        v = acc;
+      } else {
+#pragma unroll
+        for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trx[1][k][D][q] - w.trn[1][k][D][q]);
+        v = -acc;
+      }
     }
+    w.flux[side][k][f][tt] = hinv * v;
   }
   __syncthreads();
   // ---- phase 6: assemble (A x)_E and the residual ----
@@ -401,18 +433,19 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
       const int i = f;
 #pragma unroll
       for (int k = 0; k < D; ++k) {
-        const int ak = digit<M>(a, k), tt = tang<M>(a, k);
-        const T* sv = w.s[0][i * D + k];
+        const int ak = k == 0 ? digit_c<M, 0>(a) : (k == 1 ? digit_c<M, 1>(a) : digit_c<M, 2>(a));
+        const int tt = k == 0 ? tang_c<M, 0>(a) : (k == 1 ? tang_c<M, 1>(a) : tang_c<M, 2>(a));
+        const int base = compose<M>(tt, 0, k), st = stride_of<M>(k);
+        const T* sv = &w.s0[i * D + k][base];
         T vol = 0;
 #pragma unroll
-        for (int bb = 0; bb < M; ++bb) vol += (T)tab.K[bb * M + ak] * sv[compose<M>(tt, bb, k)];
-        acc += hinv * vol;
-        acc += (T)tab.e0[ak] * w.flux[0][k][i][tt] + (T)tab.e1[ak] * w.flux[1][k][i][tt];
+        for (int bb = 0; bb < M; ++bb) vol += tab.K[bb * M + ak] * sv[bb * st];
+        acc += hinv * vol + tab.e0[ak] * w.flux[0][k][i][tt] + tab.e1[ak] * w.flux[1][k][i][tt];
         if (k == i) {
-          const T* pv = &w.xs[0][D * NQ];
+          const T* pv = &w.xs[0][D * NQ + base];
           T pvol = 0;
 #pragma unroll
-          for (int bb = 0; bb < M; ++bb) pvol += (T)tab.K[bb * M + ak] * pv[compose<M>(tt, bb, k)];
+          for (int bb = 0; bb < M; ++bb) pvol += tab.K[bb * M + ak] * pv[bb * st];
           acc -= hinv * pvol;
         }
       }
@@ -422,12 +455,13 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
       for (int i = 0; i < D; ++i) acc -= w.g[0][i * D + i][a];
 #pragma unroll
       for (int k = 0; k < D; ++k) {
-        const int ak = digit<M>(a, k), tt = tang<M>(a, k);
-        acc += (T)tab.e0[ak] * w.flux[0][k][D][tt] + (T)tab.e1[ak] * w.flux[1][k][D][tt];
+        const int ak = k == 0 ? digit_c<M, 0>(a) : (k == 1 ? digit_c<M, 1>(a) : digit_c<M, 2>(a));
+        const int tt = k == 0 ? tang_c<M, 0>(a) : (k == 1 ? tang_c<M, 1>(a) : tang_c<M, 2>(a));
+        acc += tab.e0[ak] * w.flux[0][k][D][tt] + tab.e1[ak] * w.flux[1][k][D][tt];
       }
     }
     if (lev.dscale) acc *= lev.dscale[2 * E + (f == D ? 1 : 0)];
-    w.res[t] = (mode == 0) ? b[E * NB + t] - acc : acc;
+    w.res[t] = (mode == 0) ? b[(size_t)E * NB + t] - acc : acc;
   }
   __syncthreads();
 }
@@ -455,7 +489,7 @@ __device__ __forceinline__ T inv_entry(const u32x4& raw, int v) {
 // into registers before the residual is evaluated.
 // ---------------------------------------------------------------------------
 template <typename T, typename TI, int D, int P>
-__global__ __launch_bounds__(WG) void k_smooth_colour(DevLevel<T> lev, Tab1D tab, const int* __restrict__ elems,
+__global__ __launch_bounds__(WG) void k_smooth_colour(DevLevel<T> lev, TabT<T> tab, const int* __restrict__ elems,
                                                       const TI* __restrict__ inv, const T* __restrict__ b,
                                                       T* __restrict__ x) {
   using S = Sz<D, P>;
@@ -466,8 +500,8 @@ __global__ __launch_bounds__(WG) void k_smooth_colour(DevLevel<T> lev, Tab1D tab
   __shared__ Work<T, D, P> w;
   __shared__ T part[LY.S][LY.NBP];
   const int lane = threadIdx.x;
-  const int64_t idx = blockIdx.x;
-  const int64_t E = elems[idx];
+  const int idx = blockIdx.x;
+  const int E = elems[idx];
   const u32x4* Ai = reinterpret_cast<const u32x4*>(inv + (size_t)idx * NB * LY.NBP);
   u32x4 pre[PF];
   if (lane < RGS) {
@@ -495,48 +529,46 @@ __global__ __launch_bounds__(WG) void k_smooth_colour(DevLevel<T> lev, Tab1D tab
     T acc = 0;
 #pragma unroll
     for (int s = 0; s < LY.S; ++s) acc += part[s][row];
-    x[E * NB + row] += acc;
+    x[(size_t)E * NB + row] += acc;
   }
 }
 
 template <typename T, int D, int P>
-__global__ __launch_bounds__(WG) void k_residual(DevLevel<T> lev, Tab1D tab, const T* __restrict__ b,
+__global__ __launch_bounds__(WG) void k_residual(DevLevel<T> lev, TabT<T> tab, const T* __restrict__ b,
                                                  const T* __restrict__ x, T* __restrict__ out, int mode) {
   using S = Sz<D, P>;
   __shared__ Work<T, D, P> w;
-  const int64_t E = blockIdx.x;
+  const int E = blockIdx.x;
   element_operator<T, D, P>(lev, tab, E, x, b, mode, w);
-  for (int t = threadIdx.x; t < S::NB; t += WG) out[E * S::NB + t] = w.res[t];
+  for (int t = threadIdx.x; t < S::NB; t += WG) out[(size_t)E * S::NB + t] = w.res[t];
 }
 
 // product of 1D injection entries: (P_o)[af][ac] for child offset bits o
-template <int D, int M>
-__device__ __forceinline__ double pfull(const Tab1D& tab, int o, int af, int ac) {
-  double v = 1.0;
+template <typename T, int D, int M>
+__device__ __forceinline__ T pfull(const TabT<T>& tab, int o, int af, int ac) {
+  T v = 1;
+  int fa = af, ca = ac;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
-    const int fk = (af / ipow<M>(k)) % M, ck = (ac / ipow<M>(k)) % M;
-    v *= tab.P[(o >> k) & 1][fk * M + ck];
+    v *= tab.P[(o >> k) & 1][(fa % M) * M + (ca % M)];
+    fa /= M;
+    ca /= M;
   }
   return v;
 }
 
 // r_c = I^T (b - A x): one work-group per coarse element, looping over children.
 template <typename T, int D, int P>
-__global__ __launch_bounds__(WG) void k_residual_restrict(DevLevel<T> lev, Tab1D tab, const T* __restrict__ b,
+__global__ __launch_bounds__(WG) void k_residual_restrict(DevLevel<T> lev, TabT<T> tab, const T* __restrict__ b,
                                                           const T* __restrict__ x, T* __restrict__ rc) {
   using S = Sz<D, P>;
   constexpr int M = S::M, NQ = S::NQ, NB = S::NB;
   constexpr int PER = (NB + WG - 1) / WG;
   __shared__ Work<T, D, P> w;
-  const int nc = lev.n / 2;
-  const int64_t C = blockIdx.x;
+  const int lgc = lev.lgn - 1;
+  const int C = blockIdx.x;
   int cc[D];
-  {
-    int64_t r = C;
-#pragma unroll
-    for (int j = 0; j < D; ++j) { cc[j] = (int)(r % nc); r /= nc; }
-  }
+  coords_of<D>(C, lgc, cc);
   T acc[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) acc[q] = 0;
@@ -544,7 +576,7 @@ __global__ __launch_bounds__(WG) void k_residual_restrict(DevLevel<T> lev, Tab1D
     int cf[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) cf[j] = 2 * cc[j] + ((o >> j) & 1);
-    const int64_t E = elem_index<D>(cf, lev.n);
+    const int E = index_of<D>(cf, lev.lgn);
     element_operator<T, D, P>(lev, tab, E, x, b, 0, w);
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -552,7 +584,7 @@ __global__ __launch_bounds__(WG) void k_residual_restrict(DevLevel<T> lev, Tab1D
       if (t < NB) {
         const int f = t / NQ, ac = t % NQ;
         T s = 0;
-        for (int af = 0; af < NQ; ++af) s += (T)pfull<D, M>(tab, o, af, ac) * w.res[f * NQ + af];
+        for (int af = 0; af < NQ; ++af) s += pfull<T, D, M>(tab, o, af, ac) * w.res[f * NQ + af];
         acc[q] += s;
       }
     }
@@ -561,13 +593,13 @@ __global__ __launch_bounds__(WG) void k_residual_restrict(DevLevel<T> lev, Tab1D
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int t = threadIdx.x + q * WG;
-    if (t < NB) rc[C * NB + t] = acc[q];
+    if (t < NB) rc[(size_t)C * NB + t] = acc[q];
   }
 }
 
 // x += I x_c: one thread per fine coefficient.
 template <typename T, int D, int P>
-__global__ void k_prolong_add(int n, Tab1D tab, const T* __restrict__ xc, T* __restrict__ x, int64_t total) {
+__global__ void k_prolong_add(int n, TabT<T> tab, const T* __restrict__ xc, T* __restrict__ x, int64_t total) {
   using S = Sz<D, P>;
   constexpr int M = S::M, NQ = S::NQ, NB = S::NB;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -575,17 +607,15 @@ __global__ void k_prolong_add(int n, Tab1D tab, const T* __restrict__ xc, T* __r
   int64_t E = t / NB;
   int r = (int)(t % NB);
   int f = r / NQ, af = r % NQ;
+  const int lgn = 31 - __builtin_clz(n);
   int c[D], o = 0;
-  {
-    int64_t rr = E;
-    for (int j = 0; j < D; ++j) { c[j] = (int)(rr % n); rr /= n; }
-  }
+  coords_of<D>((int)E, lgn, c);
   int pc[D];
-  for (int j = 0; j < D; ++j) { pc[j] = c[j] / 2; o |= (c[j] & 1) << j; }
-  int64_t C = elem_index<D>(pc, n / 2);
+  for (int j = 0; j < D; ++j) { pc[j] = c[j] >> 1; o |= (c[j] & 1) << j; }
+  const int64_t C = index_of<D>(pc, lgn - 1);
   const T* xv = xc + C * NB + f * NQ;
   T s = 0;
-  for (int ac = 0; ac < NQ; ++ac) s += (T)pfull<D, M>(tab, o, af, ac) * xv[ac];
+  for (int ac = 0; ac < NQ; ++ac) s += pfull<T, D, M>(tab, o, af, ac) * xv[ac];
   x[t] += s;
 }
 
@@ -709,17 +739,18 @@ int launch_smooth_colour(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D
                          int64_t nelems, const void* inv, int inv_kind, const T* b, T* x) {
   if (nelems <= 0) return 0;
   hipStream_t st = (hipStream_t)c.stream;
+  const TabT<T> tt = tab_of<T>(tab);
   if constexpr (sizeof(T) == 8) {
     if (inv_kind != 0) return 2;
     if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_smooth_colour<T, double, D_, P_>), dim3((unsigned)nelems), dim3(WG), 0, st,
-                                                  lev, tab, elems, (const double*)inv, b, x); })) return 2;
+                                                  lev, tt, elems, (const double*)inv, b, x); })) return 2;
   } else {
     if (inv_kind == 1) {
       if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_smooth_colour<T, float, D_, P_>), dim3((unsigned)nelems), dim3(WG), 0, st,
-                                                    lev, tab, elems, (const float*)inv, b, x); })) return 2;
+                                                    lev, tt, elems, (const float*)inv, b, x); })) return 2;
     } else if (inv_kind == 2) {
       if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_smooth_colour<T, uint16_t, D_, P_>), dim3((unsigned)nelems), dim3(WG), 0, st,
-                                                    lev, tab, elems, (const uint16_t*)inv, b, x); })) return 2;
+                                                    lev, tt, elems, (const uint16_t*)inv, b, x); })) return 2;
     } else {
       return 2;
     }
@@ -733,8 +764,9 @@ int launch_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab
   int64_t NE = 1;
   for (int j = 0; j < c.dim; ++j) NE *= lev.n;
   hipStream_t st = (hipStream_t)c.stream;
+  const TabT<T> tt = tab_of<T>(tab);
   if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_residual<T, D_, P_>), dim3((unsigned)NE), dim3(WG), 0, st,
-                                                lev, tab, b, x, out, mode); })) return 2;
+                                                lev, tt, b, x, out, mode); })) return 2;
   return hip_ok();
 }
 
@@ -744,8 +776,9 @@ int launch_residual_restrict(const LaunchCfg& c, const DevLevel<T>& lev, const T
   int64_t NC = 1;
   for (int j = 0; j < c.dim; ++j) NC *= lev.n / 2;
   hipStream_t st = (hipStream_t)c.stream;
+  const TabT<T> tt = tab_of<T>(tab);
   if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_residual_restrict<T, D_, P_>), dim3((unsigned)NC), dim3(WG), 0, st,
-                                                lev, tab, b, x, rc); })) return 2;
+                                                lev, tt, b, x, rc); })) return 2;
   return hip_ok();
 }
 
@@ -757,8 +790,9 @@ int launch_prolong_add(const LaunchCfg& c, int n_fine, const Tab1D& tab, const T
   for (int j = 0; j < c.dim; ++j) nb *= (c.p + 1);
   int64_t total = NE * nb;
   hipStream_t st = (hipStream_t)c.stream;
+  const TabT<T> tt = tab_of<T>(tab);
   if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_prolong_add<T, D_, P_>), dim3(grid1(total, 256)), dim3(256), 0, st,
-                                                n_fine, tab, xc, x, total); })) return 2;
+                                                n_fine, tt, xc, x, total); })) return 2;
   return hip_ok();
 }
 

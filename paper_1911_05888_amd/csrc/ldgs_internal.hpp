@@ -70,12 +70,14 @@ constexpr InvLayout inv_layout(int nb, int bytes) {
 template <typename T>
 struct DevLevel {
   int n;                 // elements per axis
+  int lgn;               // log2(n)
   int nf[3];             // faces per grid line along each axis (n or n+1)
   T hinv;                // 1 / h
   const unsigned char* ftype[3];   // [faces]
   const T* fw[3];                  // [faces][2] = (wL, wR)
   const T* fT[3];                  // [faces][MT*MT] penalty matrices
   const T* mmu;                    // [NE][NQ*NQ] or nullptr (then mu_const)
+  const T* rmu;                    // [NE][D][MT*NQ] low-face trace rows (e0^T)_k M_mu, with mmu
   T mu_const;
   T rho_delta;                     // rho / delta (0: steady)
   const T* dscale;                 // [NE][2] (alpha, beta) or nullptr
