@@ -186,18 +186,87 @@ ldgs_status ldgs_vcycle(ldgs_ctx* ctx, const double* b_dev, double* x_dev);
 /* Solve A x = b to ||b - A x|| <= tol ||b|| from the x given (use zeros).
  * b is first projected onto range(A) (its components along the trivial
  * kernel are removed, in place).  maxit bounds the outer iterations;
- * fgmres_m is the restart length; use_learned applies the learned
- * correction after each cycle's post-smoothing (requires ldgs_set_learned).
- * info may be NULL.  Synchronises. */
+ * fgmres_m is the restart length.  use_learned (outer = LDGS_IR only; needs
+ * ldgs_set_learned) adds the learned correction of r - A z to each V-cycle
+ * result z, in the cycle's precision, under a guard: the first two
+ * iterations are plain and give rho_plain = (||r_2|| / ||r_0||)^(1/2); the
+ * correction is switched off for the rest of the solve when an iteration's
+ * reduction c_k = ||r_k|| / ||r_{k-1}|| exceeds 1, or exceeds 1.1 rho_plain
+ * twice in a row, and that iteration is redone without it
+ * (info->fallback_events counts this).  info may be NULL.  Synchronises. */
 ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b_dev, double* x_dev, double tol, int maxit,
                        int outer, int fgmres_m, int use_learned, ldgs_info* info);
 
 /* Switch the precision used by ldgs_vcycle / ldgs_solve among those built. */
 ldgs_status ldgs_set_vprec(ldgs_ctx* ctx, int vprec);
 
-/* Learned correction weights (device blob, copied).  Returns
- * LDGS_E_UNSUPPORTED in this version. */
-ldgs_status ldgs_set_learned(ldgs_ctx* ctx, const void* weights_dev, int64_t nbytes);
+/* ---- Learned post-smoothing correction ---------------------------------
+ * Not part of the paper's method; an optional extra step after the V-cycle.
+ * Per finest element E a small network maps the 3^d patch of elements around
+ * E (offsets in {-1,0,1}^d, axis 0 fastest; zero beyond a non-periodic wall,
+ * wrapped on periodic axes) to a correction of x_E:
+ *   z_F  = n_b residual coefficients of F divided by the global RMS s_f of
+ *          their field (velocity or pressure), then log10 of F's mean
+ *          viscosity: n_b + 1 channels per patch element;
+ *   h1   = relu(W1 z + b1), h2 = relu(W2 h1 + b2), y = W3 h2 + b3;
+ *   dx_E = y * s_f * c_f per coefficient, f the coefficient's field.
+ * Hidden width H = 16.  Inference and training run in bfloat16 (inputs,
+ * weights, hidden activations; round to nearest even) on matrix cores with
+ * FP32 accumulation; biases are FP32.
+ *
+ * Flat parameter layout (FP32, host): W1 [H][3^d][n_b+1] | b1 [H] |
+ * W2 [H][H] | b2 [H] | W3 [n_b][H] | b3 [n_b];
+ * nparams = H 3^d (n_b+1) + 2H + H^2 + n_b H + n_b. */
+typedef struct {
+  int dim, degree, hidden;  /* must match the context; hidden = 16 */
+  const float* params;      /* host, flat layout above (copied) */
+  int64_t nparams;
+  double c_vel, c_pre;      /* output scales c_f (RMS of e / s_f on training data) */
+} ldgs_net;
+
+/* Load (net non-NULL) or remove (NULL) the correction network. */
+ldgs_status ldgs_set_learned(ldgs_ctx* ctx, const ldgs_net* net);
+
+/* dx = the network's correction for residual r (finest level, unscaled,
+ * FP64 device vectors of N entries).  Asynchronous on the context stream.
+ * LDGS_E_ARG without a loaded network. */
+ldgs_status ldgs_learned_correction(ldgs_ctx* ctx, const double* r_dev, double* dx_dev);
+
+/* Training pairs from plain V-cycles (the context's precision) on
+ * A x = A x*, from x = 0: after cycle k (k < ncycles) with iterate x_k,
+ *   r = b - A x_k and e = x* - x_k with the trivial kernel removed,
+ * written as crops.  Crop c of cycle k has origin origins[(k*ncrops + c)*d + j]
+ * (host ints; 0 <= origin_j, and origin_j + C <= n on non-periodic axes):
+ *   feat [k][c][(C+2)^d][CHP] bf16: channels of the crop and a one-element
+ *        halo (layout of the network input, CHP = roundup(n_b+1, 8), unused
+ *        channels zero);
+ *   targ [k][c][C^d][n_b] bf16: e / s_f on the crop.
+ * C is a power of two with 4 <= C <= n.  stats_host (may be NULL) receives
+ * per cycle (s_vel, s_pre, RMS(e_vel)/s_vel, RMS(e_pre)/s_pre).  x* is a
+ * device FP64 vector; feat and targ device arrays.  Synchronises. */
+ldgs_status ldgs_learned_collect(ldgs_ctx* ctx, const double* xstar_dev, int ncycles, int crop, int ncrops,
+                                 const int* origins, uint16_t* feat_dev, uint16_t* targ_dev,
+                                 double* stats_host);
+
+/* Training on crops written by ldgs_learned_collect: Adam (Kingma and Ba) on
+ * FP32 master weights; forward and backward in bfloat16 with FP32
+ * accumulation; loss = mean over the batch of (y - targ / c_f)^2. */
+typedef struct {
+  void* hip_stream;         /* NULL = default stream */
+  int dim, degree, hidden, crop, ncrops;
+  const uint16_t* feat;     /* device, [ncrops][(C+2)^d][CHP] */
+  const uint16_t* targ;     /* device, [ncrops][C^d][n_b] */
+  double c_vel, c_pre;
+  int batch, steps;
+  const int* order;         /* host [steps][batch] crop indices */
+  float lr, beta1, beta2, eps;
+} ldgs_train_args;
+
+/* params: in/out, flat layout (host FP32).  loss_out: host [steps], the
+ * batch loss before each update (may be NULL).  grad0_out: host, flat
+ * layout, the gradient of the first step (may be NULL).  Synchronises.
+ * Errors are reported through ldgs_last_error(NULL). */
+ldgs_status ldgs_learned_train(const ldgs_train_args* args, float* params, double* loss_out, float* grad0_out);
 
 /* Remove from v its components along the trivial kernel (constant pressure,
  * and constant velocity for periodic steady problems), in place. */

@@ -14,6 +14,7 @@
 
 #include "build.hpp"
 #include "host.hpp"
+#include "learned_internal.hpp"
 
 namespace ldgs {
 void assemble_rhs_host(const ldgs_problem& P, const Geometry& g, const Basis& B, const Level& L,
@@ -89,6 +90,19 @@ struct ldgs_ctx {
   float *w_b32 = nullptr, *w_x32 = nullptr;
   double* d_dscale0 = nullptr;      // finest-level scaling (double) for user <-> scaled
   std::vector<double*> kry;         // FGMRES basis storage
+  // learned correction
+  bool net_loaded = false;
+  NetShape ns{};
+  float* d_net = nullptr;           // padded FP32 parameters
+  uint16_t* d_netbf = nullptr;      // BF16 copy
+  double c_net[2] = {1.0, 1.0};
+  float* d_logmu = nullptr;         // finest-level log10 of the element mean of mu
+  double* d_sums = nullptr;         // [2] sums of squares (velocity, pressure)
+  double *w_xold = nullptr, *w_zl = nullptr, *w_r64b = nullptr;
+  float* w_r32 = nullptr;
+  double *w_cb = nullptr, *w_cx = nullptr, *w_ce = nullptr;
+  int* d_orig = nullptr;
+  int64_t d_orig_cap = 0;
   // optional timing of the finest-level smoother launches (HIP events on the stream)
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
@@ -554,6 +568,111 @@ void project_kernel(ldgs_ctx* c, double* v) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// learned correction
+// ---------------------------------------------------------------------------
+int periodic_mask(const ldgs_problem& P) {
+  int m = 0;
+  for (int k = 0; k < P.dim; ++k)
+    if (P.bc[k] == LDGS_PERIODIC) m |= 1 << k;
+  return m;
+}
+int log2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// flat host layout <-> padded device layout
+void net_pack(const NetShape& s, const float* flat, std::vector<float>& pad) {
+  const int H = NET_H;
+  pad.assign(s.total, 0.f);
+  const float* q = flat;
+  for (int h = 0; h < H; ++h)
+    for (int o = 0; o < s.noff; ++o)
+      for (int c = 0; c < s.ch; ++c) pad[s.oW1 + (int64_t)h * s.k1p + o * s.chp + c] = *q++;
+  for (int h = 0; h < H; ++h) pad[s.ob1 + h] = *q++;
+  for (int i = 0; i < H * H; ++i) pad[s.oW2 + i] = *q++;
+  for (int h = 0; h < H; ++h) pad[s.ob2 + h] = *q++;
+  for (int o = 0; o < s.nb; ++o)
+    for (int h = 0; h < H; ++h) pad[s.oW3 + (int64_t)o * H + h] = *q++;
+  for (int o = 0; o < s.nb; ++o) pad[s.ob3 + o] = *q++;
+}
+void net_unpack(const NetShape& s, const std::vector<float>& pad, float* flat) {
+  const int H = NET_H;
+  float* q = flat;
+  for (int h = 0; h < H; ++h)
+    for (int o = 0; o < s.noff; ++o)
+      for (int c = 0; c < s.ch; ++c) *q++ = pad[s.oW1 + (int64_t)h * s.k1p + o * s.chp + c];
+  for (int h = 0; h < H; ++h) *q++ = pad[s.ob1 + h];
+  for (int i = 0; i < H * H; ++i) *q++ = pad[s.oW2 + i];
+  for (int h = 0; h < H; ++h) *q++ = pad[s.ob2 + h];
+  for (int o = 0; o < s.nb; ++o)
+    for (int h = 0; h < H; ++h) *q++ = pad[s.oW3 + (int64_t)o * H + h];
+  for (int o = 0; o < s.nb; ++o) *q++ = pad[s.ob3 + o];
+}
+
+// per-context buffers of the correction (allocated once)
+void learned_buffers(ldgs_ctx* c) {
+  if (c->d_logmu) return;
+  const Level& L = c->levels[0];
+  const int nq = c->g.nq;
+  std::vector<float> lm(L.NE);
+  for (int64_t e = 0; e < L.NE; ++e)
+    lm[e] = (float)std::log10(L.mu_is_const ? L.mu_c : L.mmu[(size_t)e * nq * nq]);
+  c->d_logmu = dalloc<float>(c, L.NE);
+  HIPCHK(hipMemcpy(c->d_logmu, lm.data(), lm.size() * sizeof(float), hipMemcpyHostToDevice));
+  c->d_sums = dalloc<double>(c, 2);
+  const int64_t N = c->ndof();
+  c->w_xold = dalloc<double>(c, N);
+  c->w_zl = dalloc<double>(c, N);
+}
+
+NetDev net_dev(ldgs_ctx* c) { return NetDev{c->d_net, c->d_netbf}; }
+
+constexpr int SUMSQ_BLK = 512;
+
+// out = base + N(r') with r' = (b - A x) of the V-cycle's finest level as it
+// stands after the last cycle (scaled variables; unscaled inside the kernel)
+void learned_after_cycle(ldgs_ctx* c, int vp, const double* base, double* out) {
+  LaunchCfg cfg{c->g.d, c->g.p, c->stream};
+  const Level& L = c->levels[0];
+  const int64_t NE = L.NE;
+  const int nb = c->g.nb, nvel = c->g.d * c->g.nq;
+  const double* ds = dscale0(c);
+  const double cu = (double)NE * nvel, cp = (double)NE * (nb - nvel);
+  if (vp == LDGS_V_FP64) {
+    if (!c->w_r64b) c->w_r64b = dalloc<double>(c, NE * nb);
+    LCHK(launch_residual<double>(cfg, c->s64.lv[0].view, c->tab, c->w_b, c->w_x, c->w_r64b, 0));
+    LCHK(launch_field_sumsq<double>(c->stream, NE, nb, nvel, c->w_r64b, ds, c->w_part, SUMSQ_BLK, c->d_sums));
+    LCHK(launch_net_apply<double>(c->stream, c->g.d, c->g.p, L.n, log2i(L.n), periodic_mask(c->P), c->w_r64b, ds,
+                                  c->d_logmu, c->d_sums, cu, cp, c->c_net[0], c->c_net[1], net_dev(c), base, out));
+  } else {
+    PrecStore<float>& S = (vp == LDGS_V_FP32) ? c->s32 : c->s16;
+    if (!c->w_r32) c->w_r32 = dalloc<float>(c, NE * nb);
+    LCHK(launch_residual<float>(cfg, S.lv[0].view, c->tab, c->w_b32, c->w_x32, c->w_r32, 0));
+    LCHK(launch_field_sumsq<float>(c->stream, NE, nb, nvel, c->w_r32, ds, c->w_part, SUMSQ_BLK, c->d_sums));
+    LCHK(launch_net_apply<float>(c->stream, c->g.d, c->g.p, L.n, log2i(L.n), periodic_mask(c->P), c->w_r32, ds,
+                                 c->d_logmu, c->d_sums, cu, cp, c->c_net[0], c->c_net[1], net_dev(c), base, out));
+  }
+}
+
+// RAII device buffers for the context-free training entry point
+struct DevBufs {
+  std::vector<void*> p;
+  template <typename T>
+  T* get(size_t n) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, (n ? n : 1) * sizeof(T));
+    if (e != hipSuccess) throw Fail{LDGS_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+    p.push_back(q);
+    return (T*)q;
+  }
+  ~DevBufs() {
+    for (void* q : p) (void)hipFree(q);
+  }
+};
+
 }  // namespace
 
 // ===========================================================================
@@ -735,10 +854,192 @@ ldgs_status ldgs_set_vprec(ldgs_ctx* ctx, int vprec) {
   return LDGS_OK;
 }
 
-ldgs_status ldgs_set_learned(ldgs_ctx* ctx, const void*, int64_t) {
-  if (!ctx) return LDGS_E_ARG;
-  ctx->err = "learned correction not available in this version";
-  return LDGS_E_UNSUPPORTED;
+ldgs_status ldgs_set_learned(ldgs_ctx* ctx, const ldgs_net* net) {
+  try {
+    check_ctx(ctx, true);
+    if (!net) {
+      ctx->net_loaded = false;
+      return LDGS_OK;
+    }
+    if (net->dim != ctx->P.dim || net->degree != ctx->P.degree) throw Fail{LDGS_E_ARG, "network dim/degree mismatch"};
+    if (net->hidden != NET_H) throw Fail{LDGS_E_UNSUPPORTED, "network hidden width must be 16"};
+    const NetShape ns = net_shape(ctx->P.dim, ctx->P.degree);
+    if (!net->params || net->nparams != ns.flat_total)
+      throw Fail{LDGS_E_ARG, "network parameter count: expected " + std::to_string(ns.flat_total)};
+    if (!(net->c_vel > 0) || !(net->c_pre > 0)) throw Fail{LDGS_E_ARG, "output scales must be positive"};
+    for (int64_t i = 0; i < ns.flat_total; ++i)
+      if (!std::isfinite(net->params[i])) throw Fail{LDGS_E_NONFINITE, "network parameters"};
+    learned_buffers(ctx);
+    if (!ctx->d_net) {
+      ctx->d_net = dalloc<float>(ctx, ns.total);
+      ctx->d_netbf = dalloc<uint16_t>(ctx, ns.total);
+    }
+    std::vector<float> pad;
+    net_pack(ns, net->params, pad);
+    HIPCHK(hipMemcpy(ctx->d_net, pad.data(), pad.size() * sizeof(float), hipMemcpyHostToDevice));
+    LCHK(launch_to_bf16(ctx->stream, ns.total, ctx->d_net, ctx->d_netbf));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ctx->ns = ns;
+    ctx->c_net[0] = net->c_vel;
+    ctx->c_net[1] = net->c_pre;
+    ctx->net_loaded = true;
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+ldgs_status ldgs_learned_correction(ldgs_ctx* ctx, const double* r, double* dx) {
+  try {
+    check_ctx(ctx, true);
+    if (!r || !dx) throw Fail{LDGS_E_ARG, "null argument"};
+    if (!ctx->net_loaded) throw Fail{LDGS_E_ARG, "no network loaded"};
+    const Level& L = ctx->levels[0];
+    const int nb = ctx->g.nb, nvel = ctx->g.d * ctx->g.nq;
+    LCHK(launch_field_sumsq<double>(ctx->stream, L.NE, nb, nvel, r, nullptr, ctx->w_part, SUMSQ_BLK, ctx->d_sums));
+    LCHK(launch_net_apply<double>(ctx->stream, ctx->g.d, ctx->g.p, L.n, log2i(L.n), periodic_mask(ctx->P), r, nullptr,
+                                  ctx->d_logmu, ctx->d_sums, (double)L.NE * nvel, (double)L.NE * (nb - nvel),
+                                  ctx->c_net[0], ctx->c_net[1], net_dev(ctx), nullptr, dx));
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+ldgs_status ldgs_learned_collect(ldgs_ctx* ctx, const double* xstar, int ncycles, int crop, int ncrops,
+                                 const int* origins, uint16_t* feat, uint16_t* targ, double* stats) {
+  try {
+    check_ctx(ctx, true);
+    const Level& L = ctx->levels[0];
+    const int d = ctx->g.d;
+    if (!xstar || !origins || !feat || !targ || ncycles < 1 || ncrops < 1) throw Fail{LDGS_E_ARG, "bad argument"};
+    if (!pow2(crop) || crop < 4 || crop > L.n) throw Fail{LDGS_E_ARG, "crop must be a power of two in [4, n]"};
+    const int64_t norig = (int64_t)ncycles * ncrops * d;
+    for (int64_t i = 0; i < norig; ++i) {
+      const int k = (int)(i % d);
+      const int o = origins[i];
+      const bool per = ctx->P.bc[k] == LDGS_PERIODIC;
+      if (o < 0 || o >= L.n || (!per && o + crop > L.n)) throw Fail{LDGS_E_ARG, "crop origin out of range"};
+    }
+    learned_buffers(ctx);
+    const NetShape ns = net_shape(d, ctx->P.degree);
+    const int64_t N = ctx->ndof();
+    const int nb = ctx->g.nb, nvel = d * ctx->g.nq;
+    if (!ctx->w_cb) {
+      ctx->w_cb = dalloc<double>(ctx, N);
+      ctx->w_cx = dalloc<double>(ctx, N);
+      ctx->w_ce = dalloc<double>(ctx, N);
+    }
+    if (ctx->d_orig_cap < norig) {
+      ctx->d_orig = dalloc<int>(ctx, norig);
+      ctx->d_orig_cap = norig;
+    }
+    HIPCHK(hipMemcpy(ctx->d_orig, origins, norig * sizeof(int), hipMemcpyHostToDevice));
+    int64_t Md = 1, Cd = 1;
+    for (int k = 0; k < d; ++k) {
+      Md *= crop + 2;
+      Cd *= crop;
+    }
+    LaunchCfg cfg{d, ctx->g.p, ctx->stream};
+    LCHK(launch_residual<double>(cfg, ctx->s64.lv[0].unscaled, ctx->tab, nullptr, xstar, ctx->w_cb, 1));
+    LCHK(launch_fill<double>(ctx->stream, N, 0.0, ctx->w_cx));
+    const double cu = (double)L.NE * nvel, cp = (double)L.NE * (nb - nvel);
+    for (int k = 0; k < ncycles; ++k) {
+      vcycle_user(ctx, ctx->vprec, ctx->w_cb, ctx->w_cx, false);
+      residual_fine(ctx, ctx->w_cb, ctx->w_cx, ctx->w_r);
+      LCHK(launch_scale_copy(ctx->stream, N, 1.0, xstar, ctx->w_ce));
+      LCHK(launch_axpy(ctx->stream, N, -1.0, ctx->w_cx, ctx->w_ce));
+      project_kernel(ctx, ctx->w_ce);
+      LCHK(launch_field_sumsq<double>(ctx->stream, L.NE, nb, nvel, ctx->w_r, nullptr, ctx->w_part, SUMSQ_BLK,
+                                      ctx->d_sums));
+      LCHK(launch_collect_crops(ctx->stream, d, ctx->g.p, L.n, log2i(L.n), periodic_mask(ctx->P), crop, log2i(crop),
+                                ncrops, ctx->d_orig + (int64_t)k * ncrops * d, ctx->w_r, ctx->w_ce, ctx->d_logmu,
+                                ctx->d_sums, cu, cp, feat + (int64_t)k * ncrops * Md * ns.chp,
+                                targ + (int64_t)k * ncrops * Cd * nb));
+      if (stats) {
+        double sr[2], se[2];
+        HIPCHK(hipMemcpyAsync(sr, ctx->d_sums, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        LCHK(launch_field_sumsq<double>(ctx->stream, L.NE, nb, nvel, ctx->w_ce, nullptr, ctx->w_part, SUMSQ_BLK,
+                                        ctx->d_sums));
+        HIPCHK(hipMemcpyAsync(se, ctx->d_sums, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        const double su = sr[0] > 0 ? std::sqrt(sr[0] / cu) : 1.0, sp = sr[1] > 0 ? std::sqrt(sr[1] / cp) : 1.0;
+        stats[4 * k + 0] = su;
+        stats[4 * k + 1] = sp;
+        stats[4 * k + 2] = std::sqrt(se[0] / cu) / su;
+        stats[4 * k + 3] = std::sqrt(se[1] / cp) / sp;
+      }
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
+ldgs_status ldgs_learned_train(const ldgs_train_args* a, float* params, double* loss_out, float* grad0_out) {
+  try {
+    if (!a || !params || !a->feat || !a->targ || !a->order) throw Fail{LDGS_E_ARG, "null argument"};
+    if ((a->dim != 2 && a->dim != 3) || a->degree < 1 || a->degree > (a->dim == 2 ? 3 : 2))
+      throw Fail{LDGS_E_UNSUPPORTED, "dim/degree"};
+    if (a->hidden != NET_H) throw Fail{LDGS_E_UNSUPPORTED, "hidden width must be 16"};
+    if (!pow2(a->crop) || a->crop < 4) throw Fail{LDGS_E_ARG, "crop must be a power of two >= 4"};
+    if (a->batch < 1 || a->steps < 0 || a->ncrops < 1) throw Fail{LDGS_E_ARG, "batch/steps/ncrops"};
+    if (!(a->c_vel > 0) || !(a->c_pre > 0) || !(a->lr > 0)) throw Fail{LDGS_E_ARG, "scales and lr must be positive"};
+    for (int64_t i = 0; i < (int64_t)a->steps * a->batch; ++i)
+      if (a->order[i] < 0 || a->order[i] >= a->ncrops) throw Fail{LDGS_E_ARG, "order index out of range"};
+    const NetShape ns = net_shape(a->dim, a->degree);
+    hipStream_t st = (hipStream_t)a->hip_stream;
+    DevBufs B;
+    float* w = B.get<float>(ns.total);
+    uint16_t* wbf = B.get<uint16_t>(ns.total);
+    float* g = B.get<float>(ns.total);
+    float* m = B.get<float>(ns.total);
+    float* v = B.get<float>(ns.total);
+    const int nsteps = a->steps > 0 ? a->steps : 1;
+    double* dl = B.get<double>(nsteps);
+    int* ord = B.get<int>((size_t)nsteps * a->batch);
+    std::vector<float> pad;
+    net_pack(ns, params, pad);
+    HIPCHK(hipMemcpy(w, pad.data(), pad.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ord, a->order, (size_t)std::max(a->steps, 1) * a->batch * sizeof(int), hipMemcpyHostToDevice));
+    LCHK(launch_to_bf16(st, ns.total, w, wbf));
+    LCHK(launch_fill<float>(st, ns.total, 0.f, m));
+    LCHK(launch_fill<float>(st, ns.total, 0.f, v));
+    LCHK(launch_fill<double>(st, nsteps, 0.0, dl));
+    int64_t Cd = 1;
+    for (int k = 0; k < a->dim; ++k) Cd *= a->crop;
+    const double inv_count = 1.0 / ((double)a->batch * Cd * ns.nb);
+    const int steps_run = (a->steps == 0 && grad0_out) ? 1 : a->steps;
+    for (int s = 0; s < steps_run; ++s) {
+      LCHK(launch_fill<float>(st, ns.total, 0.f, g));
+      LCHK(launch_train_grad(st, a->dim, a->degree, a->crop, log2i(a->crop), a->batch, ord + (int64_t)s * a->batch,
+                             a->feat, a->targ, a->c_vel, a->c_pre, inv_count, NetDev{w, wbf}, g, dl + s));
+      if (s == 0 && grad0_out) {
+        std::vector<float> gp(ns.total);
+        HIPCHK(hipMemcpyAsync(gp.data(), g, ns.total * sizeof(float), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        net_unpack(ns, gp, grad0_out);
+      }
+      if (a->steps == 0) break;
+      const int t = s + 1;
+      const float bc1 = (float)(1.0 / (1.0 - std::pow((double)a->beta1, t)));
+      const float bc2 = (float)(1.0 / (1.0 - std::pow((double)a->beta2, t)));
+      LCHK(launch_adam(st, ns.total, w, wbf, g, m, v, a->lr, a->beta1, a->beta2, a->eps, bc1, bc2));
+    }
+    HIPCHK(hipMemcpyAsync(pad.data(), w, ns.total * sizeof(float), hipMemcpyDeviceToHost, st));
+    std::vector<double> hl(nsteps);
+    HIPCHK(hipMemcpyAsync(hl.data(), dl, nsteps * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    net_unpack(ns, pad, params);
+    if (loss_out)
+      for (int s = 0; s < a->steps; ++s) loss_out[s] = hl[s] * inv_count;
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    g_setup_error = f.msg;
+    return f.st;
+  }
 }
 
 ldgs_status ldgs_project_kernel(ldgs_ctx* ctx, double* v) {
@@ -757,7 +1058,10 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxi
   try {
     check_ctx(ctx, true);
     if (!b || !x || maxit < 0 || !(tol >= 0)) throw Fail{LDGS_E_ARG, "bad argument"};
-    if (use_learned) throw Fail{LDGS_E_UNSUPPORTED, "learned correction not available in this version"};
+    if (use_learned) {
+      if (outer != LDGS_IR) throw Fail{LDGS_E_UNSUPPORTED, "the learned correction is used with outer = IR"};
+      if (!ctx->net_loaded) throw Fail{LDGS_E_ARG, "no network loaded"};
+    }
     auto t0 = std::chrono::steady_clock::now();
     const int64_t N = ctx->ndof();
     project_kernel(ctx, b);
@@ -766,6 +1070,7 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxi
     double rel = 0.0;
     std::vector<double> hist;
     ldgs_status st = LDGS_OK;
+    int events = 0;
     auto relres = [&]() {
       residual_fine(ctx, b, x, ctx->w_r);
       double v = std::sqrt(dot(ctx, ctx->w_r, ctx->w_r));
@@ -778,16 +1083,39 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxi
     } else if (outer == LDGS_STATIONARY || outer == LDGS_IR) {
       rel = relres();
       hist.push_back(rel);
+      bool learn_on = use_learned != 0;
+      double rho_plain = 0.0;
+      int strikes = 0;
       while (rel > tol && it < maxit) {
+        double rn;
         if (outer == LDGS_STATIONARY) {
           vcycle_user(ctx, ctx->vprec, b, x, false);
-        } else {
+          rn = relres();
+        } else if (!(learn_on && it >= 2)) {
           // r = b - A x is in w_r from relres()
           precond_add(ctx, ctx->vprec, ctx->w_r, x);
+          rn = relres();
+        } else {
+          // z = V(r); x_old + (z + dx), dx from r - A z; guarded below
+          vcycle_user(ctx, ctx->vprec, ctx->w_r, ctx->w_z, true);
+          learned_after_cycle(ctx, ctx->vprec, ctx->w_z, ctx->w_zl);
+          HIPCHK(hipMemcpyAsync(ctx->w_xold, x, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+          LCHK(launch_axpy(ctx->stream, N, 1.0, ctx->w_zl, x));
+          rn = relres();
+          const double ck = rn / hist.back();
+          strikes = (ck > 1.1 * rho_plain) ? strikes + 1 : 0;
+          if (ck > 1.0 || strikes >= 2) {
+            learn_on = false;
+            ++events;
+            HIPCHK(hipMemcpyAsync(x, ctx->w_xold, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+            LCHK(launch_axpy(ctx->stream, N, 1.0, ctx->w_z, x));
+            rn = relres();
+          }
         }
         ++it;
-        rel = relres();
+        rel = rn;
         hist.push_back(rel);
+        if (use_learned && it == 2) rho_plain = std::sqrt(hist[2] / hist[0]);
         if (!std::isfinite(rel)) { st = LDGS_E_NONFINITE; break; }
         if (rel > 1e3 * hist[0]) { st = LDGS_E_NOT_CONVERGED; break; }
       }
@@ -856,7 +1184,7 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxi
     if (st == LDGS_OK && rel > tol) st = LDGS_E_NOT_CONVERGED;
     if (info) {
       info->iters = it;
-      info->fallback_events = 0;
+      info->fallback_events = events;
       info->relres = rel;
       info->rho_measured = (it > 0 && rel > 0 && hist[0] > 0) ? std::pow(rel / hist[0], 1.0 / it) : 0.0;
       info->t_solve_s = secs;

@@ -29,6 +29,7 @@ V_FP64, V_FP32, V_FP32_BF16BLK = 0, 1, 2
 STATIONARY, IR, FGMRES = 0, 1, 2
 FIELD_CONST, FIELD_SINSIN, FIELD_LOGNORMAL_RFF, FIELD_PHASE_CONST, FIELD_CALLBACK = range(5)
 LEVELSET_NONE, LEVELSET_BOX = 0, 1
+NET_HIDDEN = 16          # hidden width of the learned correction network
 
 EVAL_FN = C.CFUNCTYPE(None, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int),
                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p)
@@ -61,6 +62,19 @@ class Info(C.Structure):
                 ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int), ("history_len", C.c_int)]
 
 
+class NetStruct(C.Structure):
+    _fields_ = [("dim", C.c_int), ("degree", C.c_int), ("hidden", C.c_int), ("params", C.POINTER(C.c_float)),
+                ("nparams", C.c_int64), ("c_vel", C.c_double), ("c_pre", C.c_double)]
+
+
+class TrainArgs(C.Structure):
+    _fields_ = [("hip_stream", C.c_void_p), ("dim", C.c_int), ("degree", C.c_int), ("hidden", C.c_int),
+                ("crop", C.c_int), ("ncrops", C.c_int), ("feat", C.c_void_p), ("targ", C.c_void_p),
+                ("c_vel", C.c_double), ("c_pre", C.c_double), ("batch", C.c_int), ("steps", C.c_int),
+                ("order", C.POINTER(C.c_int)), ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
+
+
 _P = C.c_void_p
 _D = C.POINTER(C.c_double)
 _SIGS = {
@@ -72,7 +86,10 @@ _SIGS = {
     "ldgs_vcycle": ([_P, _P, _P]),
     "ldgs_solve": ([_P, _P, _P, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(Info)]),
     "ldgs_set_vprec": ([_P, C.c_int]),
-    "ldgs_set_learned": ([_P, _P, C.c_int64]),
+    "ldgs_set_learned": ([_P, C.POINTER(NetStruct)]),
+    "ldgs_learned_correction": ([_P, _P, _P]),
+    "ldgs_learned_collect": ([_P, _P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), _P, _P, _D]),
+    "ldgs_learned_train": ([C.POINTER(TrainArgs), C.POINTER(C.c_float), _D, C.POINTER(C.c_float)]),
     "ldgs_project_kernel": ([_P, _P]),
     "ldgs_level_info": ([_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "ldgs_level_smooth_colour": ([_P, C.c_int, C.c_int, _P, _P]),
@@ -290,8 +307,41 @@ class Context:
         if st != OK and (raise_on_failure or st not in (E_NOT_CONVERGED,)):
             self._check(st)
         return st, dict(iters=info.iters, relres=info.relres, rho=info.rho_measured,
-                        t_solve_s=info.t_solve_s,
+                        t_solve_s=info.t_solve_s, fallback_events=info.fallback_events,
                         history=np.array(hist[:info.history_len]))
+
+    # ---- learned correction -------------------------------------------------
+    def set_learned(self, params, c_vel, c_pre, hidden=NET_HIDDEN):
+        """params: flat FP32 array in the layout of ldgs_net (or None to remove)."""
+        if params is None:
+            self._check(_lib.ldgs_set_learned(self._h, None))
+            return
+        flat = np.ascontiguousarray(params, dtype=np.float32)
+        net = NetStruct(self.prob.dim, self.prob.p, hidden, flat.ctypes.data_as(C.POINTER(C.c_float)),
+                        flat.size, c_vel, c_pre)
+        self._check(_lib.ldgs_set_learned(self._h, C.byref(net)))
+
+    def learned_correction(self, r, dx=None):
+        dx = self.zeros() if dx is None else dx
+        self._check(_lib.ldgs_learned_correction(self._h, _dptr(r), _dptr(dx)))
+        return dx
+
+    def learned_collect(self, xstar, ncycles, crop, origins):
+        """origins: int array (ncycles, ncrops, d).  Returns (feat, targ, stats):
+        feat/targ device int16 tensors holding bfloat16 bits, stats (ncycles, 4)."""
+        import torch
+        org = np.ascontiguousarray(origins, dtype=np.int32)
+        ncrops = org.shape[1]
+        d = self.prob.dim
+        nb = (d + 1) * (self.prob.p + 1) ** d
+        chp = (nb + 1 + 7) // 8 * 8
+        feat = torch.empty(ncycles * ncrops * (crop + 2) ** d * chp, dtype=torch.int16, device="cuda")
+        targ = torch.empty(ncycles * ncrops * crop ** d * nb, dtype=torch.int16, device="cuda")
+        stats = np.zeros((ncycles, 4))
+        self._check(_lib.ldgs_learned_collect(self._h, _dptr(xstar), ncycles, crop, ncrops,
+                                              org.ctypes.data_as(C.POINTER(C.c_int)), _dptr(feat), _dptr(targ),
+                                              stats.ctypes.data_as(_D)))
+        return feat, targ, stats
 
     # ---- stages -------------------------------------------------------------
     def level_info(self, level):
@@ -347,3 +397,30 @@ class Context:
         self._check(_lib.ldgs_bottom_info(self._h, None, pinv.ctypes.data_as(C.POINTER(C.c_double)),
                                           eig.ctypes.data_as(C.POINTER(C.c_double))))
         return pinv, eig
+
+
+def net_nparams(dim, degree, hidden=NET_HIDDEN):
+    nb = (dim + 1) * (degree + 1) ** dim
+    return hidden * 3 ** dim * (nb + 1) + 2 * hidden + hidden * hidden + nb * hidden + nb
+
+
+def learned_train(dim, degree, crop, ncrops, feat, targ, c_vel, c_pre, params, order, lr=1e-3,
+                  beta1=0.9, beta2=0.999, eps=1e-8, want_grad0=False, hidden=NET_HIDDEN):
+    """Runs len(order) Adam steps (order: int array (steps, batch) of crop
+    indices) on device crops; returns (params, losses, grad0 or None)."""
+    import torch
+    p = np.array(params, dtype=np.float32, copy=True)
+    org = np.ascontiguousarray(order, dtype=np.int32)
+    if org.ndim != 2:
+        raise ValueError("order must be (steps, batch)")
+    steps, batch = org.shape
+    a = TrainArgs(C.c_void_p(torch.cuda.current_stream().cuda_stream), dim, degree, hidden, crop, ncrops,
+                  _dptr(feat), _dptr(targ), c_vel, c_pre, batch, steps,
+                  org.ctypes.data_as(C.POINTER(C.c_int)), lr, beta1, beta2, eps)
+    losses = np.zeros(max(steps, 1))
+    g0 = np.zeros_like(p) if want_grad0 else None
+    st = _lib.ldgs_learned_train(C.byref(a), p.ctypes.data_as(C.POINTER(C.c_float)), losses.ctypes.data_as(_D),
+                                 g0.ctypes.data_as(C.POINTER(C.c_float)) if want_grad0 else None)
+    if st != OK:
+        raise LdgsError(st, _lib.ldgs_last_error(None).decode())
+    return p, losses[:steps], g0

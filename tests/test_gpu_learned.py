@@ -1,0 +1,289 @@
+"""GPU parity of the learned correction through the C ABI: the inference
+kernel against the oracle network (BF16 emulation and FP64), crop collection
+against the oracle's training pairs, first-step gradients of the training
+kernel against the oracle's BF16-emulated backward pass, the zero-output
+network reproducing the plain solve exactly, and the guard."""
+import numpy as np
+import pytest
+
+from synth import Problem, c1_periodic_standard, c2_dirichlet_varmu
+from synth.learning import random_smooth_coeffs, crop_origins, batch_order, bf16_grid_values
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "c2_n16_p3": lambda: c2_dirichlet_varmu(n=16, p=3),
+    "c1_n16_p2": lambda: c1_periodic_standard(n=16, p=2),
+    "per3d_n8_p1": lambda: Problem(name="p3", dim=3, n=8, p=1, gamma=1, bc=("periodic",) * 3),
+    "dir3d_n8_p2": lambda: Problem(name="d3", dim=3, n=8, p=2, gamma=1, bc=("dirichlet",) * 3),
+}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _setup(prob, vprec=0):
+    from oracle import build_hierarchy
+    from oracle import learned as L
+    from paper_1911_05888_amd import Context
+    H = build_hierarchy(prob)
+    g = L.grid_of(H)
+    ctx = Context(prob, vprec=vprec)
+    return H, g, ctx
+
+
+def _params(d, nb, seed, bias=0.1):
+    from oracle import learned as L
+    p = L.init_params(d, nb, 16, seed)
+    rng = np.random.default_rng(seed + 100)
+    for k in ("b1", "b2", "b3"):
+        p[k] = bias * rng.standard_normal(p[k].shape)
+    return p
+
+
+def _flat(p):
+    return np.concatenate([p[k].ravel() for k in ("W1", "b1", "W2", "b2", "W3", "b3")]).astype(np.float32)
+
+
+def _unflat(v, d, nb, H=16):
+    K = 3 ** d * (nb + 1)
+    sizes = [("W1", (H, K)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (nb, H)), ("b3", (nb,))]
+    out, o = {}, 0
+    for k, sh in sizes:
+        n = int(np.prod(sh))
+        out[k] = np.asarray(v[o:o + n], dtype=np.float64).reshape(sh)
+        o += n
+    return out
+
+
+def _master_f32(p):
+    """The parameters as the library stores them (FP32)."""
+    return {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_correction_matches_oracle(name):
+    from oracle import learned as L
+    torch = _torch()
+    prob = CASES[name]()
+    H, g, ctx = _setup(prob)
+    print(f"[learned] correction case {name}", flush=True)
+    p = _params(g.d, g.nb, seed=3)
+    cvec = (0.7, 1.9)
+    ctx.set_learned(_flat(p), *cvec)
+    rng = np.random.Generator(np.random.PCG64(21))
+    r = rng.standard_normal(ctx.ndof)
+    dx = ctx.learned_correction(torch.tensor(r, device="cuda")).cpu().numpy()
+    ref16 = L.correction(_master_f32(p), cvec, g, r, emulate_bf16=True)
+    ref64 = L.correction(p, cvec, g, r)
+    e16 = np.linalg.norm(dx - ref16) / np.linalg.norm(ref16)
+    e64 = np.linalg.norm(dx - ref64) / np.linalg.norm(ref64)
+    print(f"[learned] {name}: rel err vs BF16 emulation {e16:.2e}, vs FP64 {e64:.2e}", flush=True)
+    assert e16 <= 1e-2
+    assert e64 <= 3e-2
+
+
+def test_zero_output_network_gives_zero_correction():
+    torch = _torch()
+    prob = c2_dirichlet_varmu(n=16, p=3)
+    H, g, ctx = _setup(prob)
+    p = _params(g.d, g.nb, seed=4)
+    p["W3"][:] = 0.0
+    p["b3"][:] = 0.0
+    ctx.set_learned(_flat(p), 1.0, 1.0)
+    r = torch.tensor(np.random.default_rng(5).standard_normal(ctx.ndof), device="cuda")
+    dx = ctx.learned_correction(r)
+    assert torch.count_nonzero(dx).item() == 0
+
+
+@pytest.mark.parametrize("name", ["c2_n16_p3", "c1_n16_p2", "per3d_n8_p1"])
+def test_collect_matches_oracle_pairs(name):
+    from oracle import learned as L
+    from oracle.solvers import Solver
+    torch = _torch()
+    prob = CASES[name]()
+    H, g, ctx = _setup(prob)
+    print(f"[learned] collect case {name}", flush=True)
+    d, n, nb = g.d, g.n, g.nb
+    crop, ncyc, ncrop = 4, 3, 3
+    xstar = H.project_kernel(random_smooth_coeffs(7, d, n, prob.p))
+    org = crop_origins(8, ncyc, ncrop, d, n, crop, g.periodic)
+    feat, targ, stats = ctx.learned_collect(torch.tensor(xstar, device="cuda"), ncyc, crop, org)
+    chp = (nb + 1 + 7) // 8 * 8
+    m = crop + 2
+    F = feat.cpu().numpy().view(np.uint16).reshape(ncyc, ncrop, m ** d, chp)
+    T = targ.cpu().numpy().view(np.uint16).reshape(ncyc, ncrop, crop ** d, nb)
+    Ff = (F.astype(np.uint32) << 16).view(np.float32)
+    Tf = (T.astype(np.uint32) << 16).view(np.float32)
+    pairs = L.collect_pairs(Solver(H), xstar, ncyc)
+    for k, (r, e) in enumerate(pairs):
+        Z, s = L.element_channels(r, g.logmu, d, g.nq)
+        assert np.allclose(stats[k, :2], s, rtol=1e-9)
+        E = e.reshape(-1, nb).copy()
+        E[:, :d * g.nq] /= s[0]
+        E[:, d * g.nq:] /= s[1]
+        assert np.allclose(stats[k, 2], np.sqrt(np.mean(E[:, :d * g.nq] ** 2)), rtol=1e-9)
+        assert np.allclose(stats[k, 3], np.sqrt(np.mean(E[:, d * g.nq:] ** 2)), rtol=1e-9)
+        for c in range(ncrop):
+            zc = L.crop(Z, (n,) * d, g.periodic, org[k, c], crop, 1)
+            ec = L.crop(E, (n,) * d, g.periodic, org[k, c], crop, 0)
+            want_f = L.bf16(zc)
+            got = Ff[k, c]
+            assert np.all(got[:, nb + 1:] == 0)
+            # equal up to one bfloat16 step (inputs computed in different
+            # orders); entries at rounding level of the RMS-one data (residuals
+            # of the last colour, log10 of a constant mu) compare absolutely
+            assert np.all(np.abs(got[:, :nb + 1] - want_f) <= 2.0 ** -7 * np.abs(want_f) + 1e-9)
+            want_t = L.bf16(ec)
+            assert np.all(np.abs(Tf[k, c] - want_t) <= 2.0 ** -7 * np.abs(want_t) + 1e-9)
+
+
+def _crop_rows(Ff, Tf, d, crop, nb, order_row):
+    """Patch rows X and targets of the crops listed (oracle side)."""
+    from oracle.learned import offsets
+    m = crop + 2
+    X, T = [], []
+    for cid in order_row:
+        for q in range(crop ** d):
+            lc = [(q // crop ** k) % crop for k in range(d)]
+            row = []
+            for o in offsets(d):
+                idx = sum((lc[k] + 1 + o[k]) * m ** k for k in range(d))
+                row.append(Ff[cid, idx, :nb + 1])
+            X.append(np.concatenate(row))
+            T.append(Tf[cid, q])
+    return np.array(X, dtype=np.float64), np.array(T, dtype=np.float64)
+
+
+@pytest.mark.parametrize("d,p", [(2, 3), (2, 2), (3, 1)])
+def test_training_gradient_matches_oracle_bf16(d, p):
+    from oracle import learned as L
+    from paper_1911_05888_amd import learned_train
+    torch = _torch()
+    print(f"[learned] gradient case d={d} p={p}", flush=True)
+    nb = (d + 1) * (p + 1) ** d
+    chp = (nb + 1 + 7) // 8 * 8
+    crop, ncrops, batch = 4, 6, 3
+    m = crop + 2
+    rng = np.random.Generator(np.random.PCG64(31))
+    Ff, Fb = bf16_grid_values(rng, (ncrops, m ** d, chp))
+    Ff[:, :, nb + 1:] = 0.0
+    Fb[:, :, nb + 1:] = 0
+    Tf, Tb = bf16_grid_values(rng, (ncrops, crop ** d, nb), scale=0.5)
+    feat = torch.tensor(Fb.view(np.int16).ravel(), device="cuda")
+    targ = torch.tensor(Tb.view(np.int16).ravel(), device="cuda")
+    p0 = _params(d, nb, seed=5)
+    order = batch_order(9, 1, batch, ncrops)
+    cvec = (0.8, 1.3)
+    _, losses, g0 = learned_train(d, p, crop, ncrops, feat, targ, cvec[0], cvec[1], _flat(p0), order,
+                                  want_grad0=True)
+    X, T = _crop_rows(Ff, Tf, d, crop, nb, order[0])
+    scale = np.array([cvec[0]] * (d * (p + 1) ** d) + [cvec[1]] * (p + 1) ** d, dtype=np.float32)
+    T = (T.astype(np.float32) / scale[None, :]).astype(np.float64)
+    loss_o, g_o = L.loss_and_grad(_master_f32(p0), X, T, emulate_bf16=True)
+    assert abs(losses[0] - loss_o) <= 1e-3 * loss_o
+    g_gpu = _unflat(g0, d, nb)
+    for k in g_o:
+        a = np.asarray(g_o[k], dtype=np.float64).ravel()
+        b = g_gpu[k].ravel()
+        rel = np.linalg.norm(a - b) / np.linalg.norm(a)
+        cos = a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+        print(f"[learned]   grad {k}: rel {rel:.2e} cos {cos:.6f}", flush=True)
+        assert rel <= 2e-2 and cos >= 0.999, k
+
+
+def test_training_reduces_loss_on_collected_crops():
+    from paper_1911_05888_amd import learned_train
+    torch = _torch()
+    prob = c2_dirichlet_varmu(n=32, p=2)
+    H, g, ctx = _setup(prob, vprec=1)
+    d, nb = g.d, g.nb
+    crop, ncyc, ncrop = 8, 4, 8
+    feats, targs, stats = [], [], []
+    for seed in range(4):
+        xstar = H.project_kernel(random_smooth_coeffs(100 + seed, d, g.n, prob.p))
+        org = crop_origins(200 + seed, ncyc, ncrop, d, g.n, crop, g.periodic)
+        f, t, s = ctx.learned_collect(torch.tensor(xstar, device="cuda"), ncyc, crop, org)
+        feats.append(f)
+        targs.append(t)
+        stats.append(s)
+    feat, targ = torch.cat(feats), torch.cat(targs)
+    st = np.concatenate(stats)
+    cvec = (np.sqrt(np.mean(st[:, 2] ** 2)), np.sqrt(np.mean(st[:, 3] ** 2)))
+    ncrops = 4 * ncyc * ncrop
+    order = batch_order(3, 400, 8, ncrops)
+    p0 = _params(d, nb, seed=6, bias=0.0)
+    p1, losses, _ = learned_train(d, prob.p, crop, ncrops, feat, targ, cvec[0], cvec[1], _flat(p0), order)
+    first, last = losses[:20].mean(), losses[-20:].mean()
+    print(f"[learned] training loss {first:.4f} -> {last:.4f}", flush=True)
+    assert np.all(np.isfinite(p1))
+    assert last < 0.7 * first
+
+
+def _rhs(ctx, prob):
+    return ctx.assemble_rhs(prob.rhs_source())
+
+
+def test_zero_output_network_reproduces_plain_solve_exactly():
+    from paper_1911_05888_amd import IR
+    prob = c2_dirichlet_varmu(n=32, p=3)
+    H, g, ctx = _setup(prob, vprec=1)
+    p = _params(g.d, g.nb, seed=7)
+    p["W3"][:] = 0.0
+    p["b3"][:] = 0.0
+    ctx.set_learned(_flat(p), 1.0, 1.0)
+    b = _rhs(ctx, prob)
+    x1, x2 = ctx.zeros(), ctx.zeros()
+    st1, i1 = ctx.solve(b.clone(), x1, tol=1e-10, maxit=40, outer=IR)
+    st2, i2 = ctx.solve(b.clone(), x2, tol=1e-10, maxit=40, outer=IR, use_learned=True)
+    assert st1 == 0 and st2 == 0
+    # the guard may still fire where the plain contraction itself slows down;
+    # its reverted step is the plain step, so the iterates are unchanged
+    print(f"[learned] zero-output network: fallback events {i2['fallback_events']}", flush=True)
+    assert np.array_equal(i1["history"], i2["history"])
+    assert bool((x1 == x2).all())
+
+
+def test_guard_switches_a_harmful_correction_off():
+    from paper_1911_05888_amd import IR
+    prob = c2_dirichlet_varmu(n=32, p=3)
+    H, g, ctx = _setup(prob, vprec=1)
+    p = _params(g.d, g.nb, seed=8)
+    p["b3"][:] = 50.0
+    ctx.set_learned(_flat(p), 1.0, 1.0)
+    b = _rhs(ctx, prob)
+    st1, i1 = ctx.solve(b.clone(), ctx.zeros(), tol=1e-10, maxit=40, outer=IR)
+    st2, i2 = ctx.solve(b.clone(), ctx.zeros(), tol=1e-10, maxit=40, outer=IR, use_learned=True)
+    assert st2 == 0 and i2["fallback_events"] == 1
+    assert np.array_equal(i1["history"], i2["history"])
+
+
+def test_learned_solve_follows_oracle_guarded_refinement():
+    """FP64 V-cycles with a small correction: GPU and oracle histories agree
+    to the accuracy of the BF16 network (its outputs differ by rounding)."""
+    from oracle import learned as L
+    from oracle.solvers import Solver
+    from oracle.rhs import assemble_rhs
+    from paper_1911_05888_amd import IR
+    torch = _torch()
+    prob = c2_dirichlet_varmu(n=16, p=2)
+    H, g, ctx = _setup(prob, vprec=0)
+    p = _params(g.d, g.nb, seed=9)
+    cvec = (0.02, 0.02)
+    ctx.set_learned(_flat(p), *cvec)
+    b_o = assemble_rhs(prob, H.fine.ops)
+    _, h_o, ev_o = L.refinement_learned(Solver(H), b_o, _master_f32(p), cvec, g, tol=1e-10, maxit=40,
+                                        dtype=np.float64, emulate_bf16=True)
+    b = torch.tensor(b_o, device="cuda")
+    st, info = ctx.solve(b, ctx.zeros(), tol=1e-10, maxit=40, outer=IR, use_learned=True)
+    h = info["history"]
+    print(f"[learned] oracle history {h_o[:6]} events {ev_o}; gpu {h[:6]} events {info['fallback_events']}",
+          flush=True)
+    assert st == 0
+    assert info["fallback_events"] == ev_o
+    assert abs(len(h) - len(h_o)) <= 1
+    k = min(len(h), len(h_o))
+    assert np.allclose(h[:3], h_o[:3], rtol=1e-9)          # plain iterations
+    assert np.all(np.abs(np.log(h[3:k] / h_o[3:k])) <= np.log(1.5))
