@@ -65,6 +65,35 @@ def cpu_baseline(n_sample=32, cycles=15):
                        f"({prob.n_dof} unknowns, {cycles} cycles, {dt:.1f} s); scipy sparse products, one thread")
 
 
+def train_correction(ctx, prob, nseeds=16, ncycles=8, ncrops=16, crop=16, steps=2000, batch=16):
+    """Training pairs from plain V-cycles of the benchmark operator on random
+    smooth exact solutions (not the benchmark's right-hand side), then Adam on
+    bf16 crops; returns (flat params, c_vel, c_pre, info)."""
+    import torch
+    from paper_1911_05888_amd import learned_train, init_net_params
+    from synth.learning import random_smooth_coeffs, crop_origins, batch_order
+    t0 = time.perf_counter()
+    feats, targs, stats = [], [], []
+    per = tuple(bc == "periodic" for bc in prob.bc)
+    for s in range(nseeds):
+        xs = torch.tensor(random_smooth_coeffs(1000 + s, prob.dim, prob.n, prob.p), device="cuda")
+        ctx.project_kernel(xs)
+        org = crop_origins(2000 + s, ncycles, ncrops, prob.dim, prob.n, crop, per)
+        f, t, st = ctx.learned_collect(xs, ncycles, crop, org)
+        feats.append(f)
+        targs.append(t)
+        stats.append(st)
+    feat, targ, st = torch.cat(feats), torch.cat(targs), np.concatenate(stats)
+    c_vel, c_pre = float(np.sqrt(np.mean(st[:, 2] ** 2))), float(np.sqrt(np.mean(st[:, 3] ** 2)))
+    ncr = nseeds * ncycles * ncrops
+    params, losses, _ = learned_train(prob.dim, prob.p, crop, ncr, feat, targ, c_vel, c_pre,
+                                      init_net_params(prob.dim, prob.p, 0), batch_order(5, steps, batch, ncr))
+    torch.cuda.synchronize()
+    info = dict(train_s=time.perf_counter() - t0, pairs=nseeds * ncycles, crops=ncr, steps=steps,
+                loss_first=float(np.mean(losses[:50])), loss_last=float(np.mean(losses[-50:])))
+    return params, c_vel, c_pre, info
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,11 +131,11 @@ def main():
     b0 = ctx.assemble_rhs(prob.exact)
     ncol = ctx.level_info(0)[2]
 
-    def solve(vprec, outer, tol=1e-10, maxit=60):
+    def solve(vprec, outer, tol=1e-10, maxit=60, learned=False):
         ctx.set_vprec(vprec)
         b = b0.clone()
         x = torch.zeros_like(b)
-        st, info = ctx.solve(b, x, tol=tol, maxit=maxit, outer=outer)
+        st, info = ctx.solve(b, x, tol=tol, maxit=maxit, outer=outer, use_learned=learned)
         if st != 0:
             raise RuntimeError(f"solve failed: status {st}, {info}")
         return info
@@ -139,18 +168,28 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        for label, vp, outer in [("plain_fp64_stationary", V_FP64, STATIONARY),
-                                 ("fp32_bf16blk_ir", V_FP32_BF16BLK, IR)]:
-            solve(vp, outer)
+        ctx.set_vprec(V_FP32)
+        params, c_vel, c_pre, tinfo = train_correction(ctx, prob)
+        ctx.set_learned(params, c_vel, c_pre)
+        print(f"[bench] learned correction trained in {tinfo['train_s']:.1f} s, loss "
+              f"{tinfo['loss_first']:.3f} -> {tinfo['loss_last']:.3f}", file=sys.stderr, flush=True)
+        for label, vp, outer, learned in [("plain_fp64_stationary", V_FP64, STATIONARY, False),
+                                          ("plain_fp64_ir", V_FP64, IR, False),
+                                          ("fp32_bf16blk_ir", V_FP32_BF16BLK, IR, False),
+                                          ("fp32_learned_ir", V_FP32, IR, True)]:
+            solve(vp, outer, learned=learned)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             reps = 3
             its = 0
             for _ in range(reps):
-                its += solve(vp, outer)["iters"]
+                info = solve(vp, outer, learned=learned)
+                its += info["iters"]
             torch.cuda.synchronize()
             tt = (time.perf_counter() - t1) / reps
             extras[label] = dict(time_to_tol_s=tt, iters=its / reps, vcycle_dof_per_s=ctx.ndof * its / reps / tt)
+            if learned:
+                extras[label].update(fallback_events=info["fallback_events"], training=tinfo)
             print(f"[bench] {label}: {its / reps:.1f} iters, {tt * 1e3:.2f} ms", file=sys.stderr, flush=True)
 
     line = dict(

@@ -125,6 +125,14 @@ __device__ __forceinline__ int face_index(const int* c, int n, int nfk, int k, i
   return e;
 }
 
+// stencil slot of F - e_k for F = E (fi = 0) or F = E + e_{fi-1}
+template <int D>
+__device__ __forceinline__ int low_slot(int fi, int k) {
+  if (fi == 0) return 1 + k;
+  if (k == fi - 1) return 0;
+  return 1 + 2 * D + (fi - 1) * (D - 1) + (k < fi - 1 ? k : k - 1);
+}
+
 // shared-memory work area of one element evaluation
 template <typename T, int D, int P>
 struct Work {
@@ -142,9 +150,6 @@ struct Work {
   T trr[D][D][S::MT];                 // s_{E+e_k}[i][k] at its low face along k
   T flux[2][D][D + 1][S::MT];         // coefficients of e0 (lo) and e1 (hi) per axis/field
   T res[S::NB];
-  int slot_e[S::NSLOT];
-  int fid[S::NFS][D][2];              // face ids of F = E, E+e_k (low/high face along each axis)
-  int lslot[S::NFS][D];               // slot of F - e_k
   unsigned char ft[S::NFS][D][2];
   T fwl[S::NFS][D][2], fwr[S::NFS][D][2];
 };
@@ -165,81 +170,152 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
 
   int c[D];
   coords_of<D>(E, lgn, c);
-  // ---- setup: stencil slots (lanes 0..NSLOT-1), face tables (lanes 16..) ----
-  if (lane < NSLOT) {
-    int e = -1;
-    int cc[D];
+  // ---- stencil and face data of E (uniform across the wavefront) ----
+  int se[NSLOT];   // element of each slot, -1 outside a wall
+  se[0] = E;
 #pragma unroll
-    for (int j = 0; j < D; ++j) cc[j] = c[j];
-    if (lane == 0) {
-      e = E;
-    } else if (lane < 1 + D) {
-      const int k = lane - 1;
-      if (shift1(cc, k, -1, n, lev.nf[k] == n)) e = index_of<D>(cc, lgn);
-    } else if (lane < 1 + 2 * D) {
-      const int k = lane - 1 - D;
-      if (shift1(cc, k, +1, n, lev.nf[k] == n)) e = index_of<D>(cc, lgn);
-    } else {
-      const int u = lane - 1 - 2 * D;
-      const int k = u / (D - 1), q = u % (D - 1);
+  for (int k = 0; k < D; ++k) {
+    int cm[D], cp[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) cm[j] = cp[j] = c[j];
+    se[1 + k] = shift1(cm, k, -1, n, lev.nf[k] == n) ? index_of<D>(cm, lgn) : -1;
+    se[1 + D + k] = shift1(cp, k, +1, n, lev.nf[k] == n) ? index_of<D>(cp, lgn) : -1;
+#pragma unroll
+    for (int q = 0; q < D - 1; ++q) {
       const int kk = q < k ? q : q + 1;
-      if (shift1(cc, k, +1, n, lev.nf[k] == n) && shift1(cc, kk, -1, n, lev.nf[kk] == n)) e = index_of<D>(cc, lgn);
+      int cq[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) cq[j] = c[j];
+      const bool ok = shift1(cq, k, +1, n, lev.nf[k] == n) && shift1(cq, kk, -1, n, lev.nf[kk] == n);
+      se[1 + 2 * D + k * (D - 1) + q] = ok ? index_of<D>(cq, lgn) : -1;
     }
-    w.slot_e[lane] = e;
-  } else if (lane >= 16 && lane < 16 + NFS * D * 2) {
-    const int u = lane - 16;
-    const int fi = u / (2 * D), k = (u / 2) % D, side = u % 2;
+  }
+  int vmask = 0;
+#pragma unroll
+  for (int sl = 0; sl < NSLOT; ++sl) vmask |= (se[sl] >= 0 ? 1 : 0) << sl;
+  // ---- phase 1: issue every load of the element at once, then stage in LDS ----
+  constexpr int XQ = (NB + WG - 1) / WG;
+  T xr[NSLOT][XQ];
+#pragma unroll
+  for (int sl = 0; sl < NSLOT; ++sl)
+#pragma unroll
+    for (int q = 0; q < XQ; ++q) {
+      const int i = lane + q * WG;
+      const int e = se[sl] >= 0 ? se[sl] : E;          // in-bounds address either way
+      const T v = x[(size_t)e * NB + (i < NB ? i : 0)];
+      xr[sl][q] = (i < NB && se[sl] >= 0) ? v : (T)0;
+    }
+  constexpr int MQ = W::STAGE_M ? (NQ * NQ + WG - 1) / WG : 1;
+  constexpr int RQ = (MT * NQ + WG - 1) / WG;
+  T mr[MQ], rv[D][RQ];
+  if (lev.mmu) {
+    if constexpr (W::STAGE_M) {
+#pragma unroll
+      for (int q = 0; q < MQ; ++q) {
+        const int t = lane + q * WG;
+        const T v = lev.mmu[(size_t)E * NQ * NQ + (t < NQ * NQ ? t : 0)];
+        mr[q] = t < NQ * NQ ? v : (T)0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+      for (int q = 0; q < RQ; ++q) {
+        const int t = lane + q * WG;
+        const int e = se[1 + D + k];
+        const T v = lev.rmu[((size_t)(e >= 0 ? e : E) * D + k) * MT * NQ + (t < MT * NQ ? t : 0)];
+        rv[k][q] = (t < MT * NQ && e >= 0) ? v : (T)0;
+      }
+  }
+  // faces of F = E (fi = 0) and F = E + e_j (fi = 1 + j): type and lifting weights
+  unsigned char fty[NFS][D][2];
+  T fwl_[NFS][D][2], fwr_[NFS][D][2];
+  int fid0[D][2];
+#pragma unroll
+  for (int fi = 0; fi < NFS; ++fi) {
     int cF[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) cF[j] = c[j];
     const bool valid = (fi == 0) || shift1(cF, fi - 1, +1, n, lev.nf[fi - 1] == n);
-    unsigned char ty = F_NONE;
-    T wl = 0, wr = 0;
-    int id = 0;
-    if (valid) {
-      int f = cF[k] + side;
-      if (lev.nf[k] == n) f &= n - 1;
-      id = face_index<D>(cF, n, lev.nf[k], k, f);
-      ty = lev.ftype[k][id];
-      wl = lev.fw[k][2 * id];
-      wr = lev.fw[k][2 * id + 1];
-    }
-    w.fid[fi][k][side] = id;
-    w.ft[fi][k][side] = ty;
-    w.fwl[fi][k][side] = wl;
-    w.fwr[fi][k][side] = wr;
-    if (side == 0) {
-      int sl;
-      if (fi == 0) sl = 1 + k;
-      else if (k == fi - 1) sl = 0;
-      else sl = 1 + 2 * D + (fi - 1) * (D - 1) + (k < fi - 1 ? k : k - 1);
-      w.lslot[fi][k] = sl;
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        int f = cF[k] + side;
+        if (lev.nf[k] == n) f &= n - 1;
+        const int id = face_index<D>(cF, n, lev.nf[k], k, f);
+        fty[fi][k][side] = valid ? lev.ftype[k][id] : (unsigned char)F_NONE;
+        fwl_[fi][k][side] = valid ? lev.fw[k][2 * id] : (T)0;
+        fwr_[fi][k][side] = valid ? lev.fw[k][2 * id + 1] : (T)0;
+        if (fi == 0) fid0[k][side] = id;
+      }
+  }
+  constexpr int TQ = (MT * MT + WG - 1) / WG;
+  T tr[D][2][TQ];
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+#pragma unroll
+    for (int side = 0; side < 2; ++side)
+#pragma unroll
+      for (int q = 0; q < TQ; ++q) {
+        const int t = lane + q * WG;
+        const T v = lev.fT[k][(size_t)fid0[k][side] * MT * MT + (t < MT * MT ? t : 0)];
+        tr[k][side][q] = t < MT * MT ? v : (T)0;
+      }
+  T dsv[NSLOT], dsp[NSLOT];
+#pragma unroll
+  for (int sl = 0; sl < NSLOT; ++sl) {
+    dsv[sl] = (T)1;
+    dsp[sl] = (T)1;
+    if (lev.dscale) {
+      const int e = se[sl] >= 0 ? se[sl] : E;
+      dsv[sl] = lev.dscale[2 * e];
+      dsp[sl] = lev.dscale[2 * e + 1];
     }
   }
-  __syncthreads();
-  // ---- phase 1: stage x of the stencil (scaled when set), M_mu, R_k, penalty matrices ----
-  for (int t = lane; t < NSLOT * NB; t += WG) {
-    const int sl = t / NB, i = t % NB;
-    const int e = w.slot_e[sl];
-    T v = 0;
-    if (e >= 0) {
-      v = x[(size_t)e * NB + i];
-      if (lev.dscale) v *= lev.dscale[2 * e + (i >= D * NQ ? 1 : 0)];
+#pragma unroll
+  for (int sl = 0; sl < NSLOT; ++sl)
+#pragma unroll
+    for (int q = 0; q < XQ; ++q) {
+      const int i = lane + q * WG;
+      if (i < NB) w.xs[sl][i] = xr[sl][q] * (i >= D * NQ ? dsp[sl] : dsv[sl]);
     }
-    w.xs[sl][i] = v;
-  }
   if (lev.mmu) {
-    if constexpr (W::STAGE_M)
-      for (int t = lane; t < NQ * NQ; t += WG) w.mm[t] = lev.mmu[(size_t)E * NQ * NQ + t];
-    for (int t = lane; t < D * MT * NQ; t += WG) {
-      const int k = t / (MT * NQ);
-      const int e = w.slot_e[1 + D + k];
-      w.rr[k][t % (MT * NQ)] = e >= 0 ? lev.rmu[((size_t)e * D + k) * MT * NQ + t % (MT * NQ)] : (T)0;
+    if constexpr (W::STAGE_M) {
+#pragma unroll
+      for (int q = 0; q < MQ; ++q) {
+        const int t = lane + q * WG;
+        if (t < NQ * NQ) w.mm[t] = mr[q];
+      }
     }
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+#pragma unroll
+      for (int q = 0; q < RQ; ++q) {
+        const int t = lane + q * WG;
+        if (t < MT * NQ) w.rr[k][t] = rv[k][q];
+      }
   }
-  for (int t = lane; t < 2 * D * MT * MT; t += WG) {
-    const int side = t / (D * MT * MT), k = (t / (MT * MT)) % D, q = t % (MT * MT);
-    w.th[side][k][q] = lev.fT[k][(size_t)w.fid[0][k][side] * MT * MT + q];
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+#pragma unroll
+    for (int side = 0; side < 2; ++side)
+#pragma unroll
+      for (int q = 0; q < TQ; ++q) {
+        const int t = lane + q * WG;
+        if (t < MT * MT) w.th[side][k][t] = tr[k][side][q];
+      }
+  if (lane == 0) {
+#pragma unroll
+    for (int fi = 0; fi < NFS; ++fi)
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          w.ft[fi][k][side] = fty[fi][k][side];
+          w.fwl[fi][k][side] = fwl_[fi][k][side];
+          w.fwr[fi][k][side] = fwr_[fi][k][side];
+        }
   }
   __syncthreads();
   // ---- phase 2: gradient lines g_F = G_k u_i along axis k ----
@@ -256,12 +332,12 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
       else if (q < 2 * D) { fi = 1 + k; i = q - D; }
       else { const int j0 = q - 2 * D; const int j = j0 < k ? j0 : j0 + 1; fi = 1 + j; i = j; }
       const int sF = (fi == 0) ? 0 : 1 + D + (fi - 1);
-      if (w.slot_e[sF] < 0) continue;
+      if (!((vmask >> sF) & 1)) continue;
       const unsigned char tlo = w.ft[fi][k][0], thi = w.ft[fi][k][1];
       const T wR = w.fwr[fi][k][0], wL = w.fwl[fi][k][1];
       const int base = compose<M>(t, 0, k), st = stride_of<M>(k);
       const T* uu = &w.xs[sF][i * NQ + base];
-      const T* ul = &w.xs[w.lslot[fi][k]][i * NQ + base];
+      const T* ul = &w.xs[low_slot<D>(fi, k)][i * NQ + base];
       T uv[M];
       T trlo = 0, trhi = 0, trLhi = 0;
 #pragma unroll
@@ -310,7 +386,7 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
         const int r = u - NS0;
         const int t = r % MT, i = (r / MT) % D, k = r / (MT * D);
         T v = 0;
-        if (w.slot_e[1 + D + k] >= 0) {
+        if ((vmask >> (1 + D + k)) & 1) {
           const T* g1 = w.g[1 + k][i * D + k];
           const T* g2 = w.g[1 + k][k * D + i];
           if (lev.mmu) {

@@ -424,3 +424,15 @@ def learned_train(dim, degree, crop, ncrops, feat, targ, c_vel, c_pre, params, o
     if st != OK:
         raise LdgsError(st, _lib.ldgs_last_error(None).decode())
     return p, losses[:steps], g0
+
+
+def init_net_params(dim, degree, seed, hidden=NET_HIDDEN, out_scale=0.1):
+    """He-normal initial weights in the flat layout of ldgs_net (zero biases;
+    the output layer scaled by out_scale)."""
+    nb = (dim + 1) * (degree + 1) ** dim
+    K = 3 ** dim * (nb + 1)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = [rng.standard_normal(hidden * K) * np.sqrt(2.0 / K), np.zeros(hidden),
+             rng.standard_normal(hidden * hidden) * np.sqrt(2.0 / hidden), np.zeros(hidden),
+             out_scale * rng.standard_normal(nb * hidden) * np.sqrt(1.0 / hidden), np.zeros(nb)]
+    return np.concatenate(parts).astype(np.float32)
