@@ -156,10 +156,17 @@ struct Work {
 
 // Evaluates (A x)_E (mode 1) or b_E - (A x)_E (mode 0) into w.res.
 // Operators of the diagonally scaled system D A D when lev.dscale is set.
-template <typename T, int D, int P>
+struct NoHook {
+  __device__ void operator()() const {}
+};
+
+// `after_loads` runs once the element's loads are issued and before they are
+// waited for: loads it issues (the smoother's inverse block) then overlap the
+// evaluation instead of delaying it.
+template <typename T, int D, int P, class Hook = NoHook>
 __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const TabT<T>& tab, int E,
                                                  const T* __restrict__ x, const T* __restrict__ b,
-                                                 int mode, Work<T, D, P>& w) {
+                                                 int mode, Work<T, D, P>& w, Hook after_loads = Hook()) {
   using S = Sz<D, P>;
   constexpr int M = S::M, NQ = S::NQ, MT = S::MT, NB = S::NB, NFS = S::NFS, NSLOT = S::NSLOT;
   using W = Work<T, D, P>;
@@ -202,8 +209,7 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
     for (int q = 0; q < XQ; ++q) {
       const int i = lane + q * WG;
       const int e = se[sl] >= 0 ? se[sl] : E;          // in-bounds address either way
-      const T v = x[(size_t)e * NB + (i < NB ? i : 0)];
-      xr[sl][q] = (i < NB && se[sl] >= 0) ? v : (T)0;
+      xr[sl][q] = x[(size_t)e * NB + (i < NB ? i : 0)];   // masked when staged
     }
   constexpr int MQ = W::STAGE_M ? (NQ * NQ + WG - 1) / WG : 1;
   constexpr int RQ = (MT * NQ + WG - 1) / WG;
@@ -213,8 +219,7 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
 #pragma unroll
       for (int q = 0; q < MQ; ++q) {
         const int t = lane + q * WG;
-        const T v = lev.mmu[(size_t)E * NQ * NQ + (t < NQ * NQ ? t : 0)];
-        mr[q] = t < NQ * NQ ? v : (T)0;
+        mr[q] = lev.mmu[(size_t)E * NQ * NQ + (t < NQ * NQ ? t : 0)];
       }
     }
 #pragma unroll
@@ -223,8 +228,7 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
       for (int q = 0; q < RQ; ++q) {
         const int t = lane + q * WG;
         const int e = se[1 + D + k];
-        const T v = lev.rmu[((size_t)(e >= 0 ? e : E) * D + k) * MT * NQ + (t < MT * NQ ? t : 0)];
-        rv[k][q] = (t < MT * NQ && e >= 0) ? v : (T)0;
+        rv[k][q] = lev.rmu[((size_t)(e >= 0 ? e : E) * D + k) * MT * NQ + (t < MT * NQ ? t : 0)];
       }
   }
   // faces of F = E (fi = 0) and F = E + e_j (fi = 1 + j): type and lifting weights
@@ -259,9 +263,9 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
 #pragma unroll
       for (int q = 0; q < TQ; ++q) {
         const int t = lane + q * WG;
-        const T v = lev.fT[k][(size_t)fid0[k][side] * MT * MT + (t < MT * MT ? t : 0)];
-        tr[k][side][q] = t < MT * MT ? v : (T)0;
+        tr[k][side][q] = lev.fT[k][(size_t)fid0[k][side] * MT * MT + (t < MT * MT ? t : 0)];
       }
+  after_loads();
   T dsv[NSLOT], dsp[NSLOT];
 #pragma unroll
   for (int sl = 0; sl < NSLOT; ++sl) {
@@ -278,7 +282,7 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
 #pragma unroll
     for (int q = 0; q < XQ; ++q) {
       const int i = lane + q * WG;
-      if (i < NB) w.xs[sl][i] = xr[sl][q] * (i >= D * NQ ? dsp[sl] : dsv[sl]);
+      if (i < NB) w.xs[sl][i] = se[sl] >= 0 ? xr[sl][q] * (i >= D * NQ ? dsp[sl] : dsv[sl]) : (T)0;
     }
   if (lev.mmu) {
     if constexpr (W::STAGE_M) {
@@ -293,7 +297,7 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
 #pragma unroll
       for (int q = 0; q < RQ; ++q) {
         const int t = lane + q * WG;
-        if (t < MT * NQ) w.rr[k][t] = rv[k][q];
+        if (t < MT * NQ) w.rr[k][t] = se[1 + D + k] >= 0 ? rv[k][q] : (T)0;
       }
   }
 #pragma unroll
@@ -580,11 +584,12 @@ __global__ __launch_bounds__(WG) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
   const int E = elems[idx];
   const u32x4* Ai = reinterpret_cast<const u32x4*>(inv + (size_t)idx * NB * LY.NBP);
   u32x4 pre[PF];
-  if (lane < RGS) {
+  element_operator<T, D, P>(lev, tab, E, x, b, 0, w, [&]() {
+    if (lane < RGS) {
 #pragma unroll
-    for (int kk = 0; kk < PF; ++kk) pre[kk] = __builtin_nontemporal_load(&Ai[kk * RGS + lane]);
-  }
-  element_operator<T, D, P>(lev, tab, E, x, b, 0, w);
+      for (int kk = 0; kk < PF; ++kk) pre[kk] = __builtin_nontemporal_load(&Ai[kk * RGS + lane]);
+    }
+  });
   if (lane < RGS) {
     const int g = lane % LY.RG, s = lane / LY.RG;
     T y[V];
