@@ -208,6 +208,14 @@ void build_smoother_host(ldgs_ctx* c) {
   }
 }
 
+// stride of the axis-k coordinate in the face numbering of axis k (axis 0
+// fastest; every axis before k has n entries)
+int64_t face_stride(int n, int k) {
+  int64_t s = 1;
+  for (int j = 0; j < k; ++j) s *= n;
+  return s;
+}
+
 template <typename T>
 DevLevel<T> make_view(ldgs_ctx* c, const Level& L, bool with_scale) {
   DevLevel<T> v{};
@@ -218,6 +226,18 @@ DevLevel<T> make_view(ldgs_ctx* c, const Level& L, bool with_scale) {
     if (k < d) {
       const FaceSet& fs = L.faces[k];
       v.nf[k] = fs.nfk;
+      // the kernels derive face types and lifting weights from the position
+      // (intraphase inside, Dirichlet at non-periodic walls); check that the
+      // level matches
+      for (int64_t id = 0; id < fs.count; ++id) {
+        const int64_t f = (id / face_stride(L.n, k)) % fs.nfk;
+        unsigned char want = F_INTRA;
+        if (fs.nfk != L.n && f == 0) want = F_DIR_LO;
+        if (fs.nfk != L.n && f == L.n) want = F_DIR_HI;
+        const double wl = fs.w[2 * id], wr = fs.w[2 * id + 1];
+        if (fs.type[id] != want || wl != (want == F_DIR_HI ? 1.0 : 0.0) || wr != (want == F_DIR_HI ? 0.0 : 1.0))
+          throw Fail{LDGS_E_UNSUPPORTED, "face types other than intraphase and Dirichlet are not supported on the GPU"};
+      }
       unsigned char* ft = dalloc<unsigned char>(c, fs.count);
       HIPCHK(hipMemcpy(ft, fs.type.data(), fs.count, hipMemcpyHostToDevice));
       v.ftype[k] = ft;

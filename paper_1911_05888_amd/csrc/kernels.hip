@@ -154,39 +154,50 @@ struct Work {
   T fwl[S::NFS][D][2], fwr[S::NFS][D][2];
 };
 
-// Evaluates (A x)_E (mode 1) or b_E - (A x)_E (mode 0) into w.res.
-// Operators of the diagonally scaled system D A D when lev.dscale is set.
-struct NoHook {
-  __device__ void operator()() const {}
+// Registers of one element's evaluation between issuing its loads and
+// staging them in LDS: the stencil (uniform), the raw loaded values, the face
+// data (uniform).
+template <typename T, int D, int P, int NT>
+struct ElemData {
+  using S = Sz<D, P>;
+  static constexpr int XQ = (S::NB + NT - 1) / NT;
+  static constexpr int MQ = Work<T, D, P>::STAGE_M ? (S::NQ * S::NQ + NT - 1) / NT : 1;
+  static constexpr int RQ = (S::MT * S::NQ + NT - 1) / NT;
+  static constexpr int TQ = (S::MT * S::MT + NT - 1) / NT;
+  int E;
+  int se[S::NSLOT];              // element of each slot, -1 outside a wall
+  int vmask;                     // bit sl set when slot sl exists
+  T xr[S::NSLOT][XQ];
+  T mr[MQ];
+  T rv[D][RQ];
+  T tr[D][2][TQ];
+  T br[XQ];
+  unsigned char fty[S::NFS][D][2];
+  T fwl[S::NFS][D][2], fwr[S::NFS][D][2];
+  T dsv[S::NSLOT], dsp[S::NSLOT];
 };
 
-// `after_loads` runs once the element's loads are issued and before they are
-// waited for: loads it issues (the smoother's inverse block) then overlap the
-// evaluation instead of delaying it.
-template <typename T, int D, int P, class Hook = NoHook>
-__device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const TabT<T>& tab, int E,
-                                                 const T* __restrict__ x, const T* __restrict__ b,
-                                                 int mode, Work<T, D, P>& w, Hook after_loads = Hook()) {
+// Computes the stencil and face data of E and issues every load of the
+// element at once (addresses in bounds; masks are applied when staging).
+template <typename T, int D, int P, int NT>
+__device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, int E, const T* __restrict__ x,
+                                           const T* __restrict__ b, int mode, ElemData<T, D, P, NT>& d, int lane) {
   using S = Sz<D, P>;
-  constexpr int M = S::M, NQ = S::NQ, MT = S::MT, NB = S::NB, NFS = S::NFS, NSLOT = S::NSLOT;
-  using W = Work<T, D, P>;
-  const int lane = threadIdx.x;
-  const int n = lev.n, lgn = lev.lgn;
-  const T hinv = lev.hinv;
-  const T gam = (T)lev.gamma;
-
+  using ED = ElemData<T, D, P, NT>;
+  constexpr int NQ = S::NQ, MT = S::MT, NB = S::NB, NFS = S::NFS, NSLOT = S::NSLOT;
+  constexpr int XQ = ED::XQ, MQ = ED::MQ, RQ = ED::RQ, TQ = ED::TQ;
+    const int n = lev.n, lgn = lev.lgn;
+  d.E = E;
   int c[D];
   coords_of<D>(E, lgn, c);
-  // ---- stencil and face data of E (uniform across the wavefront) ----
-  int se[NSLOT];   // element of each slot, -1 outside a wall
-  se[0] = E;
+  d.se[0] = E;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     int cm[D], cp[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) cm[j] = cp[j] = c[j];
-    se[1 + k] = shift1(cm, k, -1, n, lev.nf[k] == n) ? index_of<D>(cm, lgn) : -1;
-    se[1 + D + k] = shift1(cp, k, +1, n, lev.nf[k] == n) ? index_of<D>(cp, lgn) : -1;
+    d.se[1 + k] = shift1(cm, k, -1, n, lev.nf[k] == n) ? index_of<D>(cm, lgn) : -1;
+    d.se[1 + D + k] = shift1(cp, k, +1, n, lev.nf[k] == n) ? index_of<D>(cp, lgn) : -1;
 #pragma unroll
     for (int q = 0; q < D - 1; ++q) {
       const int kk = q < k ? q : q + 1;
@@ -194,46 +205,37 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
 #pragma unroll
       for (int j = 0; j < D; ++j) cq[j] = c[j];
       const bool ok = shift1(cq, k, +1, n, lev.nf[k] == n) && shift1(cq, kk, -1, n, lev.nf[kk] == n);
-      se[1 + 2 * D + k * (D - 1) + q] = ok ? index_of<D>(cq, lgn) : -1;
+      d.se[1 + 2 * D + k * (D - 1) + q] = ok ? index_of<D>(cq, lgn) : -1;
     }
   }
-  int vmask = 0;
+  d.vmask = 0;
 #pragma unroll
-  for (int sl = 0; sl < NSLOT; ++sl) vmask |= (se[sl] >= 0 ? 1 : 0) << sl;
-  // ---- phase 1: issue every load of the element at once, then stage in LDS ----
-  constexpr int XQ = (NB + WG - 1) / WG;
-  T xr[NSLOT][XQ];
+  for (int sl = 0; sl < NSLOT; ++sl) d.vmask |= (d.se[sl] >= 0 ? 1 : 0) << sl;
 #pragma unroll
   for (int sl = 0; sl < NSLOT; ++sl)
 #pragma unroll
     for (int q = 0; q < XQ; ++q) {
-      const int i = lane + q * WG;
-      const int e = se[sl] >= 0 ? se[sl] : E;          // in-bounds address either way
-      xr[sl][q] = x[(size_t)e * NB + (i < NB ? i : 0)];   // masked when staged
+      const int i = lane + q * NT;
+      const int e = d.se[sl] >= 0 ? d.se[sl] : E;
+      d.xr[sl][q] = x[(size_t)e * NB + (i < NB ? i : 0)];
     }
-  constexpr int MQ = W::STAGE_M ? (NQ * NQ + WG - 1) / WG : 1;
-  constexpr int RQ = (MT * NQ + WG - 1) / WG;
-  T mr[MQ], rv[D][RQ];
   if (lev.mmu) {
-    if constexpr (W::STAGE_M) {
+    if constexpr (Work<T, D, P>::STAGE_M) {
 #pragma unroll
       for (int q = 0; q < MQ; ++q) {
-        const int t = lane + q * WG;
-        mr[q] = lev.mmu[(size_t)E * NQ * NQ + (t < NQ * NQ ? t : 0)];
+        const int t = lane + q * NT;
+        d.mr[q] = lev.mmu[(size_t)E * NQ * NQ + (t < NQ * NQ ? t : 0)];
       }
     }
 #pragma unroll
     for (int k = 0; k < D; ++k)
 #pragma unroll
       for (int q = 0; q < RQ; ++q) {
-        const int t = lane + q * WG;
-        const int e = se[1 + D + k];
-        rv[k][q] = lev.rmu[((size_t)(e >= 0 ? e : E) * D + k) * MT * NQ + (t < MT * NQ ? t : 0)];
+        const int t = lane + q * NT;
+        const int e = d.se[1 + D + k];
+        d.rv[k][q] = lev.rmu[((size_t)(e >= 0 ? e : E) * D + k) * MT * NQ + (t < MT * NQ ? t : 0)];
       }
   }
-  // faces of F = E (fi = 0) and F = E + e_j (fi = 1 + j): type and lifting weights
-  unsigned char fty[NFS][D][2];
-  T fwl_[NFS][D][2], fwr_[NFS][D][2];
   int fid0[D][2];
 #pragma unroll
   for (int fi = 0; fi < NFS; ++fi) {
@@ -245,59 +247,76 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
     for (int k = 0; k < D; ++k)
 #pragma unroll
       for (int side = 0; side < 2; ++side) {
+        // without interphase faces the type and the lifting weights follow
+        // from the position: Dirichlet faces at the walls (weight 1 on their
+        // element), intraphase faces elsewhere, (wL, wR) = (0, 1)
+        const bool per = lev.nf[k] == n;
         int f = cF[k] + side;
-        if (lev.nf[k] == n) f &= n - 1;
-        const int id = face_index<D>(cF, n, lev.nf[k], k, f);
-        fty[fi][k][side] = valid ? lev.ftype[k][id] : (unsigned char)F_NONE;
-        fwl_[fi][k][side] = valid ? lev.fw[k][2 * id] : (T)0;
-        fwr_[fi][k][side] = valid ? lev.fw[k][2 * id + 1] : (T)0;
-        if (fi == 0) fid0[k][side] = id;
+        unsigned char ty = F_INTRA;
+        if (!per && f == 0) ty = F_DIR_LO;
+        if (!per && f == n) ty = F_DIR_HI;
+        if (per) f &= n - 1;
+        d.fty[fi][k][side] = valid ? ty : (unsigned char)F_NONE;
+        d.fwl[fi][k][side] = (valid && ty == F_DIR_HI) ? (T)1 : (T)0;
+        d.fwr[fi][k][side] = (valid && ty != F_DIR_HI) ? (T)1 : (T)0;
+        if (fi == 0) fid0[k][side] = face_index<D>(cF, n, lev.nf[k], k, f);
       }
   }
-  constexpr int TQ = (MT * MT + WG - 1) / WG;
-  T tr[D][2][TQ];
 #pragma unroll
   for (int k = 0; k < D; ++k)
 #pragma unroll
     for (int side = 0; side < 2; ++side)
 #pragma unroll
       for (int q = 0; q < TQ; ++q) {
-        const int t = lane + q * WG;
-        tr[k][side][q] = lev.fT[k][(size_t)fid0[k][side] * MT * MT + (t < MT * MT ? t : 0)];
+        const int t = lane + q * NT;
+        d.tr[k][side][q] = lev.fT[k][(size_t)fid0[k][side] * MT * MT + (t < MT * MT ? t : 0)];
       }
-  after_loads();
-  T dsv[NSLOT], dsp[NSLOT];
 #pragma unroll
-  for (int sl = 0; sl < NSLOT; ++sl) {
-    dsv[sl] = (T)1;
-    dsp[sl] = (T)1;
-    if (lev.dscale) {
-      const int e = se[sl] >= 0 ? se[sl] : E;
-      dsv[sl] = lev.dscale[2 * e];
-      dsp[sl] = lev.dscale[2 * e + 1];
-    }
+  for (int q = 0; q < XQ; ++q) {
+    const int i = lane + q * NT;
+    d.br[q] = (mode == 0) ? b[(size_t)E * NB + (i < NB ? i : 0)] : (T)0;
   }
 #pragma unroll
+  for (int sl = 0; sl < NSLOT; ++sl) {
+    d.dsv[sl] = (T)1;
+    d.dsp[sl] = (T)1;
+    if (lev.dscale) {
+      const int e = d.se[sl] >= 0 ? d.se[sl] : E;
+      d.dsv[sl] = lev.dscale[2 * e];
+      d.dsp[sl] = lev.dscale[2 * e + 1];
+    }
+  }
+}
+
+// Writes the loaded element data to LDS (waits for the loads).
+template <typename T, int D, int P, int NT>
+__device__ __forceinline__ void elem_stage(const DevLevel<T>& lev, const ElemData<T, D, P, NT>& d, Work<T, D, P>& w,
+                                           int lane) {
+  using S = Sz<D, P>;
+  using ED = ElemData<T, D, P, NT>;
+  constexpr int NQ = S::NQ, MT = S::MT, NB = S::NB, NFS = S::NFS, NSLOT = S::NSLOT;
+  constexpr int XQ = ED::XQ, MQ = ED::MQ, RQ = ED::RQ, TQ = ED::TQ;
+  #pragma unroll
   for (int sl = 0; sl < NSLOT; ++sl)
 #pragma unroll
     for (int q = 0; q < XQ; ++q) {
-      const int i = lane + q * WG;
-      if (i < NB) w.xs[sl][i] = se[sl] >= 0 ? xr[sl][q] * (i >= D * NQ ? dsp[sl] : dsv[sl]) : (T)0;
+      const int i = lane + q * NT;
+      if (i < NB) w.xs[sl][i] = d.se[sl] >= 0 ? d.xr[sl][q] * (i >= D * NQ ? d.dsp[sl] : d.dsv[sl]) : (T)0;
     }
   if (lev.mmu) {
-    if constexpr (W::STAGE_M) {
+    if constexpr (Work<T, D, P>::STAGE_M) {
 #pragma unroll
       for (int q = 0; q < MQ; ++q) {
-        const int t = lane + q * WG;
-        if (t < NQ * NQ) w.mm[t] = mr[q];
+        const int t = lane + q * NT;
+        if (t < NQ * NQ) w.mm[t] = d.mr[q];
       }
     }
 #pragma unroll
     for (int k = 0; k < D; ++k)
 #pragma unroll
       for (int q = 0; q < RQ; ++q) {
-        const int t = lane + q * WG;
-        if (t < MT * NQ) w.rr[k][t] = se[1 + D + k] >= 0 ? rv[k][q] : (T)0;
+        const int t = lane + q * NT;
+        if (t < MT * NQ) w.rr[k][t] = d.se[1 + D + k] >= 0 ? d.rv[k][q] : (T)0;
       }
   }
 #pragma unroll
@@ -306,8 +325,8 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
     for (int side = 0; side < 2; ++side)
 #pragma unroll
       for (int q = 0; q < TQ; ++q) {
-        const int t = lane + q * WG;
-        if (t < MT * MT) w.th[side][k][t] = tr[k][side][q];
+        const int t = lane + q * NT;
+        if (t < MT * MT) w.th[side][k][t] = d.tr[k][side][q];
       }
   if (lane == 0) {
 #pragma unroll
@@ -316,17 +335,32 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
       for (int k = 0; k < D; ++k)
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
-          w.ft[fi][k][side] = fty[fi][k][side];
-          w.fwl[fi][k][side] = fwl_[fi][k][side];
-          w.fwr[fi][k][side] = fwr_[fi][k][side];
+          w.ft[fi][k][side] = d.fty[fi][k][side];
+          w.fwl[fi][k][side] = d.fwl[fi][k][side];
+          w.fwr[fi][k][side] = d.fwr[fi][k][side];
         }
   }
   __syncthreads();
+}
+
+// Phases 2-6 on the staged element: (A x)_E (mode 1) or b_E - (A x)_E
+// (mode 0, b_E in bc) into w.res.  Operators of the diagonally scaled system
+// D A D when lev.dscale is set (ds0v, ds0p: the element's scaling).
+template <typename T, int D, int P, int NT>
+__device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<T>& tab, int E, int vmask, int mode,
+                                             const T* bc, T ds0v, T ds0p, Work<T, D, P>& w, int lane) {
+  using S = Sz<D, P>;
+  constexpr int M = S::M, NQ = S::NQ, MT = S::MT, NB = S::NB, NFS = S::NFS;
+  constexpr int XQ = ElemData<T, D, P, NT>::XQ;
+  using W = Work<T, D, P>;
+    const T hinv = lev.hinv;
+  const T gam = (T)lev.gamma;
+  (void)NFS;
   // ---- phase 2: gradient lines g_F = G_k u_i along axis k ----
   // per axis k: F = E (all i), F = E+e_k (all i), F = E+e_j (j != k, component i = j)
   {
     constexpr int PER_K = (3 * D - 1) * MT;
-    for (int u = lane; u < D * PER_K; u += WG) {
+    for (int u = lane; u < D * PER_K; u += NT) {
       const int k = u / PER_K;
       const int r = u % PER_K;
       const int t = r % MT;
@@ -368,7 +402,7 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
   {
     constexpr int NPAIR = D * D;
     constexpr int NS0 = NPAIR * NQ;
-    for (int u = lane; u < NS0 + D * D * MT; u += WG) {
+    for (int u = lane; u < NS0 + D * D * MT; u += NT) {
       if (u < NS0) {
         const int a = u % NQ, pr = u / NQ, i = pr / D, k = pr % D;
         if (lev.gamma && i > k) continue;       // symmetric: filled from (k, i)
@@ -413,9 +447,9 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
   {
     constexpr int NX = 2 * (D + 1) * MT;   // x_E lo/hi
     constexpr int NN = 2 * (D + 1) * MT;   // x_{E-e_k}|hi, x_{E+e_k}|lo
-    constexpr int NT = 2 * D * MT;         // s_E[i][k] lo/hi
-    constexpr int PER_K = NX + NN + NT;
-    for (int u = lane; u < D * PER_K; u += WG) {
+    constexpr int NTR = 2 * D * MT;        // s_E[i][k] lo/hi
+    constexpr int PER_K = NX + NN + NTR;
+    for (int u = lane; u < D * PER_K; u += NT) {
       const int k = u / PER_K, r = u % PER_K;
       const int base_mt = r % MT;
       const int base = compose<M>(base_mt, 0, k), st = stride_of<M>(k);
@@ -447,7 +481,7 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
   }
   __syncthreads();
   // ---- phase 5: face fluxes ----
-  for (int u = lane; u < D * 2 * (D + 1) * MT; u += WG) {
+  for (int u = lane; u < D * 2 * (D + 1) * MT; u += NT) {
     const int tt = u % MT, f = (u / MT) % (D + 1), side = (u / (MT * (D + 1))) % 2, k = u / (2 * MT * (D + 1));
     const unsigned char ty = w.ft[0][k][side];
     const T wL = w.fwl[0][k][side], wR = w.fwr[0][k][side];
@@ -506,7 +540,10 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
   }
   __syncthreads();
   // ---- phase 6: assemble (A x)_E and the residual ----
-  for (int t = lane; t < NB; t += WG) {
+#pragma unroll
+  for (int q = 0; q < XQ; ++q) {
+    const int t = lane + q * NT;
+    if (t >= NB) break;
     const int f = t / NQ, a = t % NQ;
     T acc = 0;
     if (f < D) {
@@ -540,10 +577,29 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
         acc += tab.e0[ak] * w.flux[0][k][D][tt] + tab.e1[ak] * w.flux[1][k][D][tt];
       }
     }
-    if (lev.dscale) acc *= lev.dscale[2 * E + (f == D ? 1 : 0)];
-    w.res[t] = (mode == 0) ? b[(size_t)E * NB + t] - acc : acc;
+    if (lev.dscale) acc *= (f == D ? ds0p : ds0v);
+    w.res[t] = (mode == 0) ? bc[q] - acc : acc;
   }
   __syncthreads();
+}
+
+struct NoHook {
+  __device__ void operator()() const {}
+};
+
+// Evaluates (A x)_E (mode 1) or b_E - (A x)_E (mode 0) into w.res.
+// `after_loads` runs once the element's loads are issued and before they are
+// waited for: loads it issues then overlap the evaluation.
+template <typename T, int D, int P, int NT, class Hook = NoHook>
+__device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const TabT<T>& tab, int E,
+                                                 const T* __restrict__ x, const T* __restrict__ b,
+                                                 int mode, Work<T, D, P>& w, Hook after_loads = Hook()) {
+  ElemData<T, D, P, NT> d;
+  const int lane = threadIdx.x;
+  elem_issue<T, D, P, NT>(lev, E, x, b, mode, d, lane);
+  after_loads();
+  elem_stage<T, D, P, NT>(lev, d, w, lane);
+  elem_compute<T, D, P, NT>(lev, tab, E, d.vmask, mode, d.br, d.dsv[0], d.dsp[0], w, lane);
 }
 
 // 16-byte word of the inverse and entry v of it in the arithmetic type
@@ -568,15 +624,15 @@ __device__ __forceinline__ T inv_entry(const u32x4& raw, int v) {
 // The element's inverse (lane-blocked layout, see inv_layout) is prefetched
 // into registers before the residual is evaluated.
 // ---------------------------------------------------------------------------
-template <typename T, typename TI, int D, int P>
-__global__ __launch_bounds__(WG) void k_smooth_colour(DevLevel<T> lev, TabT<T> tab, const int* __restrict__ elems,
+template <typename T, typename TI, int D, int P, int NT>
+__global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> tab, const int* __restrict__ elems,
                                                       const TI* __restrict__ inv, const T* __restrict__ b,
                                                       T* __restrict__ x) {
   using S = Sz<D, P>;
   constexpr int NB = S::NB;
   constexpr InvLayout LY = inv_layout(NB, (int)sizeof(TI));
   constexpr int V = LY.V, RGS = LY.RG * LY.S, CS = LY.CS;
-  constexpr int PF = CS < 16 ? CS : 16;     // chunks prefetched before the residual
+  constexpr int PF = CS < 16 ? CS : 16;     // chunks requested before the residual is evaluated
   __shared__ Work<T, D, P> w;
   __shared__ T part[LY.S][LY.NBP];
   const int lane = threadIdx.x;
@@ -584,7 +640,7 @@ __global__ __launch_bounds__(WG) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
   const int E = elems[idx];
   const u32x4* Ai = reinterpret_cast<const u32x4*>(inv + (size_t)idx * NB * LY.NBP);
   u32x4 pre[PF];
-  element_operator<T, D, P>(lev, tab, E, x, b, 0, w, [&]() {
+  element_operator<T, D, P, NT>(lev, tab, E, x, b, 0, w, [&]() {
     if (lane < RGS) {
 #pragma unroll
       for (int kk = 0; kk < PF; ++kk) pre[kk] = __builtin_nontemporal_load(&Ai[kk * RGS + lane]);
@@ -606,7 +662,7 @@ __global__ __launch_bounds__(WG) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
     for (int v = 0; v < V; ++v) part[s][g * V + v] = y[v];
   }
   __syncthreads();
-  for (int row = lane; row < NB; row += WG) {
+  for (int row = lane; row < NB; row += NT) {
     T acc = 0;
 #pragma unroll
     for (int s = 0; s < LY.S; ++s) acc += part[s][row];
@@ -614,14 +670,14 @@ __global__ __launch_bounds__(WG) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
   }
 }
 
-template <typename T, int D, int P>
-__global__ __launch_bounds__(WG) void k_residual(DevLevel<T> lev, TabT<T> tab, const T* __restrict__ b,
+template <typename T, int D, int P, int NT>
+__global__ __launch_bounds__(NT) void k_residual(DevLevel<T> lev, TabT<T> tab, const T* __restrict__ b,
                                                  const T* __restrict__ x, T* __restrict__ out, int mode) {
   using S = Sz<D, P>;
   __shared__ Work<T, D, P> w;
   const int E = blockIdx.x;
-  element_operator<T, D, P>(lev, tab, E, x, b, mode, w);
-  for (int t = threadIdx.x; t < S::NB; t += WG) out[(size_t)E * S::NB + t] = w.res[t];
+  element_operator<T, D, P, NT>(lev, tab, E, x, b, mode, w);
+  for (int t = threadIdx.x; t < S::NB; t += NT) out[(size_t)E * S::NB + t] = w.res[t];
 }
 
 // product of 1D injection entries: (P_o)[af][ac] for child offset bits o
@@ -639,12 +695,12 @@ __device__ __forceinline__ T pfull(const TabT<T>& tab, int o, int af, int ac) {
 }
 
 // r_c = I^T (b - A x): one work-group per coarse element, looping over children.
-template <typename T, int D, int P>
-__global__ __launch_bounds__(WG) void k_residual_restrict(DevLevel<T> lev, TabT<T> tab, const T* __restrict__ b,
+template <typename T, int D, int P, int NT>
+__global__ __launch_bounds__(NT) void k_residual_restrict(DevLevel<T> lev, TabT<T> tab, const T* __restrict__ b,
                                                           const T* __restrict__ x, T* __restrict__ rc) {
   using S = Sz<D, P>;
   constexpr int M = S::M, NQ = S::NQ, NB = S::NB;
-  constexpr int PER = (NB + WG - 1) / WG;
+  constexpr int PER = (NB + NT - 1) / NT;
   __shared__ Work<T, D, P> w;
   const int lgc = lev.lgn - 1;
   const int C = blockIdx.x;
@@ -658,10 +714,10 @@ __global__ __launch_bounds__(WG) void k_residual_restrict(DevLevel<T> lev, TabT<
 #pragma unroll
     for (int j = 0; j < D; ++j) cf[j] = 2 * cc[j] + ((o >> j) & 1);
     const int E = index_of<D>(cf, lev.lgn);
-    element_operator<T, D, P>(lev, tab, E, x, b, 0, w);
+    element_operator<T, D, P, NT>(lev, tab, E, x, b, 0, w);
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int t = threadIdx.x + q * WG;
+      const int t = threadIdx.x + q * NT;
       if (t < NB) {
         const int f = t / NQ, ac = t % NQ;
         T s = 0;
@@ -673,7 +729,7 @@ __global__ __launch_bounds__(WG) void k_residual_restrict(DevLevel<T> lev, TabT<
   }
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int t = threadIdx.x + q * WG;
+    const int t = threadIdx.x + q * NT;
     if (t < NB) rc[(size_t)C * NB + t] = acc[q];
   }
 }
@@ -815,23 +871,36 @@ static int dispatch(int dim, int p, F&& f) {
   return 0;
 }
 
+// threads per work-group for the element kernels: one wavefront per element
+// when the launch has enough elements to fill the chip, several wavefronts
+// per element on small (coarse) grids, where the latency of one element's
+// evaluation sets the time of the launch
+constexpr int SMALL_GRID = 4096;
+constexpr int NT_SMALL = 256;
+template <class F>
+static void dispatch_nt(int64_t nelems, F&& f) {
+  if (nelems >= SMALL_GRID) f(std::integral_constant<int, WG>{});
+  else f(std::integral_constant<int, NT_SMALL>{});
+}
+
 template <typename T>
 int launch_smooth_colour(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const int* elems,
                          int64_t nelems, const void* inv, int inv_kind, const T* b, T* x) {
   if (nelems <= 0) return 0;
+  const unsigned grid = (unsigned)nelems;
   hipStream_t st = (hipStream_t)c.stream;
   const TabT<T> tt = tab_of<T>(tab);
   if constexpr (sizeof(T) == 8) {
     if (inv_kind != 0) return 2;
-    if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_smooth_colour<T, double, D_, P_>), dim3((unsigned)nelems), dim3(WG), 0, st,
-                                                  lev, tt, elems, (const double*)inv, b, x); })) return 2;
+    if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; dispatch_nt(nelems, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, double, D_, P_, NT_>), dim3(grid), dim3(NT_), 0, st,
+                                                  lev, tt, elems, (const double*)inv, b, x); }); })) return 2;
   } else {
     if (inv_kind == 1) {
-      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_smooth_colour<T, float, D_, P_>), dim3((unsigned)nelems), dim3(WG), 0, st,
-                                                    lev, tt, elems, (const float*)inv, b, x); })) return 2;
+      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; dispatch_nt(nelems, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, float, D_, P_, NT_>), dim3(grid), dim3(NT_), 0, st,
+                                                    lev, tt, elems, (const float*)inv, b, x); }); })) return 2;
     } else if (inv_kind == 2) {
-      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_smooth_colour<T, uint16_t, D_, P_>), dim3((unsigned)nelems), dim3(WG), 0, st,
-                                                    lev, tt, elems, (const uint16_t*)inv, b, x); })) return 2;
+      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; dispatch_nt(nelems, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, uint16_t, D_, P_, NT_>), dim3(grid), dim3(NT_), 0, st,
+                                                    lev, tt, elems, (const uint16_t*)inv, b, x); }); })) return 2;
     } else {
       return 2;
     }
@@ -846,8 +915,8 @@ int launch_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab
   for (int j = 0; j < c.dim; ++j) NE *= lev.n;
   hipStream_t st = (hipStream_t)c.stream;
   const TabT<T> tt = tab_of<T>(tab);
-  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_residual<T, D_, P_>), dim3((unsigned)NE), dim3(WG), 0, st,
-                                                lev, tt, b, x, out, mode); })) return 2;
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; dispatch_nt(NE, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual<T, D_, P_, NT_>), dim3((unsigned)NE), dim3(NT_), 0, st,
+                                                lev, tt, b, x, out, mode); }); })) return 2;
   return hip_ok();
 }
 
@@ -858,8 +927,8 @@ int launch_residual_restrict(const LaunchCfg& c, const DevLevel<T>& lev, const T
   for (int j = 0; j < c.dim; ++j) NC *= lev.n / 2;
   hipStream_t st = (hipStream_t)c.stream;
   const TabT<T> tt = tab_of<T>(tab);
-  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_residual_restrict<T, D_, P_>), dim3((unsigned)NC), dim3(WG), 0, st,
-                                                lev, tt, b, x, rc); })) return 2;
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; dispatch_nt(NC, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual_restrict<T, D_, P_, NT_>), dim3((unsigned)NC), dim3(NT_), 0, st,
+                                                lev, tt, b, x, rc); }); })) return 2;
   return hip_ok();
 }
 

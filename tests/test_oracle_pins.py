@@ -342,3 +342,30 @@ def test_s5_reading_printed_form_degrades_velocity_order(monkeypatch):
         errs.append(solution_errors(prob, H.project_kernel(x), H.k0))
     order = math.log2(errs[0]["u_l2"] / errs[1]["u_l2"])
     assert order < 2.5, order
+
+
+# ---------------------------------------------------------------- scaling --
+@pytest.mark.parametrize("p", [1, 2])
+def test_operator_h_scaling_on_periodic_grids(p):
+    """With the orthonormal basis the blocks of A scale as h^-2 (viscous),
+    h^-1 (gradient) and h^0 (pressure penalty tau h / mu against face masses
+    of order h^-1), and the periodic constant-viscosity operator is translation
+    invariant: A(h/2) on a field repeated twice equals S A(h) S repeated, with
+    S = 2 on velocity and 1 on pressure.  A wrong power of h anywhere in the
+    assembly breaks this."""
+    def tile(v, ns, nbig, nb):
+        V = v.reshape(ns, ns, nb)
+        r = nbig // ns
+        return np.tile(V, (r, r, 1)).ravel()
+    Hs = build_hierarchy(Problem(name="a", dim=2, n=8, p=p, gamma=1, bc=("periodic", "periodic")))
+    Hb = build_hierarchy(Problem(name="b", dim=2, n=16, p=p, gamma=1, bc=("periodic", "periodic")))
+    nb, nvel = Hs.fine.nb, 2 * Hs.fine.nq
+
+    def S(v, f):
+        w = v.reshape(-1, nb).copy()
+        w[:, :nvel] *= f
+        return w.ravel()
+    x = np.random.default_rng(0).standard_normal(Hs.fine.A.shape[0])
+    lhs = Hb.fine.A @ tile(S(x, 0.5), 8, 16, nb)
+    rhs = tile(S(Hs.fine.A @ x, 2.0), 8, 16, nb)
+    assert np.abs(lhs - rhs).max() <= 1e-13 * np.abs(rhs).max()
