@@ -163,8 +163,14 @@ def main():
     achieved = bytes_launch / avg_s / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
+        # counters are valid only for the kernel source they were measured on
+        import hashlib
         with open(TRAFFIC_FILE) as fh:
-            traffic = json.load(fh).get("bytes_per_launch")
+            tj = json.load(fh)
+        with open(os.path.join(ROOT, "paper_1911_05888_amd", "csrc", "kernels.hip"), "rb") as fh:
+            sha = hashlib.sha1(fh.read()).hexdigest()
+        if tj.get("kernels_hip_sha1") == sha:
+            traffic = tj.get("bytes_per_launch")
 
     extras = {}
     if not args.no_extras:
@@ -205,7 +211,7 @@ def main():
                     setup_s=t_setup, **extras),
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=achieved / HBM_PEAK_GBS, traffic=traffic,
-                      kernel="k_smooth_colour<float,float,2,3> (finest level)",
+                      kernel="k_smooth_colour<float,float,2,3,64> (finest level)",
                       avg_launch_us=avg_s * 1e6, algorithmic_bytes_per_launch=bytes_launch,
                       launches=k_launches),
     )
