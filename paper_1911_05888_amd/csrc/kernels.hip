@@ -138,20 +138,20 @@ template <typename T, int D, int P>
 struct Work {
   using S = Sz<D, P>;
   static constexpr bool STAGE_M = (size_t)S::NQ * S::NQ * sizeof(T) <= 8192;
-  T xs[S::NSLOT][S::NB];
-  T mm[STAGE_M ? S::NQ * S::NQ : 1];   // M_mu of E
-  T rr[D][S::MT * S::NQ];             // R_k = (e0^T)_k M_mu of E+e_k
-  T th[2][D][S::MT * S::MT];          // penalty matrices of E's low/high faces
-  T g[S::NFS][D * D][S::NQ];          // G_k u_i at E and E+e_k (needed components)
-  T s0[D * D][S::NQ];                 // s_ik at E
-  T trx[2][D][D + 1][S::MT];          // traces of x_E: [lo/hi][axis][field][t]
-  T trn[2][D][D + 1][S::MT];          // [0]: x_{E-e_k}|hi, [1]: x_{E+e_k}|lo
-  T trs[2][D][D][S::MT];              // s_E[i][k] lo/hi along k
-  T trr[D][D][S::MT];                 // s_{E+e_k}[i][k] at its low face along k
-  T flux[2][D][D + 1][S::MT];         // coefficients of e0 (lo) and e1 (hi) per axis/field
-  T res[S::NB];
+  alignas(16) T xs[S::NSLOT][S::NB];
+  alignas(16) T mm[STAGE_M ? S::NQ * S::NQ : 1];   // M_mu of E
+  alignas(16) T rr[D][S::MT * S::NQ];             // R_k = (e0^T)_k M_mu of E+e_k
+  alignas(16) T th[2][D][S::MT * S::MT];          // penalty matrices of E's low/high faces
+  alignas(16) T g[S::NFS][D * D][S::NQ];          // G_k u_i at E and E+e_k (needed components)
+  alignas(16) T s0[D * D][S::NQ];                 // s_ik at E
+  alignas(16) T trx[2][D][D + 1][S::MT];          // traces of x_E: [lo/hi][axis][field][t]
+  alignas(16) T trn[2][D][D + 1][S::MT];          // [0]: x_{E-e_k}|hi, [1]: x_{E+e_k}|lo
+  alignas(16) T trs[2][D][D][S::MT];              // s_E[i][k] lo/hi along k
+  alignas(16) T trr[D][D][S::MT];                 // s_{E+e_k}[i][k] at its low face along k
+  alignas(16) T flux[2][D][D + 1][S::MT];         // coefficients of e0 (lo) and e1 (hi) per axis/field
+  alignas(16) T res[S::NB];
   unsigned char ft[S::NFS][D][2];
-  T fwl[S::NFS][D][2], fwr[S::NFS][D][2];
+  alignas(16) T fwl[S::NFS][D][2], fwr[S::NFS][D][2];
 };
 
 // Registers of one element's evaluation between issuing its loads and
@@ -414,7 +414,7 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
           if constexpr (W::STAGE_M) Mm = w.mm;
           else Mm = lev.mmu + (size_t)E * NQ * NQ;
 #pragma unroll 8
-          for (int bb = 0; bb < NQ; ++bb) v += Mm[bb * NQ + a] * (g1[bb] + gam * g2[bb]);
+          for (int bb = 0; bb < NQ; ++bb) v += Mm[a * NQ + bb] * (g1[bb] + gam * g2[bb]);   // M_mu symmetric
         } else {
           v = lev.mu_const * (g1[a] + gam * g2[a]);
         }
@@ -583,6 +583,16 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
   __syncthreads();
 }
 
+// Work-groups are dispatched round-robin over the 8 XCDs (block b runs on
+// XCD b mod 8).  Give each XCD a contiguous range of the launch's elements so
+// that neighbours in a stencil are read through the same L2.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+  const int q = G / NXCD, r = G % NXCD;
+  const int x = b % NXCD, j = b / NXCD;
+  return x * q + (x < r ? x : r) + j;
+}
+
 struct NoHook {
   __device__ void operator()() const {}
 };
@@ -636,7 +646,7 @@ __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
   __shared__ Work<T, D, P> w;
   __shared__ T part[LY.S][LY.NBP];
   const int lane = threadIdx.x;
-  const int idx = blockIdx.x;
+  const int idx = xcd_remap(blockIdx.x, gridDim.x);
   const int E = elems[idx];
   const u32x4* Ai = reinterpret_cast<const u32x4*>(inv + (size_t)idx * NB * LY.NBP);
   u32x4 pre[PF];
@@ -675,7 +685,7 @@ __global__ __launch_bounds__(NT) void k_residual(DevLevel<T> lev, TabT<T> tab, c
                                                  const T* __restrict__ x, T* __restrict__ out, int mode) {
   using S = Sz<D, P>;
   __shared__ Work<T, D, P> w;
-  const int E = blockIdx.x;
+  const int E = xcd_remap(blockIdx.x, gridDim.x);
   element_operator<T, D, P, NT>(lev, tab, E, x, b, mode, w);
   for (int t = threadIdx.x; t < S::NB; t += NT) out[(size_t)E * S::NB + t] = w.res[t];
 }
@@ -703,7 +713,7 @@ __global__ __launch_bounds__(NT) void k_residual_restrict(DevLevel<T> lev, TabT<
   constexpr int PER = (NB + NT - 1) / NT;
   __shared__ Work<T, D, P> w;
   const int lgc = lev.lgn - 1;
-  const int C = blockIdx.x;
+  const int C = xcd_remap(blockIdx.x, gridDim.x);
   int cc[D];
   coords_of<D>(C, lgc, cc);
   T acc[PER];
