@@ -642,7 +642,9 @@ __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
   constexpr int NB = S::NB;
   constexpr InvLayout LY = inv_layout(NB, (int)sizeof(TI));
   constexpr int V = LY.V, RGS = LY.RG * LY.S, CS = LY.CS;
-  constexpr int PF = CS < 16 ? CS : 16;     // chunks requested before the residual is evaluated
+  // chunks requested before the residual is evaluated: all of a bf16 block, half
+  // of an FP32 one (the rest is loaded in the product; fewer registers held)
+  constexpr int PF = sizeof(TI) == 2 ? (CS < 16 ? CS : 16) : (CS / 2 > 0 ? CS / 2 : 1);
   __shared__ Work<T, D, P> w;
   __shared__ T part[LY.S][LY.NBP];
   const int lane = threadIdx.x;
@@ -886,7 +888,7 @@ static int dispatch(int dim, int p, F&& f) {
 // per element on small (coarse) grids, where the latency of one element's
 // evaluation sets the time of the launch
 constexpr int SMALL_GRID = 4096;
-constexpr int NT_SMALL = 256;
+constexpr int NT_SMALL = 128;
 template <class F>
 static void dispatch_nt(int64_t nelems, F&& f) {
   if (nelems >= SMALL_GRID) f(std::integral_constant<int, WG>{});
