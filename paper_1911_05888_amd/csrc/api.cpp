@@ -173,7 +173,7 @@ void validate(const ldgs_problem& P) {
   }
   if (P.levelset_kind != LDGS_LEVELSET_NONE) {
     if (P.levelset_kind != LDGS_LEVELSET_BOX) throw Fail{LDGS_E_UNSUPPORTED, "curved level sets"};
-    throw Fail{LDGS_E_UNSUPPORTED, "interphase faces are not supported by the GPU smoother yet"};
+    if (!P.host_only && P.dim != 2) throw Fail{LDGS_E_UNSUPPORTED, "interphase faces are supported in 2D"};
   }
   if (P.delta > 0.0) {
     if (P.rho.kind != LDGS_FIELD_CONST || P.mu.kind != LDGS_FIELD_CONST)
@@ -220,16 +220,23 @@ template <typename T>
 DevLevel<T> make_view(ldgs_ctx* c, const Level& L, bool with_scale) {
   DevLevel<T> v{};
   const int d = c->g.d, mt = c->g.mt, nq = c->g.nq;
+  bool iface = false;
+  for (int k = 0; k < d; ++k)
+    for (unsigned char t : L.faces[k].type) iface = iface || t == F_INTER;
+  v.iface = iface ? 1 : 0;
   v.n = L.n;
   v.hinv = (T)(1.0 / L.h);
   for (int k = 0; k < 3; ++k) {
     if (k < d) {
       const FaceSet& fs = L.faces[k];
       v.nf[k] = fs.nfk;
-      // the kernels derive face types and lifting weights from the position
-      // (intraphase inside, Dirichlet at non-periodic walls); check that the
-      // level matches
-      for (int64_t id = 0; id < fs.count; ++id) {
+      // without interphase faces the kernels derive face types and lifting
+      // weights from the position (intraphase inside, Dirichlet at
+      // non-periodic walls); check that the level matches
+      if (iface) {
+        // interphase faces: 2D only (extended stencil), data from the tables
+        if (d != 2) throw Fail{LDGS_E_UNSUPPORTED, "interphase faces are supported in 2D"};
+      } else for (int64_t id = 0; id < fs.count; ++id) {
         const int64_t f = (id / face_stride(L.n, k)) % fs.nfk;
         unsigned char want = F_INTRA;
         if (fs.nfk != L.n && f == 0) want = F_DIR_LO;
@@ -255,25 +262,31 @@ DevLevel<T> make_view(ldgs_ctx* c, const Level& L, bool with_scale) {
   v.lgn = lg;
   v.mmu = L.mu_is_const ? nullptr : upload<T>(c, L.mmu);
   v.rmu = nullptr;
+  v.rmuh = nullptr;
   if (!L.mu_is_const) {
-    // R_k = (e0^T)_k M_mu: low-face trace rows of the mass block along axis k
+    // (e0^T)_k M_mu and (e1^T)_k M_mu: low- and high-face trace rows of the
+    // mass block along axis k
     const int M = c->g.p + 1;
-    std::vector<double> R((size_t)L.NE * d * mt * nq, 0.0);
-    for (int64_t e = 0; e < L.NE; ++e) {
-      const double* Me = L.mmu.data() + (size_t)e * nq * nq;
-      for (int k = 0; k < d; ++k) {
-        int lo = 1;
-        for (int j = 0; j < k; ++j) lo *= M;
-        double* Rk = R.data() + ((size_t)e * d + k) * mt * nq;
-        for (int t = 0; t < mt; ++t)
-          for (int cc = 0; cc < M; ++cc) {
-            const int a = t % lo + lo * cc + lo * M * (t / lo);
-            const double w = c->tab.e0[cc];
-            for (int b = 0; b < nq; ++b) Rk[t * nq + b] += w * Me[a * nq + b];
-          }
+    auto rows = [&](const double* ev) {
+      std::vector<double> R((size_t)L.NE * d * mt * nq, 0.0);
+      for (int64_t e = 0; e < L.NE; ++e) {
+        const double* Me = L.mmu.data() + (size_t)e * nq * nq;
+        for (int k = 0; k < d; ++k) {
+          int lo = 1;
+          for (int j = 0; j < k; ++j) lo *= M;
+          double* Rk = R.data() + ((size_t)e * d + k) * mt * nq;
+          for (int t = 0; t < mt; ++t)
+            for (int cc = 0; cc < M; ++cc) {
+              const int a = t % lo + lo * cc + lo * M * (t / lo);
+              const double w = ev[cc];
+              for (int b = 0; b < nq; ++b) Rk[t * nq + b] += w * Me[a * nq + b];
+            }
+        }
       }
-    }
-    v.rmu = upload<T>(c, R);
+      return R;
+    };
+    v.rmu = upload<T>(c, rows(c->tab.e0));
+    if (v.iface) v.rmuh = upload<T>(c, rows(c->tab.e1));
   }
   v.mu_const = (T)L.mu_c;
   v.rho_delta = (T)L.rho_delta;
@@ -1137,7 +1150,7 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxi
         hist.push_back(rel);
         if (use_learned && it == 2) rho_plain = std::sqrt(hist[2] / hist[0]);
         if (!std::isfinite(rel)) { st = LDGS_E_NONFINITE; break; }
-        if (rel > 1e3 * hist[0]) { st = LDGS_E_NOT_CONVERGED; break; }
+        if (rel > 1e10 * hist[0]) { st = LDGS_E_NOT_CONVERGED; break; }   // blow-up (a first cycle may raise the residual transiently)
       }
     } else if (outer == LDGS_FGMRES) {
       const int m = fgmres_m > 0 ? fgmres_m : 30;

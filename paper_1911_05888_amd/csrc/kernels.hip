@@ -31,15 +31,19 @@ struct Pow { static constexpr int v = B * Pow<B, E - 1>::v; };
 template <int B>
 struct Pow<B, 0> { static constexpr int v = 1; };
 
-template <int D, int P>
+template <int D, int P, bool IF = false>
 struct Sz {
   static constexpr int M = P + 1;
   static constexpr int NQ = Pow<M, D>::v;
   static constexpr int MT = Pow<M, D - 1>::v;
   static constexpr int NB = (D + 1) * NQ;
-  // stencil slots: E, E-e_k, E+e_k, E+e_k-e_j (j != k)
-  static constexpr int NSLOT = 1 + 2 * D + D * (D - 1);
-  static constexpr int NFS = 1 + D;   // elements whose gradient is needed: E, E+e_k
+  // stencil slots: E, E-e_k, E+e_k, E+e_k-e_j (j != k); with interphase
+  // faces (IF) also E-2e_k, E+2e_k, E-e_k-e_j, E+e_k+e_j (k < j)
+  static constexpr int NBASE = 1 + 2 * D + D * (D - 1);
+  static constexpr int NPAIR = D * (D - 1) / 2;
+  static constexpr int NSLOT = IF ? NBASE + 2 * D + 2 * NPAIR : NBASE;
+  // elements whose gradient is needed: E, E+e_k, and with IF E-e_k
+  static constexpr int NFS = IF ? 1 + 2 * D : 1 + D;
 };
 
 constexpr int WG = 64;
@@ -125,29 +129,67 @@ __device__ __forceinline__ int face_index(const int* c, int n, int nfk, int k, i
   return e;
 }
 
-// stencil slot of F - e_k for F = E (fi = 0) or F = E + e_{fi-1}
+// stencil slots (see Sz)
+template <int D>
+__device__ __forceinline__ int pair_of(int a, int b) {   // a != b
+  const int lo = a < b ? a : b, hi = a < b ? b : a;
+  return D == 2 ? 0 : (lo == 0 ? hi - 1 : 2);
+}
+template <int D>
+struct Slot {
+  static constexpr int NBASE = 1 + 2 * D + D * (D - 1), NPAIR = D * (D - 1) / 2;
+  __device__ static int m(int k) { return 1 + k; }                                       // E - e_k
+  __device__ static int p(int k) { return 1 + D + k; }                                   // E + e_k
+  __device__ static int pm(int k, int j) { return 1 + 2 * D + k * (D - 1) + (j < k ? j : j - 1); }  // E+e_k-e_j
+  __device__ static int mm2(int k) { return NBASE + k; }                                 // E - 2e_k
+  __device__ static int pp2(int k) { return NBASE + D + k; }                             // E + 2e_k
+  __device__ static int mm(int k, int j) { return NBASE + 2 * D + pair_of<D>(k, j); }     // E-e_k-e_j
+  __device__ static int pp(int k, int j) { return NBASE + 2 * D + NPAIR + pair_of<D>(k, j); }  // E+e_k+e_j
+};
+// gradient element fi: E (0), E + e_j (1 + j), E - e_j (1 + D + j)
+template <int D>
+__device__ __forceinline__ int f_slot(int fi) {
+  return fi == 0 ? 0 : (fi <= D ? Slot<D>::p(fi - 1) : Slot<D>::m(fi - 1 - D));
+}
+// slot of F - e_k and of F + e_k for gradient element fi
 template <int D>
 __device__ __forceinline__ int low_slot(int fi, int k) {
-  if (fi == 0) return 1 + k;
-  if (k == fi - 1) return 0;
-  return 1 + 2 * D + (fi - 1) * (D - 1) + (k < fi - 1 ? k : k - 1);
+  if (fi == 0) return Slot<D>::m(k);
+  if (fi <= D) {
+    const int j = fi - 1;
+    return k == j ? 0 : Slot<D>::pm(j, k);
+  }
+  const int j = fi - 1 - D;
+  return k == j ? Slot<D>::mm2(j) : Slot<D>::mm(j, k);
+}
+template <int D>
+__device__ __forceinline__ int high_slot(int fi, int k) {
+  if (fi == 0) return Slot<D>::p(k);
+  if (fi <= D) {
+    const int j = fi - 1;
+    return k == j ? Slot<D>::pp2(j) : Slot<D>::pp(j, k);
+  }
+  const int j = fi - 1 - D;
+  return k == j ? 0 : Slot<D>::pm(k, j);
 }
 
 // shared-memory work area of one element evaluation
-template <typename T, int D, int P>
+template <typename T, int D, int P, bool IF = false>
 struct Work {
-  using S = Sz<D, P>;
+  using S = Sz<D, P, IF>;
   static constexpr bool STAGE_M = (size_t)S::NQ * S::NQ * sizeof(T) <= 8192;
   alignas(16) T xs[S::NSLOT][S::NB];
   alignas(16) T mm[STAGE_M ? S::NQ * S::NQ : 1];   // M_mu of E
   alignas(16) T rr[D][S::MT * S::NQ];             // R_k = (e0^T)_k M_mu of E+e_k
   alignas(16) T th[2][D][S::MT * S::MT];          // penalty matrices of E's low/high faces
-  alignas(16) T g[S::NFS][D * D][S::NQ];          // G_k u_i at E and E+e_k (needed components)
+  alignas(16) T g[S::NFS][D * D][S::NQ];          // G_k u_i at E, E+e_k (and E-e_k) (needed components)
   alignas(16) T s0[D * D][S::NQ];                 // s_ik at E
   alignas(16) T trx[2][D][D + 1][S::MT];          // traces of x_E: [lo/hi][axis][field][t]
   alignas(16) T trn[2][D][D + 1][S::MT];          // [0]: x_{E-e_k}|hi, [1]: x_{E+e_k}|lo
   alignas(16) T trs[2][D][D][S::MT];              // s_E[i][k] lo/hi along k
   alignas(16) T trr[D][D][S::MT];                 // s_{E+e_k}[i][k] at its low face along k
+  alignas(16) T rrh[IF ? D : 1][S::MT * S::NQ];   // (IF) (e1^T)_k M_mu of E-e_k
+  alignas(16) T trrh[IF ? D : 1][D][S::MT];       // (IF) s_{E-e_k}[i][k] at its high face along k
   alignas(16) T flux[2][D][D + 1][S::MT];         // coefficients of e0 (lo) and e1 (hi) per axis/field
   alignas(16) T res[S::NB];
   unsigned char ft[S::NFS][D][2];
@@ -157,11 +199,11 @@ struct Work {
 // Registers of one element's evaluation between issuing its loads and
 // staging them in LDS: the stencil (uniform), the raw loaded values, the face
 // data (uniform).
-template <typename T, int D, int P, int NT>
+template <typename T, int D, int P, int NT, bool IF = false>
 struct ElemData {
-  using S = Sz<D, P>;
+  using S = Sz<D, P, IF>;
   static constexpr int XQ = (S::NB + NT - 1) / NT;
-  static constexpr int MQ = Work<T, D, P>::STAGE_M ? (S::NQ * S::NQ + NT - 1) / NT : 1;
+  static constexpr int MQ = Work<T, D, P, IF>::STAGE_M ? (S::NQ * S::NQ + NT - 1) / NT : 1;
   static constexpr int RQ = (S::MT * S::NQ + NT - 1) / NT;
   static constexpr int TQ = (S::MT * S::MT + NT - 1) / NT;
   int E;
@@ -170,6 +212,7 @@ struct ElemData {
   T xr[S::NSLOT][XQ];
   T mr[MQ];
   T rv[D][RQ];
+  T rvh[IF ? D : 1][RQ];
   T tr[D][2][TQ];
   T br[XQ];
   unsigned char fty[S::NFS][D][2];
@@ -179,11 +222,12 @@ struct ElemData {
 
 // Computes the stencil and face data of E and issues every load of the
 // element at once (addresses in bounds; masks are applied when staging).
-template <typename T, int D, int P, int NT>
+template <typename T, int D, int P, int NT, bool IF>
 __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, int E, const T* __restrict__ x,
-                                           const T* __restrict__ b, int mode, ElemData<T, D, P, NT>& d, int lane) {
-  using S = Sz<D, P>;
-  using ED = ElemData<T, D, P, NT>;
+                                           const T* __restrict__ b, int mode, ElemData<T, D, P, NT, IF>& d,
+                                           int lane) {
+  using S = Sz<D, P, IF>;
+  using ED = ElemData<T, D, P, NT, IF>;
   constexpr int NQ = S::NQ, MT = S::MT, NB = S::NB, NFS = S::NFS, NSLOT = S::NSLOT;
   constexpr int XQ = ED::XQ, MQ = ED::MQ, RQ = ED::RQ, TQ = ED::TQ;
     const int n = lev.n, lgn = lev.lgn;
@@ -208,6 +252,30 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, int E, const 
       d.se[1 + 2 * D + k * (D - 1) + q] = ok ? index_of<D>(cq, lgn) : -1;
     }
   }
+  if constexpr (IF) {
+    // two-step neighbours reached by the interphase liftings
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      int cm[D], cp[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) cm[j] = cp[j] = c[j];
+      const bool per = lev.nf[k] == n;
+      const bool okm = shift1(cm, k, -1, n, per) && shift1(cm, k, -1, n, per);
+      const bool okp = shift1(cp, k, +1, n, per) && shift1(cp, k, +1, n, per);
+      d.se[Slot<D>::mm2(k)] = okm ? index_of<D>(cm, lgn) : -1;
+      d.se[Slot<D>::pp2(k)] = okp ? index_of<D>(cp, lgn) : -1;
+#pragma unroll
+      for (int j = k + 1; j < D; ++j) {
+        int cmm[D], cpp[D];
+#pragma unroll
+        for (int l = 0; l < D; ++l) cmm[l] = cpp[l] = c[l];
+        const bool okmm = shift1(cmm, k, -1, n, per) && shift1(cmm, j, -1, n, lev.nf[j] == n);
+        const bool okpp = shift1(cpp, k, +1, n, per) && shift1(cpp, j, +1, n, lev.nf[j] == n);
+        d.se[Slot<D>::mm(k, j)] = okmm ? index_of<D>(cmm, lgn) : -1;
+        d.se[Slot<D>::pp(k, j)] = okpp ? index_of<D>(cpp, lgn) : -1;
+      }
+    }
+  }
   d.vmask = 0;
 #pragma unroll
   for (int sl = 0; sl < NSLOT; ++sl) d.vmask |= (d.se[sl] >= 0 ? 1 : 0) << sl;
@@ -220,12 +288,22 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, int E, const 
       d.xr[sl][q] = x[(size_t)e * NB + (i < NB ? i : 0)];
     }
   if (lev.mmu) {
-    if constexpr (Work<T, D, P>::STAGE_M) {
+    if constexpr (Work<T, D, P, IF>::STAGE_M) {
 #pragma unroll
       for (int q = 0; q < MQ; ++q) {
         const int t = lane + q * NT;
         d.mr[q] = lev.mmu[(size_t)E * NQ * NQ + (t < NQ * NQ ? t : 0)];
       }
+    }
+    if constexpr (IF) {
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) {
+          const int t = lane + q * NT;
+          const int e = d.se[1 + k];
+          d.rvh[k][q] = lev.rmuh[((size_t)(e >= 0 ? e : E) * D + k) * MT * NQ + (t < MT * NQ ? t : 0)];
+        }
     }
 #pragma unroll
     for (int k = 0; k < D; ++k)
@@ -242,24 +320,34 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, int E, const 
     int cF[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) cF[j] = c[j];
-    const bool valid = (fi == 0) || shift1(cF, fi - 1, +1, n, lev.nf[fi - 1] == n);
+    bool valid = true;
+    if (fi >= 1 && fi <= D) valid = shift1(cF, fi - 1, +1, n, lev.nf[fi - 1] == n);
+    if (fi > D) valid = shift1(cF, fi - 1 - D, -1, n, lev.nf[fi - 1 - D] == n);
 #pragma unroll
     for (int k = 0; k < D; ++k)
 #pragma unroll
       for (int side = 0; side < 2; ++side) {
-        // without interphase faces the type and the lifting weights follow
-        // from the position: Dirichlet faces at the walls (weight 1 on their
-        // element), intraphase faces elsewhere, (wL, wR) = (0, 1)
         const bool per = lev.nf[k] == n;
         int f = cF[k] + side;
         unsigned char ty = F_INTRA;
         if (!per && f == 0) ty = F_DIR_LO;
         if (!per && f == n) ty = F_DIR_HI;
         if (per) f &= n - 1;
-        d.fty[fi][k][side] = valid ? ty : (unsigned char)F_NONE;
-        d.fwl[fi][k][side] = (valid && ty == F_DIR_HI) ? (T)1 : (T)0;
-        d.fwr[fi][k][side] = (valid && ty != F_DIR_HI) ? (T)1 : (T)0;
-        if (fi == 0) fid0[k][side] = face_index<D>(cF, n, lev.nf[k], k, f);
+        const int id = face_index<D>(cF, n, lev.nf[k], k, f);
+        if constexpr (IF) {
+          // interphase faces: type and lifting weights from the level's tables
+          d.fty[fi][k][side] = valid ? lev.ftype[k][id] : (unsigned char)F_NONE;
+          d.fwl[fi][k][side] = valid ? lev.fw[k][2 * id] : (T)0;
+          d.fwr[fi][k][side] = valid ? lev.fw[k][2 * id + 1] : (T)0;
+        } else {
+          // without interphase faces the type and the lifting weights follow
+          // from the position: Dirichlet faces at the walls (weight 1 on their
+          // element), intraphase faces elsewhere, (wL, wR) = (0, 1)
+          d.fty[fi][k][side] = valid ? ty : (unsigned char)F_NONE;
+          d.fwl[fi][k][side] = (valid && ty == F_DIR_HI) ? (T)1 : (T)0;
+          d.fwr[fi][k][side] = (valid && ty != F_DIR_HI) ? (T)1 : (T)0;
+        }
+        if (fi == 0) fid0[k][side] = id;
       }
   }
 #pragma unroll
@@ -289,11 +377,11 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, int E, const 
 }
 
 // Writes the loaded element data to LDS (waits for the loads).
-template <typename T, int D, int P, int NT>
-__device__ __forceinline__ void elem_stage(const DevLevel<T>& lev, const ElemData<T, D, P, NT>& d, Work<T, D, P>& w,
-                                           int lane) {
-  using S = Sz<D, P>;
-  using ED = ElemData<T, D, P, NT>;
+template <typename T, int D, int P, int NT, bool IF>
+__device__ __forceinline__ void elem_stage(const DevLevel<T>& lev, const ElemData<T, D, P, NT, IF>& d,
+                                           Work<T, D, P, IF>& w, int lane) {
+  using S = Sz<D, P, IF>;
+  using ED = ElemData<T, D, P, NT, IF>;
   constexpr int NQ = S::NQ, MT = S::MT, NB = S::NB, NFS = S::NFS, NSLOT = S::NSLOT;
   constexpr int XQ = ED::XQ, MQ = ED::MQ, RQ = ED::RQ, TQ = ED::TQ;
   #pragma unroll
@@ -304,12 +392,21 @@ __device__ __forceinline__ void elem_stage(const DevLevel<T>& lev, const ElemDat
       if (i < NB) w.xs[sl][i] = d.se[sl] >= 0 ? d.xr[sl][q] * (i >= D * NQ ? d.dsp[sl] : d.dsv[sl]) : (T)0;
     }
   if (lev.mmu) {
-    if constexpr (Work<T, D, P>::STAGE_M) {
+    if constexpr (Work<T, D, P, IF>::STAGE_M) {
 #pragma unroll
       for (int q = 0; q < MQ; ++q) {
         const int t = lane + q * NT;
         if (t < NQ * NQ) w.mm[t] = d.mr[q];
       }
+    }
+    if constexpr (IF) {
+#pragma unroll
+      for (int k = 0; k < D; ++k)
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) {
+          const int t = lane + q * NT;
+          if (t < MT * NQ) w.rrh[k][t] = d.se[1 + k] >= 0 ? d.rvh[k][q] : (T)0;
+        }
     }
 #pragma unroll
     for (int k = 0; k < D; ++k)
@@ -346,20 +443,21 @@ __device__ __forceinline__ void elem_stage(const DevLevel<T>& lev, const ElemDat
 // Phases 2-6 on the staged element: (A x)_E (mode 1) or b_E - (A x)_E
 // (mode 0, b_E in bc) into w.res.  Operators of the diagonally scaled system
 // D A D when lev.dscale is set (ds0v, ds0p: the element's scaling).
-template <typename T, int D, int P, int NT>
+template <typename T, int D, int P, int NT, bool IF>
 __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<T>& tab, int E, int vmask, int mode,
-                                             const T* bc, T ds0v, T ds0p, Work<T, D, P>& w, int lane) {
-  using S = Sz<D, P>;
+                                             const T* bc, T ds0v, T ds0p, Work<T, D, P, IF>& w, int lane) {
+  using S = Sz<D, P, IF>;
   constexpr int M = S::M, NQ = S::NQ, MT = S::MT, NB = S::NB, NFS = S::NFS;
-  constexpr int XQ = ElemData<T, D, P, NT>::XQ;
-  using W = Work<T, D, P>;
+  constexpr int XQ = ElemData<T, D, P, NT, IF>::XQ;
+  using W = Work<T, D, P, IF>;
     const T hinv = lev.hinv;
   const T gam = (T)lev.gamma;
   (void)NFS;
   // ---- phase 2: gradient lines g_F = G_k u_i along axis k ----
-  // per axis k: F = E (all i), F = E+e_k (all i), F = E+e_j (j != k, component i = j)
+  // per axis k: F = E (all i), F = E+e_k (all i), F = E+e_j (j != k, component
+  // i = j); with interphase faces also F = E-e_k (all i), F = E-e_j (i = j)
   {
-    constexpr int PER_K = (3 * D - 1) * MT;
+    constexpr int PER_K = (IF ? 5 * D - 2 : 3 * D - 1) * MT;
     for (int u = lane; u < D * PER_K; u += NT) {
       const int k = u / PER_K;
       const int r = u % PER_K;
@@ -368,8 +466,10 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
       int fi, i;
       if (q < D) { fi = 0; i = q; }
       else if (q < 2 * D) { fi = 1 + k; i = q - D; }
-      else { const int j0 = q - 2 * D; const int j = j0 < k ? j0 : j0 + 1; fi = 1 + j; i = j; }
-      const int sF = (fi == 0) ? 0 : 1 + D + (fi - 1);
+      else if (q < 3 * D - 1) { const int j0 = q - 2 * D; const int j = j0 < k ? j0 : j0 + 1; fi = 1 + j; i = j; }
+      else if (q < 4 * D - 1) { fi = 1 + D + k; i = q - (3 * D - 1); }
+      else { const int j0 = q - (4 * D - 1); const int j = j0 < k ? j0 : j0 + 1; fi = 1 + D + j; i = j; }
+      const int sF = f_slot<D>(fi);
       if (!((vmask >> sF) & 1)) continue;
       const unsigned char tlo = w.ft[fi][k][0], thi = w.ft[fi][k][1];
       const T wR = w.fwr[fi][k][0], wL = w.fwl[fi][k][1];
@@ -386,7 +486,18 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
         trLhi += tab.e1[bb] * ul[bb * st];
       }
       const T jlo = (tlo == F_NONE) ? (T)0 : wR * (trlo - ((tlo == F_INTRA || tlo == F_INTER) ? trLhi : (T)0));
-      const T jhi = (thi == F_DIR_HI) ? wL * trhi : (T)0;
+      // lifting of the high-face jump onto F (weight wL: Dirichlet, or an
+      // interphase face lifting onto its low element)
+      T jhi = (thi == F_DIR_HI) ? wL * trhi : (T)0;
+      if constexpr (IF) {
+        if (thi == F_INTRA || thi == F_INTER) {
+          const T* uh = &w.xs[high_slot<D>(fi, k)][i * NQ + base];
+          T trHlo = 0;
+#pragma unroll
+          for (int bb = 0; bb < M; ++bb) trHlo += tab.e0[bb] * uh[bb * st];
+          jhi = wL * (trhi - trHlo);
+        }
+      }
       T* go = &w.g[fi][i * D + k][base];
 #pragma unroll
       for (int ak = 0; ak < M; ++ak) {
@@ -402,8 +513,30 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
   {
     constexpr int NPAIR = D * D;
     constexpr int NS0 = NPAIR * NQ;
-    for (int u = lane; u < NS0 + D * D * MT; u += NT) {
-      if (u < NS0) {
+    constexpr int NTRR = D * D * MT;
+    for (int u = lane; u < NS0 + (IF ? 2 : 1) * NTRR; u += NT) {
+      if (IF && u >= NS0 + NTRR) {
+        // high-face traces of s at E - e_k (interphase liftings onto E)
+        const int r = u - NS0 - NTRR;
+        const int t = r % MT, i = (r / MT) % D, k = r / (MT * D);
+        T v = 0;
+        if ((vmask >> (1 + k)) & 1) {
+          const int fi = 1 + D + k;
+          const T* g1 = w.g[fi][i * D + k];
+          const T* g2 = w.g[fi][k * D + i];
+          if (lev.mmu) {
+            const T* R = &w.rrh[IF ? k : 0][t * NQ];
+#pragma unroll 8
+            for (int bb = 0; bb < NQ; ++bb) v += R[bb] * (g1[bb] + gam * g2[bb]);
+          } else {
+            const int base = compose<M>(t, 0, k), st = stride_of<M>(k);
+#pragma unroll
+            for (int cc = 0; cc < M; ++cc) v += tab.e1[cc] * (g1[base + cc * st] + gam * g2[base + cc * st]);
+            v *= lev.mu_const;
+          }
+        }
+        w.trrh[IF ? k : 0][i][t] = v;
+      } else if (u < NS0) {
         const int a = u % NQ, pr = u / NQ, i = pr / D, k = pr % D;
         if (lev.gamma && i > k) continue;       // symmetric: filled from (k, i)
         const T* g1 = w.g[0][i * D + k];
@@ -504,6 +637,13 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
           v -= acc;
         }
         if (k == i && ty != F_NONE) v -= wR * w.trx[0][k][D][tt];
+        if constexpr (IF) {
+          // interphase face lifting onto its low element E - e_k: adjoint terms
+          if (ty == F_INTRA || ty == F_INTER) {
+            v += wL * w.trrh[IF ? k : 0][i][tt];
+            if (k == i) v -= wL * w.trn[0][k][D][tt];
+          }
+        }
       } else {
         // E is the low element L of its high face
         const T sR = (ty == F_INTRA || ty == F_INTER) ? w.trr[k][i][tt] : (T)0;
@@ -600,16 +740,16 @@ struct NoHook {
 // Evaluates (A x)_E (mode 1) or b_E - (A x)_E (mode 0) into w.res.
 // `after_loads` runs once the element's loads are issued and before they are
 // waited for: loads it issues then overlap the evaluation.
-template <typename T, int D, int P, int NT, class Hook = NoHook>
+template <typename T, int D, int P, int NT, bool IF, class Hook = NoHook>
 __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const TabT<T>& tab, int E,
                                                  const T* __restrict__ x, const T* __restrict__ b,
-                                                 int mode, Work<T, D, P>& w, Hook after_loads = Hook()) {
-  ElemData<T, D, P, NT> d;
+                                                 int mode, Work<T, D, P, IF>& w, Hook after_loads = Hook()) {
+  ElemData<T, D, P, NT, IF> d;
   const int lane = threadIdx.x;
-  elem_issue<T, D, P, NT>(lev, E, x, b, mode, d, lane);
+  elem_issue<T, D, P, NT, IF>(lev, E, x, b, mode, d, lane);
   after_loads();
-  elem_stage<T, D, P, NT>(lev, d, w, lane);
-  elem_compute<T, D, P, NT>(lev, tab, E, d.vmask, mode, d.br, d.dsv[0], d.dsp[0], w, lane);
+  elem_stage<T, D, P, NT, IF>(lev, d, w, lane);
+  elem_compute<T, D, P, NT, IF>(lev, tab, E, d.vmask, mode, d.br, d.dsv[0], d.dsp[0], w, lane);
 }
 
 // 16-byte word of the inverse and entry v of it in the arithmetic type
@@ -634,7 +774,7 @@ __device__ __forceinline__ T inv_entry(const u32x4& raw, int v) {
 // The element's inverse (lane-blocked layout, see inv_layout) is prefetched
 // into registers before the residual is evaluated.
 // ---------------------------------------------------------------------------
-template <typename T, typename TI, int D, int P, int NT>
+template <typename T, typename TI, int D, int P, int NT, bool IF>
 __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> tab, const int* __restrict__ elems,
                                                       const TI* __restrict__ inv, const T* __restrict__ b,
                                                       T* __restrict__ x) {
@@ -645,14 +785,14 @@ __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
   // chunks requested before the residual is evaluated: all of a bf16 block, half
   // of an FP32 one (the rest is loaded in the product; fewer registers held)
   constexpr int PF = sizeof(TI) == 2 ? (CS < 16 ? CS : 16) : (CS / 2 > 0 ? CS / 2 : 1);
-  __shared__ Work<T, D, P> w;
+  __shared__ Work<T, D, P, IF> w;
   __shared__ T part[LY.S][LY.NBP];
   const int lane = threadIdx.x;
   const int idx = xcd_remap(blockIdx.x, gridDim.x);
   const int E = elems[idx];
   const u32x4* Ai = reinterpret_cast<const u32x4*>(inv + (size_t)idx * NB * LY.NBP);
   u32x4 pre[PF];
-  element_operator<T, D, P, NT>(lev, tab, E, x, b, 0, w, [&]() {
+  element_operator<T, D, P, NT, IF>(lev, tab, E, x, b, 0, w, [&]() {
     if (lane < RGS) {
 #pragma unroll
       for (int kk = 0; kk < PF; ++kk) pre[kk] = __builtin_nontemporal_load(&Ai[kk * RGS + lane]);
@@ -682,13 +822,13 @@ __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
   }
 }
 
-template <typename T, int D, int P, int NT>
+template <typename T, int D, int P, int NT, bool IF>
 __global__ __launch_bounds__(NT) void k_residual(DevLevel<T> lev, TabT<T> tab, const T* __restrict__ b,
                                                  const T* __restrict__ x, T* __restrict__ out, int mode) {
   using S = Sz<D, P>;
-  __shared__ Work<T, D, P> w;
+  __shared__ Work<T, D, P, IF> w;
   const int E = xcd_remap(blockIdx.x, gridDim.x);
-  element_operator<T, D, P, NT>(lev, tab, E, x, b, mode, w);
+  element_operator<T, D, P, NT, IF>(lev, tab, E, x, b, mode, w);
   for (int t = threadIdx.x; t < S::NB; t += NT) out[(size_t)E * S::NB + t] = w.res[t];
 }
 
@@ -707,13 +847,13 @@ __device__ __forceinline__ T pfull(const TabT<T>& tab, int o, int af, int ac) {
 }
 
 // r_c = I^T (b - A x): one work-group per coarse element, looping over children.
-template <typename T, int D, int P, int NT>
+template <typename T, int D, int P, int NT, bool IF>
 __global__ __launch_bounds__(NT) void k_residual_restrict(DevLevel<T> lev, TabT<T> tab, const T* __restrict__ b,
                                                           const T* __restrict__ x, T* __restrict__ rc) {
   using S = Sz<D, P>;
   constexpr int M = S::M, NQ = S::NQ, NB = S::NB;
   constexpr int PER = (NB + NT - 1) / NT;
-  __shared__ Work<T, D, P> w;
+  __shared__ Work<T, D, P, IF> w;
   const int lgc = lev.lgn - 1;
   const int C = xcd_remap(blockIdx.x, gridDim.x);
   int cc[D];
@@ -726,7 +866,7 @@ __global__ __launch_bounds__(NT) void k_residual_restrict(DevLevel<T> lev, TabT<
 #pragma unroll
     for (int j = 0; j < D; ++j) cf[j] = 2 * cc[j] + ((o >> j) & 1);
     const int E = index_of<D>(cf, lev.lgn);
-    element_operator<T, D, P, NT>(lev, tab, E, x, b, 0, w);
+    element_operator<T, D, P, NT, IF>(lev, tab, E, x, b, 0, w);
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int t = threadIdx.x + q * NT;
@@ -889,6 +1029,17 @@ static int dispatch(int dim, int p, F&& f) {
 // evaluation sets the time of the launch
 constexpr int SMALL_GRID = 4096;
 constexpr int NT_SMALL = 128;
+// levels with interphase faces use the extended stencil (2D only)
+template <class F>
+static int dispatch_if(int iface, int dim, F&& f) {
+  if (!iface) {
+    f(std::false_type{});
+    return 0;
+  }
+  if (dim != 2) return 2;
+  f(std::true_type{});
+  return 0;
+}
 template <class F>
 static void dispatch_nt(int64_t nelems, F&& f) {
   if (nelems >= SMALL_GRID) f(std::integral_constant<int, WG>{});
@@ -900,23 +1051,25 @@ int launch_smooth_colour(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D
                          int64_t nelems, const void* inv, int inv_kind, const T* b, T* x) {
   if (nelems <= 0) return 0;
   const unsigned grid = (unsigned)nelems;
+  bool bad = false;   // no kernel for this level (interphase faces in 3D)
   hipStream_t st = (hipStream_t)c.stream;
   const TabT<T> tt = tab_of<T>(tab);
   if constexpr (sizeof(T) == 8) {
     if (inv_kind != 0) return 2;
-    if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; dispatch_nt(nelems, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, double, D_, P_, NT_>), dim3(grid), dim3(NT_), 0, st,
-                                                  lev, tt, elems, (const double*)inv, b, x); }); })) return 2;
+    if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, double, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), 0, st,
+                                                  lev, tt, elems, (const double*)inv, b, x); }); })) bad = true; })) return 2;
   } else {
     if (inv_kind == 1) {
-      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; dispatch_nt(nelems, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, float, D_, P_, NT_>), dim3(grid), dim3(NT_), 0, st,
-                                                    lev, tt, elems, (const float*)inv, b, x); }); })) return 2;
+      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, float, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), 0, st,
+                                                    lev, tt, elems, (const float*)inv, b, x); }); })) bad = true; })) return 2;
     } else if (inv_kind == 2) {
-      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; dispatch_nt(nelems, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, uint16_t, D_, P_, NT_>), dim3(grid), dim3(NT_), 0, st,
-                                                    lev, tt, elems, (const uint16_t*)inv, b, x); }); })) return 2;
+      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, uint16_t, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), 0, st,
+                                                    lev, tt, elems, (const uint16_t*)inv, b, x); }); })) bad = true; })) return 2;
     } else {
       return 2;
     }
   }
+  if (bad) return 2;
   return hip_ok();
 }
 
@@ -925,10 +1078,12 @@ int launch_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab
                     int mode) {
   int64_t NE = 1;
   for (int j = 0; j < c.dim; ++j) NE *= lev.n;
+  bool bad = false;   // no kernel for this level (interphase faces in 3D)
   hipStream_t st = (hipStream_t)c.stream;
   const TabT<T> tt = tab_of<T>(tab);
-  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; dispatch_nt(NE, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual<T, D_, P_, NT_>), dim3((unsigned)NE), dim3(NT_), 0, st,
-                                                lev, tt, b, x, out, mode); }); })) return 2;
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(NE, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual<T, D_, P_, NT_, IF_>), dim3((unsigned)NE), dim3(NT_), 0, st,
+                                                lev, tt, b, x, out, mode); }); })) bad = true; })) return 2;
+  if (bad) return 2;
   return hip_ok();
 }
 
@@ -937,10 +1092,12 @@ int launch_residual_restrict(const LaunchCfg& c, const DevLevel<T>& lev, const T
                              T* rc) {
   int64_t NC = 1;
   for (int j = 0; j < c.dim; ++j) NC *= lev.n / 2;
+  bool bad = false;   // no kernel for this level (interphase faces in 3D)
   hipStream_t st = (hipStream_t)c.stream;
   const TabT<T> tt = tab_of<T>(tab);
-  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; dispatch_nt(NC, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual_restrict<T, D_, P_, NT_>), dim3((unsigned)NC), dim3(NT_), 0, st,
-                                                lev, tt, b, x, rc); }); })) return 2;
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(NC, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual_restrict<T, D_, P_, NT_, IF_>), dim3((unsigned)NC), dim3(NT_), 0, st,
+                                                lev, tt, b, x, rc); }); })) bad = true; })) return 2;
+  if (bad) return 2;
   return hip_ok();
 }
 

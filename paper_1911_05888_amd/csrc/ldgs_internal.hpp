@@ -78,6 +78,8 @@ struct DevLevel {
   const T* fT[3];                  // [faces][MT*MT] penalty matrices
   const T* mmu;                    // [NE][NQ*NQ] or nullptr (then mu_const)
   const T* rmu;                    // [NE][D][MT*NQ] low-face trace rows (e0^T)_k M_mu, with mmu
+  const T* rmuh;                   // [NE][D][MT*NQ] high-face trace rows (e1^T)_k M_mu (levels with interphase faces)
+  int iface;                       // level has interphase faces: extended stencil, face data from the tables
   T mu_const;
   T rho_delta;                     // rho / delta (0: steady)
   const T* dscale;                 // [NE][2] (alpha, beta) or nullptr

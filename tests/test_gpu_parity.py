@@ -15,7 +15,7 @@ oracle builds its own b for the RHS parity test).  Tolerances:
 import numpy as np
 import pytest
 
-from synth import Problem, c1_periodic_standard, c2_dirichlet_varmu, c3_unsteady_periodic
+from synth import Problem, c1_periodic_standard, c2_dirichlet_varmu, c3_unsteady_periodic, c4a_square_inclusion
 
 pytestmark = pytest.mark.gpu
 
@@ -25,6 +25,8 @@ CASES = {
     "c2_n16_p2": lambda: c2_dirichlet_varmu(n=16, p=2),
     "per3d_n8_p2": lambda: Problem(name="per3d_n8_p2", dim=3, n=8, p=2, gamma=1, bc=("periodic",) * 3),
     "c3_n8_p2": lambda: c3_unsteady_periodic(n=8, p=2, re_eff=10.0, h_ref=1.0 / 64),
+    "c4a_n16_p2": lambda: c4a_square_inclusion(n=16, p=2),
+    "c4a_n32_p1": lambda: c4a_square_inclusion(n=32, p=1),
 }
 
 _cache = {}
@@ -136,11 +138,15 @@ def test_bottom_solve(name):
     rng = np.random.Generator(np.random.PCG64(15))
     b = rng.standard_normal(bot.A.shape[0])
     # a right-hand side in the range of A_c (bottom residuals are): orthogonal
-    # to the constant fields of the trivial kernel
+    # to the trivial kernel
     fields = [prob.dim] if H.k0 == 1 else list(range(prob.dim + 1))
     for f in fields:
+        # kernel vector of the (possibly scaled) bottom operator D A D: the
+        # constant field divided by the scaling
+        kv = np.zeros(bot.A.shape[0])
         sel = np.arange(bot.NE) * bot.nb + f * bot.nq
-        b[sel] -= b[sel].mean()
+        kv[sel] = 1.0 if bot.dscale is None else 1.0 / bot.dscale[sel]
+        b -= kv * (kv @ b) / (kv @ kv)
     x = dev(np.zeros_like(b))
     ctx.bottom_solve(dev(b), x)
     xg = host(x)
@@ -168,9 +174,10 @@ def test_apply_and_rhs_fine(name):
     assert rel(y, Solver(H).A @ x) <= 1e-12
 
 
-@pytest.mark.parametrize("name", ["c1_n16_p2", "c2_n32_p3", "per3d_n8_p2", "c3_n8_p2"])
+@pytest.mark.parametrize("name", ["c1_n16_p2", "c2_n32_p3", "per3d_n8_p2", "c3_n8_p2", "c4a_n16_p2", "c4a_n32_p1"])
 def test_vcycle_residual_history(name):
-    """Stationary FP64 V-cycle: rho_k within 1e-11 of the oracle's for k <= 8."""
+    """Stationary FP64 V-cycle: rho_k within 1e-11 (times the largest rho of the
+    run) of the oracle's for k <= 8."""
     from oracle.solvers import Solver
     prob, H, ctx = setup_case(name)
     rng = np.random.Generator(np.random.PCG64(17))
@@ -182,7 +189,11 @@ def test_vcycle_residual_history(name):
     hist_g = info["history"]
     assert len(hist_g) == len(hist_o)
     print(name, "rho_k gpu", hist_g, "oracle", hist_o)
-    assert np.abs(hist_g - hist_o).max() <= 1e-11, np.abs(hist_g - hist_o)
+    # relative to the largest residual of the run: ||r_0|| unless a cycle raises
+    # the residual (the first cycle does, by 1e4, for the 1e4 viscosity
+    # contrast of the inclusion in the unscaled norm)
+    scale = max(1.0, np.abs(hist_o).max())
+    assert np.abs(hist_g - hist_o).max() <= 1e-11 * scale, np.abs(hist_g - hist_o)
 
 
 @pytest.mark.parametrize("name", ["c1_n16_p2", "c2_n32_p3"])
