@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
@@ -76,6 +77,7 @@ struct ldgs_ctx {
   hipStream_t stream = nullptr;
   int vprec = 0;
   int k0 = 1;
+  int small_grid = 4096;       // see LaunchCfg; LDGS_SMALL_GRID overrides (tests)
   std::vector<int> kernel_offsets;
   PrecStore<double> s64;
   PrecStore<float> s32;      // float arithmetic, float inverses
@@ -478,7 +480,7 @@ hipEvent_t next_event(ldgs_ctx* c) {
 
 template <typename T>
 void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* x) {
-  LaunchCfg cfg{c->g.d, c->g.p, c->stream};
+  LaunchCfg cfg{c->g.d, c->g.p, c->stream, c->small_grid};
   PrecLevel<T>& pl = S.lv[l];
   const size_t esz = pl.inv_kind == 0 ? 8 : (pl.inv_kind == 1 ? 4 : 2);
   int64_t o = pl.col_off[col], cnt = pl.col_off[col + 1] - o;
@@ -524,7 +526,7 @@ void bottom_solve(ldgs_ctx* c, const T* b, T* x) {
 template <typename T>
 void cycle(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x) {
   const int bottom = (int)c->levels.size() - 1;
-  LaunchCfg cfg{c->g.d, c->g.p, c->stream};
+  LaunchCfg cfg{c->g.d, c->g.p, c->stream, c->small_grid};
   if (l == bottom) {
     bottom_solve(c, b, x);
     return;
@@ -587,7 +589,7 @@ double dot(ldgs_ctx* c, const double* x, const double* y) {
 }
 
 void residual_fine(ldgs_ctx* c, const double* b, const double* x, double* r) {
-  LaunchCfg cfg{c->g.d, c->g.p, c->stream};
+  LaunchCfg cfg{c->g.d, c->g.p, c->stream, c->small_grid};
   LCHK(launch_residual<double>(cfg, c->s64.lv[0].unscaled, c->tab, b, x, r, 0));
 }
 
@@ -668,7 +670,7 @@ constexpr int SUMSQ_BLK = 512;
 // out = base + N(r') with r' = (b - A x) of the V-cycle's finest level as it
 // stands after the last cycle (scaled variables; unscaled inside the kernel)
 void learned_after_cycle(ldgs_ctx* c, int vp, const double* base, double* out) {
-  LaunchCfg cfg{c->g.d, c->g.p, c->stream};
+  LaunchCfg cfg{c->g.d, c->g.p, c->stream, c->small_grid};
   const Level& L = c->levels[0];
   const int64_t NE = L.NE;
   const int nb = c->g.nb, nvel = c->g.d * c->g.nq;
@@ -744,6 +746,10 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
     c->B.init(P.degree);
     c->tab = c->B.tab();
     c->vprec = P.vprec;
+    if (const char* sg = std::getenv("LDGS_SMALL_GRID")) {
+      const long v = std::strtol(sg, nullptr, 10);
+      if (v >= 1) c->small_grid = (int)v;
+    }
     c->k0 = kernel_dim(P);
     if (c->k0 == 1) c->kernel_offsets = {P.dim * c->g.nq};
     else for (int i = 0; i <= P.dim; ++i) c->kernel_offsets.push_back(i * c->g.nq);
@@ -844,7 +850,7 @@ ldgs_status ldgs_apply(ldgs_ctx* ctx, const double* x, double* y) {
   try {
     check_ctx(ctx, true);
     if (!x || !y || x == y) throw Fail{LDGS_E_ARG, "x, y must be distinct non-null"};
-    LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream};
+    LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream, ctx->small_grid};
     LCHK(launch_residual<double>(cfg, ctx->s64.lv[0].unscaled, ctx->tab, nullptr, x, y, 1));
     return LDGS_OK;
   } catch (const Fail& f) {
@@ -973,7 +979,7 @@ ldgs_status ldgs_learned_collect(ldgs_ctx* ctx, const double* xstar, int ncycles
       Md *= crop + 2;
       Cd *= crop;
     }
-    LaunchCfg cfg{d, ctx->g.p, ctx->stream};
+    LaunchCfg cfg{d, ctx->g.p, ctx->stream, ctx->small_grid};
     LCHK(launch_residual<double>(cfg, ctx->s64.lv[0].unscaled, ctx->tab, nullptr, xstar, ctx->w_cb, 1));
     LCHK(launch_fill<double>(ctx->stream, N, 0.0, ctx->w_cx));
     const double cu = (double)L.NE * nvel, cp = (double)L.NE * (nb - nvel);
@@ -1168,7 +1174,7 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxi
         for (int j = 0; j < m && it < maxit; ++j) {
           LCHK(launch_fill<double>(ctx->stream, N, 0.0, Z[j]));
           precond_add(ctx, ctx->vprec, V[j], Z[j]);
-          LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream};
+          LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream, ctx->small_grid};
           LCHK(launch_residual<double>(cfg, ctx->s64.lv[0].unscaled, ctx->tab, nullptr, Z[j], V[j + 1], 1));
           for (int i = 0; i <= j; ++i) {
             double hij = dot(ctx, V[j + 1], V[i]);
@@ -1297,7 +1303,7 @@ ldgs_status ldgs_level_residual_restrict(ldgs_ctx* ctx, int level, const double*
     check_ctx(ctx, true);
     if (!ctx->s64.built) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
     if (level < 0 || level + 1 >= (int)ctx->levels.size() || !b || !x || !rc) throw Fail{LDGS_E_ARG, "level"};
-    LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream};
+    LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream, ctx->small_grid};
     LCHK(launch_residual_restrict<double>(cfg, ctx->s64.lv[level].view, ctx->tab, b, x, rc));
     return LDGS_OK;
   } catch (const Fail& f) {
@@ -1309,7 +1315,7 @@ ldgs_status ldgs_level_prolong_add(ldgs_ctx* ctx, int level, const double* xc, d
   try {
     check_ctx(ctx, true);
     if (level < 0 || level + 1 >= (int)ctx->levels.size() || !xc || !x) throw Fail{LDGS_E_ARG, "level"};
-    LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream};
+    LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream, ctx->small_grid};
     LCHK(launch_prolong_add<double>(cfg, ctx->levels[level].n, ctx->tab, xc, x));
     return LDGS_OK;
   } catch (const Fail& f) {
@@ -1335,7 +1341,7 @@ ldgs_status ldgs_level_apply(ldgs_ctx* ctx, int level, const double* x, double* 
     if (level < 0 || level >= (int)ctx->levels.size() || !x || !y) throw Fail{LDGS_E_ARG, "level"};
     if (level == (int)ctx->levels.size() - 1 && ctx->levels[level].n < 4)
       throw Fail{LDGS_E_UNSUPPORTED, "device apply needs n >= 4 on the level"};
-    LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream};
+    LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream, ctx->small_grid};
     LCHK(launch_residual<double>(cfg, ctx->s64.lv[level].view, ctx->tab, nullptr, x, y, 1));
     return LDGS_OK;
   } catch (const Fail& f) {

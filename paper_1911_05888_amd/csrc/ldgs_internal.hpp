@@ -91,6 +91,10 @@ struct DevLevel {
 struct LaunchCfg {
   int dim, p;
   void* stream;
+  // launches with at least this many elements run one wavefront per element,
+  // smaller ones two (the context's setting; tests lower it to reach the
+  // one-wavefront kernels on grids the oracle assembles quickly)
+  int small_grid = 4096;
 };
 
 template <typename T>

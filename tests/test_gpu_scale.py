@@ -130,3 +130,42 @@ def test_full_size_colour_pass_invariants():
     e = np.linalg.norm(d) / np.linalg.norm(_host(x64))
     print(f"[scale] FP32 vs FP64 colour passes: relative difference {e:.2e}", flush=True)
     assert e <= 1e-4
+
+
+SMALL_CASES = {
+    "c4a_n16_p2": lambda: __import__("synth").c4a_square_inclusion(n=16, p=2),
+    "c2_n16_p3": lambda: c2_dirichlet_varmu(n=16, p=3),
+    "per3d_n8_p2": lambda: Problem(name="per3d", dim=3, n=8, p=2, gamma=1, bc=("periodic",) * 3),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL_CASES))
+def test_one_wavefront_kernels_match_oracle(name, monkeypatch):
+    """The launch threshold lowered to 1 element (LDGS_SMALL_GRID, read at
+    setup): every element kernel runs its one-wavefront variant, compared with
+    the oracle directly (interphase variant included)."""
+    from oracle import build_hierarchy
+    from oracle.multigrid import colour_pass
+    from paper_1911_05888_amd import Context
+    monkeypatch.setenv("LDGS_SMALL_GRID", "1")
+    prob = SMALL_CASES[name]()
+    print(f"[scale] one-wavefront kernels {name}", flush=True)
+    H = build_hierarchy(prob)
+    ctx = Context(prob)
+    rng = np.random.Generator(np.random.PCG64(43))
+    for l, lv in enumerate(H.levels[:-1]):
+        x = rng.standard_normal(lv.A.shape[0])
+        b = rng.standard_normal(lv.A.shape[0])
+        y = _dev(np.zeros_like(x))
+        ctx.level_apply(l, _dev(x), y)
+        assert _rel(_host(y), lv.A @ x) <= 1e-12, (name, l)
+        rc = _dev(np.zeros(H.levels[l + 1].A.shape[0]))
+        ctx.level_residual_restrict(l, _dev(b), _dev(x), rc)
+        assert _rel(_host(rc), lv.I.T @ (b - lv.A @ x)) <= 1e-12, (name, l)
+        xo = x.copy()
+        xg = _dev(x)
+        bg = _dev(b)
+        for c in range(lv.ncol):
+            colour_pass(lv.A, lv.Ainv, xo, b, np.nonzero(lv.colours == c)[0], lv.nb)
+            ctx.level_smooth_colour(l, c, bg, xg)
+            assert _rel(_host(xg), xo) <= 1e-11, (name, l, c)
