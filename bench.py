@@ -94,12 +94,36 @@ def train_correction(ctx, prob, nseeds=16, ncycles=8, ncrops=16, crop=16, steps=
     return params, c_vel, c_pre, info
 
 
+WORKLOADS = {
+    # name: (problem factory, description, extra precisions built beside FP32)
+    "c2": ("2D viscous-stress Stokes, Dirichlet walls, {n}x{n} elements, Q_3, "
+           "mu = 1 + 0.9 sin2pi x sin2pi y, manufactured solution; FP32 V(3,3) in FP64 iterative refinement to 1e-10"),
+    "c4a": ("2D two-phase viscous-stress Stokes, square inclusion (1/4,3/4)^2 with mu 1e4 inside and 1 outside, "
+            "Dirichlet walls, {n}x{n} elements, Q_2, two-phase manufactured solution, mod-3 colouring, diagonal scaling; "
+            "FP32 V(3,3) in FP64 iterative refinement to 1e-10"),
+    "c5": ("3D viscous-stress Stokes, Dirichlet walls, {n}^3 elements, Q_2, log-normal viscosity (random Fourier "
+           "features, seed 1001), manufactured solution, parity colouring, diagonal scaling; FP32 V(3,3) in FP64 "
+           "iterative refinement to 1e-10"),
+}
+
+
+def make_problem(workload, n):
+    from synth import c2_dirichlet_varmu, c4a_square_inclusion, c5_lognormal
+    if workload == "c2":
+        return c2_dirichlet_varmu(n=n or 256, p=3)
+    if workload == "c4a":
+        return c4a_square_inclusion(n=n or 512, p=2)
+    return c5_lognormal(n=n or 128, p=2)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--n", type=int, default=0, help="elements per axis (default: the workload's)")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2",
+                    help="c2 (default, the benchmark configuration); c4a and c5 measure the other configurations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 / BF16 comparison solves")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -122,13 +146,19 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    prob = c2_dirichlet_varmu(n=args.n, p=3)
+    prob = make_problem(args.workload, args.n)
+    n = prob.n
+    # the 3D workload keeps FP32 (and BF16-block) V-cycle data only: its FP64
+    # block inverses alone would take 196 GB
+    builds = (1 << V_FP32_BF16BLK) if args.workload == "c5" else (1 << V_FP64) | (1 << V_FP32_BF16BLK)
     t0 = time.perf_counter()
-    ctx = Context(prob, vprec=V_FP32, build_precisions=(1 << V_FP64) | (1 << V_FP32_BF16BLK))
+    ctx = Context(prob, vprec=V_FP32, build_precisions=builds)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     print(f"[bench] setup {t_setup:.1f} s, {ctx.ndof} unknowns, {ctx.n_levels} levels", file=sys.stderr, flush=True)
-    b0 = ctx.assemble_rhs(prob.exact)
+    t0 = time.perf_counter()
+    b0 = ctx.assemble_rhs(prob.rhs_source())
+    print(f"[bench] right-hand side assembled in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     ncol = ctx.level_info(0)[2]
 
     def solve(vprec, outer, tol=1e-10, maxit=60, learned=False):
@@ -162,7 +192,7 @@ def main():
     avg_s = k_ms * 1e-3 / max(k_launches, 1)
     achieved = bytes_launch / avg_s / 1e9
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
+    if args.workload == "c2" and n == 256 and os.path.exists(TRAFFIC_FILE):
         # counters are valid only for the kernel source they were measured on
         import hashlib
         with open(TRAFFIC_FILE) as fh:
@@ -174,15 +204,17 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        ctx.set_vprec(V_FP32)
-        params, c_vel, c_pre, tinfo = train_correction(ctx, prob)
-        ctx.set_learned(params, c_vel, c_pre)
-        print(f"[bench] learned correction trained in {tinfo['train_s']:.1f} s, loss "
-              f"{tinfo['loss_first']:.3f} -> {tinfo['loss_last']:.3f}", file=sys.stderr, flush=True)
-        for label, vp, outer, learned in [("plain_fp64_stationary", V_FP64, STATIONARY, False),
-                                          ("plain_fp64_ir", V_FP64, IR, False),
-                                          ("fp32_bf16blk_ir", V_FP32_BF16BLK, IR, False),
-                                          ("fp32_learned_ir", V_FP32, IR, True)]:
+        runs = [("fp32_bf16blk_ir", V_FP32_BF16BLK, IR, False)]
+        if args.workload != "c5":
+            runs = [("plain_fp64_stationary", V_FP64, STATIONARY, False), ("plain_fp64_ir", V_FP64, IR, False)] + runs
+        if args.workload == "c2":
+            ctx.set_vprec(V_FP32)
+            params, c_vel, c_pre, tinfo = train_correction(ctx, prob)
+            ctx.set_learned(params, c_vel, c_pre)
+            print(f"[bench] learned correction trained in {tinfo['train_s']:.1f} s, loss "
+                  f"{tinfo['loss_first']:.3f} -> {tinfo['loss_last']:.3f}", file=sys.stderr, flush=True)
+            runs.append(("fp32_learned_ir", V_FP32, IR, True))
+        for label, vp, outer, learned in runs:
             solve(vp, outer, learned=learned)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -203,19 +235,17 @@ def main():
         value=value, unit="DOF/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=ms_per_step, higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype="fp32 V-cycle, fp64 outer residual", data="synthetic",
-        config=dict(workload=f"2D viscous-stress Stokes, Dirichlet walls, {args.n}x{args.n} elements, Q_3, "
-                             "mu = 1 + 0.9 sin2pi x sin2pi y, manufactured solution; "
-                             "FP32 V(3,3) in FP64 iterative refinement to 1e-10",
-                    n=args.n, p=3, unknowns=ctx.ndof, levels=ctx.n_levels, colours=ncol,
+        config=dict(workload=WORKLOADS[args.workload].format(n=n),
+                    n=n, p=prob.p, dim=prob.dim, unknowns=ctx.ndof, levels=ctx.n_levels, colours=ncol,
                     time_to_tol_s=dt / args.steps, vcycles_per_solve=iters / args.steps,
                     setup_s=t_setup, **extras),
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=achieved / HBM_PEAK_GBS, traffic=traffic,
-                      kernel="k_smooth_colour<float,float,2,3,64> (finest level)",
+                      kernel=f"k_smooth_colour<float,float,{prob.dim},{prob.p},64> (finest level)",
                       avg_launch_us=avg_s * 1e6, algorithmic_bytes_per_launch=bytes_launch,
                       launches=k_launches),
     )
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "c2":
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
 

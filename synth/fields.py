@@ -8,6 +8,7 @@ eq. (govern1)-(govern3) and its unsteady variant eq. (timedep1).
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -107,19 +108,38 @@ class LogNormalRFF:
         phases = rng.uniform(0.0, TWO_PI, size=K)
         return LogNormalRFF(kvecs=kvecs, phases=phases)
 
-    def _g(self, x):
+    def _eval(self, x, want_grad):
+        """g (and its gradient) at the points x, evaluated in row blocks on a
+        thread pool (numpy releases the interpreter lock inside the products
+        and the trigonometric functions)."""
         K = self.kvecs.shape[0]
-        arg = x @ self.kvecs.T + self.phases[None, :]
-        return math.sqrt(2.0 / K) * np.cos(arg).sum(axis=1), arg
+        x = np.asarray(x, dtype=float)
+        n = x.shape[0]
+        g = np.empty(n)
+        dg = np.empty_like(x) if want_grad else None
+        sc = math.sqrt(2.0 / K)
+
+        def block(lo, hi):
+            arg = x[lo:hi] @ self.kvecs.T + self.phases[None, :]
+            g[lo:hi] = sc * np.cos(arg).sum(axis=1)
+            if want_grad:
+                dg[lo:hi] = -sc * (np.sin(arg) @ self.kvecs)
+
+        step = 8192
+        if n <= step:
+            block(0, n)
+        else:
+            from concurrent.futures import ThreadPoolExecutor
+            with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+                list(ex.map(lambda lo: block(lo, min(lo + step, n)), range(0, n, step)))
+        return g, dg
 
     def value(self, x, chi=None):
-        g, _ = self._g(x)
+        g, _ = self._eval(x, False)
         return 10.0 ** g
 
     def grad(self, x, chi=None):
-        K = self.kvecs.shape[0]
-        g, arg = self._g(x)
-        dg = -math.sqrt(2.0 / K) * (np.sin(arg) @ self.kvecs)
+        g, dg = self._eval(x, True)
         return (10.0 ** g)[:, None] * math.log(10.0) * dg
 
     def params(self):

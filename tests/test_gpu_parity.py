@@ -15,7 +15,8 @@ oracle builds its own b for the RHS parity test).  Tolerances:
 import numpy as np
 import pytest
 
-from synth import Problem, c1_periodic_standard, c2_dirichlet_varmu, c3_unsteady_periodic, c4a_square_inclusion
+from synth import (Problem, c1_periodic_standard, c2_dirichlet_varmu, c3_unsteady_periodic, c4a_square_inclusion,
+                   c5_lognormal)
 
 pytestmark = pytest.mark.gpu
 
@@ -27,6 +28,7 @@ CASES = {
     "c3_n8_p2": lambda: c3_unsteady_periodic(n=8, p=2, re_eff=10.0, h_ref=1.0 / 64),
     "c4a_n16_p2": lambda: c4a_square_inclusion(n=16, p=2),
     "c4a_n32_p1": lambda: c4a_square_inclusion(n=32, p=1),
+    "c5_n8_p2": lambda: c5_lognormal(n=8, p=2),
 }
 
 _cache = {}
@@ -174,7 +176,8 @@ def test_apply_and_rhs_fine(name):
     assert rel(y, Solver(H).A @ x) <= 1e-12
 
 
-@pytest.mark.parametrize("name", ["c1_n16_p2", "c2_n32_p3", "per3d_n8_p2", "c3_n8_p2", "c4a_n16_p2", "c4a_n32_p1"])
+@pytest.mark.parametrize("name", ["c1_n16_p2", "c2_n32_p3", "per3d_n8_p2", "c3_n8_p2", "c4a_n16_p2", "c4a_n32_p1",
+                                  "c5_n8_p2"])
 def test_vcycle_residual_history(name):
     """Stationary FP64 V-cycle: rho_k within 1e-11 (times the largest rho of the
     run) of the oracle's for k <= 8."""
