@@ -52,6 +52,7 @@ struct PrecLevel {
   int inv_kind = 0;              // 0 double, 1 float, 2 bf16
   int* elems = nullptr;          // colour-major element ids
   std::vector<int64_t> col_off;  // colour offsets (elements)
+  std::vector<int64_t> col_reg;  // per colour: leading elements whose evaluation touches no interphase face
   size_t inv_stride = 0;         // entries per element in the inverse layout
   T* x = nullptr;                // level work vectors (levels >= 1)
   T* b = nullptr;
@@ -337,6 +338,35 @@ static uint16_t to_bf16(double d) {
   return (uint16_t)(u >> 16);
 }
 
+// true when the evaluation of E uses an interphase face: a face of E or of E + e_j
+bool touches_interphase(const Level& L, int d, int64_t E) {
+  int c[3] = {0, 0, 0};
+  int64_t r = E;
+  for (int j = 0; j < d; ++j) {
+    c[j] = (int)(r % L.n);
+    r /= L.n;
+  }
+  for (int fi = 0; fi <= d; ++fi) {
+    int cf[3] = {c[0], c[1], c[2]};
+    if (fi > 0) {
+      const int j = fi - 1;
+      int v = cf[j] + 1;
+      if (v >= L.n) {
+        if (L.faces[j].nfk != L.n) continue;   // beyond a wall
+        v -= L.n;
+      }
+      cf[j] = v;
+    }
+    for (int k = 0; k < d; ++k)
+      for (int side = 0; side < 2; ++side) {
+        int f = cf[k] + side;
+        if (L.faces[k].nfk == L.n) f %= L.n;
+        if (L.faces[k].type[face_id(L, d, k, cf, f)] == F_INTER) return true;
+      }
+  }
+  return false;
+}
+
 // inverse blocks of all smoothed levels into the stores that need them
 void build_inverses(ldgs_ctx* c, bool need64, bool need32, bool need16) {
   const int nb = c->g.nb;
@@ -348,9 +378,23 @@ void build_inverses(ldgs_ctx* c, bool need64, bool need32, bool need16) {
     Level& L = c->levels[l];
     std::vector<int64_t> off(L.ncol + 1, 0);
     for (int col = 0; col < L.ncol; ++col) off[col + 1] = off[col] + (int64_t)L.elems[col].size();
+    // colour-major element order; on levels with interphase faces each colour
+    // lists first the elements the regular kernel can evaluate, then the rest
     std::vector<int> order;
     order.reserve(L.NE);
-    for (int col = 0; col < L.ncol; ++col) order.insert(order.end(), L.elems[col].begin(), L.elems[col].end());
+    std::vector<int64_t> reg(L.ncol, 0);
+    bool iface = false;
+    for (int k = 0; k < c->g.d; ++k)
+      for (unsigned char t : L.faces[k].type) iface = iface || t == F_INTER;
+    for (int col = 0; col < L.ncol; ++col) {
+      std::vector<int> rest;
+      for (int E : L.elems[col]) {
+        if (iface && touches_interphase(L, c->g.d, E)) rest.push_back(E);
+        else order.push_back(E);
+      }
+      reg[col] = (int64_t)L.elems[col].size() - (int64_t)rest.size();
+      order.insert(order.end(), rest.begin(), rest.end());
+    }
     double* inv64 = need64 ? dalloc<double>(c, L.NE * st64) : nullptr;
     float* inv32 = need32 ? dalloc<float>(c, L.NE * st32) : nullptr;
     uint16_t* inv16 = need16 ? dalloc<uint16_t>(c, L.NE * st16) : nullptr;
@@ -397,9 +441,9 @@ void build_inverses(ldgs_ctx* c, bool need64, bool need32, bool need16) {
         HIPCHK(hipMemcpy(inv16 + p0 * st16, h16.data(), cnt * st16 * sizeof(uint16_t), hipMemcpyHostToDevice));
       }
     }
-    if (need64) { c->s64.lv[l].inv = inv64; c->s64.lv[l].inv_kind = 0; c->s64.lv[l].elems = elems; c->s64.lv[l].col_off = off; c->s64.lv[l].inv_stride = st64; }
-    if (need32) { c->s32.lv[l].inv = inv32; c->s32.lv[l].inv_kind = 1; c->s32.lv[l].elems = elems; c->s32.lv[l].col_off = off; c->s32.lv[l].inv_stride = st32; }
-    if (need16) { c->s16.lv[l].inv = inv16; c->s16.lv[l].inv_kind = 2; c->s16.lv[l].elems = elems; c->s16.lv[l].col_off = off; c->s16.lv[l].inv_stride = st16; }
+    if (need64) { c->s64.lv[l].inv = inv64; c->s64.lv[l].inv_kind = 0; c->s64.lv[l].elems = elems; c->s64.lv[l].col_off = off; c->s64.lv[l].col_reg = reg; c->s64.lv[l].inv_stride = st64; }
+    if (need32) { c->s32.lv[l].inv = inv32; c->s32.lv[l].inv_kind = 1; c->s32.lv[l].elems = elems; c->s32.lv[l].col_off = off; c->s32.lv[l].col_reg = reg; c->s32.lv[l].inv_stride = st32; }
+    if (need16) { c->s16.lv[l].inv = inv16; c->s16.lv[l].inv_kind = 2; c->s16.lv[l].elems = elems; c->s16.lv[l].col_off = off; c->s16.lv[l].col_reg = reg; c->s16.lv[l].inv_stride = st16; }
   }
 }
 
@@ -492,7 +536,20 @@ void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* 
     e1 = next_event(c);
     HIPCHK(hipEventRecord(e0, c->stream));
   }
-  LCHK(launch_smooth_colour<T>(cfg, pl.view, c->tab, pl.elems + o, cnt, inv, pl.inv_kind, b, x));
+  const int64_t nreg = pl.col_reg.empty() ? cnt : pl.col_reg[col];
+  // (split only large launches: on coarse levels the second launch would cost
+  // more than the extended stencil)
+  if (!pl.view.iface || nreg == cnt || cnt < c->small_grid) {
+    LCHK(launch_smooth_colour<T>(cfg, pl.view, c->tab, pl.elems + o, cnt, inv, pl.inv_kind, b, x));
+  } else {
+    // elements away from the interfaces: regular kernel; the rest: the
+    // extended-stencil variant (the two ranges of one colour are uncoupled)
+    DevLevel<T> regular = pl.view;
+    regular.iface = 0;
+    if (nreg > 0) LCHK(launch_smooth_colour<T>(cfg, regular, c->tab, pl.elems + o, nreg, inv, pl.inv_kind, b, x));
+    const void* inv_i = (const char*)inv + nreg * pl.inv_stride * esz;
+    LCHK(launch_smooth_colour<T>(cfg, pl.view, c->tab, pl.elems + o + nreg, cnt - nreg, inv_i, pl.inv_kind, b, x));
+  }
   if (timed) {
     HIPCHK(hipEventRecord(e1, c->stream));
     c->prof_ev.emplace_back(e0, e1);
