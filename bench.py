@@ -101,6 +101,9 @@ WORKLOADS = {
     "c4a": ("2D two-phase viscous-stress Stokes, square inclusion (1/4,3/4)^2 with mu 1e4 inside and 1 outside, "
             "Dirichlet walls, {n}x{n} elements, Q_2, two-phase manufactured solution, mod-3 colouring, diagonal scaling; "
             "FP32 V(3,3) in FP64 iterative refinement to 1e-10"),
+    "c3": ("3D unsteady viscous-stress Stokes, periodic, {n}^3 elements, Q_2, rho = mu = 1, delta = h^2 / 10 "
+           "(Re_eff = 10), seeded Fourier forcing (seed 0), parity colouring; FP32 V(3,3) in FP64 iterative "
+           "refinement to 1e-10"),
     "c5": ("3D viscous-stress Stokes, Dirichlet walls, {n}^3 elements, Q_2, log-normal viscosity (random Fourier "
            "features, seed 1001), manufactured solution, parity colouring, diagonal scaling; FP32 V(3,3) in FP64 "
            "iterative refinement to 1e-10"),
@@ -108,9 +111,11 @@ WORKLOADS = {
 
 
 def make_problem(workload, n):
-    from synth import c2_dirichlet_varmu, c4a_square_inclusion, c5_lognormal
+    from synth import c2_dirichlet_varmu, c3_unsteady_periodic, c4a_square_inclusion, c5_lognormal
     if workload == "c2":
         return c2_dirichlet_varmu(n=n or 256, p=3)
+    if workload == "c3":
+        return c3_unsteady_periodic(n=n or 64, p=2, re_eff=10.0)
     if workload == "c4a":
         return c4a_square_inclusion(n=n or 512, p=2)
     return c5_lognormal(n=n or 128, p=2)
@@ -123,7 +128,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=0, help="elements per axis (default: the workload's)")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2",
-                    help="c2 (default, the benchmark configuration); c4a and c5 measure the other configurations")
+                    help="c2 (default, the benchmark configuration); c3, c4a and c5 measure the other configurations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64 / BF16 comparison solves")
     ap.add_argument("--calibrate-copy", action="store_true",

@@ -313,9 +313,40 @@ class FourierForcing:
         rms = np.sqrt(0.5 * (a ** 2 + b ** 2).sum(axis=1))
         return FourierForcing(dim=dim, kmodes=kmodes, a=a / rms[:, None], b=b / rms[:, None])
 
-    def forcing(self, x, chi=None):
+    def forcing_direct(self, x):
         arg = TWO_PI * (x @ self.kmodes.T)
         return np.cos(arg) @ self.a.T + np.sin(arg) @ self.b.T
+
+    def forcing(self, x, chi=None):
+        """Same sum, evaluated axis by axis: a cos(2pi k.x) + b sin(2pi k.x) is
+        Re[(a - i b) prod_j exp(2 pi i k_j x_j)], and the wave vectors fill a
+        tensor grid, so the sum contracts one axis at a time."""
+        x = np.asarray(x, dtype=float)
+        n, d = x.shape
+        km = int(self.kmodes.max()) + 1
+        C = np.zeros((self.dim,) + (km,) * d, dtype=complex)
+        C[(slice(None),) + tuple(self.kmodes[:, j] for j in range(d))] = (self.a - 1j * self.b)
+        m = np.arange(km)
+        out = np.empty((n, self.dim))
+        Cm = C.reshape(-1, km).T
+
+        def block(lo, hi):
+            xs = x[lo:hi]
+            nb = xs.shape[0]
+            Z = [np.exp(2j * np.pi * xs[:, j:j + 1] * m[None, :]) for j in range(d)]
+            T = Z[d - 1] @ Cm                                   # (nb, dim * km^(d-1)), last axis contracted
+            for j in range(d - 2, -1, -1):
+                T = (T.reshape(nb, -1, km) * Z[j][:, None, :]).sum(axis=2)
+            out[lo:hi] = T.real.reshape(nb, self.dim)
+
+        step = 8192
+        if n <= step:
+            block(0, n)
+        else:
+            from concurrent.futures import ThreadPoolExecutor
+            with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+                list(ex.map(lambda lo: block(lo, min(lo + step, n)), range(0, n, step)))
+        return out
 
     def forcing_div(self, x, chi=None):
         return np.zeros(x.shape[0])
