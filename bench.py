@@ -17,7 +17,8 @@ The roofline object covers the dominant kernel (the finest-level smoother
 colour pass), timed with HIP events on the library's stream during the timed
 solves; the algorithmic bytes per launch are (elements in the colour) x
 (n_b^2 inverse entries + 3 n_b vector entries + (p+2)^d viscosity values) x
-the storage width.  cpu_baseline times the FP64 oracle on a bounded sample.
+the storage width; on levels whose blocks are all equal (periodic, constant
+coefficients) the one inverse is not streamed and the n_b^2 term is dropped.  cpu_baseline times the FP64 oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -193,7 +194,12 @@ def main():
     print(f"[bench] mixed FP32-in-IR: {iters / args.steps:.1f} V-cycles/solve, {ms_per_step:.2f} ms/solve",
           file=sys.stderr, flush=True)
 
-    bytes_launch = smoother_bytes_per_launch(prob, ncol, 4, 4)
+    # a level whose blocks are all equal holds one inverse: no inverse
+    # entries are streamed, the colour pass is the residual + shared update
+    shared = ctx.level_shared_inverse(0)
+    bytes_launch = smoother_bytes_per_launch(prob, ncol, 0 if shared else 4, 4)
+    kname = (f"k_colour_residual<float,{prob.dim},{prob.p},64,false> + k_shared_update<float,{prob.nb}>"
+             if shared else f"k_smooth_colour<float,float,{prob.dim},{prob.p},64>")
     avg_s = k_ms * 1e-3 / max(k_launches, 1)
     achieved = bytes_launch / avg_s / 1e9
     traffic = None
@@ -246,7 +252,7 @@ def main():
                     setup_s=t_setup, **extras),
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=achieved / HBM_PEAK_GBS, traffic=traffic,
-                      kernel=f"k_smooth_colour<float,float,{prob.dim},{prob.p},64> (finest level)",
+                      kernel=kname + " (finest level)",
                       avg_launch_us=avg_s * 1e6, algorithmic_bytes_per_launch=bytes_launch,
                       launches=k_launches),
     )

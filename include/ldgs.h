@@ -280,6 +280,15 @@ ldgs_status ldgs_project_kernel(ldgs_ctx* ctx, double* v_dev);
 /* Grid size n_l, number of levels and colours. */
 ldgs_status ldgs_level_info(const ldgs_ctx* ctx, int level, int* n_l, int* n_levels, int* n_colours);
 
+/* *shared = 1 when every diagonal block of level `level` is the same matrix
+ * (constant viscosity and density, a periodic grid, no interphase faces: the
+ * operator is translation invariant), so that its colour passes hold one
+ * inverse for the level instead of one per element; 0 otherwise (and on the
+ * coarsest level, which is not smoothed).  Setting the environment variable
+ * LDGS_SHARED_INVERSE=0 before setup turns this off.  Works on host-only
+ * contexts.  Errors: LDGS_E_ARG for a null pointer or a level out of range. */
+ldgs_status ldgs_level_shared_inverse(const ldgs_ctx* ctx, int level, int* shared);
+
 /* One colour pass of block Gauss-Seidel on level `level`: for every element E
  * of colour `colour`, x_E += A_EE^{-1} (b - A x)_E, all from the x at entry. */
 ldgs_status ldgs_level_smooth_colour(ldgs_ctx* ctx, int level, int colour,

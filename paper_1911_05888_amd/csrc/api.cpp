@@ -54,6 +54,8 @@ struct PrecLevel {
   std::vector<int64_t> col_off;  // colour offsets (elements)
   std::vector<int64_t> col_reg;  // per colour: leading elements whose evaluation touches no interphase face
   size_t inv_stride = 0;         // entries per element in the inverse layout
+  const T* ainv_sh = nullptr;    // set when every element has the same block: its inverse, k-major (a[k nb + row])
+  T* rbuf = nullptr;             // colour residuals for the shared-inverse pass ([largest colour][nb])
   T* x = nullptr;                // level work vectors (levels >= 1)
   T* b = nullptr;
 };
@@ -79,6 +81,7 @@ struct ldgs_ctx {
   int vprec = 0;
   int k0 = 1;
   int small_grid = 4096;       // see LaunchCfg; LDGS_SMALL_GRID overrides (tests)
+  bool shared_inverse = true;  // one inverse per level with equal blocks; LDGS_SHARED_INVERSE=0 disables
   std::vector<int> kernel_offsets;
   PrecStore<double> s64;
   PrecStore<float> s32;      // float arithmetic, float inverses
@@ -368,6 +371,40 @@ bool touches_interphase(const Level& L, int d, int64_t E) {
 }
 
 // inverse blocks of all smoothed levels into the stores that need them
+// True when every diagonal block of the level is the same matrix: constant
+// viscosity, all faces intraphase (periodic grid) with equal weights and
+// penalty blocks, one phase and one scaling.  The blocks are then translation
+// invariant; three elements' blocks are compared as a check.
+static bool uniform_blocks(const ldgs_ctx* c, const Level& L) {
+  if (!L.mu_is_const || L.NE < 1) return false;
+  for (int k = 0; k < c->g.d; ++k) {
+    const FaceSet& F = L.faces[k];
+    for (unsigned char t : F.type)
+      if (t != F_INTRA) return false;
+    auto constant = [](const std::vector<double>& v, size_t stride) {
+      for (size_t i = stride; i < v.size(); ++i)
+        if (v[i] != v[i % stride]) return false;
+      return true;
+    };
+    const size_t mt2 = (size_t)c->g.mt * c->g.mt;
+    if (!constant(F.w, 2) || !constant(F.T, mt2) || !constant(F.Tmu, mt2) || !constant(F.Trho, mt2)) return false;
+  }
+  for (size_t i = 1; i < L.chi.size(); ++i)
+    if (L.chi[i] != L.chi[0]) return false;
+  for (size_t i = 2; i < L.dscale.size(); ++i)
+    if (L.dscale[i] != L.dscale[i % 2]) return false;
+  const int nb = c->g.nb;
+  std::vector<double> A0((size_t)nb * nb), A1((size_t)nb * nb);
+  host_diag_block(L, c->g, c->B, c->P.form, 0, A0.data());
+  for (int64_t E : {L.NE / 2 + 1, L.NE - 1}) {
+    if (E >= L.NE) continue;
+    host_diag_block(L, c->g, c->B, c->P.form, E, A1.data());
+    for (size_t i = 0; i < A0.size(); ++i)
+      if (std::fabs(A1[i] - A0[i]) > 1e-13 * (std::fabs(A0[i]) + 1.0)) return false;
+  }
+  return true;
+}
+
 void build_inverses(ldgs_ctx* c, bool need64, bool need32, bool need16) {
   const int nb = c->g.nb;
   const size_t nb2 = (size_t)nb * nb;
@@ -394,6 +431,39 @@ void build_inverses(ldgs_ctx* c, bool need64, bool need32, bool need16) {
       }
       reg[col] = (int64_t)L.elems[col].size() - (int64_t)rest.size();
       order.insert(order.end(), rest.begin(), rest.end());
+    }
+    if (L.uniform) {
+      // one inverse for the level, held dense (FP64 for the FP64 cycle, FP32
+      // for both the FP32 and the BF16-inverse cycles: nothing to stream)
+      std::vector<double> A(nb2), inv(nb2);
+      host_diag_block(L, c->g, c->B, c->P.form, 0, A.data());
+      if (!block_inverse(nb, A.data(), inv.data(), 1e-14))
+        throw Fail{LDGS_E_SINGULAR_BLOCK, "singular element block 0 on level " + std::to_string(l)};
+      auto kmajor = [&](int bytes) {
+        std::vector<double> t((size_t)shared_inverse_rows(nb, bytes) * nb, 0.0);
+        for (int r = 0; r < nb; ++r)
+          for (int k = 0; k < nb; ++k) t[(size_t)k * nb + r] = inv[(size_t)r * nb + k];
+        return t;
+      };
+      int64_t maxc = 0;
+      for (int col = 0; col < L.ncol; ++col) maxc = std::max(maxc, off[col + 1] - off[col]);
+      int* elems = dalloc<int>(c, L.NE);
+      HIPCHK(hipMemcpy(elems, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice));
+      auto set = [&](auto& S) {
+        using T = std::remove_pointer_t<decltype(S.lv[l].x)>;
+        PrecLevel<T>& pl = S.lv[l];
+        pl.ainv_sh = upload<T>(c, kmajor((int)sizeof(T)));
+        pl.rbuf = dalloc<T>(c, (size_t)maxc * nb);
+        pl.inv = nullptr;
+        pl.elems = elems;
+        pl.col_off = off;
+        pl.col_reg = reg;
+        pl.inv_stride = 0;
+      };
+      if (need64) set(c->s64);
+      if (need32) set(c->s32);
+      if (need16) set(c->s16);
+      continue;
     }
     double* inv64 = need64 ? dalloc<double>(c, L.NE * st64) : nullptr;
     float* inv32 = need32 ? dalloc<float>(c, L.NE * st32) : nullptr;
@@ -537,6 +607,11 @@ void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* 
     HIPCHK(hipEventRecord(e0, c->stream));
   }
   const int64_t nreg = pl.col_reg.empty() ? cnt : pl.col_reg[col];
+  if (pl.ainv_sh) {
+    // one inverse for the level: residuals of the colour, then the shared update
+    LCHK(launch_colour_residual<T>(cfg, pl.view, c->tab, pl.elems + o, cnt, b, x, pl.rbuf));
+    LCHK(launch_shared_update<T>(c->stream, cnt, c->g.nb, pl.ainv_sh, pl.rbuf, pl.elems + o, x));
+  } else
   // (split only large launches: on coarse levels the second launch would cost
   // more than the extended stencil)
   if (!pl.view.iface || nreg == cnt || cnt < c->small_grid) {
@@ -807,6 +882,7 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
       const long v = std::strtol(sg, nullptr, 10);
       if (v >= 1) c->small_grid = (int)v;
     }
+    if (const char* si = std::getenv("LDGS_SHARED_INVERSE")) c->shared_inverse = std::strtol(si, nullptr, 10) != 0;
     c->k0 = kernel_dim(P);
     if (c->k0 == 1) c->kernel_offsets = {P.dim * c->g.nq};
     else for (int i = 0; i <= P.dim; ++i) c->kernel_offsets.push_back(i * c->g.nq);
@@ -821,6 +897,8 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
     if (P.diag_scaling)
       for (Level& L : c->levels) set_scaling(L, c->g);
     build_smoother_host(c.get());
+    if (c->shared_inverse)
+      for (size_t l = 0; l + 1 < c->levels.size(); ++l) c->levels[l].uniform = uniform_blocks(c.get(), c->levels[l]);
     build_bottom(c.get());
     if (!c->host_only) {
       if (P.hip_stream) c->stream = (hipStream_t)P.hip_stream;
@@ -886,6 +964,12 @@ ldgs_status ldgs_level_info(const ldgs_ctx* ctx, int level, int* n_l, int* n_lev
   if (n_l) *n_l = ctx->levels[level].n;
   if (n_levels) *n_levels = (int)ctx->levels.size();
   if (n_colours) *n_colours = ctx->levels[level].ncol;
+  return LDGS_OK;
+}
+
+ldgs_status ldgs_level_shared_inverse(const ldgs_ctx* ctx, int level, int* shared) {
+  if (!ctx || !shared || level < 0 || level >= (int)ctx->levels.size()) return LDGS_E_ARG;
+  *shared = ctx->levels[level].uniform ? 1 : 0;
   return LDGS_OK;
 }
 

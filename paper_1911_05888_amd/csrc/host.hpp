@@ -49,6 +49,7 @@ struct Level {
   int ncol = 0;
   std::vector<int> colour;           // per element
   std::vector<std::vector<int>> elems;   // per colour, element ids
+  bool uniform = false;              // every diagonal block is the same matrix (one inverse for the level)
 };
 
 struct Geometry {

@@ -832,6 +832,93 @@ __global__ __launch_bounds__(NT) void k_residual(DevLevel<T> lev, TabT<T> tab, c
   for (int t = threadIdx.x; t < S::NB; t += NT) out[(size_t)E * S::NB + t] = w.res[t];
 }
 
+// Residual of the listed elements into a compact buffer: r[idx] = (b - A x)_E,
+// E = elems[idx] (the first half of a colour pass with a shared inverse).
+template <typename T, int D, int P, int NT, bool IF>
+__global__ __launch_bounds__(NT) void k_colour_residual(DevLevel<T> lev, TabT<T> tab, const int* __restrict__ elems,
+                                                        const T* __restrict__ b, const T* __restrict__ x,
+                                                        T* __restrict__ r) {
+  using S = Sz<D, P, IF>;
+  __shared__ Work<T, D, P, IF> w;
+  const int idx = xcd_remap(blockIdx.x, gridDim.x);
+  element_operator<T, D, P, NT, IF>(lev, tab, elems[idx], x, b, 0, w);
+  for (int t = threadIdx.x; t < S::NB; t += NT) r[(size_t)idx * S::NB + t] = w.res[t];
+}
+
+// x_E += Ainv r[idx] for the listed elements, Ainv shared by every element of
+// the level (translation-invariant operator: constant coefficients, periodic
+// grid).  A dense product Ainv [NB x NB] * R [NB x n] on vector ALUs (n is one
+// colour, tens of thousands of columns; the work is bound by streaming R and x).
+// Ainv is given k-major and zero-padded to RS rows (a[k * NB + row], k < RS);
+// it is staged in LDS when it fits in 64 KB, else read through the caches.
+// A work-group of 256 threads has G = 256 / NB element groups of NB threads
+// (one output row each); a thread accumulates Q elements of its group, so a
+// tile holds TE = G * Q elements.  R tiles are staged in LDS with row stride
+// RS (16-byte aligned) and read as 16-byte broadcasts.
+constexpr int SU_THREADS = 256;
+template <typename T, int NB>
+struct SuCfg {
+  static constexpr int V = 16 / sizeof(T);                    // entries per 16-byte read
+  static constexpr int RS = (NB + V - 1) / V * V;
+  static constexpr int G = SU_THREADS / NB;
+  static constexpr int Q = 16;
+  static constexpr int TE = G * Q;
+  static constexpr bool A_LDS = (size_t)RS * NB * sizeof(T) + (size_t)TE * RS * sizeof(T) <= 65536;
+  static constexpr int A_SZ = A_LDS ? RS * NB : 1;
+};
+
+template <typename T, int NB>
+__global__ __launch_bounds__(SU_THREADS) void k_shared_update(int nelems, const T* __restrict__ ainv,
+                                                              const T* __restrict__ r, const int* __restrict__ elems,
+                                                              T* __restrict__ x) {
+  using C = SuCfg<T, NB>;
+  using V4 = std::conditional_t<sizeof(T) == 8, double2, float4>;
+  __shared__ alignas(16) T As[C::A_SZ];
+  __shared__ alignas(16) T Rs[C::TE * C::RS];
+  const int tid = threadIdx.x;
+  if constexpr (C::A_LDS)
+    for (int i = tid; i < C::RS * NB; i += SU_THREADS) As[i] = ainv[i];
+  const T* A = C::A_LDS ? As : ainv;
+  const int g = tid / NB, row = tid - g * NB;
+  const bool active = g < C::G;
+  const int ntile = (nelems + C::TE - 1) / C::TE;
+  for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int base = tile * C::TE;
+    const int cnt = min(C::TE, nelems - base);
+    __syncthreads();
+    for (int i = tid; i < C::TE * C::RS; i += SU_THREADS) {
+      const int e = i / C::RS, k = i - e * C::RS;
+      Rs[i] = (e < cnt && k < NB) ? r[(size_t)(base + e) * NB + k] : T(0);
+    }
+    __syncthreads();
+    if (active) {
+      T acc[C::Q];
+#pragma unroll
+      for (int q = 0; q < C::Q; ++q) acc[q] = 0;
+      const T* Rg = Rs + g * C::Q * C::RS;
+#pragma unroll 2
+      for (int k = 0; k < C::RS; k += C::V) {
+        T a[C::V];
+#pragma unroll
+        for (int j = 0; j < C::V; ++j) a[j] = A[(k + j) * NB + row];
+#pragma unroll
+        for (int q = 0; q < C::Q; ++q) {
+          const V4 rv = *reinterpret_cast<const V4*>(Rg + q * C::RS + k);
+          if constexpr (C::V == 4)
+            acc[q] += a[0] * rv.x + a[1] * rv.y + a[2] * rv.z + a[3] * rv.w;
+          else
+            acc[q] += a[0] * rv.x + a[1] * rv.y;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < C::Q; ++q) {
+        const int e = g * C::Q + q;
+        if (e < cnt) x[(size_t)elems[base + e] * NB + row] += acc[q];
+      }
+    }
+  }
+}
+
 // product of 1D injection entries: (P_o)[af][ac] for child offset bits o
 template <typename T, int D, int M>
 __device__ __forceinline__ T pfull(const TabT<T>& tab, int o, int af, int ac) {
@@ -1087,6 +1174,49 @@ int launch_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab
 }
 
 template <typename T>
+int launch_colour_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const int* elems,
+                           int64_t nelems, const T* b, const T* x, T* r) {
+  if (nelems <= 0) return 0;
+  bool bad = false;
+  hipStream_t st = (hipStream_t)c.stream;
+  const TabT<T> tt = tab_of<T>(tab);
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_colour_residual<T, D_, P_, NT_, IF_>), dim3((unsigned)nelems), dim3(NT_), 0, st,
+                                                lev, tt, elems, b, x, r); }); })) bad = true; })) return 2;
+  if (bad) return 2;
+  return hip_ok();
+}
+
+template <typename T, int NB>
+static void shared_update_nb(hipStream_t st, int64_t nelems, const T* ainv, const T* r, const int* elems, T* x) {
+  using C = SuCfg<T, NB>;
+  int64_t g = (nelems + C::TE - 1) / C::TE;
+  if (g > 512) g = 512;
+  hipLaunchKernelGGL((k_shared_update<T, NB>), dim3((unsigned)g), dim3(SU_THREADS), 0, st, (int)nelems, ainv, r,
+                     elems, x);
+}
+
+template <typename T>
+int launch_shared_update(void* stream, int64_t nelems, int nb, const T* ainv, const T* r, const int* elems, T* x) {
+  if (nelems <= 0) return 0;
+  hipStream_t st = (hipStream_t)stream;
+  switch (nb) {
+    case 12: shared_update_nb<T, 12>(st, nelems, ainv, r, elems, x); break;
+    case 27: shared_update_nb<T, 27>(st, nelems, ainv, r, elems, x); break;
+    case 48: shared_update_nb<T, 48>(st, nelems, ainv, r, elems, x); break;
+    case 32: shared_update_nb<T, 32>(st, nelems, ainv, r, elems, x); break;
+    case 108: shared_update_nb<T, 108>(st, nelems, ainv, r, elems, x); break;
+    case 256: shared_update_nb<T, 256>(st, nelems, ainv, r, elems, x); break;
+    default: return 2;
+  }
+  return hip_ok();
+}
+
+int shared_inverse_rows(int nb, int bytes) {
+  const int v = 16 / bytes;
+  return (nb + v - 1) / v * v;
+}
+
+template <typename T>
 int launch_residual_restrict(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const T* b, const T* x,
                              T* rc) {
   int64_t NC = 1;
@@ -1187,6 +1317,12 @@ template int launch_residual_restrict<double>(const LaunchCfg&, const DevLevel<d
                                               const double*, double*);
 template int launch_residual_restrict<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const float*,
                                              const float*, float*);
+template int launch_colour_residual<double>(const LaunchCfg&, const DevLevel<double>&, const Tab1D&, const int*,
+                                            int64_t, const double*, const double*, double*);
+template int launch_colour_residual<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const int*, int64_t,
+                                           const float*, const float*, float*);
+template int launch_shared_update<double>(void*, int64_t, int, const double*, const double*, const int*, double*);
+template int launch_shared_update<float>(void*, int64_t, int, const float*, const float*, const int*, float*);
 template int launch_prolong_add<double>(const LaunchCfg&, int, const Tab1D&, const double*, double*);
 template int launch_prolong_add<float>(const LaunchCfg&, int, const Tab1D&, const float*, float*);
 template int launch_dense_mv<double, double>(void*, int64_t, const double*, const double*, const double*, double, double*);

@@ -107,6 +107,15 @@ int launch_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab
 template <typename T>
 int launch_residual_restrict(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab,
                              const T* b, const T* x, T* rc);
+// colour pass with an inverse shared by all elements: residuals of the listed
+// elements into r (compact, [nelems][nb]), then x_E += Ainv r (Ainv k-major,
+// a[k nb + row], zero-padded to shared_inverse_rows(nb, sizeof(T)) rows)
+int shared_inverse_rows(int nb, int bytes);
+template <typename T>
+int launch_colour_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const int* elems,
+                           int64_t nelems, const T* b, const T* x, T* r);
+template <typename T>
+int launch_shared_update(void* stream, int64_t nelems, int nb, const T* ainv, const T* r, const int* elems, T* x);
 template <typename T>
 int launch_prolong_add(const LaunchCfg& c, int n_fine, const Tab1D& tab, const T* xc, T* x);
 // y = z + sign * M x, M dense row-major FP64 N x N, z optional

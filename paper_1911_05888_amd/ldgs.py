@@ -92,6 +92,7 @@ _SIGS = {
     "ldgs_learned_train": ([C.POINTER(TrainArgs), C.POINTER(C.c_float), _D, C.POINTER(C.c_float)]),
     "ldgs_project_kernel": ([_P, _P]),
     "ldgs_level_info": ([_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "ldgs_level_shared_inverse": ([_P, C.c_int, C.POINTER(C.c_int)]),
     "ldgs_level_smooth_colour": ([_P, C.c_int, C.c_int, _P, _P]),
     "ldgs_level_residual_restrict": ([_P, C.c_int, _P, _P, _P]),
     "ldgs_level_prolong_add": ([_P, C.c_int, _P, _P]),
@@ -348,6 +349,11 @@ class Context:
         n, nl, nc = C.c_int(), C.c_int(), C.c_int()
         self._check(_lib.ldgs_level_info(self._h, level, C.byref(n), C.byref(nl), C.byref(nc)))
         return n.value, nl.value, nc.value
+
+    def level_shared_inverse(self, level):
+        v = C.c_int()
+        self._check(_lib.ldgs_level_shared_inverse(self._h, level, C.byref(v)))
+        return bool(v.value)
 
     def level_smooth_colour(self, level, colour, b, x):
         self._check(_lib.ldgs_level_smooth_colour(self._h, level, colour, _dptr(b), _dptr(x)))

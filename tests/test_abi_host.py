@@ -141,6 +141,23 @@ def test_host_setup_matches_oracle(name):
     assert np.linalg.norm(b - bot.A @ x) <= 1e-13 * scale
 
 
+@pytest.mark.parametrize("name", list(HOST_CASES))
+def test_shared_inverse_levels_are_those_with_equal_blocks(name):
+    """A level holds one inverse for all its elements exactly when the oracle's
+    diagonal blocks of that level are all the same matrix."""
+    from oracle import build_hierarchy
+    prob = HOST_CASES[name]()
+    H = build_hierarchy(prob)
+    ctx = _ctx(prob)
+    for l, lv in enumerate(H.levels[:-1]):
+        B = np.asarray(lv.Ainv)
+        equal = np.abs(B - B[0]).max() <= 1e-12 * np.abs(B[0]).max()
+        assert ctx.level_shared_inverse(l) == equal, (name, l)
+        if equal:                                       # the one inverse is the oracle's
+            assert np.abs(ctx.level_block_inverse(l, lv.NE - 1) - B[0]).max() <= 1e-12 * np.abs(B[0]).max()
+    assert not ctx.level_shared_inverse(len(H.levels) - 1)
+
+
 @pytest.mark.parametrize("name", ["c1_n8_p2", "c2_n8_p3", "c3_n8_p1", "c4a_n16_p2"])
 def test_host_rhs_matches_oracle(name):
     from oracle import build_hierarchy

@@ -169,3 +169,40 @@ def test_one_wavefront_kernels_match_oracle(name, monkeypatch):
             colour_pass(lv.A, lv.Ainv, xo, b, np.nonzero(lv.colours == c)[0], lv.nb)
             ctx.level_smooth_colour(l, c, bg, xg)
             assert _rel(_host(xg), xo) <= 1e-11, (name, l, c)
+
+
+def test_shared_inverse_matches_per_element_inverses(monkeypatch):
+    """3D unsteady periodic workload at 32^3 (colours of 4096 elements, the
+    one-wavefront-per-element launches): colour passes with the level's one
+    inverse agree with those that stream a copy per element (the shared path
+    turned off with LDGS_SHARED_INVERSE=0), in FP64 and FP32."""
+    import torch
+    from paper_1911_05888_amd import Context, V_FP32
+    from synth import c3_unsteady_periodic
+    prob = c3_unsteady_periodic(n=32, p=2, re_eff=10.0, h_ref=1.0 / 64)
+    print("[scale] shared vs per-element inverses, 3D unsteady 32^3 Q_2", flush=True)
+    ctxs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("LDGS_SHARED_INVERSE", flag)
+        ctxs.append(Context(prob, build_precisions=(1 << V_FP32)))
+    shared, plain = ctxs
+    assert shared.level_shared_inverse(0) and not plain.level_shared_inverse(0)
+    N = shared.ndof
+    rng = np.random.Generator(np.random.PCG64(44))
+    x0 = rng.standard_normal(N)
+    b = rng.standard_normal(N)
+    _, _, ncol = shared.level_info(0)
+    xs, xp, bg = _dev(x0), _dev(x0), _dev(b)
+    for c in range(ncol):
+        shared.level_smooth_colour(0, c, bg, xs)
+        plain.level_smooth_colour(0, c, bg, xp)
+        assert _rel(_host(xs), _host(xp)) <= 1e-12, c
+    xs = torch.tensor(x0, dtype=torch.float32, device="cuda")
+    xp = xs.clone()
+    b32 = torch.tensor(b, dtype=torch.float32, device="cuda")
+    for c in range(ncol):
+        shared.level_smooth_colour_f32(0, c, V_FP32, b32, xs)
+        plain.level_smooth_colour_f32(0, c, V_FP32, b32, xp)
+    e = _rel(_host(xs.double()), _host(xp.double()))
+    print(f"[scale] FP32 shared vs per-element: {e:.2e}", flush=True)
+    assert e <= 1e-4
