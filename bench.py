@@ -16,9 +16,9 @@ the BF16-block variant, are measured beside it.
 The roofline object covers the dominant kernel (the finest-level smoother
 colour pass), timed with HIP events on the library's stream during the timed
 solves; the algorithmic bytes per launch are (elements in the colour) x
-(n_b^2 inverse entries + 3 n_b vector entries + (p+2)^d viscosity values) x
-the storage width; on levels whose blocks are all equal (periodic, constant
-coefficients) the one inverse is not streamed and the n_b^2 term is dropped.  cpu_baseline times the FP64 oracle on a bounded sample.
+(n_b (n_b + 1) / 2 entries of the symmetric inverse + 3 n_b vector entries +
+(p+2)^d viscosity values) x the storage width; on levels whose blocks are all equal (periodic, constant
+coefficients) the one inverse is not streamed and that term is dropped.  cpu_baseline times the FP64 oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -40,7 +40,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_smooth_colour_c2_n256_p3.
 
 def smoother_bytes_per_launch(prob, ncolours, inv_bytes, vec_bytes):
     nb = prob.nb
-    per_elem = nb * nb * inv_bytes + 3 * nb * vec_bytes + (prob.p + 2) ** prob.dim * vec_bytes
+    # the inverse is symmetric: n_b (n_b + 1) / 2 entries determine it
+    per_elem = nb * (nb + 1) // 2 * inv_bytes + 3 * nb * vec_bytes + (prob.p + 2) ** prob.dim * vec_bytes
     return prob.n_elements / ncolours * per_elem
 
 

@@ -318,18 +318,22 @@ void upload_ops(ldgs_ctx* c, PrecStore<T>& S, bool all_levels) {
   S.ops = true;
 }
 
-// entries of one element's inverse in the smoother's lane-blocked layout
-// (see inv_layout): inv is row-major nb x nb, out receives nb * NBP values
+// entries of one element's inverse in the smoother's symmetric tile layout
+// (see sym_tiles): inv is row-major nb x nb; its symmetric part is stored, out
+// receives NTILE * 256 values
 static void arrange_inverse(const double* inv, int nb, int bytes, double* out) {
-  const InvLayout L = inv_layout(nb, bytes);
-  const int RGS = L.RG * L.S;
-  for (int kk = 0; kk < L.CS; ++kk)
-    for (int l = 0; l < RGS; ++l) {
-      const int g = l % L.RG, s = l / L.RG, col = s * L.CS + kk;
-      for (int v = 0; v < L.V; ++v) {
-        const int row = L.V * g + v;
-        out[((size_t)kk * RGS + l) * L.V + v] = row < nb ? inv[(size_t)row * nb + col] : 0.0;
-      }
+  const SymTiles L = sym_tiles(nb, bytes);
+  auto sym = [&](int r, int c) {
+    return (r < nb && c < nb) ? 0.5 * (inv[(size_t)r * nb + c] + inv[(size_t)c * nb + r]) : 0.0;
+  };
+  for (int i = 0; i < L.TR; ++i)
+    for (int j = i; j < L.TR; ++j) {
+      const int t = i * L.TR - i * (i - 1) / 2 + (j - i);
+      for (int l = 0; l < 64; ++l)
+        for (int v = 0; v < 4; ++v) {
+          const int h = v / L.EL, u = v % L.EL;
+          out[((size_t)(t * L.H + h) * 64 + l) * L.EL + u] = sym(16 * i + l / 4, 16 * j + 4 * (l % 4) + v);
+        }
     }
 }
 
@@ -408,9 +412,9 @@ static bool uniform_blocks(const ldgs_ctx* c, const Level& L) {
 void build_inverses(ldgs_ctx* c, bool need64, bool need32, bool need16) {
   const int nb = c->g.nb;
   const size_t nb2 = (size_t)nb * nb;
-  const size_t st64 = (size_t)nb * inv_layout(nb, 8).NBP;
-  const size_t st32 = (size_t)nb * inv_layout(nb, 4).NBP;
-  const size_t st16 = (size_t)nb * inv_layout(nb, 2).NBP;
+  const size_t st64 = (size_t)sym_tiles(nb, 8).NTILE * 256;
+  const size_t st32 = (size_t)sym_tiles(nb, 4).NTILE * 256;
+  const size_t st16 = (size_t)sym_tiles(nb, 2).NTILE * 256;
   for (size_t l = 0; l + 1 < c->levels.size(); ++l) {
     Level& L = c->levels[l];
     std::vector<int64_t> off(L.ncol + 1, 0);

@@ -752,27 +752,40 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
   elem_compute<T, D, P, NT, IF>(lev, tab, E, d.vmask, mode, d.br, d.dsv[0], d.dsp[0], w, lane);
 }
 
-// 16-byte word of the inverse and entry v of it in the arithmetic type
+// Raw words of one lane's load of the inverse (sym_tiles: LB bytes) and entry
+// u of them in the arithmetic type
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename TI>
+using InvWord = std::conditional_t<sizeof(TI) == 2, u32x2, u32x4>;
 
 template <typename T, typename TI>
-__device__ __forceinline__ T inv_entry(const u32x4& raw, int v) {
+__device__ __forceinline__ T inv_entry(const InvWord<TI>& raw, int u) {
   if constexpr (sizeof(TI) == 8) {
-    const unsigned long long bits = (unsigned long long)raw[2 * v] | ((unsigned long long)raw[2 * v + 1] << 32);
+    const unsigned long long bits = (unsigned long long)raw[2 * u] | ((unsigned long long)raw[2 * u + 1] << 32);
     return (T)__longlong_as_double((long long)bits);
   } else if constexpr (sizeof(TI) == 4) {
-    return (T)__uint_as_float(raw[v]);
+    return (T)__uint_as_float(raw[u]);
   } else {
-    const unsigned int word = raw[v >> 1];
-    const unsigned int bits = (v & 1) ? (word & 0xffff0000u) : (word << 16);
+    const unsigned int word = raw[u >> 1];
+    const unsigned int bits = (u & 1) ? (word & 0xffff0000u) : (word << 16);
     return (T)__uint_as_float(bits);
   }
 }
 
+template <typename T>
+__device__ __forceinline__ T shfl_xor64(T v, int m) {
+  return __shfl_xor(v, m, 64);
+}
+
 // ---------------------------------------------------------------------------
 // Smoother: one colour pass.  x_E += Ainv_E (b - A x)_E for the listed elements.
-// The element's inverse (lane-blocked layout, see inv_layout) is prefetched
-// into registers before the residual is evaluated.
+// Ainv_E is symmetric and stored as its upper 16 x 16 tiles (sym_tiles); the
+// first wave forms the product: for tile (i, j) lane (row, 4 columns) adds
+// T r_j to its row of y_i and, off the diagonal, T^T r_i to its columns of y_j;
+// the partial sums are reduced across lanes.  The first tiles are requested
+// before the residual is evaluated.
 // ---------------------------------------------------------------------------
 template <typename T, typename TI, int D, int P, int NT, bool IF>
 __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> tab, const int* __restrict__ elems,
@@ -780,46 +793,90 @@ __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
                                                       T* __restrict__ x) {
   using S = Sz<D, P>;
   constexpr int NB = S::NB;
-  constexpr InvLayout LY = inv_layout(NB, (int)sizeof(TI));
-  constexpr int V = LY.V, RGS = LY.RG * LY.S, CS = LY.CS;
-  // chunks requested before the residual is evaluated: all of a bf16 block, half
-  // of an FP32 one (the rest is loaded in the product; fewer registers held)
-  constexpr int PF = sizeof(TI) == 2 ? (CS < 16 ? CS : 16) : (CS / 2 > 0 ? CS / 2 : 1);
+  constexpr SymTiles LY = sym_tiles(NB, (int)sizeof(TI));
+  constexpr int TR = LY.TR, NTILE = LY.NTILE, H = LY.H, EL = LY.EL;
+  using Word = InvWord<TI>;
+  // tiles requested before the residual is evaluated (32 registers of words)
+  constexpr int PFMAX = 32 / (H * (int)(sizeof(Word) / 4));
+  constexpr int PF = NTILE < PFMAX ? NTILE : PFMAX;
   __shared__ Work<T, D, P, IF> w;
-  __shared__ T part[LY.S][LY.NBP];
+  __shared__ T part[2][16 * TR];
   const int lane = threadIdx.x;
+  const int l = lane & 63;
+  const bool w0 = lane < 64;
   const int idx = xcd_remap(blockIdx.x, gridDim.x);
   const int E = elems[idx];
-  const u32x4* Ai = reinterpret_cast<const u32x4*>(inv + (size_t)idx * NB * LY.NBP);
-  u32x4 pre[PF];
+  const Word* Ai = reinterpret_cast<const Word*>(inv + (size_t)idx * NTILE * 256);
+  Word pre[PF][H];
   element_operator<T, D, P, NT, IF>(lev, tab, E, x, b, 0, w, [&]() {
-    if (lane < RGS) {
+    if (w0) {
 #pragma unroll
-      for (int kk = 0; kk < PF; ++kk) pre[kk] = __builtin_nontemporal_load(&Ai[kk * RGS + lane]);
+      for (int t = 0; t < PF; ++t)
+#pragma unroll
+        for (int h = 0; h < H; ++h) pre[t][h] = __builtin_nontemporal_load(&Ai[(t * H + h) * 64 + l]);
     }
   });
-  if (lane < RGS) {
-    const int g = lane % LY.RG, s = lane / LY.RG;
-    T y[V];
+  if (w0) {
+    const int row = l >> 2, c4 = (l & 3) * 4;
+    T dir[TR], trn[TR][4];
 #pragma unroll
-    for (int v = 0; v < V; ++v) y[v] = 0;
+    for (int i = 0; i < TR; ++i) {
+      dir[i] = 0;
 #pragma unroll
-    for (int kk = 0; kk < CS; ++kk) {
-      const u32x4 raw = (kk < PF) ? pre[kk < PF ? kk : 0] : __builtin_nontemporal_load(&Ai[kk * RGS + lane]);
-      const T r = w.res[s * CS + kk];
-#pragma unroll
-      for (int v = 0; v < V; ++v) y[v] += inv_entry<T, TI>(raw, v) * r;
+      for (int v = 0; v < 4; ++v) trn[i][v] = 0;
     }
 #pragma unroll
-    for (int v = 0; v < V; ++v) part[s][g * V + v] = y[v];
+    for (int i = 0; i < TR; ++i) {
+      const T ri = (16 * i + row < NB) ? w.res[16 * i + row] : (T)0;
+#pragma unroll
+      for (int j = i; j < TR; ++j) {
+        const int t = i * TR - i * (i - 1) / 2 + (j - i);
+        Word raw[H];
+#pragma unroll
+        for (int h = 0; h < H; ++h)
+          raw[h] = (t < PF) ? pre[t < PF ? t : 0][h] : __builtin_nontemporal_load(&Ai[(t * H + h) * 64 + l]);
+        T a[4], rj[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          a[v] = inv_entry<T, TI>(raw[v / EL], v % EL);
+          const int cj = 16 * j + c4 + v;
+          rj[v] = cj < NB ? w.res[cj] : (T)0;
+        }
+        dir[i] += a[0] * rj[0] + a[1] * rj[1] + a[2] * rj[2] + a[3] * rj[3];
+        if (j != i) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) trn[j][v] += a[v] * ri;
+        }
+      }
+    }
+    // dir: sum over the 4 lanes of a row; trn: over the 16 lanes of a column set
+#pragma unroll
+    for (int i = 0; i < TR; ++i) {
+      dir[i] += shfl_xor64(dir[i], 1);
+      dir[i] += shfl_xor64(dir[i], 2);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        T s = trn[i][v];
+        s += shfl_xor64(s, 4);
+        s += shfl_xor64(s, 8);
+        s += shfl_xor64(s, 16);
+        s += shfl_xor64(s, 32);
+        trn[i][v] = s;
+      }
+    }
+    if ((l & 3) == 0) {
+#pragma unroll
+      for (int i = 0; i < TR; ++i) part[0][16 * i + row] = dir[i];
+    }
+    if (l < 4) {
+#pragma unroll
+      for (int i = 0; i < TR; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part[1][16 * i + c4 + v] = trn[i][v];
+    }
   }
   __syncthreads();
-  for (int row = lane; row < NB; row += NT) {
-    T acc = 0;
-#pragma unroll
-    for (int s = 0; s < LY.S; ++s) acc += part[s][row];
-    x[(size_t)E * NB + row] += acc;
-  }
+  for (int r = lane; r < NB; r += NT) x[(size_t)E * NB + r] += part[0][r] + part[1][r];
 }
 
 template <typename T, int D, int P, int NT, bool IF>

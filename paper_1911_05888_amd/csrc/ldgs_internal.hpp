@@ -45,24 +45,26 @@ struct Tab1D {
   double P[2][MAXM * MAXM];
 };
 
-// Lane-blocked layout of one element's inverse block for the smoother's
-// matrix-vector product.  V = 16 / (bytes per entry) values per 16-byte load,
-// NBP = nb rounded up to a multiple of V (padding rows are zero), RG = NBP / V
-// row groups, S = number of column subsets (the largest divisor of nb with
-// RG * S <= 64 lanes), CS = nb / S columns per subset.  Lane l = g + RG * s
-// owns rows V g .. V g + V - 1 of columns s * CS + kk, kk < CS; its chunk kk
-// is stored at entry offset (kk * RG * S + l) * V, so the RG * S lanes read
-// consecutive 16-byte words at every step.  Element stride: nb * NBP entries.
-struct InvLayout {
-  int V, NBP, RG, S, CS;
+// Symmetric tile layout of one element's inverse block for the smoother's
+// matrix-vector product.  The diagonal block of the (symmetric) LDG operator
+// is symmetric, so is its inverse: only the tiles on and above the diagonal
+// are stored.  The block, zero-padded to 16 TR rows and columns
+// (TR = ceil(nb / 16)), is cut into 16 x 16 tiles; tile (i, j), i <= j, has
+// number t = i TR - i (i - 1) / 2 + (j - i), NTILE = TR (TR + 1) / 2 tiles.
+// Lane l < 64 of a tile owns row l / 4 and columns 4 (l % 4) + v, v < 4.  One
+// load per lane reads LB = min(16, 4 * bytes) bytes (EL = LB / bytes entries);
+// H = 4 * bytes / LB loads cover the lane's four entries.  Entry v = h EL + u
+// of lane l in tile t is stored at entry offset ((t H + h) 64 + l) EL + u, so
+// the 64 lanes read consecutive words at every load.  Element stride: NTILE *
+// 256 entries.
+struct SymTiles {
+  int TR, NTILE, LB, EL, H;
 };
-constexpr InvLayout inv_layout(int nb, int bytes) {
-  InvLayout L{16 / bytes, 0, 0, 1, nb};
-  L.NBP = (nb + L.V - 1) / L.V * L.V;
-  L.RG = L.NBP / L.V;
-  for (int s = 1; s <= 64; ++s)
-    if (nb % s == 0 && L.RG * s <= 64) L.S = s;
-  L.CS = nb / L.S;
+constexpr SymTiles sym_tiles(int nb, int bytes) {
+  SymTiles L{(nb + 15) / 16, 0, 4 * bytes < 16 ? 4 * bytes : 16, 0, 0};
+  L.NTILE = L.TR * (L.TR + 1) / 2;
+  L.EL = L.LB / bytes;
+  L.H = 4 * bytes / L.LB;
   return L;
 }
 

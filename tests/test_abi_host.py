@@ -179,19 +179,32 @@ def test_host_only_context_refuses_device_calls():
 
 
 def test_inverse_layout_covers_every_entry():
-    """The smoother's lane-blocked layout (include-level contract shared by the
-    host packing and the kernel) places every entry of the block exactly once."""
-    for nb in (12, 27, 32, 48, 108):
+    """The smoother's symmetric tile layout (the contract between the host
+    packing and the kernel): the stored upper 16 x 16 tiles, read as the kernel
+    reads them (tile (i, j) as T and, off the diagonal, T^T), give every entry
+    of the block exactly once, and the stored words are all distinct."""
+    for nb in (12, 27, 32, 48, 108, 256):
         for bytes_ in (8, 4, 2):
-            V = 16 // bytes_
-            NBP = (nb + V - 1) // V * V
-            RG = NBP // V
-            S = max(s for s in range(1, 65) if nb % s == 0 and RG * s <= 64)
-            CS = nb // S
-            seen = np.zeros((NBP, nb), dtype=int)
-            for kk in range(CS):
-                for l in range(RG * S):
-                    g, s = l % RG, l // RG
-                    for v in range(V):
-                        seen[V * g + v, s * CS + kk] += 1
+            TR = (nb + 15) // 16
+            NTILE = TR * (TR + 1) // 2
+            LB = min(16, 4 * bytes_)
+            EL = LB // bytes_
+            H = 4 * bytes_ // LB
+            seen = np.zeros((16 * TR, 16 * TR), dtype=int)
+            offsets = set()
+            for i in range(TR):
+                for j in range(i, TR):
+                    t = i * TR - i * (i - 1) // 2 + (j - i)
+                    assert 0 <= t < NTILE
+                    for l in range(64):
+                        for v in range(4):
+                            h, u = divmod(v, EL)
+                            off = ((t * H + h) * 64 + l) * EL + u
+                            assert off not in offsets and off < NTILE * 256
+                            offsets.add(off)
+                            r, c = 16 * i + l // 4, 16 * j + 4 * (l % 4) + v
+                            seen[r, c] += 1
+                            if i != j:
+                                seen[c, r] += 1
             assert (seen == 1).all()
+            assert len(offsets) == NTILE * 256
