@@ -53,6 +53,7 @@ struct PrecLevel {
   int* elems = nullptr;          // colour-major element ids
   std::vector<int64_t> col_off;  // colour offsets (elements)
   std::vector<int64_t> col_reg;  // per colour: leading elements whose evaluation touches no interphase face
+  bool parity = false;           // parity colouring, each colour in increasing order (kernels compute the ids)
   size_t inv_stride = 0;         // entries per element in the inverse layout
   const T* ainv_sh = nullptr;    // set when every element has the same block: its inverse, k-major (a[k nb + row])
   T* rbuf = nullptr;             // colour residuals for the shared-inverse pass ([largest colour][nb])
@@ -106,6 +107,8 @@ struct ldgs_ctx {
   double* d_sums = nullptr;         // [2] sums of squares (velocity, pressure)
   double *w_xold = nullptr, *w_zl = nullptr, *w_r64b = nullptr;
   float* w_r32 = nullptr;
+  double* w_rf64 = nullptr;         // fine residual scratch of the split residual + restriction (small grids)
+  float* w_rf32 = nullptr;
   double *w_cb = nullptr, *w_cx = nullptr, *w_ce = nullptr;
   int* d_orig = nullptr;
   int64_t d_orig_cap = 0;
@@ -194,6 +197,12 @@ void validate(const ldgs_problem& P) {
 }
 
 // smoothed levels: colouring, blocks, inverses
+int log2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
 void build_smoother_host(ldgs_ctx* c) {
   const int d = c->g.d;
   for (size_t l = 0; l + 1 < c->levels.size(); ++l) {
@@ -436,6 +445,18 @@ void build_inverses(ldgs_ctx* c, bool need64, bool need32, bool need16) {
       reg[col] = (int64_t)L.elems[col].size() - (int64_t)rest.size();
       order.insert(order.end(), rest.begin(), rest.end());
     }
+    // parity colouring with each colour in increasing order: the kernels
+    // compute element ids from the launch index instead of reading them
+    bool parity = !iface;
+    {
+      const int lgn = log2i(L.n), lgh = lgn - 1, hm = (1 << lgh) - 1;
+      for (int col = 0; col < L.ncol && parity; ++col)
+        for (int64_t i = 0; i < off[col + 1] - off[col] && parity; ++i) {
+          int64_t E = 0;
+          for (int k = 0; k < c->g.d; ++k) E |= ((((i >> (k * lgh)) & hm) << 1) | ((col >> k) & 1)) << (k * lgn);
+          parity = order[off[col] + i] == E;
+        }
+    }
     if (L.uniform) {
       // one inverse for the level, held dense (FP64 for the FP64 cycle, FP32
       // for both the FP32 and the BF16-inverse cycles: nothing to stream)
@@ -463,6 +484,7 @@ void build_inverses(ldgs_ctx* c, bool need64, bool need32, bool need16) {
         pl.col_off = off;
         pl.col_reg = reg;
         pl.inv_stride = 0;
+        pl.parity = parity;
       };
       if (need64) set(c->s64);
       if (need32) set(c->s32);
@@ -515,9 +537,9 @@ void build_inverses(ldgs_ctx* c, bool need64, bool need32, bool need16) {
         HIPCHK(hipMemcpy(inv16 + p0 * st16, h16.data(), cnt * st16 * sizeof(uint16_t), hipMemcpyHostToDevice));
       }
     }
-    if (need64) { c->s64.lv[l].inv = inv64; c->s64.lv[l].inv_kind = 0; c->s64.lv[l].elems = elems; c->s64.lv[l].col_off = off; c->s64.lv[l].col_reg = reg; c->s64.lv[l].inv_stride = st64; }
-    if (need32) { c->s32.lv[l].inv = inv32; c->s32.lv[l].inv_kind = 1; c->s32.lv[l].elems = elems; c->s32.lv[l].col_off = off; c->s32.lv[l].col_reg = reg; c->s32.lv[l].inv_stride = st32; }
-    if (need16) { c->s16.lv[l].inv = inv16; c->s16.lv[l].inv_kind = 2; c->s16.lv[l].elems = elems; c->s16.lv[l].col_off = off; c->s16.lv[l].col_reg = reg; c->s16.lv[l].inv_stride = st16; }
+    if (need64) { c->s64.lv[l].inv = inv64; c->s64.lv[l].inv_kind = 0; c->s64.lv[l].elems = elems; c->s64.lv[l].col_off = off; c->s64.lv[l].col_reg = reg; c->s64.lv[l].inv_stride = st64; c->s64.lv[l].parity = parity; }
+    if (need32) { c->s32.lv[l].inv = inv32; c->s32.lv[l].inv_kind = 1; c->s32.lv[l].elems = elems; c->s32.lv[l].col_off = off; c->s32.lv[l].col_reg = reg; c->s32.lv[l].inv_stride = st32; c->s32.lv[l].parity = parity; }
+    if (need16) { c->s16.lv[l].inv = inv16; c->s16.lv[l].inv_kind = 2; c->s16.lv[l].elems = elems; c->s16.lv[l].col_off = off; c->s16.lv[l].col_reg = reg; c->s16.lv[l].inv_stride = st16; c->s16.lv[l].parity = parity; }
   }
 }
 
@@ -597,6 +619,12 @@ hipEvent_t next_event(ldgs_ctx* c) {
 }
 
 template <typename T>
+T* rf_scratch(ldgs_ctx* c) {
+  if constexpr (sizeof(T) == 8) return c->w_rf64;
+  else return c->w_rf32;
+}
+
+template <typename T>
 void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* x) {
   LaunchCfg cfg{c->g.d, c->g.p, c->stream, c->small_grid};
   PrecLevel<T>& pl = S.lv[l];
@@ -611,23 +639,24 @@ void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* 
     HIPCHK(hipEventRecord(e0, c->stream));
   }
   const int64_t nreg = pl.col_reg.empty() ? cnt : pl.col_reg[col];
+  const int pcol = pl.parity ? col : -1;
   if (pl.ainv_sh) {
     // one inverse for the level: residuals of the colour, then the shared update
-    LCHK(launch_colour_residual<T>(cfg, pl.view, c->tab, pl.elems + o, cnt, b, x, pl.rbuf));
+    LCHK(launch_colour_residual<T>(cfg, pl.view, c->tab, pl.elems + o, pcol, cnt, b, x, pl.rbuf));
     LCHK(launch_shared_update<T>(c->stream, cnt, c->g.nb, pl.ainv_sh, pl.rbuf, pl.elems + o, x));
   } else
   // (split only large launches: on coarse levels the second launch would cost
   // more than the extended stencil)
   if (!pl.view.iface || nreg == cnt || cnt < c->small_grid) {
-    LCHK(launch_smooth_colour<T>(cfg, pl.view, c->tab, pl.elems + o, cnt, inv, pl.inv_kind, b, x));
+    LCHK(launch_smooth_colour<T>(cfg, pl.view, c->tab, pl.elems + o, pcol, cnt, inv, pl.inv_kind, b, x));
   } else {
     // elements away from the interfaces: regular kernel; the rest: the
     // extended-stencil variant (the two ranges of one colour are uncoupled)
     DevLevel<T> regular = pl.view;
     regular.iface = 0;
-    if (nreg > 0) LCHK(launch_smooth_colour<T>(cfg, regular, c->tab, pl.elems + o, nreg, inv, pl.inv_kind, b, x));
+    if (nreg > 0) LCHK(launch_smooth_colour<T>(cfg, regular, c->tab, pl.elems + o, -1, nreg, inv, pl.inv_kind, b, x));
     const void* inv_i = (const char*)inv + nreg * pl.inv_stride * esz;
-    LCHK(launch_smooth_colour<T>(cfg, pl.view, c->tab, pl.elems + o + nreg, cnt - nreg, inv_i, pl.inv_kind, b, x));
+    LCHK(launch_smooth_colour<T>(cfg, pl.view, c->tab, pl.elems + o + nreg, -1, cnt - nreg, inv_i, pl.inv_kind, b, x));
   }
   if (timed) {
     HIPCHK(hipEventRecord(e1, c->stream));
@@ -669,7 +698,7 @@ void cycle(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x) {
   }
   smooth(c, S, l, b, x, c->P.nu1);
   PrecLevel<T>& nx = S.lv[l + 1];
-  LCHK(launch_residual_restrict<T>(cfg, S.lv[l].view, c->tab, b, x, nx.b));
+  LCHK(launch_residual_restrict<T>(cfg, S.lv[l].view, c->tab, b, x, nx.b, rf_scratch<T>(c)));
   if (l + 1 < bottom) LCHK(launch_fill<T>(c->stream, c->levels[l + 1].NE * c->g.nb, (T)0, nx.x));
   cycle(c, S, l + 1, nx.b, nx.x);
   LCHK(launch_prolong_add<T>(cfg, c->levels[l].n, c->tab, nx.x, x));
@@ -747,11 +776,6 @@ int periodic_mask(const ldgs_problem& P) {
   for (int k = 0; k < P.dim; ++k)
     if (P.bc[k] == LDGS_PERIODIC) m |= 1 << k;
   return m;
-}
-int log2i(int v) {
-  int l = 0;
-  while ((1 << l) < v) ++l;
-  return l;
 }
 
 // flat host layout <-> padded device layout
@@ -916,6 +940,17 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
         c->s16.ops = true;
       }
       build_inverses(c.get(), n64, n32, n16);
+      {
+        // scratch of the split residual + restriction: the largest level whose
+        // coarse grid has fewer than small_grid elements
+        int64_t rf = 0;
+        for (size_t l = 0; l + 1 < c->levels.size(); ++l)
+          if (c->levels[l + 1].NE < c->small_grid) rf = std::max(rf, c->levels[l].NE * c->g.nb);
+        if (rf > 0) {
+          c->w_rf64 = dalloc<double>(c.get(), rf);
+          if (n32 || n16) c->w_rf32 = dalloc<float>(c.get(), rf);
+        }
+      }
       c->s64.built = n64;
       c->s32.built = n32;
       c->s16.built = n16;
@@ -1449,7 +1484,7 @@ ldgs_status ldgs_level_residual_restrict(ldgs_ctx* ctx, int level, const double*
     if (!ctx->s64.built) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
     if (level < 0 || level + 1 >= (int)ctx->levels.size() || !b || !x || !rc) throw Fail{LDGS_E_ARG, "level"};
     LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream, ctx->small_grid};
-    LCHK(launch_residual_restrict<double>(cfg, ctx->s64.lv[level].view, ctx->tab, b, x, rc));
+    LCHK(launch_residual_restrict<double>(cfg, ctx->s64.lv[level].view, ctx->tab, b, x, rc, ctx->w_rf64));
     return LDGS_OK;
   } catch (const Fail& f) {
     return handle(ctx, f);

@@ -110,13 +110,11 @@ __device__ __forceinline__ int index_of(const int* c, int lgn) {
 }
 // shift coordinate k by s; false if it leaves a non-periodic grid
 __device__ __forceinline__ bool shift1(int* c, int k, int s, int n, bool per) {
-  int v = c[k] + s;
-  if (v < 0 || v >= n) {
-    if (!per) return false;
-    v = (v + n) & (n - 1);
-  }
-  c[k] = v;
-  return true;
+  // n is a power of two: the mask wraps -1 to n - 1 and n to 0 (periodic);
+  // without periodicity an outside neighbour is reported absent
+  const int v = c[k] + s;
+  c[k] = v & (n - 1);
+  return per || (unsigned)v < (unsigned)n;
 }
 template <int D>
 __device__ __forceinline__ int face_index(const int* c, int n, int nfk, int k, int f) {
@@ -127,6 +125,32 @@ __device__ __forceinline__ int face_index(const int* c, int n, int nfk, int k, i
     s *= (j == k) ? nfk : n;
   }
   return e;
+}
+
+// Element idx of colour pcol under parity colouring with the elements of a
+// colour in increasing order (colour bits b_k = c_k mod 2, c_k = 2 i_k + b_k,
+// idx = sum_k i_k (n/2)^k); pcol < 0: the colour's element list.
+template <int D>
+__device__ __forceinline__ int colour_elem(int idx, int pcol, int lgn, const int* __restrict__ elems) {
+  if (pcol < 0) return elems[idx];
+  const int lgh = lgn - 1, hm = (1 << lgh) - 1;
+  int E = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) E |= ((((idx >> (k * lgh)) & hm) << 1) | ((pcol >> k) & 1)) << (k * lgn);
+  return E;
+}
+
+// face with both neighbours present (intraphase, or interphase on levels
+// that have interphase faces)
+template <bool IF>
+__device__ __forceinline__ bool two_sided(unsigned char t) {
+  if constexpr (IF) return t == F_INTRA || t == F_INTER;
+  else return t == F_INTRA;
+}
+template <bool IF>
+__device__ __forceinline__ bool is_inter(unsigned char t) {
+  if constexpr (IF) return t == F_INTER;
+  else return false;
 }
 
 // stencil slots (see Sz)
@@ -485,7 +509,7 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
         trhi += tab.e1[bb] * uv[bb];
         trLhi += tab.e1[bb] * ul[bb * st];
       }
-      const T jlo = (tlo == F_NONE) ? (T)0 : wR * (trlo - ((tlo == F_INTRA || tlo == F_INTER) ? trLhi : (T)0));
+      const T jlo = (tlo == F_NONE) ? (T)0 : wR * (trlo - (two_sided<IF>(tlo) ? trLhi : (T)0));
       // lifting of the high-face jump onto F (weight wL: Dirichlet, or an
       // interphase face lifting onto its low element)
       T jhi = (thi == F_DIR_HI) ? wL * trhi : (T)0;
@@ -630,7 +654,7 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
 #pragma unroll
           for (int q = 0; q < MT; ++q) acc += Th[q] * w.trx[0][k][i][q];
           v += acc;
-        } else if (ty == F_INTER) {
+        } else if (is_inter<IF>(ty)) {
           T acc = 0;
 #pragma unroll
           for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trn[0][k][i][q] - w.trx[0][k][i][q]);
@@ -646,21 +670,21 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
         }
       } else {
         // E is the low element L of its high face
-        const T sR = (ty == F_INTRA || ty == F_INTER) ? w.trr[k][i][tt] : (T)0;
+        const T sR = two_sided<IF>(ty) ? w.trr[k][i][tt] : (T)0;
         v -= wR * sR + wL * w.trs[1][k][i][tt];
         if (ty == F_DIR_HI) {
           T acc = 0;
 #pragma unroll
           for (int q = 0; q < MT; ++q) acc += Th[q] * w.trx[1][k][i][q];
           v += acc;
-        } else if (ty == F_INTER) {
+        } else if (is_inter<IF>(ty)) {
           T acc = 0;
 #pragma unroll
           for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trx[1][k][i][q] - w.trn[1][k][i][q]);
           v += acc;
         }
         if (k == i) {
-          const T pR = (ty == F_INTRA || ty == F_INTER) ? w.trn[1][k][D][tt] : (T)0;
+          const T pR = two_sided<IF>(ty) ? w.trn[1][k][D][tt] : (T)0;
           v += wR * pR + wL * w.trx[1][k][D][tt];
         }
       }
@@ -789,7 +813,7 @@ __device__ __forceinline__ T shfl_xor64(T v, int m) {
 // ---------------------------------------------------------------------------
 template <typename T, typename TI, int D, int P, int NT, bool IF>
 __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> tab, const int* __restrict__ elems,
-                                                      const TI* __restrict__ inv, const T* __restrict__ b,
+                                                      int pcol, const TI* __restrict__ inv, const T* __restrict__ b,
                                                       T* __restrict__ x) {
   using S = Sz<D, P>;
   constexpr int NB = S::NB;
@@ -805,7 +829,7 @@ __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
   const int l = lane & 63;
   const bool w0 = lane < 64;
   const int idx = xcd_remap(blockIdx.x, gridDim.x);
-  const int E = elems[idx];
+  const int E = colour_elem<D>(idx, pcol, lev.lgn, elems);
   const Word* Ai = reinterpret_cast<const Word*>(inv + (size_t)idx * NTILE * 256);
   Word pre[PF][H];
   element_operator<T, D, P, NT, IF>(lev, tab, E, x, b, 0, w, [&]() {
@@ -893,12 +917,12 @@ __global__ __launch_bounds__(NT) void k_residual(DevLevel<T> lev, TabT<T> tab, c
 // E = elems[idx] (the first half of a colour pass with a shared inverse).
 template <typename T, int D, int P, int NT, bool IF>
 __global__ __launch_bounds__(NT) void k_colour_residual(DevLevel<T> lev, TabT<T> tab, const int* __restrict__ elems,
-                                                        const T* __restrict__ b, const T* __restrict__ x,
+                                                        int pcol, const T* __restrict__ b, const T* __restrict__ x,
                                                         T* __restrict__ r) {
   using S = Sz<D, P, IF>;
   __shared__ Work<T, D, P, IF> w;
   const int idx = xcd_remap(blockIdx.x, gridDim.x);
-  element_operator<T, D, P, NT, IF>(lev, tab, elems[idx], x, b, 0, w);
+  element_operator<T, D, P, NT, IF>(lev, tab, colour_elem<D>(idx, pcol, lev.lgn, elems), x, b, 0, w);
   for (int t = threadIdx.x; t < S::NB; t += NT) r[(size_t)idx * S::NB + t] = w.res[t];
 }
 
@@ -1028,6 +1052,33 @@ __global__ __launch_bounds__(NT) void k_residual_restrict(DevLevel<T> lev, TabT<
     const int t = threadIdx.x + q * NT;
     if (t < NB) rc[(size_t)C * NB + t] = acc[q];
   }
+}
+
+// rc = I^T r for a fine-level residual r already formed: one thread per
+// coarse coefficient (the second half of the split residual + restriction used
+// on small grids, where evaluating the 2^d children of a coarse element one
+// after another in one work-group is latency bound)
+template <typename T, int D, int P>
+__global__ void k_restrict(int lgn, TabT<T> tab, const T* __restrict__ r, T* __restrict__ rc, int64_t total) {
+  using S = Sz<D, P>;
+  constexpr int M = S::M, NQ = S::NQ, NB = S::NB;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int C = (int)(t / NB), rem = (int)(t % NB);
+  const int f = rem / NQ, ac = rem % NQ;
+  int cc[D];
+  coords_of<D>(C, lgn - 1, cc);
+  T acc = 0;
+  for (int o = 0; o < (1 << D); ++o) {
+    int cf[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) cf[j] = 2 * cc[j] + ((o >> j) & 1);
+    const T* rv = r + (size_t)index_of<D>(cf, lgn) * NB + f * NQ;
+    T s = 0;
+    for (int af = 0; af < NQ; ++af) s += pfull<T, D, M>(tab, o, af, ac) * rv[af];
+    acc += s;
+  }
+  rc[t] = acc;
 }
 
 // x += I x_c: one thread per fine coefficient.
@@ -1190,7 +1241,7 @@ static void dispatch_nt(int64_t nelems, int small_grid, F&& f) {
 }
 
 template <typename T>
-int launch_smooth_colour(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const int* elems,
+int launch_smooth_colour(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const int* elems, int pcol,
                          int64_t nelems, const void* inv, int inv_kind, const T* b, T* x) {
   if (nelems <= 0) return 0;
   const unsigned grid = (unsigned)nelems;
@@ -1200,14 +1251,14 @@ int launch_smooth_colour(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D
   if constexpr (sizeof(T) == 8) {
     if (inv_kind != 0) return 2;
     if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, double, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), 0, st,
-                                                  lev, tt, elems, (const double*)inv, b, x); }); })) bad = true; })) return 2;
+                                                  lev, tt, elems, pcol, (const double*)inv, b, x); }); })) bad = true; })) return 2;
   } else {
     if (inv_kind == 1) {
       if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, float, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), 0, st,
-                                                    lev, tt, elems, (const float*)inv, b, x); }); })) bad = true; })) return 2;
+                                                    lev, tt, elems, pcol, (const float*)inv, b, x); }); })) bad = true; })) return 2;
     } else if (inv_kind == 2) {
       if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, uint16_t, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), 0, st,
-                                                    lev, tt, elems, (const uint16_t*)inv, b, x); }); })) bad = true; })) return 2;
+                                                    lev, tt, elems, pcol, (const uint16_t*)inv, b, x); }); })) bad = true; })) return 2;
     } else {
       return 2;
     }
@@ -1231,14 +1282,14 @@ int launch_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab
 }
 
 template <typename T>
-int launch_colour_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const int* elems,
+int launch_colour_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const int* elems, int pcol,
                            int64_t nelems, const T* b, const T* x, T* r) {
   if (nelems <= 0) return 0;
   bool bad = false;
   hipStream_t st = (hipStream_t)c.stream;
   const TabT<T> tt = tab_of<T>(tab);
   if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_colour_residual<T, D_, P_, NT_, IF_>), dim3((unsigned)nelems), dim3(NT_), 0, st,
-                                                lev, tt, elems, b, x, r); }); })) bad = true; })) return 2;
+                                                lev, tt, elems, pcol, b, x, r); }); })) bad = true; })) return 2;
   if (bad) return 2;
   return hip_ok();
 }
@@ -1275,12 +1326,26 @@ int shared_inverse_rows(int nb, int bytes) {
 
 template <typename T>
 int launch_residual_restrict(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const T* b, const T* x,
-                             T* rc) {
+                             T* rc, T* rfine) {
   int64_t NC = 1;
   for (int j = 0; j < c.dim; ++j) NC *= lev.n / 2;
   bool bad = false;   // no kernel for this level (interphase faces in 3D)
   hipStream_t st = (hipStream_t)c.stream;
   const TabT<T> tt = tab_of<T>(tab);
+  if (rfine && NC < c.small_grid) {
+    // small grids: every fine element's residual in parallel, then I^T r
+    const int r1 = launch_residual<T>(c, lev, tab, b, x, rfine, 0);
+    if (r1 != 0) return r1;
+    if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) {
+          constexpr int D_ = decltype(Dc)::value;
+          constexpr int P_ = decltype(Pc)::value;
+          const int64_t total = NC * Sz<D_, P_>::NB;
+          hipLaunchKernelGGL((k_restrict<T, D_, P_>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, lev.lgn,
+                             tt, (const T*)rfine, rc, total);
+        }))
+      return 2;
+    return hip_ok();
+  }
   if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(NC, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual_restrict<T, D_, P_, NT_, IF_>), dim3((unsigned)NC), dim3(NT_), 0, st,
                                                 lev, tt, b, x, rc); }); })) bad = true; })) return 2;
   if (bad) return 2;
@@ -1362,22 +1427,22 @@ int launch_scale_cast(void* stream, int64_t ne, int nb, int nvel, const double* 
 template int launch_scale_cast<double, double>(void*, int64_t, int, int, const double*, const double*, double*, int, int);
 template int launch_scale_cast<double, float>(void*, int64_t, int, int, const double*, const double*, float*, int, int);
 template int launch_scale_cast<float, double>(void*, int64_t, int, int, const double*, const float*, double*, int, int);
-template int launch_smooth_colour<double>(const LaunchCfg&, const DevLevel<double>&, const Tab1D&, const int*, int64_t,
+template int launch_smooth_colour<double>(const LaunchCfg&, const DevLevel<double>&, const Tab1D&, const int*, int, int64_t,
                                           const void*, int, const double*, double*);
-template int launch_smooth_colour<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const int*, int64_t,
+template int launch_smooth_colour<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const int*, int, int64_t,
                                          const void*, int, const float*, float*);
 template int launch_residual<double>(const LaunchCfg&, const DevLevel<double>&, const Tab1D&, const double*,
                                      const double*, double*, int);
 template int launch_residual<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const float*, const float*,
                                     float*, int);
 template int launch_residual_restrict<double>(const LaunchCfg&, const DevLevel<double>&, const Tab1D&, const double*,
-                                              const double*, double*);
+                                              const double*, double*, double*);
 template int launch_residual_restrict<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const float*,
-                                             const float*, float*);
-template int launch_colour_residual<double>(const LaunchCfg&, const DevLevel<double>&, const Tab1D&, const int*,
+                                             const float*, float*, float*);
+template int launch_colour_residual<double>(const LaunchCfg&, const DevLevel<double>&, const Tab1D&, const int*, int,
                                             int64_t, const double*, const double*, double*);
-template int launch_colour_residual<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const int*, int64_t,
-                                           const float*, const float*, float*);
+template int launch_colour_residual<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const int*, int,
+                                           int64_t, const float*, const float*, float*);
 template int launch_shared_update<double>(void*, int64_t, int, const double*, const double*, const int*, double*);
 template int launch_shared_update<float>(void*, int64_t, int, const float*, const float*, const int*, float*);
 template int launch_prolong_add<double>(const LaunchCfg&, int, const Tab1D&, const double*, double*);

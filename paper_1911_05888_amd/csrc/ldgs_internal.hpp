@@ -99,22 +99,26 @@ struct LaunchCfg {
   int small_grid = 4096;
 };
 
+// elems: the colour's elements; pcol >= 0 instead: parity colour pcol with
+// its elements in increasing order, computed from the launch index
 template <typename T>
 int launch_smooth_colour(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab,
-                         const int* elems, int64_t nelems, const void* inv, int inv_kind,
+                         const int* elems, int pcol, int64_t nelems, const void* inv, int inv_kind,
                          const T* b, T* x);
 template <typename T>
 int launch_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab,
                     const T* b, const T* x, T* out, int mode);   // mode 0: b - A x, 1: A x
 template <typename T>
+// rc = I^T (b - A x); rfine (fine-level size, may be null): scratch for the
+// split form used when the coarse grid has fewer than small_grid elements
 int launch_residual_restrict(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab,
-                             const T* b, const T* x, T* rc);
+                             const T* b, const T* x, T* rc, T* rfine);
 // colour pass with an inverse shared by all elements: residuals of the listed
 // elements into r (compact, [nelems][nb]), then x_E += Ainv r (Ainv k-major,
 // a[k nb + row], zero-padded to shared_inverse_rows(nb, sizeof(T)) rows)
 int shared_inverse_rows(int nb, int bytes);
 template <typename T>
-int launch_colour_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const int* elems,
+int launch_colour_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const int* elems, int pcol,
                            int64_t nelems, const T* b, const T* x, T* r);
 template <typename T>
 int launch_shared_update(void* stream, int64_t nelems, int nb, const T* ainv, const T* r, const int* elems, T* x);
