@@ -643,7 +643,7 @@ void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* 
   if (pl.ainv_sh) {
     // one inverse for the level: residuals of the colour, then the shared update
     LCHK(launch_colour_residual<T>(cfg, pl.view, c->tab, pl.elems + o, pcol, cnt, b, x, pl.rbuf));
-    LCHK(launch_shared_update<T>(c->stream, cnt, c->g.nb, pl.ainv_sh, pl.rbuf, pl.elems + o, x));
+    LCHK(launch_shared_update<T>(c->stream, cnt, c->g.nb, pl.ainv_sh, pl.rbuf, pl.elems + o, x, 0, nullptr, 0));
   } else
   // (split only large launches: on coarse levels the second launch would cost
   // more than the extended stencil)
@@ -664,10 +664,42 @@ void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* 
   }
 }
 
+// First colour pass from x = 0 (x need not be initialised): x_E = Ainv_E b_E
+// on colour 0, every other element set to zero, in one launch.
 template <typename T>
-void smooth(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x, int sweeps) {
+void first_colour(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x) {
+  LaunchCfg cfg{c->g.d, c->g.p, c->stream, c->small_grid};
+  PrecLevel<T>& pl = S.lv[l];
+  const int64_t cnt = pl.col_off[1], nzero = c->levels[l].NE - cnt;
+  const int pcol = pl.parity ? 0 : -1;
+  const bool timed = c->prof && l == 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed) {
+    e0 = next_event(c);
+    e1 = next_event(c);
+    HIPCHK(hipEventRecord(e0, c->stream));
+  }
+  if (pl.ainv_sh)
+    LCHK(launch_shared_update<T>(c->stream, cnt, c->g.nb, pl.ainv_sh, b, pl.elems, x, 1, pl.elems + cnt, nzero));
+  else
+    LCHK(launch_first_colour<T>(cfg, log2i(c->levels[l].n), pl.elems, pcol, cnt, pl.inv, pl.inv_kind, b, x,
+                                pl.elems + cnt, nzero));
+  if (timed) {
+    HIPCHK(hipEventRecord(e1, c->stream));
+    c->prof_ev.emplace_back(e0, e1);
+  }
+}
+
+// sweeps of colour passes; zero_x: x is taken as zero on entry (and need not
+// be initialised)
+template <typename T>
+void smooth(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x, int sweeps, bool zero_x = false) {
+  if (zero_x && sweeps == 0) LCHK(launch_fill<T>(c->stream, c->levels[l].NE * c->g.nb, (T)0, x));
   for (int s = 0; s < sweeps; ++s)
-    for (int col = 0; col < c->levels[l].ncol; ++col) smooth_colour(c, S, l, col, b, x);
+    for (int col = 0; col < c->levels[l].ncol; ++col) {
+      if (zero_x && s == 0 && col == 0) first_colour(c, S, l, b, x);
+      else smooth_colour(c, S, l, col, b, x);
+    }
 }
 
 // Least-squares bottom solve x = A_c^+ b (footnote to the bottom solver):
@@ -688,19 +720,20 @@ void bottom_solve(ldgs_ctx* c, const T* b, T* x) {
   LCHK((launch_dense_mv<double, T>(c->stream, N, c->d_pinv, c->d_bt2, c->d_bt1, 1.0, x)));
 }
 
+// V-cycle on level l; zero_x: x is taken as zero on entry (the coarse levels'
+// corrections, and the finest level inside the outer iterations)
 template <typename T>
-void cycle(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x) {
+void cycle(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x, bool zero_x) {
   const int bottom = (int)c->levels.size() - 1;
   LaunchCfg cfg{c->g.d, c->g.p, c->stream, c->small_grid};
   if (l == bottom) {
-    bottom_solve(c, b, x);
+    bottom_solve(c, b, x);    // overwrites x
     return;
   }
-  smooth(c, S, l, b, x, c->P.nu1);
+  smooth(c, S, l, b, x, c->P.nu1, zero_x);
   PrecLevel<T>& nx = S.lv[l + 1];
   LCHK(launch_residual_restrict<T>(cfg, S.lv[l].view, c->tab, b, x, nx.b, rf_scratch<T>(c)));
-  if (l + 1 < bottom) LCHK(launch_fill<T>(c->stream, c->levels[l + 1].NE * c->g.nb, (T)0, nx.x));
-  cycle(c, S, l + 1, nx.b, nx.x);
+  cycle(c, S, l + 1, nx.b, nx.x, true);
   LCHK(launch_prolong_add<T>(cfg, c->levels[l].n, c->tab, nx.x, x));
   smooth(c, S, l, b, x, c->P.nu2);
 }
@@ -716,17 +749,15 @@ void vcycle_user(ldgs_ctx* c, int vp, const double* b, double* x, bool zero_x) {
   if (vp == LDGS_V_FP64) {
     if (!c->s64.built) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
     LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, b, c->w_b, 0, 0)));
-    if (zero_x) LCHK(launch_fill<double>(c->stream, NE * nb, 0.0, c->w_x));
-    else LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, x, c->w_x, 1, 0)));
-    cycle<double>(c, c->s64, 0, c->w_b, c->w_x);
+    if (!zero_x) LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, x, c->w_x, 1, 0)));
+    cycle<double>(c, c->s64, 0, c->w_b, c->w_x, zero_x);
     LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, c->w_x, x, 0, 0)));
   } else {
     PrecStore<float>& S = (vp == LDGS_V_FP32) ? c->s32 : c->s16;
     if (!S.built) throw Fail{LDGS_E_UNSUPPORTED, "requested V-cycle precision not built"};
     LCHK((launch_scale_cast<double, float>(c->stream, NE, nb, nvel, ds, b, c->w_b32, 0, 0)));
-    if (zero_x) LCHK(launch_fill<float>(c->stream, NE * nb, 0.0f, c->w_x32));
-    else LCHK((launch_scale_cast<double, float>(c->stream, NE, nb, nvel, ds, x, c->w_x32, 1, 0)));
-    cycle<float>(c, S, 0, c->w_b32, c->w_x32);
+    if (!zero_x) LCHK((launch_scale_cast<double, float>(c->stream, NE, nb, nvel, ds, x, c->w_x32, 1, 0)));
+    cycle<float>(c, S, 0, c->w_b32, c->w_x32, zero_x);
     LCHK((launch_scale_cast<float, double>(c->stream, NE, nb, nvel, ds, c->w_x32, x, 0, 0)));
   }
 }

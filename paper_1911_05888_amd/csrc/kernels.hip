@@ -811,36 +811,40 @@ __device__ __forceinline__ T shfl_xor64(T v, int m) {
 // the partial sums are reduced across lanes.  The first tiles are requested
 // before the residual is evaluated.
 // ---------------------------------------------------------------------------
-template <typename T, typename TI, int D, int P, int NT, bool IF>
-__global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> tab, const int* __restrict__ elems,
-                                                      int pcol, const TI* __restrict__ inv, const T* __restrict__ b,
-                                                      T* __restrict__ x) {
-  using S = Sz<D, P>;
-  constexpr int NB = S::NB;
-  constexpr SymTiles LY = sym_tiles(NB, (int)sizeof(TI));
-  constexpr int TR = LY.TR, NTILE = LY.NTILE, H = LY.H, EL = LY.EL;
+// Tiles of the element's inverse requested ahead of the product (32 registers
+// of words) and the product itself: the first wavefront forms y = Ainv res
+// from the stored upper tiles; y = part[0] + part[1] on return (after a
+// work-group barrier).
+template <typename TI, int NB>
+struct SymProd {
+  static constexpr SymTiles LY = sym_tiles(NB, (int)sizeof(TI));
+  static constexpr int TR = LY.TR, NTILE = LY.NTILE, H = LY.H, EL = LY.EL;
   using Word = InvWord<TI>;
-  // tiles requested before the residual is evaluated (32 registers of words)
-  constexpr int PFMAX = 32 / (H * (int)(sizeof(Word) / 4));
-  constexpr int PF = NTILE < PFMAX ? NTILE : PFMAX;
-  __shared__ Work<T, D, P, IF> w;
-  __shared__ T part[2][16 * TR];
-  const int lane = threadIdx.x;
-  const int l = lane & 63;
-  const bool w0 = lane < 64;
-  const int idx = xcd_remap(blockIdx.x, gridDim.x);
-  const int E = colour_elem<D>(idx, pcol, lev.lgn, elems);
-  const Word* Ai = reinterpret_cast<const Word*>(inv + (size_t)idx * NTILE * 256);
-  Word pre[PF][H];
-  element_operator<T, D, P, NT, IF>(lev, tab, E, x, b, 0, w, [&]() {
-    if (w0) {
+  static constexpr int PFMAX = 32 / (H * (int)(sizeof(Word) / 4));
+  static constexpr int PF = NTILE < PFMAX ? NTILE : PFMAX;
+};
+
+template <typename TI, int NB>
+__device__ __forceinline__ void sym_prefetch(const InvWord<TI>* __restrict__ Ai,
+                                             InvWord<TI> (&pre)[SymProd<TI, NB>::PF][SymProd<TI, NB>::H], int lane) {
+  using SP = SymProd<TI, NB>;
+  if (lane < 64) {
 #pragma unroll
-      for (int t = 0; t < PF; ++t)
+    for (int t = 0; t < SP::PF; ++t)
 #pragma unroll
-        for (int h = 0; h < H; ++h) pre[t][h] = __builtin_nontemporal_load(&Ai[(t * H + h) * 64 + l]);
-    }
-  });
-  if (w0) {
+      for (int h = 0; h < SP::H; ++h) pre[t][h] = __builtin_nontemporal_load(&Ai[(t * SP::H + h) * 64 + lane]);
+  }
+}
+
+template <typename T, typename TI, int NB>
+__device__ __forceinline__ void sym_product(const InvWord<TI>* __restrict__ Ai,
+                                            const InvWord<TI> (&pre)[SymProd<TI, NB>::PF][SymProd<TI, NB>::H],
+                                            const T* res, T (*part)[16 * SymProd<TI, NB>::TR], int lane) {
+  using SP = SymProd<TI, NB>;
+  constexpr int TR = SP::TR, PF = SP::PF, H = SP::H, EL = SP::EL;
+  using Word = typename SP::Word;
+  if (lane < 64) {
+    const int l = lane;
     const int row = l >> 2, c4 = (l & 3) * 4;
     T dir[TR], trn[TR][4];
 #pragma unroll
@@ -851,7 +855,7 @@ __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
     }
 #pragma unroll
     for (int i = 0; i < TR; ++i) {
-      const T ri = (16 * i + row < NB) ? w.res[16 * i + row] : (T)0;
+      const T ri = (16 * i + row < NB) ? res[16 * i + row] : (T)0;
 #pragma unroll
       for (int j = i; j < TR; ++j) {
         const int t = i * TR - i * (i - 1) / 2 + (j - i);
@@ -864,7 +868,7 @@ __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
         for (int v = 0; v < 4; ++v) {
           a[v] = inv_entry<T, TI>(raw[v / EL], v % EL);
           const int cj = 16 * j + c4 + v;
-          rj[v] = cj < NB ? w.res[cj] : (T)0;
+          rj[v] = cj < NB ? res[cj] : (T)0;
         }
         dir[i] += a[0] * rj[0] + a[1] * rj[1] + a[2] * rj[2] + a[3] * rj[3];
         if (j != i) {
@@ -900,7 +904,63 @@ __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
     }
   }
   __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Smoother: one colour pass.  x_E += Ainv_E (b - A x)_E for the listed elements.
+// Ainv_E is symmetric and stored as its upper 16 x 16 tiles (sym_tiles); the
+// first wave forms the product: for tile (i, j) lane (row, 4 columns) adds
+// T r_j to its row of y_i and, off the diagonal, T^T r_i to its columns of y_j;
+// the partial sums are reduced across lanes.  The first tiles are requested
+// before the residual is evaluated.
+// ---------------------------------------------------------------------------
+template <typename T, typename TI, int D, int P, int NT, bool IF>
+__global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> tab, const int* __restrict__ elems,
+                                                      int pcol, const TI* __restrict__ inv, const T* __restrict__ b,
+                                                      T* __restrict__ x) {
+  using S = Sz<D, P>;
+  constexpr int NB = S::NB;
+  using SP = SymProd<TI, NB>;
+  __shared__ Work<T, D, P, IF> w;
+  __shared__ T part[2][16 * SP::TR];
+  const int lane = threadIdx.x;
+  const int idx = xcd_remap(blockIdx.x, gridDim.x);
+  const int E = colour_elem<D>(idx, pcol, lev.lgn, elems);
+  const auto* Ai = reinterpret_cast<const typename SP::Word*>(inv + (size_t)idx * SP::NTILE * 256);
+  typename SP::Word pre[SP::PF][SP::H];
+  element_operator<T, D, P, NT, IF>(lev, tab, E, x, b, 0, w, [&]() { sym_prefetch<TI, NB>(Ai, pre, lane); });
+  sym_product<T, TI, NB>(Ai, pre, w.res, part, lane);
   for (int r = lane; r < NB; r += NT) x[(size_t)E * NB + r] += part[0][r] + part[1][r];
+}
+
+// First colour pass from x = 0: the residual is b, so x_E = Ainv_E b_E with
+// no operator evaluation; the work-groups also set every other element of
+// the level to zero (zl: those elements, nzero of them; work-group idx takes
+// entries idx, idx + cnt, ...).  Same results as zeroing x and running the
+// colour pass.
+template <typename T, typename TI, int D, int P, int NT>
+__global__ __launch_bounds__(NT) void k_first_colour(int lgn, const int* __restrict__ elems, int pcol,
+                                                     const TI* __restrict__ inv, const T* __restrict__ b,
+                                                     T* __restrict__ x, const int* __restrict__ zl, int nzero) {
+  using S = Sz<D, P>;
+  constexpr int NB = S::NB;
+  using SP = SymProd<TI, NB>;
+  __shared__ alignas(16) T res[NB];
+  __shared__ T part[2][16 * SP::TR];
+  const int lane = threadIdx.x;
+  const int idx = xcd_remap(blockIdx.x, gridDim.x);
+  const int E = colour_elem<D>(idx, pcol, lgn, elems);
+  const auto* Ai = reinterpret_cast<const typename SP::Word*>(inv + (size_t)idx * SP::NTILE * 256);
+  typename SP::Word pre[SP::PF][SP::H];
+  sym_prefetch<TI, NB>(Ai, pre, lane);
+  for (int t = lane; t < NB; t += NT) res[t] = b[(size_t)E * NB + t];
+  for (int m = idx; m < nzero; m += (int)gridDim.x) {
+    const size_t z = (size_t)zl[m] * NB;
+    for (int t = lane; t < NB; t += NT) x[z + t] = (T)0;
+  }
+  __syncthreads();
+  sym_product<T, TI, NB>(Ai, pre, res, part, lane);
+  for (int r = lane; r < NB; r += NT) x[(size_t)E * NB + r] = part[0][r] + part[1][r];
 }
 
 template <typename T, int D, int P, int NT, bool IF>
@@ -948,10 +1008,13 @@ struct SuCfg {
   static constexpr int A_SZ = A_LDS ? RS * NB : 1;
 };
 
+// first: first pass from x = 0 (r is b, read at the listed elements; x_E is
+// assigned; the nzero elements zl of the other colours are set to zero)
 template <typename T, int NB>
 __global__ __launch_bounds__(SU_THREADS) void k_shared_update(int nelems, const T* __restrict__ ainv,
                                                               const T* __restrict__ r, const int* __restrict__ elems,
-                                                              T* __restrict__ x) {
+                                                              T* __restrict__ x, int first, const int* __restrict__ zl,
+                                                              int nzero) {
   using C = SuCfg<T, NB>;
   using V4 = std::conditional_t<sizeof(T) == 8, double2, float4>;
   __shared__ alignas(16) T As[C::A_SZ];
@@ -969,7 +1032,9 @@ __global__ __launch_bounds__(SU_THREADS) void k_shared_update(int nelems, const 
     __syncthreads();
     for (int i = tid; i < C::TE * C::RS; i += SU_THREADS) {
       const int e = i / C::RS, k = i - e * C::RS;
-      Rs[i] = (e < cnt && k < NB) ? r[(size_t)(base + e) * NB + k] : T(0);
+      T v = T(0);
+      if (e < cnt && k < NB) v = first ? r[(size_t)elems[base + e] * NB + k] : r[(size_t)(base + e) * NB + k];
+      Rs[i] = v;
     }
     __syncthreads();
     if (active) {
@@ -994,10 +1059,15 @@ __global__ __launch_bounds__(SU_THREADS) void k_shared_update(int nelems, const 
 #pragma unroll
       for (int q = 0; q < C::Q; ++q) {
         const int e = g * C::Q + q;
-        if (e < cnt) x[(size_t)elems[base + e] * NB + row] += acc[q];
+        if (e < cnt) {
+          T* xe = &x[(size_t)elems[base + e] * NB + row];
+          *xe = first ? acc[q] : *xe + acc[q];
+        }
       }
     }
   }
+  for (int64_t i = (int64_t)blockIdx.x * SU_THREADS + tid; i < (int64_t)nzero * NB; i += (int64_t)gridDim.x * SU_THREADS)
+    x[(size_t)zl[i / NB] * NB + i % NB] = T(0);
 }
 
 // product of 1D injection entries: (P_o)[af][ac] for child offset bits o
@@ -1295,27 +1365,57 @@ int launch_colour_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab
 }
 
 template <typename T, int NB>
-static void shared_update_nb(hipStream_t st, int64_t nelems, const T* ainv, const T* r, const int* elems, T* x) {
+static void shared_update_nb(hipStream_t st, int64_t nelems, const T* ainv, const T* r, const int* elems, T* x,
+                             int first, const int* zl, int64_t nzero) {
   using C = SuCfg<T, NB>;
   int64_t g = (nelems + C::TE - 1) / C::TE;
   if (g > 512) g = 512;
   hipLaunchKernelGGL((k_shared_update<T, NB>), dim3((unsigned)g), dim3(SU_THREADS), 0, st, (int)nelems, ainv, r,
-                     elems, x);
+                     elems, x, first, zl, (int)nzero);
 }
 
 template <typename T>
-int launch_shared_update(void* stream, int64_t nelems, int nb, const T* ainv, const T* r, const int* elems, T* x) {
+int launch_shared_update(void* stream, int64_t nelems, int nb, const T* ainv, const T* r, const int* elems, T* x,
+                         int first, const int* zl, int64_t nzero) {
   if (nelems <= 0) return 0;
   hipStream_t st = (hipStream_t)stream;
   switch (nb) {
-    case 12: shared_update_nb<T, 12>(st, nelems, ainv, r, elems, x); break;
-    case 27: shared_update_nb<T, 27>(st, nelems, ainv, r, elems, x); break;
-    case 48: shared_update_nb<T, 48>(st, nelems, ainv, r, elems, x); break;
-    case 32: shared_update_nb<T, 32>(st, nelems, ainv, r, elems, x); break;
-    case 108: shared_update_nb<T, 108>(st, nelems, ainv, r, elems, x); break;
-    case 256: shared_update_nb<T, 256>(st, nelems, ainv, r, elems, x); break;
+#define LDGS_SU(NBV) \
+  case NBV: shared_update_nb<T, NBV>(st, nelems, ainv, r, elems, x, first, zl, nzero); break;
+    LDGS_SU(12) LDGS_SU(27) LDGS_SU(48) LDGS_SU(32) LDGS_SU(108) LDGS_SU(256)
+#undef LDGS_SU
     default: return 2;
   }
+  return hip_ok();
+}
+
+template <typename T>
+int launch_first_colour(const LaunchCfg& c, int lgn, const int* elems, int pcol, int64_t nelems, const void* inv,
+                        int inv_kind, const T* b, T* x, const int* zl, int64_t nzero) {
+  if (nelems <= 0) return 0;
+  hipStream_t st = (hipStream_t)c.stream;
+  auto go = [&](auto tag) {
+    using TI = decltype(tag);
+    return dispatch(c.dim, c.p, [&](auto Dc, auto Pc) {
+      constexpr int D_ = decltype(Dc)::value;
+      constexpr int P_ = decltype(Pc)::value;
+      dispatch_nt(nelems, c.small_grid, [&](auto Nc) {
+        constexpr int NT_ = decltype(Nc)::value;
+        hipLaunchKernelGGL((k_first_colour<T, TI, D_, P_, NT_>), dim3((unsigned)nelems), dim3(NT_), 0, st, lgn, elems,
+                           pcol, (const TI*)inv, b, x, zl, (int)nzero);
+      });
+    });
+  };
+  bool bad;
+  if constexpr (sizeof(T) == 8) {
+    if (inv_kind != 0) return 2;
+    bad = go(double{});
+  } else {
+    if (inv_kind == 1) bad = go(float{});
+    else if (inv_kind == 2) bad = go(uint16_t{});
+    else return 2;
+  }
+  if (bad) return 2;
   return hip_ok();
 }
 
@@ -1443,8 +1543,14 @@ template int launch_colour_residual<double>(const LaunchCfg&, const DevLevel<dou
                                             int64_t, const double*, const double*, double*);
 template int launch_colour_residual<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const int*, int,
                                            int64_t, const float*, const float*, float*);
-template int launch_shared_update<double>(void*, int64_t, int, const double*, const double*, const int*, double*);
-template int launch_shared_update<float>(void*, int64_t, int, const float*, const float*, const int*, float*);
+template int launch_shared_update<double>(void*, int64_t, int, const double*, const double*, const int*, double*,
+                                          int, const int*, int64_t);
+template int launch_shared_update<float>(void*, int64_t, int, const float*, const float*, const int*, float*, int,
+                                         const int*, int64_t);
+template int launch_first_colour<double>(const LaunchCfg&, int, const int*, int, int64_t, const void*, int,
+                                         const double*, double*, const int*, int64_t);
+template int launch_first_colour<float>(const LaunchCfg&, int, const int*, int, int64_t, const void*, int,
+                                        const float*, float*, const int*, int64_t);
 template int launch_prolong_add<double>(const LaunchCfg&, int, const Tab1D&, const double*, double*);
 template int launch_prolong_add<float>(const LaunchCfg&, int, const Tab1D&, const float*, float*);
 template int launch_dense_mv<double, double>(void*, int64_t, const double*, const double*, const double*, double, double*);

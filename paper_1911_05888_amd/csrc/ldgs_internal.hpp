@@ -120,8 +120,17 @@ int shared_inverse_rows(int nb, int bytes);
 template <typename T>
 int launch_colour_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const int* elems, int pcol,
                            int64_t nelems, const T* b, const T* x, T* r);
+// first != 0: the first pass from x = 0 (r is then b, read at the listed
+// elements; x_E is assigned and the nzero elements zl are set to zero)
 template <typename T>
-int launch_shared_update(void* stream, int64_t nelems, int nb, const T* ainv, const T* r, const int* elems, T* x);
+int launch_shared_update(void* stream, int64_t nelems, int nb, const T* ainv, const T* r, const int* elems, T* x,
+                         int first, const int* zl, int64_t nzero);
+// first colour pass from x = 0 with per-element inverses: x_E = Ainv_E b_E for
+// the listed elements (same element / inverse conventions as
+// launch_smooth_colour), and the nzero elements zl set to zero
+template <typename T>
+int launch_first_colour(const LaunchCfg& c, int lgn, const int* elems, int pcol, int64_t nelems, const void* inv,
+                        int inv_kind, const T* b, T* x, const int* zl, int64_t nzero);
 template <typename T>
 int launch_prolong_add(const LaunchCfg& c, int n_fine, const Tab1D& tab, const T* xc, T* x);
 // y = z + sign * M x, M dense row-major FP64 N x N, z optional
