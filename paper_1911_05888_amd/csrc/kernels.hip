@@ -20,6 +20,7 @@
 // rows R_k = (e0^T)_k M_mu of that neighbour.
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <type_traits>
 
 #include "ldgs_internal.hpp"
@@ -203,8 +204,6 @@ struct Work {
   using S = Sz<D, P, IF>;
   static constexpr bool STAGE_M = (size_t)S::NQ * S::NQ * sizeof(T) <= 8192;
   alignas(16) T xs[S::NSLOT][S::NB];
-  alignas(16) T mm[STAGE_M ? S::NQ * S::NQ : 1];   // M_mu of E
-  alignas(16) T rr[D][S::MT * S::NQ];             // R_k = (e0^T)_k M_mu of E+e_k
   alignas(16) T th[2][D][S::MT * S::MT];          // penalty matrices of E's low/high faces
   alignas(16) T g[S::NFS][D * D][S::NQ];          // G_k u_i at E, E+e_k (and E-e_k) (needed components)
   alignas(16) T s0[D * D][S::NQ];                 // s_ik at E
@@ -212,13 +211,30 @@ struct Work {
   alignas(16) T trn[2][D][D + 1][S::MT];          // [0]: x_{E-e_k}|hi, [1]: x_{E+e_k}|lo
   alignas(16) T trs[2][D][D][S::MT];              // s_E[i][k] lo/hi along k
   alignas(16) T trr[D][D][S::MT];                 // s_{E+e_k}[i][k] at its low face along k
-  alignas(16) T rrh[IF ? D : 1][S::MT * S::NQ];   // (IF) (e1^T)_k M_mu of E-e_k
   alignas(16) T trrh[IF ? D : 1][D][S::MT];       // (IF) s_{E-e_k}[i][k] at its high face along k
   alignas(16) T flux[2][D][D + 1][S::MT];         // coefficients of e0 (lo) and e1 (hi) per axis/field
   alignas(16) T res[S::NB];
   unsigned char ft[S::NFS][D][2];
   alignas(16) T fwl[S::NFS][D][2], fwr[S::NFS][D][2];
+  // viscosity data, last: levels with constant viscosity do not allocate it
+  alignas(16) T rr[D][S::MT * S::NQ];             // R_k = (e0^T)_k M_mu of E+e_k
+  alignas(16) T rrh[IF ? D : 1][S::MT * S::NQ];   // (IF) (e1^T)_k M_mu of E-e_k
+  alignas(16) T mm[STAGE_M ? S::NQ * S::NQ : 1];   // M_mu of E
 };
+
+// LDS bytes of the evaluation (dynamic shared memory of the element kernels):
+// the viscosity part only when the level's viscosity varies
+template <typename T, int D, int P, bool IF>
+constexpr size_t work_bytes(bool var_mu) {
+  using W = Work<T, D, P, IF>;
+  return var_mu ? sizeof(W) : offsetof(W, rr);
+}
+
+extern __shared__ __align__(16) unsigned char dyn_lds[];
+template <typename T, int D, int P, bool IF>
+__device__ __forceinline__ Work<T, D, P, IF>& work_lds() {
+  return *reinterpret_cast<Work<T, D, P, IF>*>(dyn_lds);
+}
 
 // Registers of one element's evaluation between issuing its loads and
 // staging them in LDS: the stencil (uniform), the raw loaded values, the face
@@ -921,7 +937,7 @@ __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
   using S = Sz<D, P>;
   constexpr int NB = S::NB;
   using SP = SymProd<TI, NB>;
-  __shared__ Work<T, D, P, IF> w;
+  Work<T, D, P, IF>& w = work_lds<T, D, P, IF>();
   __shared__ T part[2][16 * SP::TR];
   const int lane = threadIdx.x;
   const int idx = xcd_remap(blockIdx.x, gridDim.x);
@@ -967,7 +983,7 @@ template <typename T, int D, int P, int NT, bool IF>
 __global__ __launch_bounds__(NT) void k_residual(DevLevel<T> lev, TabT<T> tab, const T* __restrict__ b,
                                                  const T* __restrict__ x, T* __restrict__ out, int mode) {
   using S = Sz<D, P>;
-  __shared__ Work<T, D, P, IF> w;
+  Work<T, D, P, IF>& w = work_lds<T, D, P, IF>();
   const int E = xcd_remap(blockIdx.x, gridDim.x);
   element_operator<T, D, P, NT, IF>(lev, tab, E, x, b, mode, w);
   for (int t = threadIdx.x; t < S::NB; t += NT) out[(size_t)E * S::NB + t] = w.res[t];
@@ -980,7 +996,7 @@ __global__ __launch_bounds__(NT) void k_colour_residual(DevLevel<T> lev, TabT<T>
                                                         int pcol, const T* __restrict__ b, const T* __restrict__ x,
                                                         T* __restrict__ r) {
   using S = Sz<D, P, IF>;
-  __shared__ Work<T, D, P, IF> w;
+  Work<T, D, P, IF>& w = work_lds<T, D, P, IF>();
   const int idx = xcd_remap(blockIdx.x, gridDim.x);
   element_operator<T, D, P, NT, IF>(lev, tab, colour_elem<D>(idx, pcol, lev.lgn, elems), x, b, 0, w);
   for (int t = threadIdx.x; t < S::NB; t += NT) r[(size_t)idx * S::NB + t] = w.res[t];
@@ -1091,7 +1107,7 @@ __global__ __launch_bounds__(NT) void k_residual_restrict(DevLevel<T> lev, TabT<
   using S = Sz<D, P>;
   constexpr int M = S::M, NQ = S::NQ, NB = S::NB;
   constexpr int PER = (NB + NT - 1) / NT;
-  __shared__ Work<T, D, P, IF> w;
+  Work<T, D, P, IF>& w = work_lds<T, D, P, IF>();
   const int lgc = lev.lgn - 1;
   const int C = xcd_remap(blockIdx.x, gridDim.x);
   int cc[D];
@@ -1320,14 +1336,14 @@ int launch_smooth_colour(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D
   const TabT<T> tt = tab_of<T>(tab);
   if constexpr (sizeof(T) == 8) {
     if (inv_kind != 0) return 2;
-    if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, double, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), 0, st,
+    if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, double, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                   lev, tt, elems, pcol, (const double*)inv, b, x); }); })) bad = true; })) return 2;
   } else {
     if (inv_kind == 1) {
-      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, float, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), 0, st,
+      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, float, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                     lev, tt, elems, pcol, (const float*)inv, b, x); }); })) bad = true; })) return 2;
     } else if (inv_kind == 2) {
-      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, uint16_t, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), 0, st,
+      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, uint16_t, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                     lev, tt, elems, pcol, (const uint16_t*)inv, b, x); }); })) bad = true; })) return 2;
     } else {
       return 2;
@@ -1345,7 +1361,7 @@ int launch_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab
   bool bad = false;   // no kernel for this level (interphase faces in 3D)
   hipStream_t st = (hipStream_t)c.stream;
   const TabT<T> tt = tab_of<T>(tab);
-  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(NE, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual<T, D_, P_, NT_, IF_>), dim3((unsigned)NE), dim3(NT_), 0, st,
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(NE, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual<T, D_, P_, NT_, IF_>), dim3((unsigned)NE), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                 lev, tt, b, x, out, mode); }); })) bad = true; })) return 2;
   if (bad) return 2;
   return hip_ok();
@@ -1358,7 +1374,7 @@ int launch_colour_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab
   bool bad = false;
   hipStream_t st = (hipStream_t)c.stream;
   const TabT<T> tt = tab_of<T>(tab);
-  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_colour_residual<T, D_, P_, NT_, IF_>), dim3((unsigned)nelems), dim3(NT_), 0, st,
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_colour_residual<T, D_, P_, NT_, IF_>), dim3((unsigned)nelems), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                 lev, tt, elems, pcol, b, x, r); }); })) bad = true; })) return 2;
   if (bad) return 2;
   return hip_ok();
@@ -1446,7 +1462,7 @@ int launch_residual_restrict(const LaunchCfg& c, const DevLevel<T>& lev, const T
       return 2;
     return hip_ok();
   }
-  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(NC, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual_restrict<T, D_, P_, NT_, IF_>), dim3((unsigned)NC), dim3(NT_), 0, st,
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(NC, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual_restrict<T, D_, P_, NT_, IF_>), dim3((unsigned)NC), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                 lev, tt, b, x, rc); }); })) bad = true; })) return 2;
   if (bad) return 2;
   return hip_ok();
