@@ -1013,25 +1013,26 @@ __global__ __launch_bounds__(NT) void k_colour_residual(DevLevel<T> lev, TabT<T>
 // tile holds TE = G * Q elements.  R tiles are staged in LDS with row stride
 // RS (16-byte aligned) and read as 16-byte broadcasts.
 constexpr int SU_THREADS = 256;
-template <typename T, int NB>
+template <typename T, int NB, int Q_>
 struct SuCfg {
   static constexpr int V = 16 / sizeof(T);                    // entries per 16-byte read
   static constexpr int RS = (NB + V - 1) / V * V;
   static constexpr int G = SU_THREADS / NB;
-  static constexpr int Q = 16;
+  static constexpr int Q = Q_;
   static constexpr int TE = G * Q;
-  static constexpr bool A_LDS = (size_t)RS * NB * sizeof(T) + (size_t)TE * RS * sizeof(T) <= 65536;
+  // A in LDS only while it leaves room for several work-groups per CU
+  static constexpr bool A_LDS = (size_t)RS * NB * sizeof(T) <= 32768;
   static constexpr int A_SZ = A_LDS ? RS * NB : 1;
 };
 
 // first: first pass from x = 0 (r is b, read at the listed elements; x_E is
 // assigned; the nzero elements zl of the other colours are set to zero)
-template <typename T, int NB>
+template <typename T, int NB, int Q>
 __global__ __launch_bounds__(SU_THREADS) void k_shared_update(int nelems, const T* __restrict__ ainv,
                                                               const T* __restrict__ r, const int* __restrict__ elems,
                                                               T* __restrict__ x, int first, const int* __restrict__ zl,
                                                               int nzero) {
-  using C = SuCfg<T, NB>;
+  using C = SuCfg<T, NB, Q>;
   using V4 = std::conditional_t<sizeof(T) == 8, double2, float4>;
   __shared__ alignas(16) T As[C::A_SZ];
   __shared__ alignas(16) T Rs[C::TE * C::RS];
@@ -1380,14 +1381,22 @@ int launch_colour_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab
   return hip_ok();
 }
 
+template <typename T, int NB, int Q>
+static void shared_update_q(hipStream_t st, int64_t nelems, const T* ainv, const T* r, const int* elems, T* x,
+                            int first, const int* zl, int64_t nzero) {
+  using C = SuCfg<T, NB, Q>;
+  int64_t g = (nelems + C::TE - 1) / C::TE;
+  if (g > 2048) g = 2048;
+  hipLaunchKernelGGL((k_shared_update<T, NB, Q>), dim3((unsigned)g), dim3(SU_THREADS), 0, st, (int)nelems, ainv, r,
+                     elems, x, first, zl, (int)nzero);
+}
+// 16 elements per thread on large colours; 4 on small ones (more work-groups,
+// shorter chains: small launches are latency bound)
 template <typename T, int NB>
 static void shared_update_nb(hipStream_t st, int64_t nelems, const T* ainv, const T* r, const int* elems, T* x,
                              int first, const int* zl, int64_t nzero) {
-  using C = SuCfg<T, NB>;
-  int64_t g = (nelems + C::TE - 1) / C::TE;
-  if (g > 512) g = 512;
-  hipLaunchKernelGGL((k_shared_update<T, NB>), dim3((unsigned)g), dim3(SU_THREADS), 0, st, (int)nelems, ainv, r,
-                     elems, x, first, zl, (int)nzero);
+  if (nelems >= 8192) shared_update_q<T, NB, 16>(st, nelems, ainv, r, elems, x, first, zl, nzero);
+  else shared_update_q<T, NB, 4>(st, nelems, ainv, r, elems, x, first, zl, nzero);
 }
 
 template <typename T>
