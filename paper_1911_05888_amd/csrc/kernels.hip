@@ -1321,9 +1321,13 @@ static int dispatch_if(int iface, int dim, F&& f) {
   f(std::true_type{});
   return 0;
 }
+// Work-groups whose LDS block exceeds this also run two wavefronts per element
+// on large grids: LDS then limits the work-groups per CU, and one wavefront
+// each would leave the SIMDs idle (3D, FP64).
+constexpr size_t LDS_WIDE = 12288;
 template <class F>
-static void dispatch_nt(int64_t nelems, int small_grid, F&& f) {
-  if (nelems >= small_grid) f(std::integral_constant<int, WG>{});
+static void dispatch_nt(int64_t nelems, int small_grid, size_t lds_bytes, F&& f) {
+  if (nelems >= small_grid && lds_bytes <= LDS_WIDE) f(std::integral_constant<int, WG>{});
   else f(std::integral_constant<int, NT_SMALL>{});
 }
 
@@ -1337,14 +1341,14 @@ int launch_smooth_colour(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D
   const TabT<T> tt = tab_of<T>(tab);
   if constexpr (sizeof(T) == 8) {
     if (inv_kind != 0) return 2;
-    if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, double, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
+    if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, double, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                   lev, tt, elems, pcol, (const double*)inv, b, x); }); })) bad = true; })) return 2;
   } else {
     if (inv_kind == 1) {
-      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, float, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
+      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, float, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                     lev, tt, elems, pcol, (const float*)inv, b, x); }); })) bad = true; })) return 2;
     } else if (inv_kind == 2) {
-      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, uint16_t, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
+      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, uint16_t, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                     lev, tt, elems, pcol, (const uint16_t*)inv, b, x); }); })) bad = true; })) return 2;
     } else {
       return 2;
@@ -1362,7 +1366,7 @@ int launch_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab
   bool bad = false;   // no kernel for this level (interphase faces in 3D)
   hipStream_t st = (hipStream_t)c.stream;
   const TabT<T> tt = tab_of<T>(tab);
-  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(NE, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual<T, D_, P_, NT_, IF_>), dim3((unsigned)NE), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(NE, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual<T, D_, P_, NT_, IF_>), dim3((unsigned)NE), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                 lev, tt, b, x, out, mode); }); })) bad = true; })) return 2;
   if (bad) return 2;
   return hip_ok();
@@ -1375,7 +1379,7 @@ int launch_colour_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab
   bool bad = false;
   hipStream_t st = (hipStream_t)c.stream;
   const TabT<T> tt = tab_of<T>(tab);
-  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_colour_residual<T, D_, P_, NT_, IF_>), dim3((unsigned)nelems), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_colour_residual<T, D_, P_, NT_, IF_>), dim3((unsigned)nelems), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                 lev, tt, elems, pcol, b, x, r); }); })) bad = true; })) return 2;
   if (bad) return 2;
   return hip_ok();
@@ -1424,7 +1428,7 @@ int launch_first_colour(const LaunchCfg& c, int lgn, const int* elems, int pcol,
     return dispatch(c.dim, c.p, [&](auto Dc, auto Pc) {
       constexpr int D_ = decltype(Dc)::value;
       constexpr int P_ = decltype(Pc)::value;
-      dispatch_nt(nelems, c.small_grid, [&](auto Nc) {
+      dispatch_nt(nelems, c.small_grid, 0, [&](auto Nc) {
         constexpr int NT_ = decltype(Nc)::value;
         hipLaunchKernelGGL((k_first_colour<T, TI, D_, P_, NT_>), dim3((unsigned)nelems), dim3(NT_), 0, st, lgn, elems,
                            pcol, (const TI*)inv, b, x, zl, (int)nzero);
@@ -1471,7 +1475,7 @@ int launch_residual_restrict(const LaunchCfg& c, const DevLevel<T>& lev, const T
       return 2;
     return hip_ok();
   }
-  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(NC, c.small_grid, [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual_restrict<T, D_, P_, NT_, IF_>), dim3((unsigned)NC), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(NC, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual_restrict<T, D_, P_, NT_, IF_>), dim3((unsigned)NC), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                 lev, tt, b, x, rc); }); })) bad = true; })) return 2;
   if (bad) return 2;
   return hip_ok();
