@@ -576,6 +576,28 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
           }
         }
         w.trrh[IF ? k : 0][i][t] = v;
+      } else if (lev.mmu && W::STAGE_M) {
+        // variable viscosity, one code path for both kinds of row: s_E = M_mu
+        // (g + gamma g^T) at node a of E, and the low-face trace of s at E+e_k
+        // from its trace row (e0^T)_k M_mu
+        const bool isS = u < NS0;
+        const int a = u % NQ, pr = u / NQ;
+        const int r = u - NS0;
+        const int t = r % MT, ir = (r / MT) % D, kr = r / (MT * D);
+        const int i = isS ? pr / D : ir, k = isS ? pr % D : kr;
+        if (isS && lev.gamma && i > k) continue;       // symmetric: filled from (k, i)
+        const int fi = isS ? 0 : 1 + k;
+        const bool valid = isS || ((vmask >> (1 + D + k)) & 1);
+        const T* g1 = w.g[fi][i * D + k];
+        const T* g2 = w.g[fi][k * D + i];
+        const T* R = isS ? &w.mm[a * NQ] : &w.rr[k][t * NQ];   // M_mu symmetric: row a
+        T v = 0;
+#pragma unroll 8
+        for (int bb = 0; bb < NQ; ++bb) v += R[bb] * (g1[bb] + gam * g2[bb]);
+        v = valid ? v : (T)0;
+        T* o = isS ? &w.s0[i * D + k][a] : &w.trr[k][i][t];
+        *o = v;
+        if (isS && lev.gamma && i != k) w.s0[k * D + i][a] = v;
       } else if (u < NS0) {
         const int a = u % NQ, pr = u / NQ, i = pr / D, k = pr % D;
         if (lev.gamma && i > k) continue;       // symmetric: filled from (k, i)
@@ -622,34 +644,26 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
     constexpr int NN = 2 * (D + 1) * MT;   // x_{E-e_k}|hi, x_{E+e_k}|lo
     constexpr int NTR = 2 * D * MT;        // s_E[i][k] lo/hi
     constexpr int PER_K = NX + NN + NTR;
+    // one code path for the three kinds of trace (selected source, face and
+    // destination): x_E at its faces, the neighbours' x at the shared faces,
+    // s_E at its faces
     for (int u = lane; u < D * PER_K; u += NT) {
       const int k = u / PER_K, r = u % PER_K;
       const int base_mt = r % MT;
       const int base = compose<M>(base_mt, 0, k), st = stride_of<M>(k);
-      if (r < NX) {
-        const int f = (r / MT) % (D + 1), side = r / (MT * (D + 1));
-        const T* uu = &w.xs[0][f * NQ + base];
-        T v = 0;
+      const bool isx = r < NX, isn = !isx && r < NX + NN;
+      const int r2 = isx ? r : (isn ? r - NX : r - NX - NN);
+      const int fx = (r2 / MT) % (D + 1), sx = r2 / (MT * (D + 1));
+      const int fs = (r2 / MT) % D, ss = r2 / (MT * D);
+      const int f = isx || isn ? fx : fs, side = isx || isn ? sx : ss;
+      const T* src = isx ? &w.xs[0][f * NQ + base]
+                         : (isn ? &w.xs[side ? 1 + D + k : 1 + k][f * NQ + base] : &w.s0[f * D + k][base]);
+      T* dst = isx ? &w.trx[side][k][f][base_mt] : (isn ? &w.trn[side][k][f][base_mt] : &w.trs[side][k][f][base_mt]);
+      const bool hi = isn ? side == 0 : side != 0;   // trace at the element's high face (e1) or low face (e0)
+      T v = 0;
 #pragma unroll
-        for (int bb = 0; bb < M; ++bb) v += (side ? tab.e1[bb] : tab.e0[bb]) * uu[bb * st];
-        w.trx[side][k][f][base_mt] = v;
-      } else if (r < NX + NN) {
-        const int r2 = r - NX;
-        const int f = (r2 / MT) % (D + 1), side = r2 / (MT * (D + 1));
-        const T* uu = &w.xs[side ? 1 + D + k : 1 + k][f * NQ + base];
-        T v = 0;
-#pragma unroll
-        for (int bb = 0; bb < M; ++bb) v += (side ? tab.e0[bb] : tab.e1[bb]) * uu[bb * st];
-        w.trn[side][k][f][base_mt] = v;
-      } else {
-        const int r2 = r - NX - NN;
-        const int i = (r2 / MT) % D, side = r2 / (MT * D);
-        const T* sv = &w.s0[i * D + k][base];
-        T v = 0;
-#pragma unroll
-        for (int bb = 0; bb < M; ++bb) v += (side ? tab.e1[bb] : tab.e0[bb]) * sv[bb * st];
-        w.trs[side][k][i][base_mt] = v;
-      }
+      for (int bb = 0; bb < M; ++bb) v += (hi ? tab.e1[bb] : tab.e0[bb]) * src[bb * st];
+      *dst = v;
     }
   }
   __syncthreads();
@@ -852,10 +866,12 @@ __device__ __forceinline__ void sym_prefetch(const InvWord<TI>* __restrict__ Ai,
   }
 }
 
-template <typename T, typename TI, int NB>
+// red: LDS scratch of 256 TR entries (not overlapping res or part), for the
+// column sums of the transposed contributions
+template <typename T, typename TI, int NB, int NT>
 __device__ __forceinline__ void sym_product(const InvWord<TI>* __restrict__ Ai,
                                             const InvWord<TI> (&pre)[SymProd<TI, NB>::PF][SymProd<TI, NB>::H],
-                                            const T* res, T (*part)[16 * SymProd<TI, NB>::TR], int lane) {
+                                            const T* res, T (*part)[16 * SymProd<TI, NB>::TR], T* red, int lane) {
   using SP = SymProd<TI, NB>;
   constexpr int TR = SP::TR, PF = SP::PF, H = SP::H, EL = SP::EL;
   using Word = typename SP::Word;
@@ -893,31 +909,30 @@ __device__ __forceinline__ void sym_product(const InvWord<TI>* __restrict__ Ai,
         }
       }
     }
-    // dir: sum over the 4 lanes of a row; trn: over the 16 lanes of a column set
+    // dir: sum over the 4 lanes of a row (cross-lane); trn: the 16 rows'
+    // partial column sums go through LDS (red[row][column])
 #pragma unroll
     for (int i = 0; i < TR; ++i) {
       dir[i] += shfl_xor64(dir[i], 1);
       dir[i] += shfl_xor64(dir[i], 2);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        T s = trn[i][v];
-        s += shfl_xor64(s, 4);
-        s += shfl_xor64(s, 8);
-        s += shfl_xor64(s, 16);
-        s += shfl_xor64(s, 32);
-        trn[i][v] = s;
-      }
     }
     if ((l & 3) == 0) {
 #pragma unroll
       for (int i = 0; i < TR; ++i) part[0][16 * i + row] = dir[i];
     }
-    if (l < 4) {
 #pragma unroll
-      for (int i = 0; i < TR; ++i)
+    for (int j = 1; j < TR; ++j)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) part[1][16 * i + c4 + v] = trn[i][v];
+      for (int v = 0; v < 4; ++v) red[row * 16 * TR + 16 * j + c4 + v] = trn[j][v];
+  }
+  __syncthreads();
+  for (int col = lane; col < 16 * TR; col += NT) {
+    T sum = 0;
+    if (col >= 16) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) sum += red[r * 16 * TR + col];
     }
+    part[1][col] = sum;
   }
   __syncthreads();
 }
@@ -945,7 +960,10 @@ __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
   const auto* Ai = reinterpret_cast<const typename SP::Word*>(inv + (size_t)idx * SP::NTILE * 256);
   typename SP::Word pre[SP::PF][SP::H];
   element_operator<T, D, P, NT, IF>(lev, tab, E, x, b, 0, w, [&]() { sym_prefetch<TI, NB>(Ai, pre, lane); });
-  sym_product<T, TI, NB>(Ai, pre, w.res, part, lane);
+  // the evaluation's arrays before res are free again: column-sum scratch
+  using W = Work<T, D, P, IF>;
+  static_assert(offsetof(W, res) >= 256 * SP::TR * sizeof(T), "LDS scratch");
+  sym_product<T, TI, NB, NT>(Ai, pre, w.res, part, reinterpret_cast<T*>(&w), lane);
   for (int r = lane; r < NB; r += NT) x[(size_t)E * NB + r] += part[0][r] + part[1][r];
 }
 
@@ -963,6 +981,7 @@ __global__ __launch_bounds__(NT) void k_first_colour(int lgn, const int* __restr
   using SP = SymProd<TI, NB>;
   __shared__ alignas(16) T res[NB];
   __shared__ T part[2][16 * SP::TR];
+  __shared__ T red[256 * SP::TR];
   const int lane = threadIdx.x;
   const int idx = xcd_remap(blockIdx.x, gridDim.x);
   const int E = colour_elem<D>(idx, pcol, lgn, elems);
@@ -975,7 +994,7 @@ __global__ __launch_bounds__(NT) void k_first_colour(int lgn, const int* __restr
     for (int t = lane; t < NB; t += NT) x[z + t] = (T)0;
   }
   __syncthreads();
-  sym_product<T, TI, NB>(Ai, pre, res, part, lane);
+  sym_product<T, TI, NB, NT>(Ai, pre, res, part, red, lane);
   for (int r = lane; r < NB; r += NT) x[(size_t)E * NB + r] = part[0][r] + part[1][r];
 }
 
