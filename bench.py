@@ -16,8 +16,10 @@ the BF16-block variant, are measured beside it.
 The roofline object covers the dominant kernel (the finest-level smoother
 colour pass), timed with HIP events on the library's stream during the timed
 solves; the algorithmic bytes per launch are (elements in the colour) x
-(n_b (n_b + 1) / 2 entries of the symmetric inverse + 3 n_b vector entries +
-(p+2)^d viscosity values) x the storage width; on levels whose blocks are all equal (periodic, constant
+(n_b^2 inverse entries + 3 n_b vector entries + (p+2)^d viscosity values) x
+the storage width, the method's byte model (the kernel moves only the upper
+tiles of the symmetric inverse: an effective bandwidth; `traffic` gives the
+bytes the counters saw); on levels whose blocks are all equal (periodic, constant
 coefficients) the one inverse is not streamed and that term is dropped.  cpu_baseline times the FP64 oracle on a bounded sample.
 """
 from __future__ import annotations
@@ -39,9 +41,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_smooth_colour_c2_n256_p3.
 
 
 def smoother_bytes_per_launch(prob, ncolours, inv_bytes, vec_bytes):
+    # the byte model of the method: every element's n_b x n_b inverse once per
+    # sweep, x and b in, x out, (p+2)^d viscosity values (the kernel stores and
+    # moves only the upper 16 x 16 tiles of the symmetric inverse, so this is
+    # an effective bandwidth in the model's units; the measured HBM traffic is
+    # reported beside it)
     nb = prob.nb
-    # the inverse is symmetric: n_b (n_b + 1) / 2 entries determine it
-    per_elem = nb * (nb + 1) // 2 * inv_bytes + 3 * nb * vec_bytes + (prob.p + 2) ** prob.dim * vec_bytes
+    per_elem = nb * nb * inv_bytes + 3 * nb * vec_bytes + (prob.p + 2) ** prob.dim * vec_bytes
     return prob.n_elements / ncolours * per_elem
 
 
