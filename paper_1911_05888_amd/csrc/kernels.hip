@@ -214,6 +214,9 @@ struct Work {
   alignas(16) T trrh[IF ? D : 1][D][S::MT];       // (IF) s_{E-e_k}[i][k] at its high face along k
   alignas(16) T flux[2][D][D + 1][S::MT];         // coefficients of e0 (lo) and e1 (hi) per axis/field
   alignas(16) T res[S::NB];
+  // the 1D tables K, e0, e1 (TabT layout) for lookups whose index differs
+  // between lanes (kernel-argument arrays indexed per lane become memory loads)
+  alignas(16) T tabs[MAXM * MAXM + 2 * MAXM];
   unsigned char ft[S::NFS][D][2];
   alignas(16) T fwl[S::NFS][D][2], fwr[S::NFS][D][2];
   // viscosity data, last: levels with constant viscosity do not allocate it
@@ -255,6 +258,7 @@ struct ElemData {
   T rvh[IF ? D : 1][RQ];
   T tr[D][2][TQ];
   T br[XQ];
+  T tabv;                        // entry `lane` of the tables K, e0, e1
   unsigned char fty[S::NFS][D][2];
   T fwl[S::NFS][D][2], fwr[S::NFS][D][2];
   T dsv[S::NSLOT], dsp[S::NSLOT];
@@ -263,15 +267,17 @@ struct ElemData {
 // Computes the stencil and face data of E and issues every load of the
 // element at once (addresses in bounds; masks are applied when staging).
 template <typename T, int D, int P, int NT, bool IF>
-__device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, int E, const T* __restrict__ x,
-                                           const T* __restrict__ b, int mode, ElemData<T, D, P, NT, IF>& d,
-                                           int lane) {
+__device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, const TabT<T>& tab, int E,
+                                           const T* __restrict__ x, const T* __restrict__ b, int mode,
+                                           ElemData<T, D, P, NT, IF>& d, int lane) {
   using S = Sz<D, P, IF>;
   using ED = ElemData<T, D, P, NT, IF>;
   constexpr int NQ = S::NQ, MT = S::MT, NB = S::NB, NFS = S::NFS, NSLOT = S::NSLOT;
   constexpr int XQ = ED::XQ, MQ = ED::MQ, RQ = ED::RQ, TQ = ED::TQ;
     const int n = lev.n, lgn = lev.lgn;
   d.E = E;
+  constexpr int TABN = MAXM * MAXM + 2 * MAXM;
+  d.tabv = reinterpret_cast<const T*>(&tab)[lane < TABN ? lane : 0];
   int c[D];
   coords_of<D>(E, lgn, c);
   d.se[0] = E;
@@ -327,22 +333,29 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, int E, const 
       const int e = d.se[sl] >= 0 ? d.se[sl] : E;
       d.xr[sl][q] = x[(size_t)e * NB + (i < NB ? i : 0)];
     }
-  if (lev.mmu) {
+  {
+    // issued whether or not the viscosity varies (a load under a branch makes
+    // every later wait assume the branch skipped it): without viscosity data
+    // the loads read x[0] and are discarded when staging
+    const bool vm = lev.mmu != nullptr;
+    const T* mb = vm ? lev.mmu : x;
+    const T* rb = vm ? lev.rmu : x;
     if constexpr (Work<T, D, P, IF>::STAGE_M) {
 #pragma unroll
       for (int q = 0; q < MQ; ++q) {
         const int t = lane + q * NT;
-        d.mr[q] = lev.mmu[(size_t)E * NQ * NQ + (t < NQ * NQ ? t : 0)];
+        d.mr[q] = mb[vm ? (size_t)E * NQ * NQ + (t < NQ * NQ ? t : 0) : 0];
       }
     }
     if constexpr (IF) {
+      const T* rhb = vm ? lev.rmuh : x;
 #pragma unroll
       for (int k = 0; k < D; ++k)
 #pragma unroll
         for (int q = 0; q < RQ; ++q) {
           const int t = lane + q * NT;
           const int e = d.se[1 + k];
-          d.rvh[k][q] = lev.rmuh[((size_t)(e >= 0 ? e : E) * D + k) * MT * NQ + (t < MT * NQ ? t : 0)];
+          d.rvh[k][q] = rhb[vm ? ((size_t)(e >= 0 ? e : E) * D + k) * MT * NQ + (t < MT * NQ ? t : 0) : 0];
         }
     }
 #pragma unroll
@@ -351,7 +364,7 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, int E, const 
       for (int q = 0; q < RQ; ++q) {
         const int t = lane + q * NT;
         const int e = d.se[1 + D + k];
-        d.rv[k][q] = lev.rmu[((size_t)(e >= 0 ? e : E) * D + k) * MT * NQ + (t < MT * NQ ? t : 0)];
+        d.rv[k][q] = rb[vm ? ((size_t)(e >= 0 ? e : E) * D + k) * MT * NQ + (t < MT * NQ ? t : 0) : 0];
       }
   }
   int fid0[D][2];
@@ -420,6 +433,7 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, int E, const 
 template <typename T, int D, int P, int NT, bool IF>
 __device__ __forceinline__ void elem_stage(const DevLevel<T>& lev, const ElemData<T, D, P, NT, IF>& d,
                                            Work<T, D, P, IF>& w, int lane) {
+  if (lane < MAXM * MAXM + 2 * MAXM) w.tabs[lane] = d.tabv;
   using S = Sz<D, P, IF>;
   using ED = ElemData<T, D, P, NT, IF>;
   constexpr int NQ = S::NQ, MT = S::MT, NB = S::NB, NFS = S::NFS, NSLOT = S::NSLOT;
@@ -662,7 +676,7 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
       const bool hi = isn ? side == 0 : side != 0;   // trace at the element's high face (e1) or low face (e0)
       T v = 0;
 #pragma unroll
-      for (int bb = 0; bb < M; ++bb) v += (hi ? tab.e1[bb] : tab.e0[bb]) * src[bb * st];
+      for (int bb = 0; bb < M; ++bb) v += w.tabs[MAXM * MAXM + (hi ? MAXM : 0) + bb] * src[bb * st];
       *dst = v;
     }
   }
@@ -750,13 +764,13 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
         const T* sv = &w.s0[i * D + k][base];
         T vol = 0;
 #pragma unroll
-        for (int bb = 0; bb < M; ++bb) vol += tab.K[bb * M + ak] * sv[bb * st];
-        acc += hinv * vol + tab.e0[ak] * w.flux[0][k][i][tt] + tab.e1[ak] * w.flux[1][k][i][tt];
+        for (int bb = 0; bb < M; ++bb) vol += w.tabs[bb * M + ak] * sv[bb * st];
+        acc += hinv * vol + w.tabs[MAXM * MAXM + ak] * w.flux[0][k][i][tt] + w.tabs[MAXM * MAXM + MAXM + ak] * w.flux[1][k][i][tt];
         if (k == i) {
           const T* pv = &w.xs[0][D * NQ + base];
           T pvol = 0;
 #pragma unroll
-          for (int bb = 0; bb < M; ++bb) pvol += tab.K[bb * M + ak] * pv[bb * st];
+          for (int bb = 0; bb < M; ++bb) pvol += w.tabs[bb * M + ak] * pv[bb * st];
           acc -= hinv * pvol;
         }
       }
@@ -768,7 +782,7 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
       for (int k = 0; k < D; ++k) {
         const int ak = k == 0 ? digit_c<M, 0>(a) : (k == 1 ? digit_c<M, 1>(a) : digit_c<M, 2>(a));
         const int tt = k == 0 ? tang_c<M, 0>(a) : (k == 1 ? tang_c<M, 1>(a) : tang_c<M, 2>(a));
-        acc += tab.e0[ak] * w.flux[0][k][D][tt] + tab.e1[ak] * w.flux[1][k][D][tt];
+        acc += w.tabs[MAXM * MAXM + ak] * w.flux[0][k][D][tt] + w.tabs[MAXM * MAXM + MAXM + ak] * w.flux[1][k][D][tt];
       }
     }
     if (lev.dscale) acc *= (f == D ? ds0p : ds0v);
@@ -800,7 +814,7 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
                                                  int mode, Work<T, D, P, IF>& w, Hook after_loads = Hook()) {
   ElemData<T, D, P, NT, IF> d;
   const int lane = threadIdx.x;
-  elem_issue<T, D, P, NT, IF>(lev, E, x, b, mode, d, lane);
+  elem_issue<T, D, P, NT, IF>(lev, tab, E, x, b, mode, d, lane);
   after_loads();
   elem_stage<T, D, P, NT, IF>(lev, d, w, lane);
   elem_compute<T, D, P, NT, IF>(lev, tab, E, d.vmask, mode, d.br, d.dsv[0], d.dsp[0], w, lane);
@@ -854,16 +868,18 @@ struct SymProd {
   static constexpr int PF = NTILE < PFMAX ? NTILE : PFMAX;
 };
 
+// every lane issues the loads (lanes 64.. repeat the first wavefront's
+// addresses): a load under a branch would make the waits of the evaluation
+// that follows assume it was skipped, and wait for these tiles too
 template <typename TI, int NB>
 __device__ __forceinline__ void sym_prefetch(const InvWord<TI>* __restrict__ Ai,
                                              InvWord<TI> (&pre)[SymProd<TI, NB>::PF][SymProd<TI, NB>::H], int lane) {
   using SP = SymProd<TI, NB>;
-  if (lane < 64) {
+  const int l = lane & 63;
 #pragma unroll
-    for (int t = 0; t < SP::PF; ++t)
+  for (int t = 0; t < SP::PF; ++t)
 #pragma unroll
-      for (int h = 0; h < SP::H; ++h) pre[t][h] = __builtin_nontemporal_load(&Ai[(t * SP::H + h) * 64 + lane]);
-  }
+    for (int h = 0; h < SP::H; ++h) pre[t][h] = __builtin_nontemporal_load(&Ai[(t * SP::H + h) * 64 + l]);
 }
 
 // red: LDS scratch of 256 TR entries (not overlapping res or part), for the
