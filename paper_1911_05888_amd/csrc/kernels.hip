@@ -216,7 +216,7 @@ struct Work {
   alignas(16) T res[S::NB];
   // the 1D tables K, e0, e1 (TabT layout) for lookups whose index differs
   // between lanes (kernel-argument arrays indexed per lane become memory loads)
-  alignas(16) T tabs[MAXM * MAXM + 2 * MAXM];
+  alignas(16) T tabs[3 * MAXM * MAXM + 2 * MAXM];   // K, e0, e1, P[0], P[1]
   unsigned char ft[S::NFS][D][2];
   alignas(16) T fwl[S::NFS][D][2], fwr[S::NFS][D][2];
   // viscosity data, last: levels with constant viscosity do not allocate it
@@ -258,7 +258,7 @@ struct ElemData {
   T rvh[IF ? D : 1][RQ];
   T tr[D][2][TQ];
   T br[XQ];
-  T tabv;                        // entry `lane` of the tables K, e0, e1
+  T tabv;                        // entry `lane` of the tables K, e0, e1, P
   unsigned char fty[S::NFS][D][2];
   T fwl[S::NFS][D][2], fwr[S::NFS][D][2];
   T dsv[S::NSLOT], dsp[S::NSLOT];
@@ -276,7 +276,8 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, const TabT<T>
   constexpr int XQ = ED::XQ, MQ = ED::MQ, RQ = ED::RQ, TQ = ED::TQ;
     const int n = lev.n, lgn = lev.lgn;
   d.E = E;
-  constexpr int TABN = MAXM * MAXM + 2 * MAXM;
+  constexpr int TABN = 3 * MAXM * MAXM + 2 * MAXM;
+  static_assert(TABN <= 64, "one table entry per lane of the first wavefront");
   d.tabv = reinterpret_cast<const T*>(&tab)[lane < TABN ? lane : 0];
   int c[D];
   coords_of<D>(E, lgn, c);
@@ -433,7 +434,7 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, const TabT<T>
 template <typename T, int D, int P, int NT, bool IF>
 __device__ __forceinline__ void elem_stage(const DevLevel<T>& lev, const ElemData<T, D, P, NT, IF>& d,
                                            Work<T, D, P, IF>& w, int lane) {
-  if (lane < MAXM * MAXM + 2 * MAXM) w.tabs[lane] = d.tabv;
+  if (lane < 3 * MAXM * MAXM + 2 * MAXM) w.tabs[lane] = d.tabv;
   using S = Sz<D, P, IF>;
   using ED = ElemData<T, D, P, NT, IF>;
   constexpr int NQ = S::NQ, MT = S::MT, NB = S::NB, NFS = S::NFS, NSLOT = S::NSLOT;
@@ -1136,6 +1137,21 @@ __device__ __forceinline__ T pfull(const TabT<T>& tab, int o, int af, int ac) {
   return v;
 }
 
+// the same entry from a copy of the two 1D tables P[0], P[1] (MAXM x MAXM
+// each) in LDS, for indices that differ between lanes
+template <typename T, int D, int M>
+__device__ __forceinline__ T pfull_lds(const T* Pt, int o, int af, int ac) {
+  T v = 1;
+  int fa = af, ca = ac;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    v *= Pt[((o >> k) & 1) * MAXM * MAXM + (fa % M) * M + (ca % M)];
+    fa /= M;
+    ca /= M;
+  }
+  return v;
+}
+
 // r_c = I^T (b - A x): one work-group per coarse element, looping over children.
 template <typename T, int D, int P, int NT, bool IF>
 __global__ __launch_bounds__(NT) void k_residual_restrict(DevLevel<T> lev, TabT<T> tab, const T* __restrict__ b,
@@ -1163,7 +1179,7 @@ __global__ __launch_bounds__(NT) void k_residual_restrict(DevLevel<T> lev, TabT<
       if (t < NB) {
         const int f = t / NQ, ac = t % NQ;
         T s = 0;
-        for (int af = 0; af < NQ; ++af) s += pfull<T, D, M>(tab, o, af, ac) * w.res[f * NQ + af];
+        for (int af = 0; af < NQ; ++af) s += pfull_lds<T, D, M>(w.tabs + MAXM * MAXM + 2 * MAXM, o, af, ac) * w.res[f * NQ + af];
         acc[q] += s;
       }
     }
@@ -1184,6 +1200,9 @@ template <typename T, int D, int P>
 __global__ void k_restrict(int lgn, TabT<T> tab, const T* __restrict__ r, T* __restrict__ rc, int64_t total) {
   using S = Sz<D, P>;
   constexpr int M = S::M, NQ = S::NQ, NB = S::NB;
+  __shared__ T Pt[2 * MAXM * MAXM];
+  if (threadIdx.x < 2 * MAXM * MAXM) Pt[threadIdx.x] = (&tab.P[0][0])[threadIdx.x];
+  __syncthreads();
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= total) return;
   const int C = (int)(t / NB), rem = (int)(t % NB);
@@ -1197,7 +1216,7 @@ __global__ void k_restrict(int lgn, TabT<T> tab, const T* __restrict__ r, T* __r
     for (int j = 0; j < D; ++j) cf[j] = 2 * cc[j] + ((o >> j) & 1);
     const T* rv = r + (size_t)index_of<D>(cf, lgn) * NB + f * NQ;
     T s = 0;
-    for (int af = 0; af < NQ; ++af) s += pfull<T, D, M>(tab, o, af, ac) * rv[af];
+    for (int af = 0; af < NQ; ++af) s += pfull_lds<T, D, M>(Pt, o, af, ac) * rv[af];
     acc += s;
   }
   rc[t] = acc;
@@ -1208,6 +1227,9 @@ template <typename T, int D, int P>
 __global__ void k_prolong_add(int n, TabT<T> tab, const T* __restrict__ xc, T* __restrict__ x, int64_t total) {
   using S = Sz<D, P>;
   constexpr int M = S::M, NQ = S::NQ, NB = S::NB;
+  __shared__ T Pt[2 * MAXM * MAXM];
+  if (threadIdx.x < 2 * MAXM * MAXM) Pt[threadIdx.x] = (&tab.P[0][0])[threadIdx.x];
+  __syncthreads();
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= total) return;
   int64_t E = t / NB;
@@ -1221,7 +1243,7 @@ __global__ void k_prolong_add(int n, TabT<T> tab, const T* __restrict__ xc, T* _
   const int64_t C = index_of<D>(pc, lgn - 1);
   const T* xv = xc + C * NB + f * NQ;
   T s = 0;
-  for (int ac = 0; ac < NQ; ++ac) s += pfull<T, D, M>(tab, o, af, ac) * xv[ac];
+  for (int ac = 0; ac < NQ; ++ac) s += pfull_lds<T, D, M>(Pt, o, af, ac) * xv[ac];
   x[t] += s;
 }
 
