@@ -329,7 +329,7 @@ void upload_ops(ldgs_ctx* c, PrecStore<T>& S, bool all_levels) {
 
 // entries of one element's inverse in the smoother's symmetric tile layout
 // (see sym_tiles): inv is row-major nb x nb; its symmetric part is stored, out
-// receives NTILE * 256 values
+// receives sym_tile_off(TR, NTILE) values
 static void arrange_inverse(const double* inv, int nb, int bytes, double* out) {
   const SymTiles L = sym_tiles(nb, bytes);
   auto sym = [&](int r, int c) {
@@ -338,10 +338,16 @@ static void arrange_inverse(const double* inv, int nb, int bytes, double* out) {
   for (int i = 0; i < L.TR; ++i)
     for (int j = i; j < L.TR; ++j) {
       const int t = i * L.TR - i * (i - 1) / 2 + (j - i);
-      for (int l = 0; l < 64; ++l)
-        for (int v = 0; v < 4; ++v) {
-          const int h = v / L.EL, u = v % L.EL;
-          out[((size_t)(t * L.H + h) * 64 + l) * L.EL + u] = sym(16 * i + l / 4, 16 * j + 4 * (l % 4) + v);
+      const int nblk = i == j ? SYM_DBLOCKS : 64;
+      double* o = out + sym_tile_off(L.TR, t);
+      for (int r = 0; r < 16; ++r)
+        for (int cb = 0; cb < 4; ++cb) {
+          if (i == j && cb < r / 4) continue;       // below the diagonal: not stored
+          const int slot = i == j ? sym_dslot(r, cb) : 4 * r + cb;
+          for (int v = 0; v < 4; ++v) {
+            const int h = v / L.EL, u = v % L.EL;
+            o[((size_t)h * nblk + slot) * L.EL + u] = sym(16 * i + r, 16 * j + 4 * cb + v);
+          }
         }
     }
 }
@@ -421,9 +427,10 @@ static bool uniform_blocks(const ldgs_ctx* c, const Level& L) {
 void build_inverses(ldgs_ctx* c, bool need64, bool need32, bool need16) {
   const int nb = c->g.nb;
   const size_t nb2 = (size_t)nb * nb;
-  const size_t st64 = (size_t)sym_tiles(nb, 8).NTILE * 256;
-  const size_t st32 = (size_t)sym_tiles(nb, 4).NTILE * 256;
-  const size_t st16 = (size_t)sym_tiles(nb, 2).NTILE * 256;
+  const int trs = sym_tiles(nb, 4).TR;
+  const size_t st64 = (size_t)sym_tile_off(trs, sym_tiles(nb, 8).NTILE);
+  const size_t st32 = (size_t)sym_tile_off(trs, sym_tiles(nb, 4).NTILE);
+  const size_t st16 = (size_t)sym_tile_off(trs, sym_tiles(nb, 2).NTILE);
   for (size_t l = 0; l + 1 < c->levels.size(); ++l) {
     Level& L = c->levels[l];
     std::vector<int64_t> off(L.ncol + 1, 0);

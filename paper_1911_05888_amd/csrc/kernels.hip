@@ -864,10 +864,28 @@ template <typename TI, int NB>
 struct SymProd {
   static constexpr SymTiles LY = sym_tiles(NB, (int)sizeof(TI));
   static constexpr int TR = LY.TR, NTILE = LY.NTILE, H = LY.H, EL = LY.EL;
+  static constexpr int ESTRIDE = sym_tile_off(TR, NTILE);   // entries per element
   using Word = InvWord<TI>;
   static constexpr int PFMAX = 32 / (H * (int)(sizeof(Word) / 4));
   static constexpr int PF = NTILE < PFMAX ? NTILE : PFMAX;
 };
+
+// tile row of tile t (tiles numbered row by row over the upper triangle)
+constexpr int sym_tile_row(int TR, int t) {
+  int i = 0;
+  while (t >= TR - i) { t -= TR - i; ++i; }
+  return i;
+}
+
+// word of lane l's load h of tile t (diag: a diagonal tile, whose lanes below
+// the diagonal read the first stored block and discard it)
+template <typename TI, int NB>
+__device__ __forceinline__ int sym_word(int t, bool diag, int h, int l) {
+  using SP = SymProd<TI, NB>;
+  const int r = l >> 2, cb = l & 3;
+  const int slot = diag ? (cb >= (r >> 2) ? sym_dslot(r, cb) : 0) : l;
+  return sym_tile_off(SP::TR, t) / SP::EL + h * (diag ? SYM_DBLOCKS : 64) + slot;
+}
 
 // every lane issues the loads (lanes 64.. repeat the first wavefront's
 // addresses): a load under a branch would make the waits of the evaluation
@@ -878,9 +896,12 @@ __device__ __forceinline__ void sym_prefetch(const InvWord<TI>* __restrict__ Ai,
   using SP = SymProd<TI, NB>;
   const int l = lane & 63;
 #pragma unroll
-  for (int t = 0; t < SP::PF; ++t)
+  for (int t = 0; t < SP::PF; ++t) {
+    const int i = sym_tile_row(SP::TR, t);
+    const bool diag = t == i * SP::TR - i * (i - 1) / 2;
 #pragma unroll
-    for (int h = 0; h < SP::H; ++h) pre[t][h] = __builtin_nontemporal_load(&Ai[(t * SP::H + h) * 64 + l]);
+    for (int h = 0; h < SP::H; ++h) pre[t][h] = __builtin_nontemporal_load(&Ai[sym_word<TI, NB>(t, diag, h, l)]);
+  }
 }
 
 // red: LDS scratch of 256 TR entries (not overlapping res or part), for the
@@ -908,19 +929,23 @@ __device__ __forceinline__ void sym_product(const InvWord<TI>* __restrict__ Ai,
 #pragma unroll
       for (int j = i; j < TR; ++j) {
         const int t = i * TR - i * (i - 1) / 2 + (j - i);
+        const bool diag = j == i;
         Word raw[H];
 #pragma unroll
         for (int h = 0; h < H; ++h)
-          raw[h] = (t < PF) ? pre[t < PF ? t : 0][h] : __builtin_nontemporal_load(&Ai[(t * H + h) * 64 + l]);
+          raw[h] = (t < PF) ? pre[t < PF ? t : 0][h] : __builtin_nontemporal_load(&Ai[sym_word<TI, NB>(t, diag, h, l)]);
+        // a diagonal tile: blocks left of the diagonal block are not stored
+        // (their entries come from the mirrored blocks right of it)
+        const bool keep = !diag || (l & 3) >= (row >> 2);
         T a[4], rj[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          a[v] = inv_entry<T, TI>(raw[v / EL], v % EL);
+          a[v] = keep ? inv_entry<T, TI>(raw[v / EL], v % EL) : (T)0;
           const int cj = 16 * j + c4 + v;
           rj[v] = cj < NB ? res[cj] : (T)0;
         }
         dir[i] += a[0] * rj[0] + a[1] * rj[1] + a[2] * rj[2] + a[3] * rj[3];
-        if (j != i) {
+        if (!diag || (l & 3) > (row >> 2)) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) trn[j][v] += a[v] * ri;
         }
@@ -938,17 +963,15 @@ __device__ __forceinline__ void sym_product(const InvWord<TI>* __restrict__ Ai,
       for (int i = 0; i < TR; ++i) part[0][16 * i + row] = dir[i];
     }
 #pragma unroll
-    for (int j = 1; j < TR; ++j)
+    for (int j = 0; j < TR; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) red[row * 16 * TR + 16 * j + c4 + v] = trn[j][v];
   }
   __syncthreads();
   for (int col = lane; col < 16 * TR; col += NT) {
     T sum = 0;
-    if (col >= 16) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) sum += red[r * 16 * TR + col];
-    }
+    for (int r = 0; r < 16; ++r) sum += red[r * 16 * TR + col];
     part[1][col] = sum;
   }
   __syncthreads();
@@ -974,7 +997,7 @@ __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
   const int lane = threadIdx.x;
   const int idx = xcd_remap(blockIdx.x, gridDim.x);
   const int E = colour_elem<D>(idx, pcol, lev.lgn, elems);
-  const auto* Ai = reinterpret_cast<const typename SP::Word*>(inv + (size_t)idx * SP::NTILE * 256);
+  const auto* Ai = reinterpret_cast<const typename SP::Word*>(inv + (size_t)idx * SP::ESTRIDE);
   typename SP::Word pre[SP::PF][SP::H];
   element_operator<T, D, P, NT, IF>(lev, tab, E, x, b, 0, w, [&]() { sym_prefetch<TI, NB>(Ai, pre, lane); });
   // the evaluation's arrays before res are free again: column-sum scratch
@@ -1002,7 +1025,7 @@ __global__ __launch_bounds__(NT) void k_first_colour(int lgn, const int* __restr
   const int lane = threadIdx.x;
   const int idx = xcd_remap(blockIdx.x, gridDim.x);
   const int E = colour_elem<D>(idx, pcol, lgn, elems);
-  const auto* Ai = reinterpret_cast<const typename SP::Word*>(inv + (size_t)idx * SP::NTILE * 256);
+  const auto* Ai = reinterpret_cast<const typename SP::Word*>(inv + (size_t)idx * SP::ESTRIDE);
   typename SP::Word pre[SP::PF][SP::H];
   sym_prefetch<TI, NB>(Ai, pre, lane);
   for (int t = lane; t < NB; t += NT) res[t] = b[(size_t)E * NB + t];

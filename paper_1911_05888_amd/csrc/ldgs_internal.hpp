@@ -48,15 +48,22 @@ struct Tab1D {
 // Symmetric tile layout of one element's inverse block for the smoother's
 // matrix-vector product.  The diagonal block of the (symmetric) LDG operator
 // is symmetric, so is its inverse: only the tiles on and above the diagonal
-// are stored.  The block, zero-padded to 16 TR rows and columns
+// are stored, and of a diagonal tile only the lane blocks that reach its upper
+// triangle.  The block, zero-padded to 16 TR rows and columns
 // (TR = ceil(nb / 16)), is cut into 16 x 16 tiles; tile (i, j), i <= j, has
 // number t = i TR - i (i - 1) / 2 + (j - i), NTILE = TR (TR + 1) / 2 tiles.
-// Lane l < 64 of a tile owns row l / 4 and columns 4 (l % 4) + v, v < 4.  One
-// load per lane reads LB = min(16, 4 * bytes) bytes (EL = LB / bytes entries);
-// H = 4 * bytes / LB loads cover the lane's four entries.  Entry v = h EL + u
-// of lane l in tile t is stored at entry offset ((t H + h) 64 + l) EL + u, so
-// the 64 lanes read consecutive words at every load.  Element stride: NTILE *
-// 256 entries.
+// Lane block (r, cb) of a tile is row r < 16, columns 4 cb .. 4 cb + 3 (the
+// block of lane l = 4 r + cb).  An off-diagonal tile stores all 64 blocks at
+// slot 4 r + cb; a diagonal tile stores the 40 blocks with cb >= r / 4, at slot
+// sym_dslot(r, cb), with their true entries (those of the block on the
+// diagonal that lie below it included).  Read back: every stored entry (r, c)
+// of tile (i, j) gives A[16i + r][16j + c]; off the diagonal, and in a
+// diagonal tile for blocks with cb > r / 4, also A[16j + c][16i + r].
+// One load reads LB = min(16, 4 * bytes) bytes (EL = LB / bytes entries) of a
+// block; H = 4 * bytes / LB loads cover it.  Entry v = h EL + u of slot s of a
+// tile with nblk stored blocks is at entry (h nblk + s) EL + u of the tile,
+// tiles follow one another in the order t (sym_tile_off), so each load of the
+// stored lanes reads consecutive words.  Element stride: sym_tile_off(NTILE).
 struct SymTiles {
   int TR, NTILE, LB, EL, H;
 };
@@ -66,6 +73,22 @@ constexpr SymTiles sym_tiles(int nb, int bytes) {
   L.EL = L.LB / bytes;
   L.H = 4 * bytes / L.LB;
   return L;
+}
+constexpr int SYM_DBLOCKS = 40;   // stored blocks of a diagonal tile
+// slot of block (r, cb), cb >= r / 4, of a diagonal tile
+constexpr int sym_dslot(int r, int cb) {
+  const int g = r / 4;
+  const int base = g == 0 ? 0 : (g == 1 ? 16 : (g == 2 ? 28 : 36));
+  return base + (r % 4) * (4 - g) + (cb - g);
+}
+// entry offset of tile t (tiles in the order t) for TR tile rows
+constexpr int sym_tile_off(int TR, int t) {
+  int off = 0, i = 0, j = 0;
+  for (int q = 0; q < t; ++q) {
+    off += (i == j ? SYM_DBLOCKS : 64) * 4;
+    if (++j == TR) j = ++i;
+  }
+  return off;
 }
 
 // Device view of one level's operator, element type T.

@@ -178,11 +178,18 @@ def test_host_only_context_refuses_device_calls():
     assert ei.value.status == E_UNSUPPORTED
 
 
+def _dslot(r, cb):
+    g = r // 4
+    return (0, 16, 28, 36)[g] + (r % 4) * (4 - g) + (cb - g)
+
+
 def test_inverse_layout_covers_every_entry():
     """The smoother's symmetric tile layout (the contract between the host
-    packing and the kernel): the stored upper 16 x 16 tiles, read as the kernel
-    reads them (tile (i, j) as T and, off the diagonal, T^T), give every entry
-    of the block exactly once, and the stored words are all distinct."""
+    packing and the kernel): the stored blocks of the upper 16 x 16 tiles, read
+    as the kernel reads them (every stored entry (r, c) of tile (i, j) as
+    A[16i+r][16j+c]; as A[16j+c][16i+r] too off the diagonal, and in a diagonal
+    tile for blocks right of the diagonal block), give every entry of the block
+    exactly once, and the stored words are all distinct and dense."""
     for nb in (12, 27, 32, 48, 108, 256):
         for bytes_ in (8, 4, 2):
             TR = (nb + 15) // 16
@@ -192,19 +199,29 @@ def test_inverse_layout_covers_every_entry():
             H = 4 * bytes_ // LB
             seen = np.zeros((16 * TR, 16 * TR), dtype=int)
             offsets = set()
+            toff = 0
             for i in range(TR):
                 for j in range(i, TR):
                     t = i * TR - i * (i - 1) // 2 + (j - i)
                     assert 0 <= t < NTILE
+                    diag = i == j
+                    nblk = 40 if diag else 64
                     for l in range(64):
+                        r, cb = l // 4, l % 4
+                        if diag and cb < r // 4:
+                            continue                      # not stored
+                        slot = _dslot(r, cb) if diag else l
+                        assert 0 <= slot < nblk
                         for v in range(4):
                             h, u = divmod(v, EL)
-                            off = ((t * H + h) * 64 + l) * EL + u
-                            assert off not in offsets and off < NTILE * 256
+                            off = toff + (h * nblk + slot) * EL + u
+                            assert off not in offsets
                             offsets.add(off)
-                            r, c = 16 * i + l // 4, 16 * j + 4 * (l % 4) + v
-                            seen[r, c] += 1
-                            if i != j:
-                                seen[c, r] += 1
+                            row, col = 16 * i + r, 16 * j + 4 * cb + v
+                            seen[row, col] += 1
+                            if not diag or cb > r // 4:
+                                seen[col, row] += 1
+                    toff += nblk * 4
             assert (seen == 1).all()
-            assert len(offsets) == NTILE * 256
+            assert offsets == set(range(toff))
+            assert toff == TR * 160 + (NTILE - TR) * 256
