@@ -51,7 +51,7 @@ def smoother_bytes_per_launch(prob, ncolours, inv_bytes, vec_bytes):
     return prob.n_elements / ncolours * per_elem
 
 
-def cpu_baseline(n_sample=32, cycles=15):
+def cpu_baseline(n_sample=64, cycles=8):
     """The FP64 oracle's V-cycle on the n_sample^2 grid of the same problem."""
     from threadpoolctl import threadpool_limits
     from synth import c2_dirichlet_varmu
