@@ -14,8 +14,8 @@ solve time).  The plain FP64 stationary V-cycle to the same tolerance, and
 the BF16-block variant, are measured beside it.
 
 The roofline object covers the dominant kernel (the finest-level smoother
-colour pass), timed with HIP events on the library's stream during the timed
-solves; the algorithmic bytes per launch are (elements in the colour) x
+colour pass), timed with HIP event pairs on the library's stream around every
+8th such pass during the timed solves; the algorithmic bytes per launch are (elements in the colour) x
 (n_b^2 inverse entries + 3 n_b vector entries + (p+2)^d viscosity values) x
 the storage width, the method's byte model (the kernel moves only the upper
 tiles of the symmetric inverse: an effective bandwidth; `traffic` gives the
@@ -51,7 +51,7 @@ def smoother_bytes_per_launch(prob, ncolours, inv_bytes, vec_bytes):
     return prob.n_elements / ncolours * per_elem
 
 
-def cpu_baseline(n_sample=64, cycles=8):
+def cpu_baseline(n_sample=64, cycles=25):
     """The FP64 oracle's V-cycle on the n_sample^2 grid of the same problem."""
     from threadpoolctl import threadpool_limits
     from synth import c2_dirichlet_varmu
@@ -186,7 +186,7 @@ def main():
     for _ in range(args.warmup):
         solve(V_FP32, IR)
     torch.cuda.synchronize()
-    ctx.profile(True)
+    ctx.profile(8)        # every 8th finest colour pass carries an event pair
     iters = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):

@@ -113,7 +113,8 @@ struct ldgs_ctx {
   int* d_orig = nullptr;
   int64_t d_orig_cap = 0;
   // optional timing of the finest-level smoother launches (HIP events on the stream)
-  bool prof = false;
+  int prof = 0;                  // time every prof-th finest colour pass (0: off)
+  int64_t prof_count = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
@@ -638,7 +639,7 @@ void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* 
   const size_t esz = pl.inv_kind == 0 ? 8 : (pl.inv_kind == 1 ? 4 : 2);
   int64_t o = pl.col_off[col], cnt = pl.col_off[col + 1] - o;
   const void* inv = (const char*)pl.inv + o * pl.inv_stride * esz;
-  const bool timed = c->prof && l == 0;
+  const bool timed = c->prof > 0 && l == 0 && (c->prof_count++ % c->prof) == 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
     e0 = next_event(c);
@@ -679,22 +680,11 @@ void first_colour(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x) {
   PrecLevel<T>& pl = S.lv[l];
   const int64_t cnt = pl.col_off[1], nzero = c->levels[l].NE - cnt;
   const int pcol = pl.parity ? 0 : -1;
-  const bool timed = c->prof && l == 0;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (timed) {
-    e0 = next_event(c);
-    e1 = next_event(c);
-    HIPCHK(hipEventRecord(e0, c->stream));
-  }
   if (pl.ainv_sh)
     LCHK(launch_shared_update<T>(c->stream, cnt, c->g.nb, pl.ainv_sh, b, pl.elems, x, 1, pl.elems + cnt, nzero));
   else
     LCHK(launch_first_colour<T>(cfg, log2i(c->levels[l].n), pl.elems, pcol, cnt, pl.inv, pl.inv_kind, b, x,
                                 pl.elems + cnt, nzero));
-  if (timed) {
-    HIPCHK(hipEventRecord(e1, c->stream));
-    c->prof_ev.emplace_back(e0, e1);
-  }
 }
 
 // sweeps of colour passes; zero_x: x is taken as zero on entry (and need not
@@ -1462,7 +1452,8 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxi
 // ---- profiling -------------------------------------------------------------
 ldgs_status ldgs_profile(ldgs_ctx* ctx, int enable) {
   if (!ctx) return LDGS_E_ARG;
-  ctx->prof = enable != 0;
+  ctx->prof = enable > 0 ? enable : 0;
+  ctx->prof_count = 0;
   ctx->prof_ev.clear();
   ctx->ev_used = 0;
   return LDGS_OK;

@@ -361,8 +361,10 @@ class Context:
     def level_smooth_colour_f32(self, level, colour, vprec, b, x):
         self._check(_lib.ldgs_level_smooth_colour_f32(self._h, level, colour, vprec, _dptr(b), _dptr(x)))
 
-    def profile(self, enable=True):
-        self._check(_lib.ldgs_profile(self._h, int(bool(enable))))
+    def profile(self, stride=1):
+        """Time every `stride`-th finest colour pass (True: every one; 0 or
+        False: off)."""
+        self._check(_lib.ldgs_profile(self._h, int(stride)))
 
     def profile_read(self):
         ms, n = C.c_double(), C.c_int64()
