@@ -83,6 +83,7 @@ struct ldgs_ctx {
   int k0 = 1;
   int small_grid = 4096;       // see LaunchCfg; LDGS_SMALL_GRID overrides (tests)
   bool shared_inverse = true;  // one inverse per level with equal blocks; LDGS_SHARED_INVERSE=0 disables
+  bool use_graph = true;       // V-cycles replayed from captured HIP graphs; LDGS_GRAPH=0 disables
   std::vector<int> kernel_offsets;
   PrecStore<double> s64;
   PrecStore<float> s32;      // float arithmetic, float inverses
@@ -119,7 +120,26 @@ struct ldgs_ctx {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<void*> allocs;
+  // captured V-cycles, one per (precision, zero guess, timing stride); the
+  // event pairs recorded inside a graph are read after the next host
+  // synchronisation (they are re-recorded at every replay)
+  struct CycleGraph {
+    int vp;
+    bool zero_x;
+    int prof;
+    hipGraphExec_t exec;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  };
+  std::vector<CycleGraph> graphs;
+  bool capturing = false;
+  std::vector<hipEvent_t> cap_pool;                         // events owned by graphs
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> cap_ev;    // pairs recorded during a capture
+  const std::vector<std::pair<hipEvent_t, hipEvent_t>>* prof_pending = nullptr;
+  double prof_acc_ms = 0.0;
+  int64_t prof_acc_n = 0;
   ~ldgs_ctx() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    for (hipEvent_t e : cap_pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
     if (stream_owned && stream) (void)hipStreamDestroy(stream);
@@ -618,6 +638,12 @@ ldgs_status handle(ldgs_ctx* c, const Fail& f) {
 // the V-cycle (Algorithm 1) on one precision store
 // ---------------------------------------------------------------------------
 hipEvent_t next_event(ldgs_ctx* c) {
+  if (c->capturing) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    c->cap_pool.push_back(e);
+    return e;
+  }
   if (c->ev_used == c->ev_pool.size()) {
     hipEvent_t e;
     HIPCHK(hipEventCreate(&e));
@@ -668,7 +694,7 @@ void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* 
   }
   if (timed) {
     HIPCHK(hipEventRecord(e1, c->stream));
-    c->prof_ev.emplace_back(e0, e1);
+    (c->capturing ? c->cap_ev : c->prof_ev).emplace_back(e0, e1);
   }
 }
 
@@ -735,6 +761,75 @@ void cycle(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x, bool zero_x) {
   smooth(c, S, l, b, x, c->P.nu2);
 }
 
+// adds the timed passes of the last replayed graph (complete after a host
+// synchronisation, or waited for here) to the profile totals
+void collect_graph_prof(ldgs_ctx* c) {
+  if (!c->prof_pending) return;
+  const auto& ev = *c->prof_pending;
+  c->prof_pending = nullptr;
+  if (ev.empty()) return;
+  HIPCHK(hipEventSynchronize(ev.back().second));
+  for (const auto& pr : ev) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+    c->prof_acc_ms += ms;
+    ++c->prof_acc_n;
+  }
+}
+
+// One V-cycle on the context's finest work vectors, replayed from a captured
+// graph (captured on first use: the launch sequence and every pointer are
+// fixed after setup).  A replay takes the host about half the time of the
+// ~170 stream launches of a cycle; on the benchmark problem the GPU is the
+// slower side either way.  Any failure to capture falls back to direct
+// launches for the context's life.
+template <typename T>
+void run_cycle(ldgs_ctx* c, PrecStore<T>& S, int vp, T* b, T* x, bool zero_x) {
+  if (!c->use_graph) {
+    cycle<T>(c, S, 0, b, x, zero_x);
+    return;
+  }
+  collect_graph_prof(c);   // before the graph list can grow (it holds the pending events)
+  ldgs_ctx::CycleGraph* g = nullptr;
+  for (auto& e : c->graphs)
+    if (e.vp == vp && e.zero_x == zero_x && e.prof == c->prof) g = &e;
+  if (!g) {
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      c->use_graph = false;
+      cycle<T>(c, S, 0, b, x, zero_x);
+      return;
+    }
+    c->capturing = true;
+    c->cap_ev.clear();
+    try {
+      cycle<T>(c, S, 0, b, x, zero_x);
+    } catch (...) {
+      c->capturing = false;
+      (void)hipStreamEndCapture(c->stream, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      throw;
+    }
+    c->capturing = false;
+    hipGraphExec_t exec = nullptr;
+    const bool ok = hipStreamEndCapture(c->stream, &graph) == hipSuccess && graph &&
+                    hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (!ok) {
+      (void)hipGetLastError();
+      c->use_graph = false;
+      cycle<T>(c, S, 0, b, x, zero_x);
+      return;
+    }
+    c->graphs.push_back({vp, zero_x, c->prof, exec, c->cap_ev});
+    g = &c->graphs.back();
+  }
+  HIPCHK(hipGraphLaunch(g->exec, c->stream));
+  c->prof_pending = &g->ev;
+}
+
 const double* dscale0(ldgs_ctx* c) { return c->P.diag_scaling ? c->d_dscale0 : nullptr; }
 
 // x <- V(b, x) on user (unscaled, FP64) vectors in precision vp.
@@ -747,14 +842,14 @@ void vcycle_user(ldgs_ctx* c, int vp, const double* b, double* x, bool zero_x) {
     if (!c->s64.built) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
     LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, b, c->w_b, 0, 0)));
     if (!zero_x) LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, x, c->w_x, 1, 0)));
-    cycle<double>(c, c->s64, 0, c->w_b, c->w_x, zero_x);
+    run_cycle<double>(c, c->s64, vp, c->w_b, c->w_x, zero_x);
     LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, c->w_x, x, 0, 0)));
   } else {
     PrecStore<float>& S = (vp == LDGS_V_FP32) ? c->s32 : c->s16;
     if (!S.built) throw Fail{LDGS_E_UNSUPPORTED, "requested V-cycle precision not built"};
     LCHK((launch_scale_cast<double, float>(c->stream, NE, nb, nvel, ds, b, c->w_b32, 0, 0)));
     if (!zero_x) LCHK((launch_scale_cast<double, float>(c->stream, NE, nb, nvel, ds, x, c->w_x32, 1, 0)));
-    cycle<float>(c, S, 0, c->w_b32, c->w_x32, zero_x);
+    run_cycle<float>(c, S, vp, c->w_b32, c->w_x32, zero_x);
     LCHK((launch_scale_cast<float, double>(c->stream, NE, nb, nvel, ds, c->w_x32, x, 0, 0)));
   }
 }
@@ -770,6 +865,7 @@ double host_sum_partials(ldgs_ctx* c, int nblk) {
   std::vector<double> h(nblk);
   HIPCHK(hipMemcpyAsync(h.data(), c->w_part, nblk * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  collect_graph_prof(c);
   double s = 0.0;
   for (double v : h) s += v;
   return s;
@@ -939,6 +1035,7 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
       if (v >= 1) c->small_grid = (int)v;
     }
     if (const char* si = std::getenv("LDGS_SHARED_INVERSE")) c->shared_inverse = std::strtol(si, nullptr, 10) != 0;
+    if (const char* gr = std::getenv("LDGS_GRAPH")) c->use_graph = std::strtol(gr, nullptr, 10) != 0;
     c->k0 = kernel_dim(P);
     if (c->k0 == 1) c->kernel_offsets = {P.dim * c->g.nq};
     else for (int i = 0; i <= P.dim; ++i) c->kernel_offsets.push_back(i * c->g.nq);
@@ -1455,6 +1552,9 @@ ldgs_status ldgs_profile(ldgs_ctx* ctx, int enable) {
   ctx->prof = enable > 0 ? enable : 0;
   ctx->prof_count = 0;
   ctx->prof_ev.clear();
+  ctx->prof_pending = nullptr;
+  ctx->prof_acc_ms = 0.0;
+  ctx->prof_acc_n = 0;
   ctx->ev_used = 0;
   return LDGS_OK;
 }
@@ -1463,16 +1563,19 @@ ldgs_status ldgs_profile_read(ldgs_ctx* ctx, double* total_ms, int64_t* launches
   try {
     check_ctx(ctx, true);
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    double tot = 0.0;
+    collect_graph_prof(ctx);
+    double tot = ctx->prof_acc_ms;
     for (auto& pr : ctx->prof_ev) {
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
       tot += ms;
     }
     if (total_ms) *total_ms = tot;
-    if (launches) *launches = (int64_t)ctx->prof_ev.size();
+    if (launches) *launches = (int64_t)ctx->prof_ev.size() + ctx->prof_acc_n;
     ctx->prof_ev.clear();
     ctx->ev_used = 0;
+    ctx->prof_acc_ms = 0.0;
+    ctx->prof_acc_n = 0;
     return LDGS_OK;
   } catch (const Fail& f) {
     return handle(ctx, f);
