@@ -206,3 +206,43 @@ def test_shared_inverse_matches_per_element_inverses(monkeypatch):
     e = _rel(_host(xs.double()), _host(xp.double()))
     print(f"[scale] FP32 shared vs per-element: {e:.2e}", flush=True)
     assert e <= 1e-4
+
+
+FULL_CASES = {
+    # 3D unsteady periodic, 64^3 Q_2: every level on the one-inverse path,
+    # two-wavefront launches of the 3D evaluation
+    "c3_n64_p2": lambda: __import__("synth").c3_unsteady_periodic(n=64, p=2, re_eff=10.0),
+    # square inclusion, 512^2 Q_2: interphase faces, mod-3 colouring, regular /
+    # extended-stencil split of the large colours, diagonal scaling
+    "c4a_n512_p2": lambda: __import__("synth").c4a_square_inclusion(n=512, p=2),
+}
+
+
+@pytest.mark.parametrize("name", list(FULL_CASES))
+def test_full_size_colour_pass_invariants_other_configurations(name):
+    """At the full sizes the benchmark measures for the other configurations:
+    after an FP64 colour pass the residual of every element the pass changed
+    vanishes to rounding (scale |b_E| + |(A x)_E|, as for the 256^2 case)."""
+    import torch
+    from paper_1911_05888_amd import Context
+    prob = FULL_CASES[name]()
+    print(f"[scale] full-size colour passes {name}", flush=True)
+    ctx = Context(prob)
+    nb = prob.nb
+    N = ctx.ndof
+    _, _, ncol = ctx.level_info(0)
+    g = torch.Generator(device="cuda").manual_seed(45)
+    x = torch.randn(N, dtype=torch.float64, device="cuda", generator=g)
+    b = torch.randn(N, dtype=torch.float64, device="cuda", generator=g)
+    for c in range(min(ncol, 3)):
+        x0 = x.clone()
+        ctx.level_smooth_colour(0, c, b, x)
+        ax = torch.zeros_like(x)
+        ctx.level_apply(0, x, ax)
+        changed = (x != x0).view(-1, nb).any(dim=1)
+        assert int(changed.sum()) > 0
+        res = (b - ax).view(-1, nb)[changed]
+        scale = torch.linalg.norm(b.view(-1, nb)[changed]) + torch.linalg.norm(ax.view(-1, nb)[changed])
+        rel = float(torch.linalg.norm(res) / scale)
+        print(f"[scale] {name} colour {c}: {int(changed.sum())} elements, |r_c| / scale = {rel:.2e}", flush=True)
+        assert rel <= 1e-7, (name, c, rel)
