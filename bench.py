@@ -144,7 +144,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU domain decomposition is a design, not part of this build)", file=sys.stderr)
+              "(the library runs on one GPU; a domain decomposition over several is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
