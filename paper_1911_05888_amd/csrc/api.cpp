@@ -834,7 +834,8 @@ const double* dscale0(ldgs_ctx* c) { return c->P.diag_scaling ? c->d_dscale0 : n
 
 // x <- V(b, x) on user (unscaled, FP64) vectors in precision vp.
 // If zero_x, x is taken as zero on entry (and overwritten).
-void vcycle_user(ldgs_ctx* c, int vp, const double* b, double* x, bool zero_x) {
+// add: x += V(b, 0) instead (with zero_x)
+void vcycle_user(ldgs_ctx* c, int vp, const double* b, double* x, bool zero_x, bool add = false) {
   const int64_t NE = c->levels[0].NE;
   const int nb = c->g.nb, nvel = c->g.d * c->g.nq;
   const double* ds = dscale0(c);
@@ -843,22 +844,20 @@ void vcycle_user(ldgs_ctx* c, int vp, const double* b, double* x, bool zero_x) {
     LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, b, c->w_b, 0, 0)));
     if (!zero_x) LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, x, c->w_x, 1, 0)));
     run_cycle<double>(c, c->s64, vp, c->w_b, c->w_x, zero_x);
-    LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, c->w_x, x, 0, 0)));
+    LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, c->w_x, x, 0, add ? 1 : 0)));
   } else {
     PrecStore<float>& S = (vp == LDGS_V_FP32) ? c->s32 : c->s16;
     if (!S.built) throw Fail{LDGS_E_UNSUPPORTED, "requested V-cycle precision not built"};
     LCHK((launch_scale_cast<double, float>(c->stream, NE, nb, nvel, ds, b, c->w_b32, 0, 0)));
     if (!zero_x) LCHK((launch_scale_cast<double, float>(c->stream, NE, nb, nvel, ds, x, c->w_x32, 1, 0)));
     run_cycle<float>(c, S, vp, c->w_b32, c->w_x32, zero_x);
-    LCHK((launch_scale_cast<float, double>(c->stream, NE, nb, nvel, ds, c->w_x32, x, 0, 0)));
+    LCHK((launch_scale_cast<float, double>(c->stream, NE, nb, nvel, ds, c->w_x32, x, 0, add ? 1 : 0)));
   }
 }
 
 // z += V(r, 0) in precision vp (r, z user vectors)
 void precond_add(ldgs_ctx* c, int vp, const double* r, double* z) {
-  const int64_t N = c->ndof();
-  vcycle_user(c, vp, r, c->w_z, true);
-  LCHK(launch_axpy(c->stream, N, 1.0, c->w_z, z));
+  vcycle_user(c, vp, r, z, true, true);   // the final unscaling cast adds into z
 }
 
 double host_sum_partials(ldgs_ctx* c, int nblk) {
