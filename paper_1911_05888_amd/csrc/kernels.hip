@@ -1146,22 +1146,9 @@ __global__ __launch_bounds__(SU_THREADS) void k_shared_update(int nelems, const 
     x[(size_t)zl[i / NB] * NB + i % NB] = T(0);
 }
 
-// product of 1D injection entries: (P_o)[af][ac] for child offset bits o
-template <typename T, int D, int M>
-__device__ __forceinline__ T pfull(const TabT<T>& tab, int o, int af, int ac) {
-  T v = 1;
-  int fa = af, ca = ac;
-#pragma unroll
-  for (int k = 0; k < D; ++k) {
-    v *= tab.P[(o >> k) & 1][(fa % M) * M + (ca % M)];
-    fa /= M;
-    ca /= M;
-  }
-  return v;
-}
-
-// the same entry from a copy of the two 1D tables P[0], P[1] (MAXM x MAXM
-// each) in LDS, for indices that differ between lanes
+// product of 1D injection entries, (P_o)[af][ac] for child offset bits o, from
+// a copy of the two 1D tables P[0], P[1] (MAXM x MAXM each) in LDS (indices
+// differ between lanes: kernel-argument arrays would become memory loads)
 template <typename T, int D, int M>
 __device__ __forceinline__ T pfull_lds(const T* Pt, int o, int af, int ac) {
   T v = 1;
