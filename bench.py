@@ -205,8 +205,8 @@ def main():
     # entries are streamed, the colour pass is the residual + shared update
     shared = ctx.level_shared_inverse(0)
     bytes_launch = smoother_bytes_per_launch(prob, ncol, 0 if shared else 4, 4)
-    kname = (f"k_colour_residual<float,{prob.dim},{prob.p},64,false> + k_shared_update<float,{prob.nb}>"
-             if shared else f"k_smooth_colour<float,float,{prob.dim},{prob.p},64>")
+    kname = (f"k_colour_residual<float,{prob.dim},{prob.p}> + k_shared_update_mfma<{prob.nb}> (FP32 matrix cores "
+             f"for colours of 8192 elements or more)" if shared else f"k_smooth_colour<float,float,{prob.dim},{prob.p},64>")
     avg_s = k_ms * 1e-3 / max(k_launches, 1)
     achieved = bytes_launch / avg_s / 1e9
     traffic = None

@@ -84,6 +84,7 @@ struct ldgs_ctx {
   int small_grid = 4096;       // see LaunchCfg; LDGS_SMALL_GRID overrides (tests)
   bool shared_inverse = true;  // one inverse per level with equal blocks; LDGS_SHARED_INVERSE=0 disables
   bool use_graph = true;       // V-cycles replayed from captured HIP graphs; LDGS_GRAPH=0 disables
+  bool use_mfma = true;        // one-inverse FP32 updates of large colours on the matrix cores; LDGS_MFMA=0 disables
   std::vector<int> kernel_offsets;
   PrecStore<double> s64;
   PrecStore<float> s32;      // float arithmetic, float inverses
@@ -677,7 +678,8 @@ void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* 
   if (pl.ainv_sh) {
     // one inverse for the level: residuals of the colour, then the shared update
     LCHK(launch_colour_residual<T>(cfg, pl.view, c->tab, pl.elems + o, pcol, cnt, b, x, pl.rbuf));
-    LCHK(launch_shared_update<T>(c->stream, cnt, c->g.nb, pl.ainv_sh, pl.rbuf, pl.elems + o, x, 0, nullptr, 0));
+    LCHK(launch_shared_update<T>(c->stream, cnt, c->g.nb, pl.ainv_sh, pl.rbuf, pl.elems + o, x, 0, nullptr, 0,
+                                 c->use_mfma));
   } else
   // (split only large launches: on coarse levels the second launch would cost
   // more than the extended stencil)
@@ -707,7 +709,8 @@ void first_colour(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x) {
   const int64_t cnt = pl.col_off[1], nzero = c->levels[l].NE - cnt;
   const int pcol = pl.parity ? 0 : -1;
   if (pl.ainv_sh)
-    LCHK(launch_shared_update<T>(c->stream, cnt, c->g.nb, pl.ainv_sh, b, pl.elems, x, 1, pl.elems + cnt, nzero));
+    LCHK(launch_shared_update<T>(c->stream, cnt, c->g.nb, pl.ainv_sh, b, pl.elems, x, 1, pl.elems + cnt, nzero,
+                                 c->use_mfma));
   else
     LCHK(launch_first_colour<T>(cfg, log2i(c->levels[l].n), pl.elems, pcol, cnt, pl.inv, pl.inv_kind, b, x,
                                 pl.elems + cnt, nzero));
@@ -1035,6 +1038,7 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
     }
     if (const char* si = std::getenv("LDGS_SHARED_INVERSE")) c->shared_inverse = std::strtol(si, nullptr, 10) != 0;
     if (const char* gr = std::getenv("LDGS_GRAPH")) c->use_graph = std::strtol(gr, nullptr, 10) != 0;
+    if (const char* mf = std::getenv("LDGS_MFMA")) c->use_mfma = std::strtol(mf, nullptr, 10) != 0;
     c->k0 = kernel_dim(P);
     if (c->k0 == 1) c->kernel_offsets = {P.dim * c->g.nq};
     else for (int i = 0; i <= P.dim; ++i) c->kernel_offsets.push_back(i * c->g.nq);

@@ -1095,6 +1095,7 @@ __global__ __launch_bounds__(SU_THREADS) void k_shared_update(int nelems, const 
   using V4 = std::conditional_t<sizeof(T) == 8, double2, float4>;
   __shared__ alignas(16) T As[C::A_SZ];
   __shared__ alignas(16) T Rs[C::TE * C::RS];
+  __shared__ int Eo[C::TE];   // x offset of each staged element (-1 past the end)
   const int tid = threadIdx.x;
   if constexpr (C::A_LDS)
     for (int i = tid; i < C::RS * NB; i += SU_THREADS) As[i] = ainv[i];
@@ -1106,11 +1107,24 @@ __global__ __launch_bounds__(SU_THREADS) void k_shared_update(int nelems, const 
     const int base = tile * C::TE;
     const int cnt = min(C::TE, nelems - base);
     __syncthreads();
-    for (int i = tid; i < C::TE * C::RS; i += SU_THREADS) {
+    if (tid < C::TE) Eo[tid] = tid < cnt ? elems[base + tid] * NB : -1;
+    __syncthreads();
+    // all loads of the tile issued before any is stored (unrolled; masked
+    // loads read r[0] and are discarded)
+    constexpr int TOT = C::TE * C::RS, ITER = (TOT + SU_THREADS - 1) / SU_THREADS;
+    T v[ITER];
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int i = tid + SU_THREADS * it;
       const int e = i / C::RS, k = i - e * C::RS;
-      T v = T(0);
-      if (e < cnt && k < NB) v = first ? r[(size_t)elems[base + e] * NB + k] : r[(size_t)(base + e) * NB + k];
-      Rs[i] = v;
+      const bool ok = i < TOT && e < cnt && k < NB;
+      v[it] = r[ok ? (first ? (size_t)Eo[e] + k : (size_t)(base + e) * NB + k) : 0];
+    }
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int i = tid + SU_THREADS * it;
+      const int e = i / C::RS, k = i - e * C::RS;
+      if (i < TOT) Rs[i] = (e < cnt && k < NB) ? v[it] : T(0);
     }
     __syncthreads();
     if (active) {
@@ -1136,7 +1150,7 @@ __global__ __launch_bounds__(SU_THREADS) void k_shared_update(int nelems, const 
       for (int q = 0; q < C::Q; ++q) {
         const int e = g * C::Q + q;
         if (e < cnt) {
-          T* xe = &x[(size_t)elems[base + e] * NB + row];
+          T* xe = &x[(size_t)Eo[e] + row];
           *xe = first ? acc[q] : *xe + acc[q];
         }
       }
@@ -1144,6 +1158,106 @@ __global__ __launch_bounds__(SU_THREADS) void k_shared_update(int nelems, const 
   }
   for (int64_t i = (int64_t)blockIdx.x * SU_THREADS + tid; i < (int64_t)nzero * NB; i += (int64_t)gridDim.x * SU_THREADS)
     x[(size_t)zl[i / NB] * NB + i % NB] = T(0);
+}
+
+// The same update on the matrix cores (FP32 MFMA 16x16x4) for large colours:
+// X_c += Ainv [NB x NB] R_c [NB x n] is a dense product.  Ainv is padded to
+// KP = roundup(NB, 16); each of the 4 wavefronts keeps the A operands of its
+// 16-row tiles for the whole launch in registers (lane l holds A[16 t + l % 16]
+// [4 s + l / 16] for k-step s).  A work-group stages 32 elements of R in LDS
+// (B[k][n] = R[n][k]; lane l reads B[l / 16][l % 16] of a 16-element block),
+// and lane l receives rows 4 (l / 16) .. + 3 of column l % 16 of each 16 x 16
+// output tile.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <int NB>
+struct MfmaSu {
+  static constexpr int KP = (NB + 15) / 16 * 16;
+  static constexpr int KS = KP / 4;                  // k-steps of 4
+  static constexpr int MTILES = KP / 16;             // 16-row tiles of the output
+  static constexpr int WAVES = 4;
+  static constexpr int MPW = (MTILES + WAVES - 1) / WAVES;   // row tiles per wavefront
+  static constexpr int NSUB = 2;                     // 16-element blocks per work-group tile
+  static constexpr int TN = 16 * NSUB;
+  static constexpr int LDR = KP + 1;                 // LDS stride of one staged element
+};
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_shared_update_mfma(int nelems, const float* __restrict__ ainv,
+                                                           const float* __restrict__ r,
+                                                           const int* __restrict__ elems, float* __restrict__ x,
+                                                           int first, const int* __restrict__ zl, int nzero) {
+  using C = MfmaSu<NB>;
+  __shared__ float Rs[C::TN * C::LDR];
+  __shared__ int Eo[C::TN];   // x offset of each staged element (-1 past the end)
+  const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
+  const int lr = l & 15, lg = l >> 4;
+  float a[C::MPW][C::KS];
+#pragma unroll
+  for (int mi = 0; mi < C::MPW; ++mi) {
+    const int m = 16 * (wv + C::WAVES * mi) + lr;
+#pragma unroll
+    for (int ks = 0; ks < C::KS; ++ks) {
+      const int k = 4 * ks + lg;
+      a[mi][ks] = (m < NB && k < NB) ? ainv[k * NB + m] : 0.f;
+    }
+  }
+  const int ntiles = (nelems + C::TN - 1) / C::TN;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int base = tile * C::TN;
+    const int cnt = min(C::TN, nelems - base);
+    __syncthreads();
+    if (tid < C::TN) Eo[tid] = tid < cnt ? elems[base + tid] * NB : -1;
+    __syncthreads();
+    // all loads of the tile issued before any is stored (unrolled; masked
+    // loads read r[0] and are discarded)
+    constexpr int TOT = C::TN * C::KP, ITER = (TOT + 255) / 256;
+    float v[ITER];
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int i = tid + 256 * it;
+      const int e = i / C::KP, k = i - e * C::KP;
+      const bool ok = i < TOT && e < cnt && k < NB;
+      const size_t src = ok ? (first ? (size_t)Eo[e] + k : (size_t)(base + e) * NB + k) : 0;
+      v[it] = r[src];
+    }
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int i = tid + 256 * it;
+      const int e = i / C::KP, k = i - e * C::KP;
+      if (i < TOT) Rs[e * C::LDR + k] = (e < cnt && k < NB) ? v[it] : 0.f;
+    }
+    int eoff[C::NSUB];
+#pragma unroll
+    for (int sb = 0; sb < C::NSUB; ++sb) eoff[sb] = Eo[16 * sb + lr];
+    __syncthreads();
+#pragma unroll
+    for (int sb = 0; sb < C::NSUB; ++sb) {
+      f32x4 acc[C::MPW];
+#pragma unroll
+      for (int mi = 0; mi < C::MPW; ++mi) acc[mi] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < C::KS; ++ks) {
+        const float bv = Rs[(16 * sb + lr) * C::LDR + 4 * ks + lg];
+#pragma unroll
+        for (int mi = 0; mi < C::MPW; ++mi)
+          acc[mi] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi][ks], bv, acc[mi], 0, 0, 0);
+      }
+      if (eoff[sb] >= 0) {
+#pragma unroll
+        for (int mi = 0; mi < C::MPW; ++mi)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int m = 16 * (wv + C::WAVES * mi) + 4 * lg + i;
+            if (m < NB) {
+              float* xm = x + (size_t)eoff[sb] + m;
+              *xm = first ? acc[mi][i] : *xm + acc[mi][i];
+            }
+          }
+      }
+    }
+  }
+  for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < (int64_t)nzero * NB; i += (int64_t)gridDim.x * 256)
+    x[(size_t)zl[i / NB] * NB + i % NB] = 0.f;
 }
 
 // product of 1D injection entries, (P_o)[af][ac] for child offset bits o, from
@@ -1461,23 +1575,33 @@ static void shared_update_q(hipStream_t st, int64_t nelems, const T* ainv, const
   hipLaunchKernelGGL((k_shared_update<T, NB, Q>), dim3((unsigned)g), dim3(SU_THREADS), 0, st, (int)nelems, ainv, r,
                      elems, x, first, zl, (int)nzero);
 }
-// 16 elements per thread on large colours; 4 on small ones (more work-groups,
-// shorter chains: small launches are latency bound)
+// large colours: the matrix cores in FP32 (blocks up to 128), else 16
+// elements per thread; small colours: 4 elements per thread (more
+// work-groups, shorter chains: small launches are latency bound)
 template <typename T, int NB>
 static void shared_update_nb(hipStream_t st, int64_t nelems, const T* ainv, const T* r, const int* elems, T* x,
-                             int first, const int* zl, int64_t nzero) {
+                             int first, const int* zl, int64_t nzero, bool mfma) {
+  if constexpr (sizeof(T) == 4 && NB <= 128) {
+    if (mfma && nelems >= 8192) {
+      int64_t g = (nelems + MfmaSu<NB>::TN - 1) / MfmaSu<NB>::TN;
+      if (g > 1024) g = 1024;
+      hipLaunchKernelGGL((k_shared_update_mfma<NB>), dim3((unsigned)g), dim3(256), 0, st, (int)nelems, ainv, r, elems,
+                         x, first, zl, (int)nzero);
+      return;
+    }
+  }
   if (nelems >= 8192) shared_update_q<T, NB, 16>(st, nelems, ainv, r, elems, x, first, zl, nzero);
   else shared_update_q<T, NB, 4>(st, nelems, ainv, r, elems, x, first, zl, nzero);
 }
 
 template <typename T>
 int launch_shared_update(void* stream, int64_t nelems, int nb, const T* ainv, const T* r, const int* elems, T* x,
-                         int first, const int* zl, int64_t nzero) {
+                         int first, const int* zl, int64_t nzero, bool mfma) {
   if (nelems <= 0) return 0;
   hipStream_t st = (hipStream_t)stream;
   switch (nb) {
 #define LDGS_SU(NBV) \
-  case NBV: shared_update_nb<T, NBV>(st, nelems, ainv, r, elems, x, first, zl, nzero); break;
+  case NBV: shared_update_nb<T, NBV>(st, nelems, ainv, r, elems, x, first, zl, nzero, mfma); break;
     LDGS_SU(12) LDGS_SU(27) LDGS_SU(48) LDGS_SU(32) LDGS_SU(108) LDGS_SU(256)
 #undef LDGS_SU
     default: return 2;
@@ -1640,9 +1764,9 @@ template int launch_colour_residual<double>(const LaunchCfg&, const DevLevel<dou
 template int launch_colour_residual<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const int*, int,
                                            int64_t, const float*, const float*, float*);
 template int launch_shared_update<double>(void*, int64_t, int, const double*, const double*, const int*, double*,
-                                          int, const int*, int64_t);
+                                          int, const int*, int64_t, bool);
 template int launch_shared_update<float>(void*, int64_t, int, const float*, const float*, const int*, float*, int,
-                                         const int*, int64_t);
+                                         const int*, int64_t, bool);
 template int launch_first_colour<double>(const LaunchCfg&, int, const int*, int, int64_t, const void*, int,
                                          const double*, double*, const int*, int64_t);
 template int launch_first_colour<float>(const LaunchCfg&, int, const int*, int, int64_t, const void*, int,

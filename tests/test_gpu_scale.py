@@ -246,3 +246,58 @@ def test_full_size_colour_pass_invariants_other_configurations(name):
         rel = float(torch.linalg.norm(res) / scale)
         print(f"[scale] {name} colour {c}: {int(changed.sum())} elements, |r_c| / scale = {rel:.2e}", flush=True)
         assert rel <= 1e-7, (name, c, rel)
+
+
+MFMA_CASES = {
+    # colours of 32768 elements, 108 x 108 inverse (the 3D unsteady workload)
+    "c3_n64_p2": lambda: __import__("synth").c3_unsteady_periodic(n=64, p=2, re_eff=10.0),
+    # colours of 16384 elements, 48 x 48 inverse
+    "per2d_n256_p3": lambda: Problem(name="per2d", dim=2, n=256, p=3, gamma=1, bc=("periodic", "periodic")),
+}
+
+
+@pytest.mark.parametrize("name", list(MFMA_CASES))
+def test_shared_inverse_update_on_matrix_cores(name, monkeypatch):
+    """FP32 colour passes on a one-inverse level with colours of at least 8192
+    elements: the update on the matrix cores (FP32 MFMA) against the same
+    update on the vector ALUs (LDGS_MFMA=0), the first pass from a zero guess
+    (inside V-cycles) included, and both against FP64."""
+    import torch
+    from paper_1911_05888_amd import Context, V_FP32
+    prob = MFMA_CASES[name]()
+    print(f"[scale] matrix-core shared update {name}", flush=True)
+    ctxs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("LDGS_MFMA", flag)
+        ctxs.append(Context(prob, build_precisions=(1 << V_FP32)))
+    mf, va = ctxs
+    assert mf.level_shared_inverse(0)
+    N = mf.ndof
+    _, _, ncol = mf.level_info(0)
+    g = torch.Generator(device="cuda").manual_seed(46)
+    x0 = torch.randn(N, dtype=torch.float64, device="cuda", generator=g)
+    b = torch.randn(N, dtype=torch.float64, device="cuda", generator=g)
+    xm = x0.float()
+    xv = x0.float()
+    x64 = x0.clone()
+    b32 = b.float()
+    for c in range(ncol):
+        mf.level_smooth_colour_f32(0, c, V_FP32, b32, xm)
+        va.level_smooth_colour_f32(0, c, V_FP32, b32, xv)
+        mf.level_smooth_colour(0, c, b, x64)
+        e = float(torch.linalg.norm((xm - xv).double()) / torch.linalg.norm(xv.double()))
+        e64 = float(torch.linalg.norm(xm.double() - x64) / torch.linalg.norm(x64))
+        print(f"[scale] {name} colour {c}: MFMA vs VALU {e:.2e}, vs FP64 {e64:.2e}", flush=True)
+        assert e <= 1e-5 and e64 <= 1e-4, (c, e, e64)
+    # whole V-cycles (first pass from a zero guess through the matrix cores)
+    bp = b.clone()
+    mf.project_kernel(bp)
+    ys = []
+    for ctx in (mf, va):
+        ctx.set_vprec(V_FP32)
+        y = torch.zeros_like(bp)
+        ctx.vcycle(bp, y)
+        ys.append(y)
+    e = float(torch.linalg.norm(ys[0] - ys[1]) / torch.linalg.norm(ys[1]))
+    print(f"[scale] {name} V-cycle: MFMA vs VALU {e:.2e}", flush=True)
+    assert e <= 1e-5
