@@ -1506,10 +1506,20 @@ static int dispatch_if(int iface, int dim, F&& f) {
 // on large grids: LDS then limits the work-groups per CU, and one wavefront
 // each would leave the SIMDs idle (3D, FP64).
 constexpr size_t LDS_WIDE = 12288;
-template <class F>
+// 3D elements have 2-3x the work items per phase of 2D ones: four wavefronts
+// per element on small (latency-bound) grids and in FP64 (measured: the FP64
+// 64^3 residual 2.57 -> 2.03 ms); two for large FP32 launches (four were slower
+// there: the colour residual 164 -> 174 us)
+constexpr int NT_WIDE3 = 256;
+template <int D = 2, int TBYTES = 4, class F>
 static void dispatch_nt(int64_t nelems, int small_grid, size_t lds_bytes, F&& f) {
   if (nelems >= small_grid && lds_bytes <= LDS_WIDE) f(std::integral_constant<int, WG>{});
-  else f(std::integral_constant<int, NT_SMALL>{});
+  else if constexpr (D == 3) {
+    if (TBYTES == 8 || nelems < small_grid) f(std::integral_constant<int, NT_WIDE3>{});
+    else f(std::integral_constant<int, NT_SMALL>{});
+  } else {
+    f(std::integral_constant<int, NT_SMALL>{});
+  }
 }
 
 template <typename T>
@@ -1522,14 +1532,14 @@ int launch_smooth_colour(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D
   const TabT<T> tt = tab_of<T>(tab);
   if constexpr (sizeof(T) == 8) {
     if (inv_kind != 0) return 2;
-    if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, double, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
+    if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt<D_, (int)sizeof(T)>(nelems, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, double, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                   lev, tt, elems, pcol, (const double*)inv, b, x); }); })) bad = true; })) return 2;
   } else {
     if (inv_kind == 1) {
-      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, float, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
+      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt<D_, (int)sizeof(T)>(nelems, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, float, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                     lev, tt, elems, pcol, (const float*)inv, b, x); }); })) bad = true; })) return 2;
     } else if (inv_kind == 2) {
-      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, uint16_t, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
+      if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt<D_, (int)sizeof(T)>(nelems, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, uint16_t, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                     lev, tt, elems, pcol, (const uint16_t*)inv, b, x); }); })) bad = true; })) return 2;
     } else {
       return 2;
@@ -1547,7 +1557,7 @@ int launch_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab
   bool bad = false;   // no kernel for this level (interphase faces in 3D)
   hipStream_t st = (hipStream_t)c.stream;
   const TabT<T> tt = tab_of<T>(tab);
-  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(NE, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual<T, D_, P_, NT_, IF_>), dim3((unsigned)NE), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt<D_, (int)sizeof(T)>(NE, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual<T, D_, P_, NT_, IF_>), dim3((unsigned)NE), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                 lev, tt, b, x, out, mode); }); })) bad = true; })) return 2;
   if (bad) return 2;
   return hip_ok();
@@ -1560,7 +1570,7 @@ int launch_colour_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab
   bool bad = false;
   hipStream_t st = (hipStream_t)c.stream;
   const TabT<T> tt = tab_of<T>(tab);
-  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(nelems, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_colour_residual<T, D_, P_, NT_, IF_>), dim3((unsigned)nelems), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt<D_, (int)sizeof(T)>(nelems, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_colour_residual<T, D_, P_, NT_, IF_>), dim3((unsigned)nelems), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                 lev, tt, elems, pcol, b, x, r); }); })) bad = true; })) return 2;
   if (bad) return 2;
   return hip_ok();
@@ -1666,7 +1676,7 @@ int launch_residual_restrict(const LaunchCfg& c, const DevLevel<T>& lev, const T
       return 2;
     return hip_ok();
   }
-  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt(NC, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual_restrict<T, D_, P_, NT_, IF_>), dim3((unsigned)NC), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt<2>(NC, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_residual_restrict<T, D_, P_, NT_, IF_>), dim3((unsigned)NC), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
                                                 lev, tt, b, x, rc); }); })) bad = true; })) return 2;
   if (bad) return 2;
   return hip_ok();
