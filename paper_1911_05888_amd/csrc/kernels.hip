@@ -154,6 +154,22 @@ __device__ __forceinline__ bool is_inter(unsigned char t) {
   else return false;
 }
 
+// pair (i, k) of stress row pr: all D^2 pairs (i major), or with sym the
+// D (D + 1) / 2 pairs i <= k in the order (0,0), (0,1), ..., (1,1), ...
+template <int D>
+__device__ __forceinline__ void stress_pair(int pr, bool sym, int& i, int& k) {
+  if (!sym) {
+    i = pr / D;
+    k = pr % D;
+  } else if constexpr (D == 2) {
+    i = pr == 2 ? 1 : 0;
+    k = pr == 0 ? 0 : 1;
+  } else {
+    i = pr < 3 ? 0 : (pr < 5 ? 1 : 2);
+    k = pr < 3 ? pr : (pr < 5 ? pr - 2 : 2);
+  }
+}
+
 // stencil slots (see Sz)
 template <int D>
 __device__ __forceinline__ int pair_of(int a, int b) {   // a != b
@@ -553,6 +569,16 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
           jhi = wL * (trhi - trHlo);
         }
       }
+      // the velocity traces along k that the fluxes need come out of these
+      // lines: x_E at both faces, x_{E-e_k} at its high face, x_{E+e_k} at
+      // its low face
+      if (fi == 0) {
+        w.trx[0][k][i][t] = trlo;
+        w.trx[1][k][i][t] = trhi;
+        w.trn[0][k][i][t] = trLhi;
+      } else if (fi == 1 + k) {
+        w.trn[1][k][i][t] = trlo;
+      }
       T* go = &w.g[fi][i * D + k][base];
 #pragma unroll
       for (int ak = 0; ak < M; ++ak) {
@@ -566,9 +592,11 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
   __syncthreads();
   // ---- phase 3: s_E = M_mu (g + gamma g^T) and the low-face traces of s at E+e_k ----
   {
-    constexpr int NPAIR = D * D;
-    constexpr int NS0 = NPAIR * NQ;
     constexpr int NTRR = D * D * MT;
+    // rows of s_E: with gamma = 1 s_E is symmetric and only the pairs i <= k
+    // are formed (the other half is copied)
+    const bool sym = lev.gamma != 0;
+    const int NS0 = (sym ? D * (D + 1) / 2 : D * D) * NQ;
     for (int u = lane; u < NS0 + (IF ? 2 : 1) * NTRR; u += NT) {
       if (IF && u >= NS0 + NTRR) {
         // high-face traces of s at E - e_k (interphase liftings onto E)
@@ -599,8 +627,9 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
         const int a = u % NQ, pr = u / NQ;
         const int r = u - NS0;
         const int t = r % MT, ir = (r / MT) % D, kr = r / (MT * D);
-        const int i = isS ? pr / D : ir, k = isS ? pr % D : kr;
-        if (isS && lev.gamma && i > k) continue;       // symmetric: filled from (k, i)
+        int si, sk;
+        stress_pair<D>(pr, sym, si, sk);
+        const int i = isS ? si : ir, k = isS ? sk : kr;
         const int fi = isS ? 0 : 1 + k;
         const bool valid = isS || ((vmask >> (1 + D + k)) & 1);
         const T* g1 = w.g[fi][i * D + k];
@@ -612,10 +641,11 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
         v = valid ? v : (T)0;
         T* o = isS ? &w.s0[i * D + k][a] : &w.trr[k][i][t];
         *o = v;
-        if (isS && lev.gamma && i != k) w.s0[k * D + i][a] = v;
+        if (isS && sym && i != k) w.s0[k * D + i][a] = v;
       } else if (u < NS0) {
-        const int a = u % NQ, pr = u / NQ, i = pr / D, k = pr % D;
-        if (lev.gamma && i > k) continue;       // symmetric: filled from (k, i)
+        const int a = u % NQ, pr = u / NQ;
+        int i, k;
+        stress_pair<D>(pr, sym, i, k);
         const T* g1 = w.g[0][i * D + k];
         const T* g2 = w.g[0][k * D + i];
         T v = 0;
@@ -629,7 +659,7 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
           v = lev.mu_const * (g1[a] + gam * g2[a]);
         }
         w.s0[i * D + k][a] = v;
-        if (lev.gamma && i != k) w.s0[k * D + i][a] = v;
+        if (sym && i != k) w.s0[k * D + i][a] = v;
       } else {
         const int r = u - NS0;
         const int t = r % MT, i = (r / MT) % D, k = r / (MT * D);
@@ -653,27 +683,25 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
     }
   }
   __syncthreads();
-  // ---- phase 4: traces along each axis ----
+  // ---- phase 4: the remaining traces along each axis: p_E at both faces,
+  // p_{E-e_k} at its high face and p_{E+e_k} at its low face, s_E[i][k] at
+  // both faces (one code path with selected source, face and destination) ----
   {
-    constexpr int NX = 2 * (D + 1) * MT;   // x_E lo/hi
-    constexpr int NN = 2 * (D + 1) * MT;   // x_{E-e_k}|hi, x_{E+e_k}|lo
+    constexpr int NX = 2 * MT;             // p_E lo/hi
+    constexpr int NN = 2 * MT;             // p_{E-e_k}|hi, p_{E+e_k}|lo
     constexpr int NTR = 2 * D * MT;        // s_E[i][k] lo/hi
     constexpr int PER_K = NX + NN + NTR;
-    // one code path for the three kinds of trace (selected source, face and
-    // destination): x_E at its faces, the neighbours' x at the shared faces,
-    // s_E at its faces
     for (int u = lane; u < D * PER_K; u += NT) {
       const int k = u / PER_K, r = u % PER_K;
       const int base_mt = r % MT;
       const int base = compose<M>(base_mt, 0, k), st = stride_of<M>(k);
       const bool isx = r < NX, isn = !isx && r < NX + NN;
       const int r2 = isx ? r : (isn ? r - NX : r - NX - NN);
-      const int fx = (r2 / MT) % (D + 1), sx = r2 / (MT * (D + 1));
-      const int fs = (r2 / MT) % D, ss = r2 / (MT * D);
-      const int f = isx || isn ? fx : fs, side = isx || isn ? sx : ss;
-      const T* src = isx ? &w.xs[0][f * NQ + base]
-                         : (isn ? &w.xs[side ? 1 + D + k : 1 + k][f * NQ + base] : &w.s0[f * D + k][base]);
-      T* dst = isx ? &w.trx[side][k][f][base_mt] : (isn ? &w.trn[side][k][f][base_mt] : &w.trs[side][k][f][base_mt]);
+      const int fs = (r2 / MT) % D;
+      const int side = isx || isn ? r2 / MT : r2 / (MT * D);
+      const T* src = isx ? &w.xs[0][D * NQ + base]
+                         : (isn ? &w.xs[side ? 1 + D + k : 1 + k][D * NQ + base] : &w.s0[fs * D + k][base]);
+      T* dst = isx ? &w.trx[side][k][D][base_mt] : (isn ? &w.trn[side][k][D][base_mt] : &w.trs[side][k][fs][base_mt]);
       const bool hi = isn ? side == 0 : side != 0;   // trace at the element's high face (e1) or low face (e0)
       T v = 0;
 #pragma unroll
