@@ -541,7 +541,10 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
       else if (q < 4 * D - 1) { fi = 1 + D + k; i = q - (3 * D - 1); }
       else { const int j0 = q - (4 * D - 1); const int j = j0 < k ? j0 : j0 + 1; fi = 1 + D + j; i = j; }
       const int sF = f_slot<D>(fi);
-      if (!((vmask >> sF) & 1)) continue;
+      if (!((vmask >> sF) & 1)) {
+        if (fi == 1 + k) w.trn[1][k][i][t] = 0;   // no E + e_k: its traces read as zero
+        continue;
+      }
       const unsigned char tlo = w.ft[fi][k][0], thi = w.ft[fi][k][1];
       const T wR = w.fwr[fi][k][0], wL = w.fwl[fi][k][1];
       const int base = compose<M>(t, 0, k), st = stride_of<M>(k);
@@ -710,109 +713,73 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
     }
   }
   __syncthreads();
-  // ---- phase 5: face fluxes ----
+  // ---- phase 5: face fluxes, one code path for every kind of face and field
+  // (the terms present are selected through their coefficients) ----
   for (int u = lane; u < D * 2 * (D + 1) * MT; u += NT) {
     const int tt = u % MT, f = (u / MT) % (D + 1), side = (u / (MT * (D + 1))) % 2, k = u / (2 * MT * (D + 1));
     const unsigned char ty = w.ft[0][k][side];
     const T wL = w.fwl[0][k][side], wR = w.fwr[0][k][side];
     const T* Th = &w.th[side][k][tt * MT];
+    const bool vel = f < D, two = two_sided<IF>(ty), inter = is_inter<IF>(ty);
+    const bool dir = ty == (side ? F_DIR_HI : F_DIR_LO), has = ty != F_NONE, intra = ty == F_INTRA;
+    const int i = vel ? f : 0;
+    const bool kk = vel && k == i;
+    // penalty: Th applied to the face values of x_E (ca) and of the
+    // neighbour (cb): u at Dirichlet and interphase faces, p at intraphase faces
+    const T ca = vel ? ((dir || inter) ? (T)1 : (T)0) : (intra ? (T)-1 : (T)0);
+    const T cb = vel ? (inter ? (T)-1 : (T)0) : (intra ? (T)1 : (T)0);
+    const T* xa = w.trx[side][k][f];
+    const T* xb = w.trn[side][k][f];
     T v = 0;
-    if (f < D) {
-      const int i = f;
-      if (side == 0) {
-        // E is the high element R of its low face
-        if (ty != F_NONE) v += wR * w.trs[0][k][i][tt];
-        if (ty == F_DIR_LO) {
-          T acc = 0;
 #pragma unroll
-          for (int q = 0; q < MT; ++q) acc += Th[q] * w.trx[0][k][i][q];
-          v += acc;
-        } else if (is_inter<IF>(ty)) {
-          T acc = 0;
-#pragma unroll
-          for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trn[0][k][i][q] - w.trx[0][k][i][q]);
-          v -= acc;
-        }
-        if (k == i && ty != F_NONE) v -= wR * w.trx[0][k][D][tt];
-        if constexpr (IF) {
-          // interphase face lifting onto its low element E - e_k: adjoint terms
-          if (ty == F_INTRA || ty == F_INTER) {
-            v += wL * w.trrh[IF ? k : 0][i][tt];
-            if (k == i) v -= wL * w.trn[0][k][D][tt];
-          }
-        }
-      } else {
-        // E is the low element L of its high face
-        const T sR = two_sided<IF>(ty) ? w.trr[k][i][tt] : (T)0;
-        v -= wR * sR + wL * w.trs[1][k][i][tt];
-        if (ty == F_DIR_HI) {
-          T acc = 0;
-#pragma unroll
-          for (int q = 0; q < MT; ++q) acc += Th[q] * w.trx[1][k][i][q];
-          v += acc;
-        } else if (is_inter<IF>(ty)) {
-          T acc = 0;
-#pragma unroll
-          for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trx[1][k][i][q] - w.trn[1][k][i][q]);
-          v += acc;
-        }
-        if (k == i) {
-          const T pR = two_sided<IF>(ty) ? w.trn[1][k][D][tt] : (T)0;
-          v += wR * pR + wL * w.trx[1][k][D][tt];
-        }
-      }
-    } else if (ty == F_INTRA) {
-      T acc = 0;
-      if (side == 0) {
-#pragma unroll
-        for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trn[0][k][D][q] - w.trx[0][k][D][q]);
-        v = acc;
-      } else {
-#pragma unroll
-        for (int q = 0; q < MT; ++q) acc += Th[q] * (w.trx[1][k][D][q] - w.trn[1][k][D][q]);
-        v = -acc;
-      }
+    for (int q = 0; q < MT; ++q) v += Th[q] * (ca * xa[q] + cb * xb[q]);
+    // averages of s and p.  Low face (E is its high element R): wR s_E, the
+    // interphase lifting onto E - e_k (wL, trrh), wR p_E, wL p_{E-e_k}; high
+    // face (E is its low element L): wL s_E, wR s_{E+e_k}, wL p_E, wR p_{E+e_k}
+    T cs, cr, cpx, cpn, sr;
+    if (side == 0) {
+      cs = (vel && has) ? wR : (T)0;
+      cr = (IF && vel && two) ? wL : (T)0;
+      cpx = (kk && has) ? -wR : (T)0;
+      cpn = (IF && kk && two) ? -wL : (T)0;
+      sr = IF ? w.trrh[IF ? k : 0][i][tt] : (T)0;
+    } else {
+      cs = vel ? -wL : (T)0;
+      cr = (vel && two) ? -wR : (T)0;
+      cpx = kk ? wL : (T)0;
+      cpn = (kk && two) ? wR : (T)0;
+      sr = w.trr[k][i][tt];
     }
+    v += cs * w.trs[side][k][i][tt] + cr * sr + cpx * w.trx[side][k][D][tt] + cpn * w.trn[side][k][D][tt];
     w.flux[side][k][f][tt] = hinv * v;
   }
   __syncthreads();
-  // ---- phase 6: assemble (A x)_E and the residual ----
+  // ---- phase 6: assemble (A x)_E and the residual, one code path for the
+  // rows of u (div s, grad p, rho/delta u) and of p (div u) ----
 #pragma unroll
   for (int q = 0; q < XQ; ++q) {
     const int t = lane + q * NT;
     if (t >= NB) break;
     const int f = t / NQ, a = t % NQ;
-    T acc = 0;
-    if (f < D) {
-      const int i = f;
+    const bool vel = f < D;
+    const int i = vel ? f : 0;
+    T acc = vel ? lev.rho_delta * w.xs[0][t] : (T)0;
 #pragma unroll
-      for (int k = 0; k < D; ++k) {
-        const int ak = k == 0 ? digit_c<M, 0>(a) : (k == 1 ? digit_c<M, 1>(a) : digit_c<M, 2>(a));
-        const int tt = k == 0 ? tang_c<M, 0>(a) : (k == 1 ? tang_c<M, 1>(a) : tang_c<M, 2>(a));
-        const int base = compose<M>(tt, 0, k), st = stride_of<M>(k);
-        const T* sv = &w.s0[i * D + k][base];
-        T vol = 0;
+    for (int k = 0; k < D; ++k) {
+      const int ak = k == 0 ? digit_c<M, 0>(a) : (k == 1 ? digit_c<M, 1>(a) : digit_c<M, 2>(a));
+      const int tt = k == 0 ? tang_c<M, 0>(a) : (k == 1 ? tang_c<M, 1>(a) : tang_c<M, 2>(a));
+      const int base = compose<M>(tt, 0, k), st = stride_of<M>(k);
+      const T* sv = &w.s0[i * D + k][base];
+      const T* pv = &w.xs[0][D * NQ + base];
+      T vol = 0, pvol = 0;
 #pragma unroll
-        for (int bb = 0; bb < M; ++bb) vol += w.tabs[bb * M + ak] * sv[bb * st];
-        acc += hinv * vol + w.tabs[MAXM * MAXM + ak] * w.flux[0][k][i][tt] + w.tabs[MAXM * MAXM + MAXM + ak] * w.flux[1][k][i][tt];
-        if (k == i) {
-          const T* pv = &w.xs[0][D * NQ + base];
-          T pvol = 0;
-#pragma unroll
-          for (int bb = 0; bb < M; ++bb) pvol += w.tabs[bb * M + ak] * pv[bb * st];
-          acc -= hinv * pvol;
-        }
+      for (int bb = 0; bb < M; ++bb) {
+        vol += w.tabs[bb * M + ak] * sv[bb * st];
+        pvol += w.tabs[bb * M + ak] * pv[bb * st];
       }
-      acc += lev.rho_delta * w.xs[0][t];
-    } else {
-#pragma unroll
-      for (int i = 0; i < D; ++i) acc -= w.g[0][i * D + i][a];
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        const int ak = k == 0 ? digit_c<M, 0>(a) : (k == 1 ? digit_c<M, 1>(a) : digit_c<M, 2>(a));
-        const int tt = k == 0 ? tang_c<M, 0>(a) : (k == 1 ? tang_c<M, 1>(a) : tang_c<M, 2>(a));
-        acc += w.tabs[MAXM * MAXM + ak] * w.flux[0][k][D][tt] + w.tabs[MAXM * MAXM + MAXM + ak] * w.flux[1][k][D][tt];
-      }
+      const T cv = vel ? hinv : (T)0, cp = (vel && k == i) ? -hinv : (T)0, cg = vel ? (T)0 : (T)-1;
+      acc += cv * vol + cp * pvol + cg * w.g[0][k * D + k][a] + w.tabs[MAXM * MAXM + ak] * w.flux[0][k][f][tt] +
+             w.tabs[MAXM * MAXM + MAXM + ak] * w.flux[1][k][f][tt];
     }
     if (lev.dscale) acc *= (f == D ? ds0p : ds0v);
     w.res[t] = (mode == 0) ? bc[q] - acc : acc;
