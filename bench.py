@@ -14,8 +14,10 @@ solve time).  The plain FP64 stationary V-cycle to the same tolerance, and
 the BF16-block variant, are measured beside it.
 
 The roofline object covers the dominant kernel (the finest-level smoother
-colour pass), timed with HIP event pairs on the library's stream around every
-8th such pass during the timed solves; the algorithmic bytes per launch are (elements in the colour) x
+colour pass), timed with HIP event pairs on the library's stream, one pair
+around the back-to-back colour passes of every 4th finest sweep of the timed
+solves (the average per pass includes the short gaps between those
+launches); the algorithmic bytes per launch are (elements in the colour) x
 (n_b^2 inverse entries + 3 n_b vector entries + (p+2)^d viscosity values) x
 the storage width, the method's byte model (the kernel moves only the upper
 tiles of the symmetric inverse: an effective bandwidth; `traffic` gives the
@@ -186,7 +188,7 @@ def main():
     for _ in range(args.warmup):
         solve(V_FP32, IR)
     torch.cuda.synchronize()
-    ctx.profile(8)        # every 8th finest colour pass carries an event pair
+    ctx.profile(4)        # every 4th finest sweep: one event pair around its colour passes
     iters = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -261,7 +263,7 @@ def main():
                       frac=achieved / HBM_PEAK_GBS, traffic=traffic,
                       kernel=kname + " (finest level)",
                       avg_launch_us=avg_s * 1e6, algorithmic_bytes_per_launch=bytes_launch,
-                      launches=k_launches),
+                      launches=k_launches, timing="event pairs around whole finest sweeps, every 4th"),
     )
     if not args.no_cpu_baseline and args.workload == "c2":
         line["cpu_baseline"] = cpu_baseline()

@@ -332,13 +332,15 @@ ldgs_status ldgs_host_level_apply(ldgs_ctx* ctx, int level, const double* x_host
  * particular order); either pointer may be NULL.  *nc receives N_c. */
 ldgs_status ldgs_bottom_info(ldgs_ctx* ctx, int64_t* nc, double* pinv_host, double* eig_host);
 
-/* Timing of the finest-level smoother launches.  ldgs_profile(ctx, k) with
- * k > 0 records a HIP event pair on the library's stream around every k-th
- * colour pass of level 0 (the passes that evaluate the operator; the first
- * pass from a zero guess is not timed); k = 0 turns it off.  Each pair adds a
- * little host and queue work, so a stride above 1 keeps the timed solve close
- * to an untimed one.  ldgs_profile_read synchronises, returns the summed time
- * (ms) and the number of timed passes since the last read, and clears them. */
+/* Timing of the finest-level colour passes.  ldgs_profile(ctx, k) with k > 0
+ * records a HIP event pair on the library's stream around every k-th sweep of
+ * level 0, i.e. around all colour passes of that sweep, launched back to back
+ * (sweeps whose passes all evaluate the operator: the sweep that starts from a
+ * zero guess is not timed); k = 0 turns it off.  Each pair adds a little host
+ * and queue work, so a stride above 1 keeps the timed solve close to an
+ * untimed one.  ldgs_profile_read synchronises, returns the summed time (ms)
+ * and the number of colour passes it covers since the last read, and clears
+ * them. */
 ldgs_status ldgs_profile(ldgs_ctx* ctx, int enable);
 ldgs_status ldgs_profile_read(ldgs_ctx* ctx, double* total_ms, int64_t* launches);
 

@@ -114,10 +114,15 @@ struct ldgs_ctx {
   double *w_cb = nullptr, *w_cx = nullptr, *w_ce = nullptr;
   int* d_orig = nullptr;
   int64_t d_orig_cap = 0;
-  // optional timing of the finest-level smoother launches (HIP events on the stream)
-  int prof = 0;                  // time every prof-th finest colour pass (0: off)
+  // optional timing of the finest-level colour passes (HIP events on the
+  // stream): one event pair around all colour passes of a sweep
+  struct ProfEv {
+    hipEvent_t e0, e1;
+    int passes;                  // colour passes between the two events
+  };
+  int prof = 0;                  // time every prof-th finest sweep (0: off)
   int64_t prof_count = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+  std::vector<ProfEv> prof_ev;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<void*> allocs;
@@ -129,13 +134,13 @@ struct ldgs_ctx {
     bool zero_x;
     int prof;
     hipGraphExec_t exec;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<ProfEv> ev;
   };
   std::vector<CycleGraph> graphs;
   bool capturing = false;
   std::vector<hipEvent_t> cap_pool;                         // events owned by graphs
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> cap_ev;    // pairs recorded during a capture
-  const std::vector<std::pair<hipEvent_t, hipEvent_t>>* prof_pending = nullptr;
+  std::vector<ProfEv> cap_ev;                                // pairs recorded during a capture
+  const std::vector<ProfEv>* prof_pending = nullptr;
   double prof_acc_ms = 0.0;
   int64_t prof_acc_n = 0;
   ~ldgs_ctx() {
@@ -666,13 +671,6 @@ void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* 
   const size_t esz = pl.inv_kind == 0 ? 8 : (pl.inv_kind == 1 ? 4 : 2);
   int64_t o = pl.col_off[col], cnt = pl.col_off[col + 1] - o;
   const void* inv = (const char*)pl.inv + o * pl.inv_stride * esz;
-  const bool timed = c->prof > 0 && l == 0 && (c->prof_count++ % c->prof) == 0;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (timed) {
-    e0 = next_event(c);
-    e1 = next_event(c);
-    HIPCHK(hipEventRecord(e0, c->stream));
-  }
   const int64_t nreg = pl.col_reg.empty() ? cnt : pl.col_reg[col];
   const int pcol = pl.parity ? col : -1;
   if (pl.ainv_sh) {
@@ -693,10 +691,6 @@ void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* 
     if (nreg > 0) LCHK(launch_smooth_colour<T>(cfg, regular, c->tab, pl.elems + o, -1, nreg, inv, pl.inv_kind, b, x));
     const void* inv_i = (const char*)inv + nreg * pl.inv_stride * esz;
     LCHK(launch_smooth_colour<T>(cfg, pl.view, c->tab, pl.elems + o + nreg, -1, cnt - nreg, inv_i, pl.inv_kind, b, x));
-  }
-  if (timed) {
-    HIPCHK(hipEventRecord(e1, c->stream));
-    (c->capturing ? c->cap_ev : c->prof_ev).emplace_back(e0, e1);
   }
 }
 
@@ -721,11 +715,27 @@ void first_colour(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x) {
 template <typename T>
 void smooth(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x, int sweeps, bool zero_x = false) {
   if (zero_x && sweeps == 0) LCHK(launch_fill<T>(c->stream, c->levels[l].NE * c->g.nb, (T)0, x));
-  for (int s = 0; s < sweeps; ++s)
-    for (int col = 0; col < c->levels[l].ncol; ++col) {
-      if (zero_x && s == 0 && col == 0) first_colour(c, S, l, b, x);
+  const int ncol = c->levels[l].ncol;
+  for (int s = 0; s < sweeps; ++s) {
+    const bool first = zero_x && s == 0;
+    // finest level, profiling on: every prof-th sweep whose passes all
+    // evaluate the operator (not the one that starts from the zero guess)
+    const bool timed = c->prof > 0 && l == 0 && !first && (c->prof_count++ % c->prof) == 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+      e0 = next_event(c);
+      e1 = next_event(c);
+      HIPCHK(hipEventRecord(e0, c->stream));
+    }
+    for (int col = 0; col < ncol; ++col) {
+      if (first && col == 0) first_colour(c, S, l, b, x);
       else smooth_colour(c, S, l, col, b, x);
     }
+    if (timed) {
+      HIPCHK(hipEventRecord(e1, c->stream));
+      (c->capturing ? c->cap_ev : c->prof_ev).push_back({e0, e1, ncol});
+    }
+  }
 }
 
 // Least-squares bottom solve x = A_c^+ b (footnote to the bottom solver):
@@ -771,12 +781,12 @@ void collect_graph_prof(ldgs_ctx* c) {
   const auto& ev = *c->prof_pending;
   c->prof_pending = nullptr;
   if (ev.empty()) return;
-  HIPCHK(hipEventSynchronize(ev.back().second));
+  HIPCHK(hipEventSynchronize(ev.back().e1));
   for (const auto& pr : ev) {
     float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+    HIPCHK(hipEventElapsedTime(&ms, pr.e0, pr.e1));
     c->prof_acc_ms += ms;
-    ++c->prof_acc_n;
+    c->prof_acc_n += pr.passes;
   }
 }
 
@@ -1568,13 +1578,15 @@ ldgs_status ldgs_profile_read(ldgs_ctx* ctx, double* total_ms, int64_t* launches
     HIPCHK(hipStreamSynchronize(ctx->stream));
     collect_graph_prof(ctx);
     double tot = ctx->prof_acc_ms;
+    int64_t n = ctx->prof_acc_n;
     for (auto& pr : ctx->prof_ev) {
       float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+      HIPCHK(hipEventElapsedTime(&ms, pr.e0, pr.e1));
       tot += ms;
+      n += pr.passes;
     }
     if (total_ms) *total_ms = tot;
-    if (launches) *launches = (int64_t)ctx->prof_ev.size() + ctx->prof_acc_n;
+    if (launches) *launches = n;
     ctx->prof_ev.clear();
     ctx->ev_used = 0;
     ctx->prof_acc_ms = 0.0;

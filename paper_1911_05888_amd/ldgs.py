@@ -362,8 +362,8 @@ class Context:
         self._check(_lib.ldgs_level_smooth_colour_f32(self._h, level, colour, vprec, _dptr(b), _dptr(x)))
 
     def profile(self, stride=1):
-        """Time every `stride`-th finest colour pass (True: every one; 0 or
-        False: off)."""
+        """Time every `stride`-th finest sweep, one event pair around all its
+        colour passes (True: every sweep; 0 or False: off)."""
         self._check(_lib.ldgs_profile(self._h, int(stride)))
 
     def profile_read(self):

@@ -100,9 +100,10 @@ def test_graph_profiling_counts_timed_passes(monkeypatch):
         ctx.profile(0)
         assert st == 0 and ms > 0.0
         counts.append((n, info["iters"]))
-    # 6 sweeps x 4 colours per cycle on the finest level, the first pass from
-    # the zero guess untimed: 23 passes, every second one timed (a graph times
-    # the same 12 in every replay; direct launches alternate 12 and 11)
+    # 6 sweeps of 4 colour passes per cycle on the finest level; the sweep
+    # that starts from the zero guess is not timed, every second one of the
+    # other 5 is (a graph times the same 3 sweeps, 12 passes, in every
+    # replay; direct launches alternate 3 and 2 sweeps)
     for n, iters in counts:
-        assert 11 * iters <= n <= 12 * iters, (n, iters)
+        assert n % 4 == 0 and 8 * iters <= n <= 12 * iters, (n, iters)
     assert counts[0][1] == counts[1][1]
