@@ -225,16 +225,17 @@ struct Work {
   alignas(16) T s0[D * D][S::NQ];                 // s_ik at E
   alignas(16) T trx[2][D][D + 1][S::MT];          // traces of x_E: [lo/hi][axis][field][t]
   alignas(16) T trn[2][D][D + 1][S::MT];          // [0]: x_{E-e_k}|hi, [1]: x_{E+e_k}|lo
-  alignas(16) T trs[2][D][D][S::MT];              // s_E[i][k] lo/hi along k
   alignas(16) T trr[D][D][S::MT];                 // s_{E+e_k}[i][k] at its low face along k
   alignas(16) T trrh[IF ? D : 1][D][S::MT];       // (IF) s_{E-e_k}[i][k] at its high face along k
   alignas(16) T flux[2][D][D + 1][S::MT];         // coefficients of e0 (lo) and e1 (hi) per axis/field
-  alignas(16) T res[S::NB];
   // the 1D tables K, e0, e1 (TabT layout) for lookups whose index differs
   // between lanes (kernel-argument arrays indexed per lane become memory loads)
   alignas(16) T tabs[3 * MAXM * MAXM + 2 * MAXM];   // K, e0, e1, P[0], P[1]
   unsigned char ft[S::NFS][D][2];
   alignas(16) T fwl[S::NFS][D][2], fwr[S::NFS][D][2];
+  // residual of the element, last before the viscosity data: the arrays before
+  // it are free again once it is formed (scratch of the inverse product)
+  alignas(16) T res[S::NB];
   // viscosity data, last: levels with constant viscosity do not allocate it
   alignas(16) T rr[D][S::MT * S::NQ];             // R_k = (e0^T)_k M_mu of E+e_k
   alignas(16) T rrh[IF ? D : 1][S::MT * S::NQ];   // (IF) (e1^T)_k M_mu of E-e_k
@@ -290,7 +291,7 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, const TabT<T>
   using ED = ElemData<T, D, P, NT, IF>;
   constexpr int NQ = S::NQ, MT = S::MT, NB = S::NB, NFS = S::NFS, NSLOT = S::NSLOT;
   constexpr int XQ = ED::XQ, MQ = ED::MQ, RQ = ED::RQ, TQ = ED::TQ;
-    const int n = lev.n, lgn = lev.lgn;
+  const int n = lev.n, lgn = lev.lgn;
   d.E = E;
   constexpr int TABN = 3 * MAXM * MAXM + 2 * MAXM;
   static_assert(TABN <= 64, "one table entry per lane of the first wavefront");
@@ -511,25 +512,40 @@ __device__ __forceinline__ void elem_stage(const DevLevel<T>& lev, const ElemDat
   __syncthreads();
 }
 
-// Phases 2-6 on the staged element: (A x)_E (mode 1) or b_E - (A x)_E
+// Phases 2-5 on the staged element: (A x)_E (mode 1) or b_E - (A x)_E
 // (mode 0, b_E in bc) into w.res.  Operators of the diagonally scaled system
 // D A D when lev.dscale is set (ds0v, ds0p: the element's scaling).
 template <typename T, int D, int P, int NT, bool IF>
 __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<T>& tab, int E, int vmask, int mode,
                                              const T* bc, T ds0v, T ds0p, Work<T, D, P, IF>& w, int lane) {
   using S = Sz<D, P, IF>;
-  constexpr int M = S::M, NQ = S::NQ, MT = S::MT, NB = S::NB, NFS = S::NFS;
+  constexpr int M = S::M, NQ = S::NQ, MT = S::MT, NB = S::NB;
   constexpr int XQ = ElemData<T, D, P, NT, IF>::XQ;
   using W = Work<T, D, P, IF>;
-    const T hinv = lev.hinv;
+  const T hinv = lev.hinv;
   const T gam = (T)lev.gamma;
-  (void)NFS;
   // ---- phase 2: gradient lines g_F = G_k u_i along axis k ----
   // per axis k: F = E (all i), F = E+e_k (all i), F = E+e_j (j != k, component
-  // i = j); with interphase faces also F = E-e_k (all i), F = E-e_j (i = j)
+  // i = j); with interphase faces also F = E-e_k (all i), F = E-e_j (i = j).
+  // Further items: the traces of p along k (p_E at both faces, p_{E-e_k} at
+  // its high face, p_{E+e_k} at its low face)
   {
     constexpr int PER_K = (IF ? 5 * D - 2 : 3 * D - 1) * MT;
-    for (int u = lane; u < D * PER_K; u += NT) {
+    constexpr int NPT = D * 4 * MT;
+    for (int u = lane; u < D * PER_K + NPT; u += NT) {
+      if (u >= D * PER_K) {
+        const int r = u - D * PER_K;
+        const int t = r % MT, kind = (r / MT) % 4, k = r / (4 * MT);
+        const int base = compose<M>(t, 0, k), st = stride_of<M>(k);
+        const int sl = kind < 2 ? 0 : (kind == 2 ? Slot<D>::m(k) : Slot<D>::p(k));
+        const bool hi = kind == 1 || kind == 2;   // trace at the element's high face (e1) or low face (e0)
+        const T* src = &w.xs[sl][D * NQ + base];
+        T v = 0;
+#pragma unroll
+        for (int bb = 0; bb < M; ++bb) v += w.tabs[MAXM * MAXM + (hi ? MAXM : 0) + bb] * src[bb * st];
+        *(kind < 2 ? &w.trx[kind][k][D][t] : &w.trn[kind - 2][k][D][t]) = v;
+        continue;
+      }
       const int k = u / PER_K;
       const int r = u % PER_K;
       const int t = r % MT;
@@ -686,34 +702,7 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
     }
   }
   __syncthreads();
-  // ---- phase 4: the remaining traces along each axis: p_E at both faces,
-  // p_{E-e_k} at its high face and p_{E+e_k} at its low face, s_E[i][k] at
-  // both faces (one code path with selected source, face and destination) ----
-  {
-    constexpr int NX = 2 * MT;             // p_E lo/hi
-    constexpr int NN = 2 * MT;             // p_{E-e_k}|hi, p_{E+e_k}|lo
-    constexpr int NTR = 2 * D * MT;        // s_E[i][k] lo/hi
-    constexpr int PER_K = NX + NN + NTR;
-    for (int u = lane; u < D * PER_K; u += NT) {
-      const int k = u / PER_K, r = u % PER_K;
-      const int base_mt = r % MT;
-      const int base = compose<M>(base_mt, 0, k), st = stride_of<M>(k);
-      const bool isx = r < NX, isn = !isx && r < NX + NN;
-      const int r2 = isx ? r : (isn ? r - NX : r - NX - NN);
-      const int fs = (r2 / MT) % D;
-      const int side = isx || isn ? r2 / MT : r2 / (MT * D);
-      const T* src = isx ? &w.xs[0][D * NQ + base]
-                         : (isn ? &w.xs[side ? 1 + D + k : 1 + k][D * NQ + base] : &w.s0[fs * D + k][base]);
-      T* dst = isx ? &w.trx[side][k][D][base_mt] : (isn ? &w.trn[side][k][D][base_mt] : &w.trs[side][k][fs][base_mt]);
-      const bool hi = isn ? side == 0 : side != 0;   // trace at the element's high face (e1) or low face (e0)
-      T v = 0;
-#pragma unroll
-      for (int bb = 0; bb < M; ++bb) v += w.tabs[MAXM * MAXM + (hi ? MAXM : 0) + bb] * src[bb * st];
-      *dst = v;
-    }
-  }
-  __syncthreads();
-  // ---- phase 5: face fluxes, one code path for every kind of face and field
+  // ---- phase 4: face fluxes, one code path for every kind of face and field
   // (the terms present are selected through their coefficients) ----
   for (int u = lane; u < D * 2 * (D + 1) * MT; u += NT) {
     const int tt = u % MT, f = (u / MT) % (D + 1), side = (u / (MT * (D + 1))) % 2, k = u / (2 * MT * (D + 1));
@@ -750,11 +739,17 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
       cpn = (kk && two) ? wR : (T)0;
       sr = w.trr[k][i][tt];
     }
-    v += cs * w.trs[side][k][i][tt] + cr * sr + cpx * w.trx[side][k][D][tt] + cpn * w.trn[side][k][D][tt];
+    // s_E[i][k] at this face
+    const T* sv = &w.s0[i * D + k][compose<M>(tt, 0, k)];
+    const int st = stride_of<M>(k);
+    T se = 0;
+#pragma unroll
+    for (int bb = 0; bb < M; ++bb) se += w.tabs[MAXM * MAXM + (side ? MAXM : 0) + bb] * sv[bb * st];
+    v += cs * se + cr * sr + cpx * w.trx[side][k][D][tt] + cpn * w.trn[side][k][D][tt];
     w.flux[side][k][f][tt] = hinv * v;
   }
   __syncthreads();
-  // ---- phase 6: assemble (A x)_E and the residual, one code path for the
+  // ---- phase 5: assemble (A x)_E and the residual, one code path for the
   // rows of u (div s, grad p, rho/delta u) and of p (div u) ----
 #pragma unroll
   for (int q = 0; q < XQ; ++q) {
