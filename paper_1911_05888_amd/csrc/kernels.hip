@@ -214,6 +214,13 @@ __device__ __forceinline__ int high_slot(int fi, int k) {
   return k == j ? 0 : Slot<D>::pm(k, j);
 }
 
+// Where the traces of p and of s_E are formed: in 3D with the gradient lines
+// (p) and inline in the flux step (s), one barrier fewer (C3 125 -> 120 ms);
+// in 2D in a step of their own, which measured faster there (the finest C2
+// pass 27.7 -> 26.6 us)
+template <int D>
+constexpr bool FOLD_TRACES = D == 3;
+
 // shared-memory work area of one element evaluation
 template <typename T, int D, int P, bool IF = false>
 struct Work {
@@ -225,6 +232,8 @@ struct Work {
   alignas(16) T s0[D * D][S::NQ];                 // s_ik at E
   alignas(16) T trx[2][D][D + 1][S::MT];          // traces of x_E: [lo/hi][axis][field][t]
   alignas(16) T trn[2][D][D + 1][S::MT];          // [0]: x_{E-e_k}|hi, [1]: x_{E+e_k}|lo
+  // s_E[i][k] lo/hi along k (only where a separate trace step forms it)
+  alignas(16) T trs[FOLD_TRACES<D> ? 1 : 2][FOLD_TRACES<D> ? 1 : D][FOLD_TRACES<D> ? 1 : D][FOLD_TRACES<D> ? 1 : S::MT];
   alignas(16) T trr[D][D][S::MT];                 // s_{E+e_k}[i][k] at its low face along k
   alignas(16) T trrh[IF ? D : 1][D][S::MT];       // (IF) s_{E-e_k}[i][k] at its high face along k
   alignas(16) T flux[2][D][D + 1][S::MT];         // coefficients of e0 (lo) and e1 (hi) per axis/field
@@ -512,7 +521,7 @@ __device__ __forceinline__ void elem_stage(const DevLevel<T>& lev, const ElemDat
   __syncthreads();
 }
 
-// Phases 2-5 on the staged element: (A x)_E (mode 1) or b_E - (A x)_E
+// Phases 2-6 on the staged element: (A x)_E (mode 1) or b_E - (A x)_E
 // (mode 0, b_E in bc) into w.res.  Operators of the diagonally scaled system
 // D A D when lev.dscale is set (ds0v, ds0p: the element's scaling).
 template <typename T, int D, int P, int NT, bool IF>
@@ -527,11 +536,11 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
   // ---- phase 2: gradient lines g_F = G_k u_i along axis k ----
   // per axis k: F = E (all i), F = E+e_k (all i), F = E+e_j (j != k, component
   // i = j); with interphase faces also F = E-e_k (all i), F = E-e_j (i = j).
-  // Further items: the traces of p along k (p_E at both faces, p_{E-e_k} at
-  // its high face, p_{E+e_k} at its low face)
+  // With FOLD_TRACES further items: the traces of p along k (p_E at both
+  // faces, p_{E-e_k} at its high face, p_{E+e_k} at its low face)
   {
     constexpr int PER_K = (IF ? 5 * D - 2 : 3 * D - 1) * MT;
-    constexpr int NPT = D * 4 * MT;
+    constexpr int NPT = FOLD_TRACES<D> ? D * 4 * MT : 0;
     for (int u = lane; u < D * PER_K + NPT; u += NT) {
       if (u >= D * PER_K) {
         const int r = u - D * PER_K;
@@ -702,7 +711,38 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
     }
   }
   __syncthreads();
-  // ---- phase 4: face fluxes, one code path for every kind of face and field
+  // ---- phase 4 (without FOLD_TRACES): the remaining traces along each axis:
+  // p_E at both faces, p_{E-e_k} at its high face and p_{E+e_k} at its low
+  // face, s_E[i][k] at both faces (one code path with selected source, face
+  // and destination) ----
+  if constexpr (!FOLD_TRACES<D>) {
+    constexpr int NX = 2 * MT;             // p_E lo/hi
+    constexpr int NN = 2 * MT;             // p_{E-e_k}|hi, p_{E+e_k}|lo
+    constexpr int NTR = 2 * D * MT;        // s_E[i][k] lo/hi
+    constexpr int PER_K = NX + NN + NTR;
+    for (int u = lane; u < D * PER_K; u += NT) {
+      const int k = u / PER_K, r = u % PER_K;
+      const int base_mt = r % MT;
+      const int base = compose<M>(base_mt, 0, k), st = stride_of<M>(k);
+      const bool isx = r < NX, isn = !isx && r < NX + NN;
+      const int r2 = isx ? r : (isn ? r - NX : r - NX - NN);
+      const int fs = (r2 / MT) % D;
+      const int side = isx || isn ? r2 / MT : r2 / (MT * D);
+      const T* src = isx ? &w.xs[0][D * NQ + base]
+                         : (isn ? &w.xs[side ? 1 + D + k : 1 + k][D * NQ + base] : &w.s0[fs * D + k][base]);
+      T* dst = isx ? &w.trx[side][k][D][base_mt]
+                   : (isn ? &w.trn[side][k][D][base_mt]
+                          : &w.trs[FOLD_TRACES<D> ? 0 : side][FOLD_TRACES<D> ? 0 : k][FOLD_TRACES<D> ? 0 : fs]
+                                  [FOLD_TRACES<D> ? 0 : base_mt]);
+      const bool hi = isn ? side == 0 : side != 0;   // trace at the element's high face (e1) or low face (e0)
+      T v = 0;
+#pragma unroll
+      for (int bb = 0; bb < M; ++bb) v += w.tabs[MAXM * MAXM + (hi ? MAXM : 0) + bb] * src[bb * st];
+      *dst = v;
+    }
+    __syncthreads();
+  }
+  // ---- phase 5: face fluxes, one code path for every kind of face and field
   // (the terms present are selected through their coefficients) ----
   for (int u = lane; u < D * 2 * (D + 1) * MT; u += NT) {
     const int tt = u % MT, f = (u / MT) % (D + 1), side = (u / (MT * (D + 1))) % 2, k = u / (2 * MT * (D + 1));
@@ -740,16 +780,21 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
       sr = w.trr[k][i][tt];
     }
     // s_E[i][k] at this face
-    const T* sv = &w.s0[i * D + k][compose<M>(tt, 0, k)];
-    const int st = stride_of<M>(k);
-    T se = 0;
+    T se;
+    if constexpr (FOLD_TRACES<D>) {
+      const T* sv = &w.s0[i * D + k][compose<M>(tt, 0, k)];
+      const int st = stride_of<M>(k);
+      se = 0;
 #pragma unroll
-    for (int bb = 0; bb < M; ++bb) se += w.tabs[MAXM * MAXM + (side ? MAXM : 0) + bb] * sv[bb * st];
+      for (int bb = 0; bb < M; ++bb) se += w.tabs[MAXM * MAXM + (side ? MAXM : 0) + bb] * sv[bb * st];
+    } else {
+      se = w.trs[FOLD_TRACES<D> ? 0 : side][FOLD_TRACES<D> ? 0 : k][FOLD_TRACES<D> ? 0 : i][FOLD_TRACES<D> ? 0 : tt];
+    }
     v += cs * se + cr * sr + cpx * w.trx[side][k][D][tt] + cpn * w.trn[side][k][D][tt];
     w.flux[side][k][f][tt] = hinv * v;
   }
   __syncthreads();
-  // ---- phase 5: assemble (A x)_E and the residual, one code path for the
+  // ---- phase 6: assemble (A x)_E and the residual, one code path for the
   // rows of u (div s, grad p, rho/delta u) and of p (div u) ----
 #pragma unroll
   for (int q = 0; q < XQ; ++q) {
