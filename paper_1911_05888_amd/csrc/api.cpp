@@ -84,7 +84,10 @@ struct ldgs_ctx {
   int small_grid = 4096;       // see LaunchCfg; LDGS_SMALL_GRID overrides (tests)
   bool shared_inverse = true;  // one inverse per level with equal blocks; LDGS_SHARED_INVERSE=0 disables
   bool use_graph = true;       // V-cycles replayed from captured HIP graphs; LDGS_GRAPH=0 disables
-  bool use_mfma = true;        // one-inverse FP32 updates of large colours on the matrix cores; LDGS_MFMA=0 disables
+  // one-inverse FP32 updates of colours of at least mfma_min elements on the
+  // matrix cores (0: never); LDGS_MFMA=0 disables, LDGS_MFMA_MIN overrides
+  // the size (tests)
+  int64_t mfma_min = 8192;
   std::vector<int> kernel_offsets;
   PrecStore<double> s64;
   PrecStore<float> s32;      // float arithmetic, float inverses
@@ -677,7 +680,7 @@ void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* 
     // one inverse for the level: residuals of the colour, then the shared update
     LCHK(launch_colour_residual<T>(cfg, pl.view, c->tab, pl.elems + o, pcol, cnt, b, x, pl.rbuf));
     LCHK(launch_shared_update<T>(c->stream, cnt, c->g.nb, pl.ainv_sh, pl.rbuf, pl.elems + o, x, 0, nullptr, 0,
-                                 c->use_mfma));
+                                 c->mfma_min));
   } else
   // (split only large launches: on coarse levels the second launch would cost
   // more than the extended stencil)
@@ -704,7 +707,7 @@ void first_colour(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x) {
   const int pcol = pl.parity ? 0 : -1;
   if (pl.ainv_sh)
     LCHK(launch_shared_update<T>(c->stream, cnt, c->g.nb, pl.ainv_sh, b, pl.elems, x, 1, pl.elems + cnt, nzero,
-                                 c->use_mfma));
+                                 c->mfma_min));
   else
     LCHK(launch_first_colour<T>(cfg, log2i(c->levels[l].n), pl.elems, pcol, cnt, pl.inv, pl.inv_kind, b, x,
                                 pl.elems + cnt, nzero));
@@ -1048,7 +1051,12 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
     }
     if (const char* si = std::getenv("LDGS_SHARED_INVERSE")) c->shared_inverse = std::strtol(si, nullptr, 10) != 0;
     if (const char* gr = std::getenv("LDGS_GRAPH")) c->use_graph = std::strtol(gr, nullptr, 10) != 0;
-    if (const char* mf = std::getenv("LDGS_MFMA")) c->use_mfma = std::strtol(mf, nullptr, 10) != 0;
+    if (const char* mm = std::getenv("LDGS_MFMA_MIN")) {
+      const long v = std::strtol(mm, nullptr, 10);
+      if (v >= 1) c->mfma_min = v;
+    }
+    if (const char* mf = std::getenv("LDGS_MFMA"))
+      if (std::strtol(mf, nullptr, 10) == 0) c->mfma_min = 0;
     c->k0 = kernel_dim(P);
     if (c->k0 == 1) c->kernel_offsets = {P.dim * c->g.nq};
     else for (int i = 0; i <= P.dim; ++i) c->kernel_offsets.push_back(i * c->g.nq);

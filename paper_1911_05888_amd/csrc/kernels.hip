@@ -1620,14 +1620,15 @@ static void shared_update_q(hipStream_t st, int64_t nelems, const T* ainv, const
   hipLaunchKernelGGL((k_shared_update<T, NB, Q>), dim3((unsigned)g), dim3(SU_THREADS), 0, st, (int)nelems, ainv, r,
                      elems, x, first, zl, (int)nzero);
 }
-// large colours: the matrix cores in FP32 (blocks up to 128), else 16
-// elements per thread; small colours: 4 elements per thread (more
-// work-groups, shorter chains: small launches are latency bound)
+// large colours (at least mfma_min elements; 0: never): the matrix cores in
+// FP32 (blocks up to 128), else 16 elements per thread from 8192 elements;
+// small colours: 4 elements per thread (more work-groups, shorter chains:
+// small launches are latency bound)
 template <typename T, int NB>
 static void shared_update_nb(hipStream_t st, int64_t nelems, const T* ainv, const T* r, const int* elems, T* x,
-                             int first, const int* zl, int64_t nzero, bool mfma) {
+                             int first, const int* zl, int64_t nzero, int64_t mfma_min) {
   if constexpr (sizeof(T) == 4 && NB <= 128) {
-    if (mfma && nelems >= 8192) {
+    if (mfma_min > 0 && nelems >= mfma_min) {
       int64_t g = (nelems + MfmaSu<NB>::TN - 1) / MfmaSu<NB>::TN;
       if (g > 1024) g = 1024;
       hipLaunchKernelGGL((k_shared_update_mfma<NB>), dim3((unsigned)g), dim3(256), 0, st, (int)nelems, ainv, r, elems,
@@ -1641,12 +1642,12 @@ static void shared_update_nb(hipStream_t st, int64_t nelems, const T* ainv, cons
 
 template <typename T>
 int launch_shared_update(void* stream, int64_t nelems, int nb, const T* ainv, const T* r, const int* elems, T* x,
-                         int first, const int* zl, int64_t nzero, bool mfma) {
+                         int first, const int* zl, int64_t nzero, int64_t mfma_min) {
   if (nelems <= 0) return 0;
   hipStream_t st = (hipStream_t)stream;
   switch (nb) {
 #define LDGS_SU(NBV) \
-  case NBV: shared_update_nb<T, NBV>(st, nelems, ainv, r, elems, x, first, zl, nzero, mfma); break;
+  case NBV: shared_update_nb<T, NBV>(st, nelems, ainv, r, elems, x, first, zl, nzero, mfma_min); break;
     LDGS_SU(12) LDGS_SU(27) LDGS_SU(48) LDGS_SU(32) LDGS_SU(108) LDGS_SU(256)
 #undef LDGS_SU
     default: return 2;
@@ -1809,9 +1810,9 @@ template int launch_colour_residual<double>(const LaunchCfg&, const DevLevel<dou
 template int launch_colour_residual<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const int*, int,
                                            int64_t, const float*, const float*, float*);
 template int launch_shared_update<double>(void*, int64_t, int, const double*, const double*, const int*, double*,
-                                          int, const int*, int64_t, bool);
+                                          int, const int*, int64_t, int64_t);
 template int launch_shared_update<float>(void*, int64_t, int, const float*, const float*, const int*, float*, int,
-                                         const int*, int64_t, bool);
+                                         const int*, int64_t, int64_t);
 template int launch_first_colour<double>(const LaunchCfg&, int, const int*, int, int64_t, const void*, int,
                                          const double*, double*, const int*, int64_t);
 template int launch_first_colour<float>(const LaunchCfg&, int, const int*, int, int64_t, const void*, int,

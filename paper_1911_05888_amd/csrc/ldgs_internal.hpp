@@ -145,10 +145,11 @@ int launch_colour_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab
                            int64_t nelems, const T* b, const T* x, T* r);
 // first != 0: the first pass from x = 0 (r is then b, read at the listed
 // elements; x_E is assigned and the nzero elements zl are set to zero);
-// mfma: FP32 products of large colours on the matrix cores
+// FP32 products of colours of at least mfma_min elements (0: none) on the
+// matrix cores
 template <typename T>
 int launch_shared_update(void* stream, int64_t nelems, int nb, const T* ainv, const T* r, const int* elems, T* x,
-                         int first, const int* zl, int64_t nzero, bool mfma);
+                         int first, const int* zl, int64_t nzero, int64_t mfma_min);
 // first colour pass from x = 0 with per-element inverses: x_E = Ainv_E b_E for
 // the listed elements (same element / inverse conventions as
 // launch_smooth_colour), and the nzero elements zl set to zero

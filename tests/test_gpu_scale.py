@@ -250,22 +250,30 @@ def test_full_size_colour_pass_invariants_other_configurations(name):
 
 MFMA_CASES = {
     # colours of 32768 elements, 108 x 108 inverse (the 3D unsteady workload)
-    "c3_n64_p2": lambda: __import__("synth").c3_unsteady_periodic(n=64, p=2, re_eff=10.0),
+    "c3_n64_p2": (lambda: __import__("synth").c3_unsteady_periodic(n=64, p=2, re_eff=10.0), None),
     # colours of 16384 elements, 48 x 48 inverse
-    "per2d_n256_p3": lambda: Problem(name="per2d", dim=2, n=256, p=3, gamma=1, bc=("periodic", "periodic")),
+    "per2d_n256_p3": (lambda: Problem(name="per2d", dim=2, n=256, p=3, gamma=1, bc=("periodic", "periodic")), None),
+    # every colour on the matrix cores (threshold lowered): 64 elements per
+    # colour on the finest level (two 32-element tiles), 8 on the next (one
+    # partial tile), 108 x 108 inverse
+    "per3d_n8_p2_all": (lambda: Problem(name="per3d", dim=3, n=8, p=2, gamma=1, bc=("periodic",) * 3), "1"),
 }
 
 
 @pytest.mark.parametrize("name", list(MFMA_CASES))
 def test_shared_inverse_update_on_matrix_cores(name, monkeypatch):
     """FP32 colour passes on a one-inverse level with colours of at least 8192
-    elements: the update on the matrix cores (FP32 MFMA) against the same
-    update on the vector ALUs (LDGS_MFMA=0), the first pass from a zero guess
-    (inside V-cycles) included, and both against FP64."""
+    elements (or of any size, with the threshold lowered): the update on the
+    matrix cores (FP32 MFMA) against the same update on the vector ALUs
+    (LDGS_MFMA=0), the first pass from a zero guess (inside V-cycles)
+    included, and both against FP64."""
     import torch
     from paper_1911_05888_amd import Context, V_FP32
-    prob = MFMA_CASES[name]()
+    make, mfma_min = MFMA_CASES[name]
+    prob = make()
     print(f"[scale] matrix-core shared update {name}", flush=True)
+    if mfma_min:
+        monkeypatch.setenv("LDGS_MFMA_MIN", mfma_min)
     ctxs = []
     for flag in ("1", "0"):
         monkeypatch.setenv("LDGS_MFMA", flag)
