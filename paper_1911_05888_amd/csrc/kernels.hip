@@ -1474,9 +1474,19 @@ __global__ void k_scale_cast(int64_t ne, int nb, int nvel, const double* dscale,
 constexpr int RB = 256;
 __global__ __launch_bounds__(RB) void k_dot_partial(int64_t n, const double* x, const double* y, double* out) {
   __shared__ double sm[RB];
-  double s = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB)
-    s += x[i] * (y ? y[i] : x[i]);
+  const double* yy = y ? y : x;
+  const int64_t gs = (int64_t)gridDim.x * RB;
+  int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+  // four independent strided partial sums: four loads in flight per thread
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (; i + 3 * gs < n; i += 4 * gs) {
+    s0 += x[i] * yy[i];
+    s1 += x[i + gs] * yy[i + gs];
+    s2 += x[i + 2 * gs] * yy[i + 2 * gs];
+    s3 += x[i + 3 * gs] * yy[i + 3 * gs];
+  }
+  for (; i < n; i += gs) s0 += x[i] * yy[i];
+  const double s = (s0 + s1) + (s2 + s3);
   sm[threadIdx.x] = s;
   __syncthreads();
   for (int st = RB / 2; st > 0; st >>= 1) {
