@@ -730,10 +730,7 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
       const int side = isx || isn ? r2 / MT : r2 / (MT * D);
       const T* src = isx ? &w.xs[0][D * NQ + base]
                          : (isn ? &w.xs[side ? 1 + D + k : 1 + k][D * NQ + base] : &w.s0[fs * D + k][base]);
-      T* dst = isx ? &w.trx[side][k][D][base_mt]
-                   : (isn ? &w.trn[side][k][D][base_mt]
-                          : &w.trs[FOLD_TRACES<D> ? 0 : side][FOLD_TRACES<D> ? 0 : k][FOLD_TRACES<D> ? 0 : fs]
-                                  [FOLD_TRACES<D> ? 0 : base_mt]);
+      T* dst = isx ? &w.trx[side][k][D][base_mt] : (isn ? &w.trn[side][k][D][base_mt] : &w.trs[side][k][fs][base_mt]);
       const bool hi = isn ? side == 0 : side != 0;   // trace at the element's high face (e1) or low face (e0)
       T v = 0;
 #pragma unroll
@@ -788,7 +785,7 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
 #pragma unroll
       for (int bb = 0; bb < M; ++bb) se += w.tabs[MAXM * MAXM + (side ? MAXM : 0) + bb] * sv[bb * st];
     } else {
-      se = w.trs[FOLD_TRACES<D> ? 0 : side][FOLD_TRACES<D> ? 0 : k][FOLD_TRACES<D> ? 0 : i][FOLD_TRACES<D> ? 0 : tt];
+      se = w.trs[side][k][i][tt];
     }
     v += cs * se + cr * sr + cpx * w.trx[side][k][D][tt] + cpn * w.trn[side][k][D][tt];
     w.flux[side][k][f][tt] = hinv * v;
