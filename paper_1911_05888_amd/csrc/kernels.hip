@@ -259,6 +259,46 @@ constexpr size_t work_bytes(bool var_mu) {
   return var_mu ? sizeof(W) : offsetof(W, rr);
 }
 
+// Per-lane items of the trace step (where the traces are not folded), decoded
+// at compile time: item u takes the trace of the line at `src` (offset in the
+// work area, entries of T) with e1 (hi) or e0 along axis k (stride M^k) and
+// stores it at `dst`.  Packed: src | dst << 12 | k << 24 | hi << 26.
+template <typename T, int D, int P, bool IF>
+struct TraceItems {
+  using W = Work<T, D, P, IF>;
+  using S = Sz<D, P, IF>;
+  static constexpr int M = S::M, NQ = S::NQ, MT = S::MT, NB = S::NB;
+  static constexpr int NX = 2 * MT, NN = 2 * MT, NTR = 2 * D * MT, PER_K = NX + NN + NTR, N = D * PER_K;
+  struct Tab {
+    unsigned w[N];
+  };
+  static constexpr int off(size_t member) { return (int)(member / sizeof(T)); }
+  static constexpr Tab make() {
+    Tab t{};
+    for (int u = 0; u < N; ++u) {
+      const int k = u / PER_K, r = u % PER_K, bm = r % MT;
+      int lo = 1;
+      for (int j = 0; j < k; ++j) lo *= M;
+      const int base = bm % lo + lo * M * (bm / lo);   // line start: coordinate k = 0
+      const bool isx = r < NX, isn = !isx && r < NX + NN;
+      const int r2 = isx ? r : (isn ? r - NX : r - NX - NN);
+      const int fs = (r2 / MT) % D;
+      const int side = isx || isn ? r2 / MT : r2 / (MT * D);
+      const int src = isx ? off(offsetof(W, xs)) + D * NQ + base
+                          : (isn ? off(offsetof(W, xs)) + (side ? 1 + D + k : 1 + k) * NB + D * NQ + base
+                                 : off(offsetof(W, s0)) + (fs * D + k) * NQ + base);
+      const int dst = isx ? off(offsetof(W, trx)) + ((side * D + k) * (D + 1) + D) * MT + bm
+                          : (isn ? off(offsetof(W, trn)) + ((side * D + k) * (D + 1) + D) * MT + bm
+                                 : off(offsetof(W, trs)) + ((side * D + k) * D + fs) * MT + bm);
+      const bool hi = isn ? side == 0 : side != 0;
+      t.w[u] = (unsigned)src | ((unsigned)dst << 12) | ((unsigned)k << 24) | ((hi ? 1u : 0u) << 26);
+    }
+    return t;
+  }
+  static constexpr Tab tab = make();
+  static_assert(sizeof(W) / sizeof(T) < 4096, "12-bit offsets");
+};
+
 extern __shared__ __align__(16) unsigned char dyn_lds[];
 template <typename T, int D, int P, bool IF>
 __device__ __forceinline__ Work<T, D, P, IF>& work_lds() {
@@ -288,6 +328,7 @@ struct ElemData {
   unsigned char fty[S::NFS][D][2];
   T fwl[S::NFS][D][2], fwr[S::NFS][D][2];
   T dsv[S::NSLOT], dsp[S::NSLOT];
+  unsigned titem;                // this lane's trace-step item (TraceItems), where the traces are not folded
 };
 
 // Computes the stencil and face data of E and issues every load of the
@@ -305,6 +346,11 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, const TabT<T>
   constexpr int TABN = 3 * MAXM * MAXM + 2 * MAXM;
   static_assert(TABN <= 64, "one table entry per lane of the first wavefront");
   d.tabv = reinterpret_cast<const T*>(&tab)[lane < TABN ? lane : 0];
+  if constexpr (!FOLD_TRACES<D>) {
+    using TRI = TraceItems<T, D, P, IF>;
+    static_assert(TRI::N <= 64, "one trace item per lane of the first wavefront");
+    d.titem = TRI::tab.w[lane < TRI::N ? lane : 0];
+  }
   int c[D];
   coords_of<D>(E, lgn, c);
   d.se[0] = E;
@@ -526,7 +572,8 @@ __device__ __forceinline__ void elem_stage(const DevLevel<T>& lev, const ElemDat
 // D A D when lev.dscale is set (ds0v, ds0p: the element's scaling).
 template <typename T, int D, int P, int NT, bool IF>
 __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<T>& tab, int E, int vmask, int mode,
-                                             const T* bc, T ds0v, T ds0p, Work<T, D, P, IF>& w, int lane) {
+                                             const T* bc, T ds0v, T ds0p, unsigned titem, Work<T, D, P, IF>& w,
+                                             int lane) {
   using S = Sz<D, P, IF>;
   constexpr int M = S::M, NQ = S::NQ, MT = S::MT, NB = S::NB;
   constexpr int XQ = ElemData<T, D, P, NT, IF>::XQ;
@@ -713,28 +760,17 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
   __syncthreads();
   // ---- phase 4 (without FOLD_TRACES): the remaining traces along each axis:
   // p_E at both faces, p_{E-e_k} at its high face and p_{E+e_k} at its low
-  // face, s_E[i][k] at both faces (one code path with selected source, face
-  // and destination) ----
+  // face, s_E[i][k] at both faces; each lane's source, face and destination
+  // come decoded from TraceItems ----
   if constexpr (!FOLD_TRACES<D>) {
-    constexpr int NX = 2 * MT;             // p_E lo/hi
-    constexpr int NN = 2 * MT;             // p_{E-e_k}|hi, p_{E+e_k}|lo
-    constexpr int NTR = 2 * D * MT;        // s_E[i][k] lo/hi
-    constexpr int PER_K = NX + NN + NTR;
-    for (int u = lane; u < D * PER_K; u += NT) {
-      const int k = u / PER_K, r = u % PER_K;
-      const int base_mt = r % MT;
-      const int base = compose<M>(base_mt, 0, k), st = stride_of<M>(k);
-      const bool isx = r < NX, isn = !isx && r < NX + NN;
-      const int r2 = isx ? r : (isn ? r - NX : r - NX - NN);
-      const int fs = (r2 / MT) % D;
-      const int side = isx || isn ? r2 / MT : r2 / (MT * D);
-      const T* src = isx ? &w.xs[0][D * NQ + base]
-                         : (isn ? &w.xs[side ? 1 + D + k : 1 + k][D * NQ + base] : &w.s0[fs * D + k][base]);
-      T* dst = isx ? &w.trx[side][k][D][base_mt] : (isn ? &w.trn[side][k][D][base_mt] : &w.trs[side][k][fs][base_mt]);
-      const bool hi = isn ? side == 0 : side != 0;   // trace at the element's high face (e1) or low face (e0)
+    if (lane < TraceItems<T, D, P, IF>::N) {
+      const T* src = reinterpret_cast<const T*>(&w) + (titem & 0xfffu);
+      T* dst = reinterpret_cast<T*>(&w) + ((titem >> 12) & 0xfffu);
+      const int st = stride_of<M>((int)((titem >> 24) & 3u));
+      const T* e = &w.tabs[MAXM * MAXM + (int)((titem >> 26) & 1u) * MAXM];
       T v = 0;
 #pragma unroll
-      for (int bb = 0; bb < M; ++bb) v += w.tabs[MAXM * MAXM + (hi ? MAXM : 0) + bb] * src[bb * st];
+      for (int bb = 0; bb < M; ++bb) v += e[bb] * src[bb * st];
       *dst = v;
     }
     __syncthreads();
@@ -850,7 +886,7 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
   elem_issue<T, D, P, NT, IF>(lev, tab, E, x, b, mode, d, lane);
   after_loads();
   elem_stage<T, D, P, NT, IF>(lev, d, w, lane);
-  elem_compute<T, D, P, NT, IF>(lev, tab, E, d.vmask, mode, d.br, d.dsv[0], d.dsp[0], w, lane);
+  elem_compute<T, D, P, NT, IF>(lev, tab, E, d.vmask, mode, d.br, d.dsv[0], d.dsp[0], d.titem, w, lane);
 }
 
 // Raw words of one lane's load of the inverse (sym_tiles: LB bytes) and entry
