@@ -299,6 +299,54 @@ struct TraceItems {
   static_assert(sizeof(W) / sizeof(T) < 4096, "12-bit offsets");
 };
 
+// Per-lane items of the gradient-line step on levels without interphase faces
+// where the traces are not folded, decoded at compile time (the order of the
+// step's own decoding: axis k, then F = E, E+e_k, E+e_j, then the line t).
+// a: offset of the line of F (uu) | offset of the line of F - e_k (ul) << 12 |
+//    k << 24 | trace kind << 26 (1: F = E, 2: F = E + e_k) | slot of F << 28
+// b: offset of the output line g_F (go) | face entry fi * D + k << 12 |
+//    trace index (k (D + 1) + i) MT + t << 16
+struct alignas(8) GradWord {
+  unsigned a, b;
+};
+template <typename T, int D, int P>
+struct GradItems {
+  using W = Work<T, D, P, false>;
+  using S = Sz<D, P, false>;
+  static constexpr int M = S::M, NQ = S::NQ, MT = S::MT, NB = S::NB;
+  static constexpr int PER_K = (3 * D - 1) * MT, N = D * PER_K;
+  struct Tab {
+    GradWord w[N];
+  };
+  static constexpr int off(size_t member) { return (int)(member / sizeof(T)); }
+  static constexpr Tab make() {
+    Tab tb{};
+    for (int u = 0; u < N; ++u) {
+      const int k = u / PER_K, r = u % PER_K, t = r % MT, q = r / MT;
+      int fi, i;
+      if (q < D) { fi = 0; i = q; }
+      else if (q < 2 * D) { fi = 1 + k; i = q - D; }
+      else { const int j0 = q - 2 * D; const int j = j0 < k ? j0 : j0 + 1; fi = 1 + j; i = j; }
+      const int sF = fi == 0 ? 0 : 1 + D + (fi - 1);
+      const int jj = fi - 1;
+      const int sL = fi == 0 ? 1 + k : (k == jj ? 0 : 1 + 2 * D + jj * (D - 1) + (k < jj ? k : k - 1));
+      int lo = 1;
+      for (int j = 0; j < k; ++j) lo *= M;
+      const int base = t % lo + lo * M * (t / lo);
+      const int uu = off(offsetof(W, xs)) + sF * NB + i * NQ + base;
+      const int ul = off(offsetof(W, xs)) + sL * NB + i * NQ + base;
+      const int go = off(offsetof(W, g)) + (fi * D * D + i * D + k) * NQ + base;
+      const int kind = fi == 0 ? 1 : (fi == 1 + k ? 2 : 0);
+      const int tidx = (k * (D + 1) + i) * MT + t;
+      tb.w[u].a = (unsigned)uu | ((unsigned)ul << 12) | ((unsigned)k << 24) | ((unsigned)kind << 26) | ((unsigned)sF << 28);
+      tb.w[u].b = (unsigned)go | ((unsigned)(fi * D + k) << 12) | ((unsigned)tidx << 16);
+    }
+    return tb;
+  }
+  static constexpr Tab tab = make();
+  static_assert(sizeof(W) / sizeof(T) < 4096 && 1 + 2 * D + D * (D - 1) <= 16 && D * (D + 1) * MT <= 256, "packing");
+};
+
 extern __shared__ __align__(16) unsigned char dyn_lds[];
 template <typename T, int D, int P, bool IF>
 __device__ __forceinline__ Work<T, D, P, IF>& work_lds() {
@@ -329,6 +377,7 @@ struct ElemData {
   T fwl[S::NFS][D][2], fwr[S::NFS][D][2];
   T dsv[S::NSLOT], dsp[S::NSLOT];
   unsigned titem;                // this lane's trace-step item (TraceItems), where the traces are not folded
+  GradWord gitem;                // this lane's gradient-line item (GradItems), on the same levels without IF
 };
 
 // Computes the stencil and face data of E and issues every load of the
@@ -350,6 +399,11 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, const TabT<T>
     using TRI = TraceItems<T, D, P, IF>;
     static_assert(TRI::N <= 64, "one trace item per lane of the first wavefront");
     d.titem = TRI::tab.w[lane < TRI::N ? lane : 0];
+    if constexpr (!IF) {
+      using GRI = GradItems<T, D, P>;
+      static_assert(GRI::N <= 64, "one gradient item per lane of the first wavefront");
+      d.gitem = GRI::tab.w[lane < GRI::N ? lane : 0];
+    }
   }
   int c[D];
   coords_of<D>(E, lgn, c);
@@ -572,8 +626,8 @@ __device__ __forceinline__ void elem_stage(const DevLevel<T>& lev, const ElemDat
 // D A D when lev.dscale is set (ds0v, ds0p: the element's scaling).
 template <typename T, int D, int P, int NT, bool IF>
 __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<T>& tab, int E, int vmask, int mode,
-                                             const T* bc, T ds0v, T ds0p, unsigned titem, Work<T, D, P, IF>& w,
-                                             int lane) {
+                                             const T* bc, T ds0v, T ds0p, unsigned titem, GradWord gitem,
+                                             Work<T, D, P, IF>& w, int lane) {
   using S = Sz<D, P, IF>;
   constexpr int M = S::M, NQ = S::NQ, MT = S::MT, NB = S::NB;
   constexpr int XQ = ElemData<T, D, P, NT, IF>::XQ;
@@ -585,7 +639,75 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
   // i = j); with interphase faces also F = E-e_k (all i), F = E-e_j (i = j).
   // With FOLD_TRACES further items: the traces of p along k (p_E at both
   // faces, p_{E-e_k} at its high face, p_{E+e_k} at its low face)
-  {
+  //
+  // One line: the traces of u_i along k at the faces of F, the lifted jumps,
+  // and g_F = G_k u_i on the line (go), from the line of F (uu), of F - e_k
+  // (ul) and, with interphase faces, of F + e_k (uh, read only when needed).
+  auto line = [&](const T* uu, const T* ul, const T* uh, int st, unsigned char tlo, unsigned char thi, T wR, T wL,
+                  T* go, T& trlo, T& trhi, T& trLhi) {
+    T uv[M];
+    trlo = 0;
+    trhi = 0;
+    trLhi = 0;
+#pragma unroll
+    for (int bb = 0; bb < M; ++bb) {
+      uv[bb] = uu[bb * st];
+      trlo += tab.e0[bb] * uv[bb];
+      trhi += tab.e1[bb] * uv[bb];
+      trLhi += tab.e1[bb] * ul[bb * st];
+    }
+    const T jlo = (tlo == F_NONE) ? (T)0 : wR * (trlo - (two_sided<IF>(tlo) ? trLhi : (T)0));
+    // lifting of the high-face jump onto F (weight wL: Dirichlet, or an
+    // interphase face lifting onto its low element)
+    T jhi = (thi == F_DIR_HI) ? wL * trhi : (T)0;
+    if constexpr (IF) {
+      if (thi == F_INTRA || thi == F_INTER) {
+        T trHlo = 0;
+#pragma unroll
+        for (int bb = 0; bb < M; ++bb) trHlo += tab.e0[bb] * uh[bb * st];
+        jhi = wL * (trhi - trHlo);
+      }
+    }
+#pragma unroll
+    for (int ak = 0; ak < M; ++ak) {
+      T v = tab.e0[ak] * jlo - tab.e1[ak] * jhi;
+#pragma unroll
+      for (int bb = 0; bb < M; ++bb) v += tab.K[ak * M + bb] * uv[bb];
+      go[ak * st] = hinv * v;
+    }
+  };
+  // the velocity traces along k that the fluxes need come out of these lines:
+  // x_E at both faces (trx), x_{E-e_k} at its high face (trn[0]), x_{E+e_k}
+  // at its low face (trn[1]); entries (k (D + 1) + i) MT + t
+  T* const trx0 = &w.trx[0][0][0][0];
+  T* const trx1 = &w.trx[1][0][0][0];
+  T* const trn0 = &w.trn[0][0][0][0];
+  T* const trn1 = &w.trn[1][0][0][0];
+  if constexpr (!IF && !FOLD_TRACES<D>) {
+    // each lane's item decoded at compile time (GradItems)
+    if (lane < GradItems<T, D, P>::N) {
+      const int sF = (int)(gitem.a >> 28), kind = (int)((gitem.a >> 26) & 3u), tidx = (int)((gitem.b >> 16) & 255u);
+      if (!((vmask >> sF) & 1)) {
+        if (kind == 2) trn1[tidx] = 0;   // no E + e_k: its traces read as zero
+      } else {
+        T* wb = reinterpret_cast<T*>(&w);
+        const int k = (int)((gitem.a >> 24) & 3u), fk = (int)((gitem.b >> 12) & 15u);
+        const unsigned char* ft = &w.ft[0][0][0];
+        T trlo, trhi, trLhi;
+        line(wb + (gitem.a & 0xfffu), wb + ((gitem.a >> 12) & 0xfffu), nullptr, stride_of<M>(k), ft[2 * fk],
+             ft[2 * fk + 1], (&w.fwr[0][0][0])[2 * fk], (&w.fwl[0][0][0])[2 * fk + 1], wb + (gitem.b & 0xfffu), trlo,
+             trhi, trLhi);
+        if (kind == 1) {
+          trx0[tidx] = trlo;
+          trx1[tidx] = trhi;
+          trn0[tidx] = trLhi;
+        } else if (kind == 2) {
+          trn1[tidx] = trlo;
+        }
+      }
+    }
+  } else {
+    (void)gitem;
     constexpr int PER_K = (IF ? 5 * D - 2 : 3 * D - 1) * MT;
     constexpr int NPT = FOLD_TRACES<D> ? D * 4 * MT : 0;
     for (int u = lane; u < D * PER_K + NPT; u += NT) {
@@ -613,54 +735,22 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
       else if (q < 4 * D - 1) { fi = 1 + D + k; i = q - (3 * D - 1); }
       else { const int j0 = q - (4 * D - 1); const int j = j0 < k ? j0 : j0 + 1; fi = 1 + D + j; i = j; }
       const int sF = f_slot<D>(fi);
+      const int tidx = (k * (D + 1) + i) * MT + t;
       if (!((vmask >> sF) & 1)) {
-        if (fi == 1 + k) w.trn[1][k][i][t] = 0;   // no E + e_k: its traces read as zero
+        if (fi == 1 + k) trn1[tidx] = 0;   // no E + e_k: its traces read as zero
         continue;
       }
-      const unsigned char tlo = w.ft[fi][k][0], thi = w.ft[fi][k][1];
-      const T wR = w.fwr[fi][k][0], wL = w.fwl[fi][k][1];
       const int base = compose<M>(t, 0, k), st = stride_of<M>(k);
-      const T* uu = &w.xs[sF][i * NQ + base];
-      const T* ul = &w.xs[low_slot<D>(fi, k)][i * NQ + base];
-      T uv[M];
-      T trlo = 0, trhi = 0, trLhi = 0;
-#pragma unroll
-      for (int bb = 0; bb < M; ++bb) {
-        uv[bb] = uu[bb * st];
-        trlo += tab.e0[bb] * uv[bb];
-        trhi += tab.e1[bb] * uv[bb];
-        trLhi += tab.e1[bb] * ul[bb * st];
-      }
-      const T jlo = (tlo == F_NONE) ? (T)0 : wR * (trlo - (two_sided<IF>(tlo) ? trLhi : (T)0));
-      // lifting of the high-face jump onto F (weight wL: Dirichlet, or an
-      // interphase face lifting onto its low element)
-      T jhi = (thi == F_DIR_HI) ? wL * trhi : (T)0;
-      if constexpr (IF) {
-        if (thi == F_INTRA || thi == F_INTER) {
-          const T* uh = &w.xs[high_slot<D>(fi, k)][i * NQ + base];
-          T trHlo = 0;
-#pragma unroll
-          for (int bb = 0; bb < M; ++bb) trHlo += tab.e0[bb] * uh[bb * st];
-          jhi = wL * (trhi - trHlo);
-        }
-      }
-      // the velocity traces along k that the fluxes need come out of these
-      // lines: x_E at both faces, x_{E-e_k} at its high face, x_{E+e_k} at
-      // its low face
+      T trlo, trhi, trLhi;
+      line(&w.xs[sF][i * NQ + base], &w.xs[low_slot<D>(fi, k)][i * NQ + base],
+           IF ? &w.xs[IF ? high_slot<D>(fi, k) : 0][i * NQ + base] : nullptr, st, w.ft[fi][k][0], w.ft[fi][k][1],
+           w.fwr[fi][k][0], w.fwl[fi][k][1], &w.g[fi][i * D + k][base], trlo, trhi, trLhi);
       if (fi == 0) {
-        w.trx[0][k][i][t] = trlo;
-        w.trx[1][k][i][t] = trhi;
-        w.trn[0][k][i][t] = trLhi;
+        trx0[tidx] = trlo;
+        trx1[tidx] = trhi;
+        trn0[tidx] = trLhi;
       } else if (fi == 1 + k) {
-        w.trn[1][k][i][t] = trlo;
-      }
-      T* go = &w.g[fi][i * D + k][base];
-#pragma unroll
-      for (int ak = 0; ak < M; ++ak) {
-        T v = tab.e0[ak] * jlo - tab.e1[ak] * jhi;
-#pragma unroll
-        for (int bb = 0; bb < M; ++bb) v += tab.K[ak * M + bb] * uv[bb];
-        go[ak * st] = hinv * v;
+        trn1[tidx] = trlo;
       }
     }
   }
@@ -886,7 +976,7 @@ __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const T
   elem_issue<T, D, P, NT, IF>(lev, tab, E, x, b, mode, d, lane);
   after_loads();
   elem_stage<T, D, P, NT, IF>(lev, d, w, lane);
-  elem_compute<T, D, P, NT, IF>(lev, tab, E, d.vmask, mode, d.br, d.dsv[0], d.dsp[0], d.titem, w, lane);
+  elem_compute<T, D, P, NT, IF>(lev, tab, E, d.vmask, mode, d.br, d.dsv[0], d.dsp[0], d.titem, d.gitem, w, lane);
 }
 
 // Raw words of one lane's load of the inverse (sym_tiles: LB bytes) and entry
