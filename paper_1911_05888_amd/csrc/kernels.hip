@@ -323,7 +323,7 @@ struct GradItems {
     Tab tb{};
     for (int u = 0; u < N; ++u) {
       const int k = u / PER_K, r = u % PER_K, t = r % MT, q = r / MT;
-      int fi, i;
+      int fi = 0, i = 0;
       if (q < D) { fi = 0; i = q; }
       else if (q < 2 * D) { fi = 1 + k; i = q - D; }
       else { const int j0 = q - 2 * D; const int j = j0 < k ? j0 : j0 + 1; fi = 1 + j; i = j; }
