@@ -382,7 +382,7 @@ struct ElemData {
 
 // Computes the stencil and face data of E and issues every load of the
 // element at once (addresses in bounds; masks are applied when staging).
-template <typename T, int D, int P, int NT, bool IF>
+template <typename T, int D, int P, int NT, bool IF, bool INT = false>
 __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, const TabT<T>& tab, int E,
                                            const T* __restrict__ x, const T* __restrict__ b, int mode,
                                            ElemData<T, D, P, NT, IF>& d, int lane) {
@@ -413,8 +413,9 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, const TabT<T>
     int cm[D], cp[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) cm[j] = cp[j] = c[j];
-    d.se[1 + k] = shift1(cm, k, -1, n, lev.nf[k] == n) ? index_of<D>(cm, lgn) : -1;
-    d.se[1 + D + k] = shift1(cp, k, +1, n, lev.nf[k] == n) ? index_of<D>(cp, lgn) : -1;
+    // (INT: an interior element, whose stencil is complete)
+    d.se[1 + k] = (shift1(cm, k, -1, n, lev.nf[k] == n) || INT) ? index_of<D>(cm, lgn) : -1;
+    d.se[1 + D + k] = (shift1(cp, k, +1, n, lev.nf[k] == n) || INT) ? index_of<D>(cp, lgn) : -1;
 #pragma unroll
     for (int q = 0; q < D - 1; ++q) {
       const int kk = q < k ? q : q + 1;
@@ -422,7 +423,7 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, const TabT<T>
 #pragma unroll
       for (int j = 0; j < D; ++j) cq[j] = c[j];
       const bool ok = shift1(cq, k, +1, n, lev.nf[k] == n) && shift1(cq, kk, -1, n, lev.nf[kk] == n);
-      d.se[1 + 2 * D + k * (D - 1) + q] = ok ? index_of<D>(cq, lgn) : -1;
+      d.se[1 + 2 * D + k * (D - 1) + q] = (ok || INT) ? index_of<D>(cq, lgn) : -1;
     }
   }
   if constexpr (IF) {
@@ -452,6 +453,7 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, const TabT<T>
   d.vmask = 0;
 #pragma unroll
   for (int sl = 0; sl < NSLOT; ++sl) d.vmask |= (d.se[sl] >= 0 ? 1 : 0) << sl;
+  if constexpr (INT) d.vmask = (1 << NSLOT) - 1;
 #pragma unroll
   for (int sl = 0; sl < NSLOT; ++sl)
 #pragma unroll
@@ -519,6 +521,12 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, const TabT<T>
           d.fty[fi][k][side] = valid ? lev.ftype[k][id] : (unsigned char)F_NONE;
           d.fwl[fi][k][side] = valid ? lev.fw[k][2 * id] : (T)0;
           d.fwr[fi][k][side] = valid ? lev.fw[k][2 * id + 1] : (T)0;
+        } else if constexpr (INT) {
+          // an interior element: every face of E and E+e_j is intraphase
+          (void)valid;
+          d.fty[fi][k][side] = F_INTRA;
+          d.fwl[fi][k][side] = (T)0;
+          d.fwr[fi][k][side] = (T)1;
         } else {
           // without interphase faces the type and the lifting weights follow
           // from the position: Dirichlet faces at the walls (weight 1 on their
@@ -557,7 +565,7 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, const TabT<T>
 }
 
 // Writes the loaded element data to LDS (waits for the loads).
-template <typename T, int D, int P, int NT, bool IF>
+template <typename T, int D, int P, int NT, bool IF, bool INT = false>
 __device__ __forceinline__ void elem_stage(const DevLevel<T>& lev, const ElemData<T, D, P, NT, IF>& d,
                                            Work<T, D, P, IF>& w, int lane) {
   if (lane < 3 * MAXM * MAXM + 2 * MAXM) w.tabs[lane] = d.tabv;
@@ -606,7 +614,7 @@ __device__ __forceinline__ void elem_stage(const DevLevel<T>& lev, const ElemDat
         const int t = lane + q * NT;
         if (t < MT * MT) w.th[side][k][t] = d.tr[k][side][q];
       }
-  if (lane == 0) {
+  if (!INT && lane == 0) {
 #pragma unroll
     for (int fi = 0; fi < NFS; ++fi)
 #pragma unroll
@@ -624,8 +632,8 @@ __device__ __forceinline__ void elem_stage(const DevLevel<T>& lev, const ElemDat
 // Phases 2-6 on the staged element: (A x)_E (mode 1) or b_E - (A x)_E
 // (mode 0, b_E in bc) into w.res.  Operators of the diagonally scaled system
 // D A D when lev.dscale is set (ds0v, ds0p: the element's scaling).
-template <typename T, int D, int P, int NT, bool IF>
-__device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<T>& tab, int E, int vmask, int mode,
+template <typename T, int D, int P, int NT, bool IF, bool INT = false>
+__device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<T>& tab, int E, int vmask_in, int mode,
                                              const T* bc, T ds0v, T ds0p, unsigned titem, GradWord gitem,
                                              Work<T, D, P, IF>& w, int lane) {
   using S = Sz<D, P, IF>;
@@ -634,6 +642,10 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
   using W = Work<T, D, P, IF>;
   const T hinv = lev.hinv;
   const T gam = (T)lev.gamma;
+  // INT (an interior element): every stencil slot exists and every face of E
+  // and E+e_j is intraphase with lifting weights (wL, wR) = (0, 1); the face
+  // data are then constants instead of LDS reads
+  const int vmask = INT ? (1 << S::NSLOT) - 1 : vmask_in;
   // ---- phase 2: gradient lines g_F = G_k u_i along axis k ----
   // per axis k: F = E (all i), F = E+e_k (all i), F = E+e_j (j != k, component
   // i = j); with interphase faces also F = E-e_k (all i), F = E-e_j (i = j).
@@ -694,9 +706,10 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
         const int k = (int)((gitem.a >> 24) & 3u), fk = (int)((gitem.b >> 12) & 15u);
         const unsigned char* ft = &w.ft[0][0][0];
         T trlo, trhi, trLhi;
-        line(wb + (gitem.a & 0xfffu), wb + ((gitem.a >> 12) & 0xfffu), nullptr, stride_of<M>(k), ft[2 * fk],
-             ft[2 * fk + 1], (&w.fwr[0][0][0])[2 * fk], (&w.fwl[0][0][0])[2 * fk + 1], wb + (gitem.b & 0xfffu), trlo,
-             trhi, trLhi);
+        line(wb + (gitem.a & 0xfffu), wb + ((gitem.a >> 12) & 0xfffu), nullptr, stride_of<M>(k),
+             INT ? (unsigned char)F_INTRA : ft[2 * fk], INT ? (unsigned char)F_INTRA : ft[2 * fk + 1],
+             INT ? (T)1 : (&w.fwr[0][0][0])[2 * fk], INT ? (T)0 : (&w.fwl[0][0][0])[2 * fk + 1],
+             wb + (gitem.b & 0xfffu), trlo, trhi, trLhi);
         if (kind == 1) {
           trx0[tidx] = trlo;
           trx1[tidx] = trhi;
@@ -743,8 +756,9 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
       const int base = compose<M>(t, 0, k), st = stride_of<M>(k);
       T trlo, trhi, trLhi;
       line(&w.xs[sF][i * NQ + base], &w.xs[low_slot<D>(fi, k)][i * NQ + base],
-           IF ? &w.xs[IF ? high_slot<D>(fi, k) : 0][i * NQ + base] : nullptr, st, w.ft[fi][k][0], w.ft[fi][k][1],
-           w.fwr[fi][k][0], w.fwl[fi][k][1], &w.g[fi][i * D + k][base], trlo, trhi, trLhi);
+           IF ? &w.xs[IF ? high_slot<D>(fi, k) : 0][i * NQ + base] : nullptr, st,
+           INT ? (unsigned char)F_INTRA : w.ft[fi][k][0], INT ? (unsigned char)F_INTRA : w.ft[fi][k][1],
+           INT ? (T)1 : w.fwr[fi][k][0], INT ? (T)0 : w.fwl[fi][k][1], &w.g[fi][i * D + k][base], trlo, trhi, trLhi);
       if (fi == 0) {
         trx0[tidx] = trlo;
         trx1[tidx] = trhi;
@@ -869,8 +883,8 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
   // (the terms present are selected through their coefficients) ----
   for (int u = lane; u < D * 2 * (D + 1) * MT; u += NT) {
     const int tt = u % MT, f = (u / MT) % (D + 1), side = (u / (MT * (D + 1))) % 2, k = u / (2 * MT * (D + 1));
-    const unsigned char ty = w.ft[0][k][side];
-    const T wL = w.fwl[0][k][side], wR = w.fwr[0][k][side];
+    const unsigned char ty = INT ? (unsigned char)F_INTRA : w.ft[0][k][side];
+    const T wL = INT ? (T)0 : w.fwl[0][k][side], wR = INT ? (T)1 : w.fwr[0][k][side];
     const T* Th = &w.th[side][k][tt * MT];
     const bool vel = f < D, two = two_sided<IF>(ty), inter = is_inter<IF>(ty);
     const bool dir = ty == (side ? F_DIR_HI : F_DIR_LO), has = ty != F_NONE, intra = ty == F_INTRA;
@@ -964,19 +978,47 @@ struct NoHook {
   __device__ void operator()() const {}
 };
 
+template <typename T, int D, int P, int NT, bool IF, bool INT, class Hook>
+__device__ __forceinline__ void element_operator_v(const DevLevel<T>& lev, const TabT<T>& tab, int E,
+                                                   const T* __restrict__ x, const T* __restrict__ b, int mode,
+                                                   Work<T, D, P, IF>& w, Hook& after_loads) {
+  ElemData<T, D, P, NT, IF> d;
+  const int lane = threadIdx.x;
+  elem_issue<T, D, P, NT, IF, INT>(lev, tab, E, x, b, mode, d, lane);
+  after_loads();
+  elem_stage<T, D, P, NT, IF, INT>(lev, d, w, lane);
+  elem_compute<T, D, P, NT, IF, INT>(lev, tab, E, d.vmask, mode, d.br, d.dsv[0], d.dsp[0], d.titem, d.gitem, w,
+                                     lane);
+}
+
+// Element E is interior when along every axis the grid is periodic or
+// 1 <= c_k <= n - 3: its stencil is complete and every face of E and of
+// E+e_j is an intraphase face.
+template <typename T, int D>
+__device__ __forceinline__ bool interior_elem(const DevLevel<T>& lev, int E) {
+  int c[D];
+  coords_of<D>(E, lev.lgn, c);
+  bool in = true;
+#pragma unroll
+  for (int k = 0; k < D; ++k) in = in && (lev.nf[k] == lev.n || (c[k] >= 1 && c[k] <= lev.n - 3));
+  return in;
+}
+
 // Evaluates (A x)_E (mode 1) or b_E - (A x)_E (mode 0) into w.res.
 // `after_loads` runs once the element's loads are issued and before they are
-// waited for: loads it issues then overlap the evaluation.
+// waited for: loads it issues then overlap the evaluation.  Levels without
+// interphase faces evaluate interior elements with the face data as constants.
 template <typename T, int D, int P, int NT, bool IF, class Hook = NoHook>
 __device__ __forceinline__ void element_operator(const DevLevel<T>& lev, const TabT<T>& tab, int E,
                                                  const T* __restrict__ x, const T* __restrict__ b,
                                                  int mode, Work<T, D, P, IF>& w, Hook after_loads = Hook()) {
-  ElemData<T, D, P, NT, IF> d;
-  const int lane = threadIdx.x;
-  elem_issue<T, D, P, NT, IF>(lev, tab, E, x, b, mode, d, lane);
-  after_loads();
-  elem_stage<T, D, P, NT, IF>(lev, d, w, lane);
-  elem_compute<T, D, P, NT, IF>(lev, tab, E, d.vmask, mode, d.br, d.dsv[0], d.dsp[0], d.titem, d.gitem, w, lane);
+  if constexpr (!IF) {
+    if (interior_elem<T, D>(lev, E)) {
+      element_operator_v<T, D, P, NT, IF, true>(lev, tab, E, x, b, mode, w, after_loads);
+      return;
+    }
+  }
+  element_operator_v<T, D, P, NT, IF, false>(lev, tab, E, x, b, mode, w, after_loads);
 }
 
 // Raw words of one lane's load of the inverse (sym_tiles: LB bytes) and entry
