@@ -133,7 +133,24 @@ typedef struct {
                                validation without a GPU); device entry points then
                                return LDGS_E_UNSUPPORTED and ldgs_assemble_rhs writes
                                to a host pointer */
-  void* hip_stream;         /* hipStream_t; NULL = default stream */
+  void* hip_stream;         /* hipStream_t the context works on.  NULL: the
+                               library creates a stream of its own (the legacy
+                               null stream cannot be captured into a graph) and
+                               orders it, at every call, after the work queued
+                               on the null stream before the call, and the null
+                               stream after the work of the call */
+  /* Device allocator for all storage of the context (operator data, block
+   * inverses, work vectors, Krylov basis), e.g. a framework's caching
+   * allocator, so that the caller stays the owner of device memory.
+   * dev_alloc(bytes, alloc_user) returns a 256-byte aligned device pointer or
+   * NULL (then the call that needed it fails with LDGS_E_NOMEM);
+   * dev_free(ptr, alloc_user) receives every block back in ldgs_destroy,
+   * after the context's stream has drained.  Both NULL: hipMalloc/hipFree.
+   * Giving only one of them is LDGS_E_ARG.  The callbacks are called from
+   * the thread that calls into the library, never during graph capture. */
+  void* (*dev_alloc)(size_t bytes, void* alloc_user);
+  void (*dev_free)(void* ptr, void* alloc_user);
+  void* alloc_user;
 } ldgs_problem;
 
 /* Data of the right-hand side, eq. (govern1)-(govern3).  Each callback may be
@@ -196,6 +213,12 @@ ldgs_status ldgs_vcycle(ldgs_ctx* ctx, const double* b_dev, double* x_dev);
  * (info->fallback_events counts this).  info may be NULL.  Synchronises. */
 ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b_dev, double* x_dev, double tol, int maxit,
                        int outer, int fgmres_m, int use_learned, ldgs_info* info);
+
+/* Number of V-cycles captured into HIP graphs so far (one per precision,
+ * zero-guess flag and timing stride; each is replayed on later cycles).  0
+ * when graphs are off (environment variable LDGS_GRAPH=0 at setup) or when a
+ * capture failed, in which case the cycles are launched directly. */
+ldgs_status ldgs_graph_count(const ldgs_ctx* ctx, int* n_graphs);
 
 /* Switch the precision used by ldgs_vcycle / ldgs_solve among those built. */
 ldgs_status ldgs_set_vprec(ldgs_ctx* ctx, int vprec);

@@ -129,6 +129,10 @@ struct ldgs_ctx {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<void*> allocs;
+  // a stream of the library's own when the caller gives none (the legacy
+  // null stream cannot be captured into a graph); calls order it after the
+  // caller's null-stream work and the null stream after it (join events)
+  hipEvent_t join_in = nullptr, join_out = nullptr;
   // captured V-cycles, one per (precision, zero guess, timing stride); the
   // event pairs recorded inside a graph are read after the next host
   // synchronisation (they are re-recorded at every replay)
@@ -147,10 +151,18 @@ struct ldgs_ctx {
   double prof_acc_ms = 0.0;
   int64_t prof_acc_n = 0;
   ~ldgs_ctx() {
+    // nothing may still use the storage when it goes back to its owner (a
+    // caching allocator hands it out again at once)
+    if (!host_only) (void)hipStreamSynchronize(stream);
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
     for (hipEvent_t e : cap_pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-    for (void* p : allocs) (void)hipFree(p);
+    for (void* p : allocs) {
+      if (P.dev_free) P.dev_free(p, P.alloc_user);
+      else (void)hipFree(p);
+    }
+    if (join_in) (void)hipEventDestroy(join_in);
+    if (join_out) (void)hipEventDestroy(join_out);
     if (stream_owned && stream) (void)hipStreamDestroy(stream);
   }
   bool stream_owned = false;
@@ -159,15 +171,47 @@ struct ldgs_ctx {
 
 namespace {
 
+// Device storage of the context: from the caller's allocator when it gave
+// one (dev_alloc / dev_free of ldgs_problem), else hipMalloc.  Every block is
+// returned when the context is destroyed.
 template <typename T>
 T* dalloc(ldgs_ctx* c, size_t count) {
   void* p = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc(&p, count * sizeof(T));
-  if (e != hipSuccess) throw Fail{LDGS_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+  const size_t bytes = count * sizeof(T);
+  if (c->P.dev_alloc) {
+    p = c->P.dev_alloc(bytes, c->P.alloc_user);
+    if (!p) throw Fail{LDGS_E_NOMEM, "dev_alloc returned NULL for " + std::to_string(bytes) + " bytes"};
+    if (((uintptr_t)p & 255u) != 0) {
+      c->P.dev_free(p, c->P.alloc_user);
+      throw Fail{LDGS_E_ARG, "dev_alloc returned a block that is not 256-byte aligned"};
+    }
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) throw Fail{LDGS_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+  }
   c->allocs.push_back(p);
   return (T*)p;
 }
+
+// Orders the library's own stream (used when the caller gave none) after the
+// work the caller queued on the null stream before the call, and the null
+// stream after the work of the call.
+struct Join {
+  ldgs_ctx* c;
+  explicit Join(ldgs_ctx* c_) : c(c_) {
+    if (c && c->stream_owned) {
+      HIPCHK(hipEventRecord(c->join_in, nullptr));
+      HIPCHK(hipStreamWaitEvent(c->stream, c->join_in, 0));
+    }
+  }
+  ~Join() {
+    if (c && c->stream_owned) {
+      (void)hipEventRecord(c->join_out, c->stream);
+      (void)hipStreamWaitEvent(nullptr, c->join_out, 0);
+    }
+  }
+};
 
 template <typename T>
 T* upload(ldgs_ctx* c, const std::vector<double>& src) {
@@ -223,6 +267,8 @@ void validate(const ldgs_problem& P) {
   if (P.mu.kind != LDGS_FIELD_CALLBACK && !P.mu.params) throw Fail{LDGS_E_ARG, "mu params"};
   if (P.mu.kind == LDGS_FIELD_CALLBACK && !P.mu.fn) throw Fail{LDGS_E_ARG, "mu callback"};
   if (P.vprec < 0 || P.vprec > 2) throw Fail{LDGS_E_ARG, "vprec"};
+  if ((P.dev_alloc == nullptr) != (P.dev_free == nullptr))
+    throw Fail{LDGS_E_ARG, "dev_alloc and dev_free must be given together"};
   if (P.coloring < 0 || P.coloring > 3) throw Fail{LDGS_E_ARG, "coloring"};
 }
 
@@ -932,20 +978,6 @@ void net_pack(const NetShape& s, const float* flat, std::vector<float>& pad) {
     for (int h = 0; h < H; ++h) pad[s.oW3 + (int64_t)o * H + h] = *q++;
   for (int o = 0; o < s.nb; ++o) pad[s.ob3 + o] = *q++;
 }
-void net_unpack(const NetShape& s, const std::vector<float>& pad, float* flat) {
-  const int H = NET_H;
-  float* q = flat;
-  for (int h = 0; h < H; ++h)
-    for (int o = 0; o < s.noff; ++o)
-      for (int c = 0; c < s.ch; ++c) *q++ = pad[s.oW1 + (int64_t)h * s.k1p + o * s.chp + c];
-  for (int h = 0; h < H; ++h) *q++ = pad[s.ob1 + h];
-  for (int i = 0; i < H * H; ++i) *q++ = pad[s.oW2 + i];
-  for (int h = 0; h < H; ++h) *q++ = pad[s.ob2 + h];
-  for (int o = 0; o < s.nb; ++o)
-    for (int h = 0; h < H; ++h) *q++ = pad[s.oW3 + (int64_t)o * H + h];
-  for (int o = 0; o < s.nb; ++o) *q++ = pad[s.ob3 + o];
-}
-
 // per-context buffers of the correction (allocated once)
 void learned_buffers(ldgs_ctx* c) {
   if (c->d_logmu) return;
@@ -1006,6 +1038,100 @@ struct DevBufs {
     for (void* q : p) (void)hipFree(q);
   }
 };
+
+// device buffers of one training run: FP32 master parameters and their BF16
+// copy (padded layout), gradient, Adam moments, per-step losses, batch order
+struct TrainBufs {
+  float* w;
+  uint16_t* wbf;
+  float* g;
+  float* m;
+  float* v;
+  double* dl;
+  int* ord;
+};
+
+NetShape check_train_args(const ldgs_train_args* a, const float* params) {
+  if (!a || !params || !a->feat || !a->targ || !a->order) throw Fail{LDGS_E_ARG, "null argument"};
+  if ((a->dim != 2 && a->dim != 3) || a->degree < 1 || a->degree > (a->dim == 2 ? 3 : 2))
+    throw Fail{LDGS_E_UNSUPPORTED, "dim/degree"};
+  if (a->hidden != NET_H) throw Fail{LDGS_E_UNSUPPORTED, "hidden width must be 16"};
+  if (!pow2(a->crop) || a->crop < 4) throw Fail{LDGS_E_ARG, "crop must be a power of two >= 4"};
+  if (a->batch < 1 || a->steps < 0 || a->ncrops < 1) throw Fail{LDGS_E_ARG, "batch/steps/ncrops"};
+  if (!(a->c_vel > 0) || !(a->c_pre > 0) || !(a->lr > 0)) throw Fail{LDGS_E_ARG, "scales and lr must be positive"};
+  for (int64_t i = 0; i < (int64_t)a->steps * a->batch; ++i)
+    if (a->order[i] < 0 || a->order[i] >= a->ncrops) throw Fail{LDGS_E_ARG, "order index out of range"};
+  return net_shape(a->dim, a->degree);
+}
+
+// Host flat parameter layout <-> padded device layout, copied directly
+// between host and device memory (2D copies place each first-layer row
+// group at its padded offset; the padding itself must be zero beforehand).
+void net_upload(const NetShape& s, const float* flat, float* dev, hipStream_t st) {
+  const int H = NET_H;
+  const size_t f = sizeof(float);
+  for (int h = 0; h < H; ++h)
+    HIPCHK(hipMemcpy2DAsync(dev + s.oW1 + (int64_t)h * s.k1p, s.chp * f, flat + (int64_t)h * s.noff * s.ch, s.ch * f,
+                            s.ch * f, s.noff, hipMemcpyHostToDevice, st));
+  const float* q = flat + (int64_t)H * s.noff * s.ch;
+  HIPCHK(hipMemcpyAsync(dev + s.ob1, q, (2 * H + H * H) * f, hipMemcpyHostToDevice, st));   // b1 | W2 | b2
+  q += 2 * H + H * H;
+  HIPCHK(hipMemcpyAsync(dev + s.oW3, q, (size_t)s.nb * H * f, hipMemcpyHostToDevice, st));
+  q += (int64_t)s.nb * H;
+  HIPCHK(hipMemcpyAsync(dev + s.ob3, q, s.nb * f, hipMemcpyHostToDevice, st));
+}
+void net_download(const NetShape& s, const float* dev, float* flat, hipStream_t st) {
+  const int H = NET_H;
+  const size_t f = sizeof(float);
+  for (int h = 0; h < H; ++h)
+    HIPCHK(hipMemcpy2DAsync(flat + (int64_t)h * s.noff * s.ch, s.ch * f, dev + s.oW1 + (int64_t)h * s.k1p, s.chp * f,
+                            s.ch * f, s.noff, hipMemcpyDeviceToHost, st));
+  float* q = flat + (int64_t)H * s.noff * s.ch;
+  HIPCHK(hipMemcpyAsync(q, dev + s.ob1, (2 * H + H * H) * f, hipMemcpyDeviceToHost, st));
+  q += 2 * H + H * H;
+  HIPCHK(hipMemcpyAsync(q, dev + s.oW3, (size_t)s.nb * H * f, hipMemcpyDeviceToHost, st));
+  q += (int64_t)s.nb * H;
+  HIPCHK(hipMemcpyAsync(q, dev + s.ob3, s.nb * f, hipMemcpyDeviceToHost, st));
+}
+
+// The training loop on given device buffers: Adam on the FP32 master
+// weights, forward/backward in BF16 with FP32 accumulation.  Every buffer is
+// initialised here (parameters uploaded over a zeroed padding, gradient,
+// moments and losses zero-filled by kernels).
+void train_run(const ldgs_train_args* a, const NetShape& ns, const TrainBufs& T, float* params, double* loss_out,
+               float* grad0_out) {
+  hipStream_t st = (hipStream_t)a->hip_stream;
+  const int nsteps = a->steps > 0 ? a->steps : 1;
+  LCHK(launch_fill<float>(st, ns.total, 0.f, T.w));
+  net_upload(ns, params, T.w, st);
+  HIPCHK(hipMemcpyAsync(T.ord, a->order, (size_t)std::max(a->steps, 1) * a->batch * sizeof(int),
+                        hipMemcpyHostToDevice, st));
+  LCHK(launch_to_bf16(st, ns.total, T.w, T.wbf));
+  LCHK(launch_fill<float>(st, ns.total, 0.f, T.m));
+  LCHK(launch_fill<float>(st, ns.total, 0.f, T.v));
+  LCHK(launch_fill<double>(st, nsteps, 0.0, T.dl));
+  int64_t Cd = 1;
+  for (int k = 0; k < a->dim; ++k) Cd *= a->crop;
+  const double inv_count = 1.0 / ((double)a->batch * Cd * ns.nb);
+  const int steps_run = (a->steps == 0 && grad0_out) ? 1 : a->steps;
+  for (int s = 0; s < steps_run; ++s) {
+    LCHK(launch_fill<float>(st, ns.total, 0.f, T.g));
+    LCHK(launch_train_grad(st, a->dim, a->degree, a->crop, log2i(a->crop), a->batch, T.ord + (int64_t)s * a->batch,
+                           a->feat, a->targ, a->c_vel, a->c_pre, inv_count, NetDev{T.w, T.wbf}, T.g, T.dl + s));
+    if (s == 0 && grad0_out) net_download(ns, T.g, grad0_out, st);
+    if (a->steps == 0) break;
+    const int t = s + 1;
+    const float bc1 = (float)(1.0 / (1.0 - std::pow((double)a->beta1, t)));
+    const float bc2 = (float)(1.0 / (1.0 - std::pow((double)a->beta2, t)));
+    LCHK(launch_adam(st, ns.total, T.w, T.wbf, T.g, T.m, T.v, a->lr, a->beta1, a->beta2, a->eps, bc1, bc2));
+  }
+  net_download(ns, T.w, params, st);
+  if (loss_out && a->steps > 0)
+    HIPCHK(hipMemcpyAsync(loss_out, T.dl, (size_t)a->steps * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (loss_out)
+    for (int s = 0; s < a->steps; ++s) loss_out[s] *= inv_count;
+}
 
 }  // namespace
 
@@ -1075,7 +1201,14 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
       for (size_t l = 0; l + 1 < c->levels.size(); ++l) c->levels[l].uniform = uniform_blocks(c.get(), c->levels[l]);
     build_bottom(c.get());
     if (!c->host_only) {
-      if (P.hip_stream) c->stream = (hipStream_t)P.hip_stream;
+      if (P.hip_stream) {
+        c->stream = (hipStream_t)P.hip_stream;
+      } else {
+        HIPCHK(hipStreamCreate(&c->stream));
+        c->stream_owned = true;
+        HIPCHK(hipEventCreateWithFlags(&c->join_in, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c->join_out, hipEventDisableTiming));
+      }
       int mask = (1 << P.vprec) | P.build_precisions;
       bool n64 = mask & 1, n32 = mask & 2, n16 = mask & 4;
       upload_ops<double>(c.get(), c->s64, n64);     // finest FP64 operator always (outer residual)
@@ -1175,6 +1308,7 @@ ldgs_status ldgs_assemble_rhs(ldgs_ctx* ctx, const ldgs_rhs_data* data, double* 
 ldgs_status ldgs_apply(ldgs_ctx* ctx, const double* x, double* y) {
   try {
     check_ctx(ctx, true);
+    Join join_(ctx);
     if (!x || !y || x == y) throw Fail{LDGS_E_ARG, "x, y must be distinct non-null"};
     LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream, ctx->small_grid};
     LCHK(launch_residual<double>(cfg, ctx->s64.lv[0].unscaled, ctx->tab, nullptr, x, y, 1));
@@ -1187,6 +1321,7 @@ ldgs_status ldgs_apply(ldgs_ctx* ctx, const double* x, double* y) {
 ldgs_status ldgs_residual(ldgs_ctx* ctx, const double* b, const double* x, double* r, double* norm2) {
   try {
     check_ctx(ctx, true);
+    Join join_(ctx);
     if (!b || !x) throw Fail{LDGS_E_ARG, "null argument"};
     double* rr = r ? r : ctx->w_r;
     residual_fine(ctx, b, x, rr);
@@ -1200,12 +1335,19 @@ ldgs_status ldgs_residual(ldgs_ctx* ctx, const double* b, const double* x, doubl
 ldgs_status ldgs_vcycle(ldgs_ctx* ctx, const double* b, double* x) {
   try {
     check_ctx(ctx, true);
+    Join join_(ctx);
     if (!b || !x) throw Fail{LDGS_E_ARG, "null argument"};
     vcycle_user(ctx, ctx->vprec, b, x, false);
     return LDGS_OK;
   } catch (const Fail& f) {
     return handle(ctx, f);
   }
+}
+
+ldgs_status ldgs_graph_count(const ldgs_ctx* ctx, int* n_graphs) {
+  if (!ctx || !n_graphs) return LDGS_E_ARG;
+  *n_graphs = ctx->use_graph ? (int)ctx->graphs.size() : 0;
+  return LDGS_OK;
 }
 
 ldgs_status ldgs_set_vprec(ldgs_ctx* ctx, int vprec) {
@@ -1222,6 +1364,7 @@ ldgs_status ldgs_set_vprec(ldgs_ctx* ctx, int vprec) {
 ldgs_status ldgs_set_learned(ldgs_ctx* ctx, const ldgs_net* net) {
   try {
     check_ctx(ctx, true);
+    Join join_(ctx);
     if (!net) {
       ctx->net_loaded = false;
       return LDGS_OK;
@@ -1257,6 +1400,7 @@ ldgs_status ldgs_set_learned(ldgs_ctx* ctx, const ldgs_net* net) {
 ldgs_status ldgs_learned_correction(ldgs_ctx* ctx, const double* r, double* dx) {
   try {
     check_ctx(ctx, true);
+    Join join_(ctx);
     if (!r || !dx) throw Fail{LDGS_E_ARG, "null argument"};
     if (!ctx->net_loaded) throw Fail{LDGS_E_ARG, "no network loaded"};
     const Level& L = ctx->levels[0];
@@ -1275,6 +1419,7 @@ ldgs_status ldgs_learned_collect(ldgs_ctx* ctx, const double* xstar, int ncycles
                                  const int* origins, uint16_t* feat, uint16_t* targ, double* stats) {
   try {
     check_ctx(ctx, true);
+    Join join_(ctx);
     const Level& L = ctx->levels[0];
     const int d = ctx->g.d;
     if (!xstar || !origins || !feat || !targ || ncycles < 1 || ncrops < 1) throw Fail{LDGS_E_ARG, "bad argument"};
@@ -1345,61 +1490,18 @@ ldgs_status ldgs_learned_collect(ldgs_ctx* ctx, const double* xstar, int ncycles
 
 ldgs_status ldgs_learned_train(const ldgs_train_args* a, float* params, double* loss_out, float* grad0_out) {
   try {
-    if (!a || !params || !a->feat || !a->targ || !a->order) throw Fail{LDGS_E_ARG, "null argument"};
-    if ((a->dim != 2 && a->dim != 3) || a->degree < 1 || a->degree > (a->dim == 2 ? 3 : 2))
-      throw Fail{LDGS_E_UNSUPPORTED, "dim/degree"};
-    if (a->hidden != NET_H) throw Fail{LDGS_E_UNSUPPORTED, "hidden width must be 16"};
-    if (!pow2(a->crop) || a->crop < 4) throw Fail{LDGS_E_ARG, "crop must be a power of two >= 4"};
-    if (a->batch < 1 || a->steps < 0 || a->ncrops < 1) throw Fail{LDGS_E_ARG, "batch/steps/ncrops"};
-    if (!(a->c_vel > 0) || !(a->c_pre > 0) || !(a->lr > 0)) throw Fail{LDGS_E_ARG, "scales and lr must be positive"};
-    for (int64_t i = 0; i < (int64_t)a->steps * a->batch; ++i)
-      if (a->order[i] < 0 || a->order[i] >= a->ncrops) throw Fail{LDGS_E_ARG, "order index out of range"};
-    const NetShape ns = net_shape(a->dim, a->degree);
-    hipStream_t st = (hipStream_t)a->hip_stream;
-    DevBufs B;
-    float* w = B.get<float>(ns.total);
-    uint16_t* wbf = B.get<uint16_t>(ns.total);
-    float* g = B.get<float>(ns.total);
-    float* m = B.get<float>(ns.total);
-    float* v = B.get<float>(ns.total);
+    const NetShape ns = check_train_args(a, params);
     const int nsteps = a->steps > 0 ? a->steps : 1;
-    double* dl = B.get<double>(nsteps);
-    int* ord = B.get<int>((size_t)nsteps * a->batch);
-    std::vector<float> pad;
-    net_pack(ns, params, pad);
-    HIPCHK(hipMemcpy(w, pad.data(), pad.size() * sizeof(float), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(ord, a->order, (size_t)std::max(a->steps, 1) * a->batch * sizeof(int), hipMemcpyHostToDevice));
-    LCHK(launch_to_bf16(st, ns.total, w, wbf));
-    LCHK(launch_fill<float>(st, ns.total, 0.f, m));
-    LCHK(launch_fill<float>(st, ns.total, 0.f, v));
-    LCHK(launch_fill<double>(st, nsteps, 0.0, dl));
-    int64_t Cd = 1;
-    for (int k = 0; k < a->dim; ++k) Cd *= a->crop;
-    const double inv_count = 1.0 / ((double)a->batch * Cd * ns.nb);
-    const int steps_run = (a->steps == 0 && grad0_out) ? 1 : a->steps;
-    for (int s = 0; s < steps_run; ++s) {
-      LCHK(launch_fill<float>(st, ns.total, 0.f, g));
-      LCHK(launch_train_grad(st, a->dim, a->degree, a->crop, log2i(a->crop), a->batch, ord + (int64_t)s * a->batch,
-                             a->feat, a->targ, a->c_vel, a->c_pre, inv_count, NetDev{w, wbf}, g, dl + s));
-      if (s == 0 && grad0_out) {
-        std::vector<float> gp(ns.total);
-        HIPCHK(hipMemcpyAsync(gp.data(), g, ns.total * sizeof(float), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        net_unpack(ns, gp, grad0_out);
-      }
-      if (a->steps == 0) break;
-      const int t = s + 1;
-      const float bc1 = (float)(1.0 / (1.0 - std::pow((double)a->beta1, t)));
-      const float bc2 = (float)(1.0 / (1.0 - std::pow((double)a->beta2, t)));
-      LCHK(launch_adam(st, ns.total, w, wbf, g, m, v, a->lr, a->beta1, a->beta2, a->eps, bc1, bc2));
-    }
-    HIPCHK(hipMemcpyAsync(pad.data(), w, ns.total * sizeof(float), hipMemcpyDeviceToHost, st));
-    std::vector<double> hl(nsteps);
-    HIPCHK(hipMemcpyAsync(hl.data(), dl, nsteps * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    net_unpack(ns, pad, params);
-    if (loss_out)
-      for (int s = 0; s < a->steps; ++s) loss_out[s] = hl[s] * inv_count;
+    DevBufs B;
+    TrainBufs T{};
+    T.w = B.get<float>(ns.total);
+    T.wbf = B.get<uint16_t>(ns.total);
+    T.g = B.get<float>(ns.total);
+    T.m = B.get<float>(ns.total);
+    T.v = B.get<float>(ns.total);
+    T.dl = B.get<double>(nsteps);
+    T.ord = B.get<int>((size_t)nsteps * a->batch);
+    train_run(a, ns, T, params, loss_out, grad0_out);
     return LDGS_OK;
   } catch (const Fail& f) {
     g_setup_error = f.msg;
@@ -1410,6 +1512,7 @@ ldgs_status ldgs_learned_train(const ldgs_train_args* a, float* params, double* 
 ldgs_status ldgs_project_kernel(ldgs_ctx* ctx, double* v) {
   try {
     check_ctx(ctx, true);
+    Join join_(ctx);
     if (!v) throw Fail{LDGS_E_ARG, "null argument"};
     project_kernel(ctx, v);
     return LDGS_OK;
@@ -1422,6 +1525,7 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxi
                        int use_learned, ldgs_info* info) {
   try {
     check_ctx(ctx, true);
+    Join join_(ctx);
     if (!b || !x || maxit < 0 || !(tol >= 0)) throw Fail{LDGS_E_ARG, "bad argument"};
     if (use_learned) {
       if (outer != LDGS_IR) throw Fail{LDGS_E_UNSUPPORTED, "the learned correction is used with outer = IR"};
@@ -1583,6 +1687,7 @@ ldgs_status ldgs_profile(ldgs_ctx* ctx, int enable) {
 ldgs_status ldgs_profile_read(ldgs_ctx* ctx, double* total_ms, int64_t* launches) {
   try {
     check_ctx(ctx, true);
+    Join join_(ctx);
     HIPCHK(hipStreamSynchronize(ctx->stream));
     collect_graph_prof(ctx);
     double tot = ctx->prof_acc_ms;
@@ -1609,6 +1714,7 @@ ldgs_status ldgs_profile_read(ldgs_ctx* ctx, double* total_ms, int64_t* launches
 ldgs_status ldgs_level_smooth_colour(ldgs_ctx* ctx, int level, int colour, const double* b, double* x) {
   try {
     check_ctx(ctx, true);
+    Join join_(ctx);
     if (!ctx->s64.built) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
     if (level < 0 || level + 1 >= (int)ctx->levels.size()) throw Fail{LDGS_E_ARG, "level"};
     if (colour < 0 || colour >= ctx->levels[level].ncol || !b || !x) throw Fail{LDGS_E_ARG, "colour"};
@@ -1622,6 +1728,7 @@ ldgs_status ldgs_level_smooth_colour(ldgs_ctx* ctx, int level, int colour, const
 ldgs_status ldgs_level_smooth_colour_f32(ldgs_ctx* ctx, int level, int colour, int vprec, const float* b, float* x) {
   try {
     check_ctx(ctx, true);
+    Join join_(ctx);
     PrecStore<float>* S = vprec == LDGS_V_FP32 ? &ctx->s32 : (vprec == LDGS_V_FP32_BF16BLK ? &ctx->s16 : nullptr);
     if (!S || !S->built) throw Fail{LDGS_E_UNSUPPORTED, "requested float V-cycle not built"};
     if (level < 0 || level + 1 >= (int)ctx->levels.size()) throw Fail{LDGS_E_ARG, "level"};
@@ -1636,6 +1743,7 @@ ldgs_status ldgs_level_smooth_colour_f32(ldgs_ctx* ctx, int level, int colour, i
 ldgs_status ldgs_level_residual_restrict(ldgs_ctx* ctx, int level, const double* b, const double* x, double* rc) {
   try {
     check_ctx(ctx, true);
+    Join join_(ctx);
     if (!ctx->s64.built) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
     if (level < 0 || level + 1 >= (int)ctx->levels.size() || !b || !x || !rc) throw Fail{LDGS_E_ARG, "level"};
     LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream, ctx->small_grid};
@@ -1649,6 +1757,7 @@ ldgs_status ldgs_level_residual_restrict(ldgs_ctx* ctx, int level, const double*
 ldgs_status ldgs_level_prolong_add(ldgs_ctx* ctx, int level, const double* xc, double* x) {
   try {
     check_ctx(ctx, true);
+    Join join_(ctx);
     if (level < 0 || level + 1 >= (int)ctx->levels.size() || !xc || !x) throw Fail{LDGS_E_ARG, "level"};
     LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream, ctx->small_grid};
     LCHK(launch_prolong_add<double>(cfg, ctx->levels[level].n, ctx->tab, xc, x));
@@ -1661,6 +1770,7 @@ ldgs_status ldgs_level_prolong_add(ldgs_ctx* ctx, int level, const double* xc, d
 ldgs_status ldgs_bottom_solve(ldgs_ctx* ctx, const double* b, double* x) {
   try {
     check_ctx(ctx, true);
+    Join join_(ctx);
     if (!b || !x || b == x) throw Fail{LDGS_E_ARG, "b, x must be distinct non-null"};
     bottom_solve<double>(ctx, b, x);
     return LDGS_OK;
@@ -1672,6 +1782,7 @@ ldgs_status ldgs_bottom_solve(ldgs_ctx* ctx, const double* b, double* x) {
 ldgs_status ldgs_level_apply(ldgs_ctx* ctx, int level, const double* x, double* y) {
   try {
     check_ctx(ctx, true);
+    Join join_(ctx);
     if (!ctx->s64.built && level != 0) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
     if (level < 0 || level >= (int)ctx->levels.size() || !x || !y) throw Fail{LDGS_E_ARG, "level"};
     if (level == (int)ctx->levels.size() - 1 && ctx->levels[level].n < 4)

@@ -33,6 +33,8 @@ NET_HIDDEN = 16          # hidden width of the learned correction network
 
 EVAL_FN = C.CFUNCTYPE(None, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int),
                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class Field(C.Structure):
@@ -48,7 +50,8 @@ class ProblemStruct(C.Structure):
                 ("tau_u_inter_C", C.c_double), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("coarsest_n", C.c_int), ("coloring", C.c_int), ("vprec", C.c_int),
                 ("build_precisions", C.c_int), ("diag_scaling", C.c_int), ("host_only", C.c_int),
-                ("hip_stream", C.c_void_p)]
+                ("hip_stream", C.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
+                ("alloc_user", C.c_void_p)]
 
 
 class RhsData(C.Structure):
@@ -86,6 +89,7 @@ _SIGS = {
     "ldgs_vcycle": ([_P, _P, _P]),
     "ldgs_solve": ([_P, _P, _P, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(Info)]),
     "ldgs_set_vprec": ([_P, C.c_int]),
+    "ldgs_graph_count": ([_P, C.POINTER(C.c_int)]),
     "ldgs_set_learned": ([_P, C.POINTER(NetStruct)]),
     "ldgs_learned_correction": ([_P, _P, _P]),
     "ldgs_learned_collect": ([_P, _P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), _P, _P, _D]),
@@ -164,7 +168,28 @@ def _field(obj, dim, keep):
     return f
 
 
-def problem_struct(prob, vprec=V_FP64, build_precisions=0, host_only=False, stream=None, coloring=None):
+def torch_allocator(device=None, stream=None):
+    """(dev_alloc, dev_free) callbacks drawing the context's device storage
+    from PyTorch's caching allocator, so that PyTorch stays the owner of the
+    memory (it shows in torch.cuda.memory_allocated())."""
+    import torch
+
+    def alloc(nbytes, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream)
+        except Exception:          # out of memory: the library reports LDGS_E_NOMEM
+            return None
+
+    def free(ptr, user):
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:          # interpreter shutdown: the process frees the memory
+            pass
+    return ALLOC_FN(alloc), FREE_FN(free)
+
+
+def problem_struct(prob, vprec=V_FP64, build_precisions=0, host_only=False, stream=None, coloring=None,
+                   allocator=None):
     """ldgs_problem from a problem description object (attributes dim, n, p,
     gamma, bc, mu, rho, delta, phases, tau, tau0, tau_u_bdry_C, tau_u_inter_C,
     nu1, nu2, coarsest_n, coloring, diag_scaling).  Returns (struct, keepalive)."""
@@ -192,6 +217,9 @@ def problem_struct(prob, vprec=V_FP64, build_precisions=0, host_only=False, stre
     s.diag_scaling = int(bool(getattr(prob, "diag_scaling", False)))
     s.host_only = int(bool(host_only))
     s.hip_stream = stream
+    if allocator is not None:
+        s.dev_alloc, s.dev_free = allocator
+        keep.extend(allocator)
     return s, keep
 
 
@@ -227,14 +255,24 @@ class Context:
     """One ldgs context (levels, smoother data, bottom solver) on the GPU, or on
     the host only when ``host_only`` is set (setup validation)."""
 
-    def __init__(self, prob, vprec=V_FP64, build_precisions=0, host_only=False, coloring=None):
+    def __init__(self, prob, vprec=V_FP64, build_precisions=0, host_only=False, coloring=None,
+                 torch_memory=True):
+        """The context works on the current torch stream (on the default
+        stream the library uses a stream of its own, joined to the default
+        one at every call).  torch_memory: draw every device allocation of
+        the context from PyTorch's caching allocator."""
         stream = None
+        allocator = None
         self.host_only = host_only
         if not host_only:
             import torch
-            stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+            cur = torch.cuda.current_stream()
+            stream = C.c_void_p(cur.cuda_stream) if cur.cuda_stream else None
+            if torch_memory:
+                allocator = torch_allocator(torch.cuda.current_device(), cur)
         self.prob = prob
-        self._s, self._keep = problem_struct(prob, vprec, build_precisions, host_only, stream, coloring)
+        self._s, self._keep = problem_struct(prob, vprec, build_precisions, host_only, stream, coloring,
+                                             allocator)
         h = C.c_void_p()
         st = _lib.ldgs_setup(C.byref(self._s), C.byref(h))
         if st != OK:
@@ -291,6 +329,12 @@ class Context:
 
     def set_vprec(self, vprec):
         self._check(_lib.ldgs_set_vprec(self._h, vprec))
+
+    def graph_count(self):
+        """V-cycles captured into HIP graphs so far (0: direct launches)."""
+        v = C.c_int()
+        self._check(_lib.ldgs_graph_count(self._h, C.byref(v)))
+        return v.value
 
     def project_kernel(self, v):
         self._check(_lib.ldgs_project_kernel(self._h, _dptr(v)))

@@ -225,3 +225,22 @@ def test_inverse_layout_covers_every_entry():
             assert (seen == 1).all()
             assert offsets == set(range(toff))
             assert toff == TR * 160 + (NTILE - TR) * 256
+
+
+def test_allocator_pair_must_be_complete():
+    """dev_alloc without dev_free (or the reverse) is refused before any
+    allocation."""
+    from paper_1911_05888_amd.ldgs import _lib, problem_struct, E_ARG, ALLOC_FN, FREE_FN
+    calls = []
+    alloc = ALLOC_FN(lambda nbytes, user: calls.append(nbytes) or None)
+    free = FREE_FN(lambda ptr, user: calls.append(ptr))
+    for only in ("alloc", "free"):
+        s, keep = problem_struct(c2_dirichlet_varmu(n=8, p=2), host_only=True)
+        if only == "alloc":
+            s.dev_alloc = alloc
+        else:
+            s.dev_free = free
+        h = C.c_void_p()
+        assert _lib.ldgs_setup(C.byref(s), C.byref(h)) == E_ARG
+        assert h.value is None
+    assert calls == []

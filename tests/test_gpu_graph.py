@@ -59,6 +59,10 @@ def test_graph_replays_match_direct_launches(name, monkeypatch):
             xs.append(seq)
         for it in range(4):
             assert np.array_equal(xs[0][it], xs[1][it]), (name, vp, it)
+    # the graph context did capture its cycles (one graph per precision, for
+    # cycles from a given x); the direct one launched them
+    assert direct.graph_count() == 0
+    assert graph.graph_count() == 3
 
 
 @pytest.mark.parametrize("name", ["c2_n32_p3"])
@@ -79,6 +83,7 @@ def test_graph_solve_history_matches_direct(name, monkeypatch):
     for k in (1, 2, 3):
         assert np.array_equal(hists[0][0], hists[k][0])
         assert np.array_equal(hists[0][1], hists[k][1])
+    assert direct.graph_count() == 0 and graph.graph_count() == 1
 
 
 def test_graph_profiling_counts_timed_passes(monkeypatch):
@@ -90,6 +95,7 @@ def test_graph_profiling_counts_timed_passes(monkeypatch):
     prob = CASES["c2_n32_p3"]()
     direct, graph = _contexts(prob, monkeypatch)
     counts = []
+    assert graph.graph_count() == 0
     for ctx in (direct, graph):
         ctx.set_vprec(V_FP32)
         b = ctx.assemble_rhs(prob.rhs_source())
@@ -104,6 +110,10 @@ def test_graph_profiling_counts_timed_passes(monkeypatch):
     # that starts from the zero guess is not timed, every second one of the
     # other 5 is (a graph times the same 3 sweeps, 12 passes, in every
     # replay; direct launches alternate 3 and 2 sweeps)
-    for n, iters in counts:
-        assert n % 4 == 0 and 8 * iters <= n <= 12 * iters, (n, iters)
+    n, iters = counts[0]
+    assert n % 4 == 0 and 8 * iters <= n <= 12 * iters, (n, iters)
+    n, iters = counts[1]
+    assert n == 12 * iters, (n, iters)
     assert counts[0][1] == counts[1][1]
+    # one graph for the untimed cycles, one for those timed every second sweep
+    assert direct.graph_count() == 0 and graph.graph_count() == 2
