@@ -363,7 +363,9 @@ ldgs_status ldgs_bottom_info(ldgs_ctx* ctx, int64_t* nc, double* pinv_host, doub
  * and queue work, so a stride above 1 keeps the timed solve close to an
  * untimed one.  ldgs_profile_read synchronises, returns the summed time (ms)
  * and the number of colour passes it covers since the last read, and clears
- * them. */
+ * them.  While timing is on, V-cycles are launched directly instead of
+ * being replayed from graphs (events recorded inside a captured graph cannot
+ * be timed from the host). */
 ldgs_status ldgs_profile(ldgs_ctx* ctx, int enable);
 ldgs_status ldgs_profile_read(ldgs_ctx* ctx, double* total_ms, int64_t* launches);
 

@@ -133,29 +133,19 @@ struct ldgs_ctx {
   // null stream cannot be captured into a graph); calls order it after the
   // caller's null-stream work and the null stream after it (join events)
   hipEvent_t join_in = nullptr, join_out = nullptr;
-  // captured V-cycles, one per (precision, zero guess, timing stride); the
-  // event pairs recorded inside a graph are read after the next host
-  // synchronisation (they are re-recorded at every replay)
+  // captured V-cycles, one per (precision, zero guess); cycles timed with
+  // event pairs are launched directly
   struct CycleGraph {
     int vp;
     bool zero_x;
-    int prof;
     hipGraphExec_t exec;
-    std::vector<ProfEv> ev;
   };
   std::vector<CycleGraph> graphs;
-  bool capturing = false;
-  std::vector<hipEvent_t> cap_pool;                         // events owned by graphs
-  std::vector<ProfEv> cap_ev;                                // pairs recorded during a capture
-  const std::vector<ProfEv>* prof_pending = nullptr;
-  double prof_acc_ms = 0.0;
-  int64_t prof_acc_n = 0;
   ~ldgs_ctx() {
     // nothing may still use the storage when it goes back to its owner (a
     // caching allocator hands it out again at once)
     if (!host_only) (void)hipStreamSynchronize(stream);
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
-    for (hipEvent_t e : cap_pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : allocs) {
       if (P.dev_free) P.dev_free(p, P.alloc_user);
@@ -693,12 +683,6 @@ ldgs_status handle(ldgs_ctx* c, const Fail& f) {
 // the V-cycle (Algorithm 1) on one precision store
 // ---------------------------------------------------------------------------
 hipEvent_t next_event(ldgs_ctx* c) {
-  if (c->capturing) {
-    hipEvent_t e;
-    HIPCHK(hipEventCreate(&e));
-    c->cap_pool.push_back(e);
-    return e;
-  }
   if (c->ev_used == c->ev_pool.size()) {
     hipEvent_t e;
     HIPCHK(hipEventCreate(&e));
@@ -782,7 +766,7 @@ void smooth(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x, int sweeps, b
     }
     if (timed) {
       HIPCHK(hipEventRecord(e1, c->stream));
-      (c->capturing ? c->cap_ev : c->prof_ev).push_back({e0, e1, ncol});
+      c->prof_ev.push_back({e0, e1, ncol});
     }
   }
 }
@@ -823,22 +807,6 @@ void cycle(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x, bool zero_x) {
   smooth(c, S, l, b, x, c->P.nu2);
 }
 
-// adds the timed passes of the last replayed graph (complete after a host
-// synchronisation, or waited for here) to the profile totals
-void collect_graph_prof(ldgs_ctx* c) {
-  if (!c->prof_pending) return;
-  const auto& ev = *c->prof_pending;
-  c->prof_pending = nullptr;
-  if (ev.empty()) return;
-  HIPCHK(hipEventSynchronize(ev.back().e1));
-  for (const auto& pr : ev) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, pr.e0, pr.e1));
-    c->prof_acc_ms += ms;
-    c->prof_acc_n += pr.passes;
-  }
-}
-
 // One V-cycle on the context's finest work vectors, replayed from a captured
 // graph (captured on first use: the launch sequence and every pointer are
 // fixed after setup).  A replay takes the host about half the time of the
@@ -847,14 +815,15 @@ void collect_graph_prof(ldgs_ctx* c) {
 // launches for the context's life.
 template <typename T>
 void run_cycle(ldgs_ctx* c, PrecStore<T>& S, int vp, T* b, T* x, bool zero_x) {
-  if (!c->use_graph) {
+  // timed cycles are launched directly: events recorded inside a captured
+  // graph cannot be timed from the host
+  if (!c->use_graph || c->prof > 0) {
     cycle<T>(c, S, 0, b, x, zero_x);
     return;
   }
-  collect_graph_prof(c);   // before the graph list can grow (it holds the pending events)
   ldgs_ctx::CycleGraph* g = nullptr;
   for (auto& e : c->graphs)
-    if (e.vp == vp && e.zero_x == zero_x && e.prof == c->prof) g = &e;
+    if (e.vp == vp && e.zero_x == zero_x) g = &e;
   if (!g) {
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -863,18 +832,14 @@ void run_cycle(ldgs_ctx* c, PrecStore<T>& S, int vp, T* b, T* x, bool zero_x) {
       cycle<T>(c, S, 0, b, x, zero_x);
       return;
     }
-    c->capturing = true;
-    c->cap_ev.clear();
     try {
       cycle<T>(c, S, 0, b, x, zero_x);
     } catch (...) {
-      c->capturing = false;
       (void)hipStreamEndCapture(c->stream, &graph);
       if (graph) (void)hipGraphDestroy(graph);
       (void)hipGetLastError();
       throw;
     }
-    c->capturing = false;
     hipGraphExec_t exec = nullptr;
     const bool ok = hipStreamEndCapture(c->stream, &graph) == hipSuccess && graph &&
                     hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
@@ -885,11 +850,10 @@ void run_cycle(ldgs_ctx* c, PrecStore<T>& S, int vp, T* b, T* x, bool zero_x) {
       cycle<T>(c, S, 0, b, x, zero_x);
       return;
     }
-    c->graphs.push_back({vp, zero_x, c->prof, exec, c->cap_ev});
+    c->graphs.push_back({vp, zero_x, exec});
     g = &c->graphs.back();
   }
   HIPCHK(hipGraphLaunch(g->exec, c->stream));
-  c->prof_pending = &g->ev;
 }
 
 const double* dscale0(ldgs_ctx* c) { return c->P.diag_scaling ? c->d_dscale0 : nullptr; }
@@ -926,7 +890,6 @@ double host_sum_partials(ldgs_ctx* c, int nblk) {
   std::vector<double> h(nblk);
   HIPCHK(hipMemcpyAsync(h.data(), c->w_part, nblk * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  collect_graph_prof(c);
   double s = 0.0;
   for (double v : h) s += v;
   return s;
@@ -1677,9 +1640,6 @@ ldgs_status ldgs_profile(ldgs_ctx* ctx, int enable) {
   ctx->prof = enable > 0 ? enable : 0;
   ctx->prof_count = 0;
   ctx->prof_ev.clear();
-  ctx->prof_pending = nullptr;
-  ctx->prof_acc_ms = 0.0;
-  ctx->prof_acc_n = 0;
   ctx->ev_used = 0;
   return LDGS_OK;
 }
@@ -1689,9 +1649,8 @@ ldgs_status ldgs_profile_read(ldgs_ctx* ctx, double* total_ms, int64_t* launches
     check_ctx(ctx, true);
     Join join_(ctx);
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    collect_graph_prof(ctx);
-    double tot = ctx->prof_acc_ms;
-    int64_t n = ctx->prof_acc_n;
+    double tot = 0.0;
+    int64_t n = 0;
     for (auto& pr : ctx->prof_ev) {
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, pr.e0, pr.e1));
@@ -1702,8 +1661,6 @@ ldgs_status ldgs_profile_read(ldgs_ctx* ctx, double* total_ms, int64_t* launches
     if (launches) *launches = n;
     ctx->prof_ev.clear();
     ctx->ev_used = 0;
-    ctx->prof_acc_ms = 0.0;
-    ctx->prof_acc_n = 0;
     return LDGS_OK;
   } catch (const Fail& f) {
     return handle(ctx, f);

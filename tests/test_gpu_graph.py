@@ -87,9 +87,9 @@ def test_graph_solve_history_matches_direct(name, monkeypatch):
 
 
 def test_graph_profiling_counts_timed_passes(monkeypatch):
-    """Event pairs recorded inside a captured cycle are read back after the
-    solve's synchronisations: the profile counts the timed passes of every
-    replay."""
+    """Timed cycles are launched directly (events inside a captured graph
+    cannot be timed): with timing on, a graph context counts the same timed
+    passes as a direct one and captures no further graph."""
     import torch
     from paper_1911_05888_amd import V_FP32, IR
     prob = CASES["c2_n32_p3"]()
@@ -108,12 +108,9 @@ def test_graph_profiling_counts_timed_passes(monkeypatch):
         counts.append((n, info["iters"]))
     # 6 sweeps of 4 colour passes per cycle on the finest level; the sweep
     # that starts from the zero guess is not timed, every second one of the
-    # other 5 is (a graph times the same 3 sweeps, 12 passes, in every
-    # replay; direct launches alternate 3 and 2 sweeps)
-    n, iters = counts[0]
-    assert n % 4 == 0 and 8 * iters <= n <= 12 * iters, (n, iters)
-    n, iters = counts[1]
-    assert n == 12 * iters, (n, iters)
-    assert counts[0][1] == counts[1][1]
-    # one graph for the untimed cycles, one for those timed every second sweep
-    assert direct.graph_count() == 0 and graph.graph_count() == 2
+    # other 5 is (3 and 2 sweeps in alternate cycles)
+    for n, iters in counts:
+        assert n % 4 == 0 and 8 * iters <= n <= 12 * iters, (n, iters)
+    assert counts[0] == counts[1]
+    # only the untimed cycles were captured
+    assert direct.graph_count() == 0 and graph.graph_count() == 1

@@ -16,7 +16,7 @@ def _inverse_entries(nb):
 
 def test_context_storage_is_owned_by_torch():
     import torch
-    from paper_1911_05888_amd import Context, V_FP32, V_FP64
+    from paper_1911_05888_amd import Context, V_FP32, V_FP64, IR
     print("[memory] torch-owned context storage", flush=True)
     prob = c2_dirichlet_varmu(n=64, p=3)
     torch.cuda.synchronize()
@@ -28,7 +28,7 @@ def test_context_storage_is_owned_by_torch():
     assert grown >= need, (grown, need)
     b = ctx.assemble_rhs(prob.rhs_source())
     x = torch.zeros_like(b)
-    st, info = ctx.solve(b, x, tol=1e-10, maxit=40)
+    st, info = ctx.solve(b, x, tol=1e-10, maxit=40, outer=IR)
     assert st == 0
     ctx.close()
     del b, x
@@ -38,7 +38,7 @@ def test_context_storage_is_owned_by_torch():
 
 def test_library_allocation_leaves_torch_untouched():
     import torch
-    from paper_1911_05888_amd import Context, V_FP32
+    from paper_1911_05888_amd import Context, V_FP32, IR
     prob = c2_dirichlet_varmu(n=32, p=3)
     torch.cuda.synchronize()
     base = torch.cuda.memory_allocated()
@@ -46,6 +46,6 @@ def test_library_allocation_leaves_torch_untouched():
     assert torch.cuda.memory_allocated() == base
     b = ctx.assemble_rhs(prob.rhs_source())
     x = torch.zeros_like(b)
-    st, info = ctx.solve(b, x, tol=1e-10, maxit=40)
+    st, info = ctx.solve(b, x, tol=1e-10, maxit=40, outer=IR)
     assert st == 0
     ctx.close()
