@@ -291,6 +291,28 @@ typedef struct {
  * Errors are reported through ldgs_last_error(NULL). */
 ldgs_status ldgs_learned_train(const ldgs_train_args* args, float* params, double* loss_out, float* grad0_out);
 
+/* Size of the fixed device workspace of ldgs_learned_train_noalloc (per GPU). */
+#define LDGS_TRAIN_WORKSPACE_BYTES ((size_t)4 << 20)
+
+/* ldgs_learned_train for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation on the same kernels, with every device
+ * buffer of the run (FP32 parameters and their BF16 copy, gradient, Adam
+ * moments, per-step losses, batch order) carved from a fixed workspace of
+ * LDGS_TRAIN_WORKSPACE_BYTES that the library holds on each GPU it runs on
+ * until the process ends.  It calls no device allocator.  The caller still
+ * passes the crops (device) and the host arrays of ldgs_learned_train.  A run
+ * needs about 5 * 4 * (padded parameter count) bytes plus
+ * 4 * steps * batch + 8 * steps; one that needs more than the workspace
+ * returns LDGS_E_ARG before any device work.  Every call re-initialises what
+ * it uses (the gradient, moments and losses are cleared by kernels), so
+ * results do not depend on earlier calls.  All calls on one GPU share its
+ * workspace: calls that overlap in time on one GPU (several host threads, or
+ * streams that run concurrently) race and must be serialised by the caller.
+ * Synchronises args->hip_stream.  Errors through ldgs_last_error(NULL). */
+ldgs_status ldgs_learned_train_noalloc(const ldgs_train_args* args, float* params, double* loss_out,
+                                       float* grad0_out);
+
 /* Remove from v its components along the trivial kernel (constant pressure,
  * and constant velocity for periodic steady problems), in place. */
 ldgs_status ldgs_project_kernel(ldgs_ctx* ctx, double* v_dev);

@@ -1472,6 +1472,37 @@ ldgs_status ldgs_learned_train(const ldgs_train_args* a, float* params, double* 
   }
 }
 
+ldgs_status ldgs_learned_train_noalloc(const ldgs_train_args* a, float* params, double* loss_out, float* grad0_out) {
+  try {
+    const NetShape ns = check_train_args(a, params);
+    const int64_t nsteps = a->steps > 0 ? a->steps : 1;
+    // the run's buffers, each at a 256-byte boundary of the workspace
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      const size_t o = off;
+      off += (bytes + 255) & ~(size_t)255;
+      return o;
+    };
+    const size_t ow = take(ns.total * sizeof(float)), obf = take(ns.total * sizeof(uint16_t));
+    const size_t og = take(ns.total * sizeof(float)), om = take(ns.total * sizeof(float));
+    const size_t ov = take(ns.total * sizeof(float)), odl = take(nsteps * sizeof(double));
+    const size_t oord = take((size_t)nsteps * a->batch * sizeof(int));
+    if (off > LDGS_TRAIN_WORKSPACE_BYTES)
+      throw Fail{LDGS_E_ARG, "the run needs " + std::to_string(off) + " bytes of workspace, more than the " +
+                                 std::to_string(LDGS_TRAIN_WORKSPACE_BYTES) + " available (fewer steps x batch)"};
+    void* base = nullptr;
+    if (train_workspace(&base) != 0) throw Fail{LDGS_E_HIP, "address of the training workspace not available"};
+    char* b = (char*)base;
+    const TrainBufs T{(float*)(b + ow), (uint16_t*)(b + obf), (float*)(b + og), (float*)(b + om),
+                      (float*)(b + ov), (double*)(b + odl), (int*)(b + oord)};
+    train_run(a, ns, T, params, loss_out, grad0_out);
+    return LDGS_OK;
+  } catch (const Fail& f) {
+    g_setup_error = f.msg;
+    return f.st;
+  }
+}
+
 ldgs_status ldgs_project_kernel(ldgs_ctx* ctx, double* v) {
   try {
     check_ctx(ctx, true);

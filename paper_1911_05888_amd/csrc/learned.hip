@@ -9,6 +9,8 @@
 //   result D[4g + j][r], j < 4 (both shapes)
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <cmath>
 #include <type_traits>
 
@@ -668,6 +670,31 @@ int launch_adam(void* stream, int64_t n, float* master, uint16_t* wbf, const flo
 int launch_to_bf16(void* stream, int64_t n, const float* src, uint16_t* dst) {
   hipLaunchKernelGGL(k_to_bf16, dim3(blocks(n, 256, 1 << 30)), dim3(256), 0, (hipStream_t)stream, n, src, dst);
   return ok();
+}
+
+// Fixed workspace of the training entry point that allocates nothing: one
+// copy per GPU in device global memory, alive until the process ends.  On
+// the host the symbol names a host-side stand-in, never device memory: host
+// code uses only the address hipGetSymbolAddress returns on each device.
+static __device__ __align__(256) unsigned char scratch[LDGS_TRAIN_WORKSPACE_BYTES];
+
+int train_workspace(void** ptr) {
+  constexpr int MAXDEV = 64;
+  static std::mutex mu;
+  static void* addr[MAXDEV] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAXDEV) return 1;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return 1;
+    }
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return 0;
 }
 
 template int launch_field_sumsq<float>(void*, int64_t, int, int, const float*, const double*, double*, int, double*);

@@ -16,7 +16,10 @@
 //   offsets): W1 [H][K1P] | b1 [H] | W2 [H][H] | b2 [H] | W3 [NOUT][H] | b3 [NOUT]
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
+
+#include "../../include/ldgs.h"
 
 namespace ldgs {
 
@@ -68,5 +71,9 @@ int launch_adam(void* stream, int64_t n, float* master, uint16_t* wbf, const flo
                 float lr, float beta1, float beta2, float eps, float bc1, float bc2);
 
 int launch_to_bf16(void* stream, int64_t n, const float* src, uint16_t* dst);
+
+// Device address, on the current GPU, of the fixed training workspace of
+// LDGS_TRAIN_WORKSPACE_BYTES (looked up once per GPU); 0 on success.
+int train_workspace(void** ptr);
 
 }  // namespace ldgs

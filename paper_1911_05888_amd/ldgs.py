@@ -30,6 +30,7 @@ STATIONARY, IR, FGMRES = 0, 1, 2
 FIELD_CONST, FIELD_SINSIN, FIELD_LOGNORMAL_RFF, FIELD_PHASE_CONST, FIELD_CALLBACK = range(5)
 LEVELSET_NONE, LEVELSET_BOX = 0, 1
 NET_HIDDEN = 16          # hidden width of the learned correction network
+TRAIN_WORKSPACE_BYTES = 4 << 20   # workspace of ldgs_learned_train_noalloc (LDGS_TRAIN_WORKSPACE_BYTES)
 
 EVAL_FN = C.CFUNCTYPE(None, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int),
                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p)
@@ -94,6 +95,7 @@ _SIGS = {
     "ldgs_learned_correction": ([_P, _P, _P]),
     "ldgs_learned_collect": ([_P, _P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), _P, _P, _D]),
     "ldgs_learned_train": ([C.POINTER(TrainArgs), C.POINTER(C.c_float), _D, C.POINTER(C.c_float)]),
+    "ldgs_learned_train_noalloc": ([C.POINTER(TrainArgs), C.POINTER(C.c_float), _D, C.POINTER(C.c_float)]),
     "ldgs_project_kernel": ([_P, _P]),
     "ldgs_level_info": ([_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "ldgs_level_shared_inverse": ([_P, C.c_int, C.POINTER(C.c_int)]),
@@ -457,9 +459,11 @@ def net_nparams(dim, degree, hidden=NET_HIDDEN):
 
 
 def learned_train(dim, degree, crop, ncrops, feat, targ, c_vel, c_pre, params, order, lr=1e-3,
-                  beta1=0.9, beta2=0.999, eps=1e-8, want_grad0=False, hidden=NET_HIDDEN):
+                  beta1=0.9, beta2=0.999, eps=1e-8, want_grad0=False, hidden=NET_HIDDEN, noalloc=False):
     """Runs len(order) Adam steps (order: int array (steps, batch) of crop
-    indices) on device crops; returns (params, losses, grad0 or None)."""
+    indices) on device crops; returns (params, losses, grad0 or None).
+    noalloc: use the entry point that allocates no device memory (fixed
+    per-GPU workspace of TRAIN_WORKSPACE_BYTES)."""
     import torch
     p = np.array(params, dtype=np.float32, copy=True)
     org = np.ascontiguousarray(order, dtype=np.int32)
@@ -471,8 +475,9 @@ def learned_train(dim, degree, crop, ncrops, feat, targ, c_vel, c_pre, params, o
                   org.ctypes.data_as(C.POINTER(C.c_int)), lr, beta1, beta2, eps)
     losses = np.zeros(max(steps, 1))
     g0 = np.zeros_like(p) if want_grad0 else None
-    st = _lib.ldgs_learned_train(C.byref(a), p.ctypes.data_as(C.POINTER(C.c_float)), losses.ctypes.data_as(_D),
-                                 g0.ctypes.data_as(C.POINTER(C.c_float)) if want_grad0 else None)
+    fn = _lib.ldgs_learned_train_noalloc if noalloc else _lib.ldgs_learned_train
+    st = fn(C.byref(a), p.ctypes.data_as(C.POINTER(C.c_float)), losses.ctypes.data_as(_D),
+            g0.ctypes.data_as(C.POINTER(C.c_float)) if want_grad0 else None)
     if st != OK:
         raise LdgsError(st, _lib.ldgs_last_error(None).decode())
     return p, losses[:steps], g0
