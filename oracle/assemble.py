@@ -75,6 +75,12 @@ def _lam(mu_m, mu_p):
     return np.where(mu_m < mu_p, 0.0, np.where(mu_m > mu_p, 1.0, 0.5))
 
 
+def interphase_mu(mu_m, mu_p):
+    """Viscosity that scales the interphase velocity penalty: the smaller of
+    the two sides (appendix on penalty parameters)."""
+    return np.minimum(mu_m, mu_p)
+
+
 class _COO:
     def __init__(self, size, nq):
         self.size, self.nq = size, nq
@@ -266,7 +272,7 @@ class FineAssembly:
                 coo.add(mi, mi, self._fblock(k, tau_b, Tm[sel], Tm[sel]))
             sel = fd["type"] == 1
             if sel.any():
-                tau_i = prob.tau_u_inter_C * prob.p * np.minimum(fd["mu_m"][sel], fd["mu_p"][sel]) / g.h
+                tau_i = prob.tau_u_inter_C * prob.p * interphase_mu(fd["mu_m"][sel], fd["mu_p"][sel]) / g.h
                 self._jump_jump(coo, k, fd, sel, tau_i, Tm, Tp)
         return coo.csr()
 

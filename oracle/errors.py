@@ -25,7 +25,7 @@ def solution_errors(prob, x, k0):
     pe = prob.exact.pressure(X.reshape(-1, d), chi).reshape(NE, Q)
     err = np.concatenate([ue, pe[..., None]], axis=2) - uh
     wq = w[None, :] * g.h ** d
-    vol = wq.sum()
+    vol = NE * wq.sum()                                      # measure of the domain
     fields = [d] if k0 == 1 else list(range(d + 1))
     for f in fields:                                         # remove constants
         err[..., f] -= (err[..., f] * wq).sum() / vol

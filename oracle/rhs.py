@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import assemble as _asm
 from .assemble import FineAssembly
 
 
@@ -84,7 +85,7 @@ def assemble_rhs(prob, ops):
             ss = s[sel][:, None]
             hij = sig[..., :, k] * ss[..., None]
             lam = fd["lam"][sel]
-            tau_i = prob.tau_u_inter_C * prob.p * np.minimum(fd["mu_m"][sel], fd["mu_p"][sel]) / g.h
+            tau_i = prob.tau_u_inter_C * prob.p * _asm.interphase_mu(fd["mu_m"][sel], fd["mu_p"][sel]) / g.h
             mi, pl = fd["minus"][sel], fd["plus"][sel]
             for i in range(d):
                 Jg[i, k] += _scatter(S, nq, mi, np.einsum("q,fq,fqa->fa", w, (1 - lam) * gij[..., i] * ss, Tm[sel]))

@@ -199,13 +199,15 @@ class ExactSolution:
 
     ``u[chi]`` is a list of d SinProd components and ``p[chi]`` a SinProd, for
     each phase chi present.  ``forcing`` evaluates eq. (govern1):
-    f = -div(mu (grad u + gamma grad u^T)) + grad p and f_div = -div u.
+    f = -div(mu (grad u + gamma grad u^T)) + grad p and f_div = -div u, with
+    the term (rho / delta) u of eq. (timedep1) added when rho_delta > 0.
     """
     dim: int
     gamma: int
     mu: object
     u: dict
     p: dict
+    rho_delta: float = 0.0      # rho / delta of eq. (timedep1) (constant rho); 0: steady
 
     def _phases(self, chi, n):
         if chi is None:
@@ -255,7 +257,7 @@ class ExactSolution:
                 for j in range(d):
                     acc += dmu[:, j] * (gu[:, i, j] + self.gamma * gu[:, j, i])
                     acc += mu * (Hu[:, i, j, j] + self.gamma * Hu[:, j, i, j])
-                out[:, i] = -acc + gp[:, i]
+                out[:, i] = -acc + gp[:, i] + self.rho_delta * np.stack([q.value(y) for q in self.u[c]], axis=1)[:, i]
             return out
         return self._per_phase(x, chi, f)
 
