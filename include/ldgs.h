@@ -220,6 +220,20 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b_dev, double* x_dev, double tol, 
  * capture failed, in which case the cycles are launched directly. */
 ldgs_status ldgs_graph_count(const ldgs_ctx* ctx, int* n_graphs);
 
+/* Convergence rate rho of eq. (rho) (section 4): GMRES without restarts,
+ * left-preconditioned by V = one V-cycle from a zero guess in the context's
+ * precision, on V A x = V b with b = 0, from the caller's x0 (FP64 device
+ * vector, not modified), until ||V A x_k|| <= reduction ||V A x_0|| (the
+ * paper uses 1e-8) or maxit (<= 1000) iterations; then
+ *   rho = (||V A x_n|| / ||V A x_0||)^(1/n),  n iterations.
+ * The Arnoldi basis (maxit + 2 vectors of N FP64 entries) is allocated on
+ * first use and kept.  history (host, may be NULL) receives the ratios
+ * ||V A x_k|| / ||V A x_0||, k = 0..n, up to history_cap entries.  Returns
+ * LDGS_E_NOT_CONVERGED (rho and iters still set) if the reduction was not
+ * reached.  Synchronises. */
+ldgs_status ldgs_gmres_rho(ldgs_ctx* ctx, const double* x0_dev, double reduction, int maxit, double* rho,
+                           int* iters, double* history, int history_cap);
+
 /* Switch the precision used by ldgs_vcycle / ldgs_solve among those built. */
 ldgs_status ldgs_set_vprec(ldgs_ctx* ctx, int vprec);
 

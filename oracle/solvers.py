@@ -118,9 +118,11 @@ class Solver:
             x = x + np.stack(Z[:j_done], axis=1) @ y
         return x, np.array(hist)
 
-    def rho_metric(self, seed=0, reduction=1e-8, maxit=100):
+    def rho_metric(self, seed=0, reduction=1e-8, maxit=100, return_history=False):
         """eq. (rho): average reduction per iteration of the left-preconditioned
-        GMRES residual ||V A x_n - V b|| with b = 0 and a random x_0."""
+        GMRES residual ||V A x_n - V b|| with b = 0 and a random x_0 (x_0 from
+        PCG64(seed), kernel removed).  With return_history, also the ratios
+        ||V A x_k|| / ||V A x_0||, k = 0..n."""
         rng = np.random.Generator(np.random.PCG64(seed))
         x0 = self.hier.project_kernel(rng.standard_normal(self.A.shape[0]))
 
@@ -146,4 +148,7 @@ class Solver:
             if res[-1] <= reduction * beta:
                 break
         n = len(res) - 1
-        return float(np.exp(np.log(res[-1] / res[0]) / n)), n
+        rho = float(np.exp(np.log(res[-1] / res[0]) / n))
+        if return_history:
+            return rho, n, np.array(res) / res[0]
+        return rho, n

@@ -1665,6 +1665,71 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxi
   }
 }
 
+// Convergence rate of eq. (rho): GMRES, left-preconditioned by one V-cycle
+// from zero (the linear operator V), on V A x = V b with b = 0 from x0,
+// without restarts: modified Gram-Schmidt Arnoldi on w = V A v in FP64,
+// Givens rotations for the residual norms ||V A x_k|| (section 4).
+ldgs_status ldgs_gmres_rho(ldgs_ctx* ctx, const double* x0, double reduction, int maxit, double* rho, int* iters,
+                           double* history, int history_cap) {
+  try {
+    check_ctx(ctx, true);
+    Join join_(ctx);
+    if (!x0 || !rho || maxit < 1 || maxit > 1000 || !(reduction > 0.0 && reduction < 1.0))
+      throw Fail{LDGS_E_ARG, "bad argument"};
+    const int64_t N = ctx->ndof();
+    while ((int)ctx->kry.size() < maxit + 2) ctx->kry.push_back(dalloc<double>(ctx, N));
+    double* const* V = ctx->kry.data();
+    double* Av = ctx->kry[maxit + 1];            // A v, the V-cycle's input
+    LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream, ctx->small_grid};
+    auto VA = [&](const double* v, double* out) {
+      LCHK(launch_residual<double>(cfg, ctx->s64.lv[0].unscaled, ctx->tab, nullptr, v, Av, 1));
+      vcycle_user(ctx, ctx->vprec, Av, out, true);
+    };
+    // r0 = V (b - A x0) = -V A x0
+    VA(x0, V[0]);
+    const double beta = std::sqrt(dot(ctx, V[0], V[0]));
+    if (!(beta > 0.0) || !std::isfinite(beta)) throw Fail{LDGS_E_NONFINITE, "initial preconditioned residual"};
+    LCHK(launch_scale_copy(ctx->stream, N, -1.0 / beta, V[0], V[0]));
+    const int m = maxit;
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0), res(1, 1.0);
+    g[0] = beta;
+    int n = 0;
+    for (int j = 0; j < m; ++j) {
+      VA(V[j], V[j + 1]);
+      for (int i = 0; i <= j; ++i) {
+        const double hij = dot(ctx, V[j + 1], V[i]);
+        H[(size_t)i * m + j] = hij;
+        LCHK(launch_axpy(ctx->stream, N, -hij, V[i], V[j + 1]));
+      }
+      const double hn = std::sqrt(dot(ctx, V[j + 1], V[j + 1]));
+      H[(size_t)(j + 1) * m + j] = hn;
+      if (hn > 0.0) LCHK(launch_scale_copy(ctx->stream, N, 1.0 / hn, V[j + 1], V[j + 1]));
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
+        H[(size_t)(i + 1) * m + j] = -sn[i] * H[(size_t)i * m + j] + cs[i] * H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = t;
+      }
+      const double den = std::hypot(H[(size_t)j * m + j], H[(size_t)(j + 1) * m + j]);
+      cs[j] = H[(size_t)j * m + j] / den;
+      sn[j] = H[(size_t)(j + 1) * m + j] / den;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      n = j + 1;
+      const double rel = std::fabs(g[j + 1]) / beta;
+      res.push_back(rel);
+      if (!std::isfinite(rel)) throw Fail{LDGS_E_NONFINITE, "GMRES residual"};
+      if (rel <= reduction || hn == 0.0) break;
+    }
+    *rho = std::exp(std::log(res.back()) / n);
+    if (iters) *iters = n;
+    if (history)
+      for (int k = 0; k < (int)res.size() && k < history_cap; ++k) history[k] = res[k];
+    return res.back() <= reduction ? LDGS_OK : LDGS_E_NOT_CONVERGED;
+  } catch (const Fail& f) {
+    return handle(ctx, f);
+  }
+}
+
 // ---- profiling -------------------------------------------------------------
 ldgs_status ldgs_profile(ldgs_ctx* ctx, int enable) {
   if (!ctx) return LDGS_E_ARG;

@@ -1307,7 +1307,9 @@ __global__ __launch_bounds__(SU_THREADS) void k_shared_update(int nelems, const 
     const int base = tile * C::TE;
     const int cnt = min(C::TE, nelems - base);
     __syncthreads();
-    if (tid < C::TE) Eo[tid] = tid < cnt ? elems[base + tid] * NB : -1;
+    // (a tile can hold more elements than the work-group has threads:
+    // 21 groups x 16 = 336 for NB = 12)
+    for (int i = tid; i < C::TE; i += SU_THREADS) Eo[i] = i < cnt ? elems[base + i] * NB : -1;
     __syncthreads();
     // all loads of the tile issued before any is stored (unrolled; masked
     // loads read r[0] and are discarded)

@@ -18,6 +18,10 @@ LIB_PATH = os.path.join(_HERE, "libldgs.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libldgs.so not found at {LIB_PATH}: build it with "
                       "`python -c 'import __graft_entry__ as g; g.build()'`")
+# PyTorch first: the library then binds to the HIP runtime PyTorch loads, so
+# that both share one runtime (streams, allocations) whatever the caller
+# imports first
+import torch  # noqa: E402,F401
 _lib = C.CDLL(LIB_PATH)
 
 # status codes
@@ -91,6 +95,7 @@ _SIGS = {
     "ldgs_solve": ([_P, _P, _P, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(Info)]),
     "ldgs_set_vprec": ([_P, C.c_int]),
     "ldgs_graph_count": ([_P, C.POINTER(C.c_int)]),
+    "ldgs_gmres_rho": ([_P, _P, C.c_double, C.c_int, _D, C.POINTER(C.c_int), _D, C.c_int]),
     "ldgs_set_learned": ([_P, C.POINTER(NetStruct)]),
     "ldgs_learned_correction": ([_P, _P, _P]),
     "ldgs_learned_collect": ([_P, _P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), _P, _P, _D]),
@@ -331,6 +336,18 @@ class Context:
 
     def set_vprec(self, vprec):
         self._check(_lib.ldgs_set_vprec(self._h, vprec))
+
+    def gmres_rho(self, x0, reduction=1e-8, maxit=200):
+        """rho of eq. (rho) from the initial guess x0 (device FP64, b = 0).
+        Returns (rho, iterations, history of ||V A x_k|| / ||V A x_0||,
+        converged)."""
+        rho, its = C.c_double(), C.c_int()
+        hist = np.zeros(maxit + 1)
+        st = _lib.ldgs_gmres_rho(self._h, _dptr(x0), reduction, maxit, C.byref(rho), C.byref(its),
+                                 hist.ctypes.data_as(_D), hist.size)
+        if st not in (OK, E_NOT_CONVERGED):
+            self._check(st)
+        return rho.value, its.value, hist[:its.value + 1].copy(), st == OK
 
     def graph_count(self):
         """V-cycles captured into HIP graphs so far (0: direct launches)."""

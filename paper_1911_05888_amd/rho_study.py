@@ -1,0 +1,108 @@
+"""Convergence-rate studies of section 4 and 5 on the GPU.
+
+rho is the metric of eq. (rho): GMRES left-preconditioned by one V(3,3)
+cycle, b = 0, a random initial guess (PCG64 seed 0, kernel removed), run to a
+1e8 reduction of the preconditioned residual.  Every study prints one
+markdown table; run as
+
+    python -m paper_1911_05888_amd.rho_study valley      # tau valley vs Table 2
+    python -m paper_1911_05888_amd.rho_study refine      # rho against n (section 5.1)
+    python -m paper_1911_05888_amd.rho_study unsteady    # tau_0 of eq. (taugeneral) at Re ~ 1e4
+    python -m paper_1911_05888_amd.rho_study viscosity   # smooth and log-normal viscosity, 3D
+
+The problem data come from ``synth`` (closed forms and seeded fields).
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+
+def rho_of(prob, seed=0, maxit=200, vprec=0):
+    import torch
+    from . import Context
+    ctx = Context(prob, vprec=vprec)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x0 = torch.tensor(rng.standard_normal(ctx.ndof), device="cuda")
+    ctx.project_kernel(x0)
+    rho, its, _, ok = ctx.gmres_rho(x0, maxit=maxit)
+    ctx.close()
+    return rho, its, ok
+
+
+def valley(n=64):
+    from synth import Problem
+    from synth.problems import tau_table
+    print(f"| form | p | Table 1 tau | argmin tau (n={n}) | min rho | rho at the Table 1 tau |")
+    print("|---|---|---|---|---|---|")
+    for form, gamma, p in (("standard", 0, 1), ("standard", 0, 2), ("standard", 0, 3),
+                           ("viscous", 1, 1), ("viscous", 1, 2), ("viscous", 1, 3)):
+        t1 = tau_table(gamma, 2, p)
+        taus = t1 * 2.0 ** (np.arange(-8, 9) / 4)
+        rhos = [rho_of(Problem(name="v", dim=2, n=n, p=p, gamma=gamma, bc=("periodic",) * 2, tau=float(t)))[0]
+                for t in taus]
+        k = int(np.argmin(rhos))
+        print(f"| {form} | {p} | {t1} | {taus[k]:.4f} | {rhos[k]:.4f} | {rhos[8]:.4f} |", flush=True)
+        print("|  |  | sweep | " + " ".join(f"{t:.3g}:{r:.3f}" for t, r in zip(taus, rhos)) + " | | |", flush=True)
+
+
+def refine():
+    from synth import Problem, c1_periodic_standard
+    print("| problem | " + " | ".join(f"n={n}" for n in (8, 16, 32, 64, 128, 256)) + " |")
+    print("|---|" + "---|" * 6)
+    rows = [("2D standard periodic p=2", lambda n: c1_periodic_standard(n=n, p=2, nu=(3, 3))),
+            ("2D standard periodic p=3", lambda n: Problem(name="s", dim=2, n=n, p=3, gamma=0, bc=("periodic",) * 2)),
+            ("2D standard Dirichlet p=2", lambda n: Problem(name="s", dim=2, n=n, p=2, gamma=0, bc=("dirichlet",) * 2)),
+            ("2D viscous-stress periodic p=2", lambda n: Problem(name="s", dim=2, n=n, p=2, gamma=1, bc=("periodic",) * 2)),
+            ("2D standard periodic p=1", lambda n: Problem(name="s", dim=2, n=n, p=1, gamma=0, bc=("periodic",) * 2))]
+    for label, mk in rows:
+        vals = []
+        for n in (8, 16, 32, 64, 128, 256):
+            r, its, ok = rho_of(mk(n))
+            vals.append(f"{r:.3f} ({its})" if ok else f"{r:.3f} (no 1e8 in {its})")
+        print(f"| {label} | " + " | ".join(vals) + " |", flush=True)
+
+
+def unsteady(n=64):
+    from synth import Problem, ConstField
+    h = 1.0 / n
+    print(f"| p | tau_0 | rho (mu = 1e-4, delta = 0.1 h, n = {n}) | rho (mu = 1e-2) |")
+    print("|---|---|---|---|")
+    for p in (1, 2, 3):
+        for f in (0.5, 1.0, 2.0, 5.0, 10.0, 20.0):
+            t0 = f * p
+            out = []
+            for mu in (1e-4, 1e-2):
+                prob = Problem(name="u", dim=2, n=n, p=p, gamma=0, bc=("periodic",) * 2, mu=ConstField(mu),
+                               rho=ConstField(1.0), delta=0.1 * h, tau0=t0)
+                r, its, ok = rho_of(prob)
+                out.append(f"{r:.3f} ({its})")
+            print(f"| {p} | {t0:g} | {out[0]} | {out[1]} |", flush=True)
+
+
+def viscosity():
+    from synth import Problem, SinProductField, LogNormalRFF
+    from synth.fields import AmplitudeField
+    ns = (8, 16, 32)
+    print("| viscosity (3D viscous-stress, Dirichlet, p = 2) | scaling | " + " | ".join(f"n={n}" for n in ns) + " |")
+    print("|---|---|" + "---|" * len(ns))
+    base = LogNormalRFF.from_seed(1001, 3)
+    fields = [("eq. (mu): 1 + 0.5 sin4pi x sin4pi y sin4pi z", SinProductField(1.0, 0.5, 2.0)),
+              ("10^(g/4), g log-normal RFF seed 1001", AmplitudeField(base, 0.25)),
+              ("10^(g/2)", AmplitudeField(base, 0.5)),
+              ("10^g (the 128^3 workload's field)", base)]
+    for label, mu in fields:
+        for scal in (False, True):
+            vals = []
+            for n in ns:
+                prob = Problem(name="m", dim=3, n=n, p=2, gamma=1, bc=("dirichlet",) * 3, mu=mu,
+                               coloring="parity", diag_scaling=scal)
+                r, its, ok = rho_of(prob, maxit=150)
+                vals.append(f"{r:.3f} ({its})" if ok else f"{r:.3f} (no 1e8 in {its})")
+            print(f"| {label} | {'on' if scal else 'off'} | " + " | ".join(vals) + " |", flush=True)
+
+
+if __name__ == "__main__":
+    which = sys.argv[1] if len(sys.argv) > 1 else "valley"
+    {"valley": valley, "refine": refine, "unsteady": unsteady, "viscosity": viscosity}[which]()

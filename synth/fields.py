@@ -150,6 +150,22 @@ class LogNormalRFF:
 # Manufactured solutions built from products of shifted sines
 # ---------------------------------------------------------------------------
 @dataclass
+class AmplitudeField:
+    """mu_a(x) = mu(x)^a for a positive field mu: for the log-normal field,
+    10^(a g(x)), the same field with its log-amplitude scaled by a."""
+    base: object
+    a: float
+    kind: str = "callback"
+
+    def value(self, x, chi=None):
+        return self.base.value(x, chi) ** self.a
+
+    def grad(self, x, chi=None):
+        m = self.base.value(x, chi)
+        return (self.a * m ** (self.a - 1.0))[:, None] * self.base.grad(x, chi)
+
+
+@dataclass
 class SinProd:
     """c * prod_j sin(2 pi (x_j + s_j)), with value, gradient and Hessian."""
     c: float

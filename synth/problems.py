@@ -165,9 +165,12 @@ def c4a_square_inclusion(n=512, p=2, mu_in=1.0e4, mu_out=1.0):
                    diag_scaling=True, exact=exact)
 
 
-def c5_lognormal(n=128, p=2, seed=1001):
-    """3D viscous-stress Stokes, Dirichlet walls, log-normal random viscosity."""
+def c5_lognormal(n=128, p=2, seed=1001, diag_scaling=False):
+    """3D viscous-stress Stokes, Dirichlet walls, log-normal random viscosity.
+    The (alpha, beta) scaling of the multi-phase section is off by default:
+    for this smooth field it slows the V-cycle down (GMRES rate 0.6 without,
+    0.9 with it at n = 32)."""
     mu = LogNormalRFF.from_seed(seed, 3)
     return Problem(name=f"c5_lognormal_n{n}_p{p}_s{seed}", dim=3, n=n, p=p, gamma=1,
-                   bc=("dirichlet",) * 3, mu=mu, coloring="parity", diag_scaling=True,
+                   bc=("dirichlet",) * 3, mu=mu, coloring="parity", diag_scaling=diag_scaling,
                    exact=make_exact_paper(3, 1, mu))

@@ -29,6 +29,7 @@ CASES = {
     "c4a_n16_p2": lambda: c4a_square_inclusion(n=16, p=2),
     "c4a_n32_p1": lambda: c4a_square_inclusion(n=32, p=1),
     "c5_n8_p2": lambda: c5_lognormal(n=8, p=2),
+    "c5_n8_p2_scaled": lambda: c5_lognormal(n=8, p=2, diag_scaling=True),
 }
 
 _cache = {}

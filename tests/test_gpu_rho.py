@@ -1,0 +1,103 @@
+"""The convergence-rate metric of eq. (rho) on the GPU (left-preconditioned
+GMRES, b = 0, random x_0, run to a 1e8 reduction; section 4) against the
+oracle, and the experiments of section 4 and 5.1 built on it: the tau valley
+against the windows of Table 2, and rho under refinement."""
+import os
+
+import numpy as np
+import pytest
+
+from synth import Problem, c1_periodic_standard, c2_dirichlet_varmu, c4a_square_inclusion
+from synth.problems import tau_table
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+CASES = {
+    "c1_n16_p2_v33": lambda: c1_periodic_standard(n=16, p=2, nu=(3, 3)),
+    "c2_n16_p3": lambda: c2_dirichlet_varmu(n=16, p=3),
+    "per3d_n8_p2": lambda: Problem(name="per3d", dim=3, n=8, p=2, gamma=1, bc=("periodic",) * 3),
+    "c4a_n16_p2": lambda: c4a_square_inclusion(n=16, p=2),
+}
+
+
+def _x0(ctx, H, seed=0):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return torch.tensor(H.project_kernel(rng.standard_normal(ctx.ndof)), device="cuda")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_rho_metric_matches_oracle(name):
+    from oracle import build_hierarchy
+    from oracle.solvers import Solver
+    from paper_1911_05888_amd import Context
+    print(f"[rho] parity {name}", flush=True)
+    prob = CASES[name]()
+    H = build_hierarchy(prob)
+    rho_o, n_o, hist_o = Solver(H).rho_metric(seed=0, return_history=True)
+    ctx = Context(prob)
+    rho_g, n_g, hist_g, ok = ctx.gmres_rho(_x0(ctx, H, 0))
+    assert ok and n_g == n_o, (n_g, n_o)
+    # the ratios ||V A x_k|| / ||V A x_0|| to 1e-11 of the start, as for the
+    # V-cycle residual histories; rho = ratio_n^(1/n) with ratio_n ~ 1e-8, so
+    # an absolute 1e-15 in ratio_n is a relative 1e-7 / n in rho
+    assert np.abs(hist_g - hist_o).max() <= 1e-11, np.abs(hist_g - hist_o).max()
+    assert abs(rho_g - rho_o) <= 1e-6 * rho_o
+
+
+def _windows():
+    out = {}
+    with open(os.path.join(GOLDEN, "table2_tau_windows.txt")) as fh:
+        for line in fh:
+            f = line.split()
+            if f and not f[0].startswith("#"):
+                out[(f[0], int(f[1]), int(f[2]))] = (float(f[3]), float(f[4]))
+    return out
+
+
+def _rho_at(prob, seed=0):
+    from paper_1911_05888_amd import Context
+    import torch
+    ctx = Context(prob)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x0 = torch.tensor(rng.standard_normal(ctx.ndof), device="cuda")
+    ctx.project_kernel(x0)
+    rho, its, _, ok = ctx.gmres_rho(x0)
+    ctx.close()
+    return rho if ok else 1.0
+
+
+@pytest.mark.parametrize("form,p", [("standard", 2), ("viscous", 2), ("viscous", 3)])
+def test_tau_valley_matches_tables_1_and_2(form, p):
+    """Section 4: rho(tau) has a valley.  On a 64 x 64 periodic grid, over
+    tau = tau_1 2^(k/4), k = -6..6 (tau_1 the Table 1 value), the window of
+    near-optimal tau by the paper's own definition, rho(tau) <= (min
+    rho)^(1 - 1/9), overlaps the paper's window (Table 2) and contains
+    tau_1; the minimum itself lies within a factor 2^(1/4) of Table 2's
+    window (the valley floor is flat to a few per cent, so the grid point of
+    the minimum moves with the random initial guess)."""
+    gamma = 0 if form == "standard" else 1
+    lo, hi = _windows()[(form, 2, p)]
+    t1 = tau_table(gamma, 2, p)
+    taus = t1 * 2.0 ** (np.arange(-6, 7) / 4)
+    rhos = []
+    for tau in taus:
+        rhos.append(_rho_at(Problem(name="v", dim=2, n=64, p=p, gamma=gamma, bc=("periodic",) * 2, tau=float(tau))))
+    k = int(np.argmin(rhos))
+    print(f"[rho] {form} p={p}: " + ", ".join(f"{t:.4f}:{r:.4f}" for t, r in zip(taus, rhos)), flush=True)
+    near = taus[np.array(rhos) <= rhos[k] ** (1.0 - 1.0 / 9.0)]
+    assert near.min() <= hi and near.max() >= lo, (near.min(), near.max(), (lo, hi))
+    assert rhos[6] <= rhos[k] ** (1.0 - 1.0 / 9.0), (rhos[6], rhos[k])
+    assert lo * 2 ** -0.25 <= taus[k] <= hi * 2 ** 0.25, (taus[k], (lo, hi))
+    # the valley: rho rises on both sides of the window, and the V-cycle
+    # breaks down (rho -> 1) well below it
+    assert rhos[0] > rhos[k] and rhos[-1] > rhos[k]
+
+
+def test_rho_flat_under_refinement():
+    """Section 5.1: standard form, periodic, mu = 1, p = 2, V(3,3) at the Table 1
+    tau: rho about 0.05 and essentially independent of n."""
+    rhos = [_rho_at(c1_periodic_standard(n=n, p=2, nu=(3, 3))) for n in (16, 32, 64, 128, 256)]
+    print(f"[rho] periodic standard p=2 n=16..256: {rhos}", flush=True)
+    assert max(rhos) <= 0.1 and max(rhos) / min(rhos) <= 1.3, rhos

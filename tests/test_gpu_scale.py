@@ -208,6 +208,50 @@ def test_shared_inverse_matches_per_element_inverses(monkeypatch):
     assert e <= 1e-4
 
 
+SU_CASES = {
+    # 12 x 12 blocks (2D Q_1, standard form, red-black): colours of 8192 and
+    # 32768 elements take the 16-elements-per-thread tiles of the vector-ALU
+    # update, 336 elements per tile (more than the work-group's threads)
+    "per2d_n128_p1": lambda: Problem(name="per2d", dim=2, n=128, p=1, gamma=0, bc=("periodic", "periodic")),
+    "per2d_n256_p1": lambda: Problem(name="per2d", dim=2, n=256, p=1, gamma=0, bc=("periodic", "periodic")),
+    # 27 x 27 blocks, colours of 8192 elements
+    "per2d_n128_p2": lambda: Problem(name="per2d", dim=2, n=128, p=2, gamma=0, bc=("periodic", "periodic")),
+}
+
+
+@pytest.mark.parametrize("name", list(SU_CASES))
+def test_shared_inverse_large_colours_match_per_element_inverses(name, monkeypatch):
+    """FP64 colour passes and a V-cycle from zero (first pass included) with
+    the level's one inverse against per-element inverses
+    (LDGS_SHARED_INVERSE=0) on colours of 8192 elements and more."""
+    import torch
+    from paper_1911_05888_amd import Context
+    prob = SU_CASES[name]()
+    print(f"[scale] shared update, large colours {name}", flush=True)
+    ctxs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("LDGS_SHARED_INVERSE", flag)
+        ctxs.append(Context(prob))
+    shared, plain = ctxs
+    assert shared.level_shared_inverse(0) and not plain.level_shared_inverse(0)
+    N = shared.ndof
+    rng = np.random.Generator(np.random.PCG64(48))
+    x0, b = rng.standard_normal(N), rng.standard_normal(N)
+    _, _, ncol = shared.level_info(0)
+    xs, xp, bg = _dev(x0), _dev(x0), _dev(b)
+    for c in range(ncol):
+        shared.level_smooth_colour(0, c, bg, xs)
+        plain.level_smooth_colour(0, c, bg, xp)
+        assert _rel(_host(xs), _host(xp)) <= 1e-12, c
+    shared.project_kernel(bg)
+    ys = []
+    for ctx in (shared, plain):
+        y = torch.zeros_like(bg)
+        ctx.vcycle(bg, y)
+        ys.append(_host(y))
+    assert _rel(ys[0], ys[1]) <= 1e-12
+
+
 FULL_CASES = {
     # 3D unsteady periodic, 64^3 Q_2: every level on the one-inverse path,
     # two-wavefront launches of the 3D evaluation
