@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libldgs.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SRCS = ["setup.cpp", "build.cpp", "eigen.cpp", "rhs.cpp", "api.cpp"]
-HIP_SRCS = ["kernels.hip", "learned.hip"]
+HIP_SRCS = ["kernels.hip", "learned.hip", "setup_dev.hip"]
 
 HIPCC_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
                # no packed-FP32 instructions in generated code

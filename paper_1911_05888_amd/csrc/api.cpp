@@ -84,6 +84,7 @@ struct ldgs_ctx {
   int small_grid = 4096;       // see LaunchCfg; LDGS_SMALL_GRID overrides (tests)
   bool shared_inverse = true;  // one inverse per level with equal blocks; LDGS_SHARED_INVERSE=0 disables
   bool use_graph = true;       // V-cycles replayed from captured HIP graphs; LDGS_GRAPH=0 disables
+  bool device_setup = true;    // per-element block inverses assembled and inverted on the GPU; LDGS_DEVICE_SETUP=0: host
   // one-inverse FP32 updates of colours of at least mfma_min elements on the
   // matrix cores (0: never); LDGS_MFMA=0 disables, LDGS_MFMA_MIN overrides
   // the size (tests)
@@ -490,6 +491,78 @@ static bool uniform_blocks(const ldgs_ctx* c, const Level& L) {
   return true;
 }
 
+// Device buffers needed during setup only: drawn like the context's own
+// storage (caller's allocator or hipMalloc) and returned at scope exit, after
+// the stream has drained.
+struct TempDev {
+  ldgs_ctx* c;
+  std::vector<void*> p;
+  explicit TempDev(ldgs_ctx* c_) : c(c_) {}
+  template <typename T>
+  T* get(size_t count) {
+    const size_t bytes = (count ? count : 1) * sizeof(T);
+    void* q = nullptr;
+    if (c->P.dev_alloc) {
+      q = c->P.dev_alloc(bytes, c->P.alloc_user);
+      if (!q) throw Fail{LDGS_E_NOMEM, "dev_alloc returned NULL for " + std::to_string(bytes) + " bytes"};
+    } else {
+      hipError_t e = hipMalloc(&q, bytes);
+      if (e != hipSuccess) throw Fail{LDGS_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+    }
+    p.push_back(q);
+    return (T*)q;
+  }
+  ~TempDev() {
+    (void)hipStreamSynchronize(c->stream);
+    for (void* q : p) {
+      if (c->P.dev_free) c->P.dev_free(q, c->P.alloc_user);
+      else (void)hipFree(q);
+    }
+  }
+};
+
+// Inverses of the diagonal blocks of level l on the device (section 3; K7),
+// colour by colour: the FP64 blocks from n_b colour residuals of unit
+// vectors, FP64 Gauss-Jordan inverses of the equilibrated blocks, their
+// symmetric parts into the tile layout of each precision.
+void device_inverses(ldgs_ctx* c, size_t l, const std::vector<int64_t>& off, const int* elems, bool parity,
+                     double* inv64, float* inv32, uint16_t* inv16, size_t st64, size_t st32, size_t st16) {
+  const Level& L = c->levels[l];
+  const int nb = c->g.nb;
+  const DevLevel<double>& view = c->s64.lv[l].view;
+  int64_t maxc = 0;
+  for (int col = 0; col < L.ncol; ++col) maxc = std::max(maxc, off[col + 1] - off[col]);
+  TempDev tmp(c);
+  double* x = tmp.get<double>((size_t)L.NE * nb);
+  double* b0 = tmp.get<double>((size_t)L.NE * nb);
+  double* r = tmp.get<double>((size_t)maxc * nb);
+  double* blk = tmp.get<double>((size_t)maxc * nb * nb);
+  int* nsing = tmp.get<int>(1);
+  LCHK(launch_fill<double>(c->stream, L.NE * nb, 0.0, x));
+  LCHK(launch_fill<double>(c->stream, L.NE * nb, 0.0, b0));
+  HIPCHK(hipMemsetAsync(nsing, 0, sizeof(int), c->stream));
+  LaunchCfg cfg{c->g.d, c->g.p, c->stream, c->small_grid};
+  for (int col = 0; col < L.ncol; ++col) {
+    const int64_t o = off[col], cnt = off[col + 1] - o;
+    if (cnt == 0) continue;
+    for (int j = 0; j < nb; ++j) {
+      LCHK(launch_set_unit(c->stream, cnt, elems + o, nb, j, x));
+      LCHK(launch_colour_residual<double>(cfg, view, c->tab, elems + o, parity ? col : -1, cnt, b0, x, r));
+      LCHK(launch_take_column(c->stream, cnt, nb, j, r, blk));
+    }
+    LCHK(launch_set_unit(c->stream, cnt, elems + o, nb, nb, x));   // x back to zero
+    LCHK(launch_block_inverse(c->stream, cnt, nb, blk, nsing));
+    if (inv64) LCHK(launch_arrange_sym(c->stream, cnt, nb, blk, inv64 + o * st64, 8, (int64_t)st64));
+    if (inv32) LCHK(launch_arrange_sym(c->stream, cnt, nb, blk, inv32 + o * st32, 4, (int64_t)st32));
+    if (inv16) LCHK(launch_arrange_sym(c->stream, cnt, nb, blk, inv16 + o * st16, 2, (int64_t)st16));
+  }
+  int h_sing = 0;
+  HIPCHK(hipMemcpyAsync(&h_sing, nsing, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (h_sing > 0)
+    throw Fail{LDGS_E_SINGULAR_BLOCK, std::to_string(h_sing) + " singular element blocks on level " + std::to_string(l)};
+}
+
 void build_inverses(ldgs_ctx* c, bool need64, bool need32, bool need16) {
   const int nb = c->g.nb;
   const size_t nb2 = (size_t)nb * nb;
@@ -569,11 +642,12 @@ void build_inverses(ldgs_ctx* c, bool need64, bool need32, bool need16) {
     uint16_t* inv16 = need16 ? dalloc<uint16_t>(c, L.NE * st16) : nullptr;
     int* elems = dalloc<int>(c, L.NE);
     HIPCHK(hipMemcpy(elems, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice));
-    const int64_t CH = 8192;
+    const int64_t CH = c->device_setup ? 0 : 8192;
+    if (c->device_setup) device_inverses(c, l, off, elems, parity, inv64, inv32, inv16, st64, st32, st16);
     std::vector<double> b64, b32, b16;
     std::vector<float> h32;
     std::vector<uint16_t> h16;
-    for (int64_t p0 = 0; p0 < L.NE; p0 += CH) {
+    for (int64_t p0 = 0; CH > 0 && p0 < L.NE; p0 += CH) {
       const int64_t cnt = std::min(CH, L.NE - p0);
       if (need64) b64.assign(cnt * st64, 0.0);
       if (need32) b32.assign(cnt * st32, 0.0);
@@ -1140,29 +1214,43 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
     }
     if (const char* si = std::getenv("LDGS_SHARED_INVERSE")) c->shared_inverse = std::strtol(si, nullptr, 10) != 0;
     if (const char* gr = std::getenv("LDGS_GRAPH")) c->use_graph = std::strtol(gr, nullptr, 10) != 0;
+    if (const char* ds = std::getenv("LDGS_DEVICE_SETUP")) c->device_setup = std::strtol(ds, nullptr, 10) != 0;
     if (const char* mm = std::getenv("LDGS_MFMA_MIN")) {
       const long v = std::strtol(mm, nullptr, 10);
       if (v >= 1) c->mfma_min = v;
     }
     if (const char* mf = std::getenv("LDGS_MFMA"))
       if (std::strtol(mf, nullptr, 10) == 0) c->mfma_min = 0;
+    // LDGS_SETUP_TIMING=1: wall time of each setup phase on stderr
+    const bool timing = std::getenv("LDGS_SETUP_TIMING") && std::strtol(std::getenv("LDGS_SETUP_TIMING"), nullptr, 10);
+    auto tmark = std::chrono::steady_clock::now();
+    auto phase = [&](const char* what) {
+      if (!timing) return;
+      const auto now = std::chrono::steady_clock::now();
+      std::fprintf(stderr, "[ldgs setup] %-28s %8.3f s\n", what, std::chrono::duration<double>(now - tmark).count());
+      tmark = now;
+    };
     c->k0 = kernel_dim(P);
     if (c->k0 == 1) c->kernel_offsets = {P.dim * c->g.nq};
     else for (int i = 0; i <= P.dim; ++i) c->kernel_offsets.push_back(i * c->g.nq);
     // hierarchy
     c->levels.emplace_back();
     build_fine_level(P, c->g, c->B, c->levels[0]);
+    phase("fine level");
     while (c->levels.back().n > P.coarsest_n) {
       Level C;
       coarsen_level(P, c->g, c->B, c->levels.back(), C);
       c->levels.push_back(std::move(C));
     }
+    phase("coarse levels");
     if (P.diag_scaling)
       for (Level& L : c->levels) set_scaling(L, c->g);
     build_smoother_host(c.get());
+    phase("colouring");
     if (c->shared_inverse)
       for (size_t l = 0; l + 1 < c->levels.size(); ++l) c->levels[l].uniform = uniform_blocks(c.get(), c->levels[l]);
     build_bottom(c.get());
+    phase("bottom solver");
     if (!c->host_only) {
       if (P.hip_stream) {
         c->stream = (hipStream_t)P.hip_stream;
@@ -1174,14 +1262,18 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
       }
       int mask = (1 << P.vprec) | P.build_precisions;
       bool n64 = mask & 1, n32 = mask & 2, n16 = mask & 4;
-      upload_ops<double>(c.get(), c->s64, n64);     // finest FP64 operator always (outer residual)
+      // the finest FP64 operator always (outer residual); every level's when
+      // the block inverses are built on the device (from the FP64 operator)
+      upload_ops<double>(c.get(), c->s64, n64 || c->device_setup);
       if (n32 || n16) {
         upload_ops<float>(c.get(), c->s32, true);
         c->s16.lv = c->s32.lv;                       // same operator data and work vectors
         for (auto& l : c->s16.lv) l.inv = nullptr;
         c->s16.ops = true;
       }
+      phase("operator upload");
       build_inverses(c.get(), n64, n32, n16);
+      phase("block inverses");
       {
         // scratch of the split residual + restriction: the largest level whose
         // coarse grid has fewer than small_grid elements
@@ -1213,6 +1305,7 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
       }
       if (P.diag_scaling) c->d_dscale0 = upload<double>(c.get(), c->levels[0].dscale);
       HIPCHK(hipDeviceSynchronize());
+      phase("work vectors");
     }
   } catch (const Fail& f) {
     g_setup_error = f.msg;

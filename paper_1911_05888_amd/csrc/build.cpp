@@ -78,6 +78,69 @@ void eval_field(const ldgs_field& f, int d, int64_t n, const double* x, const in
 
 static bool field_is_const(const ldgs_field& f) { return f.kind == LDGS_FIELD_CONST; }
 
+// The log-normal field 10^g, g = sqrt(2/K) sum_m cos(k_m . x + phi_m), at the
+// points x = h (c + xi_q) of a tensor point set: anchors c (integer grid
+// coordinates of an element or a face, from anchor(a, c)) times local
+// offsets xi_q.  With e^{i k_m . x} = prod_j e^{i k_mj h c_j} e^{i k_m . h xi_q}
+// the cosines factor into per-axis tables and one table per offset, so a
+// point costs K multiply-adds instead of K cosines:
+//   g(a, q) = sqrt(2/K) sum_m Re(z_m(a) w_m(q)),  z_m(a) = prod_j T_j[c_j][m],
+//   w_m(q) = e^{i (k_m . h xi_q + phi_m)}.
+// out[a * nq + q] = 10^g.  cmax: largest grid coordinate (n for faces).
+template <class Anchor>
+static void rff_tensor_points(const ldgs_field& f, int d, double h, int cmax, int64_t nanchor, Anchor anchor,
+                              int nq, const double* xi, double* out) {
+  const int64_t K = f.nparams / (d + 1);
+  const double* kv = f.params;
+  const double* ph = f.params + K * d;
+  const double sc = std::sqrt(2.0 / (double)K);
+  const int nc = cmax + 1;
+  std::vector<double> Tr((size_t)d * nc * K), Ti((size_t)d * nc * K);
+  for (int j = 0; j < d; ++j)
+    for (int c = 0; c < nc; ++c)
+      for (int64_t m = 0; m < K; ++m) {
+        const double a = kv[m * d + j] * h * c;
+        Tr[((size_t)j * nc + c) * K + m] = std::cos(a);
+        Ti[((size_t)j * nc + c) * K + m] = std::sin(a);
+      }
+  std::vector<double> Wr((size_t)nq * K), Wi((size_t)nq * K);
+  for (int q = 0; q < nq; ++q)
+    for (int64_t m = 0; m < K; ++m) {
+      double a = ph[m];
+      for (int j = 0; j < d; ++j) a += kv[m * d + j] * h * xi[q * d + j];
+      Wr[(size_t)q * K + m] = std::cos(a);
+      Wi[(size_t)q * K + m] = std::sin(a);
+    }
+#pragma omp parallel
+  {
+    std::vector<double> zr(K), zi(K);
+#pragma omp for schedule(static)
+    for (int64_t a = 0; a < nanchor; ++a) {
+      int c[3] = {0, 0, 0};
+      anchor(a, c);
+      for (int64_t m = 0; m < K; ++m) {
+        double r = Tr[(size_t)c[0] * K + m], i = Ti[(size_t)c[0] * K + m];
+        for (int j = 1; j < d; ++j) {
+          const double tr = Tr[((size_t)j * nc + c[j]) * K + m], ti = Ti[((size_t)j * nc + c[j]) * K + m];
+          const double nr = r * tr - i * ti;
+          i = r * ti + i * tr;
+          r = nr;
+        }
+        zr[m] = r;
+        zi[m] = i;
+      }
+      for (int q = 0; q < nq; ++q) {
+        const double* wr = &Wr[(size_t)q * K];
+        const double* wi = &Wi[(size_t)q * K];
+        double g = 0.0;
+#pragma omp simd reduction(+ : g)
+        for (int64_t m = 0; m < K; ++m) g += zr[m] * wr[m] - zi[m] * wi[m];
+        out[(size_t)a * nq + q] = std::pow(10.0, sc * g);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // fine grid
 // ---------------------------------------------------------------------------
@@ -154,17 +217,22 @@ void build_fine_level(const ldgs_problem& P, const Geometry& g, const Basis& B, 
   } else {
     L.mu_is_const = false;
     L.mmu.assign((size_t)L.NE * nq * nq, 0.0);
-    std::vector<double> X((size_t)L.NE * nv * d), mu((size_t)L.NE * nv);
-    std::vector<int> ph((size_t)L.NE * nv);
-    for (int64_t E = 0; E < L.NE; ++E) {
-      int c[3];
-      coords(E, n, d, c);
-      for (int i = 0; i < nv; ++i) {
-        for (int j = 0; j < d; ++j) X[((size_t)E * nv + i) * d + j] = (c[j] + xi[i * d + j]) * h;
-        ph[(size_t)E * nv + i] = L.chi[E];
+    std::vector<double> mu((size_t)L.NE * nv);
+    if (P.mu.kind == LDGS_FIELD_LOGNORMAL_RFF) {
+      rff_tensor_points(P.mu, d, h, n, L.NE, [&](int64_t E, int* c) { coords(E, n, d, c); }, nv, xi.data(), mu.data());
+    } else {
+      std::vector<double> X((size_t)L.NE * nv * d);
+      std::vector<int> ph((size_t)L.NE * nv);
+      for (int64_t E = 0; E < L.NE; ++E) {
+        int c[3];
+        coords(E, n, d, c);
+        for (int i = 0; i < nv; ++i) {
+          for (int j = 0; j < d; ++j) X[((size_t)E * nv + i) * d + j] = (c[j] + xi[i * d + j]) * h;
+          ph[(size_t)E * nv + i] = L.chi[E];
+        }
       }
+      eval_field(P.mu, d, L.NE * nv, X.data(), ph.data(), mu.data());
     }
-    eval_field(P.mu, d, L.NE * nv, X.data(), ph.data(), mu.data());
 #pragma omp parallel for schedule(static)
     for (int64_t E = 0; E < L.NE; ++E) {
       double* M = L.mmu.data() + (size_t)E * nq * nq;
@@ -198,36 +266,55 @@ void build_fine_level(const ldgs_problem& P, const Geometry& g, const Basis& B, 
       fs.Trho.assign((size_t)fs.count * mt * mt, 0.0);
     }
     // all face quadrature points of this axis, with the phase of each side
-    std::vector<double> X((size_t)fs.count * nt * d);
-    std::vector<int> phL((size_t)fs.count * nt), phR((size_t)fs.count * nt);
+    auto face_coords = [&](int64_t id, int* c) {
+      int64_t r = id;
+      for (int j = 0; j < d; ++j) {
+        const int ext = (j == k) ? fs.nfk : n;
+        c[j] = (int)(r % ext);
+        r /= ext;
+      }
+    };
     std::vector<int64_t> EL(fs.count), ER(fs.count);
     for (int64_t id = 0; id < fs.count; ++id) {
       int c[3] = {0, 0, 0};
-      int64_t r = id;
-      int f = 0;
-      for (int j = 0; j < d; ++j) {
-        int ext = (j == k) ? fs.nfk : n;
-        int v = (int)(r % ext);
-        r /= ext;
-        if (j == k) f = v;
-        else c[j] = v;
-      }
+      face_coords(id, c);
+      const int f = c[k];
       face_elements(L, d, k, f, c, &EL[id], &ER[id]);
+    }
+    std::vector<double> muL((size_t)fs.count * nt), muR;
+    if (P.mu.kind == LDGS_FIELD_LOGNORMAL_RFF) {
+      // one value per point (the field does not depend on the phase); face
+      // points have offset 0 along the normal axis
+      std::vector<double> xf((size_t)nt * d, 0.0);
       for (int i = 0; i < nt; ++i) {
         int jj = 0;
-        for (int j = 0; j < d; ++j) {
-          double v;
-          if (j == k) v = f * h;
-          else v = (c[j] + tp[i * (d - 1) + jj++]) * h;
-          X[((size_t)id * nt + i) * d + j] = v;
-        }
-        phL[(size_t)id * nt + i] = EL[id] >= 0 ? L.chi[EL[id]] : L.chi[ER[id]];
-        phR[(size_t)id * nt + i] = ER[id] >= 0 ? L.chi[ER[id]] : L.chi[EL[id]];
+        for (int j = 0; j < d; ++j) xf[(size_t)i * d + j] = (j == k) ? 0.0 : tp[i * (d - 1) + jj++];
       }
+      rff_tensor_points(P.mu, d, h, n, fs.count, face_coords, nt, xf.data(), muL.data());
+      muR = muL;
+    } else {
+      std::vector<double> X((size_t)fs.count * nt * d);
+      std::vector<int> phL((size_t)fs.count * nt), phR((size_t)fs.count * nt);
+      for (int64_t id = 0; id < fs.count; ++id) {
+        int c[3] = {0, 0, 0};
+        face_coords(id, c);
+        const int f = c[k];
+        for (int i = 0; i < nt; ++i) {
+          int jj = 0;
+          for (int j = 0; j < d; ++j) {
+            double v;
+            if (j == k) v = f * h;
+            else v = (c[j] + tp[i * (d - 1) + jj++]) * h;
+            X[((size_t)id * nt + i) * d + j] = v;
+          }
+          phL[(size_t)id * nt + i] = EL[id] >= 0 ? L.chi[EL[id]] : L.chi[ER[id]];
+          phR[(size_t)id * nt + i] = ER[id] >= 0 ? L.chi[ER[id]] : L.chi[EL[id]];
+        }
+      }
+      muR.resize((size_t)fs.count * nt);
+      eval_field(P.mu, d, fs.count * nt, X.data(), phL.data(), muL.data());
+      eval_field(P.mu, d, fs.count * nt, X.data(), phR.data(), muR.data());
     }
-    std::vector<double> muL((size_t)fs.count * nt), muR((size_t)fs.count * nt);
-    eval_field(P.mu, d, fs.count * nt, X.data(), phL.data(), muL.data());
-    eval_field(P.mu, d, fs.count * nt, X.data(), phR.data(), muR.data());
     const double tb = P.tau_u_bdry_C * p / h;
     const double ti = P.tau_u_inter_C * p / h;
 #pragma omp parallel for schedule(static)

@@ -177,6 +177,16 @@ int launch_strided_sum_partial(void* stream, int64_t nelem, int nb, int off, con
                                double* out, int nblk);
 int launch_strided_add(void* stream, int64_t nelem, int nb, int off, double v, double* x);
 
+// Device setup of per-element inverses (setup_dev.hip): unit vectors e_j on
+// the listed elements (j = nb only clears entry nb - 1), column j of each
+// block from a colour residual r = -A x, in-place FP64 inverses of row-major
+// nb x nb blocks (nsing counts singular ones), and the symmetric part of each
+// inverse into the tile layout of SymTiles (bytes 8, 4 or 2 per entry).
+int launch_set_unit(void* stream, int64_t cnt, const int* elems, int nb, int j, double* x);
+int launch_take_column(void* stream, int64_t cnt, int nb, int j, const double* r, double* A);
+int launch_block_inverse(void* stream, int64_t nblk, int nb, double* A, int* nsing);
+int launch_arrange_sym(void* stream, int64_t cnt, int nb, const double* inv, void* out, int bytes, int64_t stride);
+
 // bf16 <-> float helpers used by the BF16-block path
 int launch_f2bf16(void* stream, int64_t n, const float* a, uint16_t* b);
 
