@@ -72,8 +72,13 @@ typedef enum { LDGS_V_FP64 = 0, LDGS_V_FP32 = 1, LDGS_V_FP32_BF16BLK = 2 } ldgs_
 
 /* Outer iteration of ldgs_solve.  STATIONARY: x <- V(b, x).  IR: r = b - A x
  * in FP64, x += V(r, 0).  FGMRES: flexible GMRES(m), right-preconditioned by
- * one V-cycle from zero, FP64 Arnoldi with modified Gram-Schmidt. */
-typedef enum { LDGS_STATIONARY = 0, LDGS_IR = 1, LDGS_FGMRES = 2 } ldgs_outer;
+ * one V-cycle from zero, FP64 Arnoldi with modified Gram-Schmidt (stores 2m+1
+ * vectors).  GMRES: GMRES(m) right-preconditioned by the same V-cycle taken
+ * as a fixed operator M (stores m+2 vectors; x += M (V_m y) at the end of
+ * each restart cycle, one extra V-cycle); the V-cycle from zero is linear,
+ * so this is exact for the FP64 cycle and holds to the cycle's rounding in
+ * FP32. */
+typedef enum { LDGS_STATIONARY = 0, LDGS_IR = 1, LDGS_FGMRES = 2, LDGS_GMRES = 3 } ldgs_outer;
 
 /* Scalar coefficient fields (viscosity mu, density rho). */
 typedef enum {

@@ -11,6 +11,7 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "build.hpp"
@@ -85,6 +86,9 @@ struct ldgs_ctx {
   bool shared_inverse = true;  // one inverse per level with equal blocks; LDGS_SHARED_INVERSE=0 disables
   bool use_graph = true;       // V-cycles replayed from captured HIP graphs; LDGS_GRAPH=0 disables
   bool device_setup = true;    // per-element block inverses assembled and inverted on the GPU; LDGS_DEVICE_SETUP=0: host
+  // colour passes with per-element inverses as two launches (residual, then
+  // the streamed product) on 3D levels; LDGS_SPLIT_PASS=0/1 overrides
+  int split_pass = -1;
   // one-inverse FP32 updates of colours of at least mfma_min elements on the
   // matrix cores (0: never); LDGS_MFMA=0 disables, LDGS_MFMA_MIN overrides
   // the size (tests)
@@ -207,9 +211,19 @@ struct Join {
 template <typename T>
 T* upload(ldgs_ctx* c, const std::vector<double>& src) {
   T* d = dalloc<T>(c, src.size());
-  if (!src.empty()) {
-    std::vector<T> tmp(src.begin(), src.end());
-    HIPCHK(hipMemcpy(d, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
+  if (src.empty()) return d;
+  if constexpr (std::is_same_v<T, double>) {
+    HIPCHK(hipMemcpy(d, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  } else {
+    // converted in pieces on all host threads
+    const size_t piece = (size_t)1 << 24;
+    std::vector<T> tmp(std::min(piece, src.size()));
+    for (size_t o = 0; o < src.size(); o += piece) {
+      const int64_t cnt = (int64_t)std::min(piece, src.size() - o);
+#pragma omp parallel for schedule(static)
+      for (int64_t i = 0; i < cnt; ++i) tmp[i] = (T)src[o + i];
+      HIPCHK(hipMemcpy(d + o, tmp.data(), cnt * sizeof(T), hipMemcpyHostToDevice));
+    }
   }
   return d;
 }
@@ -351,6 +365,7 @@ DevLevel<T> make_view(ldgs_ctx* c, const Level& L, bool with_scale) {
     const int M = c->g.p + 1;
     auto rows = [&](const double* ev) {
       std::vector<double> R((size_t)L.NE * d * mt * nq, 0.0);
+#pragma omp parallel for schedule(static)
       for (int64_t e = 0; e < L.NE; ++e) {
         const double* Me = L.mmu.data() + (size_t)e * nq * nq;
         for (int k = 0; k < d; ++k) {
@@ -684,6 +699,16 @@ void build_inverses(ldgs_ctx* c, bool need64, bool need32, bool need16) {
         HIPCHK(hipMemcpy(inv16 + p0 * st16, h16.data(), cnt * st16 * sizeof(uint16_t), hipMemcpyHostToDevice));
       }
     }
+    if (c->split_pass && !iface) {
+      int64_t maxc = 0;
+      for (int col = 0; col < L.ncol; ++col) maxc = std::max(maxc, off[col + 1] - off[col]);
+      if (need64) c->s64.lv[l].rbuf = dalloc<double>(c, (size_t)maxc * nb);
+      if (need32 || need16) {
+        float* rb = dalloc<float>(c, (size_t)maxc * nb);
+        if (need32) c->s32.lv[l].rbuf = rb;
+        if (need16) c->s16.lv[l].rbuf = rb;
+      }
+    }
     if (need64) { c->s64.lv[l].inv = inv64; c->s64.lv[l].inv_kind = 0; c->s64.lv[l].elems = elems; c->s64.lv[l].col_off = off; c->s64.lv[l].col_reg = reg; c->s64.lv[l].inv_stride = st64; c->s64.lv[l].parity = parity; }
     if (need32) { c->s32.lv[l].inv = inv32; c->s32.lv[l].inv_kind = 1; c->s32.lv[l].elems = elems; c->s32.lv[l].col_off = off; c->s32.lv[l].col_reg = reg; c->s32.lv[l].inv_stride = st32; c->s32.lv[l].parity = parity; }
     if (need16) { c->s16.lv[l].inv = inv16; c->s16.lv[l].inv_kind = 2; c->s16.lv[l].elems = elems; c->s16.lv[l].col_off = off; c->s16.lv[l].col_reg = reg; c->s16.lv[l].inv_stride = st16; c->s16.lv[l].parity = parity; }
@@ -785,6 +810,10 @@ void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* 
     LCHK(launch_colour_residual<T>(cfg, pl.view, c->tab, pl.elems + o, pcol, cnt, b, x, pl.rbuf));
     LCHK(launch_shared_update<T>(c->stream, cnt, c->g.nb, pl.ainv_sh, pl.rbuf, pl.elems + o, x, 0, nullptr, 0,
                                  c->mfma_min));
+  } else if (c->split_pass && pl.rbuf && !pl.view.iface) {
+    // residuals of the colour, then the streamed product with the inverses
+    LCHK(launch_colour_residual<T>(cfg, pl.view, c->tab, pl.elems + o, pcol, cnt, b, x, pl.rbuf));
+    LCHK(launch_apply_inverse<T>(cfg, pl.view.lgn, pl.elems + o, pcol, cnt, inv, pl.inv_kind, pl.rbuf, x));
   } else
   // (split only large launches: on coarse levels the second launch would cost
   // more than the extended stencil)
@@ -1215,6 +1244,8 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
     if (const char* si = std::getenv("LDGS_SHARED_INVERSE")) c->shared_inverse = std::strtol(si, nullptr, 10) != 0;
     if (const char* gr = std::getenv("LDGS_GRAPH")) c->use_graph = std::strtol(gr, nullptr, 10) != 0;
     if (const char* ds = std::getenv("LDGS_DEVICE_SETUP")) c->device_setup = std::strtol(ds, nullptr, 10) != 0;
+    if (const char* sp = std::getenv("LDGS_SPLIT_PASS")) c->split_pass = std::strtol(sp, nullptr, 10) != 0;
+    if (c->split_pass < 0) c->split_pass = P.dim == 3 ? 1 : 0;
     if (const char* mm = std::getenv("LDGS_MFMA_MIN")) {
       const long v = std::strtol(mm, nullptr, 10);
       if (v >= 1) c->mfma_min = v;
@@ -1675,11 +1706,15 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxi
         if (!std::isfinite(rel)) { st = LDGS_E_NONFINITE; break; }
         if (rel > 1e10 * hist[0]) { st = LDGS_E_NOT_CONVERGED; break; }   // blow-up (a first cycle may raise the residual transiently)
       }
-    } else if (outer == LDGS_FGMRES) {
+    } else if (outer == LDGS_FGMRES || outer == LDGS_GMRES) {
+      const bool flex = outer == LDGS_FGMRES;
       const int m = fgmres_m > 0 ? fgmres_m : 30;
-      while ((int)ctx->kry.size() < 2 * m + 1) ctx->kry.push_back(dalloc<double>(ctx, N));
+      const int nvec = flex ? 2 * m + 1 : m + 2;
+      while ((int)ctx->kry.size() < nvec) ctx->kry.push_back(dalloc<double>(ctx, N));
       double* const* V = ctx->kry.data();
+      // flexible: Z[j] = M v_j kept; fixed M: one temporary, M applied to V y at the end
       double* const* Z = ctx->kry.data() + (m + 1);
+      double* T = ctx->kry[m + 1];
       rel = relres();
       hist.push_back(rel);
       while (rel > tol && it < maxit) {
@@ -1689,10 +1724,10 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxi
         gvec[0] = beta;
         int jdone = 0;
         for (int j = 0; j < m && it < maxit; ++j) {
-          LCHK(launch_fill<double>(ctx->stream, N, 0.0, Z[j]));
-          precond_add(ctx, ctx->vprec, V[j], Z[j]);
+          double* zj = flex ? Z[j] : T;
+          vcycle_user(ctx, ctx->vprec, V[j], zj, true);
           LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream, ctx->small_grid};
-          LCHK(launch_residual<double>(cfg, ctx->s64.lv[0].unscaled, ctx->tab, nullptr, Z[j], V[j + 1], 1));
+          LCHK(launch_residual<double>(cfg, ctx->s64.lv[0].unscaled, ctx->tab, nullptr, zj, V[j + 1], 1));
           for (int i = 0; i <= j; ++i) {
             double hij = dot(ctx, V[j + 1], V[i]);
             H[i * m + j] = hij;
@@ -1727,7 +1762,14 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxi
           for (int q = i + 1; q < jdone; ++q) s -= H[i * m + q] * y[q];
           y[i] = s / H[i * m + i];
         }
-        for (int i = 0; i < jdone; ++i) LCHK(launch_axpy(ctx->stream, N, y[i], Z[i], x));
+        if (flex) {
+          for (int i = 0; i < jdone; ++i) LCHK(launch_axpy(ctx->stream, N, y[i], Z[i], x));
+        } else {
+          // x += M (V y): the combination into V[0] (no longer needed), then one cycle
+          LCHK(launch_scale_copy(ctx->stream, N, y[0], V[0], V[0]));
+          for (int i = 1; i < jdone; ++i) LCHK(launch_axpy(ctx->stream, N, y[i], V[i], V[0]));
+          precond_add(ctx, ctx->vprec, V[0], x);
+        }
         rel = relres();
         if (!hist.empty()) hist.back() = rel;
         if (!std::isfinite(rel)) { st = LDGS_E_NONFINITE; break; }

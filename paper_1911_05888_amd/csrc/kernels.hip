@@ -1238,6 +1238,33 @@ __global__ __launch_bounds__(NT) void k_first_colour(int lgn, const int* __restr
   for (int r = lane; r < NB; r += NT) x[(size_t)E * NB + r] = part[0][r] + part[1][r];
 }
 
+// Second half of a colour pass split into residual and product: x_E += Ainv_E
+// r[idx] for the listed elements, with the per-element inverses of the tile
+// layout.  One wavefront per element: the evaluation of the residual (an
+// LDS-bound kernel of its own) no longer holds the inverse's stream back, and
+// many elements' tiles are in flight per CU.
+template <typename T, typename TI, int D, int P>
+__global__ __launch_bounds__(64) void k_apply_inverse(int lgn, const int* __restrict__ elems, int pcol,
+                                                      const TI* __restrict__ inv, const T* __restrict__ r,
+                                                      T* __restrict__ x) {
+  using S = Sz<D, P>;
+  constexpr int NB = S::NB;
+  using SP = SymProd<TI, NB>;
+  __shared__ alignas(16) T res[NB];
+  __shared__ T part[2][16 * SP::TR];
+  __shared__ T red[256 * SP::TR];
+  const int lane = threadIdx.x;
+  const int idx = xcd_remap(blockIdx.x, gridDim.x);
+  const int E = colour_elem<D>(idx, pcol, lgn, elems);
+  const auto* Ai = reinterpret_cast<const typename SP::Word*>(inv + (size_t)idx * SP::ESTRIDE);
+  typename SP::Word pre[SP::PF][SP::H];
+  sym_prefetch<TI, NB>(Ai, pre, lane);
+  for (int t = lane; t < NB; t += 64) res[t] = r[(size_t)idx * NB + t];
+  __syncthreads();
+  sym_product<T, TI, NB, 64>(Ai, pre, res, part, red, lane);
+  for (int q = lane; q < NB; q += 64) x[(size_t)E * NB + q] += part[0][q] + part[1][q];
+}
+
 template <typename T, int D, int P, int NT, bool IF>
 __global__ __launch_bounds__(NT) void k_residual(DevLevel<T> lev, TabT<T> tab, const T* __restrict__ b,
                                                  const T* __restrict__ x, T* __restrict__ out, int mode) {
@@ -1862,6 +1889,33 @@ int launch_first_colour(const LaunchCfg& c, int lgn, const int* elems, int pcol,
   return hip_ok();
 }
 
+template <typename T>
+int launch_apply_inverse(const LaunchCfg& c, int lgn, const int* elems, int pcol, int64_t nelems, const void* inv,
+                         int inv_kind, const T* r, T* x) {
+  if (nelems <= 0) return 0;
+  hipStream_t st = (hipStream_t)c.stream;
+  auto go = [&](auto tag) {
+    using TI = decltype(tag);
+    return dispatch(c.dim, c.p, [&](auto Dc, auto Pc) {
+      constexpr int D_ = decltype(Dc)::value;
+      constexpr int P_ = decltype(Pc)::value;
+      hipLaunchKernelGGL((k_apply_inverse<T, TI, D_, P_>), dim3((unsigned)nelems), dim3(64), 0, st, lgn, elems, pcol,
+                         (const TI*)inv, r, x);
+    });
+  };
+  bool bad;
+  if constexpr (sizeof(T) == 8) {
+    if (inv_kind != 0) return 2;
+    bad = go(double{});
+  } else {
+    if (inv_kind == 1) bad = go(float{});
+    else if (inv_kind == 2) bad = go(uint16_t{});
+    else return 2;
+  }
+  if (bad) return 2;
+  return hip_ok();
+}
+
 int shared_inverse_rows(int nb, int bytes) {
   const int v = 16 / bytes;
   return (nb + v - 1) / v * v;
@@ -1992,6 +2046,10 @@ template int launch_shared_update<float>(void*, int64_t, int, const float*, cons
                                          const int*, int64_t, int64_t);
 template int launch_first_colour<double>(const LaunchCfg&, int, const int*, int, int64_t, const void*, int,
                                          const double*, double*, const int*, int64_t);
+template int launch_apply_inverse<double>(const LaunchCfg&, int, const int*, int, int64_t, const void*, int,
+                                          const double*, double*);
+template int launch_apply_inverse<float>(const LaunchCfg&, int, const int*, int, int64_t, const void*, int,
+                                         const float*, float*);
 template int launch_first_colour<float>(const LaunchCfg&, int, const int*, int, int64_t, const void*, int,
                                         const float*, float*, const int*, int64_t);
 template int launch_prolong_add<double>(const LaunchCfg&, int, const Tab1D&, const double*, double*);

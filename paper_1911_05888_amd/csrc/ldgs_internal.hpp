@@ -156,6 +156,11 @@ int launch_shared_update(void* stream, int64_t nelems, int nb, const T* ainv, co
 template <typename T>
 int launch_first_colour(const LaunchCfg& c, int lgn, const int* elems, int pcol, int64_t nelems, const void* inv,
                         int inv_kind, const T* b, T* x, const int* zl, int64_t nzero);
+// x_E += Ainv_E r[idx] for the listed elements (per-element inverses, same
+// conventions as launch_smooth_colour; r compact as from launch_colour_residual)
+template <typename T>
+int launch_apply_inverse(const LaunchCfg& c, int lgn, const int* elems, int pcol, int64_t nelems, const void* inv,
+                         int inv_kind, const T* r, T* x);
 template <typename T>
 int launch_prolong_add(const LaunchCfg& c, int n_fine, const Tab1D& tab, const T* xc, T* x);
 // y = z + sign * M x, M dense row-major FP64 N x N, z optional

@@ -30,7 +30,7 @@ STANDARD, VISCOUS_STRESS = 0, 1
 PERIODIC, DIRICHLET, STRESS = 0, 1, 2
 COLOR_AUTO, COLOR_RED_BLACK, COLOR_PARITY, COLOR_MOD3 = 0, 1, 2, 3
 V_FP64, V_FP32, V_FP32_BF16BLK = 0, 1, 2
-STATIONARY, IR, FGMRES = 0, 1, 2
+STATIONARY, IR, FGMRES, GMRES = 0, 1, 2, 3
 FIELD_CONST, FIELD_SINSIN, FIELD_LOGNORMAL_RFF, FIELD_PHASE_CONST, FIELD_CALLBACK = range(5)
 LEVELSET_NONE, LEVELSET_BOX = 0, 1
 NET_HIDDEN = 16          # hidden width of the learned correction network

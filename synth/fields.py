@@ -307,6 +307,42 @@ def make_exact_paper(dim, gamma, mu, phases=(1,), mu_chi=None):
     return ExactSolution(dim=dim, gamma=gamma, mu=mu, u=u, p=p)
 
 
+def projected_coeffs(exact, dim, n, p, q=None):
+    """Coefficients of the element-wise L2 projection of a single-phase sine
+    product solution (u_i and p each a SinProd) onto the orthonormal tensor
+    Legendre basis of the n^d grid (element-major, axis 0 fastest; fields
+    u_1..u_d, p; tensor-lexicographic coefficients).  A product of functions
+    of one coordinate projects as the product of their 1D projections, so
+    only n (p+1) one-dimensional integrals per factor are formed (Gauss rule
+    of q = p + 6 points)."""
+    from numpy.polynomial.legendre import leggauss
+    q = q or p + 6
+    m = p + 1
+    h = 1.0 / n
+    t, w = leggauss(q)
+    xi, wq = 0.5 * (t + 1.0), 0.5 * w                         # Gauss rule on [0, 1]
+    # l_a(xi) = sqrt(2a+1) P_a(2 xi - 1)
+    L = np.stack([np.sqrt(2 * a + 1) * np.polynomial.legendre.legval(2 * xi - 1, [0] * a + [1]) for a in range(m)])
+    X = (np.arange(n)[:, None] + xi[None, :]) * h              # (n, q) points per cell
+
+    def proj1d(sp, j):
+        # int over cell c of sin(2 pi (x + s_j)) h^{-1/2} l_a((x - c h)/h) dx
+        f = np.sin(TWO_PI * (X + sp.shifts[j]))
+        return (f * wq[None, :]) @ L.T * np.sqrt(h)           # (n, m)
+
+    fields = [exact.u[1][i] for i in range(dim)] + [exact.p[1]]
+    out = np.empty((n ** dim, dim + 1, m ** dim))
+    for fi, sp in enumerate(fields):
+        P = [proj1d(sp, j) for j in range(dim)]
+        if dim == 2:
+            # element (c0, c1), axis 0 fastest; coefficient (a0, a1), a0 fastest
+            T = np.einsum("xa,yb->yxba", P[0], P[1])
+        else:
+            T = np.einsum("xa,yb,zc->zyxcba", P[0], P[1], P[2])
+        out[:, fi, :] = sp.c * T.reshape(n ** dim, m ** dim)
+    return out.ravel()
+
+
 @dataclass
 class FourierForcing:
     """Seeded smooth Gaussian-random forcing.

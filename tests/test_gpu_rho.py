@@ -101,3 +101,24 @@ def test_rho_flat_under_refinement():
     rhos = [_rho_at(c1_periodic_standard(n=n, p=2, nu=(3, 3))) for n in (16, 32, 64, 128, 256)]
     print(f"[rho] periodic standard p=2 n=16..256: {rhos}", flush=True)
     assert max(rhos) <= 0.1 and max(rhos) / min(rhos) <= 1.3, rhos
+
+
+def test_gmres_with_fixed_preconditioner_matches_fgmres():
+    """Right-preconditioned GMRES(m) with the FP64 V-cycle as a fixed operator
+    (basis V only, x += M V y per restart) against flexible GMRES(m) (which
+    stores M v_j): the V-cycle from zero is linear, so the residual histories
+    agree to rounding, and both reach 1e-10."""
+    import torch
+    from paper_1911_05888_amd import Context, GMRES, FGMRES
+    prob = c2_dirichlet_varmu(n=16, p=3)
+    ctx = Context(prob)
+    b0 = ctx.assemble_rhs(prob.rhs_source())
+    hists = []
+    for outer in (FGMRES, GMRES):
+        b = b0.clone()
+        x = torch.zeros_like(b)
+        st, info = ctx.solve(b, x, tol=1e-10, maxit=60, outer=outer, fgmres_m=5)
+        assert st == 0, (outer, info)
+        hists.append(info["history"])
+    assert len(hists[0]) == len(hists[1])
+    assert np.abs(hists[0] - hists[1]).max() <= 1e-11, np.abs(hists[0] - hists[1]).max()
