@@ -1,34 +1,43 @@
 """Benchmark: LDG-Stokes multigrid on one MI355X.
 
-Workload (the configuration the metric is quoted on): 2D steady viscous-stress
-Stokes on the unit square with Dirichlet walls, 256x256 elements, Q_3
-(48 unknowns per element, 3,145,728 unknowns), mu = 1 + 0.9 sin(2 pi x) sin(2 pi y),
-the paper's manufactured solution.  Synthetic data, generated in-process.
+Default workload: the largest configuration that fits one GPU, 3D
+viscous-stress Stokes on the unit cube with Dirichlet walls, 128^3 elements,
+Q_2 (108 unknowns per element, 226,492,416 unknowns), log-normal viscosity
+10^g (g a unit-variance random Fourier field of correlation length 0.1,
+seed 1001: about four decades of viscosity), V(3,3) cycles with parity
+colouring.  Synthetic data generated in-process: the right-hand side is
+b = A x* for x* the element-wise L2 projection of the paper's manufactured
+velocity and pressure (the grid-convergence appendix), so the discrete
+solution is known.
 
-One step = one solve from x = 0 to ||b - A x|| <= 1e-10 ||b|| with the FP32
-V-cycle (V(3,3), parity colouring) inside FP64 iterative refinement: every
-stage of the hot path (smoother colour passes, residual + restriction,
-prolongation, bottom pseudo-inverse, FP64 outer residual) runs in the HIP
-library.  value = V-cycle DOF/s inside those solves (unknowns x V-cycles /
-solve time).  The plain FP64 stationary V-cycle to the same tolerance, and
-the BF16-block variant, are measured beside it.
+One step = one restart cycle of GMRES(m) from x = 0, right-preconditioned by
+the plain FP64 V-cycle (m Arnoldi steps and the final x += M V y: m + 1
+V-cycles); every stage of the hot path runs in the HIP library.  value =
+unknowns x V-cycles / time of the timed steps: the FP64 V-cycle rate inside
+the Krylov solve; the bare V-cycle rate is given beside it.  The stationary
+V-cycle does not converge on this field, and restarted GMRES stalls on it
+(relative residual about 1e-7 after 600 iterations at 128^3), while a basis
+long enough for unrestarted GMRES does not fit in HBM beside the FP64 data.
+The wall time to 1e-10, plain FP64 against the FP32 and BF16-inverse
+V-cycles in the same outer loop, is therefore measured with unrestarted
+flexible GMRES (exact for the rounding of the float cycles) on the 64^3 grid
+of the same field, in a context holding all three precisions.
 
-The roofline object covers the dominant kernel (the finest-level smoother
-colour pass), timed with HIP event pairs on the library's stream, one pair
-around the back-to-back colour passes of every 4th finest sweep of the timed
-solves (the average per pass includes the short gaps between those
-launches); the algorithmic bytes per launch are (elements in the colour) x
-(n_b^2 inverse entries + 3 n_b vector entries + (p+2)^d viscosity values) x
-the storage width, the method's byte model (the kernel moves only the upper
-tiles of the symmetric inverse: an effective bandwidth; `traffic` gives the
-bytes the counters saw); on levels whose blocks are all equal (periodic, constant
-coefficients) the one inverse is not streamed and that term is dropped.  cpu_baseline times the FP64 oracle on a bounded sample.
+roofline: the finest-level FP64 smoother colour pass (the dominant kernel),
+timed with HIP event pairs around whole finest sweeps on the library's stream
+(cycles launched directly while timed).  Algorithmic bytes per element and
+sweep are the method's own: the symmetric inverse n_b (n_b + 1) / 2 entries,
+x and b in and x out (3 n_b), and the (p+2)^d viscosity quadrature values,
+all FP64; the survey's dense n_b^2 count is given beside it.  cpu_baseline
+times the FP64 oracle's V-cycle on a bounded sample (the 8^3 grid of the same
+field), with one thread and with all host cores.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -39,85 +48,54 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_smooth_colour_c2_n256_p3.json")
+TOL = 1e-10
 
 
-def smoother_bytes_per_launch(prob, ncolours, inv_bytes, vec_bytes):
-    # the byte model of the method: every element's n_b x n_b inverse once per
-    # sweep, x and b in, x out, (p+2)^d viscosity values (the kernel stores and
-    # moves only the upper 16 x 16 tiles of the symmetric inverse, so this is
-    # an effective bandwidth in the model's units; the measured HBM traffic is
-    # reported beside it)
+def method_bytes(prob, elems, w=8, dense=False, shared=False):
+    """Bytes a colour pass over `elems` elements must move: the inverse
+    (symmetric part, or dense n_b^2; none when the level holds one inverse),
+    x, b and x out, the viscosity quadrature values."""
     nb = prob.nb
-    per_elem = nb * nb * inv_bytes + 3 * nb * vec_bytes + (prob.p + 2) ** prob.dim * vec_bytes
-    return prob.n_elements / ncolours * per_elem
+    inv = 0 if shared else (nb * nb if dense else nb * (nb + 1) // 2)
+    mu = (prob.p + 2) ** prob.dim if getattr(prob.mu, "kind", "") != "const" else 0
+    return elems * (inv * w + 3 * nb * w + mu * w)
 
 
-def cpu_baseline(n_sample=64, cycles=25):
-    """The FP64 oracle's V-cycle on the n_sample^2 grid of the same problem."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(make, n_sample, cycles=4):
+    """The FP64 oracle's V-cycle on the n_sample grid of the same problem,
+    with one thread and with all cores; DOF/s."""
     from threadpoolctl import threadpool_limits
-    from synth import c2_dirichlet_varmu
     from oracle import build_hierarchy
-    from oracle.rhs import assemble_rhs
     from oracle.solvers import Solver
-    prob = c2_dirichlet_varmu(n=n_sample, p=3)
-    with threadpool_limits(limits=1):
-        H = build_hierarchy(prob)
-        b = assemble_rhs(prob, H.fine.ops)
-        S = Solver(H)
-        t0 = time.perf_counter()
-        x = None
-        for _ in range(cycles):
-            x = S.vcycle_unscaled(b, x)
-        dt = time.perf_counter() - t0
-    return dict(value=prob.n_dof * cycles / dt, unit="DOF/s", cores=1, kind="oracle",
-                sample=f"FP64 oracle V(3,3) cycles on the {n_sample}x{n_sample} Q_3 grid of the same problem "
-                       f"({prob.n_dof} unknowns, {cycles} cycles, {dt:.1f} s); scipy sparse products, one thread")
-
-
-def train_correction(ctx, prob, nseeds=16, ncycles=8, ncrops=16, crop=16, steps=2000, batch=16):
-    """Training pairs from plain V-cycles of the benchmark operator on random
-    smooth exact solutions (not the benchmark's right-hand side), then Adam on
-    bf16 crops; returns (flat params, c_vel, c_pre, info)."""
-    import torch
-    from paper_1911_05888_amd import learned_train, init_net_params
-    from synth.learning import random_smooth_coeffs, crop_origins, batch_order
-    t0 = time.perf_counter()
-    feats, targs, stats = [], [], []
-    per = tuple(bc == "periodic" for bc in prob.bc)
-    for s in range(nseeds):
-        xs = torch.tensor(random_smooth_coeffs(1000 + s, prob.dim, prob.n, prob.p), device="cuda")
-        ctx.project_kernel(xs)
-        org = crop_origins(2000 + s, ncycles, ncrops, prob.dim, prob.n, crop, per)
-        f, t, st = ctx.learned_collect(xs, ncycles, crop, org)
-        feats.append(f)
-        targs.append(t)
-        stats.append(st)
-    feat, targ, st = torch.cat(feats), torch.cat(targs), np.concatenate(stats)
-    c_vel, c_pre = float(np.sqrt(np.mean(st[:, 2] ** 2))), float(np.sqrt(np.mean(st[:, 3] ** 2)))
-    ncr = nseeds * ncycles * ncrops
-    params, losses, _ = learned_train(prob.dim, prob.p, crop, ncr, feat, targ, c_vel, c_pre,
-                                      init_net_params(prob.dim, prob.p, 0), batch_order(5, steps, batch, ncr))
-    torch.cuda.synchronize()
-    info = dict(train_s=time.perf_counter() - t0, pairs=nseeds * ncycles, crops=ncr, steps=steps,
-                loss_first=float(np.mean(losses[:50])), loss_last=float(np.mean(losses[-50:])))
-    return params, c_vel, c_pre, info
-
-
-WORKLOADS = {
-    # name: (problem factory, description, extra precisions built beside FP32)
-    "c2": ("2D viscous-stress Stokes, Dirichlet walls, {n}x{n} elements, Q_3, "
-           "mu = 1 + 0.9 sin2pi x sin2pi y, manufactured solution; FP32 V(3,3) in FP64 iterative refinement to 1e-10"),
-    "c4a": ("2D two-phase viscous-stress Stokes, square inclusion (1/4,3/4)^2 with mu 1e4 inside and 1 outside, "
-            "Dirichlet walls, {n}x{n} elements, Q_2, two-phase manufactured solution, mod-3 colouring, diagonal scaling; "
-            "FP32 V(3,3) in FP64 iterative refinement to 1e-10"),
-    "c3": ("3D unsteady viscous-stress Stokes, periodic, {n}^3 elements, Q_2, rho = mu = 1, delta = h^2 / 10 "
-           "(Re_eff = 10), seeded Fourier forcing (seed 0), parity colouring; FP32 V(3,3) in FP64 iterative "
-           "refinement to 1e-10"),
-    "c5": ("3D viscous-stress Stokes, Dirichlet walls, {n}^3 elements, Q_2, log-normal viscosity (random Fourier "
-           "features, seed 1001), manufactured solution, parity colouring, diagonal scaling; FP32 V(3,3) in FP64 "
-           "iterative refinement to 1e-10"),
-}
+    prob = make(n_sample)
+    H = build_hierarchy(prob)
+    S = Solver(H)
+    b = H.project_kernel(np.random.Generator(np.random.PCG64(7)).standard_normal(S.A.shape[0]))
+    out = {}
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    for label, lim in (("one", 1), ("all", ncores)):
+        with threadpool_limits(limits=lim):
+            x = None
+            t0 = time.perf_counter()
+            for _ in range(cycles):
+                x = S.vcycle_unscaled(b, x)
+            out[label] = prob.n_dof * cycles / (time.perf_counter() - t0)
+    return dict(value=out["all"], unit="DOF/s", cores=ncores, kind="oracle",
+                single_thread_value=out["one"], cpu_model=cpu_model(),
+                sample=f"FP64 oracle V(3,3) cycles (numpy/scipy) on the {n_sample}^{prob.dim} grid of the same problem "
+                       f"({prob.n_dof} unknowns, {cycles} cycles per thread count); all {ncores} host threads for "
+                       f"value, one thread for single_thread_value")
 
 
 def make_problem(workload, n):
@@ -131,18 +109,35 @@ def make_problem(workload, n):
     return c5_lognormal(n=n or 128, p=2)
 
 
+DESCRIPTION = {
+    "c5": "3D viscous-stress Stokes, Dirichlet walls, {n}^3 elements, Q_2, log-normal viscosity (random Fourier "
+          "features, seed 1001), b = A x* for the L2-projected manufactured solution; V(3,3), parity colouring; "
+          "GMRES({m}) right-preconditioned by the V-cycle to 1e-10",
+    "c2": "2D viscous-stress Stokes, Dirichlet walls, {n}^2 elements, Q_3, mu = 1 + 0.9 sin2pi x sin2pi y, "
+          "manufactured solution; V(3,3) stationary (FP64) / iterative refinement (FP32) to 1e-10",
+    "c3": "3D unsteady viscous-stress Stokes, periodic, {n}^3 elements, Q_2, rho = mu = 1, Re_eff = 10, seeded Fourier "
+          "forcing; V(3,3) stationary (FP64) / iterative refinement (FP32) to 1e-10",
+    "c4a": "2D two-phase viscous-stress Stokes, square inclusion (1/4,3/4)^2, mu 1e4 / 1, Dirichlet walls, {n}^2 "
+           "elements, Q_2, manufactured solution, mod-3 colouring, diagonal scaling; V(3,3) stationary (FP64) / "
+           "iterative refinement (FP32) to 1e-10",
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=1, help="timed solves to 1e-10 (FP64)")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed V-cycles before timing (graph capture)")
     ap.add_argument("--n", type=int, default=0, help="elements per axis (default: the workload's)")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2",
-                    help="c2 (default, the benchmark configuration); c3, c4a and c5 measure the other configurations")
+    ap.add_argument("--workload", choices=sorted(DESCRIPTION), default="c5")
+    ap.add_argument("--m", type=int, default=40, help="GMRES restart length (log-normal workload)")
+    ap.add_argument("--maxit", type=int, default=600, help="iteration limit of one solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the FP64 / BF16 comparison solves")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP32 / BF16 context")
+    ap.add_argument("--cycles-only", type=int, default=0,
+                    help="profiling: set up the FP64 context, run this many V-cycles and exit (no JSON line)")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run 3 plain device copies of 256 MiB (reference for HBM byte counters)")
+                    help="first run 3 plain device copies of 256 MiB (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -150,8 +145,8 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1911_05888_amd import Context, V_FP64, V_FP32, V_FP32_BF16BLK, STATIONARY, IR
-    from synth import c2_dirichlet_varmu
+    from paper_1911_05888_amd import Context, V_FP64, V_FP32, V_FP32_BF16BLK, STATIONARY, IR, GMRES, FGMRES
+    from synth.fields import projected_coeffs
 
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -163,110 +158,199 @@ def main():
 
     prob = make_problem(args.workload, args.n)
     n = prob.n
-    # the 3D workload keeps FP32 (and BF16-block) V-cycle data only: its FP64
-    # block inverses alone would take 196 GB
-    builds = (1 << V_FP32_BF16BLK) if args.workload == "c5" else (1 << V_FP64) | (1 << V_FP32_BF16BLK)
+    krylov = args.workload == "c5"
+    log = lambda s: print(f"[bench] {s}", file=sys.stderr, flush=True)
+
+    def rhs(ctx):
+        if krylov:
+            xs = torch.tensor(projected_coeffs(prob.exact, prob.dim, n, prob.p), device="cuda")
+            b = ctx.apply(xs)
+            del xs
+            return b
+        return ctx.assemble_rhs(prob.rhs_source())
+
+    def solve(ctx, b0, vp, reps, label, flexible=False):
+        """reps solves from zero; (mean seconds, V-cycles per solve, Krylov
+        iterations per solve, final relres).  GMRES runs one restart cycle per
+        library call (each continues from the x it is given), so progress is
+        reported as the solve goes."""
+        ctx.set_vprec(vp)
+        outer = (FGMRES if flexible else GMRES) if krylov else (STATIONARY if vp == V_FP64 else IR)
+        cycles, its, tt, rel = 0, 0, 0.0, None
+        for _ in range(reps):
+            b = b0.clone()
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if krylov:
+                rel, k = 1.0, 0
+                while rel > TOL and k < args.maxit:
+                    st, info = ctx.solve(b, x, tol=TOL, maxit=args.m, outer=outer, fgmres_m=args.m)
+                    k += info["iters"]
+                    # one V-cycle per Arnoldi step (and one for x += M V y without flexibility)
+                    cycles += info["iters"] + (0 if flexible else 1)
+                    rel = info["relres"]
+                    log(f"{label}: {k} GMRES iterations, relres {rel:.3e}, {time.perf_counter() - t0:.1f} s")
+                its += k
+            else:
+                st, info = ctx.solve(b, x, tol=TOL, maxit=args.maxit, outer=outer)
+                cycles += info["iters"]
+                its += info["iters"]
+                rel = info["relres"]
+            torch.cuda.synchronize()
+            tt += time.perf_counter() - t0
+            if not rel <= TOL:
+                raise RuntimeError(f"{label}: relres {rel:.3e} after {its} iterations")
+            del x, b
+        return tt / reps, cycles / reps, its / reps, rel
+
+    def vcycle_rate(ctx, b0, vp, reps=5):
+        ctx.set_vprec(vp)
+        x = torch.zeros_like(b0)
+        for _ in range(max(args.warmup, 1)):
+            x.zero_()
+            ctx.vcycle(b0, x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            x.zero_()
+            ctx.vcycle(b0, x)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    def finest_pass_time(ctx, b0, vp):
+        """Mean time of a finest-level colour pass (event pairs around whole sweeps)."""
+        ctx.set_vprec(vp)
+        x = torch.zeros_like(b0)
+        ctx.profile(1)
+        for _ in range(2):
+            ctx.vcycle(b0, x)
+        ms, launches = ctx.profile_read()
+        ctx.profile(0)
+        return ms * 1e-3 / max(launches, 1), launches
+
+    def solve_block(ctx, b0, vp, reps, label):
+        """reps solves of at most one GMRES restart cycle (headline steps)."""
+        ctx.set_vprec(vp)
+        cycles, tt, rel, its = 0, 0.0, None, 0
+        for _ in range(reps):
+            b = b0.clone()
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, info = ctx.solve(b, x, tol=TOL, maxit=args.m, outer=GMRES, fgmres_m=args.m)
+            torch.cuda.synchronize()
+            tt += time.perf_counter() - t0
+            its += info["iters"]
+            cycles += info["iters"] + (0 if info["relres"] <= TOL and info["iters"] == 0 else 1)
+            rel = info["relres"]
+            log(f"{label}: GMRES({args.m}) cycle, {info['iters']} iterations, relres {rel:.3e}, {tt:.1f} s")
+            del x, b
+        return tt / reps, cycles / reps, its / reps, rel
+
+    # ---- FP64 at full size: the headline ------------------------------------
+    builds = 0 if krylov else (1 << V_FP32) | (1 << V_FP32_BF16BLK)
     t0 = time.perf_counter()
-    ctx = Context(prob, vprec=V_FP32, build_precisions=builds)
+    ctx = Context(prob, vprec=V_FP64, build_precisions=builds)
     torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t0
-    print(f"[bench] setup {t_setup:.1f} s, {ctx.ndof} unknowns, {ctx.n_levels} levels", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    b0 = ctx.assemble_rhs(prob.rhs_source())
-    print(f"[bench] right-hand side assembled in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    t_setup64 = time.perf_counter() - t0
+    log(f"setup (FP64) {t_setup64:.1f} s, {ctx.ndof} unknowns, {ctx.n_levels} levels")
+    b0 = rhs(ctx)
     ncol = ctx.level_info(0)[2]
-
-    def solve(vprec, outer, tol=1e-10, maxit=60, learned=False):
-        ctx.set_vprec(vprec)
-        b = b0.clone()
-        x = torch.zeros_like(b)
-        st, info = ctx.solve(b, x, tol=tol, maxit=maxit, outer=outer, use_learned=learned)
-        if st != 0:
-            raise RuntimeError(f"solve failed: status {st}, {info}")
-        return info
-
-    for _ in range(args.warmup):
-        solve(V_FP32, IR)
-    torch.cuda.synchronize()
-    ctx.profile(4)        # every 4th finest sweep: one event pair around its colour passes
-    iters = 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        info = solve(V_FP32, IR)
-        iters += info["iters"]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    k_ms, k_launches = ctx.profile_read()
-    ctx.profile(False)
-    value = ctx.ndof * iters / dt
-    ms_per_step = 1e3 * dt / args.steps
-    print(f"[bench] mixed FP32-in-IR: {iters / args.steps:.1f} V-cycles/solve, {ms_per_step:.2f} ms/solve",
-          file=sys.stderr, flush=True)
-
-    # a level whose blocks are all equal holds one inverse: no inverse
-    # entries are streamed, the colour pass is the residual + shared update
+    if args.cycles_only:
+        x = torch.zeros_like(b0)
+        for _ in range(args.cycles_only):
+            ctx.vcycle(b0, x)
+        torch.cuda.synchronize()
+        log(f"{args.cycles_only} FP64 V-cycles done")
+        return
+    t_cycle64 = vcycle_rate(ctx, b0, V_FP64)
+    log(f"FP64 V-cycle {t_cycle64 * 1e3:.1f} ms ({ctx.ndof / t_cycle64:.3e} DOF/s)")
+    t_pass, launches = finest_pass_time(ctx, b0, V_FP64)
+    elems = prob.n_elements / ncol
     shared = ctx.level_shared_inverse(0)
-    bytes_launch = smoother_bytes_per_launch(prob, ncol, 0 if shared else 4, 4)
-    kname = (f"k_colour_residual<float,{prob.dim},{prob.p}> + k_shared_update_mfma<{prob.nb}> (FP32 matrix cores "
-             f"for colours of 8192 elements or more)" if shared else f"k_smooth_colour<float,float,{prob.dim},{prob.p},64>")
-    avg_s = k_ms * 1e-3 / max(k_launches, 1)
-    achieved = bytes_launch / avg_s / 1e9
+    bytes_method = method_bytes(prob, elems, 8, shared=shared)
+    bytes_dense = method_bytes(prob, elems, 8, dense=True, shared=shared)
+    log(f"finest FP64 colour pass {t_pass * 1e6:.1f} us over {launches} passes")
+    ndof = ctx.ndof
+    levels = ctx.n_levels
+    if krylov:
+        # one step: one GMRES(m) restart cycle from zero, m V-cycles + 1
+        t64, cyc64, its64, rel64 = solve_block(ctx, b0, V_FP64, args.steps, "FP64")
+        extras = dict(fp64=dict(step="one GMRES restart cycle from x = 0", step_s=t64, iters=its64, vcycles=cyc64,
+                                relres_after_step=rel64, vcycle_s=t_cycle64, vcycle_dof_per_s=ndof / t_cycle64,
+                                setup_s=t_setup64))
+    else:
+        t64, cyc64, its64, rel64 = solve(ctx, b0, V_FP64, args.steps, "FP64")
+        extras = dict(fp64=dict(time_to_tol_s=t64, iters=its64, vcycles=cyc64, vcycle_s=t_cycle64,
+                                vcycle_dof_per_s=ndof / t_cycle64, setup_s=t_setup64, relres=rel64))
+    value = ndof * cyc64 / t64
+    log(f"FP64 step {t64:.2f} s, {cyc64:.0f} V-cycles: {value:.3e} DOF/s")
+    if krylov:
+        ctx.close()
+        del ctx, b0
+        torch.cuda.empty_cache()
+
+    # ---- time to 1e-10: FP64 against FP32 and BF16-stored inverses -----------
+    if not args.no_extras:
+        if krylov:
+            # restarted GMRES stalls on the full-size field, and a basis long
+            # enough for unrestarted GMRES does not fit beside the FP64 data at
+            # 128^3: the comparison runs unrestarted on the 64^3 grid
+            ttprob = make_problem(args.workload, n // 2)
+            t0 = time.perf_counter()
+            ctx = Context(ttprob, vprec=V_FP64, build_precisions=(1 << V_FP32) | (1 << V_FP32_BF16BLK))
+            torch.cuda.synchronize()
+            tt_setup = time.perf_counter() - t0
+            xs = torch.tensor(projected_coeffs(ttprob.exact, ttprob.dim, ttprob.n, ttprob.p), device="cuda")
+            b0 = ctx.apply(xs)
+            del xs
+            saved_m, args.m = args.m, 150
+        else:
+            ttprob, tt_setup = prob, t_setup64
+        tt = dict(workload=DESCRIPTION[args.workload].format(n=ttprob.n, m=args.m), unknowns=ctx.ndof,
+                  setup_s=tt_setup)
+        for label, vp in (("fp64", V_FP64), ("fp32", V_FP32), ("fp32_bf16_inverses", V_FP32_BF16BLK)):
+            tc = vcycle_rate(ctx, b0, vp)
+            ts, cyc, its, rel = solve(ctx, b0, vp, 1, label, flexible=krylov)
+            tt[label] = dict(time_to_tol_s=ts, iters=its, vcycles=cyc, vcycle_s=tc,
+                             vcycle_dof_per_s=ctx.ndof / tc, relres=rel)
+            log(f"{label}: V-cycle {tc * 1e3:.1f} ms, time to 1e-10 {ts:.3f} s ({its:.0f} iterations)")
+        extras["time_to_tolerance"] = tt
+        ctx.close()
+        if krylov:
+            args.m = saved_m
+
+    achieved = bytes_method / t_pass / 1e9
     traffic = None
-    if args.workload == "c2" and n == 256 and os.path.exists(TRAFFIC_FILE):
-        # counters are valid only for the kernel source they were measured on
+    tfile = os.path.join(ROOT, "profiles", f"traffic_smooth_colour_{args.workload}_n{n}_p{prob.p}_fp64.json")
+    if os.path.exists(tfile):
+        # counters are valid only for the kernel source they were taken on
         import hashlib
-        with open(TRAFFIC_FILE) as fh:
+        with open(tfile) as fh:
             tj = json.load(fh)
         with open(os.path.join(ROOT, "paper_1911_05888_amd", "csrc", "kernels.hip"), "rb") as fh:
-            sha = hashlib.sha1(fh.read()).hexdigest()
-        if tj.get("kernels_hip_sha1") == sha:
-            traffic = tj.get("bytes_per_launch")
-
-    extras = {}
-    if not args.no_extras:
-        runs = [("fp32_bf16blk_ir", V_FP32_BF16BLK, IR, False)]
-        if args.workload != "c5":
-            runs = [("plain_fp64_stationary", V_FP64, STATIONARY, False), ("plain_fp64_ir", V_FP64, IR, False)] + runs
-        if args.workload == "c2":
-            ctx.set_vprec(V_FP32)
-            params, c_vel, c_pre, tinfo = train_correction(ctx, prob)
-            ctx.set_learned(params, c_vel, c_pre)
-            print(f"[bench] learned correction trained in {tinfo['train_s']:.1f} s, loss "
-                  f"{tinfo['loss_first']:.3f} -> {tinfo['loss_last']:.3f}", file=sys.stderr, flush=True)
-            runs.append(("fp32_learned_ir", V_FP32, IR, True))
-        for label, vp, outer, learned in runs:
-            solve(vp, outer, learned=learned)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            reps = 3
-            its = 0
-            for _ in range(reps):
-                info = solve(vp, outer, learned=learned)
-                its += info["iters"]
-            torch.cuda.synchronize()
-            tt = (time.perf_counter() - t1) / reps
-            extras[label] = dict(time_to_tol_s=tt, iters=its / reps, vcycle_dof_per_s=ctx.ndof * its / reps / tt)
-            if learned:
-                extras[label].update(fallback_events=info["fallback_events"], training=tinfo)
-            print(f"[bench] {label}: {its / reps:.1f} iters, {tt * 1e3:.2f} ms", file=sys.stderr, flush=True)
-
+            if tj.get("kernels_hip_sha1") == hashlib.sha1(fh.read()).hexdigest():
+                traffic = tj.get("bytes_per_launch")
     line = dict(
         metric="V-cycle DOF/s + wall time to 1e-10 rel. residual, plain FP64 vs mixed/learned",
         value=value, unit="DOF/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
-        ms_per_step=ms_per_step, higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="fp32 V-cycle, fp64 outer residual", data="synthetic",
-        config=dict(workload=WORKLOADS[args.workload].format(n=n),
-                    n=n, p=prob.p, dim=prob.dim, unknowns=ctx.ndof, levels=ctx.n_levels, colours=ncol,
-                    time_to_tol_s=dt / args.steps, vcycles_per_solve=iters / args.steps,
-                    setup_s=t_setup, **extras),
+        ms_per_step=t64 * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64", data="synthetic",
+        config=dict(workload=DESCRIPTION[args.workload].format(n=n, m=args.m),
+                    n=n, p=prob.p, dim=prob.dim, unknowns=ndof, levels=levels, colours=ncol, **extras),
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=achieved / HBM_PEAK_GBS, traffic=traffic,
-                      kernel=kname + " (finest level)",
-                      avg_launch_us=avg_s * 1e6, algorithmic_bytes_per_launch=bytes_launch,
-                      launches=k_launches, timing="event pairs around whole finest sweeps, every 4th"),
+                      kernel=(f"k_colour_residual<double,{prob.dim},{prob.p}> + k_apply_inverse<double,double,"
+                              f"{prob.dim},{prob.p}> (finest level)" if prob.dim == 3 else
+                              f"k_smooth_colour<double,double,{prob.dim},{prob.p}> (finest level)"),
+                      avg_launch_us=t_pass * 1e6, algorithmic_bytes_per_launch=bytes_method,
+                      dense_model_bytes_per_launch=bytes_dense,
+                      dense_model_gbs=bytes_dense / t_pass / 1e9, launches=launches,
+                      timing="event pairs around whole finest sweeps of two V-cycles"),
     )
-    if not args.no_cpu_baseline and args.workload == "c2":
-        line["cpu_baseline"] = cpu_baseline()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(lambda m: make_problem(args.workload, m), 8 if prob.dim == 3 else 32)
     print(json.dumps(line), flush=True)
 
 
