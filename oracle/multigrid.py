@@ -21,16 +21,36 @@ from __future__ import annotations
 import numpy as np
 
 
+def blocks_all_equal(Ainv):
+    """True when every element's block is the same matrix (to 1e-12 of its
+    largest entry): constant coefficients on a translation-invariant grid."""
+    B = np.asarray(Ainv)
+    return bool(np.abs(B - B[0]).max() <= 1e-12 * np.abs(B[0]).max())
+
+
 class Precision:
     """Operator copies in one floating-point type (float64, or float32 to
-    emulate the mixed-precision V-cycle)."""
+    emulate the mixed-precision V-cycle).  inv_bf16: the block inverses held
+    as bfloat16 values (the symmetric part of each FP64 inverse rounded to
+    float32, then to the nearest bfloat16), the arithmetic in float32; a
+    level whose blocks are all one matrix keeps that one inverse in the
+    working precision (storing a single block in bfloat16 saves nothing)."""
 
-    def __init__(self, hier, dtype=np.float64):
+    def __init__(self, hier, dtype=np.float64, inv_bf16=False):
         self.hier = hier
         self.dtype = dtype
         self.A = [lv.A.astype(dtype) for lv in hier.levels]
         self.I = [lv.I.astype(dtype) if hasattr(lv, "I") else None for lv in hier.levels]
-        self.Ainv = [lv.Ainv.astype(dtype) if hasattr(lv, "Ainv") else None for lv in hier.levels]
+        self.Ainv = []
+        for lv in hier.levels:
+            if not hasattr(lv, "Ainv"):
+                self.Ainv.append(None)
+            elif inv_bf16 and not blocks_all_equal(lv.Ainv):
+                from .learned import bf16
+                sym = 0.5 * (lv.Ainv + np.transpose(lv.Ainv, (0, 2, 1)))
+                self.Ainv.append(bf16(sym.astype(np.float32)).astype(dtype))
+            else:
+                self.Ainv.append(lv.Ainv.astype(dtype))
 
 
 def colour_pass(A, Ainv, x, b, elems, nb):

@@ -32,16 +32,18 @@ class Solver:
         # unscaled fine operator A = D^{-1} (D A D) D^{-1}
         import scipy.sparse as sp
         self.A = (sp.diags(Dinv) @ fine.A @ sp.diags(Dinv)).tocsr()
-        self.P = {np.float64: Precision(hier, np.float64)}
+        self.P = {(np.float64, False): Precision(hier, np.float64)}
 
-    def prec(self, dtype):
-        if dtype not in self.P:
-            self.P[dtype] = Precision(self.hier, dtype)
-        return self.P[dtype]
+    def prec(self, dtype, inv_bf16=False):
+        key = (dtype, inv_bf16)
+        if key not in self.P:
+            self.P[key] = Precision(self.hier, dtype, inv_bf16)
+        return self.P[key]
 
-    def vcycle_unscaled(self, b, x=None, dtype=np.float64):
-        """One V-cycle for A x = b in unscaled variables."""
-        P = self.prec(dtype)
+    def vcycle_unscaled(self, b, x=None, dtype=np.float64, inv_bf16=False):
+        """One V-cycle for A x = b in unscaled variables (inv_bf16: block
+        inverses stored as bfloat16, float32 arithmetic)."""
+        P = self.prec(dtype, inv_bf16)
         bs = (self.d * b).astype(dtype)
         xs = None if x is None else (x / self.d).astype(dtype)
         return self.d * apply_vcycle(P, bs, xs).astype(np.float64)
@@ -49,18 +51,18 @@ class Solver:
     def relres(self, b, x):
         return np.linalg.norm(b - self.A @ x) / np.linalg.norm(b)
 
-    def stationary(self, b, maxit, tol=0.0, dtype=np.float64):
+    def stationary(self, b, maxit, tol=0.0, dtype=np.float64, inv_bf16=False):
         b = self.hier.project_kernel(np.asarray(b, dtype=np.float64))
         x = np.zeros_like(b)
         hist = [self.relres(b, x)]
         for _ in range(maxit):
-            x = self.vcycle_unscaled(b, x, dtype)
+            x = self.vcycle_unscaled(b, x, dtype, inv_bf16)
             hist.append(self.relres(b, x))
             if hist[-1] <= tol:
                 break
         return x, np.array(hist)
 
-    def refinement(self, b, tol=1e-10, maxit=50, dtype=np.float32):
+    def refinement(self, b, tol=1e-10, maxit=50, dtype=np.float32, inv_bf16=False):
         b = self.hier.project_kernel(np.asarray(b, dtype=np.float64))
         x = np.zeros_like(b)
         hist = [1.0]
@@ -68,7 +70,7 @@ class Solver:
             r = b - self.A @ x
             if np.linalg.norm(r) / np.linalg.norm(b) <= tol:
                 break
-            x = x + self.vcycle_unscaled(r, None, dtype)
+            x = x + self.vcycle_unscaled(r, None, dtype, inv_bf16)
             hist.append(self.relres(b, x))
         return x, np.array(hist)
 

@@ -4,7 +4,7 @@ above the bottom.
 
 The one-level and two-level residual histories are compared with the
 oracle's stationary V-cycle iteration, as in the parity suite (|rho_k^gpu -
-rho_k^oracle| <= 1e-11 times the largest rho of the run).
+rho_k^oracle| <= 1e-11 max(1, rho_{k-1}, rho_k)).
 """
 import numpy as np
 import pytest
@@ -44,8 +44,8 @@ def test_short_hierarchies_match_oracle(name):
     print(name, "rho_k gpu", hist_g, "oracle", hist_o, flush=True)
     # tol = 0 is never reached: the solve stops at maxit and reports it
     assert st == 7 and len(hist_g) == len(hist_o)
-    scale = max(1.0, np.abs(hist_o).max())
-    assert np.abs(hist_g - hist_o).max() <= 1e-11 * scale
+    scale = np.maximum(np.maximum(1.0, hist_o), np.concatenate([[1.0], hist_o[:-1]]))
+    assert np.all(np.abs(hist_g - hist_o) <= 1e-11 * scale)
     if len(prob.levels()) == 1:
         # an exact solve up to the kernel: the first cycle leaves rounding
         assert hist_g[1] <= 1e-10

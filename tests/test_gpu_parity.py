@@ -8,14 +8,21 @@ oracle builds its own b for the RHS parity test).  Tolerances:
 * bottom solve: residual at the rounding level of b - A x (both sides apply the least-squares
   pseudo-inverse with one refinement step); the solution itself is determined
   only to eps * cond(A_c), so it is compared to 1e-7;
-* V-cycle residual history: |rho_k^gpu - rho_k^oracle| <= 1e-11 with
-  rho_k = ||r_k|| / ||r_0|| (reading of the stated "relative 1e-11": relative
-  to the initial residual, the only scale above FP64 rounding at every k).
+* V-cycle residual history: |rho_k^gpu - rho_k^oracle| <= 1e-11 max(1,
+  rho_{k-1}, rho_k) + u F_k with rho_k = ||r_k|| / ||r_0|| (reading of the
+  stated "relative 1e-11": relative to the larger of the residuals the cycle
+  starts from and ends at, never below the initial one), u = 2^-53 and
+  F_k = || |A| |x_k| + |b| || / ||b||, the first-order rounding bound of
+  b - A x_k itself, which no evaluation of the residual gets below.  F_k is
+  about 7e3 for the single-phase cases (u F_k < 1e-12, so the 1e-11 term
+  decides) and 6e6 for the 1e4 viscosity contrast of the inclusion (u F_k
+  about 7e-10); test_gpu_history.py holds the inclusion to 1e-11 per cycle
+  in the scaled norm ||D (b - A x)||, where that floor is small.
 """
 import numpy as np
 import pytest
 
-from synth import (Problem, c1_periodic_standard, c2_dirichlet_varmu, c3_unsteady_periodic, c4a_square_inclusion,
+from synth import (Problem, SinProductField, c1_periodic_standard, c2_dirichlet_varmu, c3_unsteady_periodic, c4a_square_inclusion,
                    c5_lognormal)
 
 pytestmark = pytest.mark.gpu
@@ -26,10 +33,15 @@ CASES = {
     "c2_n16_p2": lambda: c2_dirichlet_varmu(n=16, p=2),
     "per3d_n8_p2": lambda: Problem(name="per3d_n8_p2", dim=3, n=8, p=2, gamma=1, bc=("periodic",) * 3),
     "c3_n8_p2": lambda: c3_unsteady_periodic(n=8, p=2, re_eff=10.0, h_ref=1.0 / 64),
+    "c3_n8_p2_re0.1": lambda: c3_unsteady_periodic(n=8, p=2, re_eff=0.1, h_ref=1.0 / 64),
+    "c3_n8_p2_re1000": lambda: c3_unsteady_periodic(n=8, p=2, re_eff=1000.0, h_ref=1.0 / 64),
     "c4a_n16_p2": lambda: c4a_square_inclusion(n=16, p=2),
     "c4a_n32_p1": lambda: c4a_square_inclusion(n=32, p=1),
     "c5_n8_p2": lambda: c5_lognormal(n=8, p=2),
     "c5_n8_p2_scaled": lambda: c5_lognormal(n=8, p=2, diag_scaling=True),
+    # eq. (mu) in 3D with Dirichlet walls: distinct blocks on every level, a contracting cycle
+    "mu3d_n8_p2": lambda: Problem(name="mu3d_n8_p2", dim=3, n=8, p=2, gamma=1, bc=("dirichlet",) * 3,
+                                  mu=SinProductField(1.0, 0.5, 2.0), coloring="parity"),
 }
 
 _cache = {}
@@ -177,27 +189,35 @@ def test_apply_and_rhs_fine(name):
     assert rel(y, Solver(H).A @ x) <= 1e-12
 
 
-@pytest.mark.parametrize("name", ["c1_n16_p2", "c2_n32_p3", "per3d_n8_p2", "c3_n8_p2", "c4a_n16_p2", "c4a_n32_p1",
-                                  "c5_n8_p2"])
+@pytest.mark.parametrize("name", ["c1_n16_p2", "c2_n32_p3", "per3d_n8_p2", "c3_n8_p2", "c3_n8_p2_re0.1",
+                                  "c3_n8_p2_re1000", "c4a_n16_p2", "c4a_n32_p1", "c5_n8_p2", "c5_n8_p2_scaled",
+                                  "mu3d_n8_p2"])
 def test_vcycle_residual_history(name):
-    """Stationary FP64 V-cycle: rho_k within 1e-11 (times the largest rho of the
-    run) of the oracle's for k <= 8."""
+    """Stationary FP64 V-cycle: rho_k within 1e-11 max(1, rho_{k-1}, rho_k)
+    + u F_k of the oracle's for k <= 8."""
     from oracle.solvers import Solver
     prob, H, ctx = setup_case(name)
     rng = np.random.Generator(np.random.PCG64(17))
     b = H.project_kernel(rng.standard_normal(H.fine.A.shape[0]))
-    _, hist_o = Solver(H).stationary(b, 8)
+    S = Solver(H)
+    absA = abs(S.A)
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    hist_o, floor = [1.0], [0.0]
+    for _ in range(8):
+        x = S.vcycle_unscaled(b, x)
+        hist_o.append(np.linalg.norm(b - S.A @ x) / nb)
+        floor.append(2.0 ** -53 * np.linalg.norm(absA @ np.abs(x) + np.abs(b)) / nb)
+    hist_o, floor = np.array(hist_o), np.array(floor)
     bg = dev(b)
     xg = dev(np.zeros_like(b))
     st, info = ctx.solve(bg, xg, tol=0.0, maxit=8)
     hist_g = info["history"]
     assert len(hist_g) == len(hist_o)
     print(name, "rho_k gpu", hist_g, "oracle", hist_o)
-    # relative to the largest residual of the run: ||r_0|| unless a cycle raises
-    # the residual (the first cycle does, by 1e4, for the 1e4 viscosity
-    # contrast of the inclusion in the unscaled norm)
-    scale = max(1.0, np.abs(hist_o).max())
-    assert np.abs(hist_g - hist_o).max() <= 1e-11 * scale, np.abs(hist_g - hist_o)
+    scale = np.maximum(np.maximum(1.0, hist_o), np.concatenate([[1.0], hist_o[:-1]]))
+    bar = 1e-11 * scale + floor
+    assert np.all(np.abs(hist_g - hist_o) <= bar), (np.abs(hist_g - hist_o), bar)
 
 
 @pytest.mark.parametrize("name", ["c1_n16_p2", "c2_n32_p3"])
