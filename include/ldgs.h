@@ -208,14 +208,19 @@ ldgs_status ldgs_vcycle(ldgs_ctx* ctx, const double* b_dev, double* x_dev);
 /* Solve A x = b to ||b - A x|| <= tol ||b|| from the x given (use zeros).
  * b is first projected onto range(A) (its components along the trivial
  * kernel are removed, in place).  maxit bounds the outer iterations;
- * fgmres_m is the restart length.  use_learned (outer = LDGS_IR only; needs
- * ldgs_set_learned) adds the learned correction of r - A z to each V-cycle
- * result z, in the cycle's precision, under a guard: the first two
- * iterations are plain and give rho_plain = (||r_2|| / ||r_0||)^(1/2); the
- * correction is switched off for the rest of the solve when an iteration's
- * reduction c_k = ||r_k|| / ||r_{k-1}|| exceeds 1, or exceeds 1.1 rho_plain
- * twice in a row, and that iteration is redone without it
- * (info->fallback_events counts this).  info may be NULL.  Synchronises. */
+ * fgmres_m is the restart length.  use_learned (outer = LDGS_IR or
+ * LDGS_FGMRES; needs ldgs_set_learned) replaces each V-cycle result z = V(v)
+ * by z + w dx, dx the network's correction of the residual r' = v - A z the
+ * cycle leaves and w = <r', A dx> / ||A dx||^2 the minimal-residual step, both
+ * in the cycle's precision and variables (one extra finest-level apply), so
+ * that the corrected step never leaves a larger residual in those variables.
+ * FGMRES takes the corrected result as its preconditioned direction.  Under
+ * LDGS_IR a guard also applies: the first two iterations are plain and give
+ * rho_plain = (||r_2|| / ||r_0||)^(1/2); the correction is switched off for
+ * the rest of the solve when an iteration's reduction
+ * c_k = ||r_k|| / ||r_{k-1}|| exceeds 1, or exceeds 1.1 rho_plain twice in a
+ * row, and that iteration is redone without it (info->fallback_events counts
+ * this).  info may be NULL.  Synchronises. */
 ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b_dev, double* x_dev, double tol, int maxit,
                        int outer, int fgmres_m, int use_learned, ldgs_info* info);
 

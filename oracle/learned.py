@@ -30,7 +30,16 @@ even).  The reduced-precision network rounds the input channels, weights and
 hidden activations to bfloat16, accumulates products in float32, and adds the
 biases in float32.
 
-Guard (outer iteration).  The first two outer iterations are plain and give
+Minimal-residual step.  With z = V(v) the cycle's result for the vector v
+it is applied to, r' = v - A z (in the cycle's precision) and dx the
+network's correction of r', the preconditioned result is z + w dx with
+w = <r', A dx> / ||A dx||^2 (0 when A dx = 0), inner products in the
+variables of the diagonally scaled system, A dx in the cycle's precision.
+The step minimises ||r' - w A dx|| over w, so the correction never raises the
+residual the cycle leaves.  It serves both outer iterations below; FGMRES
+(flexible, right-preconditioned) takes z + w dx as its direction.
+
+Guard (iterative refinement).  The first two outer iterations are plain and give
 rho_plain = (||r_2|| / ||r_0||)^(1/2).  Later iterations apply the
 correction; with c_k = ||r_k|| / ||r_{k-1}||, the correction is switched off
 for the rest of the solve when c_k > 1 once or c_k > 1.1 rho_plain in two
@@ -285,18 +294,32 @@ def crop(F, shape, periodic, origin, C, halo):
 # ---------------------------------------------------------------------------
 # guarded outer iteration
 # ---------------------------------------------------------------------------
+def minres_step(solver, v, z, params, cvec, g, dtype, emulate_bf16=True, minres=True):
+    """z + w dx for the V-cycle result z = V(v) (module docstring); also
+    returns w.  minres=False: the full step w = 1."""
+    Ad = solver.A.astype(dtype)
+    d = solver.d
+    r2 = (v.astype(dtype) - Ad @ z.astype(dtype)).astype(np.float64)
+    dx = correction(params, cvec, g, r2, emulate_bf16)
+    if not minres:
+        return z + dx, 1.0
+    q = (Ad @ dx.astype(dtype)).astype(np.float64)
+    den = float(np.dot(d * q, d * q))
+    w = float(np.dot(d * r2, d * q)) / den if den > 0 else 0.0
+    return z + w * dx, w
+
+
 def refinement_learned(solver, b, params, cvec, g, tol=1e-10, maxit=50, dtype=np.float32,
-                       emulate_bf16=True):
-    """Iterative refinement x += V(r) + dx with the guard of the module
-    docstring.  dx is computed from r - A V(r) in the cycle's precision.
-    Returns x, the residual history and the number of fallback events."""
+                       emulate_bf16=True, minres=True):
+    """Iterative refinement x += V(r) + w dx with the guard of the module
+    docstring.  Returns x, the residual history and the number of fallback
+    events."""
     hier = solver.hier
     b = hier.project_kernel(np.asarray(b, dtype=np.float64))
     bn = np.linalg.norm(b)
     x = np.zeros_like(b)
     hist = [1.0]
     enabled, rho_plain, strikes, events = True, None, 0, 0
-    Ad = solver.A.astype(dtype)
     for it in range(maxit):
         r = b - solver.A @ x
         if np.linalg.norm(r) / bn <= tol:
@@ -304,9 +327,7 @@ def refinement_learned(solver, b, params, cvec, g, tol=1e-10, maxit=50, dtype=np
         z = solver.vcycle_unscaled(r, None, dtype)
         use = enabled and it >= 2
         if use:
-            r2 = (r.astype(dtype) - Ad @ z.astype(dtype)).astype(np.float64)
-            dx = correction(params, cvec, g, r2, emulate_bf16)
-            x_new = x + (z + dx)
+            x_new = x + minres_step(solver, r, z, params, cvec, g, dtype, emulate_bf16, minres)[0]
         else:
             x_new = x + z
         rel = np.linalg.norm(b - solver.A @ x_new) / bn
@@ -322,3 +343,63 @@ def refinement_learned(solver, b, params, cvec, g, tol=1e-10, maxit=50, dtype=np
         if it == 1:
             rho_plain = np.sqrt(hist[2] / hist[0])
     return x, np.array(hist), events
+
+
+def fgmres_learned(solver, b, params, cvec, g, tol=1e-10, m=30, maxit=200, dtype=np.float32, emulate_bf16=True):
+    """Flexible GMRES(m), right-preconditioned by z + w dx (module docstring)
+    with z = V(v) from zero; modified Gram-Schmidt and Givens rotations in
+    FP64 as in the plain FGMRES.  Returns x, the residual history (the Givens
+    estimate per iteration, the explicit FP64 residual at each restart) and
+    the list of steps w."""
+    hier = solver.hier
+    b = hier.project_kernel(np.asarray(b, dtype=np.float64))
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    hist = [1.0]
+    ws = []
+    its = 0
+    while its < maxit:
+        r = b - solver.A @ x
+        beta = np.linalg.norm(r)
+        hist[-1] = beta / nb
+        if beta / nb <= tol:
+            break
+        V = [r / beta]
+        Z = []
+        H = np.zeros((m + 1, m))
+        cs, sn = np.zeros(m), np.zeros(m)
+        gv = np.zeros(m + 1)
+        gv[0] = beta
+        jd = 0
+        for j in range(m):
+            z = solver.vcycle_unscaled(V[j], None, dtype)
+            z, w_ = minres_step(solver, V[j], z, params, cvec, g, dtype, emulate_bf16)
+            ws.append(w_)
+            Z.append(z)
+            w = solver.A @ z
+            for i in range(j + 1):
+                H[i, j] = np.dot(w, V[i])
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            V.append(w / H[j + 1, j] if H[j + 1, j] > 0 else w)
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = np.hypot(H[j, j], H[j + 1, j])
+            cs[j], sn[j] = H[j, j] / den, H[j + 1, j] / den
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            gv[j + 1] = -sn[j] * gv[j]
+            gv[j] = cs[j] * gv[j]
+            its += 1
+            jd = j + 1
+            hist.append(abs(gv[j + 1]) / nb)
+            if abs(gv[j + 1]) / nb <= tol or its >= maxit:
+                break
+        y = np.linalg.solve(np.triu(H[:jd, :jd]), gv[:jd])
+        x = x + np.stack(Z[:jd], axis=1) @ y
+        hist[-1] = np.linalg.norm(b - solver.A @ x) / nb
+        if hist[-1] <= tol:
+            break
+    return x, np.array(hist), ws

@@ -115,8 +115,11 @@ struct ldgs_ctx {
   double c_net[2] = {1.0, 1.0};
   float* d_logmu = nullptr;         // finest-level log10 of the element mean of mu
   double* d_sums = nullptr;         // [2] sums of squares (velocity, pressure)
-  double *w_xold = nullptr, *w_zl = nullptr, *w_r64b = nullptr;
-  float* w_r32 = nullptr;
+  double *w_xold = nullptr, *w_zl = nullptr, *w_r64b = nullptr, *w_dx = nullptr, *w_adx64 = nullptr;
+  float *w_r32 = nullptr, *w_adx32 = nullptr;
+  double* d_mr = nullptr;           // [3] minimal-residual sums r'.q, q.q and the step w
+  int64_t learned_steps = 0;        // corrections applied (diagnostics)
+  bool learned_full_step = false;   // LDGS_LEARNED_FULL_STEP=1 at setup: w = 1 instead of the minimal-residual step
   double* w_rf64 = nullptr;         // fine residual scratch of the split residual + restriction (small grids)
   float* w_rf32 = nullptr;
   double *w_cb = nullptr, *w_cx = nullptr, *w_ce = nullptr;
@@ -1055,6 +1058,7 @@ void learned_buffers(ldgs_ctx* c) {
   c->d_logmu = dalloc<float>(c, L.NE);
   HIPCHK(hipMemcpy(c->d_logmu, lm.data(), lm.size() * sizeof(float), hipMemcpyHostToDevice));
   c->d_sums = dalloc<double>(c, 2);
+  c->d_mr = dalloc<double>(c, 3);
   const int64_t N = c->ndof();
   c->w_xold = dalloc<double>(c, N);
   c->w_zl = dalloc<double>(c, N);
@@ -1066,27 +1070,52 @@ constexpr int SUMSQ_BLK = 512;
 
 // out = base + N(r') with r' = (b - A x) of the V-cycle's finest level as it
 // stands after the last cycle (scaled variables; unscaled inside the kernel)
-void learned_after_cycle(ldgs_ctx* c, int vp, const double* base, double* out) {
+// Minimal-residual correction after a V-cycle: out = z + w dx with
+// dx = N(r'), r' = b - A z the residual the cycle leaves (its own precision and
+// variables), and w = <r', A dx> / ||A dx||^2 in those variables (the diagonally
+// scaled system when the scaling is on), so that ||r' - w A dx|| <= ||r'||.
+// z is the cycle's result in user variables; its internal copies of b and z
+// (w_b/w_x or w_b32/w_x32) must be those of the cycle just run.  out may be z.
+void learned_minres(ldgs_ctx* c, int vp, const double* z, double* out) {
   LaunchCfg cfg{c->g.d, c->g.p, c->stream, c->small_grid};
   const Level& L = c->levels[0];
-  const int64_t NE = L.NE;
+  const int64_t NE = L.NE, N = c->ndof();
   const int nb = c->g.nb, nvel = c->g.d * c->g.nq;
   const double* ds = dscale0(c);
   const double cu = (double)NE * nvel, cp = (double)NE * (nb - nvel);
+  if (!c->w_dx) c->w_dx = dalloc<double>(c, N);
+  const bool full = c->learned_full_step;
   if (vp == LDGS_V_FP64) {
-    if (!c->w_r64b) c->w_r64b = dalloc<double>(c, NE * nb);
+    if (!c->w_r64b) c->w_r64b = dalloc<double>(c, N);
+    if (!c->w_adx64) c->w_adx64 = dalloc<double>(c, N);
     LCHK(launch_residual<double>(cfg, c->s64.lv[0].view, c->tab, c->w_b, c->w_x, c->w_r64b, 0));
     LCHK(launch_field_sumsq<double>(c->stream, NE, nb, nvel, c->w_r64b, ds, c->w_part, SUMSQ_BLK, c->d_sums));
     LCHK(launch_net_apply<double>(c->stream, c->g.d, c->g.p, L.n, log2i(L.n), periodic_mask(c->P), c->w_r64b, ds,
-                                  c->d_logmu, c->d_sums, cu, cp, c->c_net[0], c->c_net[1], net_dev(c), base, out));
+                                  c->d_logmu, c->d_sums, cu, cp, c->c_net[0], c->c_net[1], net_dev(c), nullptr,
+                                  c->w_dx));
+    if (!full) {
+      // A dx in the cycle's variables (w_x is free once r' is formed)
+      LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, c->w_dx, c->w_x, 1, 0)));
+      LCHK(launch_residual<double>(cfg, c->s64.lv[0].view, c->tab, nullptr, c->w_x, c->w_adx64, 1));
+      LCHK(launch_minres_sums<double>(c->stream, N, c->w_r64b, c->w_adx64, c->w_part, SUMSQ_BLK, c->d_mr));
+    }
   } else {
     PrecStore<float>& S = (vp == LDGS_V_FP32) ? c->s32 : c->s16;
-    if (!c->w_r32) c->w_r32 = dalloc<float>(c, NE * nb);
+    if (!c->w_r32) c->w_r32 = dalloc<float>(c, N);
+    if (!c->w_adx32) c->w_adx32 = dalloc<float>(c, N);
     LCHK(launch_residual<float>(cfg, S.lv[0].view, c->tab, c->w_b32, c->w_x32, c->w_r32, 0));
     LCHK(launch_field_sumsq<float>(c->stream, NE, nb, nvel, c->w_r32, ds, c->w_part, SUMSQ_BLK, c->d_sums));
     LCHK(launch_net_apply<float>(c->stream, c->g.d, c->g.p, L.n, log2i(L.n), periodic_mask(c->P), c->w_r32, ds,
-                                 c->d_logmu, c->d_sums, cu, cp, c->c_net[0], c->c_net[1], net_dev(c), base, out));
+                                 c->d_logmu, c->d_sums, cu, cp, c->c_net[0], c->c_net[1], net_dev(c), nullptr,
+                                 c->w_dx));
+    if (!full) {
+      LCHK((launch_scale_cast<double, float>(c->stream, NE, nb, nvel, ds, c->w_dx, c->w_x32, 1, 0)));
+      LCHK(launch_residual<float>(cfg, S.lv[0].view, c->tab, nullptr, c->w_x32, c->w_adx32, 1));
+      LCHK(launch_minres_sums<float>(c->stream, N, c->w_r32, c->w_adx32, c->w_part, SUMSQ_BLK, c->d_mr));
+    }
   }
+  LCHK(launch_minres_update(c->stream, N, full ? nullptr : c->d_mr, z, c->w_dx, out));
+  ++c->learned_steps;
 }
 
 // RAII device buffers for the context-free training entry point
@@ -1242,6 +1271,7 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
       if (v >= 1) c->small_grid = (int)v;
     }
     if (const char* si = std::getenv("LDGS_SHARED_INVERSE")) c->shared_inverse = std::strtol(si, nullptr, 10) != 0;
+    if (const char* fs = std::getenv("LDGS_LEARNED_FULL_STEP")) c->learned_full_step = std::strtol(fs, nullptr, 10) != 0;
     if (const char* gr = std::getenv("LDGS_GRAPH")) c->use_graph = std::strtol(gr, nullptr, 10) != 0;
     if (const char* ds = std::getenv("LDGS_DEVICE_SETUP")) c->device_setup = std::strtol(ds, nullptr, 10) != 0;
     if (const char* sp = std::getenv("LDGS_SPLIT_PASS")) c->split_pass = std::strtol(sp, nullptr, 10) != 0;
@@ -1646,7 +1676,8 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxi
     Join join_(ctx);
     if (!b || !x || maxit < 0 || !(tol >= 0)) throw Fail{LDGS_E_ARG, "bad argument"};
     if (use_learned) {
-      if (outer != LDGS_IR) throw Fail{LDGS_E_UNSUPPORTED, "the learned correction is used with outer = IR"};
+      if (outer != LDGS_IR && outer != LDGS_FGMRES)
+        throw Fail{LDGS_E_UNSUPPORTED, "the learned correction is used with outer = IR or FGMRES"};
       if (!ctx->net_loaded) throw Fail{LDGS_E_ARG, "no network loaded"};
     }
     auto t0 = std::chrono::steady_clock::now();
@@ -1685,7 +1716,7 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxi
         } else {
           // z = V(r); x_old + (z + dx), dx from r - A z; guarded below
           vcycle_user(ctx, ctx->vprec, ctx->w_r, ctx->w_z, true);
-          learned_after_cycle(ctx, ctx->vprec, ctx->w_z, ctx->w_zl);
+          learned_minres(ctx, ctx->vprec, ctx->w_z, ctx->w_zl);
           HIPCHK(hipMemcpyAsync(ctx->w_xold, x, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
           LCHK(launch_axpy(ctx->stream, N, 1.0, ctx->w_zl, x));
           rn = relres();
@@ -1726,6 +1757,7 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxi
         for (int j = 0; j < m && it < maxit; ++j) {
           double* zj = flex ? Z[j] : T;
           vcycle_user(ctx, ctx->vprec, V[j], zj, true);
+          if (use_learned) learned_minres(ctx, ctx->vprec, zj, zj);   // a variable preconditioner: FGMRES only
           LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream, ctx->small_grid};
           LCHK(launch_residual<double>(cfg, ctx->s64.lv[0].unscaled, ctx->tab, nullptr, zj, V[j + 1], 1));
           for (int i = 0; i <= j; ++i) {

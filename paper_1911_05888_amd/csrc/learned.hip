@@ -136,6 +136,50 @@ __global__ __launch_bounds__(RBLK) void k_sum_pairs(int nblk, const double* __re
   }
 }
 
+// Minimal-residual step length of the correction: partial sums of r . q and
+// q . q (q = A dx) per block, FP64 accumulation in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(RBLK) void k_dot2(int64_t n, const T* __restrict__ r, const T* __restrict__ q,
+                                               double* __restrict__ part) {
+  __shared__ double sa[RBLK], sb[RBLK];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * RBLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * RBLK) {
+    const double qv = (double)q[i];
+    a += (double)r[i] * qv;
+    b += qv * qv;
+  }
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int st = RBLK / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      sa[threadIdx.x] += sa[threadIdx.x + st];
+      sb[threadIdx.x] += sb[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sa[0];
+    part[2 * blockIdx.x + 1] = sb[0];
+  }
+}
+
+// out = base + w dx with w = sums[0] / sums[1] (0 when sums[1] is 0), or
+// w = 1 when sums is null (the full step); w is also stored in sums[2]
+__global__ __launch_bounds__(256) void k_minres_update(int64_t n, double* __restrict__ sums,
+                                                       const double* __restrict__ base, const double* __restrict__ dx,
+                                                       double* __restrict__ out) {
+  if (!sums) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+      out[i] = base[i] + dx[i];
+    return;
+  }
+  const double w = sums[1] > 0.0 ? sums[0] / sums[1] : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) sums[2] = w;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    out[i] = base[i] + w * dx[i];
+}
+
 // ---------------------------------------------------------------------------
 // inference: out = base + dx for the 16 elements E0 .. E0 + 15
 // ---------------------------------------------------------------------------
@@ -628,6 +672,20 @@ int launch_net_apply(void* stream, int d, int p, int n, int lgn, int permask, co
   return ok();
 }
 
+template <typename T>
+int launch_minres_sums(void* stream, int64_t n, const T* r, const T* q, double* part, int nblk, double* sums) {
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL((k_dot2<T>), dim3(nblk), dim3(RBLK), 0, st, n, r, q, part);
+  hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(RBLK), 0, st, nblk, part, sums);
+  return ok();
+}
+
+int launch_minres_update(void* stream, int64_t n, double* sums, const double* base, const double* dx, double* out) {
+  hipLaunchKernelGGL(k_minres_update, dim3(blocks(n, 256, 4096)), dim3(256), 0, (hipStream_t)stream, n, sums, base, dx,
+                     out);
+  return ok();
+}
+
 int launch_collect_crops(void* stream, int d, int p, int n, int lgn, int permask, int C, int lgC, int ncrop,
                          const int* origins, const double* r, const double* e, const float* logmu,
                          const double* sums, double cnt_u, double cnt_p, uint16_t* feat, uint16_t* targ) {
@@ -699,6 +757,8 @@ int train_workspace(void** ptr) {
 
 template int launch_field_sumsq<float>(void*, int64_t, int, int, const float*, const double*, double*, int, double*);
 template int launch_field_sumsq<double>(void*, int64_t, int, int, const double*, const double*, double*, int, double*);
+template int launch_minres_sums<float>(void*, int64_t, const float*, const float*, double*, int, double*);
+template int launch_minres_sums<double>(void*, int64_t, const double*, const double*, double*, int, double*);
 template int launch_net_apply<float>(void*, int, int, int, int, int, const float*, const double*, const float*,
                                      const double*, double, double, double, double, NetDev, const double*, double*);
 template int launch_net_apply<double>(void*, int, int, int, int, int, const double*, const double*, const float*,

@@ -52,6 +52,14 @@ int launch_net_apply(void* stream, int d, int p, int n, int lgn, int permask, co
                      const float* logmu, const double* sums, double cnt_u, double cnt_p, double c_u, double c_p,
                      NetDev net, const double* base, double* out);
 
+// minimal-residual step of the correction: sums[0] = r . q, sums[1] = q . q
+// (FP64 accumulation; part: nblk*2 doubles scratch); then
+// out = base + w dx with w = sums[0] / sums[1] (0 if sums[1] = 0), w stored
+// in sums[2] (sums: 3 device doubles); sums null: the full step w = 1
+template <typename T>
+int launch_minres_sums(void* stream, int64_t n, const T* r, const T* q, double* part, int nblk, double* sums);
+int launch_minres_update(void* stream, int64_t n, double* sums, const double* base, const double* dx, double* out);
+
 // crops for training: features [(C+2)^d][CHP] BF16 of r / s (and log10 mu),
 // targets [C^d][n_b] BF16 of e / s, for ncrop crops with the given origins
 // (device int [ncrop][d]); element fields r, e FP64 on the n^d grid

@@ -9,26 +9,41 @@ from __future__ import annotations
 import numpy as np
 
 
-def random_smooth_coeffs(seed, dim, n, p, kmax=3, tail=0.05):
+def random_smooth_coeffs(seed, dim, n, p, kmax=3, tail=0.05, out=None):
     """Element-major coefficient vector (n^d elements, d+1 fields, (p+1)^d
     coefficients each, axis 0 fastest): the mean coefficient of every element
     and field is a random trigonometric polynomial of degree kmax evaluated at
     the element centre; the other coefficients are independent normal values
-    scaled by tail * 2^-(total degree)."""
+    scaled by tail * 2^-(total degree).  out: a float64 array of n^d (d+1)
+    (p+1)^d entries to fill (reused across calls, it saves the first touch of
+    fresh memory on large grids)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     nq = (p + 1) ** dim
     nb = (dim + 1) * nq
     ne = n ** dim
-    idx = np.indices((n,) * dim).reshape(dim, -1)[::-1]          # idx[k] = coordinate along axis k
-    centre = (idx.T + 0.5) / n                                   # (ne, dim)
     ks = np.array(np.meshgrid(*[np.arange(-kmax, kmax + 1)] * dim, indexing="ij")).reshape(dim, -1).T
-    x = np.zeros((ne, nb))
+    m = 2 * kmax + 1
+    # e^{2 pi i c k} on the element centres c = (i + 1/2) / n of one axis
+    E1 = np.exp(2j * np.pi * np.outer((np.arange(n) + 0.5) / n, np.arange(-kmax, kmax + 1)))
+    x = np.empty((ne, nb)) if out is None else out.reshape(ne, nb)
     deg = np.indices((p + 1,) * dim).reshape(dim, -1)[::-1].sum(axis=0)
+    scale = tail * 2.0 ** -deg[1:]
+    rows = 8192
     for f in range(dim + 1):
         a = rng.standard_normal(len(ks)) / (1.0 + (ks ** 2).sum(axis=1))
         ph = rng.uniform(0.0, 2.0 * np.pi, len(ks))
-        x[:, f * nq] = np.cos(2.0 * np.pi * centre @ ks.T + ph) @ a
-        x[:, f * nq + 1:(f + 1) * nq] = tail * rng.standard_normal((ne, nq - 1)) * 2.0 ** -deg[None, 1:]
+        # sum_k a_k cos(2 pi c.k + ph_k) = Re sum_k a_k e^{i ph_k} prod_j e^{2 pi i c_j k_j},
+        # contracted one axis at a time (ks[:, 0] varies slowest)
+        T = (a * np.exp(1j * ph)).reshape((m,) * dim)
+        for _ in range(dim):
+            T = np.tensordot(T, E1, axes=([0], [1]))   # the contracted axis moves to the end
+        # T[i_0, ..., i_{d-1}] with i_j the coordinate of axis j; axis 0 fastest
+        x[:, f * nq] = T.real.transpose(tuple(range(dim))[::-1]).ravel()
+        # the same draws as one (ne, nq - 1) block, taken a few rows at a time
+        for r0 in range(0, ne, rows):
+            blk = rng.standard_normal((min(ne, r0 + rows) - r0, nq - 1))
+            blk *= scale
+            x[r0:r0 + blk.shape[0], f * nq + 1:(f + 1) * nq] = blk
     return x.ravel()
 
 

@@ -2,7 +2,9 @@
 kernel against the oracle network (BF16 emulation and FP64), crop collection
 against the oracle's training pairs, first-step gradients of the training
 kernel against the oracle's BF16-emulated backward pass, the zero-output
-network reproducing the plain solve exactly, and the guard."""
+network reproducing the plain solve exactly, the guard, the minimal-residual
+step in iterative refinement and in FGMRES against the oracle, and the gain
+of the trained network on held-out viscosity seeds."""
 import numpy as np
 import pytest
 
@@ -80,8 +82,21 @@ def test_correction_matches_oracle(name):
     ref64 = L.correction(p, cvec, g, r)
     e16 = np.linalg.norm(dx - ref16) / np.linalg.norm(ref16)
     e64 = np.linalg.norm(dx - ref64) / np.linalg.norm(ref64)
-    print(f"[learned] {name}: rel err vs BF16 emulation {e16:.2e}, vs FP64 {e64:.2e}", flush=True)
-    assert e16 <= 1e-2
+    # per element: both sides round the same values to bfloat16; their float32
+    # sums differ in order only (about 1e-8), except where that difference
+    # moves a hidden activation across a bfloat16 rounding boundary, which
+    # changes it by one bfloat16 unit (2^-8 relative) and that element's output
+    # by about as much.  With K = 3^d (n_b + 1) terms per sum such crossings
+    # are rare: at most 1% of the elements may differ by more than 1e-6.
+    D = (dx - ref16).reshape(-1, g.nb)
+    R = ref16.reshape(-1, g.nb)
+    el = np.linalg.norm(D, axis=1) / np.maximum(np.linalg.norm(R, axis=1), 1e-300)
+    off = np.count_nonzero(el > 1e-6)
+    print(f"[learned] {name}: rel err vs BF16 emulation {e16:.2e} (elements above 1e-6: {off} of {el.size}, "
+          f"largest {el.max():.2e}), vs FP64 {e64:.2e}", flush=True)
+    assert off <= 0.01 * el.size
+    assert el.max() <= 2.0 ** -7
+    assert e16 <= 2.0 ** -8
     assert e64 <= 3e-2
 
 
@@ -246,8 +261,12 @@ def test_zero_output_network_reproduces_plain_solve_exactly():
     assert bool((x1 == x2).all())
 
 
-def test_guard_switches_a_harmful_correction_off():
+def test_guard_switches_a_harmful_correction_off(monkeypatch):
+    """With the full step (w = 1, switched on from the host at setup) a
+    correction far larger than the error raises the residual and the guard
+    switches it off; the minimal-residual step would have shrunk it."""
     from paper_1911_05888_amd import IR
+    monkeypatch.setenv("LDGS_LEARNED_FULL_STEP", "1")
     prob = c2_dirichlet_varmu(n=32, p=3)
     H, g, ctx = _setup(prob, vprec=1)
     p = _params(g.d, g.nb, seed=8)
@@ -287,3 +306,63 @@ def test_learned_solve_follows_oracle_guarded_refinement():
     k = min(len(h), len(h_o))
     assert np.allclose(h[:3], h_o[:3], rtol=1e-9)          # plain iterations
     assert np.all(np.abs(np.log(h[3:k] / h_o[3:k])) <= np.log(1.5))
+
+
+@pytest.mark.parametrize("name", ["c2_n16_p2", "c5_n8_p2"])
+def test_learned_fgmres_follows_oracle(name):
+    """FGMRES with the minimal-residual correction, FP64 cycles, a random
+    network, against the oracle (the 2D benchmark problem at 16^2, Q_2, about
+    20 iterations; the 3D log-normal viscosity problem at 8^3, Q_2, about 80).
+    The corrections agree to the float32 summation order of the network
+    (about 1e-8) except where that order moves an activation across a
+    bfloat16 rounding boundary (test_correction_matches_oracle), which one of
+    the network's many applications in a solve is likely to meet; the Krylov
+    process carries such a difference on.  Bar: relative deviation of the
+    residual history 1e-3 in 2D (measured 5e-5) and 1e-2 in 3D (measured
+    3.5e-3), iteration counts equal within one."""
+    from oracle import learned as L
+    from oracle.solvers import Solver
+    from paper_1911_05888_amd import FGMRES
+    from synth import c5_lognormal
+    torch = _torch()
+    prob = c5_lognormal(n=8, p=2) if name.startswith("c5") else c2_dirichlet_varmu(n=16, p=2)
+    H, g, ctx = _setup(prob, vprec=0)
+    p = _params(g.d, g.nb, seed=10)
+    cvec = (0.3, 0.3)
+    ctx.set_learned(_flat(p), *cvec)
+    rng = np.random.Generator(np.random.PCG64(22))
+    b = H.project_kernel(rng.standard_normal(H.fine.A.shape[0]))
+    _, h_o, ws = L.fgmres_learned(Solver(H), b, _master_f32(p), cvec, g, tol=1e-10, m=30, maxit=120,
+                                  dtype=np.float64, emulate_bf16=True)
+    st, info = ctx.solve(torch.tensor(b, device="cuda"), ctx.zeros(), tol=1e-10, maxit=120, outer=FGMRES,
+                         fgmres_m=30, use_learned=True)
+    h = info["history"]
+    print(f"[learned] fgmres oracle {len(h_o) - 1} its, gpu {len(h) - 1} its; steps w {np.round(ws[:6], 4)}",
+          flush=True)
+    assert st == 0 and h_o[-1] <= 1e-10
+    k = min(len(h), len(h_o))
+    dev = np.abs(h[:k] - h_o[:k]) / h_o[:k]
+    print(f"[learned] {name}: largest relative deviation {dev.max():.2e} (first 10: {dev[:11].max():.2e})",
+          flush=True)
+    assert abs(len(h) - len(h_o)) <= 1
+    assert dev.max() <= (1e-2 if name.startswith("c5") else 1e-3)
+    assert max(abs(w) for w in ws) > 0.0          # the correction takes part
+
+
+def test_trained_correction_on_held_out_seeds():
+    """The committed network (trained on 2004 pairs from 167 viscosity seeds
+    at 64^3) on two held-out seeds at 32^3: FGMRES(150) with the FP32
+    V-cycle, iterations and wall time with and without the correction.  Both
+    must reach 1e-10; the measured gain or loss is printed, not asserted
+    (measured: 29 -> 29 and 28 -> 28 iterations, 12 % more time: no gain)."""
+    import os
+    from paper_1911_05888_amd import train_learned as T
+    path = os.path.join(os.path.dirname(T.__file__), "weights", "c5_q2_h16.npz")
+    if not os.path.exists(path):
+        pytest.skip("no trained weights")
+    params, c_vel, c_pre, rec = T.load(path)
+    res = T.evaluate(params, c_vel, c_pre, [3002, 3003], 32, log=lambda s: print(s, flush=True))
+    for r in res:
+        assert r["plain"]["converged"] and r["learned"]["converged"]
+        print(f"[learned] held-out seed {r['seed']}: iterations {r['plain']['iters']} -> {r['learned']['iters']}, "
+              f"time {r['plain']['time_s']:.3f} s -> {r['learned']['time_s']:.3f} s", flush=True)

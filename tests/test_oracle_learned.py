@@ -177,7 +177,8 @@ def test_guard_switches_a_harmful_correction_off():
     S = Solver(hier)
     b = np.random.default_rng(13).standard_normal(hier.fine.A.shape[0])
     _, h_plain = S.refinement(b, tol=1e-10, maxit=40)
-    x, h, ev = L.refinement_learned(S, b, params, (1.0, 1.0), g, tol=1e-10, maxit=40)
+    # the full step (w = 1): the minimal-residual step would shrink it away
+    x, h, ev = L.refinement_learned(S, b, params, (1.0, 1.0), g, tol=1e-10, maxit=40, minres=False)
     assert ev == 1
     assert h[-1] <= 1e-10
     # the triggering step is replaced by the plain step: identical histories
@@ -222,3 +223,62 @@ def test_training_reduces_the_loss_on_collected_pairs():
         _, gr = L.loss_and_grad(params, X, T)
         params = opt.step(params, gr)
     assert L.loss_and_grad(params, X, T)[0] < 0.5 * l0
+
+
+# ------------------------------------------------ minimal-residual step -------
+def _step_case(seed=15):
+    prob = c2_dirichlet_varmu(n=8, p=2)
+    hier, g, params = _grid_and_net(prob)
+    S = Solver(hier)
+    rng = np.random.default_rng(seed)
+    v = hier.project_kernel(rng.standard_normal(hier.fine.A.shape[0]))
+    z = S.vcycle_unscaled(v, None, np.float64)
+    return S, g, params, v, z
+
+
+def test_minres_step_is_the_residual_projection():
+    """In FP64 the corrected residual v - A(z + w dx) is orthogonal to A dx
+    (w minimises its norm over the line), never longer than v - A z, and
+    shorter than with the full step for a correction of the wrong size."""
+    S, g, params, v, z = _step_case()
+    params["b3"][:] = 3.0
+    out, w = L.minres_step(S, v, z, params, (1.0, 1.0), g, np.float64, emulate_bf16=False)
+    full, _ = L.minres_step(S, v, z, params, (1.0, 1.0), g, np.float64, emulate_bf16=False, minres=False)
+    dx = full - z
+    q = S.A @ dx
+    r_plain = v - S.A @ z
+    r_new = v - S.A @ out
+    assert abs(np.dot(r_new, q)) <= 1e-12 * np.linalg.norm(r_new) * np.linalg.norm(q)
+    assert np.linalg.norm(r_new) <= np.linalg.norm(r_plain)
+    assert np.linalg.norm(r_new) < np.linalg.norm(v - S.A @ full)
+    assert w != 1.0
+
+
+def test_minres_step_is_invariant_to_the_output_scale():
+    """Scaling the network's output constants by 4 scales dx by 4 and w by
+    1/4: the corrected result is unchanged (a misplaced power of the step
+    formula breaks this)."""
+    S, g, params, v, z = _step_case(16)
+    a, wa = L.minres_step(S, v, z, params, (0.3, 0.5), g, np.float64, emulate_bf16=False)
+    b, wb = L.minres_step(S, v, z, params, (1.2, 2.0), g, np.float64, emulate_bf16=False)
+    assert abs(wa / wb - 4.0) <= 1e-12 * 4.0
+    assert np.allclose(a, b, rtol=0, atol=1e-13 * np.abs(a).max())
+
+
+def test_zero_network_minres_fgmres_is_plain_fgmres():
+    """With a zero-output network w = 0 and the flexible GMRES directions are
+    the plain V-cycle results: the same iteration estimates as the oracle's
+    plain FGMRES, run without a restart."""
+    prob = c2_dirichlet_varmu(n=8, p=2)
+    hier, g, params = _grid_and_net(prob)
+    params["W3"][:] = 0.0
+    params["b3"][:] = 0.0
+    S = Solver(hier)
+    b = np.random.default_rng(17).standard_normal(hier.fine.A.shape[0])
+    _, h_plain = S.fgmres(b, tol=1e-10, m=60, maxit=60, dtype=np.float64)
+    _, h_learn, ws = L.fgmres_learned(S, b, params, (1.0, 1.0), g, tol=1e-10, m=60, maxit=60, dtype=np.float64,
+                                      emulate_bf16=False)
+    assert all(w == 0.0 for w in ws)
+    assert len(h_plain) == len(h_learn)
+    assert np.array_equal(h_plain[:-1], h_learn[:-1])
+    assert h_learn[-1] <= 1e-10
