@@ -1243,6 +1243,114 @@ __global__ __launch_bounds__(NT) void k_first_colour(int lgn, const int* __restr
 // layout.  One wavefront per element: the evaluation of the residual (an
 // LDS-bound kernel of its own) no longer holds the inverse's stream back, and
 // many elements' tiles are in flight per CU.
+// The product of one wavefront with the stored upper tiles, streamed column
+// by column of tiles (j outer, i <= j inner), so that the transposed sums of
+// a tile column are complete when the column ends and leave the registers:
+// live are the row sums of every tile row, the row values r_i met so far and
+// one column's transposed sums.  Tile requests run WIN tiles ahead of their
+// use in a ring of registers; a scheduling barrier after each request keeps
+// the later requests behind it (otherwise every tile of a large block is
+// hoisted to the start: for n_b = 108 in FP64 that took over 400 registers
+// and left one wavefront per SIMD).  The transposed sums of a column are
+// summed over the lanes that share bits 0-1 and 4-5 of the lane index (bits
+// 2-3 cross-lane, then bits 4-5 through LDS: red holds 64 TR entries).
+// y = part[0] + part[1] on return.
+// tile number and kind of the s-th tile in column order, as a table decoded
+// at compile time (indexed with unrolled loop counters, its entries fold into
+// immediates)
+template <int TR>
+struct ColOrder {
+  struct Tab {
+    int tile[TR * (TR + 1) / 2];
+    bool diag[TR * (TR + 1) / 2];
+  };
+  static constexpr Tab make() {
+    Tab tb{};
+    int s = 0;
+    for (int j = 0; j < TR; ++j)
+      for (int i = 0; i <= j; ++i, ++s) {
+        tb.tile[s] = i * TR - i * (i - 1) / 2 + (j - i);
+        tb.diag[s] = i == j;
+      }
+    return tb;
+  }
+  static constexpr Tab tab = make();
+};
+template <typename T, typename TI, int NB, int WIN>
+__device__ __forceinline__ void sym_product_stream(const InvWord<TI>* __restrict__ Ai, const T* __restrict__ rsrc,
+                                                   T* res, T (*part)[16 * SymProd<TI, NB>::TR], T* red, int lane) {
+  using SP = SymProd<TI, NB>;
+  constexpr int TR = SP::TR, NTILE = SP::NTILE, H = SP::H, EL = SP::EL;
+  using Word = typename SP::Word;
+  const int l = lane;
+  const int row = l >> 2, c4 = (l & 3) * 4;
+  auto request = [&](int s, Word (&w)[H]) {
+    const int t = ColOrder<TR>::tab.tile[s];
+    const bool diag = ColOrder<TR>::tab.diag[s];
+#pragma unroll
+    for (int h = 0; h < H; ++h) w[h] = __builtin_nontemporal_load(&Ai[sym_word<TI, NB>(t, diag, h, l)]);
+  };
+  Word ring[WIN][H];
+#pragma unroll
+  for (int s = 0; s < WIN && s < NTILE; ++s) request(s, ring[s]);
+  // the residual after the first requests, so that they are in flight meanwhile
+  for (int q = lane; q < NB; q += 64) res[q] = rsrc[q];
+  __syncthreads();
+  T dir[TR], ri[TR];
+#pragma unroll
+  for (int i = 0; i < TR; ++i) dir[i] = 0;
+#pragma unroll
+  for (int j = 0; j < TR; ++j) {
+    ri[j] = (16 * j + row < NB) ? res[16 * j + row] : (T)0;
+    T rj[4], trn[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) rj[v] = (16 * j + c4 + v < NB) ? res[16 * j + c4 + v] : (T)0;
+#pragma unroll
+    for (int i = 0; i <= j; ++i) {
+      const int s = j * (j + 1) / 2 + i;
+      const bool diag = j == i;
+      Word raw[H];
+#pragma unroll
+      for (int h = 0; h < H; ++h) raw[h] = ring[s % WIN][h];
+      if (s + WIN < NTILE) request(s + WIN, ring[s % WIN]);
+      __builtin_amdgcn_sched_barrier(0);
+      // a diagonal tile: blocks left of the diagonal block are not stored
+      const bool keep = !diag || (l & 3) >= (row >> 2);
+      T a[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a[v] = keep ? inv_entry<T, TI>(raw[v / EL], v % EL) : (T)0;
+      dir[i] += a[0] * rj[0] + a[1] * rj[1] + a[2] * rj[2] + a[3] * rj[3];
+      if (!diag || (l & 3) > (row >> 2)) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) trn[v] += a[v] * ri[i];
+      }
+    }
+    // column j done: its transposed sums over the rows of the lane's group
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      trn[v] += shfl_xor64(trn[v], 4);
+      trn[v] += shfl_xor64(trn[v], 8);
+    }
+    if (((l >> 2) & 3) == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[(l >> 4) * 16 * TR + 16 * j + c4 + v] = trn[v];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < TR; ++i) {
+    dir[i] += shfl_xor64(dir[i], 1);
+    dir[i] += shfl_xor64(dir[i], 2);
+  }
+  if ((l & 3) == 0) {
+#pragma unroll
+    for (int i = 0; i < TR; ++i) part[0][16 * i + row] = dir[i];
+  }
+  __syncthreads();
+  for (int col = lane; col < 16 * TR; col += 64)
+    part[1][col] = red[col] + red[16 * TR + col] + red[32 * TR + col] + red[48 * TR + col];
+  __syncthreads();
+}
+
 template <typename T, typename TI, int D, int P>
 __global__ __launch_bounds__(64) void k_apply_inverse(int lgn, const int* __restrict__ elems, int pcol,
                                                       const TI* __restrict__ inv, const T* __restrict__ r,
@@ -1250,18 +1358,17 @@ __global__ __launch_bounds__(64) void k_apply_inverse(int lgn, const int* __rest
   using S = Sz<D, P>;
   constexpr int NB = S::NB;
   using SP = SymProd<TI, NB>;
+  // tiles in flight per wavefront: 64 registers of requests
+  constexpr int TILE_REGS = SP::H * (int)sizeof(typename SP::Word) / 4;
+  constexpr int WIN = 64 / TILE_REGS < 1 ? 1 : 64 / TILE_REGS;
   __shared__ alignas(16) T res[NB];
   __shared__ T part[2][16 * SP::TR];
-  __shared__ T red[256 * SP::TR];
+  __shared__ T red[64 * SP::TR];
   const int lane = threadIdx.x;
   const int idx = xcd_remap(blockIdx.x, gridDim.x);
   const int E = colour_elem<D>(idx, pcol, lgn, elems);
   const auto* Ai = reinterpret_cast<const typename SP::Word*>(inv + (size_t)idx * SP::ESTRIDE);
-  typename SP::Word pre[SP::PF][SP::H];
-  sym_prefetch<TI, NB>(Ai, pre, lane);
-  for (int t = lane; t < NB; t += 64) res[t] = r[(size_t)idx * NB + t];
-  __syncthreads();
-  sym_product<T, TI, NB, 64>(Ai, pre, res, part, red, lane);
+  sym_product_stream<T, TI, NB, WIN>(Ai, r + (size_t)idx * NB, res, part, red, lane);
   for (int q = lane; q < NB; q += 64) x[(size_t)E * NB + q] += part[0][q] + part[1][q];
 }
 
