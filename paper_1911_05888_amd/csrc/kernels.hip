@@ -222,11 +222,21 @@ template <int D>
 constexpr bool FOLD_TRACES = D == 3;
 
 // shared-memory work area of one element evaluation
+// In 3D without interphase faces the slots E+e_a-e_b are read only for
+// their component a (the line of G_b u_a at E+e_a reaches back into them):
+// they are held compactly, one field each (xpm), which keeps the work area of
+// the FP64 evaluation small enough for four work-groups per CU.
+template <int D, bool IF>
+constexpr bool COMPACT_PM = D == 3 && !IF;
+
 template <typename T, int D, int P, bool IF = false>
 struct Work {
   using S = Sz<D, P, IF>;
   static constexpr bool STAGE_M = (size_t)S::NQ * S::NQ * sizeof(T) <= 8192;
-  alignas(16) T xs[S::NSLOT][S::NB];
+  static constexpr bool CPM = COMPACT_PM<D, IF>;
+  static constexpr int NXS = CPM ? 1 + 2 * D : S::NSLOT;   // slots held whole
+  alignas(16) T xs[NXS][S::NB];
+  alignas(16) T xpm[CPM ? D * (D - 1) : 1][CPM ? S::NQ : 1];   // component a of E+e_a-e_b
   alignas(16) T th[2][D][S::MT * S::MT];          // penalty matrices of E's low/high faces
   alignas(16) T g[S::NFS][D * D][S::NQ];          // G_k u_i at E, E+e_k (and E-e_k) (needed components)
   alignas(16) T s0[D * D][S::NQ];                 // s_ik at E
@@ -235,7 +245,7 @@ struct Work {
   // s_E[i][k] lo/hi along k (only where a separate trace step forms it)
   alignas(16) T trs[FOLD_TRACES<D> ? 1 : 2][FOLD_TRACES<D> ? 1 : D][FOLD_TRACES<D> ? 1 : D][FOLD_TRACES<D> ? 1 : S::MT];
   alignas(16) T trr[D][D][S::MT];                 // s_{E+e_k}[i][k] at its low face along k
-  alignas(16) T trrh[IF ? D : 1][D][S::MT];       // (IF) s_{E-e_k}[i][k] at its high face along k
+  alignas(16) T trrh[IF ? D : 1][IF ? D : 1][IF ? S::MT : 1];   // (IF) s_{E-e_k}[i][k] at its high face along k
   alignas(16) T flux[2][D][D + 1][S::MT];         // coefficients of e0 (lo) and e1 (hi) per axis/field
   // the 1D tables K, e0, e1 (TabT layout) for lookups whose index differs
   // between lanes (kernel-argument arrays indexed per lane become memory loads)
@@ -247,7 +257,7 @@ struct Work {
   alignas(16) T res[S::NB];
   // viscosity data, last: levels with constant viscosity do not allocate it
   alignas(16) T rr[D][S::MT * S::NQ];             // R_k = (e0^T)_k M_mu of E+e_k
-  alignas(16) T rrh[IF ? D : 1][S::MT * S::NQ];   // (IF) (e1^T)_k M_mu of E-e_k
+  alignas(16) T rrh[IF ? D : 1][IF ? S::MT * S::NQ : 1];   // (IF) (e1^T)_k M_mu of E-e_k
   alignas(16) T mm[STAGE_M ? S::NQ * S::NQ : 1];   // M_mu of E
 };
 
@@ -573,12 +583,24 @@ __device__ __forceinline__ void elem_stage(const DevLevel<T>& lev, const ElemDat
   using ED = ElemData<T, D, P, NT, IF>;
   constexpr int NQ = S::NQ, MT = S::MT, NB = S::NB, NFS = S::NFS, NSLOT = S::NSLOT;
   constexpr int XQ = ED::XQ, MQ = ED::MQ, RQ = ED::RQ, TQ = ED::TQ;
-  #pragma unroll
+  using W = Work<T, D, P, IF>;
+#pragma unroll
   for (int sl = 0; sl < NSLOT; ++sl)
 #pragma unroll
     for (int q = 0; q < XQ; ++q) {
       const int i = lane + q * NT;
-      if (i < NB) w.xs[sl][i] = d.se[sl] >= 0 ? d.xr[sl][q] * (i >= D * NQ ? d.dsp[sl] : d.dsv[sl]) : (T)0;
+      const T v = d.se[sl] >= 0 ? d.xr[sl][q] * (i >= D * NQ ? d.dsp[sl] : d.dsv[sl]) : (T)0;
+      if constexpr (W::CPM) {
+        if (sl < W::NXS) {
+          if (i < NB) w.xs[sl < W::NXS ? sl : 0][i] = v;
+        } else {
+          // slot E+e_a-e_b keeps component a only
+          const int pm = sl - W::NXS, a = pm / (D - 1);
+          if (i >= a * NQ && i < (a + 1) * NQ) w.xpm[pm][i - a * NQ] = v;
+        }
+      } else {
+        if (i < NB) w.xs[sl][i] = v;
+      }
     }
   if (lev.mmu) {
     if constexpr (Work<T, D, P, IF>::STAGE_M) {
@@ -755,7 +777,11 @@ __device__ __forceinline__ void elem_compute(const DevLevel<T>& lev, const TabT<
       }
       const int base = compose<M>(t, 0, k), st = stride_of<M>(k);
       T trlo, trhi, trLhi;
-      line(&w.xs[sF][i * NQ + base], &w.xs[low_slot<D>(fi, k)][i * NQ + base],
+      const int sL = low_slot<D>(fi, k);
+      const T* ul;
+      if constexpr (W::CPM) ul = sL < W::NXS ? &w.xs[sL < W::NXS ? sL : 0][i * NQ + base] : &w.xpm[sL - W::NXS][base];
+      else ul = &w.xs[sL][i * NQ + base];
+      line(&w.xs[sF][i * NQ + base], ul,
            IF ? &w.xs[IF ? high_slot<D>(fi, k) : 0][i * NQ + base] : nullptr, st,
            INT ? (unsigned char)F_INTRA : w.ft[fi][k][0], INT ? (unsigned char)F_INTRA : w.ft[fi][k][1],
            INT ? (T)1 : w.fwr[fi][k][0], INT ? (T)0 : w.fwl[fi][k][1], &w.g[fi][i * D + k][base], trlo, trhi, trLhi);
