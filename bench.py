@@ -169,7 +169,7 @@ def main():
             return b
         return ctx.assemble_rhs(prob.rhs_source())
 
-    def solve(ctx, b0, vp, reps, label, flexible=False):
+    def solve(ctx, b0, vp, reps, label, flexible=False, learned=False):
         """reps solves from zero; (mean seconds, V-cycles per solve, Krylov
         iterations per solve, final relres).  GMRES runs one restart cycle per
         library call (each continues from the x it is given), so progress is
@@ -185,7 +185,8 @@ def main():
             if krylov:
                 rel, k = 1.0, 0
                 while rel > TOL and k < args.maxit:
-                    st, info = ctx.solve(b, x, tol=TOL, maxit=args.m, outer=outer, fgmres_m=args.m)
+                    st, info = ctx.solve(b, x, tol=TOL, maxit=args.m, outer=outer, fgmres_m=args.m,
+                                         use_learned=learned)
                     k += info["iters"]
                     # one V-cycle per Arnoldi step (and one for x += M V y without flexibility)
                     cycles += info["iters"] + (0 if flexible else 1)
@@ -310,11 +311,22 @@ def main():
             ttprob, tt_setup = prob, t_setup64
         tt = dict(workload=DESCRIPTION[args.workload].format(n=ttprob.n, m=args.m), unknowns=ctx.ndof,
                   setup_s=tt_setup)
-        for label, vp in (("fp64", V_FP64), ("fp32", V_FP32), ("fp32_bf16_inverses", V_FP32_BF16BLK)):
+        runs = [("fp64", V_FP64, False), ("fp32", V_FP32, False), ("fp32_bf16_inverses", V_FP32_BF16BLK, False)]
+        wfile = os.path.join(ROOT, "paper_1911_05888_amd", "weights", "c5_q2_h16.npz")
+        if krylov and ttprob.p == 2 and os.path.exists(wfile):
+            # the committed network, trained on other viscosity seeds (the
+            # benchmark's field is not among them); minimal-residual step in FGMRES
+            from paper_1911_05888_amd.train_learned import load as load_weights
+            params, c_vel, c_pre, wrec = load_weights(wfile)
+            ctx.set_learned(params, c_vel, c_pre)
+            runs.append(("fp32_learned", V_FP32, True))
+        for label, vp, learned in runs:
             tc = vcycle_rate(ctx, b0, vp)
-            ts, cyc, its, rel = solve(ctx, b0, vp, 1, label, flexible=krylov)
+            ts, cyc, its, rel = solve(ctx, b0, vp, 1, label, flexible=krylov, learned=learned)
             tt[label] = dict(time_to_tol_s=ts, iters=its, vcycles=cyc, vcycle_s=tc,
                              vcycle_dof_per_s=ctx.ndof / tc, relres=rel)
+            if learned:
+                tt[label]["training"] = {k: wrec[k] for k in ("n", "pairs", "seeds", "loss_first", "loss_last")}
             log(f"{label}: V-cycle {tc * 1e3:.1f} ms, time to 1e-10 {ts:.3f} s ({its:.0f} iterations)")
         extras["time_to_tolerance"] = tt
         ctx.close()
@@ -341,7 +353,9 @@ def main():
                     n=n, p=prob.p, dim=prob.dim, unknowns=ndof, levels=levels, colours=ncol, **extras),
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=achieved / HBM_PEAK_GBS, traffic=traffic,
-                      kernel=(f"k_colour_residual<double,{prob.dim},{prob.p}> + k_apply_inverse<double,double,"
+                      kernel=(f"k_colour_residual<double,{prob.dim},{prob.p}> + k_shared_update<double,"
+                              f"{(prob.dim + 1) * (prob.p + 1) ** prob.dim}> (finest level, one inverse)" if shared else
+                              f"k_colour_residual<double,{prob.dim},{prob.p}> + k_apply_inverse<double,double,"
                               f"{prob.dim},{prob.p}> (finest level)" if prob.dim == 3 else
                               f"k_smooth_colour<double,double,{prob.dim},{prob.p}> (finest level)"),
                       avg_launch_us=t_pass * 1e6, algorithmic_bytes_per_launch=bytes_method,
