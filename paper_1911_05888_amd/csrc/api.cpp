@@ -1336,11 +1336,11 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
       build_inverses(c.get(), n64, n32, n16);
       phase("block inverses");
       {
-        // scratch of the split residual + restriction: the largest level whose
-        // coarse grid has fewer than small_grid elements
+        // scratch of the split residual + restriction: the largest level that
+        // uses it (coarse grid below small_grid elements; every level in 3D)
         int64_t rf = 0;
         for (size_t l = 0; l + 1 < c->levels.size(); ++l)
-          if (c->levels[l + 1].NE < c->small_grid) rf = std::max(rf, c->levels[l].NE * c->g.nb);
+          if (c->levels[l + 1].NE < c->small_grid || c->g.d == 3) rf = std::max(rf, c->levels[l].NE * c->g.nb);
         if (rf > 0) {
           c->w_rf64 = dalloc<double>(c.get(), rf);
           if (n32 || n16) c->w_rf32 = dalloc<float>(c.get(), rf);
