@@ -169,7 +169,10 @@ class FineAssembly:
     def face_data(self, axis):
         """Per face along ``axis``: minus/plus elements, the reference traces
         of each side, the normal sign s (n = s e_axis), physical points, the
-        face type and lambda.  Types: 0 intraphase, 1 interphase, 2 boundary."""
+        face type and lambda.  Types: 0 intraphase, 1 interphase, 2 Dirichlet
+        boundary, 3 stress boundary (eq. govern3: u-hat = u- and sigma-hat the
+        data, so the face adds nothing to the operator, eq. ustarflux and
+        eq. qstarflux)."""
         g = self.grid
         fd = self.face[axis]
         L, R, anchor, side = g.faces(axis)
@@ -182,7 +185,7 @@ class FineAssembly:
         both = (L >= 0) & (R >= 0)
         inter = both & (g.chi[np.maximum(L, 0)] != g.chi[np.maximum(R, 0)])
         ftype[inter] = 1
-        ftype[~both] = 2
+        ftype[~both] = 3 if g.bc[axis] == "stress" else 2
         # boundary faces: normal outward; a low-side boundary face has the
         # interior element above it, so n = -e_axis and the minus trace is at xi = 0
         s[(L < 0)] = -1.0
@@ -220,6 +223,7 @@ class FineAssembly:
                      + int_intraphase (u+ - u-) v+ n_k
                      + int_interphase [(1-lam) v- + lam v+] (u+ - u-) n_k
                      - int_Dirichlet u- v- n_k
+        (stress walls: u-hat = u-, no term)
         """
         g = self.grid
         coo = _COO(self.S, g.nq)

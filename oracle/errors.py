@@ -1,6 +1,7 @@
 """Discretisation errors, as in the grid-convergence appendix: the error
 (u - u_h, p - p_h) with its components along the trivial kernel (constant
-fields) removed by Gram-Schmidt, measured in L2 and at a fine Gauss grid per
+fields; the rigid motions of the velocity with stress walls) removed by
+Gram-Schmidt, measured in L2 and at a fine Gauss grid per
 element (max norm)."""
 from __future__ import annotations
 
@@ -26,9 +27,35 @@ def solution_errors(prob, x, k0):
     err = np.concatenate([ue, pe[..., None]], axis=2) - uh
     wq = w[None, :] * g.h ** d
     vol = NE * wq.sum()                                      # measure of the domain
-    fields = [d] if k0 == 1 else list(range(d + 1))
-    for f in fields:                                         # remove constants
-        err[..., f] -= (err[..., f] * wq).sum() / vol
+    if all(b == "stress" for b in prob.bc):
+        # rigid motions of the velocity (the stress-wall kernel), removed by
+        # Gram-Schmidt in L2 over the domain
+        modes = []
+        for i in range(d):
+            F = np.zeros((NE, Q, d + 1))
+            F[..., i] = 1.0
+            modes.append(F)
+        if prob.gamma and not prob.unsteady:
+            for a in range(d):
+                for b in range(a + 1, d):
+                    F = np.zeros((NE, Q, d + 1))
+                    F[..., b] = X[..., a] - 0.5
+                    F[..., a] = -(X[..., b] - 0.5)
+                    modes.append(F)
+        if prob.unsteady:
+            modes = []
+        basis = []
+        for F in modes:
+            for Bm in basis:
+                F = F - (F * Bm * wq[..., None]).sum() * Bm
+            F = F / np.sqrt((F * F * wq[..., None]).sum())
+            basis.append(F)
+        for Bm in basis:
+            err = err - (err * Bm * wq[..., None]).sum() * Bm
+    else:
+        fields = [d] if k0 == 1 else list(range(d + 1))
+        for f in fields:                                         # remove constants
+            err[..., f] -= (err[..., f] * wq).sum() / vol
     l2 = np.sqrt((err ** 2 * wq[..., None]).sum(axis=(0, 1)))
     linf = np.abs(err).max(axis=(0, 1))
     return dict(u_l2=float(np.sqrt((l2[:d] ** 2).sum())), p_l2=float(l2[d]),

@@ -96,15 +96,56 @@ class Hierarchy:
 
     def kernel_basis(self):
         """Orthonormal basis (N, k0) of the trivial kernel of the unscaled fine
-        operator: constant velocity components (periodic steady) and constant
-        pressure, as coefficient vectors in the orthonormal basis."""
+        operator, as coefficient vectors in the orthonormal basis: constant
+        velocity components (periodic steady) and constant pressure; with
+        stress walls the constant velocity components and (viscous-stress
+        form) the rigid rotations (x_a - 1/2) e_b - (x_b - 1/2) e_a, a < b."""
         lv = self.fine
         prob = self.prob
         nq, nb, NE = lv.nq, lv.nb, lv.NE
+        if all(b == "stress" for b in prob.bc):
+            return self._rigid_modes()
         fields = [prob.dim] if self.k0 == 1 else list(range(prob.dim + 1))
         K = np.zeros((NE * nb, len(fields)))
         for c, f in enumerate(fields):
             K[np.arange(NE) * nb + f * nq, c] = 1.0 / np.sqrt(NE)
+        return K
+
+    def _rigid_modes(self):
+        """Rigid motions as coefficient vectors: the L2 projection (exact for
+        these linear fields) of each mode onto the element basis, by Gauss
+        quadrature; orthonormalised (the centred modes are already mutually
+        orthogonal, QR only normalises them)."""
+        from .assemble import FineAssembly
+        prob = self.prob
+        d = prob.dim
+        lv = self.fine
+        NE, nq, nb = lv.NE, lv.nq, lv.nb
+        fa = FineAssembly(prob)
+        X = fa.element_points()                                   # (NE, Q, d)
+        W = fa.B * fa.vol_w[:, None]                              # (Q, nq)
+        modes = []
+        for i in range(d):
+            F = np.zeros(X.shape)
+            F[..., i] = 1.0
+            modes.append(F)
+        if prob.gamma and not prob.unsteady:
+            for a in range(d):
+                for b in range(a + 1, d):
+                    F = np.zeros(X.shape)
+                    F[..., b] = X[..., a] - 0.5
+                    F[..., a] = -(X[..., b] - 0.5)
+                    modes.append(F)
+        if prob.unsteady:
+            modes = []
+        K = np.zeros((NE * nb, len(modes)))
+        for c, F in enumerate(modes):
+            coef = np.einsum("qa,eqi->eia", W, F)                  # (NE, d, nq)
+            v = np.zeros((NE, nb))
+            v[:, :d * nq] = coef.reshape(NE, d * nq)
+            K[:, c] = v.ravel()
+        if K.shape[1]:
+            K, _ = np.linalg.qr(K)
         return K
 
     def project_kernel(self, v):

@@ -72,6 +72,20 @@ def assemble_rhs(prob, ops):
                 Jg[i, k] += _scatter(S, nq, mi, np.einsum("q,fq,fqa->fa", w, gv[..., i] * ss, Tm[sel]))
                 pen[i] += _scatter(S, nq, mi, np.einsum("q,fq,fqa->fa", w, tau_b * gv[..., i], Tm[sel]))
             Jgn += _scatter(S, nq, mi, np.einsum("q,fq,fqa->fa", w, gv[..., k] * ss, Tm[sel]))
+        # stress boundary faces: sigma-hat = h n with h = sigma(exact) n, n
+        # outward; the data enter through J_h (the face has no operator terms)
+        sel = fd["type"] == 3
+        if sel.any():
+            if exact is None:
+                raise ValueError("stress data needs an exact solution")
+            Xf = fd["X"][sel]
+            F = Xf.shape[0]
+            chi = np.broadcast_to(fd["chi_m"][sel][:, None], Xf.shape[:2]).reshape(-1)
+            sig = exact.stress(Xf.reshape(-1, d), chi).reshape(F, -1, d, d)
+            hb = sig[..., :, k] * s[sel][:, None, None]          # h_i = sigma_ik n_k
+            mi = fd["minus"][sel]
+            for i in range(d):
+                Jh[i] += _scatter(S, nq, mi, np.einsum("q,fq,fqa->fa", w, hb[..., i], Tm[sel]))
         # interphase faces: jump data g_ij = [u], h_ij = [sigma n], lambda-weighted
         sel = fd["type"] == 1
         if sel.any():

@@ -9,13 +9,13 @@ their own.
 """
 from .problems import (Problem, c1_periodic_standard, c2_dirichlet_varmu,
                        c3_unsteady_periodic, c4a_square_inclusion,
-                       c5_lognormal, TAU_OPTIMAL, kernel_dimension)
+                       c5_lognormal, stress_walls, TAU_OPTIMAL, kernel_dimension)
 from .fields import (ConstField, SinProductField, PhaseField, LogNormalRFF,
                      FourierForcing, make_exact_c1, make_exact_paper)
 
 __all__ = [
     "Problem", "c1_periodic_standard", "c2_dirichlet_varmu",
-    "c3_unsteady_periodic", "c4a_square_inclusion", "c5_lognormal",
+    "c3_unsteady_periodic", "c4a_square_inclusion", "c5_lognormal", "stress_walls",
     "TAU_OPTIMAL", "kernel_dimension", "ConstField", "SinProductField",
     "PhaseField", "LogNormalRFF", "FourierForcing", "make_exact_c1",
     "make_exact_paper",

@@ -35,7 +35,7 @@ class Problem:
     n: int                          # elements per axis on the finest grid (power of two)
     p: int                          # tensor-product degree
     gamma: int                      # 0 standard form, 1 viscous-stress form
-    bc: tuple                       # per axis: "periodic" or "dirichlet" (both sides)
+    bc: tuple                       # per axis: "periodic", "dirichlet" or "stress" (both sides)
     mu: object = field(default_factory=ConstField)
     rho: Optional[object] = None    # density field (unsteady only)
     delta: Optional[float] = None   # time-step parameter; None = steady
@@ -53,6 +53,8 @@ class Problem:
     forcing: Optional[object] = None
 
     def __post_init__(self):
+        if "stress" in self.bc and any(b != "stress" for b in self.bc):
+            raise ValueError("stress boundary conditions are supported on every wall at once")
         if self.tau is None:
             self.tau = tau_table(self.gamma, self.dim, self.p)
         if self.tau0 is None:
@@ -108,11 +110,19 @@ def kernel_dimension(prob: Problem) -> int:
     """Dimension of the trivial kernel (paper's footnote on the bottom solver).
 
     Periodic steady: constant velocity components and constant pressure;
-    otherwise (Dirichlet walls, or rho/delta > 0) only constant pressure.
+    stress walls, steady: constant velocity components and, in viscous-stress
+    form, the rigid rotations (x_a e_b - x_b e_a), pressure excluded (the
+    walls fix it); unsteady with stress walls: none; otherwise (Dirichlet
+    walls, or rho/delta > 0) only constant pressure.
     """
+    d = prob.dim
+    if all(b == "stress" for b in prob.bc):
+        if prob.unsteady:
+            return 0
+        return d + (d * (d - 1) // 2 if prob.gamma else 0)
     periodic = all(b == "periodic" for b in prob.bc)
     if periodic and not prob.unsteady:
-        return prob.dim + 1
+        return d + 1
     return 1
 
 
@@ -174,3 +184,12 @@ def c5_lognormal(n=128, p=2, seed=1001, diag_scaling=False):
     return Problem(name=f"c5_lognormal_n{n}_p{p}_s{seed}", dim=3, n=n, p=p, gamma=1,
                    bc=("dirichlet",) * 3, mu=mu, coloring="parity", diag_scaling=diag_scaling,
                    exact=make_exact_paper(3, 1, mu))
+
+
+def stress_walls(dim=2, n=16, p=2, mu=None):
+    """Viscous-stress Stokes with stress boundary conditions on every wall
+    (sections 5.3 and 5.4): mu = 1 (section 5.3) or a given field such as
+    eq. (mu); the paper's manufactured solution, h = sigma n on the walls."""
+    mu = mu or ConstField(1.0)
+    return Problem(name=f"stress_d{dim}_n{n}_p{p}", dim=dim, n=n, p=p, gamma=1, bc=("stress",) * dim, mu=mu,
+                   coloring="parity", exact=make_exact_paper(dim, 1, mu))
