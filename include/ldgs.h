@@ -117,7 +117,10 @@ typedef struct {
   int n;                    /* elements per axis, a power of two */
   int degree;               /* p in {1, 2, 3} (Q_p, same degree for u and p) */
   int form;                 /* ldgs_form (gamma) */
-  int bc[3];                /* ldgs_bc per axis, both sides */
+  int bc[3];                /* ldgs_bc per axis, both sides; LDGS_STRESS (eq. govern3,
+                               u-hat = u- and sigma-hat = h n on the wall, eq. ustarflux
+                               and eq. qstarflux) must be given on every axis; the
+                               trivial kernel is then the rigid motions of the velocity */
   ldgs_field mu;            /* viscosity > 0 */
   ldgs_field rho;           /* density >= 0, used when delta > 0 */
   double delta;             /* > 0: unsteady operator (1/delta) M_rho + A of eq. (timedep2) */
@@ -159,11 +162,13 @@ typedef struct {
 } ldgs_problem;
 
 /* Data of the right-hand side, eq. (govern1)-(govern3).  Each callback may be
- * NULL (meaning zero).  ncomp: f d, f_div 1, g_dirichlet d, g_jump d, h_jump d.
- * g_jump / h_jump are the jumps [u] and [sigma n] on interphase faces, normal
- * from phase 1 into phase 2, phase[] giving the phase-1 side. */
+ * NULL (meaning zero).  ncomp: f d, f_div 1, g_dirichlet d, g_jump d, h_jump d,
+ * h_stress d.  g_jump / h_jump are the jumps [u] and [sigma n] on interphase
+ * faces, normal from phase 1 into phase 2, phase[] giving the phase-1 side.
+ * h_stress is the stress data h = sigma n on stress walls (n outward; it
+ * enters through the vector J_h of the appendix on the LDG construction). */
 typedef struct {
-  ldgs_eval_fn f, f_div, g_dirichlet, g_jump, h_jump;
+  ldgs_eval_fn f, f_div, g_dirichlet, g_jump, h_jump, h_stress;
   void* user;
 } ldgs_rhs_data;
 

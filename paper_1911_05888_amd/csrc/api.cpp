@@ -94,6 +94,7 @@ struct ldgs_ctx {
   // the size (tests)
   int64_t mfma_min = 8192;
   std::vector<int> kernel_offsets;
+  bool rotations = false;            // the rigid rotations belong to the kernel (stress walls)
   PrecStore<double> s64;
   PrecStore<float> s32;      // float arithmetic, float inverses
   PrecStore<float> s16;      // float arithmetic, bf16 inverses (shares operator data with s32)
@@ -231,10 +232,18 @@ T* upload(ldgs_ctx* c, const std::vector<double>& src) {
   return d;
 }
 
+bool stress_walls(const ldgs_problem& P) { return P.bc[0] == LDGS_STRESS; }
+
+// trivial kernel (bottom-solver footnote): periodic steady: constant velocity
+// components and pressure; stress walls, steady: constant velocity components
+// and, in viscous-stress form, the d(d-1)/2 rigid rotations (none when
+// unsteady); otherwise the constant pressure
 int kernel_dim(const ldgs_problem& P) {
+  const bool steady = !(P.delta > 0.0);
+  if (stress_walls(P)) return steady ? P.dim + (P.form ? P.dim * (P.dim - 1) / 2 : 0) : 0;
   bool per = true;
   for (int j = 0; j < P.dim; ++j) per = per && P.bc[j] == LDGS_PERIODIC;
-  return (per && !(P.delta > 0.0)) ? P.dim + 1 : 1;
+  return (per && steady) ? P.dim + 1 : 1;
 }
 
 void fill_defaults(ldgs_problem& P) {
@@ -258,10 +267,14 @@ void validate(const ldgs_problem& P) {
   if (!pow2(P.n) || !pow2(P.coarsest_n) || P.coarsest_n < 2 || P.coarsest_n > P.n)
     throw Fail{LDGS_E_ARG, "n and coarsest_n must be powers of two with 2 <= coarsest_n <= n"};
   if (P.form != 0 && P.form != 1) throw Fail{LDGS_E_ARG, "form"};
+  int nstress = 0;
   for (int j = 0; j < P.dim; ++j) {
-    if (P.bc[j] == LDGS_STRESS) throw Fail{LDGS_E_UNSUPPORTED, "stress boundary conditions"};
-    if (P.bc[j] != LDGS_PERIODIC && P.bc[j] != LDGS_DIRICHLET) throw Fail{LDGS_E_ARG, "bc"};
+    if (P.bc[j] != LDGS_PERIODIC && P.bc[j] != LDGS_DIRICHLET && P.bc[j] != LDGS_STRESS)
+      throw Fail{LDGS_E_ARG, "bc"};
+    nstress += P.bc[j] == LDGS_STRESS;
   }
+  if (nstress != 0 && nstress != P.dim)
+    throw Fail{LDGS_E_UNSUPPORTED, "stress boundary conditions must be given on every axis"};
   if (P.levelset_kind != LDGS_LEVELSET_NONE) {
     if (P.levelset_kind != LDGS_LEVELSET_BOX) throw Fail{LDGS_E_UNSUPPORTED, "curved level sets"};
     if (!P.host_only && P.dim != 2) throw Fail{LDGS_E_UNSUPPORTED, "interphase faces are supported in 2D"};
@@ -323,6 +336,7 @@ DevLevel<T> make_view(ldgs_ctx* c, const Level& L, bool with_scale) {
   for (int k = 0; k < d; ++k)
     for (unsigned char t : L.faces[k].type) iface = iface || t == F_INTER;
   v.iface = iface ? 1 : 0;
+  v.stress = stress_walls(c->P) ? 1 : 0;
   v.n = L.n;
   v.hinv = (T)(1.0 / L.h);
   for (int k = 0; k < 3; ++k) {
@@ -337,12 +351,16 @@ DevLevel<T> make_view(ldgs_ctx* c, const Level& L, bool with_scale) {
         if (d != 2) throw Fail{LDGS_E_UNSUPPORTED, "interphase faces are supported in 2D"};
       } else for (int64_t id = 0; id < fs.count; ++id) {
         const int64_t f = (id / face_stride(L.n, k)) % fs.nfk;
+        const bool wall = fs.nfk != L.n && (f == 0 || f == L.n);
+        const bool stress = wall && c->P.bc[k] == LDGS_STRESS;
         unsigned char want = F_INTRA;
         if (fs.nfk != L.n && f == 0) want = F_DIR_LO;
         if (fs.nfk != L.n && f == L.n) want = F_DIR_HI;
+        if (stress) want = F_NONE;
         const double wl = fs.w[2 * id], wr = fs.w[2 * id + 1];
-        if (fs.type[id] != want || wl != (want == F_DIR_HI ? 1.0 : 0.0) || wr != (want == F_DIR_HI ? 0.0 : 1.0))
-          throw Fail{LDGS_E_UNSUPPORTED, "face types other than intraphase and Dirichlet are not supported on the GPU"};
+        const double wl_want = want == F_DIR_HI ? 1.0 : 0.0, wr_want = (want == F_DIR_HI || stress) ? 0.0 : 1.0;
+        if (fs.type[id] != want || wl != wl_want || wr != wr_want)
+          throw Fail{LDGS_E_UNSUPPORTED, "face types other than intraphase, Dirichlet and stress walls are not supported on the GPU"};
       }
       unsigned char* ft = dalloc<unsigned char>(c, fs.count);
       HIPCHK(hipMemcpy(ft, fs.type.data(), fs.count, hipMemcpyHostToDevice));
@@ -1013,12 +1031,34 @@ void residual_fine(ldgs_ctx* c, const double* b, const double* x, double* r) {
 }
 
 void project_kernel(ldgs_ctx* c, double* v) {
-  const int64_t NE = c->levels[0].NE;
+  const Level& L = c->levels[0];
+  const int64_t NE = L.NE;
   const int nblk = 256;
   for (int off : c->kernel_offsets) {
     LCHK(launch_strided_sum_partial(c->stream, NE, c->g.nb, off, v, c->w_part, nblk));
     double mean = host_sum_partials(c, nblk) / (double)NE;
     LCHK(launch_strided_add(c->stream, NE, c->g.nb, off, -mean, v));
+  }
+  if (c->rotations) {
+    // rotation (x_a - 1/2) e_b - (x_b - 1/2) e_a, a < b: per element the mean
+    // coefficient m(E) = x_a(centre) - 1/2 and the linear coefficient h / (2
+    // sqrt 3) (times the common factor h^{d/2}), of u_b, and minus those of
+    // x_b in u_a; orthogonal to the translations and to each other
+    const int d = c->g.d, n = L.n;
+    const double lin = L.h / (2.0 * std::sqrt(3.0));
+    double cc = 0.0;   // sum over elements of m(E)^2 along one axis, times n^{d-1}
+    for (int i = 0; i < n; ++i) {
+      const double m = (i + 0.5) * L.h - 0.5;
+      cc += m * m;
+    }
+    cc *= (double)NE / n;
+    const double rr = 2.0 * (cc + (double)NE * lin * lin);
+    for (int a = 0; a < d; ++a)
+      for (int b = a + 1; b < d; ++b) {
+        LCHK(launch_rotation_dot_partial(c->stream, d, c->g.p, log2i(n), L.h, a, b, v, c->w_part, nblk));
+        const double w = host_sum_partials(c, nblk) / rr;
+        LCHK(launch_rotation_axpy(c->stream, d, c->g.p, log2i(n), L.h, a, b, -w, v));
+      }
   }
 }
 
@@ -1292,8 +1332,16 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
       tmark = now;
     };
     c->k0 = kernel_dim(P);
-    if (c->k0 == 1) c->kernel_offsets = {P.dim * c->g.nq};
-    else for (int i = 0; i <= P.dim; ++i) c->kernel_offsets.push_back(i * c->g.nq);
+    if (stress_walls(P)) {
+      // constant velocity components; the rotations are projected separately
+      if (c->k0 > 0)
+        for (int i = 0; i < P.dim; ++i) c->kernel_offsets.push_back(i * c->g.nq);
+      c->rotations = c->k0 > P.dim;
+    } else if (c->k0 == 1) {
+      c->kernel_offsets = {P.dim * c->g.nq};
+    } else {
+      for (int i = 0; i <= P.dim; ++i) c->kernel_offsets.push_back(i * c->g.nq);
+    }
     // hierarchy
     c->levels.emplace_back();
     build_fine_level(P, c->g, c->B, c->levels[0]);

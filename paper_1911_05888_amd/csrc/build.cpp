@@ -322,7 +322,12 @@ void build_fine_level(const ldgs_problem& P, const Geometry& g, const Basis& B, 
       std::vector<double> tau(nt), tmu(nt), trho(nt);
       unsigned char ty;
       double wL = 0.0, wR = 0.0;
-      if (EL[id] < 0) {
+      if ((EL[id] < 0 || ER[id] < 0) && P.bc[k] == LDGS_STRESS) {
+        // stress wall: u-hat = u- (no lift), sigma-hat = h n (data only), no
+        // velocity or pressure penalty: no operator terms
+        ty = F_NONE;
+        for (int i = 0; i < nt; ++i) tau[i] = 0.0;
+      } else if (EL[id] < 0) {
         ty = F_DIR_LO;
         wR = 1.0;
         for (int i = 0; i < nt; ++i) tau[i] = tb * muR[(size_t)id * nt + i];

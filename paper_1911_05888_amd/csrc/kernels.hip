@@ -522,8 +522,8 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, const TabT<T>
         const bool per = lev.nf[k] == n;
         int f = cF[k] + side;
         unsigned char ty = F_INTRA;
-        if (!per && f == 0) ty = F_DIR_LO;
-        if (!per && f == n) ty = F_DIR_HI;
+        if (!per && f == 0) ty = lev.stress ? (unsigned char)F_NONE : (unsigned char)F_DIR_LO;
+        if (!per && f == n) ty = lev.stress ? (unsigned char)F_NONE : (unsigned char)F_DIR_HI;
         if (per) f &= n - 1;
         const int id = face_index<D>(cF, n, lev.nf[k], k, f);
         if constexpr (IF) {
@@ -540,10 +540,11 @@ __device__ __forceinline__ void elem_issue(const DevLevel<T>& lev, const TabT<T>
         } else {
           // without interphase faces the type and the lifting weights follow
           // from the position: Dirichlet faces at the walls (weight 1 on their
-          // element), intraphase faces elsewhere, (wL, wR) = (0, 1)
+          // element), intraphase faces elsewhere, (wL, wR) = (0, 1); stress
+          // walls carry no face terms (type F_NONE, weights 0)
           d.fty[fi][k][side] = valid ? ty : (unsigned char)F_NONE;
           d.fwl[fi][k][side] = (valid && ty == F_DIR_HI) ? (T)1 : (T)0;
-          d.fwr[fi][k][side] = (valid && ty != F_DIR_HI) ? (T)1 : (T)0;
+          d.fwr[fi][k][side] = (valid && ty != F_DIR_HI && ty != F_NONE) ? (T)1 : (T)0;
         }
         if (fi == 0) fid0[k][side] = id;
       }
@@ -2138,6 +2139,70 @@ int launch_strided_sum_partial(void* stream, int64_t nelem, int nb, int off, con
   hipLaunchKernelGGL(k_strided_sum_partial, dim3(nblk), dim3(RB), 0, (hipStream_t)stream, nelem, nb, off, x, out);
   return hip_ok();
 }
+// Rigid rotation mode r of the kernel with stress walls: entry t = (E, field
+// f, coefficient q) is m_a(E) at (f = b, q = 0), h / (2 sqrt 3) at (f = b, q =
+// M^a), -m_b(E) at (f = a, q = 0), -h / (2 sqrt 3) at (f = a, q = M^b), zero
+// elsewhere; m_k(E) = (c_k(E) + 1/2) h - 1/2.  OP 0: partial sums of v . r per
+// block (out[block]); OP 1: v += alpha r.
+template <int OP>
+__global__ __launch_bounds__(256) void k_rotation(int64_t N, int d, int M, int nb, int nq, int lgn, double h, int a,
+                                                  int b, double alpha, const double* __restrict__ vin,
+                                                  double* __restrict__ vout, double* __restrict__ out) {
+  __shared__ double sm[256];
+  const double lin = h / (2.0 * sqrt(3.0));
+  int Ma = 1, Mb = 1;
+  for (int j = 0; j < a; ++j) Ma *= M;
+  for (int j = 0; j < b; ++j) Mb *= M;
+  const int n = 1 << lgn;
+  double acc = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < N; t += (int64_t)gridDim.x * 256) {
+    const int64_t E = t / nb;
+    const int r = (int)(t - E * nb), f = r / nq, q = r - f * nq;
+    double val = 0.0;
+    if (f == b || f == a) {
+      const int ax = f == b ? a : b;
+      const double sg = f == b ? 1.0 : -1.0;
+      const int c = (int)((E >> (ax * lgn)) & (n - 1));
+      if (q == 0) val = sg * ((c + 0.5) * h - 0.5);
+      else if (q == (f == b ? Ma : Mb)) val = sg * lin;
+    }
+    if (OP == 0) acc += vin[t] * val;
+    else if (val != 0.0) vout[t] += alpha * val;
+  }
+  if (OP == 0) {
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) sm[threadIdx.x] += sm[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sm[0];
+  }
+}
+
+int launch_rotation_dot_partial(void* stream, int d, int p, int lgn, double h, int a, int b, const double* v,
+                                double* out, int nblk) {
+  const int M = p + 1;
+  int nq = 1;
+  for (int j = 0; j < d; ++j) nq *= M;
+  const int nb = (d + 1) * nq;
+  const int64_t N = ((int64_t)1 << (d * lgn)) * nb;
+  hipLaunchKernelGGL(k_rotation<0>, dim3(nblk), dim3(256), 0, (hipStream_t)stream, N, d, M, nb, nq, lgn, h, a, b, 0.0,
+                     v, nullptr, out);
+  return hip_ok();
+}
+
+int launch_rotation_axpy(void* stream, int d, int p, int lgn, double h, int a, int b, double alpha, double* v) {
+  const int M = p + 1;
+  int nq = 1;
+  for (int j = 0; j < d; ++j) nq *= M;
+  const int nb = (d + 1) * nq;
+  const int64_t N = ((int64_t)1 << (d * lgn)) * nb;
+  hipLaunchKernelGGL(k_rotation<1>, dim3(grid1(N, 256)), dim3(256), 0, (hipStream_t)stream, N, d, M, nb, nq, lgn, h, a,
+                     b, alpha, nullptr, v, nullptr);
+  return hip_ok();
+}
+
 int launch_strided_add(void* stream, int64_t nelem, int nb, int off, double v, double* x) {
   hipLaunchKernelGGL(k_strided_add, dim3(grid1(nelem, 256)), dim3(256), 0, (hipStream_t)stream, nelem, nb, off, v, x);
   return hip_ok();

@@ -105,6 +105,7 @@ struct DevLevel {
   const T* rmu;                    // [NE][D][MT*NQ] low-face trace rows (e0^T)_k M_mu, with mmu
   const T* rmuh;                   // [NE][D][MT*NQ] high-face trace rows (e1^T)_k M_mu (levels with interphase faces)
   int iface;                       // level has interphase faces: extended stencil, face data from the tables
+  int stress;                      // the walls are stress walls (no face terms), not Dirichlet
   T mu_const;
   T rho_delta;                     // rho / delta (0: steady)
   const T* dscale;                 // [NE][2] (alpha, beta) or nullptr
@@ -181,6 +182,12 @@ int launch_dot_partial(void* stream, int64_t n, const double* x, const double* y
 int launch_strided_sum_partial(void* stream, int64_t nelem, int nb, int off, const double* x,
                                double* out, int nblk);
 int launch_strided_add(void* stream, int64_t nelem, int nb, int off, double v, double* x);
+// rigid rotation (x_a - 1/2) e_b - (x_b - 1/2) e_a on the n^d grid (n = 2^lgn,
+// width h), as coefficients without the common factor h^{d/2}: partial sums
+// of <v, r> (out: nblk doubles), and v += alpha r
+int launch_rotation_dot_partial(void* stream, int d, int p, int lgn, double h, int a, int b, const double* v,
+                                double* out, int nblk);
+int launch_rotation_axpy(void* stream, int d, int p, int lgn, double h, int a, int b, double alpha, double* v);
 
 // Device setup of per-element inverses (setup_dev.hip): unit vectors e_j on
 // the listed elements (j = nb only clears entry nb - 1), column j of each

@@ -123,7 +123,6 @@ void assemble_rhs_host(const ldgs_problem& P, const Geometry& g, const Basis& B,
     const FaceSet& fs = L.faces[k];
     for (int64_t id = 0; id < fs.count; ++id) {
       unsigned char ty = fs.type[id];
-      if (ty != F_DIR_LO && ty != F_DIR_HI && ty != F_INTER) continue;
       int c[3] = {0, 0, 0};
       int64_t r = id;
       int f = 0;
@@ -134,6 +133,8 @@ void assemble_rhs_host(const ldgs_problem& P, const Geometry& g, const Basis& B,
         if (j == k) f = v;
         else c[j] = v;
       }
+      const bool stress = P.bc[k] == LDGS_STRESS && fs.nfk != n && (f == 0 || f == n);
+      if (ty != F_DIR_LO && ty != F_DIR_HI && ty != F_INTER && !stress) continue;
       int64_t eL, eR;
       face_elements(L, d, k, f, c, &eL, &eR);
       std::vector<double> Xf(nt * d), nrm(nt * d, 0.0), gv(nt * d, 0.0), hv(nt * d, 0.0), mu(nt), coef(nt);
@@ -142,7 +143,23 @@ void assemble_rhs_host(const ldgs_problem& P, const Geometry& g, const Basis& B,
         int jj = 0;
         for (int j = 0; j < d; ++j) Xf[i * d + j] = (j == k) ? f * h : (c[j] + tp[i * (d - 1) + jj++]) * h;
       }
-      if (ty == F_DIR_LO || ty == F_DIR_HI) {
+      if (stress) {
+        // J_h: int_wall phi h_i with h = sigma n, n outward
+        const bool lo = f == 0;
+        const int64_t Em = lo ? eR : eL;
+        const double s = lo ? -1.0 : 1.0;
+        const double* e = lo ? B.e0.data() : B.e1.data();
+        for (int i = 0; i < nt; ++i) {
+          phm[i] = L.chi[Em];
+          nrm[i * d + k] = s;
+        }
+        if (!data.h_stress) continue;
+        data.h_stress(nt, Xf.data(), phm.data(), nrm.data(), hv.data(), data.user);
+        for (int i = 0; i < d; ++i) {
+          for (int qq = 0; qq < nt; ++qq) coef[qq] = hv[qq * d + i];
+          add_face(Jh[i], Em, k, e, coef.data(), 1.0);
+        }
+      } else if (ty == F_DIR_LO || ty == F_DIR_HI) {
         const int64_t Em = (ty == F_DIR_LO) ? eR : eL;
         const double s = (ty == F_DIR_LO) ? -1.0 : 1.0;        // outward normal n_k
         const double* e = (ty == F_DIR_LO) ? B.e0.data() : B.e1.data();

@@ -61,7 +61,7 @@ class ProblemStruct(C.Structure):
 
 class RhsData(C.Structure):
     _fields_ = [("f", EVAL_FN), ("f_div", EVAL_FN), ("g_dirichlet", EVAL_FN), ("g_jump", EVAL_FN),
-                ("h_jump", EVAL_FN), ("user", C.c_void_p)]
+                ("h_jump", EVAL_FN), ("h_stress", EVAL_FN), ("user", C.c_void_p)]
 
 
 class Info(C.Structure):
@@ -204,7 +204,7 @@ def problem_struct(prob, vprec=V_FP64, build_precisions=0, host_only=False, stre
     s = ProblemStruct()
     s.dim, s.n, s.degree, s.form = prob.dim, prob.n, prob.p, prob.gamma
     for j, b in enumerate(prob.bc):
-        s.bc[j] = PERIODIC if b == "periodic" else DIRICHLET
+        s.bc[j] = {"periodic": PERIODIC, "dirichlet": DIRICHLET, "stress": STRESS}[b]
     s.mu = _field(prob.mu, prob.dim, keep)
     if getattr(prob, "rho", None) is not None:
         s.rho = _field(prob.rho, prob.dim, keep)
@@ -255,6 +255,8 @@ def rhs_callbacks(src, dim):
             return np.einsum("nij,nj->ni", sd, nr)
         r.g_jump = mk(gj, dim)
         r.h_jump = mk(hj, dim)
+        # stress walls: h = sigma n, n the outward normal the library passes
+        r.h_stress = mk(lambda x, ph, nr: np.einsum("nij,nj->ni", src.stress(x, ph), nr), dim)
     return r, keep
 
 

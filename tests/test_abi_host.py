@@ -9,7 +9,7 @@ import re
 import numpy as np
 import pytest
 
-from synth import (Problem, ConstField, c1_periodic_standard, c2_dirichlet_varmu, c3_unsteady_periodic,
+from synth import (Problem, ConstField, SinProductField, stress_walls, c1_periodic_standard, c2_dirichlet_varmu, c3_unsteady_periodic,
                    c4a_square_inclusion)
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -100,6 +100,9 @@ HOST_CASES = {
     "per3d_n4_p2": lambda: Problem(name="p3", dim=3, n=4, p=2, gamma=1, bc=("periodic",) * 3),
     "c3_n8_p1": lambda: c3_unsteady_periodic(n=8, p=1, re_eff=1000.0, h_ref=1.0 / 64),
     "dir3d_n4_p1": lambda: Problem(name="d3", dim=3, n=4, p=1, gamma=0, bc=("dirichlet",) * 3),
+    "stress2d_n8_p2": lambda: stress_walls(dim=2, n=8, p=2),
+    "stress2d_n8_p3_mu": lambda: stress_walls(dim=2, n=8, p=3, mu=SinProductField(1.0, 0.5, 2.0)),
+    "stress3d_n4_p2": lambda: stress_walls(dim=3, n=4, p=2),
 }
 
 
@@ -126,8 +129,10 @@ def test_host_setup_matches_oracle(name):
     assert np.allclose(np.sort(eig), lam_o, atol=1e-10 * np.abs(lam_o).max())
     bot = H.levels[-1]
     b = rng.standard_normal(bot.A.shape[0])
+    if all(bc == "stress" for bc in prob.bc):
+        b = bot.A @ b                                   # in range(A_c) (rigid-motion kernel)
     # b in range(A_c): orthogonal to the trivial kernel
-    fields = [prob.dim] if H.k0 == 1 else list(range(prob.dim + 1))
+    fields = [] if all(bc == "stress" for bc in prob.bc) else ([prob.dim] if H.k0 == 1 else list(range(prob.dim + 1)))
     for f in fields:
         # kernel vector of the (possibly scaled) bottom operator D A D: the
         # constant field divided by the scaling
@@ -158,7 +163,8 @@ def test_shared_inverse_levels_are_those_with_equal_blocks(name):
     assert not ctx.level_shared_inverse(len(H.levels) - 1)
 
 
-@pytest.mark.parametrize("name", ["c1_n8_p2", "c2_n8_p3", "c3_n8_p1", "c4a_n16_p2"])
+@pytest.mark.parametrize("name", ["c1_n8_p2", "c2_n8_p3", "c3_n8_p1", "c4a_n16_p2", "stress2d_n8_p2",
+                                  "stress2d_n8_p3_mu", "stress3d_n4_p2"])
 def test_host_rhs_matches_oracle(name):
     from oracle import build_hierarchy
     from oracle.rhs import assemble_rhs

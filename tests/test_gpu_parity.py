@@ -22,7 +22,7 @@ oracle builds its own b for the RHS parity test).  Tolerances:
 import numpy as np
 import pytest
 
-from synth import (Problem, SinProductField, c1_periodic_standard, c2_dirichlet_varmu, c3_unsteady_periodic, c4a_square_inclusion,
+from synth import (Problem, SinProductField, stress_walls, c1_periodic_standard, c2_dirichlet_varmu, c3_unsteady_periodic, c4a_square_inclusion,
                    c5_lognormal)
 
 pytestmark = pytest.mark.gpu
@@ -39,6 +39,10 @@ CASES = {
     "c4a_n32_p1": lambda: c4a_square_inclusion(n=32, p=1),
     "c5_n8_p2": lambda: c5_lognormal(n=8, p=2),
     "c5_n8_p2_scaled": lambda: c5_lognormal(n=8, p=2, diag_scaling=True),
+    # stress walls (sections 5.3, 5.4): no face terms on the walls, rigid-motion kernel
+    "stress2d_n16_p2": lambda: stress_walls(dim=2, n=16, p=2),
+    "stress2d_n16_p3_mu": lambda: stress_walls(dim=2, n=16, p=3, mu=SinProductField(1.0, 0.5, 2.0)),
+    "stress3d_n8_p2": lambda: stress_walls(dim=3, n=8, p=2),
     # eq. (mu) in 3D with Dirichlet walls: distinct blocks on every level, a contracting cycle
     "mu3d_n8_p2": lambda: Problem(name="mu3d_n8_p2", dim=3, n=8, p=2, gamma=1, bc=("dirichlet",) * 3,
                                   mu=SinProductField(1.0, 0.5, 2.0), coloring="parity"),
@@ -152,9 +156,12 @@ def test_bottom_solve(name):
     bot = H.levels[-1]
     rng = np.random.Generator(np.random.PCG64(15))
     b = rng.standard_normal(bot.A.shape[0])
+    stress = all(bc == "stress" for bc in prob.bc)
+    if stress:
+        b = bot.A @ b                     # in the range (the kernel holds the rigid motions)
     # a right-hand side in the range of A_c (bottom residuals are): orthogonal
     # to the trivial kernel
-    fields = [prob.dim] if H.k0 == 1 else list(range(prob.dim + 1))
+    fields = [] if stress else ([prob.dim] if H.k0 == 1 else list(range(prob.dim + 1)))
     for f in fields:
         # kernel vector of the (possibly scaled) bottom operator D A D: the
         # constant field divided by the scaling
@@ -171,6 +178,19 @@ def test_bottom_solve(name):
     scale = np.linalg.norm(np.abs(b) + abs(bot.A) @ np.abs(xg))
     assert np.linalg.norm(b - bot.A @ xg) <= 1e-13 * scale, name
     assert rel(xg, y) <= 1e-7, name
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_project_kernel_matches_oracle(name):
+    """The library's removal of the trivial kernel (constant fields; rigid
+    motions with stress walls) equals the oracle's orthogonal projection."""
+    prob, H, ctx = setup_case(name)
+    rng = np.random.Generator(np.random.PCG64(19))
+    v = rng.standard_normal(H.fine.A.shape[0])
+    vg = dev(v)
+    ctx.project_kernel(vg)
+    vo = H.project_kernel(v)
+    assert np.abs(host(vg) - vo).max() <= 1e-12 * np.abs(v).max()
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -191,7 +211,7 @@ def test_apply_and_rhs_fine(name):
 
 @pytest.mark.parametrize("name", ["c1_n16_p2", "c2_n32_p3", "per3d_n8_p2", "c3_n8_p2", "c3_n8_p2_re0.1",
                                   "c3_n8_p2_re1000", "c4a_n16_p2", "c4a_n32_p1", "c5_n8_p2", "c5_n8_p2_scaled",
-                                  "mu3d_n8_p2"])
+                                  "mu3d_n8_p2", "stress2d_n16_p2", "stress2d_n16_p3_mu", "stress3d_n8_p2"])
 def test_vcycle_residual_history(name):
     """Stationary FP64 V-cycle: rho_k within 1e-11 max(1, rho_{k-1}, rho_k)
     + u F_k of the oracle's for k <= 8."""
@@ -255,3 +275,26 @@ def test_deterministic_residual_history():
         runs.append((info["history"], host(x)))
     assert np.array_equal(runs[0][0], runs[1][0])
     assert np.array_equal(runs[0][1], runs[1][1])
+
+
+@pytest.mark.parametrize("name", ["stress2d_n16_p2", "stress3d_n8_p2"])
+def test_stress_solve_matches_oracle_solution(name):
+    """Stress walls end to end: the library's right-hand side, FGMRES with the
+    FP64 V-cycle to 1e-10, and the discretisation error of its solution
+    against the oracle's (same error measure, rigid motions removed)."""
+    from oracle.errors import solution_errors
+    from oracle.rhs import assemble_rhs
+    from oracle.solvers import Solver
+    from paper_1911_05888_amd import FGMRES
+    prob, H, ctx = setup_case(name)
+    b = ctx.assemble_rhs(prob.rhs_source())
+    x = ctx.zeros()
+    st, info = ctx.solve(b, x, tol=1e-10, maxit=100, outer=FGMRES, fgmres_m=60)
+    print(name, "FGMRES iterations", info["iters"], "relres", info["relres"], flush=True)
+    assert st == 0 and info["iters"] <= 20
+    xo, _ = Solver(H).fgmres(assemble_rhs(prob, H.fine.ops), tol=1e-10, m=60, maxit=100)
+    eg = solution_errors(prob, H.project_kernel(host(x)), H.k0)
+    eo = solution_errors(prob, H.project_kernel(xo), H.k0)
+    print(name, "errors gpu", eg, "oracle", eo, flush=True)
+    for k in eo:
+        assert abs(eg[k] - eo[k]) <= 1e-6 * eo[k] + 1e-9, k
