@@ -9,6 +9,7 @@ markdown table; run as
     python -m paper_1911_05888_amd.rho_study refine      # rho against n (section 5.1)
     python -m paper_1911_05888_amd.rho_study unsteady    # tau_0 of eq. (taugeneral) at Re ~ 1e4
     python -m paper_1911_05888_amd.rho_study viscosity   # smooth and log-normal viscosity, 3D
+    python -m paper_1911_05888_amd.rho_study stress      # stress walls (sections 5.3, 5.4)
 
 The problem data come from ``synth`` (closed forms and seeded fields).
 """
@@ -103,6 +104,27 @@ def viscosity():
             print(f"| {label} | {'on' if scal else 'off'} | " + " | ".join(vals) + " |", flush=True)
 
 
+def stress():
+    """Stress walls, viscous-stress form (sections 5.3 and 5.4): mu = 1 and
+    eq. (mu), rho against n."""
+    from synth import stress_walls, SinProductField
+    mu = SinProductField(1.0, 0.5, 2.0)
+    rows = [("2D mu = 1, p = 2", 2, 2, None, (8, 16, 32, 64, 128)),
+            ("2D mu = 1, p = 3", 2, 3, None, (8, 16, 32, 64, 128)),
+            ("2D eq. (mu), p = 2", 2, 2, mu, (8, 16, 32, 64, 128)),
+            ("3D mu = 1, p = 2", 3, 2, None, (8, 16, 32)),
+            ("3D eq. (mu), p = 2", 3, 2, mu, (8, 16, 32))]
+    print("| stress walls | " + " | ".join(f"n={n}" for n in (8, 16, 32, 64, 128)) + " |")
+    print("|---|" + "---|" * 5)
+    for label, d, p, m, ns in rows:
+        vals = []
+        for n in ns:
+            r, its, ok = rho_of(stress_walls(dim=d, n=n, p=p, mu=m))
+            vals.append(f"{r:.3f} ({its})" if ok else f"{r:.3f} (no 1e8 in {its})")
+        vals += ["—"] * (5 - len(ns))
+        print(f"| {label} | " + " | ".join(vals) + " |", flush=True)
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "valley"
-    {"valley": valley, "refine": refine, "unsteady": unsteady, "viscosity": viscosity}[which]()
+    {"valley": valley, "refine": refine, "unsteady": unsteady, "viscosity": viscosity, "stress": stress}[which]()
