@@ -51,14 +51,15 @@ HBM_PEAK_GBS = 8000.0
 TOL = 1e-10
 
 
-def method_bytes(prob, elems, w=8, dense=False, shared=False):
+def method_bytes(prob, elems, w=8, dense=False, shared=False, w_inv=None):
     """Bytes a colour pass over `elems` elements must move: the inverse
-    (symmetric part, or dense n_b^2; none when the level holds one inverse),
-    x, b and x out, the viscosity quadrature values."""
+    (symmetric part, or dense n_b^2; none when the level holds one inverse;
+    w_inv bytes per entry, default w), x, b and x out, the viscosity
+    quadrature values."""
     nb = prob.nb
     inv = 0 if shared else (nb * nb if dense else nb * (nb + 1) // 2)
     mu = (prob.p + 2) ** prob.dim if getattr(prob.mu, "kind", "") != "const" else 0
-    return elems * (inv * w + 3 * nb * w + mu * w)
+    return elems * (inv * (w if w_inv is None else w_inv) + 3 * nb * w + mu * w)
 
 
 def cpu_model():
@@ -320,11 +321,20 @@ def main():
             params, c_vel, c_pre, wrec = load_weights(wfile)
             ctx.set_learned(params, c_vel, c_pre)
             runs.append(("fp32_learned", V_FP32, True))
+        tt_elems = ttprob.n_elements / ctx.level_info(0)[2]
+        tt_shared = ctx.level_shared_inverse(0)
         for label, vp, learned in runs:
             tc = vcycle_rate(ctx, b0, vp)
             ts, cyc, its, rel = solve(ctx, b0, vp, 1, label, flexible=krylov, learned=learned)
             tt[label] = dict(time_to_tol_s=ts, iters=its, vcycles=cyc, vcycle_s=tc,
                              vcycle_dof_per_s=ctx.ndof / tc, relres=rel)
+            if not learned:
+                # the finest colour pass of this precision against its own method bytes
+                tp, _ = finest_pass_time(ctx, b0, vp)
+                w = 8 if vp == V_FP64 else 4
+                mb = method_bytes(ttprob, tt_elems, w, shared=tt_shared, w_inv=2 if vp == V_FP32_BF16BLK else w)
+                tt[label]["finest_pass_us"] = tp * 1e6
+                tt[label]["finest_pass_frac_hbm"] = mb / tp / 1e9 / HBM_PEAK_GBS
             if learned:
                 tt[label]["training"] = {k: wrec[k] for k in ("n", "pairs", "seeds", "loss_first", "loss_last")}
             log(f"{label}: V-cycle {tc * 1e3:.1f} ms, time to 1e-10 {ts:.3f} s ({its:.0f} iterations)")

@@ -103,6 +103,10 @@ HOST_CASES = {
     "stress2d_n8_p2": lambda: stress_walls(dim=2, n=8, p=2),
     "stress2d_n8_p3_mu": lambda: stress_walls(dim=2, n=8, p=3, mu=SinProductField(1.0, 0.5, 2.0)),
     "stress3d_n4_p2": lambda: stress_walls(dim=3, n=4, p=2),
+    # standard form (kernel: translations only) and unsteady (no kernel) with stress walls
+    "stress2d_std_n8_p2": lambda: Problem(name="sstd", dim=2, n=8, p=2, gamma=0, bc=("stress",) * 2, coloring="parity"),
+    "stress2d_unsteady_n8_p2": lambda: Problem(name="sun", dim=2, n=8, p=2, gamma=1, bc=("stress",) * 2,
+                                               coloring="parity", rho=ConstField(1.0), delta=0.01),
 }
 
 

@@ -22,7 +22,7 @@ oracle builds its own b for the RHS parity test).  Tolerances:
 import numpy as np
 import pytest
 
-from synth import (Problem, SinProductField, stress_walls, c1_periodic_standard, c2_dirichlet_varmu, c3_unsteady_periodic, c4a_square_inclusion,
+from synth import (Problem, ConstField, SinProductField, stress_walls, c1_periodic_standard, c2_dirichlet_varmu, c3_unsteady_periodic, c4a_square_inclusion,
                    c5_lognormal)
 
 pytestmark = pytest.mark.gpu
@@ -43,6 +43,10 @@ CASES = {
     "stress2d_n16_p2": lambda: stress_walls(dim=2, n=16, p=2),
     "stress2d_n16_p3_mu": lambda: stress_walls(dim=2, n=16, p=3, mu=SinProductField(1.0, 0.5, 2.0)),
     "stress3d_n8_p2": lambda: stress_walls(dim=3, n=8, p=2),
+    "stress2d_std_n16_p2": lambda: Problem(name="sstd", dim=2, n=16, p=2, gamma=0, bc=("stress",) * 2,
+                                           coloring="parity"),
+    "stress2d_unsteady_n16_p2": lambda: Problem(name="sun", dim=2, n=16, p=2, gamma=1, bc=("stress",) * 2,
+                                                coloring="parity", rho=ConstField(1.0), delta=0.01),
     # eq. (mu) in 3D with Dirichlet walls: distinct blocks on every level, a contracting cycle
     "mu3d_n8_p2": lambda: Problem(name="mu3d_n8_p2", dim=3, n=8, p=2, gamma=1, bc=("dirichlet",) * 3,
                                   mu=SinProductField(1.0, 0.5, 2.0), coloring="parity"),
@@ -211,7 +215,8 @@ def test_apply_and_rhs_fine(name):
 
 @pytest.mark.parametrize("name", ["c1_n16_p2", "c2_n32_p3", "per3d_n8_p2", "c3_n8_p2", "c3_n8_p2_re0.1",
                                   "c3_n8_p2_re1000", "c4a_n16_p2", "c4a_n32_p1", "c5_n8_p2", "c5_n8_p2_scaled",
-                                  "mu3d_n8_p2", "stress2d_n16_p2", "stress2d_n16_p3_mu", "stress3d_n8_p2"])
+                                  "mu3d_n8_p2", "stress2d_n16_p2", "stress2d_n16_p3_mu", "stress3d_n8_p2",
+                                  "stress2d_std_n16_p2", "stress2d_unsteady_n16_p2"])
 def test_vcycle_residual_history(name):
     """Stationary FP64 V-cycle: rho_k within 1e-11 max(1, rho_{k-1}, rho_k)
     + u F_k of the oracle's for k <= 8."""
