@@ -1234,42 +1234,7 @@ __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
   for (int r = lane; r < NB; r += NT) x[(size_t)E * NB + r] += part[0][r] + part[1][r];
 }
 
-// First colour pass from x = 0: the residual is b, so x_E = Ainv_E b_E with
-// no operator evaluation; the work-groups also set every other element of
-// the level to zero (zl: those elements, nzero of them; work-group idx takes
-// entries idx, idx + cnt, ...).  Same results as zeroing x and running the
-// colour pass.
-template <typename T, typename TI, int D, int P, int NT>
-__global__ __launch_bounds__(NT) void k_first_colour(int lgn, const int* __restrict__ elems, int pcol,
-                                                     const TI* __restrict__ inv, const T* __restrict__ b,
-                                                     T* __restrict__ x, const int* __restrict__ zl, int nzero) {
-  using S = Sz<D, P>;
-  constexpr int NB = S::NB;
-  using SP = SymProd<TI, NB>;
-  __shared__ alignas(16) T res[NB];
-  __shared__ T part[2][16 * SP::TR];
-  __shared__ T red[256 * SP::TR];
-  const int lane = threadIdx.x;
-  const int idx = xcd_remap(blockIdx.x, gridDim.x);
-  const int E = colour_elem<D>(idx, pcol, lgn, elems);
-  const auto* Ai = reinterpret_cast<const typename SP::Word*>(inv + (size_t)idx * SP::ESTRIDE);
-  typename SP::Word pre[SP::PF][SP::H];
-  sym_prefetch<TI, NB>(Ai, pre, lane);
-  for (int t = lane; t < NB; t += NT) res[t] = b[(size_t)E * NB + t];
-  for (int m = idx; m < nzero; m += (int)gridDim.x) {
-    const size_t z = (size_t)zl[m] * NB;
-    for (int t = lane; t < NB; t += NT) x[z + t] = (T)0;
-  }
-  __syncthreads();
-  sym_product<T, TI, NB, NT>(Ai, pre, res, part, red, lane);
-  for (int r = lane; r < NB; r += NT) x[(size_t)E * NB + r] = part[0][r] + part[1][r];
-}
 
-// Second half of a colour pass split into residual and product: x_E += Ainv_E
-// r[idx] for the listed elements, with the per-element inverses of the tile
-// layout.  One wavefront per element: the evaluation of the residual (an
-// LDS-bound kernel of its own) no longer holds the inverse's stream back, and
-// many elements' tiles are in flight per CU.
 // The product of one wavefront with the stored upper tiles, streamed column
 // by column of tiles (j outer, i <= j inner), so that the transposed sums of
 // a tile column are complete when the column ends and leave the registers:
@@ -1303,6 +1268,13 @@ struct ColOrder {
   }
   static constexpr Tab tab = make();
 };
+// tiles in flight per wavefront in the streamed product: 64 registers of requests
+template <typename TI, int NB>
+constexpr int stream_window() {
+  using SP = SymProd<TI, NB>;
+  constexpr int regs = SP::H * (int)sizeof(typename SP::Word) / 4;
+  return 64 / regs < 1 ? 1 : 64 / regs;
+}
 template <typename T, typename TI, int NB, int WIN>
 __device__ __forceinline__ void sym_product_stream(const InvWord<TI>* __restrict__ Ai, const T* __restrict__ rsrc,
                                                    T* res, T (*part)[16 * SymProd<TI, NB>::TR], T* red, int lane) {
@@ -1378,6 +1350,51 @@ __device__ __forceinline__ void sym_product_stream(const InvWord<TI>* __restrict
   __syncthreads();
 }
 
+// First colour pass from x = 0: the residual is b, so x_E = Ainv_E b_E with
+// no operator evaluation; the work-groups also set every other element of
+// the level to zero (zl: those elements, nzero of them; work-group idx takes
+// entries idx, idx + cnt, ...).  Same results as zeroing x and running the
+// colour pass.
+template <typename T, typename TI, int D, int P, int NT>
+__global__ __launch_bounds__(NT) void k_first_colour(int lgn, const int* __restrict__ elems, int pcol,
+                                                     const TI* __restrict__ inv, const T* __restrict__ b,
+                                                     T* __restrict__ x, const int* __restrict__ zl, int nzero) {
+  using S = Sz<D, P>;
+  constexpr int NB = S::NB;
+  using SP = SymProd<TI, NB>;
+  __shared__ alignas(16) T res[NB];
+  __shared__ T part[2][16 * SP::TR];
+  __shared__ T red[(NT == 64 ? 64 : 256) * SP::TR];
+  const int lane = threadIdx.x;
+  const int idx = xcd_remap(blockIdx.x, gridDim.x);
+  const int E = colour_elem<D>(idx, pcol, lgn, elems);
+  const auto* Ai = reinterpret_cast<const typename SP::Word*>(inv + (size_t)idx * SP::ESTRIDE);
+  if constexpr (NT == 64) {
+    // one wavefront per element: the streamed product (as in the split pass)
+    for (int m = idx; m < nzero; m += (int)gridDim.x) {
+      const size_t z = (size_t)zl[m] * NB;
+      for (int t = lane; t < NB; t += NT) x[z + t] = (T)0;
+    }
+    sym_product_stream<T, TI, NB, stream_window<TI, NB>()>(Ai, b + (size_t)E * NB, res, part, red, lane);
+  } else {
+    typename SP::Word pre[SP::PF][SP::H];
+    sym_prefetch<TI, NB>(Ai, pre, lane);
+    for (int t = lane; t < NB; t += NT) res[t] = b[(size_t)E * NB + t];
+    for (int m = idx; m < nzero; m += (int)gridDim.x) {
+      const size_t z = (size_t)zl[m] * NB;
+      for (int t = lane; t < NB; t += NT) x[z + t] = (T)0;
+    }
+    __syncthreads();
+    sym_product<T, TI, NB, NT>(Ai, pre, res, part, red, lane);
+  }
+  for (int r = lane; r < NB; r += NT) x[(size_t)E * NB + r] = part[0][r] + part[1][r];
+}
+
+// Second half of a colour pass split into residual and product: x_E += Ainv_E
+// r[idx] for the listed elements, with the per-element inverses of the tile
+// layout.  One wavefront per element: the evaluation of the residual (an
+// LDS-bound kernel of its own) no longer holds the inverse's stream back, and
+// many elements' tiles are in flight per CU.
 template <typename T, typename TI, int D, int P>
 __global__ __launch_bounds__(64) void k_apply_inverse(int lgn, const int* __restrict__ elems, int pcol,
                                                       const TI* __restrict__ inv, const T* __restrict__ r,
@@ -1385,9 +1402,7 @@ __global__ __launch_bounds__(64) void k_apply_inverse(int lgn, const int* __rest
   using S = Sz<D, P>;
   constexpr int NB = S::NB;
   using SP = SymProd<TI, NB>;
-  // tiles in flight per wavefront: 64 registers of requests
-  constexpr int TILE_REGS = SP::H * (int)sizeof(typename SP::Word) / 4;
-  constexpr int WIN = 64 / TILE_REGS < 1 ? 1 : 64 / TILE_REGS;
+  constexpr int WIN = stream_window<TI, NB>();
   __shared__ alignas(16) T res[NB];
   __shared__ T part[2][16 * SP::TR];
   __shared__ T red[64 * SP::TR];
@@ -1679,60 +1694,109 @@ __global__ __launch_bounds__(NT) void k_residual_restrict(DevLevel<T> lev, TabT<
   }
 }
 
-// rc = I^T r for a fine-level residual r already formed: one thread per
-// coarse coefficient (the second half of the split residual + restriction used
-// on small grids, where evaluating the 2^d children of a coarse element one
-// after another in one work-group is latency bound)
+
+// sum over the coarse (or fine) coefficient digits of prod_k fac[k][digit_k] v[.]:
+// one tensor-product row of the injection applied to one field block
+template <typename T, int D, int M>
+__device__ __forceinline__ T tensor_row(const T (&fac)[D][M], const T* v) {
+  T s = 0;
+  if constexpr (D == 2) {
+#pragma unroll
+    for (int c1 = 0; c1 < M; ++c1) {
+      const T w1 = fac[1][c1];
+#pragma unroll
+      for (int c0 = 0; c0 < M; ++c0) s += w1 * fac[0][c0] * v[c0 + M * c1];
+    }
+  } else {
+#pragma unroll
+    for (int c2 = 0; c2 < M; ++c2)
+#pragma unroll
+      for (int c1 = 0; c1 < M; ++c1) {
+        const T w21 = fac[2][c2] * fac[1][c1];
+#pragma unroll
+        for (int c0 = 0; c0 < M; ++c0) s += w21 * fac[0][c0] * v[c0 + M * c1 + M * M * c2];
+      }
+  }
+  return s;
+}
+
+// r_c = I^T r, one work-group per coarse element: the 2^d children's
+// residuals are staged in LDS (coalesced reads, each value read once), then
+// every coarse coefficient is the tensor-product column of the injection
+// applied to each child's field block.
 template <typename T, int D, int P>
-__global__ void k_restrict(int lgn, TabT<T> tab, const T* __restrict__ r, T* __restrict__ rc, int64_t total) {
+__global__ __launch_bounds__(128) void k_restrict_elem(int lgn, TabT<T> tab, const T* __restrict__ r,
+                                                       T* __restrict__ rc) {
   using S = Sz<D, P>;
-  constexpr int M = S::M, NQ = S::NQ, NB = S::NB;
+  constexpr int M = S::M, NQ = S::NQ, NB = S::NB, NCH = 1 << D;
   __shared__ T Pt[2 * MAXM * MAXM];
+  __shared__ T rs[NCH][NB];
+  const int C = (int)blockIdx.x;
   if (threadIdx.x < 2 * MAXM * MAXM) Pt[threadIdx.x] = (&tab.P[0][0])[threadIdx.x];
-  __syncthreads();
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total) return;
-  const int C = (int)(t / NB), rem = (int)(t % NB);
-  const int f = rem / NQ, ac = rem % NQ;
   int cc[D];
   coords_of<D>(C, lgn - 1, cc);
-  T acc = 0;
-  for (int o = 0; o < (1 << D); ++o) {
+  for (int t = threadIdx.x; t < NCH * NB; t += 128) {
+    const int o = t / NB, q = t - o * NB;
     int cf[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) cf[j] = 2 * cc[j] + ((o >> j) & 1);
-    const T* rv = r + (size_t)index_of<D>(cf, lgn) * NB + f * NQ;
-    T s = 0;
-    for (int af = 0; af < NQ; ++af) s += pfull_lds<T, D, M>(Pt, o, af, ac) * rv[af];
-    acc += s;
+    rs[o][q] = r[(size_t)index_of<D>(cf, lgn) * NB + q];
   }
-  rc[t] = acc;
+  __syncthreads();
+  for (int q = threadIdx.x; q < NB; q += 128) {
+    const int f = q / NQ, ac = q - f * NQ;
+    T acc = 0;
+#pragma unroll
+    for (int o = 0; o < NCH; ++o) {
+      T fac[D][M];
+      int ca = ac;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        const int bit = (o >> k) & 1, ck = ca % M;
+        ca /= M;
+#pragma unroll
+        for (int m = 0; m < M; ++m) fac[k][m] = Pt[bit * MAXM * MAXM + m * M + ck];
+      }
+      acc += tensor_row<T, D, M>(fac, &rs[o][f * NQ]);
+    }
+    rc[(size_t)C * NB + q] = acc;
+  }
 }
 
-// x += I x_c: one thread per fine coefficient.
+// x += I x_c, one work-group per coarse element: its coefficients staged in
+// LDS, every fine coefficient of its 2^d children the tensor-product row of
+// the injection applied to one coarse field block.
 template <typename T, int D, int P>
-__global__ void k_prolong_add(int n, TabT<T> tab, const T* __restrict__ xc, T* __restrict__ x, int64_t total) {
+__global__ __launch_bounds__(256) void k_prolong_elem(int lgn, TabT<T> tab, const T* __restrict__ xc,
+                                                      T* __restrict__ x) {
   using S = Sz<D, P>;
-  constexpr int M = S::M, NQ = S::NQ, NB = S::NB;
+  constexpr int M = S::M, NQ = S::NQ, NB = S::NB, NCH = 1 << D;
   __shared__ T Pt[2 * MAXM * MAXM];
+  __shared__ T xs[NB];
+  const int C = (int)blockIdx.x;
   if (threadIdx.x < 2 * MAXM * MAXM) Pt[threadIdx.x] = (&tab.P[0][0])[threadIdx.x];
+  for (int q = threadIdx.x; q < NB; q += 256) xs[q] = xc[(size_t)C * NB + q];
   __syncthreads();
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total) return;
-  int64_t E = t / NB;
-  int r = (int)(t % NB);
-  int f = r / NQ, af = r % NQ;
-  const int lgn = 31 - __builtin_clz(n);
-  int c[D], o = 0;
-  coords_of<D>((int)E, lgn, c);
-  int pc[D];
-  for (int j = 0; j < D; ++j) { pc[j] = c[j] >> 1; o |= (c[j] & 1) << j; }
-  const int64_t C = index_of<D>(pc, lgn - 1);
-  const T* xv = xc + C * NB + f * NQ;
-  T s = 0;
-  for (int ac = 0; ac < NQ; ++ac) s += pfull_lds<T, D, M>(Pt, o, af, ac) * xv[ac];
-  x[t] += s;
+  int cc[D];
+  coords_of<D>(C, lgn - 1, cc);
+  for (int t = threadIdx.x; t < NCH * NB; t += 256) {
+    const int o = t / NB, q = t - o * NB;
+    const int f = q / NQ, af = q - f * NQ;
+    T fac[D][M];
+    int cf[D];
+    int fa = af;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const int bit = (o >> k) & 1, fk = fa % M;
+      fa /= M;
+      cf[k] = 2 * cc[k] + bit;
+#pragma unroll
+      for (int m = 0; m < M; ++m) fac[k][m] = Pt[bit * MAXM * MAXM + fk * M + m];
+    }
+    x[(size_t)index_of<D>(cf, lgn) * NB + q] += tensor_row<T, D, M>(fac, &xs[f * NQ]);
+  }
 }
+
 
 // y = z + sign * M x with M row-major FP64 (N x N), one wavefront per row;
 // z may be null.  Used by the bottom solve (pseudo-inverse and refinement).
@@ -2073,9 +2137,8 @@ int launch_residual_restrict(const LaunchCfg& c, const DevLevel<T>& lev, const T
     if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) {
           constexpr int D_ = decltype(Dc)::value;
           constexpr int P_ = decltype(Pc)::value;
-          const int64_t total = NC * Sz<D_, P_>::NB;
-          hipLaunchKernelGGL((k_restrict<T, D_, P_>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, lev.lgn,
-                             tt, (const T*)rfine, rc, total);
+          hipLaunchKernelGGL((k_restrict_elem<T, D_, P_>), dim3((unsigned)NC), dim3(128), 0, st, lev.lgn, tt,
+                             (const T*)rfine, rc);
         }))
       return 2;
     return hip_ok();
@@ -2095,8 +2158,12 @@ int launch_prolong_add(const LaunchCfg& c, int n_fine, const Tab1D& tab, const T
   int64_t total = NE * nb;
   hipStream_t st = (hipStream_t)c.stream;
   const TabT<T> tt = tab_of<T>(tab);
-  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_prolong_add<T, D_, P_>), dim3(grid1(total, 256)), dim3(256), 0, st,
-                                                n_fine, tt, xc, x, total); })) return 2;
+  (void)total;
+  int lgf = 0;
+  while ((1 << lgf) < n_fine) ++lgf;
+  const unsigned ncoarse = (unsigned)(NE >> c.dim);
+  if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; hipLaunchKernelGGL((k_prolong_elem<T, D_, P_>), dim3(ncoarse), dim3(256), 0, st,
+                                                lgf, tt, xc, x); })) return 2;
   return hip_ok();
 }
 
