@@ -74,19 +74,26 @@ def coarsen(ops, prob, unsteady: bool):
     fine = ops["grid"]
     coarse = Grid(fine.d, fine.n // 2, fine.p, fine.bc, prob.phases, h=2.0 * fine.h)
     I = prolongation(fine, coarse, prob.q_op)
+    out = coarsen_components(ops, I, fine.nq, unsteady)
+    out.update(n=coarse.n, h=coarse.h, grid=coarse)
+    return out
+
+
+def coarsen_components(ops, I, nq, unsteady: bool):
+    """Algorithm 2 / 3 for a given scalar injection I (any nested mesh pair)."""
     It = I.T.tocsr()
     M = ops["M"]
-    M2 = (It @ M @ I).tocsr()                                   # line 1
-    Mmu2 = (It @ ops["Mmu"] @ I).tocsr()                        # line 2
-    M2inv = block_inverse_diag(M2, fine.nq)
-    G2 = [(M2inv @ It @ M @ Gk @ I).tocsr() for Gk in ops["G"]]  # G_2h line
+    M2 = (It @ M @ I).tocsr()                                   # M_2h
+    Mmu2 = (It @ ops["Mmu"] @ I).tocsr()                        # M_mu,2h
+    M2inv = block_inverse_diag(M2, nq)
+    G2 = [(M2inv @ It @ M @ Gk @ I).tocsr() for Gk in ops["G"]]  # G_2h
     Et2 = (0.5 * (It @ ops["Et"] @ I)).tocsr()                  # velocity penalty, factor 1/2
-    out = dict(n=coarse.n, h=coarse.h, grid=coarse, M=M2, Mmu=Mmu2, G=G2, Et=Et2, I=I)
+    out = dict(M=M2, Mmu=Mmu2, G=G2, Et=Et2, I=I)
     if unsteady:
         out["Mrho"] = (It @ ops["Mrho"] @ I).tocsr()            # M_rho,2h
         out["Emu"] = (2.0 * (It @ ops["Emu"] @ I)).tocsr()      # factor 2
         out["Erho"] = (0.5 * (It @ ops["Erho"] @ I)).tocsr()    # factor 1/2
-        out["E"] = frobenius_blend(out["Emu"], out["Erho"], fine.nq)
+        out["E"] = frobenius_blend(out["Emu"], out["Erho"], nq)
     else:
         out["E"] = (2.0 * (It @ ops["E"] @ I)).tocsr()          # pressure penalty, factor 2
     return out

@@ -404,3 +404,89 @@ class FourierForcing:
 
     def forcing_div(self, x, chi=None):
         return np.zeros(x.shape[0])
+
+
+# ---------------------------------------------------------------------------
+# Circular interface (implicitly defined meshes)
+# ---------------------------------------------------------------------------
+@dataclass
+class CirclePhaseField:
+    """Two phases separated by a circle: phase 1 the open disk |x - c| < r,
+    phase 2 the rest of the unit square.  The level set is the signed
+    distance phi(x) = |x - c| - r (negative in phase 1), its gradient the unit
+    normal pointing from phase 1 into phase 2, its curvature 1 / r.
+    ``values[chi-1]`` is the field's value in phase chi."""
+    values: tuple = (1.0e4, 1.0)
+    centre: tuple = (0.5, 0.5)
+    radius: float = 0.3
+    kind: str = "circle"
+
+    def levelset(self, x):
+        x = np.atleast_2d(x)
+        return np.sqrt(((x - np.asarray(self.centre)[None, :]) ** 2).sum(axis=1)) - self.radius
+
+    def levelset_grad(self, x):
+        x = np.atleast_2d(x)
+        v = x - np.asarray(self.centre)[None, :]
+        return v / np.sqrt((v ** 2).sum(axis=1))[:, None]
+
+    def curvature(self):
+        return 1.0 / self.radius
+
+    def box_range(self, lo, hi):
+        """Exact minimum and maximum of phi over the box [lo, hi]."""
+        c = np.asarray(self.centre, dtype=float)
+        lo, hi = np.asarray(lo, dtype=float), np.asarray(hi, dtype=float)
+        near = np.clip(c, lo, hi)
+        far = np.where(np.abs(lo - c) > np.abs(hi - c), lo, hi)
+        return (float(np.sqrt(((near - c) ** 2).sum())) - self.radius,
+                float(np.sqrt(((far - c) ** 2).sum())) - self.radius)
+
+    def phase(self, x):
+        return np.where(self.levelset(x) < 0.0, 1, 2)
+
+    def value(self, x, chi=None):
+        if chi is None:
+            chi = self.phase(x)
+        vals = np.asarray(self.values, dtype=float)
+        return vals[np.asarray(chi) - 1]
+
+    def grad(self, x, chi=None):
+        return np.zeros_like(np.atleast_2d(x), dtype=float)
+
+    def params(self):
+        return np.array([self.values[0], self.values[1], self.centre[0], self.centre[1],
+                         self.radius], dtype=float)
+
+
+@dataclass
+class BubbleForcing:
+    """A static bubble: gravity rho_chi g (g = (0, -1)) in each phase, no-slip
+    walls, no velocity jump across the interface, and the stress jump of
+    surface tension: with jumps taken phase 1 (the bubble) minus phase 2, as
+    in the interface conditions of eq. (govern2), n the unit normal from
+    phase 1 into phase 2 and kappa = 1 / r, [sigma n] = -sigma_st kappa n, so
+    that at rest (sigma = -p I) phase 1's pressure exceeds phase 2's by
+    sigma_st kappa (the Young-Laplace balance)."""
+    rho: tuple = (1.0, 1.0e-3)
+    sigma_st: float = 1.0
+    kappa: float = 1.0 / 0.3
+    dim: int = 2
+
+    def forcing(self, x, chi=None):
+        x = np.atleast_2d(x)
+        chi = np.ones(x.shape[0], dtype=int) if chi is None else np.asarray(chi)
+        out = np.zeros((x.shape[0], self.dim))
+        out[:, self.dim - 1] = -np.asarray(self.rho, dtype=float)[chi - 1]
+        return out
+
+    def forcing_div(self, x, chi=None):
+        return np.zeros(np.atleast_2d(x).shape[0])
+
+    def velocity(self, x, chi=None):
+        return np.zeros((np.atleast_2d(x).shape[0], self.dim))
+
+    def interface_jumps(self, x, normal):
+        """(g, h) = ([u], [sigma n]) at points x with unit normals ``normal``."""
+        g = np.zeros_like(np.atleast_2d(x), dtype=float)
+        return g, -self.sigma_st * self.kappa * np.atleast_2d(normal)

@@ -12,7 +12,8 @@ from dataclasses import dataclass, field
 from typing import Optional
 
 from .fields import (ConstField, SinProductField, PhaseField, LogNormalRFF,
-                     FourierForcing, make_exact_c1, make_exact_paper)
+                     FourierForcing, CirclePhaseField, BubbleForcing,
+                     make_exact_c1, make_exact_paper)
 
 # Table 1 of the paper: optimal tau by (form, d), indexed by p-1.
 TAU_OPTIMAL = {
@@ -44,6 +45,8 @@ class Problem:
     tau0: Optional[float] = None
     tau_u_bdry_C: float = 10.0
     tau_u_inter_C: float = 3.0
+    tau_u_intra_C: float = 0.0      # tau_u,0 = C p mu / h on intraphase faces
+    q_cut: int = 8                  # Gauss points per piece in cut-cell quadrature
     nu1: int = 3
     nu2: int = 3
     coarsest_n: Optional[int] = None
@@ -63,6 +66,11 @@ class Problem:
             self.coarsest_n = 4 if self.dim == 2 else 2
         if self.coloring == "auto":
             self.coloring = default_coloring(self)
+
+    @property
+    def implicit(self) -> bool:
+        """True on an implicitly defined mesh (a curved interface cuts cells)."""
+        return getattr(self.phases, "kind", None) == "circle"
 
     @property
     def nb(self) -> int:
@@ -193,3 +201,24 @@ def stress_walls(dim=2, n=16, p=2, mu=None):
     mu = mu or ConstField(1.0)
     return Problem(name=f"stress_d{dim}_n{n}_p{p}", dim=dim, n=n, p=p, gamma=1, bc=("stress",) * dim, mu=mu,
                    coloring="parity", exact=make_exact_paper(dim, 1, mu))
+
+
+def c4_circle(n=512, p=2, mu_in=1.0e4, mu_out=1.0, rhs="bubble", radius=0.3, q_cut=8):
+    """2D two-phase viscous-stress Stokes on an implicitly defined mesh: a
+    circle of radius 0.3 centred in the unit square cuts the n x n grid,
+    viscosity mu_in inside / mu_out outside, Dirichlet walls; cut pieces below
+    a quarter of a cell merged into neighbours; interphase penalty C = 8 and
+    intraphase 0.5 p mu / h (appendix A for implicitly defined meshes);
+    (alpha, beta) scaling.  rhs "bubble": gravity with densities 1 / 1e-3 and
+    the unit surface-tension stress jump (no exact solution); rhs "exact":
+    the paper's two-phase manufactured solution, its jumps as interface data."""
+    ph = CirclePhaseField(values=(mu_in, mu_out), radius=radius)
+    exact = forcing = None
+    if rhs == "exact":
+        exact = make_exact_paper(2, 1, ph, phases=(1, 2), mu_chi={1: mu_in, 2: mu_out})
+    else:
+        forcing = BubbleForcing(kappa=1.0 / radius)
+    return Problem(name=f"c4_circle_n{n}_p{p}_{rhs}", dim=2, n=n, p=p, gamma=1,
+                   bc=("dirichlet", "dirichlet"), mu=ph, phases=ph, coloring="greedy",
+                   tau_u_inter_C=8.0, tau_u_intra_C=0.5, q_cut=q_cut, diag_scaling=True,
+                   exact=exact, forcing=forcing)
