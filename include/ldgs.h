@@ -93,9 +93,18 @@ typedef enum {
 
 /* Level set describing the phases.  NONE: one phase.  BOX: phase 1 is the
  * open box (params[0], params[1])^d, phase 2 its complement; box faces must
- * lie on element faces of the coarsest grid.  Curved interfaces return
- * LDGS_E_UNSUPPORTED. */
-typedef enum { LDGS_LEVELSET_NONE = 0, LDGS_LEVELSET_BOX = 1 } ldgs_levelset_kind;
+ * lie on element faces of the coarsest grid.  CIRCLE (2D, steady, Dirichlet
+ * walls): phase 1 is the disk |x - levelset_centre| < params[0], phase 2 the
+ * rest of the square; the circle cuts the grid's cells and the mesh is an
+ * implicitly defined one (section 5, "Curved domain geometry"): cut cells
+ * carry quadrature of their own (q_cut Gauss points per piece), pieces below
+ * a quarter of a cell are merged into a neighbour of their phase, the
+ * interphase penalty prefactor defaults to 8 and the intraphase one is
+ * tau_u_intra_C (appendix A), coarse levels agglomerate same-phase elements
+ * (section 3, "Mesh hierarchy") and every level is held as explicit element
+ * blocks, smoothed in greedy colour order.  Only the FP64 and FP32 V-cycles
+ * are built; the learned correction and the GMRES rate are not available. */
+typedef enum { LDGS_LEVELSET_NONE = 0, LDGS_LEVELSET_BOX = 1, LDGS_LEVELSET_CIRCLE = 2 } ldgs_levelset_kind;
 
 /* Batched host callback: evaluate at n points x (n x d, row-major).  phase[i]
  * is the phase (1 or 2) of the element owning point i; normal (n x d) is the
@@ -129,7 +138,8 @@ typedef struct {
   double tau;               /* pressure penalty prefactor of eq. (taueqn); <= 0: Table 1 */
   double tau0;              /* unsteady prefactor of eq. (taugeneral); <= 0: 0.5 p */
   double tau_u_bdry_C;      /* tau_u,boundary = C p mu^- / h; <= 0: 10 */
-  double tau_u_inter_C;     /* tau_u,interphase = C p min(mu) / h; <= 0: 3 */
+  double tau_u_inter_C;     /* tau_u,interphase = C p min(mu) / h; <= 0: 3 (8 on
+                               implicitly defined meshes) */
   int nu1, nu2;             /* pre-/post-smoothing sweeps; <= 0: 3 */
   int coarsest_n;           /* bottom grid size; <= 0: 4 (2D), 2 (3D) */
   int coloring;             /* ldgs_coloring */
@@ -159,6 +169,11 @@ typedef struct {
   void* (*dev_alloc)(size_t bytes, void* alloc_user);
   void (*dev_free)(void* ptr, void* alloc_user);
   void* alloc_user;
+  double levelset_centre[3];  /* LDGS_LEVELSET_CIRCLE: centre of the circle */
+  double tau_u_intra_C;       /* tau_u,0 = C p mu / h on intraphase faces of implicitly
+                                 defined meshes (appendix A gives 0.5 for them); Cartesian
+                                 grids use 0 */
+  int q_cut;                  /* Gauss points per piece in cut-cell quadrature; <= 0: 8 */
 } ldgs_problem;
 
 /* Data of the right-hand side, eq. (govern1)-(govern3).  Each callback may be
@@ -347,12 +362,21 @@ ldgs_status ldgs_learned_train_noalloc(const ldgs_train_args* args, float* param
 ldgs_status ldgs_project_kernel(ldgs_ctx* ctx, double* v_dev);
 
 /* ---- Stage entry points (one step of the hot path on one level) --------
- * Level 0 is the finest.  Level vectors have n_l^d (d+1)(p+1)^d FP64 entries
- * in the layout above.  They operate on the operator of that level as used by
- * the V-cycle (diagonally scaled when diag_scaling is on) in FP64. */
+ * Level 0 is the finest.  Level vectors have NE_l (d+1)(p+1)^d FP64 entries
+ * in the layout above, NE_l = n_l^d on Cartesian grids and the element count
+ * of ldgs_level_elements on implicitly defined meshes.  They operate on the
+ * operator of that level as used by the V-cycle (diagonally scaled when
+ * diag_scaling is on) in FP64. */
 
-/* Grid size n_l, number of levels and colours. */
+/* Grid size n_l (background cells per axis), number of levels and colours. */
 ldgs_status ldgs_level_info(const ldgs_ctx* ctx, int level, int* n_l, int* n_levels, int* n_colours);
+
+/* Number of elements NE_l of level `level` (n_l^d on Cartesian grids; on an
+ * implicitly defined mesh the cut, merged and agglomerated elements of
+ * section 3, "Mesh hierarchy", numbered by (host cell, phase)).  Works on
+ * host-only contexts.  Errors: LDGS_E_ARG for a null pointer or a level out
+ * of range. */
+ldgs_status ldgs_level_elements(const ldgs_ctx* ctx, int level, int64_t* ne);
 
 /* *shared = 1 when every diagonal block of level `level` is the same matrix
  * (constant viscosity and density, a periodic grid, no interphase faces: the

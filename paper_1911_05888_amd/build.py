@@ -17,8 +17,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libldgs.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HOST_SRCS = ["setup.cpp", "build.cpp", "eigen.cpp", "rhs.cpp", "api.cpp"]
-HIP_SRCS = ["kernels.hip", "learned.hip", "setup_dev.hip"]
+HOST_SRCS = ["setup.cpp", "build.cpp", "eigen.cpp", "rhs.cpp", "implicit.cpp", "api.cpp"]
+HIP_SRCS = ["kernels.hip", "learned.hip", "setup_dev.hip", "implicit.hip"]
 
 HIPCC_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
                # no packed-FP32 instructions in generated code

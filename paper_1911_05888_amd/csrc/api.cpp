@@ -16,6 +16,7 @@
 
 #include "build.hpp"
 #include "host.hpp"
+#include "implicit.hpp"
 #include "learned_internal.hpp"
 
 namespace ldgs {
@@ -165,7 +166,25 @@ struct ldgs_ctx {
     if (stream_owned && stream) (void)hipStreamDestroy(stream);
   }
   bool stream_owned = false;
-  int64_t ndof() const { return levels.empty() ? 0 : levels[0].NE * g.nb; }
+  // implicitly defined mesh (circle level set): explicit element blocks on
+  // every level, host data in imp, device arrays per level in idev
+  std::unique_ptr<ImpHier> imp;
+  struct ImpDev {
+    int64_t NE = 0;
+    int *rowptr = nullptr, *cols = nullptr, *parent = nullptr, *kid_ptr = nullptr, *kids = nullptr;
+    std::vector<int*> elems;
+    std::vector<int64_t> ncnt;
+    double *blk64 = nullptr, *inv64 = nullptr, *I64 = nullptr, *b64 = nullptr, *x64 = nullptr, *r64 = nullptr;
+    float *blk32 = nullptr, *inv32 = nullptr, *I32 = nullptr, *b32 = nullptr, *x32 = nullptr, *r32 = nullptr;
+  };
+  std::vector<ImpDev> idev;
+  double* d_kernel = nullptr;       // fine kernel vector (unit norm)
+  double* d_dinv0 = nullptr;        // fine per-element 1 / (alpha, beta)
+  bool imp64 = false, imp32 = false;
+  int64_t ndof() const {
+    if (imp) return imp->lv.empty() ? 0 : imp->lv[0].NE * imp->nb;
+    return levels.empty() ? 0 : levels[0].NE * g.nb;
+  }
 };
 
 namespace {
@@ -252,7 +271,8 @@ void fill_defaults(ldgs_problem& P) {
   if (!(P.tau > 0)) P.tau = (P.form ? tab_vs : tab_std)[P.dim - 2][P.degree - 1];
   if (!(P.tau0 > 0)) P.tau0 = 0.5 * P.degree;
   if (!(P.tau_u_bdry_C > 0)) P.tau_u_bdry_C = 10.0;
-  if (!(P.tau_u_inter_C > 0)) P.tau_u_inter_C = 3.0;
+  if (!(P.tau_u_inter_C > 0)) P.tau_u_inter_C = P.levelset_kind == LDGS_LEVELSET_CIRCLE ? 8.0 : 3.0;
+  if (P.q_cut <= 0) P.q_cut = 8;
   if (P.nu1 <= 0) P.nu1 = 3;
   if (P.nu2 <= 0) P.nu2 = 3;
   if (P.coarsest_n <= 0) P.coarsest_n = (P.dim == 2) ? 4 : 2;
@@ -275,8 +295,15 @@ void validate(const ldgs_problem& P) {
   }
   if (nstress != 0 && nstress != P.dim)
     throw Fail{LDGS_E_UNSUPPORTED, "stress boundary conditions must be given on every axis"};
-  if (P.levelset_kind != LDGS_LEVELSET_NONE) {
-    if (P.levelset_kind != LDGS_LEVELSET_BOX) throw Fail{LDGS_E_UNSUPPORTED, "curved level sets"};
+  if (P.levelset_kind == LDGS_LEVELSET_CIRCLE) {
+    if (P.dim != 2 || P.delta > 0.0 || P.bc[0] != LDGS_DIRICHLET || P.bc[1] != LDGS_DIRICHLET)
+      throw Fail{LDGS_E_UNSUPPORTED, "circle level sets: 2D steady problems with Dirichlet walls"};
+    if (!(P.levelset_params[0] > 0.0)) throw Fail{LDGS_E_ARG, "circle radius must be positive"};
+    if (P.vprec == LDGS_V_FP32_BF16BLK || (P.build_precisions & 4))
+      throw Fail{LDGS_E_UNSUPPORTED, "BF16-stored blocks are not built on implicitly defined meshes"};
+    if (P.q_cut > 32) throw Fail{LDGS_E_ARG, "q_cut"};
+  } else if (P.levelset_kind != LDGS_LEVELSET_NONE) {
+    if (P.levelset_kind != LDGS_LEVELSET_BOX) throw Fail{LDGS_E_ARG, "levelset_kind"};
     if (!P.host_only && P.dim != 2) throw Fail{LDGS_E_UNSUPPORTED, "interphase faces are supported in 2D"};
   }
   if (P.delta > 0.0) {
@@ -913,6 +940,140 @@ void bottom_solve(ldgs_ctx* c, const T* b, T* x) {
   LCHK((launch_dense_mv<double, T>(c->stream, N, c->d_pinv, c->d_bt2, c->d_bt1, 1.0, x)));
 }
 
+// ---------------------------------------------------------------------------
+// implicitly defined meshes: device data and the V-cycle on explicit blocks
+
+int* upload_int(ldgs_ctx* c, const std::vector<int>& v) {
+  int* d = dalloc<int>(c, v.size());
+  if (!v.empty()) HIPCHK(hipMemcpy(d, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice));
+  return d;
+}
+
+void imp_device(ldgs_ctx* c) {
+  const ImpHier& H = *c->imp;
+  const int mask = (1 << c->P.vprec) | c->P.build_precisions;
+  c->imp64 = mask & 1;
+  c->imp32 = (mask & 2) != 0;
+  const size_t nl = H.lv.size();
+  c->idev.assign(nl, ldgs_ctx::ImpDev{});
+  for (size_t l = 0; l < nl; ++l) {
+    const ImpLevel& L = H.lv[l];
+    ldgs_ctx::ImpDev& D = c->idev[l];
+    D.NE = L.NE;
+    const int64_t N = L.NE * H.nb;
+    D.rowptr = upload_int(c, L.rowptr);
+    D.cols = upload_int(c, L.cols);
+    // the FP64 finest operator always (outer residual and products)
+    if (c->imp64 || l == 0) D.blk64 = upload<double>(c, L.blk);
+    if (c->imp32) D.blk32 = upload<float>(c, L.blk);
+    if (l + 1 < nl) {
+      if (c->imp64) D.inv64 = upload<double>(c, L.inv);
+      if (c->imp32) D.inv32 = upload<float>(c, L.inv);
+      D.parent = upload_int(c, L.parent);
+      if (c->imp64) D.I64 = upload<double>(c, L.Iblk);
+      if (c->imp32) D.I32 = upload<float>(c, L.Iblk);
+      for (const auto& e : L.elems) {
+        D.elems.push_back(upload_int(c, e));
+        D.ncnt.push_back((int64_t)e.size());
+      }
+    }
+    if (l > 0) {
+      D.kid_ptr = upload_int(c, L.kid_ptr);
+      D.kids = upload_int(c, L.kids);
+      if (c->imp64) {
+        D.b64 = dalloc<double>(c, N);
+        D.x64 = dalloc<double>(c, N);
+      }
+      if (c->imp32) {
+        D.b32 = dalloc<float>(c, N);
+        D.x32 = dalloc<float>(c, N);
+      }
+    }
+    if (l + 1 < nl) {
+      if (c->imp64) D.r64 = dalloc<double>(c, N);
+      if (c->imp32) D.r32 = dalloc<float>(c, N);
+    }
+  }
+  c->d_pinv = upload<double>(c, H.pinv);
+  c->d_Ac = upload<double>(c, H.Ac);
+  c->d_bt0 = dalloc<double>(c, c->Nc);
+  c->d_bt1 = dalloc<double>(c, c->Nc);
+  c->d_bt2 = dalloc<double>(c, c->Nc);
+  const int64_t N = c->ndof();
+  c->w_b = dalloc<double>(c, N);
+  c->w_x = dalloc<double>(c, N);
+  c->w_r = dalloc<double>(c, N);
+  c->w_z = dalloc<double>(c, N);
+  c->w_part = dalloc<double>(c, 1024);
+  if (c->imp32) {
+    c->w_b32 = dalloc<float>(c, N);
+    c->w_x32 = dalloc<float>(c, N);
+  }
+  c->d_kernel = upload<double>(c, H.kernel);
+  if (c->P.diag_scaling) {
+    const std::vector<double>& ds = H.lv[0].dscale;
+    std::vector<double> inv(ds.size());
+    for (size_t i = 0; i < ds.size(); ++i) inv[i] = 1.0 / ds[i];
+    c->d_dscale0 = upload<double>(c, ds);
+    c->d_dinv0 = upload<double>(c, inv);
+  }
+  c->s64.built = c->imp64;
+  c->s32.built = c->imp32;
+  HIPCHK(hipDeviceSynchronize());
+}
+
+template <typename T>
+struct ImpArrays;
+template <>
+struct ImpArrays<double> {
+  static const double* blk(const ldgs_ctx::ImpDev& D) { return D.blk64; }
+  static const double* inv(const ldgs_ctx::ImpDev& D) { return D.inv64; }
+  static const double* I(const ldgs_ctx::ImpDev& D) { return D.I64; }
+  static double* b(ldgs_ctx::ImpDev& D) { return D.b64; }
+  static double* x(ldgs_ctx::ImpDev& D) { return D.x64; }
+  static double* r(ldgs_ctx::ImpDev& D) { return D.r64; }
+};
+template <>
+struct ImpArrays<float> {
+  static const float* blk(const ldgs_ctx::ImpDev& D) { return D.blk32; }
+  static const float* inv(const ldgs_ctx::ImpDev& D) { return D.inv32; }
+  static const float* I(const ldgs_ctx::ImpDev& D) { return D.I32; }
+  static float* b(ldgs_ctx::ImpDev& D) { return D.b32; }
+  static float* x(ldgs_ctx::ImpDev& D) { return D.x32; }
+  static float* r(ldgs_ctx::ImpDev& D) { return D.r32; }
+};
+
+template <typename T>
+void imp_colour(ldgs_ctx* c, int l, int col, const T* b, T* x) {
+  using A = ImpArrays<T>;
+  ldgs_ctx::ImpDev& D = c->idev[l];
+  LCHK(launch_bsr_colour<T>(c->stream, c->imp->nb, D.ncnt[col], D.elems[col], D.rowptr, D.cols, A::blk(D),
+                            A::inv(D), b, x));
+}
+
+template <typename T>
+void imp_cycle(ldgs_ctx* c, int l, const T* b, T* x, bool zero_x) {
+  using A = ImpArrays<T>;
+  const int bottom = (int)c->idev.size() - 1;
+  if (l == bottom) {
+    bottom_solve(c, b, x);
+    return;
+  }
+  ldgs_ctx::ImpDev& D = c->idev[l];
+  ldgs_ctx::ImpDev& C = c->idev[l + 1];
+  const int nb = c->imp->nb;
+  const int ncol = (int)D.elems.size();
+  if (zero_x) LCHK(launch_fill<T>(c->stream, D.NE * nb, (T)0, x));
+  for (int s = 0; s < c->P.nu1; ++s)
+    for (int col = 0; col < ncol; ++col) imp_colour<T>(c, l, col, b, x);
+  LCHK(launch_bsr_residual<T>(c->stream, nb, D.NE, D.rowptr, D.cols, A::blk(D), b, x, A::r(D), nullptr));
+  LCHK(launch_bsr_restrict<T>(c->stream, nb, C.NE, C.kid_ptr, C.kids, A::I(D), A::r(D), A::b(C)));
+  imp_cycle<T>(c, l + 1, A::b(C), A::x(C), true);
+  LCHK(launch_bsr_prolong<T>(c->stream, nb, D.NE, D.parent, A::I(D), A::x(C), x));
+  for (int s = 0; s < c->P.nu2; ++s)
+    for (int col = 0; col < ncol; ++col) imp_colour<T>(c, l, col, b, x);
+}
+
 // V-cycle on level l; zero_x: x is taken as zero on entry (the coarse levels'
 // corrections, and the finest level inside the outer iterations)
 template <typename T>
@@ -986,9 +1147,29 @@ const double* dscale0(ldgs_ctx* c) { return c->P.diag_scaling ? c->d_dscale0 : n
 // If zero_x, x is taken as zero on entry (and overwritten).
 // add: x += V(b, 0) instead (with zero_x)
 void vcycle_user(ldgs_ctx* c, int vp, const double* b, double* x, bool zero_x, bool add = false) {
+  const double* ds = dscale0(c);
+  if (c->imp) {
+    const int64_t NE = c->imp->lv[0].NE;
+    const int nb = c->imp->nb, nvel = 2 * c->imp->nq;
+    if (vp == LDGS_V_FP64) {
+      if (!c->imp64) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
+      LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, b, c->w_b, 0, 0)));
+      if (!zero_x) LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, x, c->w_x, 1, 0)));
+      imp_cycle<double>(c, 0, c->w_b, c->w_x, zero_x);
+      LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, c->w_x, x, 0, add ? 1 : 0)));
+    } else if (vp == LDGS_V_FP32) {
+      if (!c->imp32) throw Fail{LDGS_E_UNSUPPORTED, "FP32 V-cycle not built"};
+      LCHK((launch_scale_cast<double, float>(c->stream, NE, nb, nvel, ds, b, c->w_b32, 0, 0)));
+      if (!zero_x) LCHK((launch_scale_cast<double, float>(c->stream, NE, nb, nvel, ds, x, c->w_x32, 1, 0)));
+      imp_cycle<float>(c, 0, c->w_b32, c->w_x32, zero_x);
+      LCHK((launch_scale_cast<float, double>(c->stream, NE, nb, nvel, ds, c->w_x32, x, 0, add ? 1 : 0)));
+    } else {
+      throw Fail{LDGS_E_UNSUPPORTED, "BF16-stored blocks are not built on implicitly defined meshes"};
+    }
+    return;
+  }
   const int64_t NE = c->levels[0].NE;
   const int nb = c->g.nb, nvel = c->g.d * c->g.nq;
-  const double* ds = dscale0(c);
   if (vp == LDGS_V_FP64) {
     if (!c->s64.built) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
     LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, b, c->w_b, 0, 0)));
@@ -1026,11 +1207,36 @@ double dot(ldgs_ctx* c, const double* x, const double* y) {
 }
 
 void residual_fine(ldgs_ctx* c, const double* b, const double* x, double* r) {
+  if (c->imp) {
+    const ldgs_ctx::ImpDev& D = c->idev[0];
+    LCHK(launch_bsr_residual<double>(c->stream, c->imp->nb, D.NE, D.rowptr, D.cols, D.blk64, b, x, r, c->d_dinv0));
+    return;
+  }
   LaunchCfg cfg{c->g.d, c->g.p, c->stream, c->small_grid};
   LCHK(launch_residual<double>(cfg, c->s64.lv[0].unscaled, c->tab, b, x, r, 0));
 }
 
+// y = A x with the unscaled finest operator
+void apply_fine(ldgs_ctx* c, const double* x, double* y) {
+  if (c->imp) {
+    const ldgs_ctx::ImpDev& D = c->idev[0];
+    LCHK(launch_bsr_residual<double>(c->stream, c->imp->nb, D.NE, D.rowptr, D.cols, D.blk64, nullptr, x, y,
+                                     c->d_dinv0));
+    return;
+  }
+  LaunchCfg cfg{c->g.d, c->g.p, c->stream, c->small_grid};
+  LCHK(launch_residual<double>(cfg, c->s64.lv[0].unscaled, c->tab, nullptr, x, y, 1));
+}
+
 void project_kernel(ldgs_ctx* c, double* v) {
+  if (c->imp) {
+    // the constant pressure: v -= K (K^T v), K of unit norm
+    const int nblk = 512;
+    LCHK(launch_dot_partial(c->stream, c->ndof(), c->d_kernel, v, c->w_part, nblk));
+    const double w = host_sum_partials(c, nblk);
+    LCHK(launch_axpy(c->stream, c->ndof(), -w, c->d_kernel, v));
+    return;
+  }
   const Level& L = c->levels[0];
   const int64_t NE = L.NE;
   const int nblk = 256;
@@ -1331,6 +1537,35 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
       std::fprintf(stderr, "[ldgs setup] %-28s %8.3f s\n", what, std::chrono::duration<double>(now - tmark).count());
       tmark = now;
     };
+    if (P.levelset_kind == LDGS_LEVELSET_CIRCLE) {
+      // implicitly defined mesh: explicit element blocks on every level
+      c->k0 = 1;
+      c->imp.reset(new ImpHier());
+      try {
+        imp_build(P, *c->imp);
+      } catch (const std::runtime_error& ex) {
+        throw Fail{LDGS_E_ARG, ex.what()};
+      }
+      phase("implicit hierarchy");
+      c->Nc = c->imp->Nc;
+      c->h_pinv = c->imp->pinv;
+      c->h_eig = c->imp->eig;
+      if (!c->host_only) {
+        if (P.hip_stream) {
+          c->stream = (hipStream_t)P.hip_stream;
+        } else {
+          HIPCHK(hipStreamCreate(&c->stream));
+          c->stream_owned = true;
+          HIPCHK(hipEventCreateWithFlags(&c->join_in, hipEventDisableTiming));
+          HIPCHK(hipEventCreateWithFlags(&c->join_out, hipEventDisableTiming));
+        }
+        imp_device(c.get());
+        phase("implicit upload");
+      }
+      g_setup_error.clear();
+      *out = c.release();
+      return LDGS_OK;
+    }
     c->k0 = kernel_dim(P);
     if (stress_walls(P)) {
       // constant velocity components; the rotations are projected separately
@@ -1443,6 +1678,13 @@ ldgs_status ldgs_num_dofs(const ldgs_ctx* ctx, int64_t* ndof) {
 }
 
 ldgs_status ldgs_level_info(const ldgs_ctx* ctx, int level, int* n_l, int* n_levels, int* n_colours) {
+  if (ctx && ctx->imp) {
+    if (level < 0 || level >= (int)ctx->imp->lv.size()) return LDGS_E_ARG;
+    if (n_l) *n_l = ctx->imp->lv[level].n;
+    if (n_levels) *n_levels = (int)ctx->imp->lv.size();
+    if (n_colours) *n_colours = ctx->imp->lv[level].ncol;
+    return LDGS_OK;
+  }
   if (!ctx || level < 0 || level >= (int)ctx->levels.size()) return LDGS_E_ARG;
   if (n_l) *n_l = ctx->levels[level].n;
   if (n_levels) *n_levels = (int)ctx->levels.size();
@@ -1451,6 +1693,11 @@ ldgs_status ldgs_level_info(const ldgs_ctx* ctx, int level, int* n_l, int* n_lev
 }
 
 ldgs_status ldgs_level_shared_inverse(const ldgs_ctx* ctx, int level, int* shared) {
+  if (ctx && ctx->imp && shared) {
+    if (level < 0 || level >= (int)ctx->imp->lv.size()) return LDGS_E_ARG;
+    *shared = 0;
+    return LDGS_OK;
+  }
   if (!ctx || !shared || level < 0 || level >= (int)ctx->levels.size()) return LDGS_E_ARG;
   *shared = ctx->levels[level].uniform ? 1 : 0;
   return LDGS_OK;
@@ -1461,7 +1708,8 @@ ldgs_status ldgs_assemble_rhs(ldgs_ctx* ctx, const ldgs_rhs_data* data, double* 
     check_ctx(ctx, false);
     if (!data || !b) throw Fail{LDGS_E_ARG, "null argument"};
     std::vector<double> hb(ctx->ndof());
-    assemble_rhs_host(ctx->P, ctx->g, ctx->B, ctx->levels[0], *data, hb.data());
+    if (ctx->imp) imp_rhs(ctx->P, *ctx->imp, *data, hb.data());
+    else assemble_rhs_host(ctx->P, ctx->g, ctx->B, ctx->levels[0], *data, hb.data());
     if (ctx->host_only) std::memcpy(b, hb.data(), hb.size() * sizeof(double));
     else HIPCHK(hipMemcpy(b, hb.data(), hb.size() * sizeof(double), hipMemcpyHostToDevice));
     return LDGS_OK;
@@ -1475,8 +1723,7 @@ ldgs_status ldgs_apply(ldgs_ctx* ctx, const double* x, double* y) {
     check_ctx(ctx, true);
     Join join_(ctx);
     if (!x || !y || x == y) throw Fail{LDGS_E_ARG, "x, y must be distinct non-null"};
-    LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream, ctx->small_grid};
-    LCHK(launch_residual<double>(cfg, ctx->s64.lv[0].unscaled, ctx->tab, nullptr, x, y, 1));
+    apply_fine(ctx, x, y);
     return LDGS_OK;
   } catch (const Fail& f) {
     return handle(ctx, f);
@@ -1529,6 +1776,7 @@ ldgs_status ldgs_set_vprec(ldgs_ctx* ctx, int vprec) {
 ldgs_status ldgs_set_learned(ldgs_ctx* ctx, const ldgs_net* net) {
   try {
     check_ctx(ctx, true);
+    if (ctx->imp) throw Fail{LDGS_E_UNSUPPORTED, "no learned correction on implicitly defined meshes"};
     Join join_(ctx);
     if (!net) {
       ctx->net_loaded = false;
@@ -1565,6 +1813,7 @@ ldgs_status ldgs_set_learned(ldgs_ctx* ctx, const ldgs_net* net) {
 ldgs_status ldgs_learned_correction(ldgs_ctx* ctx, const double* r, double* dx) {
   try {
     check_ctx(ctx, true);
+    if (ctx->imp) throw Fail{LDGS_E_UNSUPPORTED, "no learned correction on implicitly defined meshes"};
     Join join_(ctx);
     if (!r || !dx) throw Fail{LDGS_E_ARG, "null argument"};
     if (!ctx->net_loaded) throw Fail{LDGS_E_ARG, "no network loaded"};
@@ -1584,6 +1833,7 @@ ldgs_status ldgs_learned_collect(ldgs_ctx* ctx, const double* xstar, int ncycles
                                  const int* origins, uint16_t* feat, uint16_t* targ, double* stats) {
   try {
     check_ctx(ctx, true);
+    if (ctx->imp) throw Fail{LDGS_E_UNSUPPORTED, "no learned correction on implicitly defined meshes"};
     Join join_(ctx);
     const Level& L = ctx->levels[0];
     const int d = ctx->g.d;
@@ -1806,8 +2056,7 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxi
           double* zj = flex ? Z[j] : T;
           vcycle_user(ctx, ctx->vprec, V[j], zj, true);
           if (use_learned) learned_minres(ctx, ctx->vprec, zj, zj);   // a variable preconditioner: FGMRES only
-          LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream, ctx->small_grid};
-          LCHK(launch_residual<double>(cfg, ctx->s64.lv[0].unscaled, ctx->tab, nullptr, zj, V[j + 1], 1));
+          apply_fine(ctx, zj, V[j + 1]);
           for (int i = 0; i <= j; ++i) {
             double hij = dot(ctx, V[j + 1], V[i]);
             H[i * m + j] = hij;
@@ -1895,9 +2144,8 @@ ldgs_status ldgs_gmres_rho(ldgs_ctx* ctx, const double* x0, double reduction, in
     while ((int)ctx->kry.size() < maxit + 2) ctx->kry.push_back(dalloc<double>(ctx, N));
     double* const* V = ctx->kry.data();
     double* Av = ctx->kry[maxit + 1];            // A v, the V-cycle's input
-    LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream, ctx->small_grid};
     auto VA = [&](const double* v, double* out) {
-      LCHK(launch_residual<double>(cfg, ctx->s64.lv[0].unscaled, ctx->tab, nullptr, v, Av, 1));
+      apply_fine(ctx, v, Av);
       vcycle_user(ctx, ctx->vprec, Av, out, true);
     };
     // r0 = V (b - A x0) = -V A x0
@@ -1947,6 +2195,10 @@ ldgs_status ldgs_gmres_rho(ldgs_ctx* ctx, const double* x0, double reduction, in
 
 // ---- profiling -------------------------------------------------------------
 ldgs_status ldgs_profile(ldgs_ctx* ctx, int enable) {
+  if (ctx && ctx->imp) {
+    ctx->err = "no pass timing on implicitly defined meshes";
+    return LDGS_E_UNSUPPORTED;
+  }
   if (!ctx) return LDGS_E_ARG;
   ctx->prof = enable > 0 ? enable : 0;
   ctx->prof_count = 0;
@@ -1979,10 +2231,37 @@ ldgs_status ldgs_profile_read(ldgs_ctx* ctx, double* total_ms, int64_t* launches
 }
 
 // ---- stage entry points --------------------------------------------------
+namespace {
+// level and colour checks of the level-stage entry points on implicit meshes
+void imp_level_check(ldgs_ctx* ctx, int level, bool smoothed) {
+  const int nl = (int)ctx->imp->lv.size();
+  if (level < 0 || level >= nl || (smoothed && level + 1 >= nl)) throw Fail{LDGS_E_ARG, "level"};
+}
+}  // namespace
+
+ldgs_status ldgs_level_elements(const ldgs_ctx* ctx, int level, int64_t* ne) {
+  if (!ctx || !ne) return LDGS_E_ARG;
+  if (ctx->imp) {
+    if (level < 0 || level >= (int)ctx->imp->lv.size()) return LDGS_E_ARG;
+    *ne = ctx->imp->lv[level].NE;
+  } else {
+    if (level < 0 || level >= (int)ctx->levels.size()) return LDGS_E_ARG;
+    *ne = ctx->levels[level].NE;
+  }
+  return LDGS_OK;
+}
+
 ldgs_status ldgs_level_smooth_colour(ldgs_ctx* ctx, int level, int colour, const double* b, double* x) {
   try {
     check_ctx(ctx, true);
     Join join_(ctx);
+    if (ctx->imp) {
+      if (!ctx->imp64) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
+      imp_level_check(ctx, level, true);
+      if (colour < 0 || colour >= ctx->imp->lv[level].ncol || !b || !x) throw Fail{LDGS_E_ARG, "colour"};
+      imp_colour<double>(ctx, level, colour, b, x);
+      return LDGS_OK;
+    }
     if (!ctx->s64.built) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
     if (level < 0 || level + 1 >= (int)ctx->levels.size()) throw Fail{LDGS_E_ARG, "level"};
     if (colour < 0 || colour >= ctx->levels[level].ncol || !b || !x) throw Fail{LDGS_E_ARG, "colour"};
@@ -1997,6 +2276,13 @@ ldgs_status ldgs_level_smooth_colour_f32(ldgs_ctx* ctx, int level, int colour, i
   try {
     check_ctx(ctx, true);
     Join join_(ctx);
+    if (ctx->imp) {
+      if (vprec != LDGS_V_FP32 || !ctx->imp32) throw Fail{LDGS_E_UNSUPPORTED, "requested float V-cycle not built"};
+      imp_level_check(ctx, level, true);
+      if (colour < 0 || colour >= ctx->imp->lv[level].ncol || !b || !x) throw Fail{LDGS_E_ARG, "colour"};
+      imp_colour<float>(ctx, level, colour, b, x);
+      return LDGS_OK;
+    }
     PrecStore<float>* S = vprec == LDGS_V_FP32 ? &ctx->s32 : (vprec == LDGS_V_FP32_BF16BLK ? &ctx->s16 : nullptr);
     if (!S || !S->built) throw Fail{LDGS_E_UNSUPPORTED, "requested float V-cycle not built"};
     if (level < 0 || level + 1 >= (int)ctx->levels.size()) throw Fail{LDGS_E_ARG, "level"};
@@ -2012,6 +2298,17 @@ ldgs_status ldgs_level_residual_restrict(ldgs_ctx* ctx, int level, const double*
   try {
     check_ctx(ctx, true);
     Join join_(ctx);
+    if (ctx->imp) {
+      if (!ctx->imp64) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
+      imp_level_check(ctx, level, true);
+      if (!b || !x || !rc) throw Fail{LDGS_E_ARG, "null argument"};
+      ldgs_ctx::ImpDev& D = ctx->idev[level];
+      ldgs_ctx::ImpDev& C = ctx->idev[level + 1];
+      const int nb = ctx->imp->nb;
+      LCHK(launch_bsr_residual<double>(ctx->stream, nb, D.NE, D.rowptr, D.cols, D.blk64, b, x, D.r64, nullptr));
+      LCHK(launch_bsr_restrict<double>(ctx->stream, nb, C.NE, C.kid_ptr, C.kids, D.I64, D.r64, rc));
+      return LDGS_OK;
+    }
     if (!ctx->s64.built) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
     if (level < 0 || level + 1 >= (int)ctx->levels.size() || !b || !x || !rc) throw Fail{LDGS_E_ARG, "level"};
     LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream, ctx->small_grid};
@@ -2026,6 +2323,14 @@ ldgs_status ldgs_level_prolong_add(ldgs_ctx* ctx, int level, const double* xc, d
   try {
     check_ctx(ctx, true);
     Join join_(ctx);
+    if (ctx->imp) {
+      if (!ctx->imp64) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
+      imp_level_check(ctx, level, true);
+      if (!xc || !x) throw Fail{LDGS_E_ARG, "null argument"};
+      ldgs_ctx::ImpDev& D = ctx->idev[level];
+      LCHK(launch_bsr_prolong<double>(ctx->stream, ctx->imp->nb, D.NE, D.parent, D.I64, xc, x));
+      return LDGS_OK;
+    }
     if (level < 0 || level + 1 >= (int)ctx->levels.size() || !xc || !x) throw Fail{LDGS_E_ARG, "level"};
     LaunchCfg cfg{ctx->g.d, ctx->g.p, ctx->stream, ctx->small_grid};
     LCHK(launch_prolong_add<double>(cfg, ctx->levels[level].n, ctx->tab, xc, x));
@@ -2051,6 +2356,15 @@ ldgs_status ldgs_level_apply(ldgs_ctx* ctx, int level, const double* x, double* 
   try {
     check_ctx(ctx, true);
     Join join_(ctx);
+    if (ctx->imp) {
+      imp_level_check(ctx, level, false);
+      ldgs_ctx::ImpDev& D = ctx->idev[level];
+      if (!D.blk64) throw Fail{LDGS_E_UNSUPPORTED, "FP64 operator of the level not built"};
+      if (!x || !y) throw Fail{LDGS_E_ARG, "null argument"};
+      LCHK(launch_bsr_residual<double>(ctx->stream, ctx->imp->nb, D.NE, D.rowptr, D.cols, D.blk64, nullptr, x, y,
+                                       nullptr));
+      return LDGS_OK;
+    }
     if (!ctx->s64.built && level != 0) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
     if (level < 0 || level >= (int)ctx->levels.size() || !x || !y) throw Fail{LDGS_E_ARG, "level"};
     if (level == (int)ctx->levels.size() - 1 && ctx->levels[level].n < 4)
@@ -2066,6 +2380,16 @@ ldgs_status ldgs_level_apply(ldgs_ctx* ctx, int level, const double* x, double* 
 ldgs_status ldgs_level_block_inverse(ldgs_ctx* ctx, int level, int64_t element, double* inv_host) {
   try {
     check_ctx(ctx, false);
+    if (ctx->imp) {
+      imp_level_check(ctx, level, true);
+      const ImpLevel& L = ctx->imp->lv[level];
+      if (element < 0 || element >= L.NE || !inv_host) throw Fail{LDGS_E_ARG, "element"};
+      const int nb = ctx->imp->nb;
+      const double* I = L.inv.data() + (size_t)element * nb * nb;   // column-major
+      for (int r = 0; r < nb; ++r)
+        for (int c = 0; c < nb; ++c) inv_host[r * nb + c] = I[(size_t)c * nb + r];
+      return LDGS_OK;
+    }
     if (level < 0 || level + 1 >= (int)ctx->levels.size() || !inv_host) throw Fail{LDGS_E_ARG, "level"};
     const Level& L = ctx->levels[level];
     if (element < 0 || element >= L.NE) throw Fail{LDGS_E_ARG, "element"};
@@ -2082,6 +2406,24 @@ ldgs_status ldgs_level_block_inverse(ldgs_ctx* ctx, int level, int64_t element, 
 ldgs_status ldgs_host_level_apply(ldgs_ctx* ctx, int level, const double* x, double* y) {
   try {
     check_ctx(ctx, false);
+    if (ctx->imp) {
+      // y = A_l x from the level's host element blocks
+      imp_level_check(ctx, level, false);
+      if (!x || !y) throw Fail{LDGS_E_ARG, "null argument"};
+      const ImpLevel& L = ctx->imp->lv[level];
+      const int nb = ctx->imp->nb;
+      for (int64_t e = 0; e < L.NE; ++e)
+        for (int r = 0; r < nb; ++r) {
+          double s = 0.0;
+          for (int k = L.rowptr[e]; k < L.rowptr[e + 1]; ++k) {
+            const double* B = L.blk.data() + (size_t)k * nb * nb;
+            const double* xf = x + (size_t)L.cols[k] * nb;
+            for (int c = 0; c < nb; ++c) s += B[(size_t)c * nb + r] * xf[c];
+          }
+          y[e * nb + r] = s;
+        }
+      return LDGS_OK;
+    }
     if (level < 0 || level >= (int)ctx->levels.size() || !x || !y) throw Fail{LDGS_E_ARG, "level"};
     host_apply(ctx->levels[level], ctx->g, ctx->B, ctx->P.form, x, y);
     return LDGS_OK;

@@ -32,7 +32,7 @@ COLOR_AUTO, COLOR_RED_BLACK, COLOR_PARITY, COLOR_MOD3 = 0, 1, 2, 3
 V_FP64, V_FP32, V_FP32_BF16BLK = 0, 1, 2
 STATIONARY, IR, FGMRES, GMRES = 0, 1, 2, 3
 FIELD_CONST, FIELD_SINSIN, FIELD_LOGNORMAL_RFF, FIELD_PHASE_CONST, FIELD_CALLBACK = range(5)
-LEVELSET_NONE, LEVELSET_BOX = 0, 1
+LEVELSET_NONE, LEVELSET_BOX, LEVELSET_CIRCLE = 0, 1, 2
 NET_HIDDEN = 16          # hidden width of the learned correction network
 TRAIN_WORKSPACE_BYTES = 4 << 20   # workspace of ldgs_learned_train_noalloc (LDGS_TRAIN_WORKSPACE_BYTES)
 
@@ -56,7 +56,8 @@ class ProblemStruct(C.Structure):
                 ("coarsest_n", C.c_int), ("coloring", C.c_int), ("vprec", C.c_int),
                 ("build_precisions", C.c_int), ("diag_scaling", C.c_int), ("host_only", C.c_int),
                 ("hip_stream", C.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
-                ("alloc_user", C.c_void_p)]
+                ("alloc_user", C.c_void_p), ("levelset_centre", C.c_double * 3),
+                ("tau_u_intra_C", C.c_double), ("q_cut", C.c_int)]
 
 
 class RhsData(C.Structure):
@@ -103,6 +104,7 @@ _SIGS = {
     "ldgs_learned_train_noalloc": ([C.POINTER(TrainArgs), C.POINTER(C.c_float), _D, C.POINTER(C.c_float)]),
     "ldgs_project_kernel": ([_P, _P]),
     "ldgs_level_info": ([_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "ldgs_level_elements": ([_P, C.c_int, C.POINTER(C.c_int64)]),
     "ldgs_level_shared_inverse": ([_P, C.c_int, C.POINTER(C.c_int)]),
     "ldgs_level_smooth_colour": ([_P, C.c_int, C.c_int, _P, _P]),
     "ldgs_level_residual_restrict": ([_P, C.c_int, _P, _P, _P]),
@@ -209,16 +211,23 @@ def problem_struct(prob, vprec=V_FP64, build_precisions=0, host_only=False, stre
     if getattr(prob, "rho", None) is not None:
         s.rho = _field(prob.rho, prob.dim, keep)
     s.delta = prob.delta if getattr(prob, "delta", None) else 0.0
-    if getattr(prob, "phases", None) is not None:
+    ph = getattr(prob, "phases", None)
+    if ph is not None and getattr(ph, "kind", None) == "circle":
+        s.levelset_kind = LEVELSET_CIRCLE
+        s.levelset_params[0] = ph.radius
+        s.levelset_centre[0], s.levelset_centre[1] = ph.centre
+        s.tau_u_intra_C = getattr(prob, "tau_u_intra_C", 0.0)
+        s.q_cut = getattr(prob, "q_cut", 8)
+    elif ph is not None:
         s.levelset_kind = LEVELSET_BOX
-        s.levelset_params[0] = prob.phases.lo
-        s.levelset_params[1] = prob.phases.hi
+        s.levelset_params[0] = ph.lo
+        s.levelset_params[1] = ph.hi
     s.tau, s.tau0 = prob.tau, prob.tau0
     s.tau_u_bdry_C, s.tau_u_inter_C = prob.tau_u_bdry_C, prob.tau_u_inter_C
     s.nu1, s.nu2, s.coarsest_n = prob.nu1, prob.nu2, prob.coarsest_n
     col = coloring if coloring is not None else prob.coloring
     s.coloring = {"auto": COLOR_AUTO, "rb": COLOR_RED_BLACK, "parity": COLOR_PARITY,
-                  "mod3": COLOR_MOD3}.get(col, col)
+                  "mod3": COLOR_MOD3, "greedy": COLOR_AUTO}.get(col, col)
     s.vprec = vprec
     s.build_precisions = build_precisions
     s.diag_scaling = int(bool(getattr(prob, "diag_scaling", False)))
@@ -244,7 +253,11 @@ def rhs_callbacks(src, dim):
 
     r.f = mk(lambda x, ph, nr: src.forcing(x, ph), dim)
     r.f_div = mk(lambda x, ph, nr: src.forcing_div(x, ph), 1)
-    if hasattr(src, "velocity"):
+    if hasattr(src, "interface_jumps"):
+        r.g_dirichlet = mk(lambda x, ph, nr: src.velocity(x, ph), dim)
+        r.g_jump = mk(lambda x, ph, nr: src.interface_jumps(x, nr)[0], dim)
+        r.h_jump = mk(lambda x, ph, nr: src.interface_jumps(x, nr)[1], dim)
+    elif hasattr(src, "velocity"):
         r.g_dirichlet = mk(lambda x, ph, nr: src.velocity(x, ph), dim)
 
         def gj(x, ph, nr):
@@ -414,6 +427,11 @@ class Context:
         n, nl, nc = C.c_int(), C.c_int(), C.c_int()
         self._check(_lib.ldgs_level_info(self._h, level, C.byref(n), C.byref(nl), C.byref(nc)))
         return n.value, nl.value, nc.value
+
+    def level_elements(self, level):
+        ne = C.c_int64()
+        self._check(_lib.ldgs_level_elements(self._h, level, C.byref(ne)))
+        return ne.value
 
     def level_shared_inverse(self, level):
         v = C.c_int()
