@@ -100,7 +100,9 @@ def cpu_baseline(make, n_sample, cycles=4):
 
 
 def make_problem(workload, n):
-    from synth import c2_dirichlet_varmu, c3_unsteady_periodic, c4a_square_inclusion, c5_lognormal
+    from synth import c2_dirichlet_varmu, c3_unsteady_periodic, c4a_square_inclusion, c4_circle, c5_lognormal
+    if workload == "c4":
+        return c4_circle(n=n or 512, p=2, rhs="bubble")
     if workload == "c2":
         return c2_dirichlet_varmu(n=n or 256, p=3)
     if workload == "c3":
@@ -121,7 +123,142 @@ DESCRIPTION = {
     "c4a": "2D two-phase viscous-stress Stokes, square inclusion (1/4,3/4)^2, mu 1e4 / 1, Dirichlet walls, {n}^2 "
            "elements, Q_2, manufactured solution, mod-3 colouring, diagonal scaling; V(3,3) stationary (FP64) / "
            "iterative refinement (FP32) to 1e-10",
+    "c4": "2D two-phase viscous-stress Stokes on an implicitly defined mesh: circle of radius 0.3 centred in the unit "
+          "square cutting a {n}^2 grid, mu 1e4 inside / 1 outside, densities 1 / 1e-3 under gravity, unit surface "
+          "tension, Dirichlet walls, Q_2, cut pieces below a quarter cell merged, explicit element blocks, greedy "
+          "colouring, diagonal scaling; V(3,3) in FGMRES({m}) to 1e-10",
 }
+
+
+def bench_circle(args):
+    """The circular-interface workload (implicitly defined mesh, explicit
+    element blocks): FP64 and FP32 V-cycles, FGMRES to 1e-10 with each, and
+    the finest colour pass (k_bsr_colour) against its bytes: per element of a
+    colour the stored blocks of its row and its inverse (nb^2 FP64 values
+    each) plus x and b in and x out."""
+    import torch
+    from paper_1911_05888_amd import Context, V_FP64, V_FP32, FGMRES
+    log = lambda s: print(f"[bench] {s}", file=sys.stderr, flush=True)
+    prob = make_problem("c4", args.n)
+    t0 = time.perf_counter()
+    ctx = Context(prob, vprec=V_FP64, build_precisions=1 << V_FP32)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    b0 = ctx.assemble_rhs(prob.rhs_source())
+    ndof, nl = ctx.ndof, ctx.n_levels
+    ne = [ctx.level_elements(l) for l in range(nl)]
+    nblk = ctx.level_blocks(0)
+    ncol = ctx.level_info(0)[2]
+    log(f"setup {t_setup:.1f} s, {ndof} unknowns, {nl} levels, elements {ne}, {ncol} colours")
+    if args.cycles_only:
+        x = torch.zeros_like(b0)
+        for _ in range(args.cycles_only):
+            ctx.vcycle(b0, x)
+        torch.cuda.synchronize()
+        log(f"{args.cycles_only} FP64 V-cycles done")
+        return
+
+    def cycle_time(vp, reps=5):
+        ctx.set_vprec(vp)
+        x = torch.zeros_like(b0)
+        for _ in range(max(args.warmup, 1)):
+            x.zero_()
+            ctx.vcycle(b0, x)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            x.zero_()
+            ctx.vcycle(b0, x)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    def solve(vp, label):
+        ctx.set_vprec(vp)
+        tt, its, rel = 0.0, 0, None
+        for _ in range(args.steps):
+            b = b0.clone()
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st, info = ctx.solve(b, x, tol=TOL, maxit=args.m, outer=FGMRES, fgmres_m=args.m)
+            torch.cuda.synchronize()
+            tt += time.perf_counter() - t
+            its += info["iters"]
+            rel = info["relres"]
+            if not rel <= TOL:
+                raise RuntimeError(f"{label}: relres {rel:.3e}")
+            log(f"{label}: FGMRES {info['iters']} iterations, relres {rel:.2e}, {tt:.3f} s")
+        return tt / args.steps, its / args.steps, rel
+
+    # the finest colour pass: one sweep of all colours between two events
+    def pass_time(reps=4):
+        ctx.set_vprec(V_FP64)
+        x = torch.zeros_like(b0)
+        ctx.level_smooth_colour(0, 0, b0, x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            for c in range(ncol):
+                ctx.level_smooth_colour(0, c, b0, x)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / (reps * ncol)
+
+    tc64 = cycle_time(V_FP64)
+    tc32 = cycle_time(V_FP32)
+    log(f"V-cycle FP64 {tc64 * 1e3:.2f} ms, FP32 {tc32 * 1e3:.2f} ms")
+    t64, it64, rel64 = solve(V_FP64, "FP64")
+    t32, it32, rel32 = solve(V_FP32, "FP32")
+    tp = pass_time()
+    nb = prob.nb
+    bytes_pass = ((nblk + ne[0]) * nb * nb * 8 + 3 * ne[0] * nb * 8) / ncol
+    achieved = bytes_pass / tp / 1e9
+    value = ndof * it64 / t64            # FGMRES: one V-cycle per iteration
+    line = dict(
+        metric="V-cycle DOF/s + wall time to 1e-10 rel. residual, plain FP64 vs mixed/learned",
+        value=value, unit="DOF/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=t64 * 1e3,
+        higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload=DESCRIPTION["c4"].format(n=prob.n, m=args.m), n=prob.n, p=prob.p, dim=2,
+                    unknowns=ndof, levels=nl, elements_per_level=ne, colours=ncol, blocks_fine=nblk,
+                    setup_s=t_setup,
+                    fp64=dict(time_to_tol_s=t64, iters=it64, relres=rel64, vcycle_s=tc64,
+                              vcycle_dof_per_s=ndof / tc64),
+                    fp32=dict(time_to_tol_s=t32, iters=it32, relres=rel32, vcycle_s=tc32,
+                              vcycle_dof_per_s=ndof / tc32)),
+        roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                      traffic=None, kernel=f"k_bsr_colour<double,{nb}> (finest level)", avg_launch_us=tp * 1e6,
+                      algorithmic_bytes_per_launch=bytes_pass,
+                      timing="torch events around 4 sweeps of finest colour passes (library stream joined)"),
+    )
+    ctx.close()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_circle(32)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline_circle(n_sample, cycles=4):
+    """The FP64 oracle's V-cycle on the implicit mesh of the n_sample grid."""
+    from threadpoolctl import threadpool_limits
+    from oracle.implicit_assemble import build_implicit_hierarchy
+    from oracle.solvers import Solver
+    prob = make_problem("c4", n_sample)
+    H = build_implicit_hierarchy(prob)
+    S = Solver(H)
+    b = H.project_kernel(np.random.Generator(np.random.PCG64(7)).standard_normal(S.A.shape[0]))
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    out = {}
+    for label, lim in (("one", 1), ("all", ncores)):
+        with threadpool_limits(limits=lim):
+            x = None
+            t0 = time.perf_counter()
+            for _ in range(cycles):
+                x = S.vcycle_unscaled(b, x)
+            out[label] = S.A.shape[0] * cycles / (time.perf_counter() - t0)
+    return dict(value=out["all"], unit="DOF/s", cores=ncores, kind="oracle", single_thread_value=out["one"],
+                cpu_model=cpu_model(),
+                sample=f"FP64 oracle V(3,3) cycles on the implicit mesh of the {n_sample}^2 grid "
+                       f"({S.A.shape[0]} unknowns, {cycles} cycles per thread count)")
 
 
 def main():
@@ -145,6 +282,8 @@ def main():
               "(the library runs on one GPU; a domain decomposition over several is not implemented)", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "c4":
+        return bench_circle(args)
     import torch
     from paper_1911_05888_amd import Context, V_FP64, V_FP32, V_FP32_BF16BLK, STATIONARY, IR, GMRES, FGMRES
     from synth.fields import projected_coeffs

@@ -378,6 +378,13 @@ ldgs_status ldgs_level_info(const ldgs_ctx* ctx, int level, int* n_l, int* n_lev
  * of range. */
 ldgs_status ldgs_level_elements(const ldgs_ctx* ctx, int level, int64_t* ne);
 
+/* Number of stored nb x nb element blocks A_EF of level `level` of an
+ * implicitly defined mesh (the block rows of section 3's Gauss-Seidel
+ * update; the diagonal blocks included).  Works on host-only contexts.
+ * Errors: LDGS_E_ARG for a null pointer or a level out of range,
+ * LDGS_E_UNSUPPORTED on Cartesian grids (no explicit blocks). */
+ldgs_status ldgs_level_blocks(const ldgs_ctx* ctx, int level, int64_t* nblocks);
+
 /* *shared = 1 when every diagonal block of level `level` is the same matrix
  * (constant viscosity and density, a periodic grid, no interphase faces: the
  * operator is translation invariant), so that its colour passes hold one

@@ -232,23 +232,28 @@ struct Join {
 };
 
 template <typename T>
-T* upload(ldgs_ctx* c, const std::vector<double>& src) {
-  T* d = dalloc<T>(c, src.size());
-  if (src.empty()) return d;
+T* upload(ldgs_ctx* c, const double* src, size_t n) {
+  T* d = dalloc<T>(c, n);
+  if (n == 0) return d;
   if constexpr (std::is_same_v<T, double>) {
-    HIPCHK(hipMemcpy(d, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(d, src, n * sizeof(T), hipMemcpyHostToDevice));
   } else {
     // converted in pieces on all host threads
     const size_t piece = (size_t)1 << 24;
-    std::vector<T> tmp(std::min(piece, src.size()));
-    for (size_t o = 0; o < src.size(); o += piece) {
-      const int64_t cnt = (int64_t)std::min(piece, src.size() - o);
+    std::vector<T> tmp(std::min(piece, n));
+    for (size_t o = 0; o < n; o += piece) {
+      const int64_t cnt = (int64_t)std::min(piece, n - o);
 #pragma omp parallel for schedule(static)
       for (int64_t i = 0; i < cnt; ++i) tmp[i] = (T)src[o + i];
       HIPCHK(hipMemcpy(d + o, tmp.data(), cnt * sizeof(T), hipMemcpyHostToDevice));
     }
   }
   return d;
+}
+
+template <typename T>
+T* upload(ldgs_ctx* c, const std::vector<double>& src) {
+  return upload<T>(c, src.data(), src.size());
 }
 
 bool stress_walls(const ldgs_problem& P) { return P.bc[0] == LDGS_STRESS; }
@@ -964,11 +969,11 @@ void imp_device(ldgs_ctx* c) {
     D.rowptr = upload_int(c, L.rowptr);
     D.cols = upload_int(c, L.cols);
     // the FP64 finest operator always (outer residual and products)
-    if (c->imp64 || l == 0) D.blk64 = upload<double>(c, L.blk);
-    if (c->imp32) D.blk32 = upload<float>(c, L.blk);
+    if (c->imp64 || l == 0) D.blk64 = upload<double>(c, L.blk.data(), L.blk.size());
+    if (c->imp32) D.blk32 = upload<float>(c, L.blk.data(), L.blk.size());
     if (l + 1 < nl) {
-      if (c->imp64) D.inv64 = upload<double>(c, L.inv);
-      if (c->imp32) D.inv32 = upload<float>(c, L.inv);
+      if (c->imp64) D.inv64 = upload<double>(c, L.inv.data(), L.inv.size());
+      if (c->imp32) D.inv32 = upload<float>(c, L.inv.data(), L.inv.size());
       D.parent = upload_int(c, L.parent);
       if (c->imp64) D.I64 = upload<double>(c, L.Iblk);
       if (c->imp32) D.I32 = upload<float>(c, L.Iblk);
@@ -2248,6 +2253,14 @@ ldgs_status ldgs_level_elements(const ldgs_ctx* ctx, int level, int64_t* ne) {
     if (level < 0 || level >= (int)ctx->levels.size()) return LDGS_E_ARG;
     *ne = ctx->levels[level].NE;
   }
+  return LDGS_OK;
+}
+
+ldgs_status ldgs_level_blocks(const ldgs_ctx* ctx, int level, int64_t* nblocks) {
+  if (!ctx || !nblocks) return LDGS_E_ARG;
+  if (!ctx->imp) return LDGS_E_UNSUPPORTED;   // Cartesian levels hold no explicit blocks
+  if (level < 0 || level >= (int)ctx->imp->lv.size()) return LDGS_E_ARG;
+  *nblocks = ctx->imp->lv[level].rowptr.empty() ? 0 : ctx->imp->lv[level].rowptr.back();
   return LDGS_OK;
 }
 

@@ -26,7 +26,10 @@
 #include "implicit.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <stdexcept>
@@ -561,83 +564,91 @@ void compose(const ldgs_problem& P, const ImpHier& H, ImpLevel& L) {
       L.dscale[2 * e + 1] = std::sqrt(mu);
     }
   }
+  // block structure of every row: the union of the columns its terms reach
+  L.rowptr.assign(NE + 1, 0);
   std::vector<std::vector<int>> rcols(NE);
-  std::vector<std::vector<double>> rblk(NE);
-#pragma omp parallel for schedule(dynamic, 64)
+#pragma omp parallel for schedule(dynamic, 256)
   for (int64_t e = 0; e < NE; ++e) {
-    // scalar blocks of row e: Pij = G_j^T Mmu G_i (i, j < 2), Et, E, G_i^T M, M G_i
-    std::map<int, std::vector<double>> acc;   // column -> nb x nb row-major
-    auto blk = [&](int c) -> double* {
-      auto& v = acc[c];
-      if (v.empty()) v.assign((size_t)nb * nb, 0.0);
-      return v.data();
-    };
-    auto addsub = [&](int c, int bi, int bj, const double* S, bool trans, double s) {
-      double* B = blk(c);
-      for (int a = 0; a < nq; ++a)
-        for (int b = 0; b < nq; ++b)
-          B[(size_t)(bi * nq + a) * nb + bj * nq + b] += s * (trans ? S[b * nq + a] : S[a * nq + b]);
-    };
-    std::vector<double> T(bs), U(bs);
+    std::vector<int>& c = rcols[e];
     for (int j = 0; j < 2; ++j)
       for (auto [hrow, slot] : (*tG[j])[e]) {
-        const double* Gje = L.G[j].val[hrow].data() + (size_t)slot * bs;   // G_j[h][e]
-        const double* Mh = L.Mmu.get(hrow, hrow);
-        std::fill(T.begin(), T.end(), 0.0);
-        gemm(nq, Gje, true, Mh, T.data());                                 // G_j[h][e]^T Mmu_h
-        for (int i = 0; i < 2; ++i)
-          for (size_t k = 0; k < L.G[i].col[hrow].size(); ++k) {
-            const int f = L.G[i].col[hrow][k];
-            std::fill(U.begin(), U.end(), 0.0);
-            gemm(nq, T.data(), false, L.G[i].val[hrow].data() + k * bs, U.data());   // P_ij(e, f)
-            if (i == j) {
-              addsub(f, 0, 0, U.data(), false, 1.0);
-              addsub(f, 1, 1, U.data(), false, 1.0);
-            }
-            if (gamma != 0.0) addsub(f, i, j, U.data(), false, gamma);
-          }
-        // -(G_j^T M)(e, h)
-        std::fill(U.begin(), U.end(), 0.0);
-        gemm(nq, Gje, true, L.M.get(hrow, hrow), U.data());
-        addsub(hrow, j, 2, U.data(), false, -1.0);
+        (void)slot;
+        c.push_back(hrow);
+        for (int i = 0; i < 2; ++i) c.insert(c.end(), L.G[i].col[hrow].begin(), L.G[i].col[hrow].end());
       }
-    for (size_t k = 0; k < L.Et.col[e].size(); ++k) {
-      addsub(L.Et.col[e][k], 0, 0, L.Et.val[e].data() + k * bs, false, 1.0);
-      addsub(L.Et.col[e][k], 1, 1, L.Et.val[e].data() + k * bs, false, 1.0);
-    }
-    const double* Me = L.M.get(e, (int)e);
-    for (int i = 0; i < 2; ++i)
-      for (size_t k = 0; k < L.G[i].col[e].size(); ++k) {
-        std::fill(U.begin(), U.end(), 0.0);
-        gemm(nq, Me, false, L.G[i].val[e].data() + k * bs, U.data());       // (M G_i)(e, f)
-        addsub(L.G[i].col[e][k], 2, i, U.data(), false, -1.0);
-      }
-    for (size_t k = 0; k < L.E.col[e].size(); ++k) addsub(L.E.col[e][k], 2, 2, L.E.val[e].data() + k * bs, false, -1.0);
-    for (auto& kv : acc) {
-      const int f = kv.first;
-      double* B = kv.second.data();
-      bool any = false;
-      for (double v : kv.second) any = any || v != 0.0;
-      if (!any) continue;
-      if (P.diag_scaling)
-        for (int r = 0; r < nb; ++r)
-          for (int c = 0; c < nb; ++c)
-            B[r * nb + c] *= L.dscale[2 * e + (r < 2 * nq ? 0 : 1)] * L.dscale[2 * f + (c < 2 * nq ? 0 : 1)];
-      rcols[e].push_back(f);
-      // column-major copy
-      const size_t o = rblk[e].size();
-      rblk[e].resize(o + (size_t)nb * nb);
-      for (int r = 0; r < nb; ++r)
-        for (int c = 0; c < nb; ++c) rblk[e][o + (size_t)c * nb + r] = B[r * nb + c];
-    }
+    c.insert(c.end(), L.Et.col[e].begin(), L.Et.col[e].end());
+    c.insert(c.end(), L.E.col[e].begin(), L.E.col[e].end());
+    for (int i = 0; i < 2; ++i) c.insert(c.end(), L.G[i].col[e].begin(), L.G[i].col[e].end());
+    std::sort(c.begin(), c.end());
+    c.erase(std::unique(c.begin(), c.end()), c.end());
   }
-  L.rowptr.assign(NE + 1, 0);
   for (int64_t e = 0; e < NE; ++e) L.rowptr[e + 1] = L.rowptr[e] + (int)rcols[e].size();
   L.cols.resize(L.rowptr[NE]);
-  L.blk.resize((size_t)L.rowptr[NE] * nb * nb);
-  for (int64_t e = 0; e < NE; ++e) {
-    std::copy(rcols[e].begin(), rcols[e].end(), L.cols.begin() + L.rowptr[e]);
-    std::copy(rblk[e].begin(), rblk[e].end(), L.blk.begin() + (size_t)L.rowptr[e] * nb * nb);
+  for (int64_t e = 0; e < NE; ++e) std::copy(rcols[e].begin(), rcols[e].end(), L.cols.begin() + L.rowptr[e]);
+  rcols.clear();
+  rcols.shrink_to_fit();
+  L.blk.resize((size_t)L.rowptr[NE] * nb * nb);        // every entry written below
+#pragma omp parallel
+  {
+    std::vector<double> T(bs), U(bs), R;
+#pragma omp for schedule(dynamic, 256)
+    for (int64_t e = 0; e < NE; ++e) {
+      const int k0 = L.rowptr[e], nk = L.rowptr[e + 1] - k0;
+      R.assign((size_t)nk * nb * nb, 0.0);       // the row's blocks, row-major
+      auto addsub = [&](int c, int bi, int bj, const double* S, double s) {
+        const int k = (int)(std::lower_bound(L.cols.begin() + k0, L.cols.begin() + k0 + nk, c) - (L.cols.begin() + k0));
+        double* B = R.data() + (size_t)k * nb * nb;
+        for (int a = 0; a < nq; ++a)
+          for (int b = 0; b < nq; ++b) B[(size_t)(bi * nq + a) * nb + bj * nq + b] += s * S[a * nq + b];
+      };
+      // scalar blocks of row e: P_ij = G_j^T Mmu G_i (i, j < 2), Et, E, G_j^T M, M G_i
+      for (int j = 0; j < 2; ++j)
+        for (auto [hrow, slot] : (*tG[j])[e]) {
+          const double* Gje = L.G[j].val[hrow].data() + (size_t)slot * bs;   // G_j[h][e]
+          const double* Mh = L.Mmu.get(hrow, hrow);
+          std::fill(T.begin(), T.end(), 0.0);
+          gemm(nq, Gje, true, Mh, T.data());                                 // G_j[h][e]^T Mmu_h
+          for (int i = 0; i < 2; ++i)
+            for (size_t k = 0; k < L.G[i].col[hrow].size(); ++k) {
+              const int f = L.G[i].col[hrow][k];
+              std::fill(U.begin(), U.end(), 0.0);
+              gemm(nq, T.data(), false, L.G[i].val[hrow].data() + k * bs, U.data());   // P_ij(e, f)
+              if (i == j) {
+                addsub(f, 0, 0, U.data(), 1.0);
+                addsub(f, 1, 1, U.data(), 1.0);
+              }
+              if (gamma != 0.0) addsub(f, i, j, U.data(), gamma);
+            }
+          // -(G_j^T M)(e, h)
+          std::fill(U.begin(), U.end(), 0.0);
+          gemm(nq, Gje, true, L.M.get(hrow, hrow), U.data());
+          addsub(hrow, j, 2, U.data(), -1.0);
+        }
+      for (size_t k = 0; k < L.Et.col[e].size(); ++k) {
+        addsub(L.Et.col[e][k], 0, 0, L.Et.val[e].data() + k * bs, 1.0);
+        addsub(L.Et.col[e][k], 1, 1, L.Et.val[e].data() + k * bs, 1.0);
+      }
+      const double* Me = L.M.get(e, (int)e);
+      for (int i = 0; i < 2; ++i)
+        for (size_t k = 0; k < L.G[i].col[e].size(); ++k) {
+          std::fill(U.begin(), U.end(), 0.0);
+          gemm(nq, Me, false, L.G[i].val[e].data() + k * bs, U.data());       // (M G_i)(e, f)
+          addsub(L.G[i].col[e][k], 2, i, U.data(), -1.0);
+        }
+      for (size_t k = 0; k < L.E.col[e].size(); ++k) addsub(L.E.col[e][k], 2, 2, L.E.val[e].data() + k * bs, -1.0);
+      for (int k = 0; k < nk; ++k) {
+        const int f = L.cols[k0 + k];
+        const double* B = R.data() + (size_t)k * nb * nb;
+        double* O = L.blk.data() + (size_t)(k0 + k) * nb * nb;      // column-major
+        for (int r = 0; r < nb; ++r) {
+          const double sr = P.diag_scaling ? L.dscale[2 * e + (r < 2 * nq ? 0 : 1)] : 1.0;
+          for (int c = 0; c < nb; ++c) {
+            const double sc = P.diag_scaling ? L.dscale[2 * f + (c < 2 * nq ? 0 : 1)] : 1.0;
+            O[(size_t)c * nb + r] = B[r * nb + c] * sr * sc;
+          }
+        }
+      }
+    }
   }
 }
 
@@ -645,11 +656,16 @@ void colour_and_invert(ImpLevel& L, int nb) {
   const int64_t NE = L.NE;
   std::vector<std::vector<int>> nbr(NE);
   for (int64_t e = 0; e < NE; ++e)
-    for (int k = L.rowptr[e]; k < L.rowptr[e + 1]; ++k)
-      if (L.cols[k] != e) {
-        nbr[e].push_back(L.cols[k]);
-        nbr[L.cols[k]].push_back((int)e);
-      }
+    for (int k = L.rowptr[e]; k < L.rowptr[e + 1]; ++k) {
+      if (L.cols[k] == e) continue;
+      // a block of the structure whose entries all vanish couples nothing
+      const double* B = L.blk.data() + (size_t)k * nb * nb;
+      bool any = false;
+      for (size_t i = 0; i < (size_t)nb * nb && !any; ++i) any = B[i] != 0.0;
+      if (!any) continue;
+      nbr[e].push_back(L.cols[k]);
+      nbr[L.cols[k]].push_back((int)e);
+    }
   L.colour.assign(NE, -1);
   L.ncol = 0;
   for (int64_t e = 0; e < NE; ++e) {
@@ -663,7 +679,7 @@ void colour_and_invert(ImpLevel& L, int nb) {
   }
   L.elems.assign(L.ncol, {});
   for (int64_t e = 0; e < NE; ++e) L.elems[L.colour[e]].push_back((int)e);
-  L.inv.assign((size_t)NE * nb * nb, 0.0);
+  L.inv.resize((size_t)NE * nb * nb);                  // every block written below
   bool ok = true;
 #pragma omp parallel for schedule(dynamic, 256) reduction(&& : ok)
   for (int64_t e = 0; e < NE; ++e) {
@@ -703,6 +719,15 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
   H.cy = P.levelset_centre[1];
   if (!(H.r > 0.0)) fail("circle radius must be positive");
   const Circle ls{{H.cx, H.cy}, H.r};
+  // LDGS_SETUP_TIMING=1: wall time of each phase on stderr
+  const bool timing = std::getenv("LDGS_SETUP_TIMING") && std::atoi(std::getenv("LDGS_SETUP_TIMING"));
+  auto tmark = std::chrono::steady_clock::now();
+  auto phase = [&](const char* what) {
+    if (!timing) return;
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[ldgs implicit] %-26s %8.3f s\n", what, std::chrono::duration<double>(now - tmark).count());
+    tmark = now;
+  };
   const int n = P.n, p = H.p, m = H.m, nq = H.nq;
   const int q_full = p + 2, q_cut = P.q_cut > 0 ? P.q_cut : 8;
   const double h = 1.0 / n;
@@ -739,6 +764,7 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
       }
     }
   H.n_cut = (int)F.surf.size();
+  phase("cells and quadrature");
   // --------------------------------------------------------------- merging
   auto exists = [&](int64_t key) { return !F.piece[key].w.empty(); };
   std::vector<double> frac(2 * NCELL, 0.0);
@@ -790,6 +816,7 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
     root[key] = k;
     if (target[key] >= 0) ++H.n_merged;
   }
+  phase("merging");
   // elements: roots in (cell, phase) order; members in (cell, phase) order
   F.elem_of.assign(2 * NCELL, -1);
   std::vector<int64_t> roots;
@@ -843,6 +870,7 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
     }
     qr_lower(Q, nq, R, Le);
   }
+  phase("elements and bases");
   // ----------------------------------------------------------------- faces
   H.faces.clear();
   for (int axis = 0; axis < 2; ++axis)
@@ -906,6 +934,7 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
     f.nrm = br.nrm;
     H.faces.push_back(std::move(f));
   }
+  phase("faces");
   // ------------------------------------------------------ fine operators
   const size_t bs = (size_t)nq * nq;
   L0.M.init(NE, nq);
@@ -950,9 +979,33 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
   const double Ci = P.tau_u_inter_C > 0 ? P.tau_u_inter_C : 8.0;
   const double C0 = P.tau_u_intra_C;
   const double tau = P.tau;
-  for (const ImpFace& f : H.faces) {
+  // face blocks computed in parallel into per-face lists (matrix, row,
+  // column, block), then added into the operators in face order
+  struct FaceOut {
+    std::vector<int> key;        // (matrix, row, column) triples; matrices G_0, G_1, Et, E
+    std::vector<double> val;
+  };
+  const int64_t NF = (int64_t)H.faces.size();
+  const int64_t CHUNK = 16384;
+  std::vector<FaceOut> fout((size_t)std::min(NF, CHUNK));
+  SBM* mats[4] = {&L0.G[0], &L0.G[1], &L0.Et, &L0.E};
+  for (int64_t f0 = 0; f0 < NF; f0 += CHUNK) {
+  const int64_t f1 = std::min(NF, f0 + CHUNK);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t fi = f0; fi < f1; ++fi) {
+    const ImpFace& f = H.faces[fi];
+    FaceOut& fo = fout[fi - f0];
+    fo.key.clear();
+    fo.val.clear();
+    auto slot = [&](int mat, int r, int c) {
+      fo.key.push_back(mat);
+      fo.key.push_back(r);
+      fo.key.push_back(c);
+      fo.val.resize(fo.val.size() + bs, 0.0);
+      return fo.val.data() + fo.val.size() - bs;
+    };
     const int Q = (int)f.w.size();
-    std::vector<double> Tm((size_t)Q * nq), Tp((size_t)Q * nq), mum(Q), mup(Q), one(Q, 1.0), coef(Q);
+    std::vector<double> Tm((size_t)Q * nq), Tp((size_t)Q * nq), mum(Q), mup(Q), coef(Q);
     std::vector<int> phm(Q, L0.phase[f.minus]), php(Q, f.plus >= 0 ? L0.phase[f.plus] : 0);
     imp_basis(H, L0, f.minus, Q, f.X.data(), -1, Tm.data());
     eval_field(P.mu, 2, Q, f.X.data(), phm.data(), mum.data());
@@ -961,11 +1014,11 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
       eval_field(P.mu, 2, Q, f.X.data(), php.data(), mup.data());
     }
     const int mi = f.minus, pl = f.plus;
-    auto jump = [&](SBM& A, const std::vector<double>& t) {
-      face_block(nq, Q, f.w.data(), t.data(), Tm.data(), Tm.data(), 1.0, A.at(mi, mi));
-      face_block(nq, Q, f.w.data(), t.data(), Tp.data(), Tp.data(), 1.0, A.at(pl, pl));
-      face_block(nq, Q, f.w.data(), t.data(), Tm.data(), Tp.data(), -1.0, A.at(mi, pl));
-      face_block(nq, Q, f.w.data(), t.data(), Tp.data(), Tm.data(), -1.0, A.at(pl, mi));
+    auto jump = [&](int mat, const std::vector<double>& t) {
+      face_block(nq, Q, f.w.data(), t.data(), Tm.data(), Tm.data(), 1.0, slot(mat, mi, mi));
+      face_block(nq, Q, f.w.data(), t.data(), Tp.data(), Tp.data(), 1.0, slot(mat, pl, pl));
+      face_block(nq, Q, f.w.data(), t.data(), Tm.data(), Tp.data(), -1.0, slot(mat, mi, pl));
+      face_block(nq, Q, f.w.data(), t.data(), Tp.data(), Tm.data(), -1.0, slot(mat, pl, mi));
     };
     for (int k = 0; k < 2; ++k) {
       std::vector<double> nk(Q);
@@ -975,10 +1028,9 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
         any = any || nk[q] != 0.0;
       }
       if (!any) continue;
-      SBM& G = L0.G[k];
       if (f.kind == 0) {
-        face_block(nq, Q, f.w.data(), nk.data(), Tp.data(), Tp.data(), 1.0, G.at(pl, pl));
-        face_block(nq, Q, f.w.data(), nk.data(), Tp.data(), Tm.data(), -1.0, G.at(pl, mi));
+        face_block(nq, Q, f.w.data(), nk.data(), Tp.data(), Tp.data(), 1.0, slot(k, pl, pl));
+        face_block(nq, Q, f.w.data(), nk.data(), Tp.data(), Tm.data(), -1.0, slot(k, pl, mi));
       } else if (f.kind == 1) {
         std::vector<double> cm(Q), cp(Q);
         for (int q = 0; q < Q; ++q) {
@@ -986,32 +1038,43 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
           cm[q] = (1.0 - lam) * nk[q];
           cp[q] = lam * nk[q];
         }
-        face_block(nq, Q, f.w.data(), cm.data(), Tm.data(), Tp.data(), 1.0, G.at(mi, pl));
-        face_block(nq, Q, f.w.data(), cm.data(), Tm.data(), Tm.data(), -1.0, G.at(mi, mi));
-        face_block(nq, Q, f.w.data(), cp.data(), Tp.data(), Tp.data(), 1.0, G.at(pl, pl));
-        face_block(nq, Q, f.w.data(), cp.data(), Tp.data(), Tm.data(), -1.0, G.at(pl, mi));
+        face_block(nq, Q, f.w.data(), cm.data(), Tm.data(), Tp.data(), 1.0, slot(k, mi, pl));
+        face_block(nq, Q, f.w.data(), cm.data(), Tm.data(), Tm.data(), -1.0, slot(k, mi, mi));
+        face_block(nq, Q, f.w.data(), cp.data(), Tp.data(), Tp.data(), 1.0, slot(k, pl, pl));
+        face_block(nq, Q, f.w.data(), cp.data(), Tp.data(), Tm.data(), -1.0, slot(k, pl, mi));
       } else {
-        face_block(nq, Q, f.w.data(), nk.data(), Tm.data(), Tm.data(), -1.0, G.at(mi, mi));
+        face_block(nq, Q, f.w.data(), nk.data(), Tm.data(), Tm.data(), -1.0, slot(k, mi, mi));
       }
     }
     if (f.kind == 2) {
       for (int q = 0; q < Q; ++q) coef[q] = Cb * p * mum[q] * n;
-      face_block(nq, Q, f.w.data(), coef.data(), Tm.data(), Tm.data(), 1.0, L0.Et.at(mi, mi));
+      face_block(nq, Q, f.w.data(), coef.data(), Tm.data(), Tm.data(), 1.0, slot(2, mi, mi));
     } else if (f.kind == 1) {
       for (int q = 0; q < Q; ++q) coef[q] = Ci * p * std::min(mum[q], mup[q]) * n;
-      jump(L0.Et, coef);
+      jump(2, coef);
     } else {
       if (C0 > 0.0) {
         for (int q = 0; q < Q; ++q) coef[q] = C0 * p * mum[q] * n;
-        jump(L0.Et, coef);
+        jump(2, coef);
       }
       for (int q = 0; q < Q; ++q) coef[q] = tau * h / mum[q];
-      jump(L0.E, coef);
+      jump(3, coef);
     }
+  }
+  for (int64_t fi = f0; fi < f1; ++fi) {
+    const FaceOut& fo = fout[fi - f0];
+    for (size_t t = 0; t * 3 < fo.key.size(); ++t) {
+      double* d = mats[fo.key[3 * t]]->at(fo.key[3 * t + 1], fo.key[3 * t + 2]);
+      const double* v = fo.val.data() + t * bs;
+      for (size_t i = 0; i < bs; ++i) d[i] += v[i];
+    }
+  }
   }
   (void)bs;
   (void)m;
+  phase("fine operators");
   compose(P, H, L0);
+  phase("fine Stokes blocks");
   // ------------------------------------------------------- coarse levels
   const int coarsest = P.coarsest_n > 0 ? P.coarsest_n : 4;
   Basis B1;
@@ -1106,8 +1169,10 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
     }
     coarsen_ops(H, Fl, C);
     compose(P, H, C);
+    phase("coarse level");
   }
   for (size_t l = 0; l + 1 < H.lv.size(); ++l) colour_and_invert(H.lv[l], H.nb);
+  phase("colours and inverses");
   // ----------------------------------------------------------- bottom
   {
     const ImpLevel& Bt = H.lv.back();
@@ -1150,6 +1215,7 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
       for (int64_t j = 0; j < N; ++j) H.pinv[i * N + j] *= dg[i] * dg[j];
     H.eig = lam;
   }
+  phase("bottom");
   // fine kernel: the constant pressure, sqrt(|E|) on the first pressure function
   const ImpLevel& Lf0 = H.lv[0];   // (the level vector has grown since L0 was taken)
   H.kernel.assign((size_t)Lf0.NE * H.nb, 0.0);

@@ -26,38 +26,64 @@ struct RowMap {
 };
 
 // sum_F A_EF s_F x_F for row entry r of element E (valid in lanes r < NB of
-// every half); s_F = (alpha, beta)-type column scaling when ds != nullptr
+// every half); s_F = (alpha, beta)-type column scaling when ds != nullptr.
+// Blocks are taken two at a time, all their loads issued before the
+// multiply-adds, so that a wavefront keeps two blocks' columns in flight.
+template <typename T, int NB>
+__device__ __forceinline__ void block_terms(const T* __restrict__ B, const T* __restrict__ xF, T sv, T sp,
+                                            bool scaled, int half, int r, T& acc) {
+  using RM = RowMap<NB>;
+  constexpr int NVEL = 2 * NB / 3;
+  T a[RM::NC], xv[RM::NC];
+#pragma unroll
+  for (int cc = 0; cc < RM::NC; ++cc) {
+    const int c = RM::H * cc + half;
+    const bool in = c < NB;
+    a[cc] = in ? B[c * NB + r] : (T)0;
+    xv[cc] = in ? xF[c] : (T)0;
+  }
+#pragma unroll
+  for (int cc = 0; cc < RM::NC; ++cc) {
+    const int c = RM::H * cc + half;
+    const T s = scaled ? (c < NVEL ? sv : sp) : (T)1;
+    acc += a[cc] * (xv[cc] * s);
+  }
+}
+
 template <typename T, int NB>
 __device__ __forceinline__ T block_row(const int* __restrict__ rowptr, const int* __restrict__ cols,
                                        const T* __restrict__ blk, const T* __restrict__ x, int E, int lane,
                                        const double* __restrict__ ds) {
   using RM = RowMap<NB>;
-  constexpr int NVEL = 2 * NB / 3;
   const int half = RM::H == 2 ? (lane >> 5) : 0;
   const int r = RM::H == 2 ? (lane & 31) : lane;
-  T acc = (T)0;
+  const int rr = r < NB ? r : NB - 1;        // idle lanes read a valid row and discard it
+  T acc = (T)0, acc2 = (T)0;
   const int k0 = rowptr[E], k1 = rowptr[E + 1];
-  for (int k = k0; k < k1; ++k) {
-    const int F = cols[k];
-    const T* B = blk + (size_t)k * NB * NB;
-    const T* xF = x + (size_t)F * NB;
-    T sv = (T)1, sp = (T)1;
-    if (ds) {
-      sv = (T)ds[2 * F];
-      sp = (T)ds[2 * F + 1];
+  const bool scaled = ds != nullptr;
+  int k = k0;
+  for (; k + 1 < k1; k += 2) {
+    const int F0 = cols[k], F1 = cols[k + 1];
+    T sv0 = (T)1, sp0 = (T)1, sv1 = (T)1, sp1 = (T)1;
+    if (scaled) {
+      sv0 = (T)ds[2 * F0];
+      sp0 = (T)ds[2 * F0 + 1];
+      sv1 = (T)ds[2 * F1];
+      sp1 = (T)ds[2 * F1 + 1];
     }
-    if (r < NB) {
-#pragma unroll
-      for (int cc = 0; cc < RM::NC; ++cc) {
-        const int c = RM::H * cc + half;
-        if (c < NB) {
-          T xv = xF[c];
-          if (ds) xv *= (c < NVEL ? sv : sp);
-          acc += B[c * NB + r] * xv;
-        }
-      }
-    }
+    block_terms<T, NB>(blk + (size_t)k * NB * NB, x + (size_t)F0 * NB, sv0, sp0, scaled, half, rr, acc);
+    block_terms<T, NB>(blk + (size_t)(k + 1) * NB * NB, x + (size_t)F1 * NB, sv1, sp1, scaled, half, rr, acc2);
   }
+  if (k < k1) {
+    const int F0 = cols[k];
+    T sv0 = (T)1, sp0 = (T)1;
+    if (scaled) {
+      sv0 = (T)ds[2 * F0];
+      sp0 = (T)ds[2 * F0 + 1];
+    }
+    block_terms<T, NB>(blk + (size_t)k * NB * NB, x + (size_t)F0 * NB, sv0, sp0, scaled, half, rr, acc);
+  }
+  acc += acc2;
   if constexpr (RM::H == 2) acc += __shfl_xor(acc, 32);
   return acc;
 }

@@ -5,11 +5,37 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "../../include/ldgs.h"
 
 namespace ldgs {
+
+// Allocator whose resize leaves new entries uninitialised: the operator
+// arrays (gigabytes on fine grids) are written by parallel loops, and a
+// zero fill first would touch every page from one thread.
+template <class T>
+struct UninitAlloc : std::allocator<T> {
+  UninitAlloc() = default;
+  template <class U>
+  UninitAlloc(const UninitAlloc<U>&) noexcept {}
+  template <class U>
+  struct rebind {
+    using other = UninitAlloc<U>;
+  };
+  template <class U>
+  void construct(U* p) noexcept(std::is_nothrow_default_constructible<U>::value) {
+    ::new ((void*)p) U;
+  }
+  template <class U, class... A>
+  void construct(U* p, A&&... a) {
+    ::new ((void*)p) U(std::forward<A>(a)...);
+  }
+};
+using BigVec = std::vector<double, UninitAlloc<double>>;
 
 // Square block-sparse matrix with nq x nq blocks (row-major within a block);
 // rows keep their columns sorted.
@@ -36,8 +62,8 @@ struct ImpLevel {
   SBM M, Mmu, G[2], Et, E;
   // Stokes operator, element-major nb x nb blocks, column-major in a block
   std::vector<int> rowptr, cols;
-  std::vector<double> blk;
-  std::vector<double> inv;          // [NE][nb*nb] column-major
+  BigVec blk;
+  BigVec inv;                       // [NE][nb*nb] column-major
   std::vector<double> dscale;       // [NE][2] (alpha, beta) or empty
   int ncol = 0;
   std::vector<int> colour;

@@ -105,6 +105,7 @@ _SIGS = {
     "ldgs_project_kernel": ([_P, _P]),
     "ldgs_level_info": ([_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "ldgs_level_elements": ([_P, C.c_int, C.POINTER(C.c_int64)]),
+    "ldgs_level_blocks": ([_P, C.c_int, C.POINTER(C.c_int64)]),
     "ldgs_level_shared_inverse": ([_P, C.c_int, C.POINTER(C.c_int)]),
     "ldgs_level_smooth_colour": ([_P, C.c_int, C.c_int, _P, _P]),
     "ldgs_level_residual_restrict": ([_P, C.c_int, _P, _P, _P]),
@@ -160,7 +161,7 @@ def _np_eval(fn, ncomp, dim):
 def _field(obj, dim, keep):
     """ldgs_field from a coefficient object with ``kind`` and ``params()``."""
     kind = {"const": FIELD_CONST, "sinsin": FIELD_SINSIN, "lognormal_rff": FIELD_LOGNORMAL_RFF,
-            "phase": FIELD_PHASE_CONST}.get(getattr(obj, "kind", None), FIELD_CALLBACK)
+            "phase": FIELD_PHASE_CONST, "circle": FIELD_PHASE_CONST}.get(getattr(obj, "kind", None), FIELD_CALLBACK)
     f = Field()
     f.kind = kind
     if kind == FIELD_CALLBACK:
@@ -432,6 +433,11 @@ class Context:
         ne = C.c_int64()
         self._check(_lib.ldgs_level_elements(self._h, level, C.byref(ne)))
         return ne.value
+
+    def level_blocks(self, level):
+        nbk = C.c_int64()
+        self._check(_lib.ldgs_level_blocks(self._h, level, C.byref(nbk)))
+        return nbk.value
 
     def level_shared_inverse(self, level):
         v = C.c_int()
