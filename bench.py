@@ -190,31 +190,38 @@ def bench_circle(args):
             log(f"{label}: FGMRES {info['iters']} iterations, relres {rel:.2e}, {tt:.3f} s")
         return tt / args.steps, its / args.steps, rel
 
-    # the finest colour pass: one sweep of all colours between two events
-    def pass_time(reps=4):
+    # the finest colour passes: HIP event pairs on the library's stream around
+    # whole finest sweeps of two V-cycles (12 sweeps)
+    def pass_time():
         ctx.set_vprec(V_FP64)
         x = torch.zeros_like(b0)
-        ctx.level_smooth_colour(0, 0, b0, x)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            for c in range(ncol):
-                ctx.level_smooth_colour(0, c, b0, x)
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) * 1e-3 / (reps * ncol)
+        ctx.profile(1)
+        for _ in range(2):
+            ctx.vcycle(b0, x)
+        ms, launches = ctx.profile_read()
+        ctx.profile(0)
+        return ms * 1e-3 / max(launches, 1), launches
 
     tc64 = cycle_time(V_FP64)
     tc32 = cycle_time(V_FP32)
     log(f"V-cycle FP64 {tc64 * 1e3:.2f} ms, FP32 {tc32 * 1e3:.2f} ms")
     t64, it64, rel64 = solve(V_FP64, "FP64")
     t32, it32, rel32 = solve(V_FP32, "FP32")
-    tp = pass_time()
+    tp, launches = pass_time()
     nb = prob.nb
     bytes_pass = ((nblk + ne[0]) * nb * nb * 8 + 3 * ne[0] * nb * 8) / ncol
     achieved = bytes_pass / tp / 1e9
     value = ndof * it64 / t64            # FGMRES: one V-cycle per iteration
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"traffic_bsr_colour_c4_n{prob.n}_p{prob.p}_fp64.json")
+    if os.path.exists(tfile):
+        # counters are valid only for the kernel source they were taken on
+        import hashlib
+        with open(tfile) as fh:
+            tj = json.load(fh)
+        with open(os.path.join(ROOT, "paper_1911_05888_amd", "csrc", "implicit.hip"), "rb") as fh:
+            if tj.get("implicit_hip_sha1") == hashlib.sha1(fh.read()).hexdigest():
+                traffic = tj.get("bytes_per_launch")
     line = dict(
         metric="V-cycle DOF/s + wall time to 1e-10 rel. residual, plain FP64 vs mixed/learned",
         value=value, unit="DOF/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=t64 * 1e3,
@@ -227,9 +234,9 @@ def bench_circle(args):
                     fp32=dict(time_to_tol_s=t32, iters=it32, relres=rel32, vcycle_s=tc32,
                               vcycle_dof_per_s=ndof / tc32)),
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                      traffic=None, kernel=f"k_bsr_colour<double,{nb}> (finest level)", avg_launch_us=tp * 1e6,
-                      algorithmic_bytes_per_launch=bytes_pass,
-                      timing="torch events around 4 sweeps of finest colour passes (library stream joined)"),
+                      traffic=traffic, kernel=f"k_bsr_colour<double,{nb}> (finest level)", avg_launch_us=tp * 1e6,
+                      algorithmic_bytes_per_launch=bytes_pass, launches=launches,
+                      timing="event pairs on the library's stream around whole finest sweeps of two V-cycles"),
     )
     ctx.close()
     if not args.no_cpu_baseline:
@@ -283,6 +290,14 @@ def main():
         sys.exit(2)
 
     if args.workload == "c4":
+        if args.calibrate_copy:
+            import torch
+            src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
         return bench_circle(args)
     import torch
     from paper_1911_05888_amd import Context, V_FP64, V_FP32, V_FP32_BF16BLK, STATIONARY, IR, GMRES, FGMRES

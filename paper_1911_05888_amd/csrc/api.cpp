@@ -1056,6 +1056,27 @@ void imp_colour(ldgs_ctx* c, int l, int col, const T* b, T* x) {
                             A::inv(D), b, x));
 }
 
+// sweeps of colour passes on level l; on the finest level with pass timing
+// on, every prof-th sweep is bracketed by an event pair
+template <typename T>
+void imp_smooth(ldgs_ctx* c, int l, const T* b, T* x, int sweeps) {
+  const int ncol = (int)c->idev[l].elems.size();
+  for (int s = 0; s < sweeps; ++s) {
+    const bool timed = c->prof > 0 && l == 0 && (c->prof_count++ % c->prof) == 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+      e0 = next_event(c);
+      e1 = next_event(c);
+      HIPCHK(hipEventRecord(e0, c->stream));
+    }
+    for (int col = 0; col < ncol; ++col) imp_colour<T>(c, l, col, b, x);
+    if (timed) {
+      HIPCHK(hipEventRecord(e1, c->stream));
+      c->prof_ev.push_back({e0, e1, ncol});
+    }
+  }
+}
+
 template <typename T>
 void imp_cycle(ldgs_ctx* c, int l, const T* b, T* x, bool zero_x) {
   using A = ImpArrays<T>;
@@ -1067,16 +1088,13 @@ void imp_cycle(ldgs_ctx* c, int l, const T* b, T* x, bool zero_x) {
   ldgs_ctx::ImpDev& D = c->idev[l];
   ldgs_ctx::ImpDev& C = c->idev[l + 1];
   const int nb = c->imp->nb;
-  const int ncol = (int)D.elems.size();
   if (zero_x) LCHK(launch_fill<T>(c->stream, D.NE * nb, (T)0, x));
-  for (int s = 0; s < c->P.nu1; ++s)
-    for (int col = 0; col < ncol; ++col) imp_colour<T>(c, l, col, b, x);
+  imp_smooth<T>(c, l, b, x, c->P.nu1);
   LCHK(launch_bsr_residual<T>(c->stream, nb, D.NE, D.rowptr, D.cols, A::blk(D), b, x, A::r(D), nullptr));
   LCHK(launch_bsr_restrict<T>(c->stream, nb, C.NE, C.kid_ptr, C.kids, A::I(D), A::r(D), A::b(C)));
   imp_cycle<T>(c, l + 1, A::b(C), A::x(C), true);
   LCHK(launch_bsr_prolong<T>(c->stream, nb, D.NE, D.parent, A::I(D), A::x(C), x));
-  for (int s = 0; s < c->P.nu2; ++s)
-    for (int col = 0; col < ncol; ++col) imp_colour<T>(c, l, col, b, x);
+  imp_smooth<T>(c, l, b, x, c->P.nu2);
 }
 
 // V-cycle on level l; zero_x: x is taken as zero on entry (the coarse levels'
@@ -2200,10 +2218,6 @@ ldgs_status ldgs_gmres_rho(ldgs_ctx* ctx, const double* x0, double reduction, in
 
 // ---- profiling -------------------------------------------------------------
 ldgs_status ldgs_profile(ldgs_ctx* ctx, int enable) {
-  if (ctx && ctx->imp) {
-    ctx->err = "no pass timing on implicitly defined meshes";
-    return LDGS_E_UNSUPPORTED;
-  }
   if (!ctx) return LDGS_E_ARG;
   ctx->prof = enable > 0 ? enable : 0;
   ctx->prof_count = 0;

@@ -10,8 +10,9 @@
 // so that every load instruction reads two whole columns (2 nb contiguous
 // values), each lane accumulating one row; the halves are summed with one
 // cross-half shuffle.  The row's blocks are the dominant bytes (about seven
-// blocks of nb^2 values per element for the viscous-stress stencil); x of the
-// neighbours is read as broadcasts through the caches.
+// blocks of nb^2 values per element for the viscous-stress stencil); the
+// neighbours' x vectors are staged in LDS with coalesced loads and read back
+// as broadcasts.
 #include <hip/hip_runtime.h>
 
 #include "implicit.hpp"
@@ -27,61 +28,57 @@ struct RowMap {
 
 // sum_F A_EF s_F x_F for row entry r of element E (valid in lanes r < NB of
 // every half); s_F = (alpha, beta)-type column scaling when ds != nullptr.
-// Blocks are taken two at a time, all their loads issued before the
-// multiply-adds, so that a wavefront keeps two blocks' columns in flight.
+// The x vectors of up to KS blocks of the row are staged in LDS (coalesced
+// loads of whole vectors, the scaling applied there), then the blocks are
+// streamed two at a time with all their loads issued before the
+// multiply-adds; x is read back from LDS as broadcasts.
+constexpr int KS = 8;
+
 template <typename T, int NB>
-__device__ __forceinline__ void block_terms(const T* __restrict__ B, const T* __restrict__ xF, T sv, T sp,
-                                            bool scaled, int half, int r, T& acc) {
+__device__ __forceinline__ void block_terms(const T* __restrict__ B, const T* __restrict__ xs, int half, int r,
+                                            T& acc) {
   using RM = RowMap<NB>;
-  constexpr int NVEL = 2 * NB / 3;
-  T a[RM::NC], xv[RM::NC];
+  T a[RM::NC];
 #pragma unroll
   for (int cc = 0; cc < RM::NC; ++cc) {
     const int c = RM::H * cc + half;
-    const bool in = c < NB;
-    a[cc] = in ? B[c * NB + r] : (T)0;
-    xv[cc] = in ? xF[c] : (T)0;
+    a[cc] = c < NB ? B[c * NB + r] : (T)0;
   }
 #pragma unroll
   for (int cc = 0; cc < RM::NC; ++cc) {
     const int c = RM::H * cc + half;
-    const T s = scaled ? (c < NVEL ? sv : sp) : (T)1;
-    acc += a[cc] * (xv[cc] * s);
+    if (c < NB) acc += a[cc] * xs[c];
   }
 }
 
 template <typename T, int NB>
 __device__ __forceinline__ T block_row(const int* __restrict__ rowptr, const int* __restrict__ cols,
                                        const T* __restrict__ blk, const T* __restrict__ x, int E, int lane,
-                                       const double* __restrict__ ds) {
+                                       const double* __restrict__ ds, T (*xs)[NB]) {
   using RM = RowMap<NB>;
+  constexpr int NVEL = 2 * NB / 3;
   const int half = RM::H == 2 ? (lane >> 5) : 0;
   const int r = RM::H == 2 ? (lane & 31) : lane;
   const int rr = r < NB ? r : NB - 1;        // idle lanes read a valid row and discard it
   T acc = (T)0, acc2 = (T)0;
   const int k0 = rowptr[E], k1 = rowptr[E + 1];
-  const bool scaled = ds != nullptr;
-  int k = k0;
-  for (; k + 1 < k1; k += 2) {
-    const int F0 = cols[k], F1 = cols[k + 1];
-    T sv0 = (T)1, sp0 = (T)1, sv1 = (T)1, sp1 = (T)1;
-    if (scaled) {
-      sv0 = (T)ds[2 * F0];
-      sp0 = (T)ds[2 * F0 + 1];
-      sv1 = (T)ds[2 * F1];
-      sp1 = (T)ds[2 * F1 + 1];
+  for (int kb = k0; kb < k1; kb += KS) {
+    const int kn = min(KS, k1 - kb);
+    for (int t = lane; t < kn * NB; t += 64) {
+      const int jb = t / NB, c = t - jb * NB;
+      const int F = cols[kb + jb];
+      T v = x[(size_t)F * NB + c];
+      if (ds) v *= (T)ds[2 * F + (c < NVEL ? 0 : 1)];
+      xs[jb][c] = v;
     }
-    block_terms<T, NB>(blk + (size_t)k * NB * NB, x + (size_t)F0 * NB, sv0, sp0, scaled, half, rr, acc);
-    block_terms<T, NB>(blk + (size_t)(k + 1) * NB * NB, x + (size_t)F1 * NB, sv1, sp1, scaled, half, rr, acc2);
-  }
-  if (k < k1) {
-    const int F0 = cols[k];
-    T sv0 = (T)1, sp0 = (T)1;
-    if (scaled) {
-      sv0 = (T)ds[2 * F0];
-      sp0 = (T)ds[2 * F0 + 1];
+    __syncthreads();
+    int jb = 0;
+    for (; jb + 1 < kn; jb += 2) {
+      block_terms<T, NB>(blk + (size_t)(kb + jb) * NB * NB, xs[jb], half, rr, acc);
+      block_terms<T, NB>(blk + (size_t)(kb + jb + 1) * NB * NB, xs[jb + 1], half, rr, acc2);
     }
-    block_terms<T, NB>(blk + (size_t)k * NB * NB, x + (size_t)F0 * NB, sv0, sp0, scaled, half, rr, acc);
+    if (jb < kn) block_terms<T, NB>(blk + (size_t)(kb + jb) * NB * NB, xs[jb], half, rr, acc);
+    __syncthreads();
   }
   acc += acc2;
   if constexpr (RM::H == 2) acc += __shfl_xor(acc, 32);
@@ -99,7 +96,8 @@ __global__ __launch_bounds__(64) void k_bsr_colour(int nelem, const int* __restr
   const int lane = threadIdx.x;
   const int E = elems[idx];
   __shared__ T rv[NB];
-  const T ax = block_row<T, NB>(rowptr, cols, blk, x, E, lane, nullptr);
+  __shared__ T xs[KS][NB];
+  const T ax = block_row<T, NB>(rowptr, cols, blk, x, E, lane, nullptr, xs);
   if (lane < NB) rv[lane] = b[(size_t)E * NB + lane] - ax;
   __syncthreads();
   const int half = RM::H == 2 ? (lane >> 5) : 0;
@@ -128,7 +126,8 @@ __global__ __launch_bounds__(64) void k_bsr_residual(int ne, const int* __restri
   const int E = blockIdx.x;
   if (E >= ne) return;
   const int lane = threadIdx.x;
-  T ax = block_row<T, NB>(rowptr, cols, blk, x, E, lane, ds);
+  __shared__ T xs[KS][NB];
+  T ax = block_row<T, NB>(rowptr, cols, blk, x, E, lane, ds, xs);
   if (lane < NB) {
     if (ds) ax *= (T)ds[2 * E + (lane < NVEL ? 0 : 1)];
     out[(size_t)E * NB + lane] = b ? b[(size_t)E * NB + lane] - ax : ax;
