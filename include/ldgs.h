@@ -93,8 +93,10 @@ typedef enum {
 
 /* Level set describing the phases.  NONE: one phase.  BOX: phase 1 is the
  * open box (params[0], params[1])^d, phase 2 its complement; box faces must
- * lie on element faces of the coarsest grid.  CIRCLE (2D, steady, Dirichlet
- * walls): phase 1 is the disk |x - levelset_centre| < params[0], phase 2 the
+ * lie on element faces of the coarsest grid.  CIRCLE (2D, Dirichlet walls;
+ * steady, or unsteady (delta > 0) with a density constant per phase, the
+ * pressure penalty of eq. (taugeneral) and Algorithm 3's coarsening): phase 1
+ * is the disk |x - levelset_centre| < params[0], phase 2 the
  * rest of the square; the circle cuts the grid's cells and the mesh is an
  * implicitly defined one (section 5, "Curved domain geometry"): cut cells
  * carry quadrature of their own (q_cut Gauss points per piece), pieces below
@@ -103,7 +105,7 @@ typedef enum {
  * tau_u_intra_C (appendix A), coarse levels agglomerate same-phase elements
  * (section 3, "Mesh hierarchy") and every level is held as explicit element
  * blocks, smoothed in greedy colour order.  Only the FP64 and FP32 V-cycles
- * are built; the learned correction and the GMRES rate are not available. */
+ * are built; the learned correction is not available. */
 typedef enum { LDGS_LEVELSET_NONE = 0, LDGS_LEVELSET_BOX = 1, LDGS_LEVELSET_CIRCLE = 2 } ldgs_levelset_kind;
 
 /* Batched host callback: evaluate at n points x (n x d, row-major).  phase[i]

@@ -64,8 +64,8 @@ def _fb(w, coef, Trow, Tcol):
 
 class ImplicitAssembly:
     def __init__(self, prob, mesh: ImplicitMesh):
-        if prob.dim != 2 or prob.unsteady or any(b != "dirichlet" for b in prob.bc):
-            raise ValueError("implicitly defined meshes: 2D steady problems with Dirichlet walls")
+        if prob.dim != 2 or any(b != "dirichlet" for b in prob.bc):
+            raise ValueError("implicitly defined meshes: 2D problems with Dirichlet walls")
         self.prob, self.mesh = prob, mesh
         self.nq = mesh.nq
         self.h = mesh.h
@@ -137,12 +137,28 @@ class ImplicitAssembly:
                 self._jump(acc, f, prob.tau_u_intra_C * prob.p * mu_m / h, Tm, Tp)
         return acc.csr()
 
-    def pressure_penalty(self):
+    def pressure_penalty(self, which="net"):
+        """eq. (eop) on intraphase faces: tau h / mu (eq. taueqn), or for
+        unsteady problems eq. (taugeneral) ("net") and its two limits "mu"
+        (tau h / mu) and "rho" (tau_0 delta / (h rho)), coarsened separately
+        by Algorithm 3."""
         prob, h = self.prob, self.h
         acc = _Acc(self.mesh.NE, self.nq)
+        chi = self.mesh.chi()
         for f, (Tm, Tp, mu_m, mu_p) in zip(self.mesh.faces, self.trace):
-            if f.kind == 0:
-                self._jump(acc, f, prob.tau * h / mu_m, Tm, Tp)
+            if f.kind != 0:
+                continue
+            t_mu = prob.tau * h / mu_m
+            if prob.unsteady:
+                rho = prob.rho.value(f.X, np.full(f.w.size, chi[f.minus]))
+                t_rho = prob.tau0 * prob.delta / (h * rho)
+            if which == "mu" or not prob.unsteady:
+                tau = t_mu
+            elif which == "rho":
+                tau = t_rho
+            else:
+                tau = 1.0 / (h * rho / (prob.tau0 * prob.delta) + mu_m / (prob.tau * h))
+            self._jump(acc, f, tau, Tm, Tp)
         return acc.csr()
 
 
@@ -153,8 +169,13 @@ def implicit_mesh(prob):
 def implicit_fine_operators(prob, mesh=None):
     mesh = mesh or implicit_mesh(prob)
     fa = ImplicitAssembly(prob, mesh)
-    return dict(n=prob.n, h=mesh.h, mesh=mesh, asm=fa, M=fa.mass(), Mmu=fa.weighted_mass(prob.mu),
-                G=[fa.gradient(k) for k in range(2)], Et=fa.velocity_penalty(), E=fa.pressure_penalty())
+    ops = dict(n=prob.n, h=mesh.h, mesh=mesh, asm=fa, M=fa.mass(), Mmu=fa.weighted_mass(prob.mu),
+               G=[fa.gradient(k) for k in range(2)], Et=fa.velocity_penalty(), E=fa.pressure_penalty("net"))
+    if prob.unsteady:
+        ops["Mrho"] = fa.weighted_mass(prob.rho)
+        ops["Emu"] = fa.pressure_penalty("mu")
+        ops["Erho"] = fa.pressure_penalty("rho")
+    return ops
 
 
 # ---------------------------------------------------------------------------
@@ -277,7 +298,7 @@ def build_implicit_hierarchy(prob):
         if li > 0:
             cmesh, parent = coarsen_mesh(mesh)
             I = prolongation(mesh, cmesh, parent)
-            ops = coarsen_components(ops, I, nq, False)
+            ops = coarsen_components(ops, I, nq, prob.unsteady)
             ops.update(n=cmesh.n, h=cmesh.h, mesh=cmesh)
             mesh = cmesh
         lv = Level()
@@ -285,7 +306,7 @@ def build_implicit_hierarchy(prob):
         lv.NE = mesh.NE
         lv.ops = ops
         lv.mesh = mesh
-        A = stokes_system(ops, d, prob.gamma, nq)
+        A = stokes_system(ops, d, prob.gamma, nq, prob.delta if prob.unsteady else None)
         if prob.diag_scaling:
             mu_e = np.array([ops["Mmu"][E * nq, E * nq] for E in range(lv.NE)])
             dvec = np.empty(lv.NE * nb)

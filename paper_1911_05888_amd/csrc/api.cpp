@@ -301,8 +301,13 @@ void validate(const ldgs_problem& P) {
   if (nstress != 0 && nstress != P.dim)
     throw Fail{LDGS_E_UNSUPPORTED, "stress boundary conditions must be given on every axis"};
   if (P.levelset_kind == LDGS_LEVELSET_CIRCLE) {
-    if (P.dim != 2 || P.delta > 0.0 || P.bc[0] != LDGS_DIRICHLET || P.bc[1] != LDGS_DIRICHLET)
-      throw Fail{LDGS_E_UNSUPPORTED, "circle level sets: 2D steady problems with Dirichlet walls"};
+    if (P.dim != 2 || P.bc[0] != LDGS_DIRICHLET || P.bc[1] != LDGS_DIRICHLET)
+      throw Fail{LDGS_E_UNSUPPORTED, "circle level sets: 2D problems with Dirichlet walls"};
+    if (P.delta > 0.0 && P.rho.kind != LDGS_FIELD_CONST && P.rho.kind != LDGS_FIELD_PHASE_CONST)
+      throw Fail{LDGS_E_UNSUPPORTED, "circle level sets: density constant or constant per phase"};
+    if (P.delta > 0.0 && !(P.rho.params && P.rho.params[0] > 0 &&
+                           (P.rho.kind == LDGS_FIELD_CONST || P.rho.params[1] > 0)))
+      throw Fail{LDGS_E_ARG, "rho must be positive"};
     if (!(P.levelset_params[0] > 0.0)) throw Fail{LDGS_E_ARG, "circle radius must be positive"};
     if (P.vprec == LDGS_V_FP32_BF16BLK || (P.build_precisions & 4))
       throw Fail{LDGS_E_UNSUPPORTED, "BF16-stored blocks are not built on implicitly defined meshes"};
@@ -311,7 +316,7 @@ void validate(const ldgs_problem& P) {
     if (P.levelset_kind != LDGS_LEVELSET_BOX) throw Fail{LDGS_E_ARG, "levelset_kind"};
     if (!P.host_only && P.dim != 2) throw Fail{LDGS_E_UNSUPPORTED, "interphase faces are supported in 2D"};
   }
-  if (P.delta > 0.0) {
+  if (P.delta > 0.0 && P.levelset_kind != LDGS_LEVELSET_CIRCLE) {
     if (P.rho.kind != LDGS_FIELD_CONST || P.mu.kind != LDGS_FIELD_CONST)
       throw Fail{LDGS_E_UNSUPPORTED, "unsteady problems need constant mu and rho"};
     if (!(P.rho.params && P.rho.params[0] > 0)) throw Fail{LDGS_E_ARG, "rho must be positive"};

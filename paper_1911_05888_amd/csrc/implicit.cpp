@@ -507,7 +507,37 @@ void coarsen_ops(const ImpHier& H, const ImpLevel& F, ImpLevel& C) {
   triple(rows_of(F.M), 1.0, C.M);
   triple(rows_of(F.Mmu), 1.0, C.Mmu);
   triple(rows_of(F.Et), 0.5, C.Et);
-  triple(rows_of(F.E), 2.0, C.E);
+  if (F.Mrho.NE > 0) {
+    // Algorithm 3: M_rho, the two pressure-penalty limits with factors 2 and
+    // 1/2, blended per element pair by eq. (Etimedep) (Frobenius norms)
+    triple(rows_of(F.Mrho), 1.0, C.Mrho);
+    triple(rows_of(F.Emu), 2.0, C.Emu);
+    triple(rows_of(F.Erho), 0.5, C.Erho);
+    C.E.init(NC, nq);
+    for (int64_t c = 0; c < NC; ++c) {
+      std::vector<int> cols = C.Emu.col[c];
+      cols.insert(cols.end(), C.Erho.col[c].begin(), C.Erho.col[c].end());
+      std::sort(cols.begin(), cols.end());
+      cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+      for (int f : cols) {
+        const double* a = C.Emu.get(c, f);
+        const double* b = C.Erho.get(c, f);
+        double na = 0.0, nb = 0.0;
+        for (size_t i = 0; i < bs; ++i) {
+          if (a) na += a[i] * a[i];
+          if (b) nb += b[i] * b[i];
+        }
+        na = std::sqrt(na);
+        nb = std::sqrt(nb);
+        if (na + nb == 0.0) continue;
+        const double wa = (nb / (na + nb)) * (nb / (na + nb)), wb = (na / (na + nb)) * (na / (na + nb));
+        double* o = C.E.at(c, f);
+        for (size_t i = 0; i < bs; ++i) o[i] = (a ? wa * a[i] : 0.0) + (b ? wb * b[i] : 0.0);
+      }
+    }
+  } else {
+    triple(rows_of(F.E), 2.0, C.E);
+  }
   std::vector<double> M2inv((size_t)NC * bs);
   for (int64_t c = 0; c < NC; ++c) {
     const double* m2 = C.M.get(c, (int)c);
@@ -636,6 +666,12 @@ void compose(const ldgs_problem& P, const ImpHier& H, ImpLevel& L) {
           addsub(L.G[i].col[e][k], 2, i, U.data(), -1.0);
         }
       for (size_t k = 0; k < L.E.col[e].size(); ++k) addsub(L.E.col[e][k], 2, 2, L.E.val[e].data() + k * bs, -1.0);
+      if (P.delta > 0.0) {
+        // eq. (timedep2): M_rho / delta on every velocity component
+        const double* Mr = L.Mrho.get(e, (int)e);
+        addsub((int)e, 0, 0, Mr, 1.0 / P.delta);
+        addsub((int)e, 1, 1, Mr, 1.0 / P.delta);
+      }
       for (int k = 0; k < nk; ++k) {
         const int f = L.cols[k0 + k];
         const double* B = R.data() + (size_t)k * nb * nb;
@@ -708,7 +744,6 @@ void colour_and_invert(ImpLevel& L, int nb) {
 
 void imp_build(const ldgs_problem& P, ImpHier& H) {
   if (P.dim != 2) fail("implicitly defined meshes are two-dimensional");
-  if (P.delta > 0.0) fail("implicitly defined meshes: steady problems only");
   if (P.bc[0] != LDGS_DIRICHLET || P.bc[1] != LDGS_DIRICHLET) fail("implicitly defined meshes: Dirichlet walls only");
   H.p = P.degree;
   H.m = H.p + 1;
@@ -943,6 +978,13 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
   L0.G[1].init(NE, nq);
   L0.Et.init(NE, nq);
   L0.E.init(NE, nq);
+  const bool unsteady = P.delta > 0.0;
+  if (unsteady) {
+    L0.Mrho.init(NE, nq);
+    L0.Emu.init(NE, nq);
+    L0.Erho.init(NE, nq);
+    for (int64_t e = 0; e < NE; ++e) L0.Mrho.at(e, (int)e);
+  }
   for (int64_t e = 0; e < NE; ++e) {
     L0.M.at(e, (int)e);
     L0.Mmu.at(e, (int)e);
@@ -960,6 +1002,9 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
     imp_basis(H, L0, e, Q, X, 0, D0.data());
     imp_basis(H, L0, e, Q, X, 1, D1.data());
     eval_field(P.mu, 2, Q, X, ph.data(), mu.data());
+    std::vector<double> rho(unsteady ? Q : 0);
+    if (unsteady) eval_field(P.rho, 2, Q, X, ph.data(), rho.data());
+    double* Mr = unsteady ? L0.Mrho.val[e].data() : nullptr;
     double* Me = L0.M.val[e].data();
     double* Mm = L0.Mmu.val[e].data();
     double* G0 = L0.G[0].val[e].data();
@@ -970,6 +1015,7 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
         for (int b = 0; b < nq; ++b) {
           Me[a * nq + b] += ba * B[(size_t)q * nq + b];
           Mm[a * nq + b] += ba * mu[q] * B[(size_t)q * nq + b];
+          if (Mr) Mr[a * nq + b] += ba * rho[q] * B[(size_t)q * nq + b];
           G0[a * nq + b] += ba * D0[(size_t)q * nq + b];
           G1[a * nq + b] += ba * D1[(size_t)q * nq + b];
         }
@@ -982,13 +1028,13 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
   // face blocks computed in parallel into per-face lists (matrix, row,
   // column, block), then added into the operators in face order
   struct FaceOut {
-    std::vector<int> key;        // (matrix, row, column) triples; matrices G_0, G_1, Et, E
+    std::vector<int> key;        // (matrix, row, column) triples; matrices G_0, G_1, Et, E, Emu, Erho
     std::vector<double> val;
   };
   const int64_t NF = (int64_t)H.faces.size();
   const int64_t CHUNK = 16384;
   std::vector<FaceOut> fout((size_t)std::min(NF, CHUNK));
-  SBM* mats[4] = {&L0.G[0], &L0.G[1], &L0.Et, &L0.E};
+  SBM* mats[6] = {&L0.G[0], &L0.G[1], &L0.Et, &L0.E, &L0.Emu, &L0.Erho};
   for (int64_t f0 = 0; f0 < NF; f0 += CHUNK) {
   const int64_t f1 = std::min(NF, f0 + CHUNK);
 #pragma omp parallel for schedule(dynamic, 64)
@@ -1057,8 +1103,21 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
         for (int q = 0; q < Q; ++q) coef[q] = C0 * p * mum[q] * n;
         jump(2, coef);
       }
-      for (int q = 0; q < Q; ++q) coef[q] = tau * h / mum[q];
-      jump(3, coef);
+      if (!unsteady) {
+        for (int q = 0; q < Q; ++q) coef[q] = tau * h / mum[q];
+        jump(3, coef);
+      } else {
+        // eq. (taugeneral) on the fine level, and its two limits for Algorithm 3
+        std::vector<double> rhom(Q);
+        eval_field(P.rho, 2, Q, f.X.data(), phm.data(), rhom.data());
+        for (int q = 0; q < Q; ++q)
+          coef[q] = 1.0 / (h * rhom[q] / (P.tau0 * P.delta) + mum[q] / (tau * h));
+        jump(3, coef);
+        for (int q = 0; q < Q; ++q) coef[q] = tau * h / mum[q];
+        jump(4, coef);
+        for (int q = 0; q < Q; ++q) coef[q] = P.tau0 * P.delta / (h * rhom[q]);
+        jump(5, coef);
+      }
     }
   }
   for (int64_t fi = f0; fi < f1; ++fi) {

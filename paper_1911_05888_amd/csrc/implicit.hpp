@@ -60,6 +60,7 @@ struct ImpLevel {
   std::vector<double> area;
   // scalar operator components (Algorithm 2 carries them level to level)
   SBM M, Mmu, G[2], Et, E;
+  SBM Mrho, Emu, Erho;              // unsteady: rho-weighted mass, the two pressure-penalty limits
   // Stokes operator, element-major nb x nb blocks, column-major in a block
   std::vector<int> rowptr, cols;
   BigVec blk;

@@ -10,6 +10,7 @@ markdown table; run as
     python -m paper_1911_05888_amd.rho_study unsteady    # tau_0 of eq. (taugeneral) at Re ~ 1e4
     python -m paper_1911_05888_amd.rho_study viscosity   # smooth and log-normal viscosity, 3D
     python -m paper_1911_05888_amd.rho_study stress      # stress walls (sections 5.3, 5.4)
+    python -m paper_1911_05888_amd.rho_study implicit    # circular interface on implicitly defined meshes
 
 The problem data come from ``synth`` (closed forms and seeded fields).
 """
@@ -125,6 +126,30 @@ def stress():
         print(f"| {label} | " + " | ".join(vals) + " |", flush=True)
 
 
+def implicit():
+    """Implicitly defined meshes (section 5, curved geometry; section 6, the
+    multi-phase time-dependent test): the steady circular inclusion (mu 1e4 /
+    1) and the water and gas bubbles (rho 1 / 0.001, mu 1 / 0.0002, delta =
+    0.1 h), rho against n for p = 1, 2, 3."""
+    from synth import c4_circle, bubble_unsteady
+    ns = (16, 32, 64, 128, 256)
+    rows = []
+    for p in (1, 2, 3):
+        rows.append((f"steady inclusion, mu 1e4 / 1, p = {p}", lambda n, p=p: c4_circle(n=n, p=p, rhs="exact")))
+    for p in (1, 2, 3):
+        rows.append((f"water bubble in gas, p = {p}", lambda n, p=p: bubble_unsteady(n=n, p=p, water_inside=True)))
+        rows.append((f"gas bubble in water, p = {p}", lambda n, p=p: bubble_unsteady(n=n, p=p, water_inside=False)))
+    print("| implicitly defined mesh | " + " | ".join(f"n={n}" for n in ns) + " |")
+    print("|---|" + "---|" * len(ns))
+    for label, make in rows:
+        vals = []
+        for n in ns:
+            r, its, ok = rho_of(make(n))
+            vals.append(f"{r:.3f} ({its})" if ok else f"{r:.3f} (no 1e8 in {its})")
+        print(f"| {label} | " + " | ".join(vals) + " |", flush=True)
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "valley"
-    {"valley": valley, "refine": refine, "unsteady": unsteady, "viscosity": viscosity, "stress": stress}[which]()
+    {"valley": valley, "refine": refine, "unsteady": unsteady, "viscosity": viscosity, "stress": stress,
+     "implicit": implicit}[which]()

@@ -223,7 +223,7 @@ class ExactSolution:
     mu: object
     u: dict
     p: dict
-    rho_delta: float = 0.0      # rho / delta of eq. (timedep1) (constant rho); 0: steady
+    rho_delta: object = 0.0     # rho / delta of eq. (timedep1): a number, or {phase: value}; 0: steady
 
     def _phases(self, chi, n):
         if chi is None:
@@ -273,7 +273,8 @@ class ExactSolution:
                 for j in range(d):
                     acc += dmu[:, j] * (gu[:, i, j] + self.gamma * gu[:, j, i])
                     acc += mu * (Hu[:, i, j, j] + self.gamma * Hu[:, j, i, j])
-                out[:, i] = -acc + gp[:, i] + self.rho_delta * np.stack([q.value(y) for q in self.u[c]], axis=1)[:, i]
+                rd = self.rho_delta[c] if isinstance(self.rho_delta, dict) else self.rho_delta
+                out[:, i] = -acc + gp[:, i] + rd * np.stack([q.value(y) for q in self.u[c]], axis=1)[:, i]
             return out
         return self._per_phase(x, chi, f)
 

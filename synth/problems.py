@@ -222,3 +222,28 @@ def c4_circle(n=512, p=2, mu_in=1.0e4, mu_out=1.0, rhs="bubble", radius=0.3, q_c
                    bc=("dirichlet", "dirichlet"), mu=ph, phases=ph, coloring="greedy",
                    tau_u_inter_C=8.0, tau_u_intra_C=0.5, q_cut=q_cut, diag_scaling=True,
                    exact=exact, forcing=forcing)
+
+
+def bubble_unsteady(n=64, p=2, water_inside=True, rhs="exact", radius=0.3):
+    """The paper's multi-phase time-dependent test (section 6): a water bubble
+    in gas (or a gas bubble in water) of radius 0.3 centred in the unit
+    square on an implicitly defined mesh, rho 1 / 0.001 and mu 1 / 0.0002 for
+    water / gas, viscous-stress form, Dirichlet walls, delta = 0.1 h (h of the
+    finest grid), eq. (taugeneral) for the pressure penalty, (alpha, beta)
+    scaling.  rhs "exact": the paper's two-phase manufactured solution with
+    rho / delta u in its forcing and its jumps as interface data."""
+    water, gas = (1.0, 1.0), (0.001, 0.0002)          # (rho, mu)
+    inside, outside = (water, gas) if water_inside else (gas, water)
+    mu = CirclePhaseField(values=(inside[1], outside[1]), radius=radius)
+    rho = CirclePhaseField(values=(inside[0], outside[0]), radius=radius)
+    delta = 0.1 / n
+    exact = forcing = None
+    if rhs == "exact":
+        exact = make_exact_paper(2, 1, mu, phases=(1, 2), mu_chi={1: inside[1], 2: outside[1]})
+        exact.rho_delta = {1: inside[0] / delta, 2: outside[0] / delta}
+    else:
+        forcing = BubbleForcing(rho=(inside[0], outside[0]), kappa=1.0 / radius)
+    tag = "water" if water_inside else "gas"
+    return Problem(name=f"bubble_{tag}_n{n}_p{p}", dim=2, n=n, p=p, gamma=1, bc=("dirichlet", "dirichlet"),
+                   mu=mu, rho=rho, delta=delta, phases=mu, coloring="greedy", tau_u_inter_C=8.0,
+                   tau_u_intra_C=0.5, diag_scaling=True, exact=exact, forcing=forcing)

@@ -7,7 +7,7 @@ bubble data.  Element numbering is (host cell, phase) on both sides."""
 import numpy as np
 import pytest
 
-from synth import c4_circle
+from synth import c4_circle, bubble_unsteady
 
 pytestmark = pytest.mark.filterwarnings("ignore")
 
@@ -17,11 +17,16 @@ def _ldgs():
     return ldgs
 
 
-@pytest.mark.parametrize("n,rhs", [(16, "exact"), (32, "bubble")])
+@pytest.mark.parametrize("n,rhs", [(16, "exact"), (32, "bubble"), (16, "water"), (16, "gas")])
 def test_host_levels_match_oracle(n, rhs):
+    """(water / gas: the unsteady bubbles of section 6, with the rho-weighted
+    mass, eq. (taugeneral) and Algorithm 3's coarsening)"""
     from oracle.implicit_assemble import build_implicit_hierarchy, implicit_rhs
     ldgs = _ldgs()
-    prob = c4_circle(n=n, p=2, rhs=rhs)
+    if rhs in ("water", "gas"):
+        prob = bubble_unsteady(n=n, p=2, water_inside=rhs == "water")
+    else:
+        prob = c4_circle(n=n, p=2, rhs=rhs)
     H = build_implicit_hierarchy(prob)
     ctx = ldgs.Context(prob, host_only=True)
     assert ctx.n_levels == len(H.levels)

@@ -12,7 +12,7 @@ history as in test_gpu_parity.py, 1e-11 max(1, rho_{k-1}, rho_k) + u F_k."""
 import numpy as np
 import pytest
 
-from synth import c4_circle
+from synth import c4_circle, bubble_unsteady
 
 pytestmark = pytest.mark.gpu
 
@@ -20,6 +20,9 @@ CASES = {
     "circle_n16_exact": lambda: c4_circle(n=16, p=2, rhs="exact"),
     "circle_n32_bubble": lambda: c4_circle(n=32, p=2, rhs="bubble"),
     "circle_n16_p1_exact": lambda: c4_circle(n=16, p=1, rhs="exact"),
+    # section 6: water / gas bubbles, unsteady (rho / delta, eq. taugeneral, Algorithm 3)
+    "water_bubble_n16": lambda: bubble_unsteady(n=16, p=2, water_inside=True),
+    "gas_bubble_n32_p3": lambda: bubble_unsteady(n=32, p=3, water_inside=False),
 }
 _cache = {}
 
@@ -181,7 +184,8 @@ def test_fp32_cycle_matches_float32_emulation():
 
 
 @pytest.mark.parametrize("name,vprec,outer", [("circle_n32_bubble", 0, 2), ("circle_n32_bubble", 1, 2),
-                                              ("circle_n32_bubble", 1, 1), ("circle_n16_exact", 0, 2)])
+                                              ("circle_n32_bubble", 1, 1), ("circle_n16_exact", 0, 2),
+                                              ("water_bubble_n16", 0, 2), ("gas_bubble_n32_p3", 1, 2)])
 def test_solve_to_tolerance_matches_oracle(name, vprec, outer):
     """FGMRES / IR with the FP64 or FP32 V-cycle reach 1e-10; the solution
     matches the oracle's FGMRES solution (same data) to 1e-6 (both are

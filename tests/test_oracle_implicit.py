@@ -263,3 +263,43 @@ def test_vcycle_contracts_on_implicit_mesh():
     assert rates.max() < 0.4
     x, h2 = S.fgmres(b, tol=1e-10, m=40, maxit=60)
     assert h2[-1] <= 1e-10 and len(h2) - 1 <= 14
+
+
+@pytest.mark.parametrize("water", [True, False])
+def test_bubble_orders_and_rate(water):
+    """Section 6, multi-phase time-dependent test: water (gas) bubble in gas
+    (water), rho 1 / 0.001, mu 1 / 0.0002, delta = 0.1 h.  The paper states
+    velocity order p + 1 in the maximum norm and pressure p + 1/2 in L2; the
+    manufactured solution carries rho / delta u in its forcing per phase.
+    The V-cycle contracts."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    from synth import bubble_unsteady
+    from oracle.implicit_assemble import (implicit_fine_operators, implicit_rhs, implicit_solution_errors,
+                                          build_implicit_hierarchy)
+    from oracle.assemble import stokes_system
+    from oracle.solvers import Solver
+    errs = []
+    for n in (8, 16, 32):
+        prob = bubble_unsteady(n=n, p=2, water_inside=water)
+        ops = implicit_fine_operators(prob)
+        mesh = ops["mesh"]
+        A = stokes_system(ops, 2, 1, mesh.nq, prob.delta)
+        b = implicit_rhs(prob, ops)
+        K = np.zeros(A.shape[0])
+        K[np.arange(mesh.NE) * 27 + 18] = np.sqrt([e.area for e in mesh.elements])
+        K /= np.linalg.norm(K)
+        assert np.abs(A @ K).max() <= 1e-12 * abs(A).max()
+        Ab = sp.bmat([[A, sp.csr_matrix(K[:, None])], [sp.csr_matrix(K[None, :]), None]]).tocsc()
+        x = spl.spsolve(Ab, np.concatenate([b, [0.0]]))[:-1]
+        errs.append(implicit_solution_errors(prob, mesh, x))
+    o = [{k: np.log2(a[k] / c[k]) for k in a} for a, c in zip(errs, errs[1:])]
+    print(errs, o)
+    for oo in o:
+        assert oo["u_l2"] >= 2.9 and oo["u_max"] >= 2.6
+    assert o[-1]["p_l2"] >= 2.4
+    H = build_implicit_hierarchy(bubble_unsteady(n=16, p=2, water_inside=water))
+    S = Solver(H)
+    bb = H.project_kernel(np.random.default_rng(2).standard_normal(H.fine.A.shape[0]))
+    x, hist = S.stationary(bb, maxit=10)
+    assert (hist[3:] / hist[2:-1]).max() < 0.4
