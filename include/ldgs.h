@@ -106,7 +106,17 @@ typedef enum {
  * (section 3, "Mesh hierarchy") and every level is held as explicit element
  * blocks, smoothed in greedy colour order.  Only the FP64 and FP32 V-cycles
  * are built; the learned correction is not available. */
-typedef enum { LDGS_LEVELSET_NONE = 0, LDGS_LEVELSET_BOX = 1, LDGS_LEVELSET_CIRCLE = 2 } ldgs_levelset_kind;
+/* DISK: the domain itself is the disk |x - levelset_centre| < params[0]
+ * inside the unit square (a curved domain, section 5): the mesh is the
+ * implicitly defined one of CIRCLE without phase 2, and the circle is a
+ * velocity Dirichlet boundary (data from g_dirichlet at its points, normal
+ * pointing out of the disk); one phase, the same restrictions as CIRCLE. */
+typedef enum {
+  LDGS_LEVELSET_NONE = 0,
+  LDGS_LEVELSET_BOX = 1,
+  LDGS_LEVELSET_CIRCLE = 2,
+  LDGS_LEVELSET_DISK = 3
+} ldgs_levelset_kind;
 
 /* Batched host callback: evaluate at n points x (n x d, row-major).  phase[i]
  * is the phase (1 or 2) of the element owning point i; normal (n x d) is the

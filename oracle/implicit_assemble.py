@@ -163,7 +163,8 @@ class ImplicitAssembly:
 
 
 def implicit_mesh(prob):
-    return ImplicitMesh(prob.n, prob.p, prob.phases, prob.q_op, prob.q_cut)
+    return ImplicitMesh(prob.n, prob.p, prob.phases, prob.q_op, prob.q_cut,
+                        void_outside=getattr(prob.phases, "void_outside", False))
 
 
 def implicit_fine_operators(prob, mesh=None):

@@ -101,10 +101,15 @@ class MeshLevel:
 
 
 class ImplicitMesh(MeshLevel):
-    """The finest level: cut cells, merging, faces."""
+    """The finest level: cut cells, merging, faces.  With ``void_outside``
+    (a curved domain: section 5, "Curved domain geometry") phase 2 is not
+    part of the domain: its pieces are dropped and the interface becomes a
+    Dirichlet wall of the phase-1 elements, normal pointing out of the
+    domain."""
 
-    def __init__(self, n, p, ls, q_full, q_cut):
+    def __init__(self, n, p, ls, q_full, q_cut, void_outside=False):
         self.ls = ls
+        self.void_outside = void_outside
         h = 1.0 / n
         self.n, self.h = n, h
         self.q_full, self.q_cut = q_full, q_cut
@@ -120,7 +125,7 @@ class ImplicitMesh(MeshLevel):
                 mn, mx = ls.box_range(lo, hi)
                 if mn < 0.0 < mx:
                     r = cut_box_rules(ls, lo, hi, q_cut)
-                    for chi in (1, 2):
+                    for chi in ((1,) if void_outside else (1, 2)):
                         X, w = r["vol"][chi]
                         if w.size and w.sum() > 0.0:
                             pieces[(c, chi)] = (X, w)
@@ -128,6 +133,8 @@ class ImplicitMesh(MeshLevel):
                     self.surf[c] = r["surf"]
                 else:
                     chi = 1 if mx <= 0.0 else 2
+                    if chi == 2 and void_outside:
+                        continue
                     pieces[(c, chi)] = ((np.array([i0, i1])[None, :] + tp) * h, tw * h * h)
         self.pieces = pieces
         frac = {key: w.sum() / (h * h) for key, (X, w) in pieces.items()}
@@ -216,7 +223,7 @@ class ImplicitMesh(MeshLevel):
             for m in range(n + 1):
                 for io in range(n):
                     rules = self._edge_rules(axis, m, io)
-                    for chi in (1, 2):
+                    for chi in ((1,) if self.void_outside else (1, 2)):
                         X, w = rules[chi]
                         if w.size == 0:
                             continue
@@ -245,7 +252,10 @@ class ImplicitMesh(MeshLevel):
             X, w, nrm = self.surf[c]
             if w.size == 0:
                 continue
-            faces.append(Face(1, self.elem_of[(c, 1)], self.elem_of[(c, 2)], X, w, nrm))
+            if self.void_outside:
+                faces.append(Face(2, self.elem_of[(c, 1)], -1, X, w, nrm))
+            else:
+                faces.append(Face(1, self.elem_of[(c, 1)], self.elem_of[(c, 2)], X, w, nrm))
         return faces
 
 

@@ -276,7 +276,7 @@ void fill_defaults(ldgs_problem& P) {
   if (!(P.tau > 0)) P.tau = (P.form ? tab_vs : tab_std)[P.dim - 2][P.degree - 1];
   if (!(P.tau0 > 0)) P.tau0 = 0.5 * P.degree;
   if (!(P.tau_u_bdry_C > 0)) P.tau_u_bdry_C = 10.0;
-  if (!(P.tau_u_inter_C > 0)) P.tau_u_inter_C = P.levelset_kind == LDGS_LEVELSET_CIRCLE ? 8.0 : 3.0;
+  if (!(P.tau_u_inter_C > 0)) P.tau_u_inter_C = (P.levelset_kind == LDGS_LEVELSET_CIRCLE || P.levelset_kind == LDGS_LEVELSET_DISK) ? 8.0 : 3.0;
   if (P.q_cut <= 0) P.q_cut = 8;
   if (P.nu1 <= 0) P.nu1 = 3;
   if (P.nu2 <= 0) P.nu2 = 3;
@@ -300,7 +300,7 @@ void validate(const ldgs_problem& P) {
   }
   if (nstress != 0 && nstress != P.dim)
     throw Fail{LDGS_E_UNSUPPORTED, "stress boundary conditions must be given on every axis"};
-  if (P.levelset_kind == LDGS_LEVELSET_CIRCLE) {
+  if (P.levelset_kind == LDGS_LEVELSET_CIRCLE || P.levelset_kind == LDGS_LEVELSET_DISK) {
     if (P.dim != 2 || P.bc[0] != LDGS_DIRICHLET || P.bc[1] != LDGS_DIRICHLET)
       throw Fail{LDGS_E_UNSUPPORTED, "circle level sets: 2D problems with Dirichlet walls"};
     if (P.delta > 0.0 && P.rho.kind != LDGS_FIELD_CONST && P.rho.kind != LDGS_FIELD_PHASE_CONST)
@@ -316,7 +316,7 @@ void validate(const ldgs_problem& P) {
     if (P.levelset_kind != LDGS_LEVELSET_BOX) throw Fail{LDGS_E_ARG, "levelset_kind"};
     if (!P.host_only && P.dim != 2) throw Fail{LDGS_E_UNSUPPORTED, "interphase faces are supported in 2D"};
   }
-  if (P.delta > 0.0 && P.levelset_kind != LDGS_LEVELSET_CIRCLE) {
+  if (P.delta > 0.0 && !(P.levelset_kind == LDGS_LEVELSET_CIRCLE || P.levelset_kind == LDGS_LEVELSET_DISK)) {
     if (P.rho.kind != LDGS_FIELD_CONST || P.mu.kind != LDGS_FIELD_CONST)
       throw Fail{LDGS_E_UNSUPPORTED, "unsteady problems need constant mu and rho"};
     if (!(P.rho.params && P.rho.params[0] > 0)) throw Fail{LDGS_E_ARG, "rho must be positive"};
@@ -1565,7 +1565,7 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
       std::fprintf(stderr, "[ldgs setup] %-28s %8.3f s\n", what, std::chrono::duration<double>(now - tmark).count());
       tmark = now;
     };
-    if (P.levelset_kind == LDGS_LEVELSET_CIRCLE) {
+    if (P.levelset_kind == LDGS_LEVELSET_CIRCLE || P.levelset_kind == LDGS_LEVELSET_DISK) {
       // implicitly defined mesh: explicit element blocks on every level
       c->k0 = 1;
       c->imp.reset(new ImpHier());

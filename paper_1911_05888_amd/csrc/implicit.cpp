@@ -754,6 +754,8 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
   H.cy = P.levelset_centre[1];
   if (!(H.r > 0.0)) fail("circle radius must be positive");
   const Circle ls{{H.cx, H.cy}, H.r};
+  // a curved domain (the disk alone): phase 2 is not part of the domain
+  const int nphase = P.levelset_kind == LDGS_LEVELSET_DISK ? 1 : 2;
   // LDGS_SETUP_TIMING=1: wall time of each phase on stderr
   const bool timing = std::getenv("LDGS_SETUP_TIMING") && std::atoi(std::getenv("LDGS_SETUP_TIMING"));
   auto tmark = std::chrono::steady_clock::now();
@@ -786,13 +788,14 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
       if (mn < 0.0 && 0.0 < mx) {
         BoxRules br;
         cut_box(ls, lo, hi, q_cut, gc, wc, br);
-        for (int chi = 0; chi < 2; ++chi)
+        for (int chi = 0; chi < nphase; ++chi)
           if (!br.vol[chi].w.empty() && br.vol[chi].sum() > 0.0) F.piece[2 * c + chi] = br.vol[chi];
         F.cut[c] = 1;
         F.surf_of[c] = (int)F.surf.size();
         F.surf.push_back(std::move(br));
       } else {
         const int chi = mx <= 0.0 ? 0 : 1;
+        if (chi >= nphase) continue;      // outside a curved domain
         Rule& R = F.piece[2 * c + chi];
         for (int b = 0; b < q_full; ++b)
           for (int a = 0; a < q_full; ++a) R.add((i0 + gf[a]) * h, (i1 + gf[b]) * h, wf[a] * wf[b] * h * h);
@@ -913,7 +916,7 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
       for (int io = 0; io < n; ++io) {
         Rule er[2];
         edge_rules(ls, F, axis, mp, io, q_full, q_cut, gf, wf, gc, wc, er);
-        for (int chi = 0; chi < 2; ++chi) {
+        for (int chi = 0; chi < nphase; ++chi) {
           if (er[chi].w.empty()) continue;
           int64_t lo_c = -1, hi_c = -1;
           int ij[2];
@@ -960,10 +963,17 @@ void imp_build(const ldgs_problem& P, ImpHier& H) {
     const BoxRules& br = F.surf[F.surf_of[c]];
     if (br.surf.w.empty()) continue;
     ImpFace f;
-    f.kind = 1;
     f.minus = F.elem_of[2 * c];
-    f.plus = F.elem_of[2 * c + 1];
-    if (f.minus < 0 || f.plus < 0) fail("interface piece without two elements");
+    if (nphase == 1) {
+      // the boundary of a curved domain: a Dirichlet wall of the inside element
+      f.kind = 2;
+      f.plus = -1;
+      if (f.minus < 0) fail("boundary piece without an element");
+    } else {
+      f.kind = 1;
+      f.plus = F.elem_of[2 * c + 1];
+      if (f.minus < 0 || f.plus < 0) fail("interface piece without two elements");
+    }
     f.X = br.surf.X;
     f.w = br.surf.w;
     f.nrm = br.nrm;

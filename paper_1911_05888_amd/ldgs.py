@@ -32,7 +32,7 @@ COLOR_AUTO, COLOR_RED_BLACK, COLOR_PARITY, COLOR_MOD3 = 0, 1, 2, 3
 V_FP64, V_FP32, V_FP32_BF16BLK = 0, 1, 2
 STATIONARY, IR, FGMRES, GMRES = 0, 1, 2, 3
 FIELD_CONST, FIELD_SINSIN, FIELD_LOGNORMAL_RFF, FIELD_PHASE_CONST, FIELD_CALLBACK = range(5)
-LEVELSET_NONE, LEVELSET_BOX, LEVELSET_CIRCLE = 0, 1, 2
+LEVELSET_NONE, LEVELSET_BOX, LEVELSET_CIRCLE, LEVELSET_DISK = 0, 1, 2, 3
 NET_HIDDEN = 16          # hidden width of the learned correction network
 TRAIN_WORKSPACE_BYTES = 4 << 20   # workspace of ldgs_learned_train_noalloc (LDGS_TRAIN_WORKSPACE_BYTES)
 
@@ -214,7 +214,7 @@ def problem_struct(prob, vprec=V_FP64, build_precisions=0, host_only=False, stre
     s.delta = prob.delta if getattr(prob, "delta", None) else 0.0
     ph = getattr(prob, "phases", None)
     if ph is not None and getattr(ph, "kind", None) == "circle":
-        s.levelset_kind = LEVELSET_CIRCLE
+        s.levelset_kind = LEVELSET_DISK if getattr(ph, "void_outside", False) else LEVELSET_CIRCLE
         s.levelset_params[0] = ph.radius
         s.levelset_centre[0], s.levelset_centre[1] = ph.centre
         s.tau_u_intra_C = getattr(prob, "tau_u_intra_C", 0.0)

@@ -128,12 +128,15 @@ def stress():
 
 def implicit():
     """Implicitly defined meshes (section 5, curved geometry; section 6, the
-    multi-phase time-dependent test): the steady circular inclusion (mu 1e4 /
+    multi-phase time-dependent test): the disk domain (standard form, mu = 1,
+    Dirichlet data on the circle), the steady circular inclusion (mu 1e4 /
     1) and the water and gas bubbles (rho 1 / 0.001, mu 1 / 0.0002, delta =
     0.1 h), rho against n for p = 1, 2, 3."""
-    from synth import c4_circle, bubble_unsteady
+    from synth import c4_circle, bubble_unsteady, disk_domain
     ns = (16, 32, 64, 128, 256)
     rows = []
+    for p in (2, 3):
+        rows.append((f"disk domain, standard form, p = {p}", lambda n, p=p: disk_domain(n=n, p=p, gamma=0)))
     for p in (1, 2, 3):
         rows.append((f"steady inclusion, mu 1e4 / 1, p = {p}", lambda n, p=p: c4_circle(n=n, p=p, rhs="exact")))
     for p in (1, 2, 3):

@@ -9,7 +9,7 @@ their own.
 """
 from .problems import (Problem, c1_periodic_standard, c2_dirichlet_varmu,
                        c3_unsteady_periodic, c4a_square_inclusion,
-                       c5_lognormal, stress_walls, c4_circle, bubble_unsteady, TAU_OPTIMAL, kernel_dimension)
+                       c5_lognormal, stress_walls, c4_circle, bubble_unsteady, disk_domain, TAU_OPTIMAL, kernel_dimension)
 from .fields import (ConstField, SinProductField, PhaseField, LogNormalRFF,
                      FourierForcing, CirclePhaseField, BubbleForcing,
                      make_exact_c1, make_exact_paper)
@@ -19,5 +19,5 @@ __all__ = [
     "c3_unsteady_periodic", "c4a_square_inclusion", "c5_lognormal", "stress_walls",
     "TAU_OPTIMAL", "kernel_dimension", "ConstField", "SinProductField",
     "PhaseField", "LogNormalRFF", "FourierForcing", "make_exact_c1",
-    "make_exact_paper", "c4_circle", "bubble_unsteady", "CirclePhaseField", "BubbleForcing",
+    "make_exact_paper", "c4_circle", "bubble_unsteady", "disk_domain", "CirclePhaseField", "BubbleForcing",
 ]

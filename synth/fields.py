@@ -421,6 +421,7 @@ class CirclePhaseField:
     centre: tuple = (0.5, 0.5)
     radius: float = 0.3
     kind: str = "circle"
+    void_outside: bool = False      # True: the domain is the disk alone (curved domain)
 
     def levelset(self, x):
         x = np.atleast_2d(x)

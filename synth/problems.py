@@ -247,3 +247,14 @@ def bubble_unsteady(n=64, p=2, water_inside=True, rhs="exact", radius=0.3):
     return Problem(name=f"bubble_{tag}_n{n}_p{p}", dim=2, n=n, p=p, gamma=1, bc=("dirichlet", "dirichlet"),
                    mu=mu, rho=rho, delta=delta, phases=mu, coloring="greedy", tau_u_inter_C=8.0,
                    tau_u_intra_C=0.5, diag_scaling=True, exact=exact, forcing=forcing)
+
+
+def disk_domain(n=64, p=2, gamma=0):
+    """The curved-domain test of section 5: Stokes on the unit-diameter disk
+    |x - (1/2, 1/2)| < 1/2 (the domain's boundary cuts the n x n background
+    grid of the unit square), mu = 1, velocity Dirichlet data on the circle
+    from the paper's manufactured solution, standard form by default."""
+    disk = CirclePhaseField(values=(1.0, 1.0), radius=0.5, void_outside=True)
+    mu = ConstField(1.0)
+    return Problem(name=f"disk_n{n}_p{p}_g{gamma}", dim=2, n=n, p=p, gamma=gamma, bc=("dirichlet", "dirichlet"),
+                   mu=mu, phases=disk, coloring="greedy", tau_u_intra_C=0.5, exact=make_exact_paper(2, gamma, mu))

@@ -7,7 +7,7 @@ bubble data.  Element numbering is (host cell, phase) on both sides."""
 import numpy as np
 import pytest
 
-from synth import c4_circle, bubble_unsteady
+from synth import c4_circle, bubble_unsteady, disk_domain
 
 pytestmark = pytest.mark.filterwarnings("ignore")
 
@@ -17,7 +17,8 @@ def _ldgs():
     return ldgs
 
 
-@pytest.mark.parametrize("n,rhs", [(16, "exact"), (32, "bubble"), (16, "water"), (16, "gas")])
+@pytest.mark.parametrize("n,rhs", [(16, "exact"), (32, "bubble"), (16, "water"), (16, "gas"), (16, "disk"),
+                                   (32, "disk_vs")])
 def test_host_levels_match_oracle(n, rhs):
     """(water / gas: the unsteady bubbles of section 6, with the rho-weighted
     mass, eq. (taugeneral) and Algorithm 3's coarsening)"""
@@ -25,6 +26,9 @@ def test_host_levels_match_oracle(n, rhs):
     ldgs = _ldgs()
     if rhs in ("water", "gas"):
         prob = bubble_unsteady(n=n, p=2, water_inside=rhs == "water")
+    elif rhs.startswith("disk"):
+        # the curved domain of section 5 (standard and viscous-stress form)
+        prob = disk_domain(n=n, p=2, gamma=1 if rhs == "disk_vs" else 0)
     else:
         prob = c4_circle(n=n, p=2, rhs=rhs)
     H = build_implicit_hierarchy(prob)

@@ -12,7 +12,7 @@ history as in test_gpu_parity.py, 1e-11 max(1, rho_{k-1}, rho_k) + u F_k."""
 import numpy as np
 import pytest
 
-from synth import c4_circle, bubble_unsteady
+from synth import c4_circle, bubble_unsteady, disk_domain
 
 pytestmark = pytest.mark.gpu
 
@@ -24,6 +24,9 @@ CASES = {
     "water_bubble_n16": lambda: bubble_unsteady(n=16, p=2, water_inside=True),
     "gas_bubble_n32": lambda: bubble_unsteady(n=32, p=2, water_inside=False),
     "gas_bubble_n32_p3": lambda: bubble_unsteady(n=32, p=3, water_inside=False),
+    # section 5, curved domain: the disk with Dirichlet data on the circle
+    "disk_n32_std": lambda: disk_domain(n=32, p=2, gamma=0),
+    "disk_n16_p3_vs": lambda: disk_domain(n=16, p=3, gamma=1),
 }
 # Stage-by-stage bars (1e-11 on operators) need the two sides' coarse
 # operators to agree to rounding.  With p = 3 and the gas bubble's contrasts
@@ -193,7 +196,8 @@ def test_fp32_cycle_matches_float32_emulation():
 
 @pytest.mark.parametrize("name,vprec,outer", [("circle_n32_bubble", 0, 2), ("circle_n32_bubble", 1, 2),
                                               ("circle_n32_bubble", 1, 1), ("circle_n16_exact", 0, 2),
-                                              ("water_bubble_n16", 0, 2), ("gas_bubble_n32_p3", 1, 2)])
+                                              ("water_bubble_n16", 0, 2), ("gas_bubble_n32_p3", 1, 2),
+                                              ("disk_n32_std", 0, 0), ("disk_n16_p3_vs", 1, 2)])
 def test_solve_to_tolerance_matches_oracle(name, vprec, outer):
     """FGMRES / IR with the FP64 or FP32 V-cycle reach 1e-10; the solution
     matches the oracle's FGMRES solution (same data) to 1e-6 (both are

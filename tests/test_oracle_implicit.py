@@ -303,3 +303,44 @@ def test_bubble_orders_and_rate(water):
     bb = H.project_kernel(np.random.default_rng(2).standard_normal(H.fine.A.shape[0]))
     x, hist = S.stationary(bb, maxit=10)
     assert (hist[3:] / hist[2:-1]).max() < 0.4
+
+
+def test_disk_domain_orders_and_rate():
+    """Section 5, curved domain: Stokes in standard form on the unit-diameter
+    disk, velocity Dirichlet data on the circle (the interface of the
+    implicit mesh becomes the domain's wall).  The disk's area is exact, the
+    constant pressure is in the kernel, velocity order p + 1 (L2), pressure
+    about p + 1/2 (L2); the V-cycle contracts (the paper: efficient rates)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    from synth import disk_domain
+    from oracle.implicit_assemble import (implicit_fine_operators, implicit_rhs, implicit_solution_errors,
+                                          build_implicit_hierarchy)
+    from oracle.assemble import stokes_system
+    from oracle.solvers import Solver
+    errs = []
+    for n in (8, 16, 32):
+        prob = disk_domain(n=n, p=2)
+        ops = implicit_fine_operators(prob)
+        mesh = ops["mesh"]
+        assert abs(sum(e.area for e in mesh.elements) - np.pi / 4) <= 1e-13
+        assert all(f.kind in (0, 2) for f in mesh.faces)
+        A = stokes_system(ops, 2, 0, mesh.nq)
+        b = implicit_rhs(prob, ops)
+        K = np.zeros(A.shape[0])
+        K[np.arange(mesh.NE) * 27 + 18] = np.sqrt([e.area for e in mesh.elements])
+        K /= np.linalg.norm(K)
+        assert np.abs(A @ K).max() <= 1e-15 * abs(A).max()
+        Ab = sp.bmat([[A, sp.csr_matrix(K[:, None])], [sp.csr_matrix(K[None, :]), None]]).tocsc()
+        x = spl.spsolve(Ab, np.concatenate([b, [0.0]]))[:-1]
+        errs.append(implicit_solution_errors(prob, mesh, x))
+    o = [{k: np.log2(a[k] / c[k]) for k in a} for a, c in zip(errs, errs[1:])]
+    print(errs, o)
+    for oo in o:
+        assert oo["u_l2"] >= 2.9 and oo["u_max"] >= 2.6
+        assert oo["p_l2"] >= 2.2
+    H = build_implicit_hierarchy(disk_domain(n=32, p=2))
+    S = Solver(H)
+    bb = H.project_kernel(np.random.default_rng(3).standard_normal(H.fine.A.shape[0]))
+    x, hist = S.stationary(bb, maxit=10)
+    assert (hist[3:] / hist[2:-1]).max() < 0.2
