@@ -1126,12 +1126,15 @@ void cycle(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x, bool zero_x) {
 // ~170 stream launches of a cycle; on the benchmark problem the GPU is the
 // slower side either way.  Any failure to capture falls back to direct
 // launches for the context's life.
-template <typename T>
-void run_cycle(ldgs_ctx* c, PrecStore<T>& S, int vp, T* b, T* x, bool zero_x) {
+// Runs launch() (one V-cycle's launches on c->stream) from a graph captured
+// on first use for the key (vp, zero_x); timed cycles (pass timing on) and
+// contexts whose capture failed launch directly.
+template <class Launch>
+void run_captured(ldgs_ctx* c, int vp, bool zero_x, Launch&& launch) {
   // timed cycles are launched directly: events recorded inside a captured
   // graph cannot be timed from the host
   if (!c->use_graph || c->prof > 0) {
-    cycle<T>(c, S, 0, b, x, zero_x);
+    launch();
     return;
   }
   ldgs_ctx::CycleGraph* g = nullptr;
@@ -1142,11 +1145,11 @@ void run_cycle(ldgs_ctx* c, PrecStore<T>& S, int vp, T* b, T* x, bool zero_x) {
     if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       (void)hipGetLastError();
       c->use_graph = false;
-      cycle<T>(c, S, 0, b, x, zero_x);
+      launch();
       return;
     }
     try {
-      cycle<T>(c, S, 0, b, x, zero_x);
+      launch();
     } catch (...) {
       (void)hipStreamEndCapture(c->stream, &graph);
       if (graph) (void)hipGraphDestroy(graph);
@@ -1160,13 +1163,18 @@ void run_cycle(ldgs_ctx* c, PrecStore<T>& S, int vp, T* b, T* x, bool zero_x) {
     if (!ok) {
       (void)hipGetLastError();
       c->use_graph = false;
-      cycle<T>(c, S, 0, b, x, zero_x);
+      launch();
       return;
     }
     c->graphs.push_back({vp, zero_x, exec});
     g = &c->graphs.back();
   }
   HIPCHK(hipGraphLaunch(g->exec, c->stream));
+}
+
+template <typename T>
+void run_cycle(ldgs_ctx* c, PrecStore<T>& S, int vp, T* b, T* x, bool zero_x) {
+  run_captured(c, vp, zero_x, [&]() { cycle<T>(c, S, 0, b, x, zero_x); });
 }
 
 const double* dscale0(ldgs_ctx* c) { return c->P.diag_scaling ? c->d_dscale0 : nullptr; }
@@ -1183,13 +1191,13 @@ void vcycle_user(ldgs_ctx* c, int vp, const double* b, double* x, bool zero_x, b
       if (!c->imp64) throw Fail{LDGS_E_UNSUPPORTED, "FP64 V-cycle not built"};
       LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, b, c->w_b, 0, 0)));
       if (!zero_x) LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, x, c->w_x, 1, 0)));
-      imp_cycle<double>(c, 0, c->w_b, c->w_x, zero_x);
+      run_captured(c, vp, zero_x, [&]() { imp_cycle<double>(c, 0, c->w_b, c->w_x, zero_x); });
       LCHK((launch_scale_cast<double, double>(c->stream, NE, nb, nvel, ds, c->w_x, x, 0, add ? 1 : 0)));
     } else if (vp == LDGS_V_FP32) {
       if (!c->imp32) throw Fail{LDGS_E_UNSUPPORTED, "FP32 V-cycle not built"};
       LCHK((launch_scale_cast<double, float>(c->stream, NE, nb, nvel, ds, b, c->w_b32, 0, 0)));
       if (!zero_x) LCHK((launch_scale_cast<double, float>(c->stream, NE, nb, nvel, ds, x, c->w_x32, 1, 0)));
-      imp_cycle<float>(c, 0, c->w_b32, c->w_x32, zero_x);
+      run_captured(c, vp, zero_x, [&]() { imp_cycle<float>(c, 0, c->w_b32, c->w_x32, zero_x); });
       LCHK((launch_scale_cast<float, double>(c->stream, NE, nb, nvel, ds, c->w_x32, x, 0, add ? 1 : 0)));
     } else {
       throw Fail{LDGS_E_UNSUPPORTED, "BF16-stored blocks are not built on implicitly defined meshes"};
@@ -1572,7 +1580,11 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
       try {
         imp_build(P, *c->imp);
       } catch (const std::runtime_error& ex) {
-        throw Fail{LDGS_E_ARG, ex.what()};
+        const std::string m = ex.what();
+        const ldgs_status st = m.find("colouring") != std::string::npos  ? LDGS_E_COLORING
+                               : m.find("singular") != std::string::npos ? LDGS_E_SINGULAR_BLOCK
+                                                                         : LDGS_E_ARG;
+        throw Fail{st, m};
       }
       phase("implicit hierarchy");
       c->Nc = c->imp->Nc;

@@ -713,6 +713,11 @@ void colour_and_invert(ImpLevel& L, int nb) {
     L.colour[e] = c;
     L.ncol = std::max(L.ncol, c + 1);
   }
+  // verified against the stored blocks: no block couples two elements of one
+  // colour (the colour pass updates a colour's elements simultaneously)
+  for (int64_t e = 0; e < NE; ++e)
+    for (int f : nbr[e])
+      if (L.colour[f] == L.colour[e]) fail("colouring couples two elements of one colour");
   L.elems.assign(L.ncol, {});
   for (int64_t e = 0; e < NE; ++e) L.elems[L.colour[e]].push_back((int)e);
   L.inv.resize((size_t)NE * nb * nb);                  // every block written below
