@@ -90,6 +90,16 @@ struct ldgs_ctx {
   // colour passes with per-element inverses as two launches (residual, then
   // the streamed product) on 3D levels; LDGS_SPLIT_PASS=0/1 overrides
   int split_pass = -1;
+  // split colour passes of at least overlap_min elements run in overlap_chunks
+  // chunks: the residuals of chunk k + 1 (LDS- and issue-bound) on the main
+  // stream beside the streamed product of chunk k (HBM-bound) on a second
+  // stream; elements of one colour do not couple, so the chunks' residuals do
+  // not read what the products write.  LDGS_OVERLAP=<chunks> (1: off) and
+  // LDGS_OVERLAP_MIN=<elements> override
+  int overlap_chunks = 8;
+  int64_t overlap_min = 131072;
+  hipStream_t side = nullptr;
+  hipEvent_t ov_fork = nullptr, ov_join = nullptr;
   // one-inverse FP32 updates of colours of at least mfma_min elements on the
   // matrix cores (0: never); LDGS_MFMA=0 disables, LDGS_MFMA_MIN overrides
   // the size (tests)
@@ -155,12 +165,16 @@ struct ldgs_ctx {
     // nothing may still use the storage when it goes back to its owner (a
     // caching allocator hands it out again at once)
     if (!host_only) (void)hipStreamSynchronize(stream);
+    if (side) (void)hipStreamSynchronize(side);
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : allocs) {
       if (P.dev_free) P.dev_free(p, P.alloc_user);
       else (void)hipFree(p);
     }
+    if (side) (void)hipStreamDestroy(side);
+    if (ov_fork) (void)hipEventDestroy(ov_fork);
+    if (ov_join) (void)hipEventDestroy(ov_join);
     if (join_in) (void)hipEventDestroy(join_in);
     if (join_out) (void)hipEventDestroy(join_out);
     if (stream_owned && stream) (void)hipStreamDestroy(stream);
@@ -869,9 +883,26 @@ void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* 
     LCHK(launch_shared_update<T>(c->stream, cnt, c->g.nb, pl.ainv_sh, pl.rbuf, pl.elems + o, x, 0, nullptr, 0,
                                  c->mfma_min));
   } else if (c->split_pass && pl.rbuf && !pl.view.iface) {
-    // residuals of the colour, then the streamed product with the inverses
-    LCHK(launch_colour_residual<T>(cfg, pl.view, c->tab, pl.elems + o, pcol, cnt, b, x, pl.rbuf));
-    LCHK(launch_apply_inverse<T>(cfg, pl.view.lgn, pl.elems + o, pcol, cnt, inv, pl.inv_kind, pl.rbuf, x));
+    if (c->side && c->overlap_chunks > 1 && cnt >= c->overlap_min) {
+      // chunk k's product on the side stream after chunk k's residuals, beside
+      // the residuals of chunk k + 1; the main stream waits for the last product
+      LaunchCfg cfg_side = cfg;
+      cfg_side.stream = c->side;
+      const int64_t ch = (cnt + c->overlap_chunks - 1) / c->overlap_chunks;
+      for (int64_t lo = 0; lo < cnt; lo += ch) {
+        const int64_t n = std::min(ch, cnt - lo);
+        LCHK(launch_colour_residual<T>(cfg, pl.view, c->tab, pl.elems + o, pcol, n, b, x, pl.rbuf, lo));
+        HIPCHK(hipEventRecord(c->ov_fork, c->stream));
+        HIPCHK(hipStreamWaitEvent(c->side, c->ov_fork, 0));
+        LCHK(launch_apply_inverse<T>(cfg_side, pl.view.lgn, pl.elems + o, pcol, n, inv, pl.inv_kind, pl.rbuf, x, lo));
+      }
+      HIPCHK(hipEventRecord(c->ov_join, c->side));
+      HIPCHK(hipStreamWaitEvent(c->stream, c->ov_join, 0));
+    } else {
+      // residuals of the colour, then the streamed product with the inverses
+      LCHK(launch_colour_residual<T>(cfg, pl.view, c->tab, pl.elems + o, pcol, cnt, b, x, pl.rbuf));
+      LCHK(launch_apply_inverse<T>(cfg, pl.view.lgn, pl.elems + o, pcol, cnt, inv, pl.inv_kind, pl.rbuf, x));
+    }
   } else
   // (split only large launches: on coarse levels the second launch would cost
   // more than the extended stencil)
@@ -1558,6 +1589,14 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
     if (const char* ds = std::getenv("LDGS_DEVICE_SETUP")) c->device_setup = std::strtol(ds, nullptr, 10) != 0;
     if (const char* sp = std::getenv("LDGS_SPLIT_PASS")) c->split_pass = std::strtol(sp, nullptr, 10) != 0;
     if (c->split_pass < 0) c->split_pass = P.dim == 3 ? 1 : 0;
+    if (const char* ov = std::getenv("LDGS_OVERLAP")) {
+      const long v = std::strtol(ov, nullptr, 10);
+      if (v >= 1 && v <= 64) c->overlap_chunks = (int)v;
+    }
+    if (const char* om = std::getenv("LDGS_OVERLAP_MIN")) {
+      const long v = std::strtol(om, nullptr, 10);
+      if (v >= 1) c->overlap_min = v;
+    }
     if (const char* mm = std::getenv("LDGS_MFMA_MIN")) {
       const long v = std::strtol(mm, nullptr, 10);
       if (v >= 1) c->mfma_min = v;
@@ -1643,6 +1682,11 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
         c->stream_owned = true;
         HIPCHK(hipEventCreateWithFlags(&c->join_in, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&c->join_out, hipEventDisableTiming));
+      }
+      if (c->split_pass && c->overlap_chunks > 1) {
+        HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&c->ov_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c->ov_join, hipEventDisableTiming));
       }
       int mask = (1 << P.vprec) | P.build_precisions;
       bool n64 = mask & 1, n32 = mask & 2, n16 = mask & 4;

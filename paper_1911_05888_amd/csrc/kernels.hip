@@ -1396,7 +1396,7 @@ __global__ __launch_bounds__(NT) void k_first_colour(int lgn, const int* __restr
 // LDS-bound kernel of its own) no longer holds the inverse's stream back, and
 // many elements' tiles are in flight per CU.
 template <typename T, typename TI, int D, int P>
-__global__ __launch_bounds__(64) void k_apply_inverse(int lgn, const int* __restrict__ elems, int pcol,
+__global__ __launch_bounds__(64) void k_apply_inverse(int lgn, const int* __restrict__ elems, int pcol, int ibase,
                                                       const TI* __restrict__ inv, const T* __restrict__ r,
                                                       T* __restrict__ x) {
   using S = Sz<D, P>;
@@ -1407,7 +1407,7 @@ __global__ __launch_bounds__(64) void k_apply_inverse(int lgn, const int* __rest
   __shared__ T part[2][16 * SP::TR];
   __shared__ T red[64 * SP::TR];
   const int lane = threadIdx.x;
-  const int idx = xcd_remap(blockIdx.x, gridDim.x);
+  const int idx = ibase + xcd_remap(blockIdx.x, gridDim.x);
   const int E = colour_elem<D>(idx, pcol, lgn, elems);
   const auto* Ai = reinterpret_cast<const typename SP::Word*>(inv + (size_t)idx * SP::ESTRIDE);
   sym_product_stream<T, TI, NB, WIN>(Ai, r + (size_t)idx * NB, res, part, red, lane);
@@ -1428,11 +1428,11 @@ __global__ __launch_bounds__(NT) void k_residual(DevLevel<T> lev, TabT<T> tab, c
 // E = elems[idx] (the first half of a colour pass with a shared inverse).
 template <typename T, int D, int P, int NT, bool IF>
 __global__ __launch_bounds__(NT) void k_colour_residual(DevLevel<T> lev, TabT<T> tab, const int* __restrict__ elems,
-                                                        int pcol, const T* __restrict__ b, const T* __restrict__ x,
-                                                        T* __restrict__ r) {
+                                                        int pcol, int ibase, const T* __restrict__ b,
+                                                        const T* __restrict__ x, T* __restrict__ r) {
   using S = Sz<D, P, IF>;
   Work<T, D, P, IF>& w = work_lds<T, D, P, IF>();
-  const int idx = xcd_remap(blockIdx.x, gridDim.x);
+  const int idx = ibase + xcd_remap(blockIdx.x, gridDim.x);
   element_operator<T, D, P, NT, IF>(lev, tab, colour_elem<D>(idx, pcol, lev.lgn, elems), x, b, 0, w);
   for (int t = threadIdx.x; t < S::NB; t += NT) r[(size_t)idx * S::NB + t] = w.res[t];
 }
@@ -2002,13 +2002,13 @@ int launch_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab
 
 template <typename T>
 int launch_colour_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const int* elems, int pcol,
-                           int64_t nelems, const T* b, const T* x, T* r) {
+                           int64_t nelems, const T* b, const T* x, T* r, int64_t ibase) {
   if (nelems <= 0) return 0;
   bool bad = false;
   hipStream_t st = (hipStream_t)c.stream;
   const TabT<T> tt = tab_of<T>(tab);
   if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt<D_, (int)sizeof(T)>(nelems, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_colour_residual<T, D_, P_, NT_, IF_>), dim3((unsigned)nelems), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
-                                                lev, tt, elems, pcol, b, x, r); }); })) bad = true; })) return 2;
+                                                lev, tt, elems, pcol, (int)ibase, b, x, r); }); })) bad = true; })) return 2;
   if (bad) return 2;
   return hip_ok();
 }
@@ -2089,7 +2089,7 @@ int launch_first_colour(const LaunchCfg& c, int lgn, const int* elems, int pcol,
 
 template <typename T>
 int launch_apply_inverse(const LaunchCfg& c, int lgn, const int* elems, int pcol, int64_t nelems, const void* inv,
-                         int inv_kind, const T* r, T* x) {
+                         int inv_kind, const T* r, T* x, int64_t ibase) {
   if (nelems <= 0) return 0;
   hipStream_t st = (hipStream_t)c.stream;
   auto go = [&](auto tag) {
@@ -2098,7 +2098,7 @@ int launch_apply_inverse(const LaunchCfg& c, int lgn, const int* elems, int pcol
       constexpr int D_ = decltype(Dc)::value;
       constexpr int P_ = decltype(Pc)::value;
       hipLaunchKernelGGL((k_apply_inverse<T, TI, D_, P_>), dim3((unsigned)nelems), dim3(64), 0, st, lgn, elems, pcol,
-                         (const TI*)inv, r, x);
+                         (int)ibase, (const TI*)inv, r, x);
     });
   };
   bool bad;
@@ -2305,9 +2305,9 @@ template int launch_residual_restrict<double>(const LaunchCfg&, const DevLevel<d
 template int launch_residual_restrict<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const float*,
                                              const float*, float*, float*);
 template int launch_colour_residual<double>(const LaunchCfg&, const DevLevel<double>&, const Tab1D&, const int*, int,
-                                            int64_t, const double*, const double*, double*);
+                                            int64_t, const double*, const double*, double*, int64_t);
 template int launch_colour_residual<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const int*, int,
-                                           int64_t, const float*, const float*, float*);
+                                           int64_t, const float*, const float*, float*, int64_t);
 template int launch_shared_update<double>(void*, int64_t, int, const double*, const double*, const int*, double*,
                                           int, const int*, int64_t, int64_t);
 template int launch_shared_update<float>(void*, int64_t, int, const float*, const float*, const int*, float*, int,
@@ -2315,9 +2315,9 @@ template int launch_shared_update<float>(void*, int64_t, int, const float*, cons
 template int launch_first_colour<double>(const LaunchCfg&, int, const int*, int, int64_t, const void*, int,
                                          const double*, double*, const int*, int64_t);
 template int launch_apply_inverse<double>(const LaunchCfg&, int, const int*, int, int64_t, const void*, int,
-                                          const double*, double*);
+                                          const double*, double*, int64_t);
 template int launch_apply_inverse<float>(const LaunchCfg&, int, const int*, int, int64_t, const void*, int,
-                                         const float*, float*);
+                                         const float*, float*, int64_t);
 template int launch_first_colour<float>(const LaunchCfg&, int, const int*, int, int64_t, const void*, int,
                                         const float*, float*, const int*, int64_t);
 template int launch_prolong_add<double>(const LaunchCfg&, int, const Tab1D&, const double*, double*);

@@ -141,9 +141,11 @@ int launch_residual_restrict(const LaunchCfg& c, const DevLevel<T>& lev, const T
 // elements into r (compact, [nelems][nb]), then x_E += Ainv r (Ainv k-major,
 // a[k nb + row], zero-padded to shared_inverse_rows(nb, sizeof(T)) rows)
 int shared_inverse_rows(int nb, int bytes);
+// ibase: the launch covers positions ibase .. ibase + nelems - 1 of the
+// listed elements (elems, or the parity colour pcol), r indexed by position
 template <typename T>
 int launch_colour_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const int* elems, int pcol,
-                           int64_t nelems, const T* b, const T* x, T* r);
+                           int64_t nelems, const T* b, const T* x, T* r, int64_t ibase = 0);
 // first != 0: the first pass from x = 0 (r is then b, read at the listed
 // elements; x_E is assigned and the nzero elements zl are set to zero);
 // FP32 products of colours of at least mfma_min elements (0: none) on the
@@ -158,10 +160,11 @@ template <typename T>
 int launch_first_colour(const LaunchCfg& c, int lgn, const int* elems, int pcol, int64_t nelems, const void* inv,
                         int inv_kind, const T* b, T* x, const int* zl, int64_t nzero);
 // x_E += Ainv_E r[idx] for the listed elements (per-element inverses, same
-// conventions as launch_smooth_colour; r compact as from launch_colour_residual)
+// conventions as launch_smooth_colour; r compact as from launch_colour_residual;
+// positions ibase .. ibase + nelems - 1, inv and r indexed by position)
 template <typename T>
 int launch_apply_inverse(const LaunchCfg& c, int lgn, const int* elems, int pcol, int64_t nelems, const void* inv,
-                         int inv_kind, const T* r, T* x);
+                         int inv_kind, const T* r, T* x, int64_t ibase = 0);
 template <typename T>
 int launch_prolong_add(const LaunchCfg& c, int n_fine, const Tab1D& tab, const T* xc, T* x);
 // y = z + sign * M x, M dense row-major FP64 N x N, z optional

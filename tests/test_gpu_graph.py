@@ -162,3 +162,45 @@ def test_graph_replays_on_implicit_meshes(name, monkeypatch):
         hists.append((np.asarray(info["history"]), x.cpu().numpy()))
     assert np.array_equal(hists[0][0], hists[1][0]) and np.array_equal(hists[0][1], hists[1][1])
     assert direct.graph_count() == 0 and graph.graph_count() >= 2
+
+
+@pytest.mark.parametrize("chunks", ["3", "8"])
+def test_overlapped_colour_passes_match_single_launches(chunks, monkeypatch):
+    """3D colour passes split into chunks (the residuals of chunk k + 1 on the
+    library's stream beside the product of chunk k on a second stream) give
+    the same iterates bit for bit as one residual launch and one product
+    launch per colour, launched directly and replayed from graphs, in every
+    precision; colours of 512 elements into 3 or 8 chunks (a ragged last chunk
+    with 3)."""
+    import torch
+    from paper_1911_05888_amd import Context, V_FP64, V_FP32, V_FP32_BF16BLK
+    from synth import c5_lognormal
+    prob = c5_lognormal(n=16, p=2)
+    print(f"[overlap] c5_n16_p2 chunks={chunks}", flush=True)
+    ctxs = {}
+    for label, ov, graph in (("single", "1", "1"), ("direct", chunks, "0"), ("graph", chunks, "1")):
+        monkeypatch.setenv("LDGS_OVERLAP", ov)
+        monkeypatch.setenv("LDGS_OVERLAP_MIN", "1")
+        monkeypatch.setenv("LDGS_GRAPH", graph)
+        ctxs[label] = Context(prob, build_precisions=(1 << V_FP32) | (1 << V_FP32_BF16BLK))
+    rng = np.random.Generator(np.random.PCG64(11))
+    b_host = rng.standard_normal(ctxs["single"].ndof)
+    for vp in (V_FP64, V_FP32, V_FP32_BF16BLK):
+        seqs = {}
+        for label, ctx in ctxs.items():
+            ctx.set_vprec(vp)
+            b = torch.tensor(b_host, dtype=torch.float64, device="cuda")
+            x = torch.zeros_like(b)
+            seq = []
+            for it in range(3):
+                ctx.vcycle(b, x)
+                torch.cuda.synchronize()
+                seq.append(x.cpu().numpy().copy())
+                y = torch.zeros_like(x)
+                ctx.level_apply(0, x, y)
+                torch.cuda.synchronize()
+            seqs[label] = seq
+        for label in ("direct", "graph"):
+            for it in range(3):
+                assert np.array_equal(seqs["single"][it], seqs[label][it]), (chunks, vp, label, it)
+    assert ctxs["direct"].graph_count() == 0 and ctxs["graph"].graph_count() == 3
