@@ -99,8 +99,46 @@ def cpu_baseline(make, n_sample, cycles=4):
                        f"value, one thread for single_thread_value")
 
 
+def cycle_latency(prob, args, cycles=2000):
+    """Microseconds per V-cycle on a latency-bound grid: back-to-back cycles
+    from the current x (no host synchronisation between them), replayed from
+    the captured graph and launched directly, FP64 and FP32."""
+    import torch
+    from paper_1911_05888_amd import Context, V_FP64, V_FP32
+    out = {}
+    saved = os.environ.get("LDGS_GRAPH")
+    try:
+        for label, flag in (("graph", "1"), ("direct", "0")):
+            os.environ["LDGS_GRAPH"] = flag
+            ctx = Context(prob, vprec=V_FP64, build_precisions=1 << V_FP32)
+            b = ctx.assemble_rhs(prob.rhs_source())
+            for vp, name in ((V_FP64, "fp64"), (V_FP32, "fp32")):
+                ctx.set_vprec(vp)
+                x = torch.zeros_like(b)
+                for _ in range(max(args.warmup, 20)):
+                    ctx.vcycle(b, x)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(cycles):
+                    ctx.vcycle(b, x)
+                torch.cuda.synchronize()
+                out[f"{name}_{label}_us_per_vcycle"] = (time.perf_counter() - t0) / cycles * 1e6
+            out[f"graphs_{label}"] = ctx.graph_count()
+            ctx.close()
+    finally:
+        if saved is None:
+            os.environ.pop("LDGS_GRAPH", None)
+        else:
+            os.environ["LDGS_GRAPH"] = saved
+    out["cycles"] = cycles
+    return out
+
+
 def make_problem(workload, n):
-    from synth import c2_dirichlet_varmu, c3_unsteady_periodic, c4a_square_inclusion, c4_circle, c5_lognormal
+    from synth import (c1_periodic_standard, c2_dirichlet_varmu, c3_unsteady_periodic, c4a_square_inclusion,
+                       c4_circle, c5_lognormal)
+    if workload == "c1":
+        return c1_periodic_standard(n=n or 16, p=2)
     if workload == "c4":
         return c4_circle(n=n or 512, p=2, rhs="bubble")
     if workload == "c2":
@@ -113,6 +151,10 @@ def make_problem(workload, n):
 
 
 DESCRIPTION = {
+    "c1": "2D steady standard-form Stokes, periodic unit square, {n}^2 elements, Q_2, mu = 1, closed-form "
+          "manufactured solution; V(2,2) to the 4x4 grid, red-black colouring; stationary (FP64) / iterative "
+          "refinement (FP32) to 1e-10; latency: microseconds per V-cycle replayed from a HIP graph and launched "
+          "directly",
     "c5": "3D viscous-stress Stokes, Dirichlet walls, {n}^3 elements, Q_2, log-normal viscosity (random Fourier "
           "features, seed 1001), b = A x* for the L2-projected manufactured solution; V(3,3), parity colouring; "
           "GMRES({m}) right-preconditioned by the V-cycle to 1e-10",
@@ -497,6 +539,10 @@ def main():
         if krylov:
             args.m = saved_m
 
+    if args.workload == "c1":
+        extras["latency"] = cycle_latency(prob, args)
+        log(f"latency: {extras['latency']}")
+
     achieved = bytes_method / t_pass / 1e9
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_smooth_colour_{args.workload}_n{n}_p{prob.p}_fp64.json")
@@ -528,7 +574,7 @@ def main():
                       timing="event pairs around whole finest sweeps of two V-cycles"),
     )
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(lambda m: make_problem(args.workload, m), 8 if prob.dim == 3 else 32)
+        line["cpu_baseline"] = cpu_baseline(lambda m: make_problem(args.workload, m), 8 if prob.dim == 3 else min(32, n))
     print(json.dumps(line), flush=True)
 
 
