@@ -100,6 +100,8 @@ struct ldgs_ctx {
   int64_t overlap_min = 131072;
   hipStream_t side = nullptr;
   hipEvent_t ov_fork = nullptr, ov_join = nullptr;
+  std::vector<hipEvent_t> ov_prod;   // end of each chunk's product (side stream)
+  bool ov_chain = true;              // chain the chunks across colours; LDGS_OVERLAP_CHAIN=0 disables
   // one-inverse FP32 updates of colours of at least mfma_min elements on the
   // matrix cores (0: never); LDGS_MFMA=0 disables, LDGS_MFMA_MIN overrides
   // the size (tests)
@@ -173,6 +175,7 @@ struct ldgs_ctx {
       else (void)hipFree(p);
     }
     if (side) (void)hipStreamDestroy(side);
+    for (hipEvent_t e : ov_prod) (void)hipEventDestroy(e);
     if (ov_fork) (void)hipEventDestroy(ov_fork);
     if (ov_join) (void)hipEventDestroy(ov_join);
     if (join_in) (void)hipEventDestroy(join_in);
@@ -868,8 +871,30 @@ T* rf_scratch(ldgs_ctx* c) {
   else return c->w_rf32;
 }
 
+// Chunked colour passes of one level chained across colours (and sweeps):
+// while the products of one colour's last chunks still run on the side
+// stream, the next colour's first residual chunks start on the main stream.
+// pending: the side stream holds products the main stream has not joined.
+struct OvChain {
+  bool pending = false;
+  int l = -1;
+  const void* x = nullptr;
+  int64_t ch = 0;
+  int64_t nch = 0;
+};
+
+// the main stream waits for every product queued on the side stream
+void ov_join(ldgs_ctx* c, OvChain* chain) {
+  if (!chain || !chain->pending) return;
+  HIPCHK(hipEventRecord(c->ov_join, c->side));
+  HIPCHK(hipStreamWaitEvent(c->stream, c->ov_join, 0));
+  chain->pending = false;
+}
+
+// chain: null for a single pass (joined at its end); else the state of the
+// passes before it, left pending for the caller to join with ov_join
 template <typename T>
-void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* x) {
+void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* x, OvChain* chain = nullptr) {
   LaunchCfg cfg{c->g.d, c->g.p, c->stream, c->small_grid};
   PrecLevel<T>& pl = S.lv[l];
   const size_t esz = pl.inv_kind == 0 ? 8 : (pl.inv_kind == 1 ? 4 : 2);
@@ -877,27 +902,60 @@ void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* 
   const void* inv = (const char*)pl.inv + o * pl.inv_stride * esz;
   const int64_t nreg = pl.col_reg.empty() ? cnt : pl.col_reg[col];
   const int pcol = pl.parity ? col : -1;
+  const bool chunked = !pl.ainv_sh && c->split_pass && pl.rbuf && !pl.view.iface && c->side &&
+                       c->overlap_chunks > 1 && cnt >= c->overlap_min;
+  if (!chunked) ov_join(c, chain);
   if (pl.ainv_sh) {
     // one inverse for the level: residuals of the colour, then the shared update
     LCHK(launch_colour_residual<T>(cfg, pl.view, c->tab, pl.elems + o, pcol, cnt, b, x, pl.rbuf));
     LCHK(launch_shared_update<T>(c->stream, cnt, c->g.nb, pl.ainv_sh, pl.rbuf, pl.elems + o, x, 0, nullptr, 0,
                                  c->mfma_min));
   } else if (c->split_pass && pl.rbuf && !pl.view.iface) {
-    if (c->side && c->overlap_chunks > 1 && cnt >= c->overlap_min) {
+    if (chunked) {
       // chunk k's product on the side stream after chunk k's residuals, beside
-      // the residuals of chunk k + 1; the main stream waits for the last product
+      // the residuals of chunk k + 1
       LaunchCfg cfg_side = cfg;
       cfg_side.stream = c->side;
       const int64_t ch = (cnt + c->overlap_chunks - 1) / c->overlap_chunks;
-      for (int64_t lo = 0; lo < cnt; lo += ch) {
-        const int64_t n = std::min(ch, cnt - lo);
+      const int64_t nch = (cnt + ch - 1) / ch;
+      // Chained after the previous colour's chunks (same level, x and chunk
+      // bounds; parity colours only): the residuals of chunk q read x of the
+      // previous colour only at positions within +-H of the chunk, H = 2 (n/2)^(d-1)
+      // (each half-grid coordinate of a stencil neighbour differs by at most
+      // one, or wraps on a periodic axis below the slowest), so they wait for
+      // that colour's products up to the chunk holding position (q+1) ch - 1 + H,
+      // all of them when the slowest axis is periodic.  Waiting for a later
+      // chunk also orders the previous colour's reads of r chunk q before
+      // this colour's residuals overwrite it (one side stream, in order).
+      const bool chained = chain && chain->pending && chain->l == l && chain->x == (const void*)x &&
+                           chain->ch == ch && chain->nch == nch && pcol >= 0;
+      if (chain && chain->pending && !chained) ov_join(c, chain);
+      const int64_t half = int64_t(1) << (pl.view.lgn - 1);
+      int64_t H = 2;
+      for (int k = 0; k + 1 < c->g.d; ++k) H *= half;
+      const bool wrap = c->P.bc[c->g.d - 1] == LDGS_PERIODIC;
+      for (int64_t q = 0; q < nch; ++q) {
+        const int64_t lo = q * ch, n = std::min(ch, cnt - lo);
+        if (chained) {
+          const int64_t j = wrap ? nch - 1 : std::min(nch - 1, (lo + ch - 1 + H) / ch);
+          HIPCHK(hipStreamWaitEvent(c->stream, c->ov_prod[j], 0));
+        }
         LCHK(launch_colour_residual<T>(cfg, pl.view, c->tab, pl.elems + o, pcol, n, b, x, pl.rbuf, lo));
         HIPCHK(hipEventRecord(c->ov_fork, c->stream));
         HIPCHK(hipStreamWaitEvent(c->side, c->ov_fork, 0));
         LCHK(launch_apply_inverse<T>(cfg_side, pl.view.lgn, pl.elems + o, pcol, n, inv, pl.inv_kind, pl.rbuf, x, lo));
+        HIPCHK(hipEventRecord(c->ov_prod[q], c->side));
       }
-      HIPCHK(hipEventRecord(c->ov_join, c->side));
-      HIPCHK(hipStreamWaitEvent(c->stream, c->ov_join, 0));
+      if (chain) {
+        chain->pending = true;
+        chain->l = l;
+        chain->x = (const void*)x;
+        chain->ch = ch;
+        chain->nch = nch;
+      } else {
+        HIPCHK(hipEventRecord(c->ov_join, c->side));
+        HIPCHK(hipStreamWaitEvent(c->stream, c->ov_join, 0));
+      }
     } else {
       // residuals of the colour, then the streamed product with the inverses
       LCHK(launch_colour_residual<T>(cfg, pl.view, c->tab, pl.elems + o, pcol, cnt, b, x, pl.rbuf));
@@ -941,6 +999,7 @@ template <typename T>
 void smooth(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x, int sweeps, bool zero_x = false) {
   if (zero_x && sweeps == 0) LCHK(launch_fill<T>(c->stream, c->levels[l].NE * c->g.nb, (T)0, x));
   const int ncol = c->levels[l].ncol;
+  OvChain chain;
   for (int s = 0; s < sweeps; ++s) {
     const bool first = zero_x && s == 0;
     // finest level, profiling on: every prof-th sweep whose passes all
@@ -948,19 +1007,27 @@ void smooth(ldgs_ctx* c, PrecStore<T>& S, int l, const T* b, T* x, int sweeps, b
     const bool timed = c->prof > 0 && l == 0 && !first && (c->prof_count++ % c->prof) == 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
+      // a timed sweep holds its own passes only
+      ov_join(c, &chain);
       e0 = next_event(c);
       e1 = next_event(c);
       HIPCHK(hipEventRecord(e0, c->stream));
     }
     for (int col = 0; col < ncol; ++col) {
-      if (first && col == 0) first_colour(c, S, l, b, x);
-      else smooth_colour(c, S, l, col, b, x);
+      if (first && col == 0) {
+        ov_join(c, &chain);
+        first_colour(c, S, l, b, x);
+      } else {
+        smooth_colour(c, S, l, col, b, x, c->ov_chain ? &chain : nullptr);
+      }
     }
     if (timed) {
+      ov_join(c, &chain);
       HIPCHK(hipEventRecord(e1, c->stream));
       c->prof_ev.push_back({e0, e1, ncol});
     }
   }
+  ov_join(c, &chain);
 }
 
 // Least-squares bottom solve x = A_c^+ b (footnote to the bottom solver):
@@ -1593,6 +1660,7 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
       const long v = std::strtol(ov, nullptr, 10);
       if (v >= 1 && v <= 64) c->overlap_chunks = (int)v;
     }
+    if (const char* oc = std::getenv("LDGS_OVERLAP_CHAIN")) c->ov_chain = std::strtol(oc, nullptr, 10) != 0;
     if (const char* om = std::getenv("LDGS_OVERLAP_MIN")) {
       const long v = std::strtol(om, nullptr, 10);
       if (v >= 1) c->overlap_min = v;
@@ -1687,6 +1755,8 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
         HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&c->ov_fork, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&c->ov_join, hipEventDisableTiming));
+        c->ov_prod.resize(c->overlap_chunks);
+        for (auto& e : c->ov_prod) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       }
       int mask = (1 << P.vprec) | P.build_precisions;
       bool n64 = mask & 1, n32 = mask & 2, n16 = mask & 4;

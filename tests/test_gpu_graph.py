@@ -164,25 +164,40 @@ def test_graph_replays_on_implicit_meshes(name, monkeypatch):
     assert direct.graph_count() == 0 and graph.graph_count() >= 2
 
 
-@pytest.mark.parametrize("chunks", ["3", "8"])
-def test_overlapped_colour_passes_match_single_launches(chunks, monkeypatch):
+OVERLAP_CASES = {
+    # Dirichlet walls: a chunk's residuals wait only for the previous
+    # colour's products up to the next chunk
+    "c5_n16_p2": lambda: __import__("synth").c5_lognormal(n=16, p=2),
+    # periodic on every axis, variable viscosity (per-element inverses): the
+    # slowest axis wraps, so every chunk waits for all previous products
+    "per3d_n16_p2_mu": lambda: Problem(name="per3d_n16_p2_mu", dim=3, n=16, p=2, gamma=1, bc=("periodic",) * 3,
+                                       mu=__import__("synth").SinProductField(1.0, 0.5, 1.0)),
+}
+
+
+@pytest.mark.parametrize("name,chunks", [("c5_n16_p2", "3"), ("c5_n16_p2", "8"), ("per3d_n16_p2_mu", "4")])
+def test_overlapped_colour_passes_match_single_launches(name, chunks, monkeypatch):
     """3D colour passes split into chunks (the residuals of chunk k + 1 on the
-    library's stream beside the product of chunk k on a second stream) give
-    the same iterates bit for bit as one residual launch and one product
-    launch per colour, launched directly and replayed from graphs, in every
-    precision; colours of 512 elements into 3 or 8 chunks (a ragged last chunk
-    with 3)."""
+    library's stream beside the product of chunk k on a second stream), with
+    and without chaining across colours (the next colour's first residual
+    chunks start while the last products still run), give the same iterates
+    bit for bit as one residual launch and one product launch per colour,
+    launched directly and replayed from graphs, in every precision; colours of
+    512 elements into 3, 4 or 8 chunks (a ragged last chunk with 3)."""
     import torch
     from paper_1911_05888_amd import Context, V_FP64, V_FP32, V_FP32_BF16BLK
-    from synth import c5_lognormal
-    prob = c5_lognormal(n=16, p=2)
-    print(f"[overlap] c5_n16_p2 chunks={chunks}", flush=True)
+    prob = OVERLAP_CASES[name]()
+    print(f"[overlap] {name} chunks={chunks}", flush=True)
     ctxs = {}
-    for label, ov, graph in (("single", "1", "1"), ("direct", chunks, "0"), ("graph", chunks, "1")):
+    for label, ov, chain, graph in (("single", "1", "1", "1"), ("direct", chunks, "0", "0"),
+                                    ("graph", chunks, "0", "1"), ("chained_direct", chunks, "1", "0"),
+                                    ("chained_graph", chunks, "1", "1")):
         monkeypatch.setenv("LDGS_OVERLAP", ov)
         monkeypatch.setenv("LDGS_OVERLAP_MIN", "1")
+        monkeypatch.setenv("LDGS_OVERLAP_CHAIN", chain)
         monkeypatch.setenv("LDGS_GRAPH", graph)
         ctxs[label] = Context(prob, build_precisions=(1 << V_FP32) | (1 << V_FP32_BF16BLK))
+    assert not ctxs["single"].level_shared_inverse(0)   # per-element inverses: the split pass
     rng = np.random.Generator(np.random.PCG64(11))
     b_host = rng.standard_normal(ctxs["single"].ndof)
     for vp in (V_FP64, V_FP32, V_FP32_BF16BLK):
@@ -190,6 +205,7 @@ def test_overlapped_colour_passes_match_single_launches(chunks, monkeypatch):
         for label, ctx in ctxs.items():
             ctx.set_vprec(vp)
             b = torch.tensor(b_host, dtype=torch.float64, device="cuda")
+            ctx.project_kernel(b)
             x = torch.zeros_like(b)
             seq = []
             for it in range(3):
@@ -200,7 +216,10 @@ def test_overlapped_colour_passes_match_single_launches(chunks, monkeypatch):
                 ctx.level_apply(0, x, y)
                 torch.cuda.synchronize()
             seqs[label] = seq
-        for label in ("direct", "graph"):
+        for label in ctxs:
             for it in range(3):
-                assert np.array_equal(seqs["single"][it], seqs[label][it]), (chunks, vp, label, it)
-    assert ctxs["direct"].graph_count() == 0 and ctxs["graph"].graph_count() == 3
+                assert np.array_equal(seqs["single"][it], seqs[label][it]), (name, chunks, vp, label, it)
+    for label in ("direct", "chained_direct"):
+        assert ctxs[label].graph_count() == 0
+    for label in ("graph", "chained_graph"):
+        assert ctxs[label].graph_count() == 3
