@@ -1547,6 +1547,31 @@ __global__ __launch_bounds__(SU_THREADS) void k_shared_update(int nelems, const 
 // and lane l receives rows 4 (l / 16) .. + 3 of column l % 16 of each 16 x 16
 // output tile.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// one 16 x 16 x 4 matrix-core step in the arithmetic type: A 16 x 4 (lane
+// i + 16 k holds A[i][k]) and B 4 x 16 (lane j + 16 k holds B[k][j]) in both;
+// the accumulator 16 x 16, lane j + 16 q holding four entries of column j:
+// rows 4 q .. 4 q + 3 in FP32, rows q, q + 4, q + 8, q + 12 in FP64 (row()
+// gives the row of entry v)
+template <typename T>
+struct MfmaStep;
+template <>
+struct MfmaStep<float> {
+  using Acc = f32x4;
+  static __device__ __forceinline__ Acc run(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
+};
+template <>
+struct MfmaStep<double> {
+  using Acc = f64x4;
+  static __device__ __forceinline__ Acc run(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int q, int v) { return q + 4 * v; }
+};
 template <int NB>
 struct MfmaSu {
   static constexpr int KP = (NB + 15) / 16 * 16;
@@ -1559,24 +1584,25 @@ struct MfmaSu {
   static constexpr int LDR = KP + 1;                 // LDS stride of one staged element
 };
 
-template <int NB>
-__global__ __launch_bounds__(256) void k_shared_update_mfma(int nelems, const float* __restrict__ ainv,
-                                                           const float* __restrict__ r,
-                                                           const int* __restrict__ elems, float* __restrict__ x,
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_shared_update_mfma(int nelems, const T* __restrict__ ainv,
+                                                           const T* __restrict__ r,
+                                                           const int* __restrict__ elems, T* __restrict__ x,
                                                            int first, const int* __restrict__ zl, int nzero) {
   using C = MfmaSu<NB>;
-  __shared__ float Rs[C::TN * C::LDR];
+  using M = MfmaStep<T>;
+  __shared__ T Rs[C::TN * C::LDR];
   __shared__ int Eo[C::TN];   // x offset of each staged element (-1 past the end)
   const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
   const int lr = l & 15, lg = l >> 4;
-  float a[C::MPW][C::KS];
+  T a[C::MPW][C::KS];
 #pragma unroll
   for (int mi = 0; mi < C::MPW; ++mi) {
     const int m = 16 * (wv + C::WAVES * mi) + lr;
 #pragma unroll
     for (int ks = 0; ks < C::KS; ++ks) {
       const int k = 4 * ks + lg;
-      a[mi][ks] = (m < NB && k < NB) ? ainv[k * NB + m] : 0.f;
+      a[mi][ks] = (m < NB && k < NB) ? ainv[k * NB + m] : (T)0;
     }
   }
   const int ntiles = (nelems + C::TN - 1) / C::TN;
@@ -1589,7 +1615,7 @@ __global__ __launch_bounds__(256) void k_shared_update_mfma(int nelems, const fl
     // all loads of the tile issued before any is stored (unrolled; masked
     // loads read r[0] and are discarded)
     constexpr int TOT = C::TN * C::KP, ITER = (TOT + 255) / 256;
-    float v[ITER];
+    T v[ITER];
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {
       const int i = tid + 256 * it;
@@ -1602,7 +1628,7 @@ __global__ __launch_bounds__(256) void k_shared_update_mfma(int nelems, const fl
     for (int it = 0; it < ITER; ++it) {
       const int i = tid + 256 * it;
       const int e = i / C::KP, k = i - e * C::KP;
-      if (i < TOT) Rs[e * C::LDR + k] = (e < cnt && k < NB) ? v[it] : 0.f;
+      if (i < TOT) Rs[e * C::LDR + k] = (e < cnt && k < NB) ? v[it] : (T)0;
     }
     int eoff[C::NSUB];
 #pragma unroll
@@ -1610,24 +1636,24 @@ __global__ __launch_bounds__(256) void k_shared_update_mfma(int nelems, const fl
     __syncthreads();
 #pragma unroll
     for (int sb = 0; sb < C::NSUB; ++sb) {
-      f32x4 acc[C::MPW];
+      typename M::Acc acc[C::MPW];
 #pragma unroll
-      for (int mi = 0; mi < C::MPW; ++mi) acc[mi] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int mi = 0; mi < C::MPW; ++mi) acc[mi] = typename M::Acc{0, 0, 0, 0};
 #pragma unroll
       for (int ks = 0; ks < C::KS; ++ks) {
-        const float bv = Rs[(16 * sb + lr) * C::LDR + 4 * ks + lg];
+        const T bv = Rs[(16 * sb + lr) * C::LDR + 4 * ks + lg];
 #pragma unroll
         for (int mi = 0; mi < C::MPW; ++mi)
-          acc[mi] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[mi][ks], bv, acc[mi], 0, 0, 0);
+          acc[mi] = M::run(a[mi][ks], bv, acc[mi]);
       }
       if (eoff[sb] >= 0) {
 #pragma unroll
         for (int mi = 0; mi < C::MPW; ++mi)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int m = 16 * (wv + C::WAVES * mi) + 4 * lg + i;
+            const int m = 16 * (wv + C::WAVES * mi) + M::row(lg, i);
             if (m < NB) {
-              float* xm = x + (size_t)eoff[sb] + m;
+              T* xm = x + (size_t)eoff[sb] + m;
               *xm = first ? acc[mi][i] : *xm + acc[mi][i];
             }
           }
@@ -1635,7 +1661,7 @@ __global__ __launch_bounds__(256) void k_shared_update_mfma(int nelems, const fl
     }
   }
   for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < (int64_t)nzero * NB; i += (int64_t)gridDim.x * 256)
-    x[(size_t)zl[i / NB] * NB + i % NB] = 0.f;
+    x[(size_t)zl[i / NB] * NB + i % NB] = (T)0;
 }
 
 // product of 1D injection entries, (P_o)[af][ac] for child offset bits o, from
@@ -2023,18 +2049,19 @@ static void shared_update_q(hipStream_t st, int64_t nelems, const T* ainv, const
                      elems, x, first, zl, (int)nzero);
 }
 // large colours (at least mfma_min elements; 0: never): the matrix cores in
-// FP32 (blocks up to 128), else 16 elements per thread from 8192 elements;
+// the arithmetic type, FP32 or FP64 (blocks up to 128), else 16 elements per
+// thread from 8192 elements;
 // small colours: 4 elements per thread (more work-groups, shorter chains:
 // small launches are latency bound)
 template <typename T, int NB>
 static void shared_update_nb(hipStream_t st, int64_t nelems, const T* ainv, const T* r, const int* elems, T* x,
                              int first, const int* zl, int64_t nzero, int64_t mfma_min) {
-  if constexpr (sizeof(T) == 4 && NB <= 128) {
+  if constexpr (NB <= 128) {
     if (mfma_min > 0 && nelems >= mfma_min) {
       int64_t g = (nelems + MfmaSu<NB>::TN - 1) / MfmaSu<NB>::TN;
       if (g > 1024) g = 1024;
-      hipLaunchKernelGGL((k_shared_update_mfma<NB>), dim3((unsigned)g), dim3(256), 0, st, (int)nelems, ainv, r, elems,
-                         x, first, zl, (int)nzero);
+      hipLaunchKernelGGL((k_shared_update_mfma<T, NB>), dim3((unsigned)g), dim3(256), 0, st, (int)nelems, ainv, r,
+                         elems, x, first, zl, (int)nzero);
       return;
     }
   }
