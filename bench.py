@@ -563,7 +563,8 @@ def main():
                     n=n, p=prob.p, dim=prob.dim, unknowns=ndof, levels=levels, colours=ncol, **extras),
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=achieved / HBM_PEAK_GBS, traffic=traffic,
-                      kernel=(f"k_colour_residual<double,{prob.dim},{prob.p}> + k_shared_update<double,"
+                      kernel=(f"k_colour_residual<double,{prob.dim},{prob.p}> + "
+                              f"{'k_shared_update_mfma' if elems >= 8192 else 'k_shared_update'}<double,"
                               f"{(prob.dim + 1) * (prob.p + 1) ** prob.dim}> (finest level, one inverse)" if shared else
                               f"k_colour_residual<double,{prob.dim},{prob.p}> + k_apply_inverse<double,double,"
                               f"{prob.dim},{prob.p}> (finest level)" if prob.dim == 3 else
