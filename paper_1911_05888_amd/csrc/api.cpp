@@ -102,7 +102,7 @@ struct ldgs_ctx {
   hipEvent_t ov_fork = nullptr, ov_join = nullptr;
   std::vector<hipEvent_t> ov_prod;   // end of each chunk's product (side stream)
   bool ov_chain = true;              // chain the chunks across colours; LDGS_OVERLAP_CHAIN=0 disables
-  // one-inverse FP32 updates of colours of at least mfma_min elements on the
+  // one-inverse updates (FP32 and FP64) of colours of at least mfma_min elements on the
   // matrix cores (0: never); LDGS_MFMA=0 disables, LDGS_MFMA_MIN overrides
   // the size (tests)
   int64_t mfma_min = 8192;
