@@ -58,6 +58,8 @@ struct PrecLevel {
   bool parity = false;           // parity colouring, each colour in increasing order (kernels compute the ids)
   size_t inv_stride = 0;         // entries per element in the inverse layout
   const T* ainv_sh = nullptr;    // set when every element has the same block: its inverse, k-major (a[k nb + row])
+  const void* ainv_tiles = nullptr;   // the same inverse in the symmetric tile layout (one element's worth)
+  int ainv_tiles_kind = 0;            // 0 double, 1 float
   T* rbuf = nullptr;             // colour residuals for the shared-inverse pass ([largest colour][nb])
   T* x = nullptr;                // level work vectors (levels >= 1)
   T* b = nullptr;
@@ -106,6 +108,11 @@ struct ldgs_ctx {
   // matrix cores (0: never); LDGS_MFMA=0 disables, LDGS_MFMA_MIN overrides
   // the size (tests)
   int64_t mfma_min = 8192;
+  // one-inverse colours of fewer elements than this run as one launch (the
+  // evaluation and the product with the level's inverse in one kernel)
+  // instead of a residual launch and an update launch; LDGS_FUSE_SHARED_MAX
+  // overrides (0: never)
+  int64_t fuse_shared_max = 4096;
   std::vector<int> kernel_offsets;
   bool rotations = false;            // the rigid rotations belong to the kernel (stress walls)
   PrecStore<double> s64;
@@ -708,12 +715,20 @@ void build_inverses(ldgs_ctx* c, bool need64, bool need32, bool need16) {
       };
       int64_t maxc = 0;
       for (int col = 0; col < L.ncol; ++col) maxc = std::max(maxc, off[col + 1] - off[col]);
+      double* dense_inv = upload<double>(c, inv);
       int* elems = dalloc<int>(c, L.NE);
       HIPCHK(hipMemcpy(elems, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice));
       auto set = [&](auto& S) {
         using T = std::remove_pointer_t<decltype(S.lv[l].x)>;
         PrecLevel<T>& pl = S.lv[l];
         pl.ainv_sh = upload<T>(c, kmajor((int)sizeof(T)));
+        // the symmetric tile layout of the same inverse, for the one-launch pass
+        const int tb = (int)sizeof(T);
+        const size_t st = (size_t)sym_tile_off(trs, sym_tiles(nb, tb).NTILE);
+        void* tiles = tb == 8 ? (void*)dalloc<double>(c, st) : (void*)dalloc<float>(c, st);
+        LCHK(launch_arrange_sym(c->stream, 1, nb, dense_inv, tiles, tb, (int64_t)st));
+        pl.ainv_tiles = tiles;
+        pl.ainv_tiles_kind = tb == 8 ? 0 : 1;
         pl.rbuf = dalloc<T>(c, (size_t)maxc * nb);
         pl.inv = nullptr;
         pl.elems = elems;
@@ -905,7 +920,12 @@ void smooth_colour(ldgs_ctx* c, PrecStore<T>& S, int l, int col, const T* b, T* 
   const bool chunked = !pl.ainv_sh && c->split_pass && pl.rbuf && !pl.view.iface && c->side &&
                        c->overlap_chunks > 1 && cnt >= c->overlap_min;
   if (!chunked) ov_join(c, chain);
-  if (pl.ainv_sh) {
+  if (pl.ainv_sh && pl.ainv_tiles && cnt < c->fuse_shared_max) {
+    // one inverse for the level, small colour: one launch, every element's
+    // product with the same tiles (latency-bound launches: half of them)
+    LCHK(launch_smooth_colour<T>(cfg, pl.view, c->tab, pl.elems + o, pcol, cnt, pl.ainv_tiles, pl.ainv_tiles_kind, b,
+                                 x, true));
+  } else if (pl.ainv_sh) {
     // one inverse for the level: residuals of the colour, then the shared update
     LCHK(launch_colour_residual<T>(cfg, pl.view, c->tab, pl.elems + o, pcol, cnt, b, x, pl.rbuf));
     LCHK(launch_shared_update<T>(c->stream, cnt, c->g.nb, pl.ainv_sh, pl.rbuf, pl.elems + o, x, 0, nullptr, 0,
@@ -1669,6 +1689,7 @@ ldgs_status ldgs_setup(const ldgs_problem* prob, ldgs_ctx** out) {
       const long v = std::strtol(mm, nullptr, 10);
       if (v >= 1) c->mfma_min = v;
     }
+    if (const char* fs = std::getenv("LDGS_FUSE_SHARED_MAX")) c->fuse_shared_max = std::strtol(fs, nullptr, 10);
     if (const char* mf = std::getenv("LDGS_MFMA"))
       if (std::strtol(mf, nullptr, 10) == 0) c->mfma_min = 0;
     // LDGS_SETUP_TIMING=1: wall time of each setup phase on stderr

@@ -1215,7 +1215,7 @@ __device__ __forceinline__ void sym_product(const InvWord<TI>* __restrict__ Ai,
 template <typename T, typename TI, int D, int P, int NT, bool IF>
 __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> tab, const int* __restrict__ elems,
                                                       int pcol, const TI* __restrict__ inv, const T* __restrict__ b,
-                                                      T* __restrict__ x) {
+                                                      T* __restrict__ x, int inv_shared) {
   using S = Sz<D, P>;
   constexpr int NB = S::NB;
   using SP = SymProd<TI, NB>;
@@ -1224,7 +1224,8 @@ __global__ __launch_bounds__(NT) void k_smooth_colour(DevLevel<T> lev, TabT<T> t
   const int lane = threadIdx.x;
   const int idx = xcd_remap(blockIdx.x, gridDim.x);
   const int E = colour_elem<D>(idx, pcol, lev.lgn, elems);
-  const auto* Ai = reinterpret_cast<const typename SP::Word*>(inv + (size_t)idx * SP::ESTRIDE);
+  // inv_shared: one inverse for every element of the level (read through the caches)
+  const auto* Ai = reinterpret_cast<const typename SP::Word*>(inv + (inv_shared ? (size_t)0 : (size_t)idx * SP::ESTRIDE));
   typename SP::Word pre[SP::PF][SP::H];
   element_operator<T, D, P, NT, IF>(lev, tab, E, x, b, 0, w, [&]() { sym_prefetch<TI, NB>(Ai, pre, lane); });
   // the evaluation's arrays before res are free again: column-sum scratch
@@ -1987,7 +1988,7 @@ static void dispatch_nt(int64_t nelems, int small_grid, size_t lds_bytes, F&& f)
 
 template <typename T>
 int launch_smooth_colour(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab, const int* elems, int pcol,
-                         int64_t nelems, const void* inv, int inv_kind, const T* b, T* x) {
+                         int64_t nelems, const void* inv, int inv_kind, const T* b, T* x, bool inv_shared) {
   if (nelems <= 0) return 0;
   const unsigned grid = (unsigned)nelems;
   bool bad = false;   // no kernel for this level (interphase faces in 3D)
@@ -1996,14 +1997,14 @@ int launch_smooth_colour(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D
   if constexpr (sizeof(T) == 8) {
     if (inv_kind != 0) return 2;
     if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt<D_, (int)sizeof(T)>(nelems, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, double, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
-                                                  lev, tt, elems, pcol, (const double*)inv, b, x); }); })) bad = true; })) return 2;
+                                                  lev, tt, elems, pcol, (const double*)inv, b, x, (int)inv_shared); }); })) bad = true; })) return 2;
   } else {
     if (inv_kind == 1) {
       if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt<D_, (int)sizeof(T)>(nelems, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, float, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
-                                                    lev, tt, elems, pcol, (const float*)inv, b, x); }); })) bad = true; })) return 2;
+                                                    lev, tt, elems, pcol, (const float*)inv, b, x, (int)inv_shared); }); })) bad = true; })) return 2;
     } else if (inv_kind == 2) {
       if (dispatch(c.dim, c.p, [&](auto Dc, auto Pc) { constexpr int D_ = decltype(Dc)::value; constexpr int P_ = decltype(Pc)::value; if (dispatch_if(lev.iface, D_, [&](auto Ic) { constexpr bool IF_ = decltype(Ic)::value; if constexpr (!IF_ || D_ == 2) dispatch_nt<D_, (int)sizeof(T)>(nelems, c.small_grid, work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr), [&](auto Nc) { constexpr int NT_ = decltype(Nc)::value; hipLaunchKernelGGL((k_smooth_colour<T, uint16_t, D_, P_, NT_, IF_>), dim3(grid), dim3(NT_), (work_bytes<T, D_, P_, IF_>(lev.mmu != nullptr)), st,
-                                                    lev, tt, elems, pcol, (const uint16_t*)inv, b, x); }); })) bad = true; })) return 2;
+                                                    lev, tt, elems, pcol, (const uint16_t*)inv, b, x, (int)inv_shared); }); })) bad = true; })) return 2;
     } else {
       return 2;
     }
@@ -2320,9 +2321,9 @@ template int launch_scale_cast<double, double>(void*, int64_t, int, int, const d
 template int launch_scale_cast<double, float>(void*, int64_t, int, int, const double*, const double*, float*, int, int);
 template int launch_scale_cast<float, double>(void*, int64_t, int, int, const double*, const float*, double*, int, int);
 template int launch_smooth_colour<double>(const LaunchCfg&, const DevLevel<double>&, const Tab1D&, const int*, int, int64_t,
-                                          const void*, int, const double*, double*);
+                                          const void*, int, const double*, double*, bool);
 template int launch_smooth_colour<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const int*, int, int64_t,
-                                         const void*, int, const float*, float*);
+                                         const void*, int, const float*, float*, bool);
 template int launch_residual<double>(const LaunchCfg&, const DevLevel<double>&, const Tab1D&, const double*,
                                      const double*, double*, int);
 template int launch_residual<float>(const LaunchCfg&, const DevLevel<float>&, const Tab1D&, const float*, const float*,

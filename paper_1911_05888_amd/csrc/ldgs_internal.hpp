@@ -124,11 +124,12 @@ struct LaunchCfg {
 };
 
 // elems: the colour's elements; pcol >= 0 instead: parity colour pcol with
-// its elements in increasing order, computed from the launch index
+// its elements in increasing order, computed from the launch index;
+// inv_shared: inv holds one inverse (tile layout) for every element
 template <typename T>
 int launch_smooth_colour(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab,
                          const int* elems, int pcol, int64_t nelems, const void* inv, int inv_kind,
-                         const T* b, T* x);
+                         const T* b, T* x, bool inv_shared = false);
 template <typename T>
 int launch_residual(const LaunchCfg& c, const DevLevel<T>& lev, const Tab1D& tab,
                     const T* b, const T* x, T* out, int mode);   // mode 0: b - A x, 1: A x

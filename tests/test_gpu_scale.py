@@ -360,3 +360,59 @@ def test_shared_inverse_update_on_matrix_cores(name, monkeypatch):
         e = float(torch.linalg.norm(ys[0] - ys[1]) / torch.linalg.norm(ys[1]))
         print(f"[scale] {name} V-cycle ({'FP64' if vp == V_FP64 else 'FP32'}): MFMA vs VALU {e:.2e}", flush=True)
         assert e <= tol
+
+
+FUSED_SHARED_CASES = {
+    # 2D, red-black colouring, colours of 128 elements, 27 x 27 inverse
+    "c1_n16_p2": lambda: __import__("synth").c1_periodic_standard(n=16, p=2),
+    # 3D parity colouring, colours of 512 elements, 108 x 108 inverse
+    "c3_n16_p2": lambda: __import__("synth").c3_unsteady_periodic(n=16, p=2, re_eff=10.0),
+}
+
+
+@pytest.mark.parametrize("name", list(FUSED_SHARED_CASES))
+def test_one_launch_passes_on_one_inverse_levels(name, monkeypatch):
+    """Small colours of one-inverse levels run as one launch (the element
+    evaluation and the product with the level's inverse, stored once in the
+    symmetric tile layout) instead of a residual launch and an update launch
+    (LDGS_FUSE_SHARED_MAX=0): the same colour passes and V-cycles up to the
+    order of the sums, in FP64, FP32 and with BF16 inverses."""
+    import torch
+    from paper_1911_05888_amd import Context, V_FP64, V_FP32, V_FP32_BF16BLK
+    prob = FUSED_SHARED_CASES[name]()
+    print(f"[scale] one-launch one-inverse passes {name}", flush=True)
+    ctxs = []
+    for flag in ("8192", "0"):
+        monkeypatch.setenv("LDGS_FUSE_SHARED_MAX", flag)
+        ctxs.append(Context(prob, build_precisions=(1 << V_FP32) | (1 << V_FP32_BF16BLK)))
+    fused, split = ctxs
+    assert fused.level_shared_inverse(0)
+    N = fused.ndof
+    _, _, ncol = fused.level_info(0)
+    g = torch.Generator(device="cuda").manual_seed(47)
+    x0 = torch.randn(N, dtype=torch.float64, device="cuda", generator=g)
+    b = torch.randn(N, dtype=torch.float64, device="cuda", generator=g)
+    xf, xs = x0.clone(), x0.clone()
+    xf32, xs32 = x0.float(), x0.float()
+    for c in range(ncol):
+        fused.level_smooth_colour(0, c, b, xf)
+        split.level_smooth_colour(0, c, b, xs)
+        fused.level_smooth_colour_f32(0, c, V_FP32, b.float(), xf32)
+        split.level_smooth_colour_f32(0, c, V_FP32, b.float(), xs32)
+        d64 = float(torch.linalg.norm(xf - xs) / torch.linalg.norm(xs))
+        d32 = float(torch.linalg.norm((xf32 - xs32).double()) / torch.linalg.norm(xs32.double()))
+        print(f"[scale] {name} colour {c}: one launch vs two, FP64 {d64:.2e}, FP32 {d32:.2e}", flush=True)
+        assert d64 <= 1e-12 and d32 <= 1e-5, (c, d64, d32)
+    bp = b.clone()
+    fused.project_kernel(bp)
+    for vp, tol in ((V_FP64, 1e-11), (V_FP32, 1e-5), (V_FP32_BF16BLK, 1e-5)):
+        ys = []
+        for ctx in (fused, split):
+            ctx.set_vprec(vp)
+            y = torch.zeros_like(bp)
+            for _ in range(2):
+                ctx.vcycle(bp, y)
+            ys.append(y)
+        e = float(torch.linalg.norm(ys[0] - ys[1]) / torch.linalg.norm(ys[1]))
+        print(f"[scale] {name} two V-cycles (vprec {vp}): one launch vs two {e:.2e}", flush=True)
+        assert e <= tol, (vp, e)
