@@ -1360,6 +1360,20 @@ double dot(ldgs_ctx* c, const double* x, const double* y) {
   return host_sum_partials(c, nblk);
 }
 
+// Modified Gram-Schmidt of w against V[0..j]: h[i] = <w, V[i]>, w -= h[i] V[i]
+// in turn; returns ||w||.  Each update is fused with the next inner product
+// (the last with ||w||^2), which sums exactly as the separate launches do.
+double mgs(ldgs_ctx* c, double* const* V, int j, double* w, double* h) {
+  const int nblk = 512;
+  double hij = dot(c, w, V[0]);
+  for (int i = 0; i <= j; ++i) {
+    h[i] = hij;
+    LCHK(launch_axpy_dot_partial(c->stream, c->ndof(), -hij, V[i], w, i < j ? V[i + 1] : nullptr, c->w_part, nblk));
+    hij = host_sum_partials(c, nblk);
+  }
+  return std::sqrt(hij);
+}
+
 void residual_fine(ldgs_ctx* c, const double* b, const double* x, double* r) {
   if (c->imp) {
     const ldgs_ctx::ImpDev& D = c->idev[0];
@@ -2232,12 +2246,9 @@ ldgs_status ldgs_solve(ldgs_ctx* ctx, double* b, double* x, double tol, int maxi
           vcycle_user(ctx, ctx->vprec, V[j], zj, true);
           if (use_learned) learned_minres(ctx, ctx->vprec, zj, zj);   // a variable preconditioner: FGMRES only
           apply_fine(ctx, zj, V[j + 1]);
-          for (int i = 0; i <= j; ++i) {
-            double hij = dot(ctx, V[j + 1], V[i]);
-            H[i * m + j] = hij;
-            LCHK(launch_axpy(ctx->stream, N, -hij, V[i], V[j + 1]));
-          }
-          double hn = std::sqrt(dot(ctx, V[j + 1], V[j + 1]));
+          std::vector<double> hcol(j + 1);
+          double hn = mgs(ctx, V, j, V[j + 1], hcol.data());
+          for (int i = 0; i <= j; ++i) H[i * m + j] = hcol[i];
           H[(j + 1) * m + j] = hn;
           if (hn > 0) LCHK(launch_scale_copy(ctx->stream, N, 1.0 / hn, V[j + 1], V[j + 1]));
           for (int i = 0; i < j; ++i) {
@@ -2334,12 +2345,9 @@ ldgs_status ldgs_gmres_rho(ldgs_ctx* ctx, const double* x0, double reduction, in
     int n = 0;
     for (int j = 0; j < m; ++j) {
       VA(V[j], V[j + 1]);
-      for (int i = 0; i <= j; ++i) {
-        const double hij = dot(ctx, V[j + 1], V[i]);
-        H[(size_t)i * m + j] = hij;
-        LCHK(launch_axpy(ctx->stream, N, -hij, V[i], V[j + 1]));
-      }
-      const double hn = std::sqrt(dot(ctx, V[j + 1], V[j + 1]));
+      std::vector<double> hcol(j + 1);
+      const double hn = mgs(ctx, V, j, V[j + 1], hcol.data());
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];
       H[(size_t)(j + 1) * m + j] = hn;
       if (hn > 0.0) LCHK(launch_scale_copy(ctx->stream, N, 1.0 / hn, V[j + 1], V[j + 1]));
       for (int i = 0; i < j; ++i) {

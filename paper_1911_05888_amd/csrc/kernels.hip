@@ -1914,6 +1914,46 @@ __global__ __launch_bounds__(RB) void k_dot_partial(int64_t n, const double* x, 
   }
   if (threadIdx.x == 0) out[blockIdx.x] = sm[0];
 }
+// y += a x, and the block partial sums of y . z (z null: y . y) for the updated
+// y, summed exactly as k_dot_partial sums x . y (the same strides, pairing and
+// tree), so that a fused update + inner product equals the two launches
+__global__ __launch_bounds__(RB) void k_axpy_dot_partial(int64_t n, double a, const double* __restrict__ x,
+                                                         double* __restrict__ y, const double* __restrict__ z,
+                                                         double* __restrict__ out) {
+  __shared__ double sm[RB];
+  const int64_t gs = (int64_t)gridDim.x * RB;
+  int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (; i + 3 * gs < n; i += 4 * gs) {
+    double y0 = y[i], y1 = y[i + gs], y2 = y[i + 2 * gs], y3 = y[i + 3 * gs];
+    y0 += a * x[i];
+    y1 += a * x[i + gs];
+    y2 += a * x[i + 2 * gs];
+    y3 += a * x[i + 3 * gs];
+    y[i] = y0;
+    y[i + gs] = y1;
+    y[i + 2 * gs] = y2;
+    y[i + 3 * gs] = y3;
+    s0 += y0 * (z ? z[i] : y0);
+    s1 += y1 * (z ? z[i + gs] : y1);
+    s2 += y2 * (z ? z[i + 2 * gs] : y2);
+    s3 += y3 * (z ? z[i + 3 * gs] : y3);
+  }
+  for (; i < n; i += gs) {
+    double y0 = y[i];
+    y0 += a * x[i];
+    y[i] = y0;
+    s0 += y0 * (z ? z[i] : y0);
+  }
+  const double s = (s0 + s1) + (s2 + s3);
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = RB / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sm[threadIdx.x] += sm[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sm[0];
+}
 __global__ __launch_bounds__(RB) void k_strided_sum_partial(int64_t ne, int nb, int off, const double* x, double* out) {
   __shared__ double sm[RB];
   double s = 0.0;
@@ -2228,6 +2268,11 @@ int launch_fill(void* stream, int64_t n, T v, T* y) {
 }
 int launch_dot_partial(void* stream, int64_t n, const double* x, const double* y, double* out, int nblk) {
   hipLaunchKernelGGL(k_dot_partial, dim3(nblk), dim3(RB), 0, (hipStream_t)stream, n, x, y, out);
+  return hip_ok();
+}
+int launch_axpy_dot_partial(void* stream, int64_t n, double a, const double* x, double* y, const double* z,
+                            double* out, int nblk) {
+  hipLaunchKernelGGL(k_axpy_dot_partial, dim3(nblk), dim3(RB), 0, (hipStream_t)stream, n, a, x, y, z, out);
   return hip_ok();
 }
 int launch_strided_sum_partial(void* stream, int64_t nelem, int nb, int off, const double* x, double* out, int nblk) {

@@ -182,6 +182,9 @@ template <typename T>
 int launch_fill(void* stream, int64_t n, T v, T* y);
 // partial sums: out[blk] for blk < nblk (<= 1024 blocks)
 int launch_dot_partial(void* stream, int64_t n, const double* x, const double* y, double* out, int nblk);
+// y += a x, then partial sums of y . z (z null: y . y) as launch_dot_partial(y, z)
+int launch_axpy_dot_partial(void* stream, int64_t n, double a, const double* x, double* y, const double* z,
+                            double* out, int nblk);
 // partial sums of the coefficient at offset `off` of every element (stride nb)
 int launch_strided_sum_partial(void* stream, int64_t nelem, int nb, int off, const double* x,
                                double* out, int nblk);
